@@ -1,0 +1,450 @@
+"""Plain FP64 CPU oracle for grid-based canonical/Tucker lattice sums.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product library imports, links or runs this
+module; only the tests, the smoke check and the CPU-baseline leg of the benchmark use
+it.  It shares no code with the GPU path: the only common dependency is the seeded
+input description in ``workloads``.
+
+Every function follows a passage of
+V. Khoromskaia, B. N. Khoromskij, "Tucker tensor method for fast grid-based summation
+of long-range potentials on 3D lattices with defects" (arXiv:1411.1994), cited by
+section / equation label.  The code favours being checkable by eye over speed: no
+blocking, no fusion, no reordering beyond the definitions.
+
+Readings of passages that are silent, ambiguous or garbled (each one is tested):
+
+* sinc quadrature (Sec. 2.1, eqs. ``laplace``/``hM``): the trapezoid rule with step
+  h_u is applied after the substitution t = sinh(u)/s, which makes the integrand even
+  in u; the sum over k = -M..M is folded onto k = 0..M, so the rank is M+1 for Newton
+  (the t = 0 node carries weight) and M for Yukawa/Slater.
+* Yukawa transform (Sec. 2.2, eq. ``LalpYukawa``): the exponent of the weight is read as
+  kappa^2/(4 t^2); as printed (kappa^2/t^2) the transform gives exp(-2 kappa r)/r.
+* Galerkin basis (Sec. 2.1, eq. ``galten``): psi_i is the cell indicator divided by the
+  cell volume, so tensor entries are cell averages (values of a potential).
+* grid: odd N per axis, cell i centred at (i - (N-1)/2) h; the reference vector of
+  length 2N-1 (the doubled box of Sec. 3.1, eq. ``master_pot``) has entry m at
+  displacement (m - (N-1)) h, and a charge in cell c contributes entry i - c + N - 1 at
+  cell i (the windowing operator of eq. ``sub_tens``, whose printed index range is
+  inconsistent with the index set I_0).
+* lattice (Sec. 3.2): site k of an axis sits at (k - (L-1)/2) b + centre; sites that do
+  not fall on a cell centre are snapped to the nearest one, rounding halves away from
+  zero (the paper assumes on-grid sites and accepts O(h) error otherwise).
+* RHOSVD truncation (Sec. 4.3 allows a threshold instead of fixed ranks): per mode the
+  smallest r with (sum_{k>r} sigma_k^2)^{1/2} <= eps ||A|| / (3 ||xi||), which by the
+  bound of the Appendix theorem (d) certifies ||A - A0|| <= eps ||A|| in Frobenius norm.
+* quadrature nodes whose weight is below 1e-18 of the largest weight are dropped.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+from typing import List, Sequence, Tuple
+
+import numpy as np
+from scipy.special import erf, erfc
+
+NEWTON, YUKAWA, SLATER = 0, 1, 2
+
+SQRT_PI = math.sqrt(math.pi)
+
+
+class OutOfBox(ValueError):
+    """A snapped site or sample point lies outside the grid."""
+
+
+# ---------------------------------------------------------------------------------------
+# Sec. 2.1-2.2: sinc quadrature of the Laplace-Gauss transform
+# ---------------------------------------------------------------------------------------
+
+def default_quadrature(kind: int, N: Sequence[int], h: float) -> Tuple[float, float]:
+    """Default (h_u, s): s is a quarter of the largest charge-to-cell distance in the box,
+    h_u a per-kernel step chosen to minimise the max-norm error at M = 32..40."""
+    r_max = h * math.sqrt(sum(float(n - 1) ** 2 for n in N))
+    s = r_max / 4.0
+    h_u = 0.30 if kind == SLATER else 0.35
+    return h_u, s
+
+
+def transform_density(kind: int, param: float, t: np.ndarray) -> np.ndarray:
+    """a(t) with p(z) = int_0^inf a(t) exp(-t^2 z^2) dt (Sec. 2.2):
+
+    * Newton 1/z:           a = 2/sqrt(pi)                           (eq. LalpNewt)
+    * Yukawa exp(-k z)/z:   a = 2/sqrt(pi) exp(-k^2/(4 t^2))         (eq. LalpYukawa, read)
+    * Slater exp(-l z):     a = l/sqrt(pi) t^-2 exp(-l^2/(4 t^2))    (eq. LalpSlater with
+      rho = z^2, kappa = l^2/4 and the change of variable t_paper = t^2)
+    """
+    t = np.asarray(t, dtype=np.float64)
+    a = np.zeros_like(t)
+    pos = t > 0
+    if kind == NEWTON or (kind == YUKAWA and param == 0.0):
+        a[:] = 2.0 / SQRT_PI
+    elif kind == YUKAWA:
+        a[pos] = 2.0 / SQRT_PI * np.exp(-param * param / (4.0 * t[pos] ** 2))
+    elif kind == SLATER:
+        if param <= 0:
+            raise ValueError("Slater exponent must be positive")
+        a[pos] = param / SQRT_PI / t[pos] ** 2 * np.exp(-param * param / (4.0 * t[pos] ** 2))
+    else:
+        raise ValueError(f"unknown kernel {kind}")
+    return a
+
+
+def sinc_nodes(kind: int, param: float, M: int, h_u: float, s: float):
+    """Nodes t_q and weights w_q with p(z) ~= sum_q w_q exp(-t_q^2 z^2) (Sec. 2.1, eqs.
+    ``laplace``, ``hM``, ``sinc_Newt``): trapezoid rule in u with t = sinh(u)/s on
+    u_k = k h_u, k = -M..M, folded onto k >= 0 (k = 0 keeps half of the full step)."""
+    if M < 1 or h_u <= 0 or s <= 0:
+        raise ValueError("need M >= 1, h_u > 0, s > 0")
+    k = np.arange(M + 1, dtype=np.float64)
+    u = k * h_u
+    t = np.sinh(u) / s
+    dtdu = np.cosh(u) / s
+    step = np.where(k == 0, 0.5 * h_u, h_u)
+    w = step * transform_density(kind, param, t) * dtdu
+    keep = w > 1e-18 * np.max(w)
+    return t[keep], w[keep]
+
+
+def kernel_value(kind: int, param: float, z):
+    """The kernel p(z) itself (Sec. 2.2)."""
+    z = np.asarray(z, dtype=np.float64)
+    if kind == NEWTON:
+        return 1.0 / z
+    if kind == YUKAWA:
+        return np.exp(-param * z) / z
+    if kind == SLATER:
+        return np.exp(-param * z)
+    raise ValueError(kind)
+
+
+# ---------------------------------------------------------------------------------------
+# Sec. 2.1: Galerkin (cell-average) collocation of the Gaussians; Sec. 3.1 reference tensor
+# ---------------------------------------------------------------------------------------
+
+def cell_average_gauss(t, d, h: float) -> np.ndarray:
+    """b(t; d) = (1/h) int_{d-h/2}^{d+h/2} exp(-t^2 x^2) dx, the entries of the vectors
+    b(t_k) of Sec. 2.1 for cell-average basis functions.  Closed form
+    sqrt(pi)/(2 t h) [erf(t(d+h/2)) - erf(t(d-h/2))], evaluated with erfc when both ends
+    lie in the tail (t(|d|-h/2) > 1); equals 1 at t = 0.  Uses |d| (mirror symmetry)."""
+    t = np.asarray(t, dtype=np.float64)
+    d = np.abs(np.asarray(d, dtype=np.float64))
+    t, d = np.broadcast_arrays(t, d)
+    out = np.ones(t.shape, dtype=np.float64)
+    pos = t > 0
+    tp, dp = t[pos], d[pos]
+    lo = tp * (dp - 0.5 * h)
+    hi = tp * (dp + 0.5 * h)
+    diff = np.where(lo > 1.0, erfc(lo) - erfc(hi), erf(hi) - erf(lo))
+    out[pos] = SQRT_PI / (2.0 * tp * h) * diff
+    return out
+
+
+def reference_vectors(t: np.ndarray, w: np.ndarray, N: int, h: float, weighted: bool = True):
+    """Reference canonical vectors on the doubled box (Sec. 3.1, eq. ``master_pot``; Sec. 3.2,
+    eq. ``CanMastSumNL``): row q, entry m = w_q^(1/3) b(t_q; (m-(N-1)) h), m = 0..2N-2
+    (p_q = a_q^{1/3} b(t_q) of Sec. 2.1).  ``weighted=False`` omits w_q^(1/3)."""
+    m = np.arange(2 * N - 1)
+    d = (m - (N - 1)).astype(np.float64) * h
+    B = cell_average_gauss(t[:, None], d[None, :], h)
+    if weighted:
+        B = np.cbrt(w)[:, None] * B
+    return B
+
+
+# ---------------------------------------------------------------------------------------
+# Sec. 3.1-3.2: lattice bookkeeping (shift-and-windowing offsets)
+# ---------------------------------------------------------------------------------------
+
+def snap(coord, h: float, N: int) -> np.ndarray:
+    """Cell index of coordinate(s): j = sign(x/h) floor(|x/h| + 1/2), i = j + (N-1)/2.
+    Raises OutOfBox unless 0 <= i <= N-1."""
+    u = np.asarray(coord, dtype=np.float64) / h
+    j = np.sign(u) * np.floor(np.abs(u) + 0.5)
+    i = j + (N - 1) // 2
+    if np.any(i < 0) or np.any(i > N - 1):
+        raise OutOfBox("site outside the grid")
+    return i.astype(np.int64)
+
+
+def site_coords(L: int, b: float, center: float) -> np.ndarray:
+    """Coordinates of the L sites of a centred lattice axis: (k - (L-1)/2) b + centre
+    (Sec. 3.2, the set K read as centred)."""
+    k = np.arange(L, dtype=np.float64)
+    return (k - (L - 1) / 2.0) * b + center
+
+
+def block_offsets(block, h: float, N: Sequence[int]) -> List[np.ndarray]:
+    """Per axis, the snapped cell indices of the block's sites."""
+    return [snap(site_coords(block.L[a], block.b[a], block.center[a]), h, N[a]) for a in range(3)]
+
+
+def charges(problem) -> Tuple[np.ndarray, np.ndarray]:
+    """All charges of the problem as (cell index triples (C,3), charge Z (C,)): the block's
+    charge on every site of every block, changed by dZ at defect sites (Sec. 4.1)."""
+    idx, Z = [], []
+    for bi, blk in enumerate(problem.blocks):
+        offs = block_offsets(blk, problem.h, problem.N)
+        g = np.stack(np.meshgrid(*offs, indexing="ij"), axis=-1).reshape(-1, 3)
+        z = np.full(g.shape[0], float(blk.charge))
+        L = blk.L
+        for d in problem.defects:
+            if d.block == bi:
+                z[(d.site[0] * L[1] + d.site[1]) * L[2] + d.site[2]] += d.dZ
+        idx.append(g)
+        Z.append(z)
+    return np.concatenate(idx), np.concatenate(Z)
+
+
+def quadrature_of(problem):
+    h_u, s = problem.h_u, problem.s
+    if h_u <= 0 or s <= 0:
+        dh, ds = default_quadrature(problem.kind, problem.N, problem.h)
+        h_u = h_u if h_u > 0 else dh
+        s = s if s > 0 else ds
+    return sinc_nodes(problem.kind, problem.param, problem.M, h_u, s)
+
+
+# ---------------------------------------------------------------------------------------
+# O1: brute-force sum over every charge (the plain definition, eq. ``EwaldSumE`` projected
+# onto the grid with the separable Gaussian sum of eq. ``sinc_Newt``)
+# ---------------------------------------------------------------------------------------
+
+def brute_force_points(problem, pts: np.ndarray, t=None, w=None) -> np.ndarray:
+    """V[p] = sum_c Z_c sum_q w_q prod_l b(t_q; (p_l - c_l) h) at cell-index triples pts (P,3).
+    No factorisation over lattice axes: every charge is visited for every point."""
+    if t is None:
+        t, w = quadrature_of(problem)
+    Nr = max(problem.N)
+    table = reference_vectors(t, w, Nr, problem.h, weighted=False)   # b(t_q; m h), unweighted
+    cidx, Z = charges(problem)
+    out = np.empty(len(pts))
+    for n, p in enumerate(np.asarray(pts)):
+        prod = (table[:, p[0] - cidx[:, 0] + Nr - 1]
+                * table[:, p[1] - cidx[:, 1] + Nr - 1]
+                * table[:, p[2] - cidx[:, 2] + Nr - 1])          # (R, C)
+        per_charge = w @ prod                                    # q inside
+        out[n] = np.sum(Z * per_charge)                          # charges outside
+    return out
+
+
+def brute_force_grid(problem, ranges=None, t=None, w=None) -> np.ndarray:
+    """V on a full box of cells (all cells, or index ranges per axis), charge by charge."""
+    if t is None:
+        t, w = quadrature_of(problem)
+    Nr = max(problem.N)
+    if ranges is None:
+        ranges = [np.arange(n) for n in problem.N]
+    table = reference_vectors(t, w, Nr, problem.h, weighted=False)
+    cidx, Z = charges(problem)
+    V = np.zeros(tuple(len(r) for r in ranges))
+    for c in range(len(Z)):
+        if Z[c] == 0.0:
+            continue
+        f = [table[:, ranges[a] - cidx[c, a] + Nr - 1] for a in range(3)]
+        V += Z[c] * np.einsum("q,qi,qj,qk->ijk", w, f[0], f[1], f[2], optimize=True)
+    return V
+
+
+# ---------------------------------------------------------------------------------------
+# Thm ``thm:sumCaseE`` (A), eq. ``EwaldTensorGl``: assembled canonical lattice sum
+# ---------------------------------------------------------------------------------------
+
+def window(P_ref: np.ndarray, c: int, N_axis: int, N_ref: int) -> np.ndarray:
+    """Shift-and-windowing of the reference vectors to a charge in cell c of an axis with
+    N_axis cells (Sec. 3.1, eq. ``sub_tens``): entry i is P_ref[:, i - c + N_ref - 1]."""
+    i = np.arange(N_axis)
+    return P_ref[:, i - c + N_ref - 1]
+
+
+def shift_sum(P_ref: np.ndarray, sites: np.ndarray, N_axis: int, N_ref: int) -> np.ndarray:
+    """sum_k W_(k) p_q over the sites of one axis (the 1D sums of eq. ``EwaldTensorGl``)."""
+    U = np.zeros((P_ref.shape[0], N_axis))
+    for c in sites:
+        U += window(P_ref, int(c), N_axis, N_ref)
+    return U
+
+
+def assembled_canonical(problem, t=None, w=None):
+    """Per block, the rank-R factors [U_1, U_2, U_3] (each R x N_l) of the block's lattice sum
+    (the block's charge is not applied)."""
+    if t is None:
+        t, w = quadrature_of(problem)
+    Nr = max(problem.N)
+    P = reference_vectors(t, w, Nr, problem.h)
+    out = []
+    for blk in problem.blocks:
+        offs = block_offsets(blk, problem.h, problem.N)
+        out.append([shift_sum(P, offs[a], problem.N[a], Nr) for a in range(3)])
+    return out
+
+
+def canonical_eval(factors: Sequence[np.ndarray], pts: np.ndarray, lam=None) -> np.ndarray:
+    """sum_q lam_q prod_l U_l[q, p_l] at cell-index triples (canonical format, eq. ``CP_form``)."""
+    pts = np.asarray(pts)
+    prod = factors[0][:, pts[:, 0]] * factors[1][:, pts[:, 1]] * factors[2][:, pts[:, 2]]
+    if lam is None:
+        return prod.sum(axis=0)
+    return lam @ prod
+
+
+# ---------------------------------------------------------------------------------------
+# Sec. 4.1-4.2: defected lattice as a sum of canonical tensors (eq. ``Can_LatticeSum_full``)
+# ---------------------------------------------------------------------------------------
+
+def canonical_terms(problem, t=None, w=None):
+    """The rank-1 terms of P_hat = P_0 + sum_s P_s in the normalised form of eq. ``CP_form``:
+    xi (Rhat,) and side matrices A_l (N_l x Rhat) with unit columns.  Terms: for every block
+    and node q the block's assembled vectors times the block's charge; for every defect s
+    and node q the windows of the reference vectors at the defect's cell, times dZ_s."""
+    if t is None:
+        t, w = quadrature_of(problem)
+    Nr = max(problem.N)
+    P = reference_vectors(t, w, Nr, problem.h)
+    cols = [[], [], []]
+    xi = []
+    offs_all = [block_offsets(blk, problem.h, problem.N) for blk in problem.blocks]
+    for blk, offs in zip(problem.blocks, offs_all):
+        U = [shift_sum(P, offs[a], problem.N[a], Nr) for a in range(3)]
+        nrm = [np.linalg.norm(U[a], axis=1) for a in range(3)]
+        xi.append(blk.charge * nrm[0] * nrm[1] * nrm[2])
+        for a in range(3):
+            cols[a].append(U[a] / nrm[a][:, None])
+    for d in problem.defects:
+        offs = offs_all[d.block]
+        Wv = [window(P, int(offs[a][d.site[a]]), problem.N[a], Nr) for a in range(3)]
+        nrm = [np.linalg.norm(Wv[a], axis=1) for a in range(3)]
+        xi.append(d.dZ * nrm[0] * nrm[1] * nrm[2])
+        for a in range(3):
+            cols[a].append(Wv[a] / nrm[a][:, None])
+    xi = np.concatenate(xi)
+    A = [np.concatenate(cols[a], axis=0).T for a in range(3)]   # N_l x Rhat
+    return xi, A
+
+
+def cp_norm(xi: np.ndarray, A: Sequence[np.ndarray]) -> float:
+    """Frobenius norm of sum_v xi_v a1_v (x) a2_v (x) a3_v from the factor Gram matrices."""
+    G = (A[0].T @ A[0]) * (A[1].T @ A[1]) * (A[2].T @ A[2])
+    return float(math.sqrt(max(xi @ G @ xi, 0.0)))
+
+
+def cp_full(xi: np.ndarray, A: Sequence[np.ndarray]) -> np.ndarray:
+    """The full tensor of a canonical sum (tiny sizes only)."""
+    return np.einsum("v,iv,jv,kv->ijk", xi, A[0], A[1], A[2], optimize=True)
+
+
+# ---------------------------------------------------------------------------------------
+# Definition ``def:RHOSVD`` and Appendix theorem ``thm:C2Tucker`` (c), (d)
+# ---------------------------------------------------------------------------------------
+
+@dataclass
+class TuckerResult:
+    Z: List[np.ndarray]          # N_l x r_l orthonormal
+    core: np.ndarray             # r1 x r2 x r3
+    sigma: List[np.ndarray]      # singular values of each side matrix
+    ranks: Tuple[int, int, int]
+    tails: Tuple[float, float, float]
+    bound: float                 # ||xi|| sum_l tail_l (absolute)
+    norm_A: float
+    norm_xi: float
+
+
+def tail_norms(sig: np.ndarray) -> np.ndarray:
+    """tail[r] = (sum_{k >= r} sigma_k^2)^{1/2} for r = 0..len(sig) (0-based: drops k = r..)."""
+    sq = sig.astype(np.float64) ** 2
+    suffix = np.concatenate([np.cumsum(sq[::-1])[::-1], [0.0]])
+    return np.sqrt(suffix)
+
+
+def rhosvd(xi: np.ndarray, A: Sequence[np.ndarray], eps: float = None, ranks=None,
+           norm_A: float = None) -> TuckerResult:
+    """RHOSVD of a canonical tensor: truncated SVD of each side matrix A_l, the dominant left
+    singular vectors Z_l as Tucker factors, and the core by canonical projection
+    mu = sum_v xi_v (Z_1^T a1_v) (x) (Z_2^T a2_v) (x) (Z_3^T a3_v) (Appendix, (c)).
+    Ranks are given, or chosen by the eps rule of the module docstring."""
+    norm_xi = float(np.linalg.norm(xi))
+    if norm_A is None:
+        norm_A = cp_norm(xi, A)
+    Zs, sigs, rs, tails = [], [], [], []
+    for a in range(3):
+        U, S, _ = np.linalg.svd(A[a], full_matrices=False)
+        tl = tail_norms(S)
+        if ranks is not None:
+            r = int(ranks[a])
+        else:
+            thr = eps * norm_A / (3.0 * norm_xi)
+            r = int(np.argmax(tl <= thr))         # smallest r with tail(r) <= thr
+            r = max(r, 1)
+        Zs.append(U[:, :r])
+        sigs.append(S)
+        rs.append(r)
+        tails.append(float(tl[r]))
+    Y = [Zs[a].T @ A[a] for a in range(3)]
+    core = np.einsum("v,av,bv,cv->abc", xi, Y[0], Y[1], Y[2], optimize=True)
+    bound = norm_xi * sum(tails)
+    return TuckerResult(Zs, core, sigs, tuple(rs), tuple(tails), bound, norm_A, norm_xi)
+
+
+def tucker_full(core: np.ndarray, Z: Sequence[np.ndarray]) -> np.ndarray:
+    """B x_1 T1 x_2 T2 x_3 T3 (eq. ``Tucker_singePot``) on the full grid (tiny sizes)."""
+    return np.einsum("abc,ia,jb,kc->ijk", core, Z[0], Z[1], Z[2], optimize=True)
+
+
+def tucker_tile(core: np.ndarray, Z: Sequence[np.ndarray], ranges) -> np.ndarray:
+    """The Tucker tensor restricted to index ranges per axis."""
+    return tucker_full(core, [Z[a][ranges[a], :] for a in range(3)])
+
+
+def tucker_points(core: np.ndarray, Z: Sequence[np.ndarray], pts: np.ndarray) -> np.ndarray:
+    """Tucker values at cell-index triples: sum_abc B_abc T1[p1,a] T2[p2,b] T3[p3,c]."""
+    pts = np.asarray(pts)
+    return np.einsum("abc,pa,pb,pc->p", core, Z[0][pts[:, 0]], Z[1][pts[:, 1]], Z[2][pts[:, 2]],
+                     optimize=True)
+
+
+# ---------------------------------------------------------------------------------------
+# O3: the exact Galerkin entry (no sinc quadrature), by adaptive Gauss-Kronrod
+# ---------------------------------------------------------------------------------------
+
+def exact_cell_average(kind: int, param: float, d: Sequence[float], h: float) -> float:
+    """(1/h^3) int_cell p(|x|) dx for the cell centred at displacement d (eq. ``galten`` with
+    cell averages) written as int_0^inf a(t) prod_l b(t; d_l) dt (Sec. 2.1-2.2) and
+    integrated numerically in v = log t."""
+    from scipy.integrate import quad
+
+    def f(v):
+        t = math.exp(v)
+        a = float(transform_density(kind, param, np.array([t]))[0])
+        if a == 0.0:
+            return 0.0
+        b = 1.0
+        for dl in d:
+            b *= float(cell_average_gauss(np.array([t]), np.array([dl]), h)[0])
+        return a * b * t
+
+    edges = np.linspace(-30.0, 30.0, 61)
+    total = 0.0
+    for lo, hi in zip(edges[:-1], edges[1:]):
+        total += quad(f, lo, hi, epsabs=0.0, epsrel=1e-12, limit=200)[0]
+    return total
+
+
+# ---------------------------------------------------------------------------------------
+# the same method end to end (CPU, FP64)
+# ---------------------------------------------------------------------------------------
+
+def points_to_cells(xyz: np.ndarray, h: float, N: Sequence[int]) -> np.ndarray:
+    """Cell index triples of sample points (same rounding as the sites)."""
+    xyz = np.asarray(xyz, dtype=np.float64)
+    return np.stack([snap(xyz[:, a], h, N[a]) for a in range(3)], axis=1)
+
+
+def canonical_pipeline(problem, xyz: np.ndarray):
+    """Nodes -> reference vectors -> 1D shift-sums -> potential at sample points, for a
+    defect-free problem (the steps of Thm ``thm:sumCaseE`` (A))."""
+    t, w = quadrature_of(problem)
+    fac = assembled_canonical(problem, t, w)
+    pts = points_to_cells(xyz, problem.h, problem.N)
+    v = np.zeros(len(pts))
+    for blk, f in zip(problem.blocks, fac):
+        v += blk.charge * canonical_eval(f, pts)
+    return fac, v

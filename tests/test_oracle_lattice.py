@@ -1,0 +1,301 @@
+"""Pins of the oracle's lattice bookkeeping, assembled canonical sum (Thm thm:sumCaseE (A)),
+defect algebra (Sec. 4.1) and RHOSVD (Def. def:RHOSVD, Appendix theorem).  CPU only."""
+import json
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def exact_snap(coord: Fraction, h: Fraction, N: int) -> int:
+    """Round-half-away-from-zero of coord/h in exact rational arithmetic."""
+    u = coord / h
+    j = math.floor(abs(u) + Fraction(1, 2))
+    return (j if u >= 0 else -j) + (N - 1) // 2
+
+
+def small_problem(kind=W.NEWTON, param=0.0, L=(3, 4, 2), N=(33, 41, 29), h=0.37, M=12,
+                  center=(0.1, -0.2, 0.05), defects=(), blocks=None):
+    blocks = blocks or [W.Block(L, (1.0, 1.0, 1.0), center)]
+    return W.Problem("small", kind, param, M, N, h, blocks, list(defects))
+
+
+# ------------------------------------------------------------------------------------------
+# bookkeeping
+# ------------------------------------------------------------------------------------------
+
+def test_cfg1_offsets_exact():
+    p = W.config(1)
+    offs = O.block_offsets(p.blocks[0], p.h, p.N)
+    with open(os.path.join(GOLDEN, "closed_forms.json")) as f:
+        g = json.load(f)["cfg1_snapped_offsets"]["value"]
+    for a in range(3):
+        assert offs[a].tolist() == g
+    # and from first principles with rationals
+    h = Fraction(3, 32)
+    exp = [exact_snap(Fraction(2 * k - 3, 2), h, 129) for k in range(4)]
+    assert exp == g
+
+
+@pytest.mark.parametrize("c", [1, 2, 3, 4])
+def test_config_offsets_match_rational_arithmetic(c):
+    p = W.config(c)
+    for blk in p.blocks:
+        offs = O.block_offsets(blk, p.h, p.N)
+        for a in range(3):
+            h = Fraction(p.h)           # the double h exactly
+            L = blk.L[a]
+            exp = [exact_snap((Fraction(k) - Fraction(L - 1, 2)) * Fraction(blk.b[a]) + Fraction(blk.center[a]),
+                              h, p.N[a]) for k in range(L)]
+            assert offs[a].tolist() == exp
+
+
+def test_centred_offsets_are_mirror_symmetric():
+    for c in (1, 2, 3):
+        p = W.config(c)
+        o = O.block_offsets(p.blocks[0], p.h, p.N)[0]
+        assert np.array_equal(o + o[::-1], np.full_like(o, p.N[0] - 1))
+
+
+def test_out_of_box_raises():
+    with pytest.raises(O.OutOfBox):
+        O.snap(np.array([10.0]), 0.5, 21)          # cell 30 of a 21-cell axis
+    assert O.snap(np.array([5.0, -5.0]), 0.5, 21).tolist() == [20, 0]
+
+
+def test_charges_apply_defects():
+    p = small_problem(defects=[W.Defect(0, (1, 2, 0), -1.0), W.Defect(0, (0, 0, 1), 0.75)])
+    idx, Z = O.charges(p)
+    assert len(Z) == 24 and Z.sum() == 24 - 1 + 0.75
+    assert Z[(1 * 4 + 2) * 2 + 0] == 0.0 and Z[1] == 1.75
+
+
+# ------------------------------------------------------------------------------------------
+# Theorem A: the assembled rank-R canonical tensor equals the brute-force sum
+# ------------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("kind,param", [(W.NEWTON, 0.0), (W.YUKAWA, 0.5), (W.SLATER, 1.0)])
+def test_assembled_equals_brute_force_full_grid(kind, param):
+    p = small_problem(kind, param)
+    t, w = O.quadrature_of(p)
+    fac = O.assembled_canonical(p, t, w)[0]
+    assert all(f.shape == (len(t), n) for f, n in zip(fac, p.N))      # rank stays R
+    V = np.einsum("qi,qj,qk->ijk", *fac)
+    Vb = O.brute_force_grid(p, t=t, w=w)
+    assert np.max(np.abs(V - Vb)) <= 1e-13 * np.max(np.abs(Vb))
+
+
+def test_concatenation_to_sum_rule():
+    # eq. conc2sum: CP tensors sharing two factor matrices add by adding the third factors
+    rng = np.random.default_rng(0)
+    A1, A2, A3, B3 = (rng.standard_normal((5, n)) for n in (4, 6, 7, 7))
+    full = lambda X, Y, Z: np.einsum("qi,qj,qk->ijk", X, Y, Z)
+    assert np.allclose(full(A1, A2, A3) + full(A1, A2, B3), full(A1, A2, A3 + B3), atol=1e-13)
+
+
+def test_lattice_symmetry_cubic():
+    p = W.Problem("sym", W.NEWTON, 0.0, 16, (41, 41, 41), 0.3, [W.cubic_block(5, 1.0)])
+    t, w = O.quadrature_of(p)
+    fac = O.assembled_canonical(p, t, w)[0]
+    V = np.einsum("qi,qj,qk->ijk", *fac)
+    scale = np.max(V)
+    assert np.max(np.abs(V - V[::-1, :, :])) <= 1e-14 * scale
+    assert np.max(np.abs(V - V.transpose(1, 0, 2))) <= 1e-14 * scale
+    assert np.max(np.abs(V - V.transpose(2, 1, 0))) <= 1e-14 * scale
+
+
+def test_far_field_matches_point_charges():
+    # far from every charge the lattice potential is sum_c 1/|x - c| (snapped positions)
+    p = W.Problem("ff", W.NEWTON, 0.0, 40, (257, 257, 257), 0.125, [W.cubic_block(3, 1.0)])
+    t, w = O.quadrature_of(p)
+    fac = O.assembled_canonical(p, t, w)[0]
+    idx, Z = O.charges(p)
+    pts = np.array([[0, 0, 0], [10, 200, 128], [250, 30, 60], [128, 128, 0]])
+    got = O.canonical_eval(fac, pts)
+    x = (pts - 128) * p.h
+    c = (idx - 128) * p.h
+    ref = np.array([np.sum(Z / np.linalg.norm(xi - c, axis=1)) for xi in x])
+    assert np.max(np.abs(got / ref - 1)) < 2e-5
+
+
+def test_canonical_pipeline_matches_brute_force_at_points():
+    p = small_problem(L=(4, 3, 5), N=(45, 37, 51), h=0.29)
+    B = W.half_widths(p)
+    xyz = np.random.default_rng(3).uniform(-np.array(B), np.array(B), size=(40, 3))
+    _, v = O.canonical_pipeline(p, xyz)
+    pts = O.points_to_cells(xyz, p.h, p.N)
+    vb = O.brute_force_points(p, pts)
+    assert np.max(np.abs(v - vb)) <= 1e-13 * np.max(np.abs(vb))
+
+
+# ------------------------------------------------------------------------------------------
+# defects (Sec. 4.1, eq. Can_LatticeSum_full)
+# ------------------------------------------------------------------------------------------
+
+def test_vacancy_invariant():
+    # full lattice minus vacancy windows equals the direct sum over the remaining charges
+    rng = np.random.default_rng(5)
+    base = small_problem(L=(4, 3, 3), N=(31, 27, 29), h=0.41)
+    defects = W.draw_defects(rng, base.blocks, 5, 0)
+    p = small_problem(L=(4, 3, 3), N=(31, 27, 29), h=0.41, defects=defects)
+    xi, A = O.canonical_terms(p)
+    V = O.cp_full(xi, A)
+    Vb = O.brute_force_grid(p)
+    assert np.max(np.abs(V - Vb)) <= 1e-13 * np.max(np.abs(Vb))
+    R = len(O.quadrature_of(p)[0])
+    assert len(xi) == R * (1 + len(defects))                  # eq. RankCan_def: r <= r0 + sum r_s
+
+
+def test_linearity_in_charge_change():
+    p0 = small_problem()
+    pts = np.array([[3, 5, 7], [16, 20, 14], [30, 2, 25]])
+    base = O.brute_force_points(p0, pts)
+    vals = []
+    for dz in (0.25, 0.5, 1.0):
+        p = small_problem(defects=[W.Defect(0, (1, 1, 1), dz), W.Defect(0, (2, 3, 0), -dz)])
+        xi, A = O.canonical_terms(p)
+        vals.append(np.einsum("v,pv,pv,pv->p", xi, A[0][pts[:, 0]], A[1][pts[:, 1]], A[2][pts[:, 2]]) - base)
+    assert np.allclose(vals[1], 2 * vals[0], rtol=1e-11, atol=1e-13)
+    assert np.allclose(vals[2], 4 * vals[0], rtol=1e-11, atol=1e-13)
+
+
+# ------------------------------------------------------------------------------------------
+# RHOSVD
+# ------------------------------------------------------------------------------------------
+
+def _defected(nvac=4, nimp=3, kind=W.NEWTON, param=0.0, seed=11):
+    rng = np.random.default_rng(seed)
+    base = small_problem(kind, param, L=(4, 4, 3), N=(29, 31, 27), h=0.43)
+    defects = W.draw_defects(rng, base.blocks, nvac, nimp)
+    return small_problem(kind, param, L=(4, 4, 3), N=(29, 31, 27), h=0.43, defects=defects)
+
+
+@pytest.mark.parametrize("eps", [1e-2, 1e-4, 1e-6])
+def test_rhosvd_bound_and_relative_error(eps):
+    p = _defected()
+    xi, A = O.canonical_terms(p)
+    res = O.rhosvd(xi, A, eps=eps)
+    Afull = O.cp_full(xi, A)
+    T = O.tucker_full(res.core, res.Z)
+    err = np.linalg.norm(Afull - T)
+    nA = np.linalg.norm(Afull)
+    assert abs(res.norm_A - nA) <= 1e-12 * nA
+    assert err <= res.bound * (1 + 1e-9) + 1e-12 * nA        # Appendix theorem (d)
+    assert err <= eps * nA * (1 + 1e-9)                        # the certified truncation rule
+    for Z in res.Z:
+        assert np.allclose(Z.T @ Z, np.eye(Z.shape[1]), atol=1e-13)
+    # Pythagoras: the core is an orthogonal projection of A
+    assert abs(np.linalg.norm(res.core) ** 2 + err ** 2 - nA ** 2) <= 1e-10 * nA ** 2
+
+
+def test_rhosvd_core_is_projection_of_full_tensor():
+    # Appendix (c): mu_k = <w1_k1 (x) w2_k2 (x) w3_k3, A>, computed here from the full tensor
+    p = _defected(kind=W.YUKAWA, param=0.5)
+    xi, A = O.canonical_terms(p)
+    res = O.rhosvd(xi, A, eps=1e-5)
+    Afull = O.cp_full(xi, A)
+    mu = np.einsum("ijk,ia,jb,kc->abc", Afull, *res.Z, optimize=True)
+    assert np.max(np.abs(mu - res.core)) <= 1e-12 * np.max(np.abs(mu))
+
+
+def test_rhosvd_full_rank_is_exact():
+    p = _defected(nvac=2, nimp=1)
+    xi, A = O.canonical_terms(p)
+    full = [min(a.shape) for a in A]
+    res = O.rhosvd(xi, A, ranks=full)
+    Afull = O.cp_full(xi, A)
+    assert np.max(np.abs(O.tucker_full(res.core, res.Z) - Afull)) <= 1e-12 * np.max(np.abs(Afull))
+    assert all(r <= np.linalg.matrix_rank(a) + 1 for r, a in zip(full, A))
+
+
+def test_perfect_lattice_rank_at_most_R():
+    # Thm A: a perfect lattice keeps the reference rank R in every mode
+    p = small_problem(L=(4, 4, 3), N=(29, 31, 27), h=0.43)
+    xi, A = O.canonical_terms(p)
+    R = len(xi)
+    res = O.rhosvd(xi, A, eps=1e-14)
+    assert all(r <= R for r in res.ranks)
+
+
+def test_sublattice_vacancies_rank_at_most_2R():
+    # Sec. 4.4, class (D) / Fig. fig:Vacance_L_O: vacancies on a tensor sub-lattice, written as a
+    # second block of charge -1, give Tucker ranks <= 2R; the sum equals the direct sum
+    big = W.Block((8, 8, 2), (1.0, 1.0, 1.0), (0.0, 0.0, 0.0))
+    vac = W.Block((2, 2, 1), (4.0, 4.0, 1.0), (0.5, 0.5, -0.5), charge=-1.0)
+    p = W.Problem("sub", W.NEWTON, 0.0, 14, (45, 45, 29), 0.5, [big, vac])
+    xi, A = O.canonical_terms(p)
+    R = len(O.quadrature_of(p)[0])
+    res = O.rhosvd(xi, A, eps=1e-12)
+    assert all(r <= 2 * R for r in res.ranks)
+    Afull = O.cp_full(xi, A)
+    Vb = O.brute_force_grid(p)
+    assert np.max(np.abs(Afull - Vb)) <= 1e-13 * np.max(np.abs(Vb))
+    # equivalently: the same sites removed one by one as vacancies
+    offs_big = O.block_offsets(big, p.h, p.N)
+    offs_vac = O.block_offsets(vac, p.h, p.N)
+    sites = []
+    for i in offs_vac[0]:
+        for j in offs_vac[1]:
+            for k in offs_vac[2]:
+                sites.append((int(np.where(offs_big[0] == i)[0][0]), int(np.where(offs_big[1] == j)[0][0]),
+                              int(np.where(offs_big[2] == k)[0][0])))
+    p2 = W.Problem("sub2", W.NEWTON, 0.0, 14, (45, 45, 29), 0.5, [big], [W.Defect(0, s, -1.0) for s in sites])
+    xi2, A2 = O.canonical_terms(p2)
+    assert np.max(np.abs(O.cp_full(xi2, A2) - Afull)) <= 1e-13 * np.max(np.abs(Vb))
+
+
+def test_single_kernel_tucker_rank_ballpark():
+    # soft pin from Table Table_Times: the Tucker rank of one Newton kernel at eps = 1e-6 is
+    # about 6..12 on the paper's grids; RHOSVD (no ALS) of the centred reference
+    with open(os.path.join(GOLDEN, "paper_numbers.json")) as f:
+        ranks = json.load(f)["table_times"]["tucker_rank"]
+    p = W.Problem("one", W.NEWTON, 0.0, 40, (257, 257, 257), 8.75 / 256, [W.cubic_block(1)])
+    xi, A = O.canonical_terms(p)
+    res = O.rhosvd(xi, A, eps=1e-6)
+    assert min(ranks) - 2 <= max(res.ranks) <= 2 * max(ranks)
+
+
+def test_tucker_evaluators_agree_with_direct_triple_sum():
+    rng = np.random.default_rng(2)
+    core = rng.standard_normal((3, 2, 4))
+    Z = [rng.standard_normal((n, r)) for n, r in zip((5, 6, 7), core.shape)]
+    full = O.tucker_full(core, Z)
+    for (i, j, k) in [(0, 0, 0), (4, 5, 6), (2, 3, 1)]:
+        s = 0.0
+        for a in range(3):
+            for b in range(2):
+                for c in range(4):
+                    s += core[a, b, c] * Z[0][i, a] * Z[1][j, b] * Z[2][k, c]
+        assert abs(full[i, j, k] - s) < 1e-12
+    pts = np.array([[1, 2, 3], [4, 0, 6]])
+    assert np.allclose(O.tucker_points(core, Z, pts), full[pts[:, 0], pts[:, 1], pts[:, 2]], atol=1e-13)
+    tile = O.tucker_tile(core, Z, [np.arange(1, 4), np.arange(2, 6), np.arange(0, 7)])
+    assert np.allclose(tile, full[1:4, 2:6, 0:7], atol=1e-13)
+
+
+def test_snap_rounds_halves_away_from_zero():
+    # exact ties: x/h = +-2.5 -> +-3 (not banker's rounding), +-0.5 -> +-1
+    assert O.snap(np.array([1.25, -1.25, 0.25, -0.25, 0.0]), 0.5, 21).tolist() == [13, 7, 11, 9, 10]
+
+
+def test_truncation_rule_is_smallest_certified_rank():
+    # the chosen r_l is the smallest rank whose discarded tail is <= eps ||A|| / (3 ||xi||);
+    # singular values recomputed here from the eigenvalues of A A^T (a different route)
+    p = _defected(nvac=5, nimp=2)
+    xi, A = O.canonical_terms(p)
+    for eps in (1e-3, 1e-5):
+        res = O.rhosvd(xi, A, eps=eps)
+        thr = eps * res.norm_A / (3.0 * np.linalg.norm(xi))
+        for a in range(3):
+            lam = np.sort(np.clip(np.linalg.eigvalsh(A[a] @ A[a].T), 0, None))[::-1]
+            tail = lambda r: math.sqrt(lam[r:].sum())
+            r = res.ranks[a]
+            assert tail(r) <= thr * (1 + 1e-6) + 1e-12
+            assert r == 1 or tail(r - 1) > thr * (1 - 1e-6)
