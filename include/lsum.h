@@ -1,0 +1,223 @@
+/*
+ * lsum.h -- C ABI of the MI355X (gfx950) grid-based lattice-sum library.
+ *
+ * The library computes the projected potential of charges on 3D lattices (with vacancies,
+ * impurities and unions of rectangular blocks) as a low-rank tensor on a fine N1 x N2 x N3
+ * grid, following V. Khoromskaia, B. N. Khoromskij, "Tucker tensor method for fast
+ * grid-based summation of long-range potentials on 3D lattices with defects"
+ * (arXiv:1411.1994):
+ *
+ *   1. sinc-quadrature nodes/weights of the kernel's Laplace-Gauss transform (Sec. 2.1-2.2),
+ *   2. reference canonical vectors by cell-average collocation on the doubled box (Sec. 3.1),
+ *   3. assembled 1D shift-sums over the lattice (Thm thm:sumCaseE (A), eq. EwaldTensorGl),
+ *   4. defects and blocks as algebraic sums of canonical tensors (Sec. 4.1-4.2),
+ *   5. RHOSVD eps-rank reduction to Tucker format (Def. def:RHOSVD, Appendix theorem),
+ *   6. Tucker/canonical evaluation on grid tiles and at points (eq. Tucker_singePot).
+ *
+ * Conventions used by every call:
+ *   - Grid: N[l] odd cells per axis l, one mesh size h; cell i of axis l is centred at
+ *     (i - (N[l]-1)/2) h.  Cell values are cell averages of the potential.
+ *   - Reference vectors: R rows of length 2*N_ref-1 (row stride ldg); entry m of row q is
+ *     w_q^(1/3) times the cell average of exp(-t_q^2 x^2) over the cell at displacement
+ *     (m - (N_ref-1)) h.  An axis with N[l] <= N_ref uses the same rows.
+ *   - Lattice block: L[3] sites per axis, spacing b[3], geometric centre center[3], every
+ *     site carrying charge `charge`; site k of axis l sits at (k-(L-1)/2) b + center and is
+ *     snapped to the cell j + (N-1)/2, j = sign(x/h) floor(|x/h| + 1/2) (halves away from
+ *     zero).  A snapped site outside [0, N-1] is an error (LSUM_E_OUT_OF_BOX).
+ *   - Canonical factor matrices are stored vector-major: R rows of N[l] doubles (row q is
+ *     the q-th canonical vector of axis l).  Tucker factors Z_l are stored the same way:
+ *     r_l rows of N[l] doubles (row a is the a-th orthonormal Tucker vector).  The Tucker
+ *     core is r1 x r2 x r3 with the last index fastest.
+ *   - Errors: every call returns LSUM_OK (0) or a negative LSUM_E_* code; lsum_last_error()
+ *     returns a message for the calling thread.  No C++ exception crosses this boundary.
+ *   - Pointers named *_dev are device (HBM) pointers on the context's device, allocated and
+ *     owned by the caller unless stated otherwise; all other pointers are host pointers.
+ *     `stream` is a hipStream_t passed as void* (NULL: the context's own stream).  Calls
+ *     taking a stream are asynchronous with respect to the host unless stated otherwise.
+ */
+#ifndef LSUM_H
+#define LSUM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------------------------ */
+#define LSUM_OK 0
+#define LSUM_E_INVALID (-1)    /* bad argument: even N, M < 1, unknown kernel, bad eps, ...   */
+#define LSUM_E_OUT_OF_BOX (-2) /* a snapped site or point lies outside the grid               */
+#define LSUM_E_DUP_DEFECT (-3) /* two defects at the same site                                */
+#define LSUM_E_NOMEM (-4)      /* the job can never fit the context's HBM budget              */
+#define LSUM_E_BUSY (-5)       /* non-blocking submit on a full queue                         */
+#define LSUM_E_CANCELLED (-6)  /* the request was cancelled before it ran                     */
+#define LSUM_E_DEVICE (-7)     /* a HIP runtime error                                         */
+#define LSUM_E_TIMEOUT (-8)    /* lsum_wait ran out of time (the request keeps running)       */
+#define LSUM_E_STATE (-9)      /* result not available in this state / format                 */
+#define LSUM_E_NOCONV (-10)    /* the Jacobi SVD did not converge within its sweep limit      */
+
+/* ---- problem description ---------------------------------------------------------------- */
+enum { LSUM_NEWTON = 0, LSUM_YUKAWA = 1, LSUM_SLATER = 2 };
+enum { LSUM_FP64 = 0, LSUM_FP32 = 1, LSUM_BF16X3 = 2 };
+
+/* Kernel p(r): Newton 1/r, Yukawa exp(-param r)/r, Slater exp(-param r) (Sec. 2.2).
+ * Quadrature: u_k = k h_u, t_k = sinh(u_k)/s, k = 0..M (trapezoid rule of eq. hM after the
+ * substitution t = sinh(u)/s, folded onto k >= 0).  h_u <= 0 or s <= 0 select defaults:
+ * s = h sqrt(sum_l (N_l-1)^2) / 4, h_u = 0.30 (Slater) or 0.35 (Newton, Yukawa). */
+typedef struct {
+    int kind;
+    double param;
+    int M;
+    double h_u;
+    double s;
+} lsum_kernel;
+
+typedef struct {
+    int L[3];
+    double b[3];
+    double center[3];
+    double charge;   /* charge of every site; -1 describes a tensor sub-lattice of vacancies */
+} lsum_block;
+
+/* A change dZ of the charge at site `site` (indices 0..L-1 per axis) of block `block`:
+ * dZ = -charge is a vacancy, dZ = Z - charge an impurity of charge Z (Sec. 4.1). */
+typedef struct {
+    int block;
+    int site[3];
+    double dZ;
+} lsum_defect;
+
+typedef struct {
+    lsum_kernel kernel;
+    int N[3];                 /* odd cell counts                                               */
+    double h;                 /* mesh size                                                     */
+    int n_blocks;
+    const lsum_block* blocks;
+    int n_defects;
+    const lsum_defect* defects;
+    double eps;               /* > 0: RHOSVD to a Tucker tensor with relative Frobenius error
+                                 <= eps (certified); <= 0: canonical output, no reduction     */
+    int precision;            /* arithmetic of projection, core and tile (LSUM_FP64/FP32/BF16X3);
+                                 quadrature, collocation, shift-sums, SVD and truncation are
+                                 always FP64                                                   */
+    int tile_lo[3];           /* optional reconstruction tile: cells [lo, lo+T) per axis      */
+    int tile_T[3];            /* T = 0: no tile                                                */
+} lsum_problem;
+
+/* ---- host-side steps (FP64 / integer, no device work) ----------------------------------- */
+
+/* Sinc quadrature of the kernel's Laplace-Gauss transform (Sec. 2.1 eqs. laplace, hM,
+ * sinc_Newt; Sec. 2.2 eqs. LalpNewt, LalpYukawa with exponent param^2/(4 t^2), LalpSlater).
+ * Writes up to `cap` nodes t[] and weights w[] (nodes with w < 1e-18 max w are dropped) and
+ * the rank R = number written.  Needs N and h only for the default (h_u, s). */
+int lsum_nodes(const lsum_kernel* k, const int N[3], double h, double* t, double* w, int cap,
+               int* R);
+
+/* Snapped cell indices of a block's sites (windowing offsets of Sec. 3.1 eq. sub_tens for the
+ * centred lattice of Sec. 3.2): offs[0..L0-1] axis 0, then L1 for axis 1, then L2 for axis 2.
+ * Bit-exact IEEE FP64 arithmetic: x = (k - (L-1)/2) * b + center; u = x / h. */
+int lsum_block_offsets(const lsum_block* blk, const int N[3], double h, int32_t* offs);
+
+/* ---- context ----------------------------------------------------------------------------- */
+typedef struct lsum_ctx_s* lsum_ctx;
+typedef struct lsum_req_s* lsum_req;
+
+/* Create a context on HIP device `device` with `hbm_budget_bytes` of HBM for request data
+ * (0: 80% of the device's free memory) and `n_slots` concurrent request slots (each slot a
+ * HIP stream and a worker thread; 0: 4).  The context owns its streams, caches and workers. */
+int lsum_create(lsum_ctx* ctx, int device, size_t hbm_budget_bytes, int n_slots);
+int lsum_destroy(lsum_ctx ctx);
+const char* lsum_last_error(void);
+
+/* ---- device steps of the path (each one kernel family, on `stream`) --------------------- */
+
+/* Reference vectors (Sec. 2.1 b(t_k); Sec. 3.1 eq. master_pot): G_dev[q*ldg + m],
+ * q < R, m < 2*N_ref-1, from host nodes t[R], weights w[R].  ldg >= 2*N_ref-1. */
+int lsum_collocate(lsum_ctx ctx, void* stream, int R, const double* t, const double* w,
+                   int N_ref, double h, double* G_dev, int ldg);
+
+/* Assembled 1D sums (Thm thm:sumCaseE (A)): U_dev[q*ldu + i] = sum_k G[q*ldg + i - c_k +
+ * N_ref - 1] for i < N_axis, over the n_sites host cell indices c_k (0 <= c_k < N_axis <=
+ * N_ref).  Summation order k = 0..n_sites-1 in FP64. */
+int lsum_shift_sum(lsum_ctx ctx, void* stream, int R, const double* G_dev, int ldg, int N_ref,
+                   int N_axis, int n_sites, const int32_t* sites, double* U_dev, int ldu);
+
+/* Potential of a canonical sum at points (eq. CP_form evaluated pointwise):
+ * out_dev[p] = sum_f lam_f sum_q prod_l U_f,l[q, i_l(p)] over n_fac factor sets, where
+ * i_l(p) snaps xyz_dev[3p+l]; U_dev holds n_fac sets of 3 axis blocks, each R x ldu
+ * (set f, axis l at offset (3f+l)*R*ldu).  Points outside the grid yield NaN. */
+int lsum_sample_canonical(lsum_ctx ctx, void* stream, int n_fac, int R, const double* U_dev,
+                          int ldu, const double* lam, const int N[3], double h, int n_pts,
+                          const double* xyz_dev, double* out_dev);
+
+/* Truncated SVD of a side matrix (Def. def:RHOSVD): the D columns a_j (row j of A_dev, length
+ * N, stride lda) are rotated in place by a one-sided block-Jacobi SVD in FP64 until every
+ * pair of columns has relative coupling |a_i.a_j|/(|a_i||a_j|) <= tol (or lies below an
+ * absolute floor of 1e-30 of the matrix norm).  On return the rows of A_dev hold the rotated
+ * columns sorted by descending norm and sigma[0..D-1] (host) their norms; the leading rows
+ * divided by sigma are the left singular vectors.  Synchronous.  Returns LSUM_E_NOCONV after
+ * `max_sweeps` sweeps without convergence (results are still written). */
+int lsum_jacobi_svd(lsum_ctx ctx, void* stream, int D, int N, double* A_dev, int lda,
+                    double tol, int max_sweeps, double* sigma, int* sweeps);
+
+/* Dense contraction used by the projections Z^T A (Appendix theorem (c)) and the mode
+ * products of the Tucker reconstruction (eq. Tucker_singePot): C(m,n) = alpha * sum_k A(m,k)
+ * B(k,n) + beta * C(m,n) with A(m,k) = A_dev[m*sam + k*sak], B(k,n) = B_dev[k*sbk + n*sbn],
+ * C(m,n) = C_dev[m*scm + n*scn] (element strides).  prec: LSUM_FP64 (double operands, FP64
+ * MFMA), LSUM_FP32 (float operands, FP32 MFMA) or LSUM_BF16X3 (float operands split into two
+ * bfloat16 parts, three BF16 MFMA products, FP32 accumulation).  Synchronous. */
+int lsum_contract(lsum_ctx ctx, void* stream, int prec, int m, int n, int k, const void* A_dev,
+                  long sam, long sak, const void* B_dev, long sbk, long sbn, void* C_dev, long scm,
+                  long scn, double alpha, double beta);
+
+/* ---- requests (the whole path for one problem) ------------------------------------------ */
+
+/* Validate and enqueue a problem; the caller's arrays are deep-copied, so they may be freed on
+ * return.  Non-blocking: LSUM_E_BUSY if `nonblocking` and the queue is full.  The request is
+ * admitted when its planned HBM footprint fits the free budget (LSUM_E_NOMEM if it can never
+ * fit).  Requests run concurrently on the context's slots. */
+int lsum_submit(lsum_ctx ctx, const lsum_problem* p, int nonblocking, lsum_req* req);
+/* Wait up to timeout_ms (< 0: forever); returns the request's final status or LSUM_E_TIMEOUT. */
+int lsum_wait(lsum_req req, int timeout_ms);
+/* Cancel a request that has not started (LSUM_E_STATE once it runs). */
+int lsum_cancel(lsum_req req);
+
+typedef struct {
+    int status;        /* LSUM_OK, a negative error, or 1 while queued/running               */
+    int R;             /* quadrature rank                                                    */
+    int n_terms;       /* canonical terms R * (n_blocks + n_defects)                         */
+    int is_tucker;     /* 1 if reduced to Tucker format                                      */
+    int r[3];          /* Tucker ranks                                                       */
+    int D[3];          /* distinct side-matrix columns per mode                              */
+    double norm_A;     /* Frobenius norm of the canonical tensor                             */
+    double norm_xi;    /* ||xi||                                                             */
+    double bound;      /* ||xi|| sum_l tail_l: certified bound on ||A - A0||_F              */
+    double rel_bound;  /* bound / norm_A                                                     */
+    double t_queue_ms, t_run_ms;  /* enqueue->start, start->finish                            */
+} lsum_info;
+int lsum_get_info(lsum_req req, lsum_info* info);
+
+/* Canonical factors of block `block` (vector-major, R rows of N[l] each) into U[3][R*N[l]]
+ * (host, or device if on_device) and the weight of the block (its charge). */
+int lsum_get_canonical(lsum_req req, int block, double* U0, double* U1, double* U2, int on_device);
+/* Tucker factors Z_l (r_l rows of N[l]) and core (r1*r2*r3, last index fastest), FP64. */
+int lsum_get_tucker(lsum_req req, double* Z0, double* Z1, double* Z2, double* core, int on_device);
+/* Singular values of the three side matrices (D[l] each, descending). */
+int lsum_get_sigma(lsum_req req, double* s0, double* s1, double* s2);
+/* Potential at n points xyz[3n]: the canonical sum with all defects, or the Tucker tensor.
+ * Synchronous. */
+int lsum_sample(lsum_req req, int n, const double* xyz, double* out, int on_device);
+/* The reconstructed tile (T0*T1*T2 values, last index fastest) as float (precision FP32 or
+ * BF16X3) or double (FP64); `elem_size` must match (4 or 8). */
+int lsum_get_tile(lsum_req req, void* out, int elem_size, int on_device);
+/* JSON with ranks, sigma tails, bound, stage times (ms) and bytes; returns the needed length. */
+int lsum_get_stats(lsum_req req, char* buf, size_t len);
+/* Free the request's device results and the handle. */
+int lsum_release(lsum_req req);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LSUM_H */

@@ -1,0 +1,332 @@
+"""Python binding of the MI355X lattice-sum library (``include/lsum.h``).
+
+Argument marshalling only: every step of the computation runs in the HIP library
+``lib/liblsum.so``.  Importing this package loads that library and raises if it is missing;
+there is no fallback implementation.  Functions keep the C names (``lsum_*``); device
+pointers may be passed as integers or as objects with ``data_ptr()`` (e.g. torch tensors).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import json
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "lib", "liblsum.so")
+
+LSUM_OK = 0
+ERRORS = {-1: "INVALID", -2: "OUT_OF_BOX", -3: "DUP_DEFECT", -4: "NOMEM", -5: "BUSY", -6: "CANCELLED",
+          -7: "DEVICE", -8: "TIMEOUT", -9: "STATE", -10: "NOCONV"}
+NEWTON, YUKAWA, SLATER = 0, 1, 2
+FP64, FP32, BF16X3 = 0, 1, 2
+
+# every symbol declared in include/lsum.h
+SYMBOLS = ["lsum_nodes", "lsum_block_offsets", "lsum_create", "lsum_destroy", "lsum_last_error",
+           "lsum_collocate", "lsum_shift_sum", "lsum_sample_canonical", "lsum_jacobi_svd",
+           "lsum_contract",
+           "lsum_submit", "lsum_wait", "lsum_cancel", "lsum_get_info", "lsum_get_canonical",
+           "lsum_get_tucker", "lsum_get_sigma", "lsum_sample", "lsum_get_tile", "lsum_get_stats",
+           "lsum_release"]
+
+
+class LsumError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"lsum error {code} ({ERRORS.get(code, '?')}): {msg}")
+        self.code = code
+
+
+class lsum_kernel(C.Structure):
+    _fields_ = [("kind", C.c_int), ("param", C.c_double), ("M", C.c_int), ("h_u", C.c_double),
+                ("s", C.c_double)]
+
+
+class lsum_block(C.Structure):
+    _fields_ = [("L", C.c_int * 3), ("b", C.c_double * 3), ("center", C.c_double * 3),
+                ("charge", C.c_double)]
+
+
+class lsum_defect(C.Structure):
+    _fields_ = [("block", C.c_int), ("site", C.c_int * 3), ("dZ", C.c_double)]
+
+
+class lsum_problem(C.Structure):
+    _fields_ = [("kernel", lsum_kernel), ("N", C.c_int * 3), ("h", C.c_double),
+                ("n_blocks", C.c_int), ("blocks", C.POINTER(lsum_block)),
+                ("n_defects", C.c_int), ("defects", C.POINTER(lsum_defect)),
+                ("eps", C.c_double), ("precision", C.c_int), ("tile_lo", C.c_int * 3),
+                ("tile_T", C.c_int * 3)]
+
+
+class lsum_info(C.Structure):
+    _fields_ = [("status", C.c_int), ("R", C.c_int), ("n_terms", C.c_int), ("is_tucker", C.c_int),
+                ("r", C.c_int * 3), ("D", C.c_int * 3), ("norm_A", C.c_double),
+                ("norm_xi", C.c_double), ("bound", C.c_double), ("rel_bound", C.c_double),
+                ("t_queue_ms", C.c_double), ("t_run_ms", C.c_double)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_1411_1994_amd/build.py` "
+                          "(there is no non-HIP implementation)")
+    lib = C.CDLL(LIB_PATH)
+    P, I, D, VP = C.POINTER, C.c_int, C.c_double, C.c_void_p
+    sig = {
+        "lsum_nodes": (I, [P(lsum_kernel), P(I), D, P(D), P(D), I, P(I)]),
+        "lsum_block_offsets": (I, [P(lsum_block), P(I), D, P(C.c_int32)]),
+        "lsum_create": (I, [P(VP), I, C.c_size_t, I]),
+        "lsum_destroy": (I, [VP]),
+        "lsum_last_error": (C.c_char_p, []),
+        "lsum_collocate": (I, [VP, VP, I, P(D), P(D), I, D, VP, I]),
+        "lsum_shift_sum": (I, [VP, VP, I, VP, I, I, I, I, P(C.c_int32), VP, I]),
+        "lsum_sample_canonical": (I, [VP, VP, I, I, VP, I, P(D), P(I), D, I, VP, VP]),
+        "lsum_jacobi_svd": (I, [VP, VP, I, I, VP, I, D, I, P(D), P(I)]),
+        "lsum_contract": (I, [VP, VP, I, I, I, I, VP, C.c_long, C.c_long, VP, C.c_long, C.c_long, VP,
+                              C.c_long, C.c_long, D, D]),
+        "lsum_submit": (I, [VP, P(lsum_problem), I, P(VP)]),
+        "lsum_wait": (I, [VP, I]),
+        "lsum_cancel": (I, [VP]),
+        "lsum_get_info": (I, [VP, P(lsum_info)]),
+        "lsum_get_canonical": (I, [VP, I, VP, VP, VP, I]),
+        "lsum_get_tucker": (I, [VP, VP, VP, VP, VP, I]),
+        "lsum_get_sigma": (I, [VP, P(D), P(D), P(D)]),
+        "lsum_sample": (I, [VP, I, VP, VP, I]),
+        "lsum_get_tile": (I, [VP, VP, I, I]),
+        "lsum_get_stats": (I, [VP, C.c_char_p, C.c_size_t]),
+        "lsum_release": (I, [VP]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+_lib = _load()
+
+
+def _check(rc: int) -> int:
+    if rc < 0:
+        msg = _lib.lsum_last_error()
+        raise LsumError(rc, msg.decode() if msg else "")
+    return rc
+
+
+def _ptr(x) -> Optional[int]:
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    if hasattr(x, "data_ptr"):
+        return int(x.data_ptr())
+    if isinstance(x, np.ndarray):
+        return x.ctypes.data
+    raise TypeError(f"cannot take a pointer of {type(x)}")
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _stream(s) -> Optional[int]:
+    if s is None:
+        return None
+    if isinstance(s, int):
+        return s
+    return int(s.cuda_stream)      # torch.cuda.Stream
+
+
+# ------------------------------------------------------------------------------------------
+# host-side steps
+# ------------------------------------------------------------------------------------------
+
+def lsum_nodes(kind: int, param: float, M: int, N: Sequence[int], h: float, h_u: float = 0.0,
+               s: float = 0.0):
+    k = lsum_kernel(kind, param, M, h_u, s)
+    t = np.zeros(M + 1)
+    w = np.zeros(M + 1)
+    R = C.c_int(0)
+    _check(_lib.lsum_nodes(C.byref(k), (C.c_int * 3)(*N), h, _dptr(t), _dptr(w), M + 1, C.byref(R)))
+    return t[:R.value].copy(), w[:R.value].copy()
+
+
+def _block(b) -> lsum_block:
+    return lsum_block((C.c_int * 3)(*b.L), (C.c_double * 3)(*b.b), (C.c_double * 3)(*b.center),
+                      float(getattr(b, "charge", 1.0)))
+
+
+def lsum_block_offsets(block, N: Sequence[int], h: float):
+    blk = _block(block)
+    out = np.zeros(sum(block.L), dtype=np.int32)
+    _check(_lib.lsum_block_offsets(C.byref(blk), (C.c_int * 3)(*N), h,
+                                   out.ctypes.data_as(C.POINTER(C.c_int32))))
+    L = block.L
+    return [out[:L[0]].copy(), out[L[0]:L[0] + L[1]].copy(), out[L[0] + L[1]:].copy()]
+
+
+# ------------------------------------------------------------------------------------------
+# context and device steps
+# ------------------------------------------------------------------------------------------
+
+class Context:
+    """A library context on one device: request slots, buffer pool, reference cache."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0, n_slots: int = 0):
+        h = C.c_void_p()
+        _check(_lib.lsum_create(C.byref(h), device, hbm_budget_bytes, n_slots))
+        self.handle = h
+
+    def close(self):
+        if self.handle:
+            _lib.lsum_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- device steps --------------------------------------------------------------------
+    def collocate(self, t: np.ndarray, w: np.ndarray, N_ref: int, h: float, G_dev, ldg: int, stream=None):
+        t = np.ascontiguousarray(t, dtype=np.float64)
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        _check(_lib.lsum_collocate(self.handle, _stream(stream), len(t), _dptr(t), _dptr(w), N_ref, h,
+                                   _ptr(G_dev), ldg))
+
+    def shift_sum(self, R: int, G_dev, ldg: int, N_ref: int, N_axis: int, sites: np.ndarray, U_dev,
+                  ldu: int, stream=None):
+        sites = np.ascontiguousarray(sites, dtype=np.int32)
+        _check(_lib.lsum_shift_sum(self.handle, _stream(stream), R, _ptr(G_dev), ldg, N_ref, N_axis,
+                                   len(sites), sites.ctypes.data_as(C.POINTER(C.c_int32)),
+                                   _ptr(U_dev), ldu))
+
+    def sample_canonical(self, n_fac: int, R: int, U_dev, ldu: int, lam: np.ndarray, N, h: float,
+                         n_pts: int, xyz_dev, out_dev, stream=None):
+        lam = np.ascontiguousarray(lam, dtype=np.float64)
+        _check(_lib.lsum_sample_canonical(self.handle, _stream(stream), n_fac, R, _ptr(U_dev), ldu,
+                                          _dptr(lam), (C.c_int * 3)(*N), h, n_pts, _ptr(xyz_dev),
+                                          _ptr(out_dev)))
+
+    def jacobi_svd(self, D: int, N: int, A_dev, lda: int, tol: float = 1e-12, max_sweeps: int = 40,
+                   stream=None):
+        sig = np.zeros(D)
+        sweeps = C.c_int(0)
+        rc = _lib.lsum_jacobi_svd(self.handle, _stream(stream), D, N, _ptr(A_dev), lda, tol, max_sweeps,
+                                  _dptr(sig), C.byref(sweeps))
+        _check(rc)
+        return sig, sweeps.value
+
+    def contract(self, prec: int, m: int, n: int, k: int, A_dev, sam: int, sak: int, B_dev, sbk: int,
+                 sbn: int, C_dev, scm: int, scn: int, alpha: float = 1.0, beta: float = 0.0, stream=None):
+        _check(_lib.lsum_contract(self.handle, _stream(stream), prec, m, n, k, _ptr(A_dev), sam, sak,
+                                  _ptr(B_dev), sbk, sbn, _ptr(C_dev), scm, scn, alpha, beta))
+
+    # -- requests -------------------------------------------------------------------------
+    def submit(self, problem, nonblocking: bool = False) -> "Request":
+        return Request(self, problem, nonblocking)
+
+
+def make_problem(p) -> tuple:
+    """A C ``lsum_problem`` from any object with the fields of ``workloads.Problem``; returns
+    (struct, keep-alive list)."""
+    blocks = (lsum_block * len(p.blocks))(*[_block(b) for b in p.blocks])
+    nd = len(p.defects)
+    defects = (lsum_defect * max(nd, 1))(*[lsum_defect(d.block, (C.c_int * 3)(*d.site), float(d.dZ))
+                                          for d in p.defects])
+    prob = lsum_problem(lsum_kernel(p.kind, float(p.param), p.M, float(getattr(p, "h_u", 0.0)),
+                                    float(getattr(p, "s", 0.0))),
+                        (C.c_int * 3)(*p.N), float(p.h), len(p.blocks),
+                        C.cast(blocks, C.POINTER(lsum_block)), nd,
+                        C.cast(defects, C.POINTER(lsum_defect)) if nd else None,
+                        float(p.eps), int(p.precision), (C.c_int * 3)(*p.tile_lo),
+                        (C.c_int * 3)(*p.tile_T))
+    return prob, [blocks, defects]
+
+
+class Request:
+    """One submitted problem (``lsum_submit`` ... ``lsum_release``)."""
+
+    def __init__(self, ctx: Context, problem, nonblocking: bool = False):
+        self.ctx = ctx
+        self.problem = problem
+        prob, keep = make_problem(problem)
+        h = C.c_void_p()
+        _check(_lib.lsum_submit(ctx.handle, C.byref(prob), 1 if nonblocking else 0, C.byref(h)))
+        self.handle = h
+
+    def wait(self, timeout_ms: int = -1) -> int:
+        rc = _lib.lsum_wait(self.handle, timeout_ms)
+        return _check(rc)
+
+    def cancel(self):
+        _check(_lib.lsum_cancel(self.handle))
+
+    def info(self) -> lsum_info:
+        inf = lsum_info()
+        _check(_lib.lsum_get_info(self.handle, C.byref(inf)))
+        return inf
+
+    def canonical(self, block: int = 0):
+        p = self.problem
+        inf = self.info()
+        U = [np.zeros((inf.R, n)) for n in p.N]
+        _check(_lib.lsum_get_canonical(self.handle, block, *[u.ctypes.data for u in U], 0))
+        return U
+
+    def tucker(self):
+        p = self.problem
+        inf = self.info()
+        r = list(inf.r)
+        Z = [np.zeros((r[l], p.N[l])) for l in range(3)]
+        core = np.zeros(tuple(r))
+        _check(_lib.lsum_get_tucker(self.handle, *[z.ctypes.data for z in Z], core.ctypes.data, 0))
+        return Z, core
+
+    def sigma(self):
+        inf = self.info()
+        s = [np.zeros(inf.D[l]) for l in range(3)]
+        _check(_lib.lsum_get_sigma(self.handle, *[_dptr(x) for x in s]))
+        return s
+
+    def sample(self, xyz, out=None, on_device: bool = False):
+        if on_device:
+            n = int(xyz.shape[0])
+            _check(_lib.lsum_sample(self.handle, n, _ptr(xyz), _ptr(out), 1))
+            return out
+        xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+        res = np.zeros(xyz.shape[0])
+        _check(_lib.lsum_sample(self.handle, xyz.shape[0], xyz.ctypes.data, res.ctypes.data, 0))
+        return res
+
+    def tile(self):
+        p = self.problem
+        dt = np.float64 if p.precision == FP64 else np.float32
+        out = np.zeros(tuple(p.tile_T), dtype=dt)
+        _check(_lib.lsum_get_tile(self.handle, out.ctypes.data, out.itemsize, 0))
+        return out
+
+    def stats(self) -> dict:
+        n = _lib.lsum_get_stats(self.handle, None, 0)
+        buf = C.create_string_buffer(n + 16)
+        _lib.lsum_get_stats(self.handle, buf, n + 16)
+        return json.loads(buf.value.decode())
+
+    def release(self):
+        if self.handle:
+            _lib.lsum_release(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:
+            pass

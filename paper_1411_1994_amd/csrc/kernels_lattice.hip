@@ -1,0 +1,383 @@
+// HIP kernels (gfx950) for the lattice stages: cell-average collocation of the quadrature
+// Gaussians, assembled 1D shift-sums, side-matrix column gathering, and point evaluation.
+// All arithmetic is FP64.  These stages stream memory (no dense contraction), so they use
+// plain coalesced loads/stores and leave MFMA to the contraction kernels.
+#include <hip/hip_runtime.h>
+
+#include "lsum_internal.h"
+
+namespace lsum {
+
+namespace {
+
+constexpr double kSqrtPi = 1.7724538509055160273;
+
+// --------------------------------------------------------------------------------------------
+// Reference vectors (Sec. 2.1 b(t_k), Sec. 3.1 eq. master_pot): one thread per entry.
+// Entry m of row q: w_q^(1/3) * (1/h) int over the cell at displacement d = (m-(N_ref-1)) h of
+// exp(-t_q^2 x^2) dx = w_q^(1/3) sqrt(pi)/(2 t h) [erf(t(|d|+h/2)) - erf(t(|d|-h/2))], with the
+// complementary form when both ends are in the tail.  Padding entries are zero.
+// --------------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_collocate(int R, const double* __restrict__ t,
+                                                   const double* __restrict__ w13, int N_ref,
+                                                   double h, double* __restrict__ G, int ldg) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    const int q = blockIdx.y;
+    if (m >= ldg || q >= R) return;
+    double v = 0.0;
+    if (m < 2 * N_ref - 1) {
+        const double d = fabs((double)(m - (N_ref - 1)) * h);
+        const double tq = t[q];
+        double b = 1.0;
+        if (tq > 0.0) {
+            const double lo = tq * (d - 0.5 * h);
+            const double hi = tq * (d + 0.5 * h);
+            const double diff = lo > 1.0 ? erfc(lo) - erfc(hi) : erf(hi) - erf(lo);
+            b = kSqrtPi / (2.0 * tq * h) * diff;
+        }
+        v = w13[q] * b;
+    }
+    G[(size_t)q * ldg + m] = v;
+}
+
+// --------------------------------------------------------------------------------------------
+// Assembled 1D sums (Thm thm:sumCaseE (A)): U[q, i] = sum_k G[q, i - c_k + N_ref - 1].
+// Grid (x: cell tiles of 256, y: node q, z: job).  The site list is uniform across the
+// workgroup (scalar loads); the reference row is read through L2 with unit stride in i.
+// --------------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_shift_sum(const ShiftJob* __restrict__ jobs) {
+    const ShiftJob jb = jobs[blockIdx.z];
+    const int q = blockIdx.y;
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (q >= jb.R || i >= jb.N_axis) return;
+    const double* __restrict__ g = jb.G + (size_t)q * jb.ldg + (i + jb.N_ref - 1);
+    const int32_t* __restrict__ c = jb.sites;
+    const int n = jb.n_sites;
+    double acc = 0.0;
+    int k = 0;
+    for (; k + 4 <= n; k += 4) {
+        const double a0 = g[-c[k]], a1 = g[-c[k + 1]], a2 = g[-c[k + 2]], a3 = g[-c[k + 3]];
+        acc += a0;
+        acc += a1;
+        acc += a2;
+        acc += a3;
+    }
+    for (; k < n; ++k) acc += g[-c[k]];
+    jb.U[(size_t)q * jb.ldu + i] = acc;
+}
+
+__device__ __forceinline__ int snap_dev(double x, double h, int N) {
+    const double u = x / h;
+    double j = floor(fabs(u) + 0.5);
+    if (u < 0.0) j = -j;
+    const double i = j + (double)((N - 1) / 2);
+    return (i >= 0.0 && i <= (double)(N - 1)) ? (int)i : -1;
+}
+
+// Canonical sum at points: out[p] = sum_f lam_f sum_q prod_l U[f][l][q, i_l(p)].
+__global__ void __launch_bounds__(256) k_sample_cp(int n_fac, int R, const double* __restrict__ U,
+                                                   int ldu, const double* __restrict__ lam, int N0,
+                                                   int N1, int N2, double h, int n_pts,
+                                                   const double* __restrict__ xyz,
+                                                   double* __restrict__ out) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n_pts) return;
+    const int i0 = snap_dev(xyz[3 * (size_t)p + 0], h, N0);
+    const int i1 = snap_dev(xyz[3 * (size_t)p + 1], h, N1);
+    const int i2 = snap_dev(xyz[3 * (size_t)p + 2], h, N2);
+    if (i0 < 0 || i1 < 0 || i2 < 0) {
+        out[p] = __builtin_nan("");
+        return;
+    }
+    const size_t axis = (size_t)R * ldu;
+    double total = 0.0;
+    for (int f = 0; f < n_fac; ++f) {
+        const double* u0 = U + (3 * (size_t)f + 0) * axis + i0;
+        const double* u1 = U + (3 * (size_t)f + 1) * axis + i1;
+        const double* u2 = U + (3 * (size_t)f + 2) * axis + i2;
+        double acc = 0.0;
+        for (int q = 0; q < R; ++q)
+            acc += u0[(size_t)q * ldu] * u1[(size_t)q * ldu] * u2[(size_t)q * ldu];
+        total += lam[f] * acc;
+    }
+    out[p] = total;
+}
+
+// One block: out[p] += lam * sum_q U0[q, i0] U1[q, i1] U2[q, i2] (per-axis row strides N_l).
+__global__ void __launch_bounds__(256) k_sample_block(int R, const double* __restrict__ U0,
+                                                      const double* __restrict__ U1,
+                                                      const double* __restrict__ U2, int N0, int N1,
+                                                      int N2, double h, double lam, int n_pts,
+                                                      const double* __restrict__ xyz,
+                                                      double* __restrict__ out) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n_pts) return;
+    const int i0 = snap_dev(xyz[3 * (size_t)p + 0], h, N0);
+    const int i1 = snap_dev(xyz[3 * (size_t)p + 1], h, N1);
+    const int i2 = snap_dev(xyz[3 * (size_t)p + 2], h, N2);
+    if (i0 < 0 || i1 < 0 || i2 < 0) {
+        out[p] = __builtin_nan("");
+        return;
+    }
+    double acc = 0.0;
+    for (int q = 0; q < R; ++q)
+        acc += U0[(size_t)q * N0 + i0] * U1[(size_t)q * N1 + i1] * U2[(size_t)q * N2 + i2];
+    out[p] += lam * acc;
+}
+
+// Defect terms straight from the reference rows: out[p] += sum_s dZ_s sum_q prod_l
+// G[q, i_l(p) - c_s,l + N_ref - 1] (the windowed reference tensor of Sec. 3.1 per defect).
+__global__ void __launch_bounds__(256) k_sample_windows(int R, const double* __restrict__ G, int ldg,
+                                                        int N_ref, int n_def,
+                                                        const int32_t* __restrict__ cells,
+                                                        const double* __restrict__ scale, int N0,
+                                                        int N1, int N2, double h, int n_pts,
+                                                        const double* __restrict__ xyz,
+                                                        double* __restrict__ out) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n_pts) return;
+    const int i0 = snap_dev(xyz[3 * (size_t)p + 0], h, N0);
+    const int i1 = snap_dev(xyz[3 * (size_t)p + 1], h, N1);
+    const int i2 = snap_dev(xyz[3 * (size_t)p + 2], h, N2);
+    if (i0 < 0 || i1 < 0 || i2 < 0) return;
+    double total = 0.0;
+    for (int s = 0; s < n_def; ++s) {
+        const int m0 = i0 - cells[3 * s + 0] + N_ref - 1;
+        const int m1 = i1 - cells[3 * s + 1] + N_ref - 1;
+        const int m2 = i2 - cells[3 * s + 2] + N_ref - 1;
+        double acc = 0.0;
+        for (int q = 0; q < R; ++q) {
+            const double* g = G + (size_t)q * ldg;
+            acc += g[m0] * g[m1] * g[m2];
+        }
+        total += scale[s] * acc;
+    }
+    out[p] += total;
+}
+
+// Side-matrix columns of one mode (Sec. 4.2 side matrices; rows = columns of the paper's A):
+// row src*R + q is the lattice sum of source src (src < n_lat) or the window of reference
+// row q at the source's defect cell.
+__global__ void __launch_bounds__(256) k_gather_columns(int R, int n_lat,
+                                                        const double* const* __restrict__ lat_U,
+                                                        int ldu, const int32_t* __restrict__ win_cells,
+                                                        const double* __restrict__ G, int ldg,
+                                                        int N_ref, int N_axis,
+                                                        double* __restrict__ cols, int ldc) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int row = blockIdx.y;
+    if (i >= ldc) return;
+    const int src = row / R, q = row % R;
+    double v = 0.0;
+    if (i < N_axis) {
+        if (src < n_lat) {
+            v = lat_U[src][(size_t)q * ldu + i];
+        } else {
+            const int c = win_cells[src - n_lat];
+            v = G[(size_t)q * ldg + (i - c + N_ref - 1)];
+        }
+    }
+    cols[(size_t)row * ldc + i] = v;
+}
+
+// Euclidean norm of each row, one workgroup per row, fixed reduction order.
+__global__ void __launch_bounds__(256) k_row_norms(int n, const double* __restrict__ X, int ldx,
+                                                   double* __restrict__ nrm) {
+    __shared__ double red[256];
+    const double* x = X + (size_t)blockIdx.x * ldx;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) acc += x[i] * x[i];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) nrm[blockIdx.x] = sqrt(red[0]);
+}
+
+__global__ void __launch_bounds__(256) k_scale_rows(int n, const double* __restrict__ X, int ldx,
+                                                    const double* __restrict__ scale,
+                                                    double* __restrict__ Y, int ldy) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int row = blockIdx.y;
+    if (i >= n) return;
+    Y[(size_t)row * ldy + i] = X[(size_t)row * ldx + i] * scale[row];
+}
+
+__global__ void __launch_bounds__(256) k_gather_scale_rows(int n, const double* __restrict__ X,
+                                                           int ldx, const int32_t* __restrict__ order,
+                                                           const double* __restrict__ inv_sigma,
+                                                           double* __restrict__ Z, int ldz) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int a = blockIdx.y;
+    if (i >= ldz) return;
+    Z[(size_t)a * ldz + i] = i < n ? X[(size_t)order[a] * ldx + i] * inv_sigma[a] : 0.0;
+}
+
+__global__ void __launch_bounds__(256) k_f64_to_f32(long n, const double* __restrict__ x,
+                                                    float* __restrict__ y) {
+    const long i = (long)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) y[i] = (float)x[i];
+}
+
+__global__ void __launch_bounds__(256) k_f32_to_f64(long n, const float* __restrict__ x,
+                                                    double* __restrict__ y) {
+    const long i = (long)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) y[i] = (double)x[i];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_select_cols(int nsel, const T* __restrict__ Z, long ldz,
+                                                     const int32_t* __restrict__ idx,
+                                                     T* __restrict__ out) {
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    const int a = blockIdx.y;
+    if (p >= nsel) return;
+    out[(size_t)a * nsel + p] = Z[(size_t)a * ldz + idx[p]];
+}
+
+__global__ void __launch_bounds__(256) k_snap_points(int n, const double* __restrict__ xyz, int N0,
+                                                     int N1, int N2, double h,
+                                                     int32_t* __restrict__ idx) {
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= n) return;
+    idx[p] = snap_dev(xyz[3 * (size_t)p + 0], h, N0);
+    idx[n + p] = snap_dev(xyz[3 * (size_t)p + 1], h, N1);
+    idx[2 * (size_t)n + p] = snap_dev(xyz[3 * (size_t)p + 2], h, N2);
+}
+
+// Tucker value at points after the mode-3 contraction: W[(a*r2+b)*P + p] holds
+// sum_c mu[a,b,c] Z3[c, i3(p)]; out[p] = sum_ab W Z1[a, i1(p)] Z2[b, i2(p)].
+__global__ void __launch_bounds__(256) k_tucker_finish(int r1, int r2, int P,
+                                                       const double* __restrict__ W,
+                                                       const double* __restrict__ Z1, int ld1,
+                                                       const double* __restrict__ Z2, int ld2,
+                                                       const int32_t* __restrict__ i1,
+                                                       const int32_t* __restrict__ i2,
+                                                       double* __restrict__ out) {
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= P) return;
+    const int c1 = i1[p], c2 = i2[p];
+    if (c1 < 0 || c2 < 0) {
+        out[p] = __builtin_nan("");
+        return;
+    }
+    double total = 0.0;
+    for (int a = 0; a < r1; ++a) {
+        double acc = 0.0;
+        const double* w = W + (size_t)a * r2 * P + p;
+        for (int b = 0; b < r2; ++b) acc += w[(size_t)b * P] * Z2[(size_t)b * ld2 + c2];
+        total += acc * Z1[(size_t)a * ld1 + c1];
+    }
+    out[p] = total;
+}
+
+inline unsigned cdiv(long a, long b) { return (unsigned)((a + b - 1) / b); }
+
+}  // namespace
+
+void launch_collocate(hipStream_t st, int R, const double* t_dev, const double* w13_dev, int N_ref,
+                      double h, double* G, int ldg) {
+    dim3 grid(cdiv(ldg, 256), R);
+    hipLaunchKernelGGL(k_collocate, grid, dim3(256), 0, st, R, t_dev, w13_dev, N_ref, h, G, ldg);
+}
+
+void launch_shift_sum(hipStream_t st, const ShiftJob* jobs_dev, int n_jobs, int max_N, int max_R) {
+    if (n_jobs <= 0) return;
+    dim3 grid(cdiv(max_N, 256), max_R, n_jobs);
+    hipLaunchKernelGGL(k_shift_sum, grid, dim3(256), 0, st, jobs_dev);
+}
+
+void launch_sample_cp(hipStream_t st, int n_fac, int R, const double* U, int ldu,
+                      const double* lam_dev, int N0, int N1, int N2, double h, int n_pts,
+                      const double* xyz, double* out) {
+    if (n_pts <= 0) return;
+    hipLaunchKernelGGL(k_sample_cp, dim3(cdiv(n_pts, 256)), dim3(256), 0, st, n_fac, R, U, ldu,
+                       lam_dev, N0, N1, N2, h, n_pts, xyz, out);
+}
+
+void launch_sample_block(hipStream_t st, int R, const double* U0, const double* U1, const double* U2,
+                         int N0, int N1, int N2, double h, double lam, int n_pts, const double* xyz,
+                         double* out) {
+    if (n_pts <= 0) return;
+    hipLaunchKernelGGL(k_sample_block, dim3(cdiv(n_pts, 256)), dim3(256), 0, st, R, U0, U1, U2, N0,
+                       N1, N2, h, lam, n_pts, xyz, out);
+}
+
+void launch_sample_windows(hipStream_t st, int R, const double* G, int ldg, int N_ref, int n_def,
+                           const int32_t* def_cells, const double* def_scale, int N0, int N1,
+                           int N2, double h, int n_pts, const double* xyz, double* out) {
+    if (n_pts <= 0 || n_def <= 0) return;
+    hipLaunchKernelGGL(k_sample_windows, dim3(cdiv(n_pts, 256)), dim3(256), 0, st, R, G, ldg,
+                       N_ref, n_def, def_cells, def_scale, N0, N1, N2, h, n_pts, xyz, out);
+}
+
+void launch_gather_columns(hipStream_t st, int R, int n_lat, const double* const* lat_U_dev, int ldu,
+                           int n_win, const int32_t* win_cells_dev, const double* G, int ldg,
+                           int N_ref, int N_axis, double* cols, int ldc) {
+    const int rows = R * (n_lat + n_win);
+    if (rows <= 0) return;
+    dim3 grid(cdiv(ldc, 256), rows);
+    hipLaunchKernelGGL(k_gather_columns, grid, dim3(256), 0, st, R, n_lat, lat_U_dev, ldu,
+                       win_cells_dev, G, ldg, N_ref, N_axis, cols, ldc);
+}
+
+void launch_row_norms(hipStream_t st, int rows, int n, const double* X, int ldx, double* nrm) {
+    if (rows <= 0) return;
+    hipLaunchKernelGGL(k_row_norms, dim3(rows), dim3(256), 0, st, n, X, ldx, nrm);
+}
+
+void launch_scale_rows(hipStream_t st, int rows, int n, const double* X, int ldx, const double* scale,
+                       double* Y, int ldy) {
+    if (rows <= 0) return;
+    hipLaunchKernelGGL(k_scale_rows, dim3(cdiv(n, 256), rows), dim3(256), 0, st, n, X, ldx, scale, Y,
+                       ldy);
+}
+
+void launch_gather_scale_rows(hipStream_t st, int r, int n, const double* X, int ldx,
+                              const int32_t* order_dev, const double* inv_sigma_dev, double* Z,
+                              int ldz) {
+    if (r <= 0) return;
+    hipLaunchKernelGGL(k_gather_scale_rows, dim3(cdiv(ldz, 256), r), dim3(256), 0, st, n, X, ldx,
+                       order_dev, inv_sigma_dev, Z, ldz);
+}
+
+void launch_f64_to_f32(hipStream_t st, long n, const double* x, float* y) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_f64_to_f32, dim3(cdiv(n, 256)), dim3(256), 0, st, n, x, y);
+}
+
+void launch_f32_to_f64(hipStream_t st, long n, const float* x, double* y) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_f32_to_f64, dim3(cdiv(n, 256)), dim3(256), 0, st, n, x, y);
+}
+
+void launch_select_cols(hipStream_t st, int rows, int nsel, const void* Z, long ldz,
+                        const int32_t* idx, void* out, int elem_size) {
+    if (rows <= 0 || nsel <= 0) return;
+    dim3 grid(cdiv(nsel, 256), rows);
+    if (elem_size == 8)
+        hipLaunchKernelGGL(k_select_cols<double>, grid, dim3(256), 0, st, nsel,
+                           (const double*)Z, ldz, idx, (double*)out);
+    else
+        hipLaunchKernelGGL(k_select_cols<float>, grid, dim3(256), 0, st, nsel, (const float*)Z,
+                           ldz, idx, (float*)out);
+}
+
+void launch_tucker_finish(hipStream_t st, int r1, int r2, int P, const double* W, const double* Z1,
+                          int ld1, const double* Z2, int ld2, const int32_t* i1, const int32_t* i2,
+                          double* out) {
+    if (P <= 0) return;
+    hipLaunchKernelGGL(k_tucker_finish, dim3(cdiv(P, 256)), dim3(256), 0, st, r1, r2, P, W, Z1, ld1,
+                       Z2, ld2, i1, i2, out);
+}
+
+void launch_snap_points(hipStream_t st, int n, const double* xyz, int N0, int N1, int N2, double h,
+                        int32_t* idx) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_snap_points, dim3(cdiv(n, 256)), dim3(256), 0, st, n, xyz, N0, N1, N2, h,
+                       idx);
+}
+
+}  // namespace lsum

@@ -1,0 +1,277 @@
+// Host-side steps of the lattice-sum path: FP64 quadrature nodes, integer snapping and the
+// bookkeeping plan (side-matrix column sources, term groups, multiplicities).
+// Compiled with -ffp-contract=off: every FP64 operation here is a single IEEE operation, so
+// the snapped indices are reproducible bit for bit.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <set>
+#include <tuple>
+
+#include "lsum_internal.h"
+
+namespace lsum {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+int fail(int code, const std::string& msg) {
+    g_last_error = msg;
+    return code;
+}
+
+const char* last_error() { return g_last_error.c_str(); }
+
+// Default quadrature parameters: s is a quarter of the largest charge-to-cell distance of the
+// box, h_u a per-kernel trapezoid step (chosen for the max-norm error at M = 32..40).
+void default_quadrature(int kind, const int N[3], double h, double* h_u, double* s) {
+    double acc = 0.0;
+    for (int l = 0; l < 3; ++l) {
+        double d = (double)(N[l] - 1);
+        acc += d * d;
+    }
+    *s = h * std::sqrt(acc) / 4.0;
+    *h_u = (kind == LSUM_SLATER) ? 0.30 : 0.35;
+}
+
+// Laplace-Gauss density a(t), p(z) = int_0^inf a(t) exp(-t^2 z^2) dt (Sec. 2.2):
+// Newton 2/sqrt(pi); Yukawa 2/sqrt(pi) exp(-k^2/(4t^2)); Slater l/sqrt(pi) t^-2 exp(-l^2/(4t^2)).
+static double density(int kind, double param, double t) {
+    const double two_over_sqrt_pi = 2.0 / std::sqrt(M_PI);
+    if (kind == LSUM_NEWTON || (kind == LSUM_YUKAWA && param == 0.0)) return two_over_sqrt_pi;
+    if (t <= 0.0) return 0.0;
+    double e = std::exp(-param * param / (4.0 * (t * t)));
+    if (kind == LSUM_YUKAWA) return two_over_sqrt_pi * e;
+    return param / std::sqrt(M_PI) / (t * t) * e;   // Slater
+}
+
+// Sinc quadrature (Sec. 2.1, eqs. laplace, hM): trapezoid rule with step h_u in u after the
+// substitution t = sinh(u)/s (even integrand), folded onto u_k = k h_u, k = 0..M.
+int sinc_nodes(int kind, double param, int M, double h_u, double s, std::vector<double>& t,
+               std::vector<double>& w) {
+    if (kind < LSUM_NEWTON || kind > LSUM_SLATER) return fail(LSUM_E_INVALID, "unknown kernel");
+    if (M < 1 || M > 4096) return fail(LSUM_E_INVALID, "M must be in [1, 4096]");
+    if (!(h_u > 0.0) || !(s > 0.0)) return fail(LSUM_E_INVALID, "h_u and s must be positive");
+    if (kind != LSUM_NEWTON && !(param >= 0.0)) return fail(LSUM_E_INVALID, "negative kernel parameter");
+    if (kind == LSUM_SLATER && !(param > 0.0)) return fail(LSUM_E_INVALID, "Slater needs param > 0");
+    std::vector<double> tt(M + 1), ww(M + 1);
+    double wmax = 0.0;
+    for (int k = 0; k <= M; ++k) {
+        double u = (double)k * h_u;
+        double tk = std::sinh(u) / s;
+        double dtdu = std::cosh(u) / s;
+        double step = (k == 0) ? 0.5 * h_u : h_u;
+        tt[k] = tk;
+        ww[k] = step * density(kind, param, tk) * dtdu;
+        wmax = std::max(wmax, ww[k]);
+    }
+    t.clear();
+    w.clear();
+    for (int k = 0; k <= M; ++k) {
+        if (ww[k] > 1e-18 * wmax) {
+            t.push_back(tt[k]);
+            w.push_back(ww[k]);
+        }
+    }
+    if (t.empty()) return fail(LSUM_E_INVALID, "no quadrature node carries weight");
+    return LSUM_OK;
+}
+
+// Cell of a coordinate: j = sign(x/h) floor(|x/h| + 1/2) (halves away from zero), i = j + (N-1)/2.
+int snap_coord(double x, double h, int N, int32_t* idx) {
+    double u = x / h;
+    double j = std::floor(std::fabs(u) + 0.5);
+    if (u < 0.0) j = -j;
+    double i = j + (double)((N - 1) / 2);
+    if (!(i >= 0.0 && i <= (double)(N - 1))) return LSUM_E_OUT_OF_BOX;
+    *idx = (int32_t)i;
+    return LSUM_OK;
+}
+
+int block_offsets(const lsum_block& blk, const int N[3], double h, std::vector<int32_t> offs[3]) {
+    for (int l = 0; l < 3; ++l) {
+        if (blk.L[l] < 1) return fail(LSUM_E_INVALID, "block with L < 1");
+        offs[l].resize(blk.L[l]);
+        double half = (double)(blk.L[l] - 1) / 2.0;
+        for (int k = 0; k < blk.L[l]; ++k) {
+            double x = ((double)k - half) * blk.b[l] + blk.center[l];
+            int rc = snap_coord(x, h, N[l], &offs[l][k]);
+            if (rc != LSUM_OK) return fail(rc, "lattice site outside the grid");
+        }
+    }
+    return LSUM_OK;
+}
+
+size_t Plan::planned_bytes() const {
+    size_t b = 0;
+    size_t sumN = (size_t)N[0] + N[1] + N[2];
+    b += (size_t)R * ldg * 8;                                  // reference rows (if not cached)
+    b += blocks.size() * (size_t)R * sumN * 8;                 // canonical factors
+    if (tucker()) {
+        size_t rmax[3];
+        for (int l = 0; l < 3; ++l) {
+            b += 2 * (size_t)D[l] * N[l] * 8;                  // raw + weighted columns
+            rmax[l] = std::min<size_t>(std::min(D[l], N[l]), 1024);
+            b += rmax[l] * N[l] * 8 * 2 + rmax[l] * D[l] * 8 * 2;   // Z, Y
+            b += (size_t)D[l] * D[l] * 8;                      // column Gram
+        }
+        b += rmax[0] * rmax[1] * rmax[2] * 8;                  // core
+        if (has_tile()) {
+            size_t T0 = tile_T[0], T1 = tile_T[1], T2 = tile_T[2];
+            size_t e = precision == LSUM_FP64 ? 8 : 4;
+            b += (T0 * T1 * T2 + rmax[0] * rmax[1] * T2 + rmax[0] * T1 * T2) * e;
+        }
+    }
+    return b + (16u << 20);
+}
+
+int make_plan(const lsum_problem& p, Plan& plan) {
+    plan = Plan();
+    plan.kernel = p.kernel;
+    for (int l = 0; l < 3; ++l) {
+        if (p.N[l] < 1 || (p.N[l] % 2) == 0) return fail(LSUM_E_INVALID, "N must be odd and positive");
+        if (p.N[l] > (1 << 20)) return fail(LSUM_E_INVALID, "N too large");
+        plan.N[l] = p.N[l];
+        plan.tile_lo[l] = p.tile_lo[l];
+        plan.tile_T[l] = p.tile_T[l];
+    }
+    if (!(p.h > 0.0) || !std::isfinite(p.h)) return fail(LSUM_E_INVALID, "h must be positive");
+    plan.h = p.h;
+    if (p.n_blocks < 1 || !p.blocks) return fail(LSUM_E_INVALID, "need at least one block");
+    if (p.n_defects < 0 || (p.n_defects > 0 && !p.defects)) return fail(LSUM_E_INVALID, "bad defect list");
+    if (!(p.eps < 1.0) || std::isnan(p.eps)) return fail(LSUM_E_INVALID, "eps must be < 1");
+    if (p.precision < LSUM_FP64 || p.precision > LSUM_BF16X3) return fail(LSUM_E_INVALID, "bad precision");
+    plan.eps = p.eps;
+    plan.precision = p.precision;
+    plan.blocks.assign(p.blocks, p.blocks + p.n_blocks);
+    plan.defects.assign(p.defects, p.defects + p.n_defects);
+    if (plan.has_tile()) {
+        if (!plan.tucker()) return fail(LSUM_E_INVALID, "a tile needs eps > 0 (Tucker output)");
+        for (int l = 0; l < 3; ++l)
+            if (p.tile_lo[l] < 0 || p.tile_lo[l] + p.tile_T[l] > p.N[l])
+                return fail(LSUM_E_INVALID, "tile outside the grid");
+    }
+
+    // quadrature
+    double h_u = p.kernel.h_u, s = p.kernel.s, dh, ds;
+    default_quadrature(p.kernel.kind, p.N, p.h, &dh, &ds);
+    if (!(h_u > 0.0)) h_u = dh;
+    if (!(s > 0.0)) s = ds;
+    plan.h_u = h_u;
+    plan.s = s;
+    int rc = sinc_nodes(p.kernel.kind, p.kernel.param, p.kernel.M, h_u, s, plan.t, plan.w);
+    if (rc != LSUM_OK) return rc;
+    plan.R = (int)plan.t.size();
+    plan.N_ref = std::max(p.N[0], std::max(p.N[1], p.N[2]));
+    plan.ldg = ((2 * plan.N_ref - 1) + 7) / 8 * 8;
+
+    // snapping
+    const int nb = p.n_blocks;
+    for (int l = 0; l < 3; ++l) plan.offs[l].resize(nb);
+    for (int b = 0; b < nb; ++b) {
+        if (!std::isfinite(p.blocks[b].charge)) return fail(LSUM_E_INVALID, "bad block charge");
+        std::vector<int32_t> o[3];
+        rc = block_offsets(p.blocks[b], p.N, p.h, o);
+        if (rc != LSUM_OK) return rc;
+        for (int l = 0; l < 3; ++l) plan.offs[l][b] = std::move(o[l]);
+    }
+    // defects: validation and duplicate detection
+    std::set<std::tuple<int, int, int, int>> seen;
+    for (const auto& d : plan.defects) {
+        if (d.block < 0 || d.block >= nb) return fail(LSUM_E_INVALID, "defect block out of range");
+        for (int l = 0; l < 3; ++l)
+            if (d.site[l] < 0 || d.site[l] >= p.blocks[d.block].L[l])
+                return fail(LSUM_E_OUT_OF_BOX, "defect site outside its block");
+        if (!std::isfinite(d.dZ)) return fail(LSUM_E_INVALID, "bad defect charge");
+        auto key = std::make_tuple(d.block, d.site[0], d.site[1], d.site[2]);
+        if (!seen.insert(key).second) return fail(LSUM_E_DUP_DEFECT, "two defects at the same site");
+    }
+
+    // column sources per mode and term groups (blocks, then defects)
+    plan.n_groups = nb + (int)plan.defects.size();
+    plan.g_scale.resize(plan.n_groups);
+    for (int b = 0; b < nb; ++b) plan.g_scale[b] = p.blocks[b].charge;
+    for (size_t s2 = 0; s2 < plan.defects.size(); ++s2) plan.g_scale[nb + s2] = plan.defects[s2].dZ;
+    for (int l = 0; l < 3; ++l) {
+        plan.g_src[l].assign(plan.n_groups, -1);
+        // lattice sources: distinct offset lists
+        std::map<std::vector<int32_t>, int> lat;
+        for (int b = 0; b < nb; ++b) {
+            auto it = lat.find(plan.offs[l][b]);
+            if (it == lat.end()) {
+                int id = (int)plan.lat_block[l].size();
+                lat.emplace(plan.offs[l][b], id);
+                plan.lat_block[l].push_back(b);
+                plan.g_src[l][b] = id;
+            } else {
+                plan.g_src[l][b] = it->second;
+            }
+        }
+        plan.n_lat[l] = (int)plan.lat_block[l].size();
+        // window sources: distinct defect cells
+        std::map<int32_t, int> win;
+        for (size_t s2 = 0; s2 < plan.defects.size(); ++s2) {
+            const auto& d = plan.defects[s2];
+            int32_t cell = plan.offs[l][d.block][d.site[l]];
+            auto it = win.find(cell);
+            int id;
+            if (it == win.end()) {
+                id = (int)plan.win_cell[l].size();
+                win.emplace(cell, id);
+                plan.win_cell[l].push_back(cell);
+            } else {
+                id = it->second;
+            }
+            plan.g_src[l][nb + s2] = plan.n_lat[l] + id;
+        }
+        plan.n_win[l] = (int)plan.win_cell[l].size();
+        plan.src_mult[l].assign(plan.n_lat[l] + plan.n_win[l], 0);
+        for (int g = 0; g < plan.n_groups; ++g) plan.src_mult[l][plan.g_src[l][g]] += 1;
+        plan.D[l] = plan.R * (plan.n_lat[l] + plan.n_win[l]);
+    }
+    return LSUM_OK;
+}
+
+}  // namespace lsum
+
+// ------------------------------------------------------------------------------------------
+// C ABI: host-side steps
+// ------------------------------------------------------------------------------------------
+extern "C" {
+
+const char* lsum_last_error(void) { return lsum::last_error(); }
+
+int lsum_nodes(const lsum_kernel* k, const int N[3], double h, double* t, double* w, int cap, int* R) {
+    if (!k || !N || !t || !w || !R) return lsum::fail(LSUM_E_INVALID, "null argument");
+    double h_u = k->h_u, s = k->s, dh, ds;
+    lsum::default_quadrature(k->kind, N, h, &dh, &ds);
+    if (!(h_u > 0.0)) h_u = dh;
+    if (!(s > 0.0)) s = ds;
+    std::vector<double> tt, ww;
+    int rc = lsum::sinc_nodes(k->kind, k->param, k->M, h_u, s, tt, ww);
+    if (rc != LSUM_OK) return rc;
+    if ((int)tt.size() > cap) return lsum::fail(LSUM_E_INVALID, "output capacity too small");
+    std::memcpy(t, tt.data(), tt.size() * sizeof(double));
+    std::memcpy(w, ww.data(), ww.size() * sizeof(double));
+    *R = (int)tt.size();
+    return LSUM_OK;
+}
+
+int lsum_block_offsets(const lsum_block* blk, const int N[3], double h, int32_t* offs) {
+    if (!blk || !N || !offs) return lsum::fail(LSUM_E_INVALID, "null argument");
+    for (int l = 0; l < 3; ++l)
+        if (N[l] < 1 || (N[l] % 2) == 0) return lsum::fail(LSUM_E_INVALID, "N must be odd");
+    std::vector<int32_t> o[3];
+    int rc = lsum::block_offsets(*blk, N, h, o);
+    if (rc != LSUM_OK) return rc;
+    size_t pos = 0;
+    for (int l = 0; l < 3; ++l) {
+        std::memcpy(offs + pos, o[l].data(), o[l].size() * sizeof(int32_t));
+        pos += o[l].size();
+    }
+    return LSUM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,173 @@
+// Internal declarations shared by the host driver and the HIP kernels of the lattice-sum
+// library.  Not part of the public ABI (see include/lsum.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "lsum.h"
+
+namespace lsum {
+
+// ------------------------------------------------------------------------------------------
+// error handling
+// ------------------------------------------------------------------------------------------
+void set_error(const std::string& msg);
+int fail(int code, const std::string& msg);
+
+#define LSUM_HIP(call)                                                                      \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return ::lsum::fail(LSUM_E_DEVICE, std::string(#call ": ") + hipGetErrorString(e_)); \
+    } while (0)
+
+// ------------------------------------------------------------------------------------------
+// host-side steps (FP64 / integer)
+// ------------------------------------------------------------------------------------------
+void default_quadrature(int kind, const int N[3], double h, double* h_u, double* s);
+// Returns LSUM_OK or an error; t/w receive R <= M+1 nodes.
+int sinc_nodes(int kind, double param, int M, double h_u, double s, std::vector<double>& t,
+               std::vector<double>& w);
+int snap_coord(double x, double h, int N, int32_t* idx);
+int block_offsets(const lsum_block& blk, const int N[3], double h, std::vector<int32_t> offs[3]);
+
+// ------------------------------------------------------------------------------------------
+// plan of one problem: bookkeeping shared by every stage
+// ------------------------------------------------------------------------------------------
+struct Plan {
+    // problem (deep copy)
+    lsum_kernel kernel{};
+    int N[3]{};
+    double h = 0;
+    std::vector<lsum_block> blocks;
+    std::vector<lsum_defect> defects;
+    double eps = 0;
+    int precision = LSUM_FP64;
+    int tile_lo[3]{}, tile_T[3]{};
+
+    // quadrature
+    double h_u = 0, s = 0;
+    std::vector<double> t, w;
+    int R = 0;
+    int N_ref = 0;   // max N
+    int ldg = 0;     // reference row stride
+
+    // per block, per axis snapped cell indices
+    std::vector<std::vector<int32_t>> offs[3];   // offs[axis][block]
+
+    // Side-matrix columns per mode, grouped in "sources" of R columns (one per node q):
+    // sources [0, n_lat[l]) are distinct lattice offset lists, the rest distinct defect cells.
+    int n_lat[3]{}, n_win[3]{};
+    std::vector<int32_t> lat_block[3];   // representative block of each lattice source
+    std::vector<int32_t> win_cell[3];    // cell index of each window source
+    // term groups: blocks first, then defects; scale = block charge or dZ
+    int n_groups = 0;
+    std::vector<double> g_scale;
+    std::vector<int32_t> g_src[3];       // source index of each group per mode
+    std::vector<int32_t> src_mult[3];    // multiplicity of each source (groups using it)
+    int D[3]{};                          // R * (n_lat + n_win)
+
+    bool tucker() const { return eps > 0; }
+    bool has_tile() const { return tile_T[0] > 0 && tile_T[1] > 0 && tile_T[2] > 0; }
+    size_t planned_bytes() const;        // HBM footprint estimate of the request
+};
+
+// Validates the problem and fills the plan (host only).  Returns LSUM_OK or an error.
+int make_plan(const lsum_problem& p, Plan& plan);
+
+// ------------------------------------------------------------------------------------------
+// kernel launchers (defined in the .hip files); all asynchronous on `st`
+// ------------------------------------------------------------------------------------------
+void launch_collocate(hipStream_t st, int R, const double* t_dev, const double* w13_dev, int N_ref,
+                      double h, double* G, int ldg);
+// Shift-sum for a batch of (row block) jobs; see kernels_lattice.hip.
+struct ShiftJob {
+    const double* G;      // reference rows (R x ldg)
+    double* U;            // output rows (R x ldu)
+    const int32_t* sites; // device cell indices
+    int n_sites;
+    int N_axis;
+    int ldu;
+    int ldg;
+    int N_ref;
+    int R;
+};
+void launch_shift_sum(hipStream_t st, const ShiftJob* jobs_dev, int n_jobs, int max_N, int max_R);
+void launch_sample_cp(hipStream_t st, int n_fac, int R, const double* U, int ldu,
+                      const double* lam_dev, int N0, int N1, int N2, double h, int n_pts,
+                      const double* xyz, double* out);
+// One block's canonical factors (axis l: R rows of N_l, stride N_l): out[p] += lam * sum_q prod.
+void launch_sample_block(hipStream_t st, int R, const double* U0, const double* U1, const double* U2,
+                         int N0, int N1, int N2, double h, double lam, int n_pts, const double* xyz,
+                         double* out);
+// Defect windows evaluated straight from the reference rows, added to out.
+void launch_sample_windows(hipStream_t st, int R, const double* G, int ldg, int N_ref,
+                           int n_def, const int32_t* def_cells, const double* def_scale,
+                           int N0, int N1, int N2, double h, int n_pts, const double* xyz,
+                           double* out);
+// Side-matrix columns of one mode: rows [src*R + q] of cols (D x ldc).
+void launch_gather_columns(hipStream_t st, int R, int n_lat, const double* const* lat_U_dev,
+                           int ldu, int n_win, const int32_t* win_cells_dev, const double* G,
+                           int ldg, int N_ref, int N_axis, double* cols, int ldc);
+void launch_row_norms(hipStream_t st, int rows, int n, const double* X, int ldx, double* nrm);
+// Y[j, :] = X[j, :] * scale[j]
+void launch_scale_rows(hipStream_t st, int rows, int n, const double* X, int ldx,
+                       const double* scale, double* Y, int ldy);
+
+// General strided GEMM on MFMA: C(m,n) = alpha * sum_k A(m,k) B(k,n) + beta * C(m,n),
+// A(m,k) = A[m*sam + k*sak], B(k,n) = B[k*sbk + n*sbn], C(m,n) = C[m*scm + n*scn].
+// Batched over `batch` with element offsets bA, bB, bC between batches.
+struct GemmArgs {
+    int m, n, k;
+    const void* A; long sam, sak;
+    const void* B; long sbk, sbn;
+    void* C; long scm, scn;
+    double alpha, beta;
+    int batch; long bA, bB, bC;
+};
+enum GemmPrec { GEMM_F64 = 0, GEMM_F32 = 1, GEMM_BF16X3 = 2 };
+void launch_gemm(hipStream_t st, GemmPrec prec, const GemmArgs& a);
+
+// Core contraction mu[a,b,c] = sum_g scale_g sum_q Y1[a, s1(g)R+q] Y2[b, s2(g)R+q] Y3[c, s3(g)R+q]
+struct CoreArgs {
+    int r1, r2, r3, R, n_groups;
+    const void* Y1; const void* Y2; const void* Y3;   // r_l x ldy_l
+    long ldy1, ldy2, ldy3;
+    const int32_t* src1; const int32_t* src2; const int32_t* src3;  // per group
+    const double* scale;
+    void* core;                                       // r1*r2*r3, last index fastest
+};
+void launch_core(hipStream_t st, GemmPrec prec, const CoreArgs& a, int k_split, void* work);
+// ||A||^2 from the three unnormalised column Grams (D x D) and the group table.
+void launch_cp_norm2(hipStream_t st, int R, int n_groups, const int32_t* src1, const int32_t* src2,
+                     const int32_t* src3, const double* scale, const double* C1, const double* C2,
+                     const double* C3, int D1, int D2, int D3, double* partial, int n_partial);
+
+// one sweep-round of block Jacobi
+int jacobi_svd(hipStream_t st, int D, int N, double* A, int lda, double tol, int max_sweeps,
+               std::vector<double>& sigma, std::vector<int32_t>& order, int* sweeps_out,
+               double* work_dev, size_t work_bytes);
+size_t jacobi_work_bytes(int D, int N);
+
+// type conversions
+void launch_f64_to_f32(hipStream_t st, long n, const double* x, float* y);
+void launch_f32_to_f64(hipStream_t st, long n, const float* x, double* y);
+// Z rows a = X[order[a]] / sigma[a]
+void launch_gather_scale_rows(hipStream_t st, int r, int n, const double* X, int ldx,
+                              const int32_t* order_dev, const double* inv_sigma_dev, double* Z,
+                              int ldz);
+// Rows of a factor selected by index lists: out[a * nsel + p] = Z[a * ldz + idx[p]]
+void launch_select_cols(hipStream_t st, int rows, int nsel, const void* Z, long ldz,
+                        const int32_t* idx, void* out, int elem_size);
+// Tucker values at points from W (r1*r2 x P, layout [a*r2+b][p]) and Z1, Z2 rows
+void launch_tucker_finish(hipStream_t st, int r1, int r2, int P, const double* W, const double* Z1,
+                          int ld1, const double* Z2, int ld2, const int32_t* i1, const int32_t* i2,
+                          double* out);
+void launch_snap_points(hipStream_t st, int n, const double* xyz, int N0, int N1, int N2, double h,
+                        int32_t* idx /* 3 x n */);
+
+}  // namespace lsum

@@ -1,0 +1,109 @@
+"""The C-ABI library loads, exports every declared symbol, and its host-side steps agree with
+the oracle: quadrature nodes to rounding, snapped offsets bit for bit.  CPU only."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lsum.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lsum_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_1411_1994_amd as L
+    lib = ctypes.CDLL(L.LIB_PATH)
+    names = declared_symbols()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(L.SYMBOLS) == names
+
+
+@pytest.mark.parametrize("kind,param", [(W.NEWTON, 0.0), (W.YUKAWA, 0.5), (W.SLATER, 1.0)])
+@pytest.mark.parametrize("c", [1, 2, 3])
+def test_nodes_match_oracle(kind, param, c):
+    import paper_1411_1994_amd as L
+    p = W.config(c)
+    t, w = L.lsum_nodes(kind, param, p.M, p.N, p.h)
+    hu, s = O.default_quadrature(kind, p.N, p.h)
+    to, wo = O.sinc_nodes(kind, param, p.M, hu, s)
+    assert len(t) == len(to)
+    # each node is sinh(u)/s and each weight a product of about four libm results (sinh, cosh,
+    # exp), each good to <= 2 ulp: 8 ulp; exp(-x) with x = param^2/(4 t^2) also amplifies the
+    # rounding of x by a factor x
+    assert np.allclose(t, to, rtol=4e-15, atol=0)
+    x = np.where(to > 0, param * param / (4.0 * np.maximum(to, 1e-150) ** 2), 0.0)
+    assert np.all(np.abs(w - wo) / wo <= 4e-15 * (1.0 + x))
+
+
+@pytest.mark.parametrize("c", [1, 2, 3, 4])
+def test_offsets_bit_exact(c):
+    import paper_1411_1994_amd as L
+    p = W.config(c)
+    for blk in p.blocks:
+        got = L.lsum_block_offsets(blk, p.N, p.h)
+        exp = O.block_offsets(blk, p.h, p.N)
+        for a in range(3):
+            assert np.array_equal(got[a], exp[a])
+
+
+def test_offsets_random_lattices_bit_exact():
+    import paper_1411_1994_amd as L
+    rng = np.random.default_rng(0)
+    for _ in range(200):
+        N = tuple(int(2 * rng.integers(20, 400) + 1) for _ in range(3))
+        h = float(rng.uniform(0.01, 0.7))
+        L_ = tuple(int(x) for x in rng.integers(1, 12, size=3))
+        b = tuple(float(x) for x in rng.uniform(0.3, 2.0, size=3))
+        half = [min(n - 1, 2 * l) * h / 4 for n, l in zip(N, L_)]
+        center = tuple(float(rng.uniform(-hh, hh) * 0.1) for hh in half)
+        blk = W.Block(L_, b, center)
+        try:
+            exp = O.block_offsets(blk, h, N)
+        except O.OutOfBox:
+            with pytest.raises(L.LsumError) as e:
+                L.lsum_block_offsets(blk, N, h)
+            assert e.value.code == -2
+            continue
+        got = L.lsum_block_offsets(blk, N, h)
+        for a in range(3):
+            assert np.array_equal(got[a], exp[a])
+
+
+def test_ties_round_away_from_zero():
+    import paper_1411_1994_amd as L
+    # sites at x/h = -2.5, -1.5, ..., 2.5 (h = 0.5, b = 0.5, L = 6, centre 0)
+    blk = W.Block((6, 1, 1), (0.5, 1.0, 1.0), (0.0, 0.0, 0.0))
+    got = L.lsum_block_offsets(blk, (21, 21, 21), 0.5)[0]
+    assert got.tolist() == (np.array([-3, -2, -1, 1, 2, 3]) + 10).tolist()
+    assert got.tolist() == O.block_offsets(blk, 0.5, (21, 21, 21))[0].tolist()
+
+
+def test_host_errors():
+    import paper_1411_1994_amd as L
+    with pytest.raises(L.LsumError) as e:
+        L.lsum_nodes(W.NEWTON, 0.0, 0, (5, 5, 5), 0.1)
+    assert e.value.code == -1
+    with pytest.raises(L.LsumError) as e:
+        L.lsum_nodes(7, 0.0, 10, (5, 5, 5), 0.1)
+    assert e.value.code == -1
+    with pytest.raises(L.LsumError) as e:
+        L.lsum_nodes(W.SLATER, 0.0, 10, (5, 5, 5), 0.1)
+    assert e.value.code == -1
+    with pytest.raises(L.LsumError) as e:
+        L.lsum_block_offsets(W.cubic_block(3), (20, 21, 21), 0.1)       # even N
+    assert e.value.code == -1
+    with pytest.raises(L.LsumError) as e:
+        L.lsum_block_offsets(W.cubic_block(30, 1.0), (21, 21, 21), 0.1)  # outside the grid
+    assert e.value.code == -2

@@ -1,0 +1,194 @@
+"""End-to-end parity of whole requests (submit -> results) against the CPU oracle."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from gpu_util import require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    require_gpu()
+    import paper_1411_1994_amd as L
+    c = L.Context(0)
+    yield c
+    c.close()
+
+
+def cells_xyz(p, pts):
+    return np.stack([(pts[:, a] - (p.N[a] - 1) // 2) * p.h for a in range(3)], axis=1)
+
+
+def run(ctx, p):
+    r = ctx.submit(p)
+    rc = r.wait()
+    assert rc == 0, r.stats()
+    return r
+
+
+def test_cfg1_all_points_match_brute_force(ctx):
+    # config 1: 4x4x4 Newton lattice, N = 129, M = 32; every one of the 129^3 cells vs O1
+    p = W.config(1)
+    r = run(ctx, p)
+    g = np.stack(np.meshgrid(*[np.arange(n) for n in p.N], indexing="ij"), -1).reshape(-1, 3)
+    got = r.sample(cells_xyz(p, g)).reshape(p.N)
+    ref = O.brute_force_grid(p)
+    err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    assert err <= 1e-12, err
+    # the canonical factors are the oracle's assembled vectors (unique given the nodes)
+    U = r.canonical(0)
+    Uo = O.assembled_canonical(p)[0]
+    for a in range(3):
+        # entries of the narrowest Gaussians underflow far from the charges: per-row floor
+        floor = 1e-13 * np.max(np.abs(Uo[a]), axis=1, keepdims=True)
+        assert np.all(np.abs(U[a] - Uo[a]) <= 1e-12 * np.abs(Uo[a]) + floor)
+    st = r.stats()
+    assert st["offsets"][0][0] == [48, 59, 69, 80]
+    r.release()
+
+
+@pytest.mark.parametrize("kind,param", [(W.NEWTON, 0.0), (W.YUKAWA, 0.5), (W.SLATER, 1.0)])
+def test_defects_and_blocks_canonical(ctx, kind, param):
+    rng = np.random.default_rng(21 + kind)
+    big = W.Block((6, 5, 4), (1.0, 1.1, 0.9), (0.13, -0.2, 0.07))
+    second = W.Block((3, 3, 2), (1.0, 1.0, 1.0), (-1.5, 4.4, 3.1), charge=0.5)
+    defects = W.draw_defects(rng, [big, second], 6, 4)
+    p = W.Problem("def", kind, param, 28, (61, 67, 55), 0.21, [big, second], defects)
+    r = run(ctx, p)
+    pts = np.stack([rng.integers(0, n, 400) for n in p.N], axis=1)
+    got = r.sample(cells_xyz(p, pts))
+    ref = O.brute_force_points(p, pts)
+    assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
+    r.release()
+
+
+def test_points_outside_grid_are_nan(ctx):
+    p = W.Problem("nan", W.NEWTON, 0.0, 10, (21, 21, 21), 0.5, [W.cubic_block(2)])
+    r = run(ctx, p)
+    v = r.sample(np.array([[0.0, 0.0, 0.0], [5.26, 0.0, 0.0], [0.0, -5.3, 0.0]]))
+    assert np.isfinite(v[0]) and np.isnan(v[1]) and np.isnan(v[2])
+    r.release()
+
+
+def _small_defected(kind=W.NEWTON, param=0.0, eps=1e-6, precision=W.FP64, seed=11, tile=True):
+    rng = np.random.default_rng(seed)
+    blocks = [W.Block((5, 4, 4), (1.0, 1.0, 1.0), (0.1, -0.2, 0.05))]
+    defects = W.draw_defects(rng, blocks, 5, 3)
+    N = (33, 37, 31)
+    p = W.Problem("rh", kind, param, 20, N, 0.37, blocks, defects, eps=eps, precision=precision)
+    if tile:
+        p.tile_lo = (0, 0, 0)
+        p.tile_T = N
+    return p
+
+
+@pytest.mark.parametrize("kind,param", [(W.NEWTON, 0.0), (W.YUKAWA, 0.5), (W.SLATER, 1.0)])
+@pytest.mark.parametrize("eps", [1e-3, 1e-6, 1e-9])
+def test_rhosvd_fp64_matches_oracle(ctx, kind, param, eps):
+    p = _small_defected(kind, param, eps)
+    r = run(ctx, p)
+    inf = r.info()
+    xi, A = O.canonical_terms(p)
+    ref = O.rhosvd(xi, A, eps=eps)
+    full = O.cp_full(xi, A)
+    nA = np.linalg.norm(full)
+    assert abs(inf.norm_A - nA) <= 1e-12 * nA
+    assert abs(inf.norm_xi - ref.norm_xi) <= 1e-12 * ref.norm_xi
+    # singular values of the (deduplicated, multiplicity-weighted) side matrices = oracle's literal ones
+    sig = r.sigma()
+    for a in range(3):
+        n = len(ref.sigma[a])
+        s = np.zeros(max(n, len(sig[a])))
+        s[:len(sig[a])] = sig[a]
+        assert np.all(np.abs(s[:n] - ref.sigma[a]) <= 1e-13 * ref.sigma[a][0])
+        # ranks: equal unless the threshold sits within rounding of a tail value
+        if inf.r[a] != ref.ranks[a]:
+            thr = eps * nA / (3 * ref.norm_xi)
+            tl = O.tail_norms(ref.sigma[a])
+            k = min(inf.r[a], ref.ranks[a])
+            assert abs(tl[k] - thr) <= 1e-9 * thr
+    tile = r.tile()
+    err = np.linalg.norm(tile - full)
+    assert err <= inf.bound * (1 + 1e-9) + 1e-12 * nA
+    assert err <= eps * nA * (1 + 1e-9) + 1e-12 * nA
+    if tuple(inf.r) == ref.ranks:
+        Tref = O.tucker_full(ref.core, ref.Z)
+        assert np.max(np.abs(tile - Tref)) <= 1e-11 * np.max(np.abs(Tref))
+    # the Tucker factors are orthonormal and the core is their projection of the canonical sum
+    Z, core = r.tucker()
+    for a in range(3):
+        assert np.max(np.abs(Z[a] @ Z[a].T - np.eye(Z[a].shape[0]))) < 1e-11
+    mu = np.einsum("ijk,ai,bj,ck->abc", full, *Z, optimize=True)
+    assert np.max(np.abs(mu - core)) <= 1e-11 * np.max(np.abs(mu))
+    # points: Tucker sampling equals the tile values
+    rng = np.random.default_rng(1)
+    pts = np.stack([rng.integers(0, n, 64) for n in p.N], axis=1)
+    v = r.sample(cells_xyz(p, pts))
+    assert np.allclose(v, tile[pts[:, 0], pts[:, 1], pts[:, 2]], rtol=1e-12, atol=1e-12 * np.max(np.abs(tile)))
+    r.release()
+
+
+@pytest.mark.parametrize("prec", [W.FP32, W.BF16X3])
+def test_rhosvd_mixed_precision_error(ctx, prec):
+    p64 = _small_defected(eps=1e-6)
+    pm = _small_defected(eps=1e-6, precision=prec)
+    r64, rm = run(ctx, p64), run(ctx, pm)
+    t64 = r64.tile()
+    tm = rm.tile().astype(np.float64)
+    assert tuple(r64.info().r) == tuple(rm.info().r)        # SVD and truncation stay FP64
+    rel = np.max(np.abs(tm - t64)) / np.max(np.abs(t64))
+    # Accumulation is chunked (16 FP32 terms, then FP64), so the error comes from rounding the
+    # stored operands: Z, the projections, the core and the two tile intermediates, about six
+    # roundings of 2^-24 each, amplified by the cancellation inside the Tucker sum
+    # (sum |mu||Z||Z||Z| / |V|, about 5 here).  Split-BF16x3 products are good to about 2^-16.
+    tol = 6 * 2.0 ** -24 * 5 * 2 if prec == W.FP32 else 1e-4
+    assert rel < tol, rel
+    r64.release()
+    rm.release()
+
+
+def test_concurrent_requests_equal_alone(ctx):
+    import paper_1411_1994_amd as L
+    probs = [_small_defected(kind=k, param=pp, eps=e, seed=s, tile=False)
+             for (k, pp, e, s) in [(0, 0.0, 1e-6, 1), (1, 0.5, 1e-4, 2), (2, 1.0, 1e-6, 3), (0, 0.0, 1e-8, 4)]]
+    pts = np.array([[0.1, 0.2, 0.3], [1.0, -2.0, 0.5], [3.0, 3.0, -3.0]])
+    alone = []
+    for p in probs:
+        r = run(ctx, p)
+        alone.append(r.sample(pts))
+        r.release()
+    reqs = [ctx.submit(p) for p in probs * 3]
+    for i, r in enumerate(reqs):
+        assert r.wait() == 0
+        assert np.array_equal(r.sample(pts), alone[i % len(probs)])   # bitwise: batch-invariant kernels
+        r.release()
+
+
+def test_invalid_problems_are_rejected(ctx):
+    import paper_1411_1994_amd as L
+    good = W.Problem("bad", W.NEWTON, 0.0, 10, (21, 21, 21), 0.5, [W.cubic_block(2)])
+    cases = [
+        (dict(N=(20, 21, 21)), -1),
+        (dict(M=0), -1),
+        (dict(kind=9), -1),
+        (dict(blocks=[W.cubic_block(40)]), -2),
+        (dict(defects=[W.Defect(0, (0, 0, 0), -1.0), W.Defect(0, (0, 0, 0), 0.5)]), -3),
+        (dict(defects=[W.Defect(0, (2, 0, 0), -1.0)]), -2),
+        (dict(eps=1e-6, tile_lo=(0, 0, 10), tile_T=(21, 21, 21)), -1),
+    ]
+    for change, code in cases:
+        q = W.Problem(**{**good.__dict__, **change})
+        with pytest.raises(L.LsumError) as e:
+            ctx.submit(q)
+        assert e.value.code == code, (change, e.value)
+    # a budget that can never hold the request
+    small = L.Context(0, hbm_budget_bytes=1 << 20, n_slots=1)
+    with pytest.raises(L.LsumError) as e:
+        small.submit(good)
+    assert e.value.code == -4
+    small.close()
