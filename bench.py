@@ -1,0 +1,239 @@
+"""Benchmark of the lattice-sum library on one MI355X.
+
+Workload (default): the 64^3 Newton lattice in a box of half-width 40 on a 4097^3 grid, M = 40
+sinc nodes (rank 41), with the potential sampled at 1e5 seeded uniform points.  One step is one
+whole lattice sum: quadrature, collocation of the reference vectors, assembled shift-sums,
+point-major factors and the 1e5-point evaluation, submitted as one request whose points are
+already resident in HBM.
+
+Two paths on the same GPU:
+  * served: requests kept in flight on several stream slots; consecutive requests are fused
+    into batches whose shift-sums run as one launch; reference vectors shared through the cache;
+  * plain FP64: one request at a time, one slot, no batching, no reference cache.
+`value` is the served throughput (lattice sums/s); p50/p99 latency, the plain throughput, the
+error against the CPU oracle's brute-force sum, the roofline of the dominant kernel (event-timed
+inside the library over the timed region) and the oracle's own CPU rate are reported beside it.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cfg2|cfg3|cfg4]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16x3": 2500.0 / 3}
+METRIC = "lattice sums/s served vs plain FP64 at 1e-6 rel err; p50/p99 latency"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2048)
+    ap.add_argument("--warmup", type=int, default=128)
+    ap.add_argument("--workload", default="cfg2", choices=["cfg2", "cfg3", "cfg4"])
+    ap.add_argument("--inflight", type=int, default=64)
+    ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--batch", type=int, default=16)
+    ap.add_argument("--plain-steps", type=int, default=256)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    return ap.parse_args()
+
+
+def percentile(x, q):
+    return float(np.percentile(np.asarray(x), q)) if len(x) else None
+
+
+def run_stream(L, ctx, problem, points, outs, steps, inflight):
+    """Submit `steps` requests keeping at most `inflight` in flight; returns (seconds, latencies)."""
+    import torch
+    from collections import deque
+    q = deque()
+    lat = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        if len(q) >= inflight:
+            r = q.popleft()
+            rc = r.wait()
+            if rc != 0:
+                raise RuntimeError(f"request failed: {rc}")
+            inf = r.info()
+            lat.append(inf.t_queue_ms + inf.t_run_ms)
+            r.release()
+        q.append(ctx.submit(problem, points=points, values=outs[i % len(outs)]))
+    while q:
+        r = q.popleft()
+        rc = r.wait()
+        if rc != 0:
+            raise RuntimeError(f"request failed: {rc}")
+        inf = r.info()
+        lat.append(inf.t_queue_ms + inf.t_run_ms)
+        r.release()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, lat
+
+
+def dominant_roofline(prof: dict, dtype_peak: str):
+    """The stage with the largest GPU time: achieved = algorithmic work per launch / mean launch time."""
+    if not prof:
+        return None, None
+    name, st = max(prof.items(), key=lambda kv: kv[1]["ms"])
+    n = max(1, st["launches"])
+    ms = st["ms"] / n
+    if st["flops"] > 0 and st["bytes"] == 0 or name in ("core", "tile", "projection", "norm"):
+        achieved = st["flops"] / n / (ms * 1e-3) / 1e12
+        peak = PEAK_TFLOPS[dtype_peak]
+        return name, {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                      "frac": achieved / peak, "traffic": None, "kernel_stage": name,
+                      "avg_launch_ms": ms, "launches": st["launches"],
+                      "work_per_launch": st["flops"] / n}
+    achieved = st["bytes"] / n / (ms * 1e-3) / 1e9
+    return name, {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                  "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel_stage": name,
+                  "avg_launch_ms": ms, "launches": st["launches"], "bytes_per_launch": st["bytes"] / n}
+
+
+def traffic_from_profiles(stage: str):
+    """HBM bytes per launch from committed rocprofv3 --pmc summaries, if they were taken on the
+    current kernel source (their recorded source hash must match)."""
+    path = os.path.join(ROOT, "profiles", f"pmc_{stage}.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+        src = os.path.join(ROOT, rec["source"])
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        if sha != rec.get("source_sha256"):
+            return None
+        return rec["hbm_bytes_per_launch"]
+    except Exception:
+        return None
+
+
+def cpu_baseline(problem, xyz, seconds):
+    """The oracle (plain numpy FP64, same method) on the host cores: lattice sums/s."""
+    import oracle as O
+    try:
+        import psutil
+        proc = psutil.Process()
+    except Exception:
+        proc = None
+    n = 0
+    c0 = proc.cpu_times() if proc else None
+    t0 = time.perf_counter()
+    while True:
+        O.canonical_pipeline(problem, xyz)
+        n += 1
+        if time.perf_counter() - t0 >= seconds:
+            break
+    wall = time.perf_counter() - t0
+    cores = None
+    if proc:
+        c1 = proc.cpu_times()
+        cores = round(((c1.user - c0.user) + (c1.system - c0.system)) / wall, 2)
+    return {"value": n / wall, "unit": "lattice sums/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n} full lattice sums of the same workload (nodes, collocation, 1D shift-sums, "
+                      f"{len(xyz)} sampled points) in {wall:.1f} s", "host_cpus": os.cpu_count()}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU; multi-GPU runs are not part of this build",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+    import oracle as O
+    import paper_1411_1994_amd as L
+    import workloads as W
+
+    cfg = {"cfg2": 2, "cfg3": 3, "cfg4": 4}[args.workload]
+    problem = W.config(cfg)
+    n_pts = 100_000 if cfg == 2 else 4096
+    xyz = W.sample_points(cfg, n_pts, W.half_widths(problem))
+    xyz_d = torch.from_numpy(xyz).cuda()
+    steps, warmup = args.steps, args.warmup
+    if cfg != 2:                     # reduction workloads take seconds per request
+        steps, warmup = min(steps, 3), min(warmup, 1)
+    n_out = min(args.inflight, steps) + 2
+    outs = [torch.zeros(n_pts, dtype=torch.float64, device="cuda") for _ in range(n_out)]
+    torch.cuda.synchronize()
+
+    # ---- served path --------------------------------------------------------------------
+    ctx = L.Context(0, n_slots=args.slots if cfg == 2 else 1)
+    ctx.set_option(L.OPT_MAX_BATCH, args.batch)
+    run_stream(L, ctx, problem, xyz_d, outs, warmup, args.inflight)
+    ctx.reset_profile()
+    secs, lat = run_stream(L, ctx, problem, xyz_d, outs, steps, args.inflight)
+    prof = ctx.profile()
+    served = steps / secs
+    ctx.close()
+
+    # ---- plain FP64 path: one at a time, no batching, no reference cache ----------------
+    pctx = L.Context(0, n_slots=1)
+    pctx.set_option(L.OPT_MAX_BATCH, 1)
+    pctx.set_option(L.OPT_REF_CACHE_BYTES, 0)
+    plain_problem = W.Problem(**{**problem.__dict__, "precision": W.FP64})
+    psteps = min(args.plain_steps, steps) if cfg == 2 else 1
+    run_stream(L, pctx, plain_problem, xyz_d, outs, min(8, psteps), 1)
+    psecs, plat = run_stream(L, pctx, plain_problem, xyz_d, outs, psteps, 1)
+    plain = psteps / psecs
+    pctx.close()
+
+    # ---- accuracy of the served result against the oracle's brute-force sum ------------
+    vals = outs[(steps - 1) % len(outs)].cpu().numpy()
+    sel = np.random.default_rng(7).choice(n_pts, 12, replace=False)
+    cells = O.points_to_cells(xyz[sel], problem.h, problem.N)
+    ref = O.brute_force_points(problem, cells)
+    rel_err = float(np.max(np.abs(vals[sel] - ref)) / np.max(np.abs(ref)))
+
+    dtype = "f64" if problem.precision == W.FP64 or cfg == 2 else ("f32" if problem.precision == W.FP32 else "bf16x3")
+    stage, roof = dominant_roofline(prof, dtype)
+    if roof is not None:
+        roof["traffic"] = traffic_from_profiles(stage)
+    out = {
+        "metric": METRIC,
+        "value": served,
+        "unit": "lattice sums/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": 1000.0 / served,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype,
+        "data": "synthetic",
+        "config": {"workload": problem.name, "kernel": "newton" if problem.kind == 0 else "yukawa",
+                   "lattice_sites": problem.n_sites, "N": list(problem.N), "M": problem.M,
+                   "sample_points": n_pts, "defects": len(problem.defects), "eps": problem.eps,
+                   "slots": args.slots, "max_batch": args.batch, "inflight": args.inflight},
+        "latency_ms": {"p50": percentile(lat, 50), "p99": percentile(lat, 99)},
+        "plain_fp64": {"value": plain, "unit": "lattice sums/s",
+                       "latency_ms": {"p50": percentile(plat, 50), "p99": percentile(plat, 99)}},
+        "served_over_plain": served / plain,
+        "max_rel_err_vs_oracle": rel_err,
+        "roofline": roof,
+        "stages": {k: {"ms_per_launch": v["ms"] / max(1, v["launches"]), "launches": v["launches"]}
+                   for k, v in prof.items()},
+    }
+    if not args.no_cpu:
+        cxyz = xyz if cfg == 2 else xyz[:1000]
+        out["cpu_baseline"] = cpu_baseline(problem if cfg == 2 else W.Problem(**{**problem.__dict__, "defects": [], "eps": 0.0}),
+                                           cxyz, args.cpu_seconds)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

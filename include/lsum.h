@@ -104,6 +104,11 @@ typedef struct {
                                  always FP64                                                   */
     int tile_lo[3];           /* optional reconstruction tile: cells [lo, lo+T) per axis      */
     int tile_T[3];            /* T = 0: no tile                                                */
+    int n_points;             /* optional: potential sampled at these points on completion    */
+    const double* points;     /* 3 * n_points coordinates (x, y, z interleaved); caller-owned,
+                                 must stay valid until the request finishes                   */
+    double* values;           /* n_points results, written before the request finishes        */
+    int points_on_device;     /* 1: points/values are device pointers on the context's device */
 } lsum_problem;
 
 /* ---- host-side steps (FP64 / integer, no device work) ----------------------------------- */
@@ -128,8 +133,23 @@ typedef struct lsum_req_s* lsum_req;
  * (0: 80% of the device's free memory) and `n_slots` concurrent request slots (each slot a
  * HIP stream and a worker thread; 0: 4).  The context owns its streams, caches and workers. */
 int lsum_create(lsum_ctx* ctx, int device, size_t hbm_budget_bytes, int n_slots);
+/* Stops the workers (queued requests finish as LSUM_E_CANCELLED); device memory is freed when
+ * the last unreleased request of the context is released. */
 int lsum_destroy(lsum_ctx ctx);
 const char* lsum_last_error(void);
+
+/* Options: LSUM_OPT_MAX_BATCH (default 32): consecutive canonical requests (eps <= 0) a slot
+ * fuses into one batch whose shift-sums run as one launch (1: no batching).
+ * LSUM_OPT_REF_CACHE_BYTES (default 4 GiB): HBM kept for reference vectors shared by requests
+ * with the same kernel, quadrature and grid (0: every request recomputes its own). */
+#define LSUM_OPT_MAX_BATCH 1
+#define LSUM_OPT_REF_CACHE_BYTES 2
+int lsum_set_option(lsum_ctx ctx, int key, double value);
+/* Per stage (collocate, shift_sum, transpose, columns, norm, svd, projection, core, tile,
+ * sample): summed event-timed GPU milliseconds, number of timed launches, and the algorithmic
+ * bytes and flops those launches had to move or compute, as JSON; returns the needed length. */
+int lsum_get_profile(lsum_ctx ctx, char* buf, size_t len);
+int lsum_reset_profile(lsum_ctx ctx);
 
 /* ---- device steps of the path (each one kernel family, on `stream`) --------------------- */
 
@@ -154,13 +174,15 @@ int lsum_sample_canonical(lsum_ctx ctx, void* stream, int n_fac, int R, const do
 
 /* Truncated SVD of a side matrix (Def. def:RHOSVD): the D columns a_j (row j of A_dev, length
  * N, stride lda) are rotated in place by a one-sided block-Jacobi SVD in FP64 until every
- * pair of columns has relative coupling |a_i.a_j|/(|a_i||a_j|) <= tol (or lies below an
- * absolute floor of 1e-30 of the matrix norm).  On return the rows of A_dev hold the rotated
- * columns sorted by descending norm and sigma[0..D-1] (host) their norms; the leading rows
- * divided by sigma are the left singular vectors.  Synchronous.  Returns LSUM_E_NOCONV after
- * `max_sweeps` sweeps without convergence (results are still written). */
+ * pair of columns whose norms both exceed `irrelevant` has relative coupling
+ * |a_i.a_j|/(|a_i||a_j|) <= tol (irrelevant <= 0: 1e-15 of the largest column norm).  On return
+ * the rows of A_dev hold the rotated columns sorted by descending norm and sigma[0..D-1] (host)
+ * their norms; the leading rows divided by sigma are left singular vectors, and for every r the
+ * residual of projecting A onto the first r of them is at most (sum_{k>=r} sigma_k^2)^(1/2).
+ * Synchronous.  Returns LSUM_E_NOCONV after `max_sweeps` sweeps without convergence (results
+ * are still written). */
 int lsum_jacobi_svd(lsum_ctx ctx, void* stream, int D, int N, double* A_dev, int lda,
-                    double tol, int max_sweeps, double* sigma, int* sweeps);
+                    double tol, double irrelevant, int max_sweeps, double* sigma, int* sweeps);
 
 /* Dense contraction used by the projections Z^T A (Appendix theorem (c)) and the mode
  * products of the Tucker reconstruction (eq. Tucker_singePot): C(m,n) = alpha * sum_k A(m,k)

@@ -29,7 +29,8 @@ SYMBOLS = ["lsum_nodes", "lsum_block_offsets", "lsum_create", "lsum_destroy", "l
            "lsum_contract",
            "lsum_submit", "lsum_wait", "lsum_cancel", "lsum_get_info", "lsum_get_canonical",
            "lsum_get_tucker", "lsum_get_sigma", "lsum_sample", "lsum_get_tile", "lsum_get_stats",
-           "lsum_release"]
+           "lsum_release", "lsum_set_option", "lsum_get_profile", "lsum_reset_profile"]
+OPT_MAX_BATCH, OPT_REF_CACHE_BYTES = 1, 2
 
 
 class LsumError(RuntimeError):
@@ -57,7 +58,8 @@ class lsum_problem(C.Structure):
                 ("n_blocks", C.c_int), ("blocks", C.POINTER(lsum_block)),
                 ("n_defects", C.c_int), ("defects", C.POINTER(lsum_defect)),
                 ("eps", C.c_double), ("precision", C.c_int), ("tile_lo", C.c_int * 3),
-                ("tile_T", C.c_int * 3)]
+                ("tile_T", C.c_int * 3), ("n_points", C.c_int), ("points", C.c_void_p),
+                ("values", C.c_void_p), ("points_on_device", C.c_int)]
 
 
 class lsum_info(C.Structure):
@@ -68,6 +70,13 @@ class lsum_info(C.Structure):
 
 
 def _load():
+    # One HIP runtime per process: torch ships its own libamdhip64 with the same SONAME as the
+    # system one this library links against, so whichever is loaded first serves both.  Load
+    # torch's first (when installed) so torch tensors and this library share the runtime.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_1411_1994_amd/build.py` "
                           "(there is no non-HIP implementation)")
@@ -82,7 +91,7 @@ def _load():
         "lsum_collocate": (I, [VP, VP, I, P(D), P(D), I, D, VP, I]),
         "lsum_shift_sum": (I, [VP, VP, I, VP, I, I, I, I, P(C.c_int32), VP, I]),
         "lsum_sample_canonical": (I, [VP, VP, I, I, VP, I, P(D), P(I), D, I, VP, VP]),
-        "lsum_jacobi_svd": (I, [VP, VP, I, I, VP, I, D, I, P(D), P(I)]),
+        "lsum_jacobi_svd": (I, [VP, VP, I, I, VP, I, D, D, I, P(D), P(I)]),
         "lsum_contract": (I, [VP, VP, I, I, I, I, VP, C.c_long, C.c_long, VP, C.c_long, C.c_long, VP,
                               C.c_long, C.c_long, D, D]),
         "lsum_submit": (I, [VP, P(lsum_problem), I, P(VP)]),
@@ -96,6 +105,9 @@ def _load():
         "lsum_get_tile": (I, [VP, VP, I, I]),
         "lsum_get_stats": (I, [VP, C.c_char_p, C.c_size_t]),
         "lsum_release": (I, [VP]),
+        "lsum_set_option": (I, [VP, I, D]),
+        "lsum_get_profile": (I, [VP, C.c_char_p, C.c_size_t]),
+        "lsum_reset_profile": (I, [VP]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -216,12 +228,12 @@ class Context:
                                           _dptr(lam), (C.c_int * 3)(*N), h, n_pts, _ptr(xyz_dev),
                                           _ptr(out_dev)))
 
-    def jacobi_svd(self, D: int, N: int, A_dev, lda: int, tol: float = 1e-12, max_sweeps: int = 40,
-                   stream=None):
+    def jacobi_svd(self, D: int, N: int, A_dev, lda: int, tol: float = 1e-12, irrelevant: float = 0.0,
+                   max_sweeps: int = 40, stream=None):
         sig = np.zeros(D)
         sweeps = C.c_int(0)
-        rc = _lib.lsum_jacobi_svd(self.handle, _stream(stream), D, N, _ptr(A_dev), lda, tol, max_sweeps,
-                                  _dptr(sig), C.byref(sweeps))
+        rc = _lib.lsum_jacobi_svd(self.handle, _stream(stream), D, N, _ptr(A_dev), lda, tol, irrelevant,
+                                  max_sweeps, _dptr(sig), C.byref(sweeps))
         _check(rc)
         return sig, sweeps.value
 
@@ -230,12 +242,27 @@ class Context:
         _check(_lib.lsum_contract(self.handle, _stream(stream), prec, m, n, k, _ptr(A_dev), sam, sak,
                                   _ptr(B_dev), sbk, sbn, _ptr(C_dev), scm, scn, alpha, beta))
 
+    # -- options and profile --------------------------------------------------------------
+    def set_option(self, key: int, value: float):
+        _check(_lib.lsum_set_option(self.handle, key, float(value)))
+
+    def profile(self) -> dict:
+        n = _lib.lsum_get_profile(self.handle, None, 0)
+        buf = C.create_string_buffer(n + 16)
+        _lib.lsum_get_profile(self.handle, buf, n + 16)
+        return json.loads(buf.value.decode())
+
+    def reset_profile(self):
+        _check(_lib.lsum_reset_profile(self.handle))
+
     # -- requests -------------------------------------------------------------------------
-    def submit(self, problem, nonblocking: bool = False) -> "Request":
-        return Request(self, problem, nonblocking)
+    def submit(self, problem, nonblocking: bool = False, points=None, values=None) -> "Request":
+        """Submit a problem; optional sample points (n x 3) and an output array (n) -- numpy arrays
+        (host) or device tensors -- are evaluated as part of the request."""
+        return Request(self, problem, nonblocking, points, values)
 
 
-def make_problem(p) -> tuple:
+def make_problem(p, points=None, values=None) -> tuple:
     """A C ``lsum_problem`` from any object with the fields of ``workloads.Problem``; returns
     (struct, keep-alive list)."""
     blocks = (lsum_block * len(p.blocks))(*[_block(b) for b in p.blocks])
@@ -249,23 +276,38 @@ def make_problem(p) -> tuple:
                         C.cast(defects, C.POINTER(lsum_defect)) if nd else None,
                         float(p.eps), int(p.precision), (C.c_int * 3)(*p.tile_lo),
                         (C.c_int * 3)(*p.tile_T))
-    return prob, [blocks, defects]
+    keep = [blocks, defects]
+    if points is not None:
+        on_dev = not isinstance(points, np.ndarray)
+        prob.n_points = int(points.shape[0])
+        prob.points = _ptr(points)
+        prob.values = _ptr(values)
+        prob.points_on_device = 1 if on_dev else 0
+        keep += [points, values]
+    return prob, keep
 
 
 class Request:
     """One submitted problem (``lsum_submit`` ... ``lsum_release``)."""
 
-    def __init__(self, ctx: Context, problem, nonblocking: bool = False):
+    def __init__(self, ctx: Context, problem, nonblocking: bool = False, points=None, values=None):
         self.ctx = ctx
         self.problem = problem
-        prob, keep = make_problem(problem)
+        if points is not None and isinstance(points, np.ndarray):
+            points = np.ascontiguousarray(points, dtype=np.float64)
+            if values is None:
+                values = np.zeros(points.shape[0])
+        prob, keep = make_problem(problem, points, values)
+        self._keep = keep            # caller memory must outlive the request
+        self.values = values
         h = C.c_void_p()
         _check(_lib.lsum_submit(ctx.handle, C.byref(prob), 1 if nonblocking else 0, C.byref(h)))
         self.handle = h
 
     def wait(self, timeout_ms: int = -1) -> int:
-        rc = _lib.lsum_wait(self.handle, timeout_ms)
-        return _check(rc)
+        """The request's final status (0, or a negative LSUM_E_* code such as -6 for a cancelled
+        request), or -8 (TIMEOUT) if it is still running after timeout_ms."""
+        return int(_lib.lsum_wait(self.handle, timeout_ms))
 
     def cancel(self):
         _check(_lib.lsum_cancel(self.handle))

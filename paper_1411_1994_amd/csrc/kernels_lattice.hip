@@ -42,28 +42,76 @@ __global__ void __launch_bounds__(256) k_collocate(int R, const double* __restri
 
 // --------------------------------------------------------------------------------------------
 // Assembled 1D sums (Thm thm:sumCaseE (A)): U[q, i] = sum_k G[q, i - c_k + N_ref - 1].
-// Grid (x: cell tiles of 256, y: node q, z: job).  The site list is uniform across the
-// workgroup (scalar loads); the reference row is read through L2 with unit stride in i.
+// One workgroup per (64-cell tile, job); lane = cell, the 4 waves split the nodes q.  With a
+// comb decomposition the sum over the L sites becomes `period` differences of strided prefix
+// sums.  Results go to the vector-major rows directly and, through an LDS tile, to the
+// point-major rows, whose 64 x R block is one contiguous, coalesced store.
 // --------------------------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_shift_sum(const ShiftJob* __restrict__ jobs) {
-    const ShiftJob jb = jobs[blockIdx.z];
-    const int q = blockIdx.y;
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (q >= jb.R || i >= jb.N_axis) return;
-    const double* __restrict__ g = jb.G + (size_t)q * jb.ldg + (i + jb.N_ref - 1);
+    __shared__ double tile[64][65];
+    const ShiftJob jb = jobs[blockIdx.y];
+    const int i0 = blockIdx.x * 64;
+    if (i0 >= jb.N_axis) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int i = i0 + lane;
     const int32_t* __restrict__ c = jb.sites;
-    const int n = jb.n_sites;
-    double acc = 0.0;
-    int k = 0;
-    for (; k + 4 <= n; k += 4) {
-        const double a0 = g[-c[k]], a1 = g[-c[k + 1]], a2 = g[-c[k + 2]], a3 = g[-c[k + 3]];
-        acc += a0;
-        acc += a1;
-        acc += a2;
-        acc += a3;
+    for (int q0 = 0; q0 < jb.R; q0 += 64) {
+        const int qn = min(64, jb.R - q0);
+        for (int qq = wave; qq < qn; qq += 4) {
+            const int q = q0 + qq;
+            double acc = 0.0;
+            if (i < jb.N_axis) {
+                const int base = i + jb.N_ref - 1;
+                if (jb.P) {
+                    const double* __restrict__ pr = jb.P + (size_t)q * jb.ldg;
+                    for (int j = 0; j < jb.period; ++j) {
+                        const int nj = (jb.n_sites - j + jb.period - 1) / jb.period;
+                        const int x1 = base - c[j];
+                        const int x2 = x1 - nj * jb.stride;
+                        acc += pr[x1] - (x2 >= 0 ? pr[x2] : 0.0);
+                    }
+                } else {
+                    const double* __restrict__ g = jb.G + (size_t)q * jb.ldg + base;
+                    const int n = jb.n_sites;
+                    int k = 0;
+                    for (; k + 4 <= n; k += 4) {
+                        const double a0 = g[-c[k]], a1 = g[-c[k + 1]], a2 = g[-c[k + 2]], a3 = g[-c[k + 3]];
+                        acc += a0;
+                        acc += a1;
+                        acc += a2;
+                        acc += a3;
+                    }
+                    for (; k < n; ++k) acc += g[-c[k]];
+                }
+                if (jb.U) jb.U[(size_t)q * jb.ldu + i] = acc;
+            }
+            tile[lane][qq] = acc;
+        }
+        __syncthreads();
+        if (jb.UT) {
+            const int rows = min(64, jb.N_axis - i0);
+            for (int e = threadIdx.x; e < rows * qn; e += 256) {
+                const int ii = e / qn, qq = e % qn;
+                jb.UT[(size_t)(i0 + ii) * jb.R + q0 + qq] = tile[ii][qq];
+            }
+        }
+        __syncthreads();
     }
-    for (; k < n; ++k) acc += g[-c[k]];
-    jb.U[(size_t)q * jb.ldu + i] = acc;
+}
+
+// Strided prefix sums of the reference rows: one thread per (q, residue class mod S).
+__global__ void __launch_bounds__(256) k_prefix(int R, const double* __restrict__ G, int ldg, int len, int S,
+                                                double* __restrict__ P) {
+    const long t = (long)blockIdx.x * 256 + threadIdx.x;
+    if (t >= (long)R * S) return;
+    const int q = (int)(t / S), rho = (int)(t % S);
+    const double* g = G + (size_t)q * ldg;
+    double* pr = P + (size_t)q * ldg;
+    double acc = 0.0;
+    for (int x = rho; x < len; x += S) {
+        acc += g[x];
+        pr[x] = acc;
+    }
 }
 
 __device__ __forceinline__ int snap_dev(double x, double h, int N) {
@@ -123,6 +171,54 @@ __global__ void __launch_bounds__(256) k_sample_block(int R, const double* __res
     for (int q = 0; q < R; ++q)
         acc += U0[(size_t)q * N0 + i0] * U1[(size_t)q * N1 + i1] * U2[(size_t)q * N2 + i2];
     out[p] += lam * acc;
+}
+
+// Vector-major R x N rows -> point-major N x R rows, through a 32 x 32 LDS tile.
+__global__ void __launch_bounds__(256) k_transpose(int R, int N, const double* __restrict__ U, int ldu,
+                                                   double* __restrict__ UT) {
+    __shared__ double tile[32][33];
+    const int i0 = blockIdx.x * 32, q0 = blockIdx.y * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+    for (int k = ty; k < 32; k += 8) {
+        const int q = q0 + k, i = i0 + tx;
+        tile[k][tx] = (q < R && i < N) ? U[(size_t)q * ldu + i] : 0.0;
+    }
+    __syncthreads();
+    for (int k = ty; k < 32; k += 8) {
+        const int i = i0 + k, q = q0 + tx;
+        if (i < N && q < R) UT[(size_t)i * R + q] = tile[tx][k];
+    }
+}
+
+// Canonical sum at points from point-major factors (row i holds the R values of cell i): each
+// wavefront evaluates 4 points with 16 lanes per point striding over the nodes q, so every
+// gather is a contiguous piece of a row; the partial products are reduced across the 16 lanes.
+// out[p] (+)= lam * sum_q prod_l UT_l[i_l(p), q].
+__global__ void __launch_bounds__(256) k_sample_rows(int R, const double* __restrict__ T0,
+                                                     const double* __restrict__ T1,
+                                                     const double* __restrict__ T2, int N0, int N1, int N2,
+                                                     double h, double lam, int accumulate, int n_pts,
+                                                     const double* __restrict__ xyz,
+                                                     double* __restrict__ out) {
+    const int l16 = threadIdx.x & 15;
+    const int p = blockIdx.x * 16 + (threadIdx.x >> 4);
+    if (p >= n_pts) return;
+    const int i0 = snap_dev(xyz[3 * (size_t)p + 0], h, N0);
+    const int i1 = snap_dev(xyz[3 * (size_t)p + 1], h, N1);
+    const int i2 = snap_dev(xyz[3 * (size_t)p + 2], h, N2);
+    const bool inside = i0 >= 0 && i1 >= 0 && i2 >= 0;
+    double acc = 0.0;
+    if (inside) {
+        const double* r0 = T0 + (size_t)i0 * R;
+        const double* r1 = T1 + (size_t)i1 * R;
+        const double* r2 = T2 + (size_t)i2 * R;
+        for (int q = l16; q < R; q += 16) acc += r0[q] * r1[q] * r2[q];
+    }
+    for (int m = 8; m > 0; m >>= 1) acc += __shfl_xor(acc, m, 16);
+    if (l16 == 0) {
+        if (!inside) out[p] = __builtin_nan("");
+        else out[p] = accumulate ? out[p] + lam * acc : lam * acc;
+    }
 }
 
 // Defect terms straight from the reference rows: out[p] += sum_s dZ_s sum_q prod_l
@@ -283,10 +379,29 @@ void launch_collocate(hipStream_t st, int R, const double* t_dev, const double* 
     hipLaunchKernelGGL(k_collocate, grid, dim3(256), 0, st, R, t_dev, w13_dev, N_ref, h, G, ldg);
 }
 
-void launch_shift_sum(hipStream_t st, const ShiftJob* jobs_dev, int n_jobs, int max_N, int max_R) {
+void launch_shift_sum(hipStream_t st, const ShiftJob* jobs_dev, int n_jobs, int max_N) {
     if (n_jobs <= 0) return;
-    dim3 grid(cdiv(max_N, 256), max_R, n_jobs);
+    dim3 grid(cdiv(max_N, 64), n_jobs);
     hipLaunchKernelGGL(k_shift_sum, grid, dim3(256), 0, st, jobs_dev);
+}
+
+void launch_prefix(hipStream_t st, int R, const double* G, int ldg, int len, int stride, double* P) {
+    if (R <= 0 || stride <= 0) return;
+    hipLaunchKernelGGL(k_prefix, dim3(cdiv((long)R * stride, 256)), dim3(256), 0, st, R, G, ldg, len, stride, P);
+}
+
+int comb_period(const int32_t* c, int n, int max_p, int* stride) {
+    for (int p = 1; p <= max_p && p < n; ++p) {
+        const int S = c[p] - c[0];
+        if (S <= 0) continue;
+        bool ok = true;
+        for (int k = 0; k + p < n && ok; ++k) ok = (c[k + p] - c[k] == S);
+        if (ok) {
+            *stride = S;
+            return p;
+        }
+    }
+    return 0;
 }
 
 void launch_sample_cp(hipStream_t st, int n_fac, int R, const double* U, int ldu,
@@ -303,6 +418,19 @@ void launch_sample_block(hipStream_t st, int R, const double* U0, const double* 
     if (n_pts <= 0) return;
     hipLaunchKernelGGL(k_sample_block, dim3(cdiv(n_pts, 256)), dim3(256), 0, st, R, U0, U1, U2, N0,
                        N1, N2, h, lam, n_pts, xyz, out);
+}
+
+void launch_transpose(hipStream_t st, int R, int N, const double* U, int ldu, double* UT) {
+    if (R <= 0 || N <= 0) return;
+    hipLaunchKernelGGL(k_transpose, dim3(cdiv(N, 32), cdiv(R, 32)), dim3(256), 0, st, R, N, U, ldu, UT);
+}
+
+void launch_sample_rows(hipStream_t st, int R, const double* T0, const double* T1, const double* T2, int N0,
+                        int N1, int N2, double h, double lam, int accumulate, int n_pts, const double* xyz,
+                        double* out) {
+    if (n_pts <= 0) return;
+    hipLaunchKernelGGL(k_sample_rows, dim3(cdiv(n_pts, 16)), dim3(256), 0, st, R, T0, T1, T2, N0, N1, N2, h, lam,
+                       accumulate, n_pts, xyz, out);
 }
 
 void launch_sample_windows(hipStream_t st, int R, const double* G, int ldg, int N_ref, int n_def,

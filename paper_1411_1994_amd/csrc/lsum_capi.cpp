@@ -1,0 +1,542 @@
+// C ABI of the lattice-sum library (include/lsum.h): context and request lifecycle, results,
+// options, profile, and the stage-level entry points used to test each kernel family.
+#include "lsum_runtime.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <sstream>
+
+using namespace lsum;
+
+struct lsum_ctx_s {
+    std::shared_ptr<Context> sp;
+    Context& c;
+    lsum_ctx_s() : sp(std::make_shared<Context>()), c(*sp) {}
+};
+struct lsum_req_s {
+    Request q;
+};
+
+extern "C" {
+
+int lsum_create(lsum_ctx* out, int device, size_t budget, int n_slots) {
+    if (!out) return fail(LSUM_E_INVALID, "null ctx pointer");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) {
+        (void)hipGetLastError();
+        return fail(LSUM_E_DEVICE, "no HIP device available");
+    }
+    if (device < 0 || device >= ndev) return fail(LSUM_E_INVALID, "bad device index");
+    LSUM_HIP(hipSetDevice(device));
+    size_t fr = 0, tot = 0;
+    LSUM_HIP(hipMemGetInfo(&fr, &tot));
+    auto* x = new lsum_ctx_s();
+    Context& c = x->c;
+    c.device = device;
+    c.budget = budget ? budget : (size_t)(0.8 * (double)fr);
+    c.n_slots = n_slots > 0 ? n_slots : 4;
+    c.pool = new DevPool();
+    if (hipStreamCreateWithFlags(&c.own_stream, hipStreamNonBlocking) != hipSuccess) {
+        c.own_stream = nullptr;
+        delete x;
+        return fail(LSUM_E_DEVICE, "stream creation failed");
+    }
+    for (int i = 0; i < c.n_slots; ++i) {
+        hipStream_t s = nullptr;
+        if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+            delete x;
+            return fail(LSUM_E_DEVICE, "stream creation failed");
+        }
+        c.streams.push_back(s);
+    }
+    for (int i = 0; i < c.n_slots; ++i) c.workers.emplace_back(worker, &c, i);
+    *out = x;
+    return LSUM_OK;
+}
+
+int lsum_destroy(lsum_ctx x) {
+    if (!x) return LSUM_OK;
+    Context& c = x->c;
+    {
+        std::lock_guard<std::mutex> lk(c.mu);
+        c.stopping = true;
+    }
+    c.cv.notify_all();
+    for (auto& t : c.workers) t.join();
+    c.workers.clear();
+    // streams, caches and the pool go when the last unreleased request lets go of the context
+    delete x;
+    return LSUM_OK;
+}
+
+int lsum_submit(lsum_ctx x, const lsum_problem* p, int nonblocking, lsum_req* out) {
+    if (!x || !p || !out) return fail(LSUM_E_INVALID, "null argument");
+    auto* r = new lsum_req_s();
+    Request& q = r->q;
+    q.ctx_ref = x->sp;
+    q.ctx = &x->c;
+    int rc = make_plan(*p, q.plan);
+    if (rc != LSUM_OK) {
+        delete r;
+        return rc;
+    }
+    if (p->n_points < 0 || (p->n_points > 0 && (!p->points || !p->values))) {
+        delete r;
+        return fail(LSUM_E_INVALID, "bad sample point arguments");
+    }
+    q.n_points = p->n_points;
+    q.points = p->points;
+    q.values = p->values;
+    q.points_on_device = p->points_on_device;
+    q.reserved = q.plan.planned_bytes() + (q.points_on_device ? 0 : (size_t)q.n_points * 32);
+    Context& c = x->c;
+    if (q.reserved > c.budget) {
+        delete r;
+        return fail(LSUM_E_NOMEM, "the request can never fit the HBM budget");
+    }
+    {
+        std::lock_guard<std::mutex> lk(c.mu);
+        if (c.stopping) {
+            delete r;
+            return fail(LSUM_E_STATE, "context is shutting down");
+        }
+        if (c.queue.size() >= c.max_queue) {
+            if (nonblocking) {
+                delete r;
+                return fail(LSUM_E_BUSY, "queue full");
+            }
+        }
+        q.t_submit = Clock::now();
+        c.queue.push_back(&q);
+    }
+    c.cv.notify_all();
+    *out = r;
+    return LSUM_OK;
+}
+
+int lsum_wait(lsum_req r, int timeout_ms) {
+    if (!r) return fail(LSUM_E_INVALID, "null request");
+    Request& q = r->q;
+    std::unique_lock<std::mutex> lk(q.mu);
+    if (timeout_ms < 0) {
+        q.cv.wait(lk, [&] { return q.done; });
+    } else if (!q.cv.wait_for(lk, std::chrono::milliseconds(timeout_ms), [&] { return q.done; })) {
+        return LSUM_E_TIMEOUT;
+    }
+    return q.status.load();
+}
+
+int lsum_cancel(lsum_req r) {
+    if (!r) return fail(LSUM_E_INVALID, "null request");
+    Request& q = r->q;
+    Context& c = *q.ctx;
+    {
+        std::lock_guard<std::mutex> lk(c.mu);
+        auto it = std::find(c.queue.begin(), c.queue.end(), &q);
+        if (it == c.queue.end()) return fail(LSUM_E_STATE, "request already started or finished");
+        c.queue.erase(it);
+    }
+    c.cv.notify_all();
+    finish(&q, LSUM_E_CANCELLED);
+    return LSUM_OK;
+}
+
+static int l_max(const Plan& P) { return P.N[0] >= P.N[1] ? (P.N[0] >= P.N[2] ? 0 : 2) : (P.N[1] >= P.N[2] ? 1 : 2); }
+
+static int need_done(lsum_req r) {
+    if (!r) return fail(LSUM_E_INVALID, "null request");
+    std::lock_guard<std::mutex> lk(r->q.mu);
+    if (!r->q.done) return fail(LSUM_E_STATE, "request not finished");
+    if (r->q.status.load() != LSUM_OK) return fail(LSUM_E_STATE, "request failed");
+    return LSUM_OK;
+}
+
+int lsum_get_info(lsum_req r, lsum_info* info) {
+    if (!r || !info) return fail(LSUM_E_INVALID, "null argument");
+    Request& q = r->q;
+    std::lock_guard<std::mutex> lk(q.mu);
+    std::memset(info, 0, sizeof(*info));
+    info->status = q.done ? q.status.load() : 1;
+    const Plan& P = q.plan;
+    info->R = P.R;
+    info->n_terms = P.R * P.n_groups;
+    info->is_tucker = P.tucker() ? 1 : 0;
+    for (int l = 0; l < 3; ++l) {
+        info->r[l] = q.r[l];
+        info->D[l] = P.D[l];
+    }
+    info->norm_A = q.norm_A;
+    info->norm_xi = q.norm_xi;
+    info->bound = q.bound;
+    info->rel_bound = q.norm_A > 0 ? q.bound / q.norm_A : 0.0;
+    if (q.started) info->t_queue_ms = ms_since(q.t_submit, q.t_start);
+    if (q.done && q.started) info->t_run_ms = ms_since(q.t_start, q.t_end);
+    return LSUM_OK;
+}
+
+static int copy_out(void* dst, const void* src, size_t bytes, int on_device, int device) {
+    LSUM_HIP(hipSetDevice(device));
+    LSUM_HIP(hipMemcpy(dst, src, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost));
+    return LSUM_OK;
+}
+
+int lsum_get_canonical(lsum_req r, int block, double* U0, double* U1, double* U2, int on_device) {
+    int rc = need_done(r);
+    if (rc) return rc;
+    Request& q = r->q;
+    const Plan& P = q.plan;
+    if (block < 0 || block >= (int)P.blocks.size()) return fail(LSUM_E_INVALID, "bad block index");
+    double* dst[3] = {U0, U1, U2};
+    const bool have_vm = q.U[block].p != nullptr;
+    DevBuf tmp;
+    if (!have_vm) {
+        LSUM_HIP(hipSetDevice(q.ctx->device));
+        if ((rc = tmp.get(q.ctx->pool, (size_t)P.R * P.N[l_max(P)] * 8))) return rc;
+    }
+    for (int l = 0; l < 3; ++l) {
+        if (!dst[l]) continue;
+        const double* src = have_vm ? q.U[block].as<double>() + q.U_axis_off[l] : nullptr;
+        if (!have_vm) {
+            // factors are kept point-major (N x R); transpose back to R x N
+            launch_transpose(q.ctx->own_stream, P.N[l], P.R, q.UT[block].as<double>() + q.U_axis_off[l], P.R,
+                             tmp.as<double>());
+            LSUM_HIP(hipStreamSynchronize(q.ctx->own_stream));
+            src = tmp.as<double>();
+        }
+        rc = copy_out(dst[l], src, (size_t)P.R * P.N[l] * 8, on_device, q.ctx->device);
+        if (rc) return rc;
+    }
+    return LSUM_OK;
+}
+
+int lsum_get_tucker(lsum_req r, double* Z0, double* Z1, double* Z2, double* core, int on_device) {
+    int rc = need_done(r);
+    if (rc) return rc;
+    Request& q = r->q;
+    const Plan& P = q.plan;
+    if (!P.tucker()) return fail(LSUM_E_STATE, "request has no Tucker output");
+    double* dst[3] = {Z0, Z1, Z2};
+    for (int l = 0; l < 3; ++l) {
+        if (!dst[l]) continue;
+        rc = copy_out(dst[l], q.Z[l].p, (size_t)q.r[l] * P.N[l] * 8, on_device, q.ctx->device);
+        if (rc) return rc;
+    }
+    if (core) {
+        const size_t n = (size_t)q.r[0] * q.r[1] * q.r[2];
+        if (P.precision == LSUM_FP64) return copy_out(core, q.core.p, n * 8, on_device, q.ctx->device);
+        LSUM_HIP(hipSetDevice(q.ctx->device));
+        DevBuf tmp;
+        if ((rc = tmp.get(q.ctx->pool, n * 8))) return rc;
+        launch_f32_to_f64(q.ctx->own_stream, (long)n, q.core.as<float>(), tmp.as<double>());
+        LSUM_HIP(hipStreamSynchronize(q.ctx->own_stream));
+        return copy_out(core, tmp.p, n * 8, on_device, q.ctx->device);
+    }
+    return LSUM_OK;
+}
+
+int lsum_get_sigma(lsum_req r, double* s0, double* s1, double* s2) {
+    int rc = need_done(r);
+    if (rc) return rc;
+    Request& q = r->q;
+    double* dst[3] = {s0, s1, s2};
+    for (int l = 0; l < 3; ++l)
+        if (dst[l]) std::copy(q.sigma[l].begin(), q.sigma[l].end(), dst[l]);
+    return LSUM_OK;
+}
+
+int lsum_sample(lsum_req r, int n, const double* xyz, double* out, int on_device) {
+    int rc = need_done(r);
+    if (rc) return rc;
+    if (n < 0 || (n > 0 && (!xyz || !out))) return fail(LSUM_E_INVALID, "bad point arguments");
+    if (n == 0) return LSUM_OK;
+    Request& q = r->q;
+    Context& c = *q.ctx;
+    const Plan& P = q.plan;
+    LSUM_HIP(hipSetDevice(c.device));
+    hipStream_t st = c.own_stream;
+    DevBuf xd, od;
+    const double* xyz_d = xyz;
+    double* out_d = out;
+    if (!on_device) {
+        if ((rc = xd.get(c.pool, (size_t)n * 24))) return rc;
+        if ((rc = od.get(c.pool, (size_t)n * 8))) return rc;
+        LSUM_HIP(hipMemcpyAsync(xd.p, xyz, (size_t)n * 24, hipMemcpyHostToDevice, st));
+        xyz_d = xd.as<double>();
+        out_d = od.as<double>();
+    }
+    (void)P;
+    rc = sample_points(&q, st, n, xyz_d, out_d);
+    if (rc) return rc;
+    LSUM_HIP(hipGetLastError());
+    if (!on_device) LSUM_HIP(hipMemcpyAsync(out, out_d, (size_t)n * 8, hipMemcpyDeviceToHost, st));
+    LSUM_HIP(hipStreamSynchronize(st));
+    return LSUM_OK;
+}
+
+int lsum_get_tile(lsum_req r, void* out, int elem_size, int on_device) {
+    int rc = need_done(r);
+    if (rc) return rc;
+    Request& q = r->q;
+    const Plan& P = q.plan;
+    if (!P.has_tile()) return fail(LSUM_E_STATE, "request has no tile");
+    const int want = P.precision == LSUM_FP64 ? 8 : 4;
+    if (elem_size != want) return fail(LSUM_E_INVALID, "tile element size does not match the precision");
+    const size_t n = (size_t)P.tile_T[0] * P.tile_T[1] * P.tile_T[2];
+    return copy_out(out, q.tile.p, n * want, on_device, q.ctx->device);
+}
+
+int lsum_get_stats(lsum_req r, char* buf, size_t len) {
+    if (!r) return fail(LSUM_E_INVALID, "null request");
+    Request& q = r->q;
+    std::ostringstream o;
+    o.precision(17);
+    const Plan& P = q.plan;
+    {
+        std::lock_guard<std::mutex> lk(q.mu);
+        o << "{\"status\":" << (q.done ? q.status.load() : 1) << ",\"R\":" << P.R << ",\"n_groups\":" << P.n_groups
+          << ",\"h_u\":" << P.h_u << ",\"s\":" << P.s << ",\"N\":[" << P.N[0] << "," << P.N[1] << "," << P.N[2]
+          << "],\"D\":[" << P.D[0] << "," << P.D[1] << "," << P.D[2] << "],\"r\":[" << q.r[0] << "," << q.r[1]
+          << "," << q.r[2] << "],\"sweeps\":[" << q.sweeps[0] << "," << q.sweeps[1] << "," << q.sweeps[2]
+          << "],\"tails\":[" << q.tails[0] << "," << q.tails[1] << "," << q.tails[2] << "],\"norm_A\":" << q.norm_A
+          << ",\"norm_xi\":" << q.norm_xi << ",\"bound\":" << q.bound << ",\"batch\":" << q.batch_size
+          << ",\"offsets\":[";
+        for (int b = 0; b < (int)P.blocks.size(); ++b) {
+            o << (b ? "," : "") << "[";
+            for (int l = 0; l < 3; ++l) {
+                o << (l ? "," : "") << "[";
+                for (size_t k = 0; k < P.offs[l][b].size(); ++k) o << (k ? "," : "") << P.offs[l][b][k];
+                o << "]";
+            }
+            o << "]";
+        }
+        o << "],\"t_ms\":{";
+        bool first = true;
+        for (auto& kv : q.t_ms) {
+            o << (first ? "" : ",") << "\"" << kv.first << "\":" << kv.second;
+            first = false;
+        }
+        o << "},\"bytes\":{";
+        first = true;
+        for (auto& kv : q.bytes) {
+            o << (first ? "" : ",") << "\"" << kv.first << "\":" << kv.second;
+            first = false;
+        }
+        o << "}";
+        if (q.started) o << ",\"t_queue_ms\":" << ms_since(q.t_submit, q.t_start);
+        if (q.done && q.started) o << ",\"t_run_ms\":" << ms_since(q.t_start, q.t_end);
+        o << "}";
+    }
+    const std::string s = o.str();
+    if (buf && len > 0) {
+        const size_t n = std::min(len - 1, s.size());
+        std::memcpy(buf, s.data(), n);
+        buf[n] = 0;
+    }
+    return (int)s.size() + 1;
+}
+
+int lsum_release(lsum_req r) {
+    if (!r) return LSUM_OK;
+    Request& q = r->q;
+    {
+        std::unique_lock<std::mutex> lk(q.mu);
+        if (!q.done) {
+            lk.unlock();
+            if (lsum_cancel(r) != LSUM_OK) lsum_wait(r, -1);
+        }
+    }
+    Context& c = *q.ctx;
+    (void)hipSetDevice(c.device);
+    drop_reference(&q);
+    {
+        std::lock_guard<std::mutex> lk(c.mu);
+        c.used -= std::min(c.used, q.retained);
+    }
+    c.cv.notify_all();
+    delete r;
+    return LSUM_OK;
+}
+
+int lsum_set_option(lsum_ctx x, int key, double value) {
+    if (!x) return fail(LSUM_E_INVALID, "null ctx");
+    Context& c = x->c;
+    std::lock_guard<std::mutex> lk(c.mu);
+    switch (key) {
+        case LSUM_OPT_MAX_BATCH:
+            if (!(value >= 1 && value <= 4096)) return fail(LSUM_E_INVALID, "batch size must be in [1, 4096]");
+            c.max_batch = (int)value;
+            return LSUM_OK;
+        case LSUM_OPT_REF_CACHE_BYTES: {
+            if (!(value >= 0)) return fail(LSUM_E_INVALID, "negative cache size");
+            std::lock_guard<std::mutex> lr(c.ref_mu);
+            c.ref_cap = (size_t)value;
+            if (c.ref_cap == 0) {
+                for (auto it = c.refs.begin(); it != c.refs.end();)
+                    if (it->second->users.load() == 0) {
+                        c.ref_bytes -= it->second->bytes;
+                        it = c.refs.erase(it);
+                    } else {
+                        ++it;
+                    }
+            }
+            return LSUM_OK;
+        }
+        default:
+            return fail(LSUM_E_INVALID, "unknown option");
+    }
+}
+
+int lsum_get_profile(lsum_ctx x, char* buf, size_t len) {
+    if (!x) return fail(LSUM_E_INVALID, "null ctx");
+    Context& c = x->c;
+    std::ostringstream o;
+    o.precision(17);
+    {
+        std::lock_guard<std::mutex> lk(c.prof_mu);
+        o << "{";
+        bool first = true;
+        for (auto& kv : c.profile) {
+            o << (first ? "" : ",") << "\"" << kv.first << "\":{\"ms\":" << kv.second.ms << ",\"launches\":"
+              << kv.second.launches << ",\"bytes\":" << kv.second.bytes << ",\"flops\":" << kv.second.flops << "}";
+            first = false;
+        }
+        o << "}";
+    }
+    const std::string s = o.str();
+    if (buf && len > 0) {
+        const size_t n = std::min(len - 1, s.size());
+        std::memcpy(buf, s.data(), n);
+        buf[n] = 0;
+    }
+    return (int)s.size() + 1;
+}
+
+int lsum_reset_profile(lsum_ctx x) {
+    if (!x) return fail(LSUM_E_INVALID, "null ctx");
+    std::lock_guard<std::mutex> lk(x->c.prof_mu);
+    x->c.profile.clear();
+    return LSUM_OK;
+}
+
+// ---- stage entry points (synchronous) -----------------------------------------------------
+
+static hipStream_t pick(lsum_ctx x, void* s) { return s ? (hipStream_t)s : x->c.own_stream; }
+
+int lsum_collocate(lsum_ctx x, void* stream, int R, const double* t, const double* w, int N_ref, double h,
+                   double* G_dev, int ldg) {
+    if (!x || !t || !w || !G_dev) return fail(LSUM_E_INVALID, "null argument");
+    if (R < 1 || N_ref < 1 || ldg < 2 * N_ref - 1 || !(h > 0)) return fail(LSUM_E_INVALID, "bad sizes");
+    LSUM_HIP(hipSetDevice(x->c.device));
+    hipStream_t st = pick(x, stream);
+    std::vector<double> w13(R);
+    for (int q = 0; q < R; ++q) {
+        if (!(w[q] > 0.0) || !(t[q] >= 0.0)) return fail(LSUM_E_INVALID, "weights must be positive, nodes non-negative");
+        w13[q] = std::cbrt(w[q]);
+    }
+    DevBuf tw;
+    int rc = tw.get(x->c.pool, 2 * (size_t)R * 8);
+    if (rc) return rc;
+    LSUM_HIP(hipMemcpyAsync(tw.as<double>(), t, R * 8, hipMemcpyHostToDevice, st));
+    LSUM_HIP(hipMemcpyAsync(tw.as<double>() + R, w13.data(), R * 8, hipMemcpyHostToDevice, st));
+    launch_collocate(st, R, tw.as<double>(), tw.as<double>() + R, N_ref, h, G_dev, ldg);
+    LSUM_HIP(hipGetLastError());
+    LSUM_HIP(hipStreamSynchronize(st));
+    return LSUM_OK;
+}
+
+int lsum_shift_sum(lsum_ctx x, void* stream, int R, const double* G_dev, int ldg, int N_ref, int N_axis,
+                   int n_sites, const int32_t* sites, double* U_dev, int ldu) {
+    if (!x || !G_dev || !U_dev || (n_sites > 0 && !sites)) return fail(LSUM_E_INVALID, "null argument");
+    if (R < 1 || N_axis < 1 || N_axis > N_ref || ldg < 2 * N_ref - 1 || ldu < N_axis || n_sites < 0)
+        return fail(LSUM_E_INVALID, "bad sizes");
+    for (int k = 0; k < n_sites; ++k)
+        if (sites[k] < 0 || sites[k] >= N_axis) return fail(LSUM_E_OUT_OF_BOX, "site index outside the axis");
+    LSUM_HIP(hipSetDevice(x->c.device));
+    hipStream_t st = pick(x, stream);
+    DevBuf sd, jd;
+    int rc = sd.get(x->c.pool, std::max(1, n_sites) * 4);
+    if (rc) return rc;
+    if ((rc = jd.get(x->c.pool, sizeof(ShiftJob)))) return rc;
+    ShiftJob j{};
+    j.G = G_dev;
+    j.U = U_dev;
+    j.sites = sd.as<int32_t>();
+    j.n_sites = n_sites;
+    j.N_axis = N_axis;
+    j.ldu = ldu;
+    j.ldg = ldg;
+    j.N_ref = N_ref;
+    j.R = R;
+    // sites forming interleaved uniform combs use strided prefix sums (2 loads per comb)
+    DevBuf pb;
+    int stride = 0;
+    const int period = n_sites >= 8 ? comb_period(sites, n_sites, n_sites / 3, &stride) : 0;
+    if (period > 0) {
+        if ((rc = pb.get(x->c.pool, (size_t)R * ldg * 8))) return rc;
+        launch_prefix(st, R, G_dev, ldg, 2 * N_ref - 1, stride, pb.as<double>());
+        j.P = pb.as<double>();
+        j.period = period;
+        j.stride = stride;
+    }
+    if (n_sites > 0) LSUM_HIP(hipMemcpyAsync(sd.p, sites, n_sites * 4, hipMemcpyHostToDevice, st));
+    LSUM_HIP(hipMemcpyAsync(jd.p, &j, sizeof(j), hipMemcpyHostToDevice, st));
+    launch_shift_sum(st, jd.as<ShiftJob>(), 1, N_axis);
+    LSUM_HIP(hipGetLastError());
+    LSUM_HIP(hipStreamSynchronize(st));
+    return LSUM_OK;
+}
+
+int lsum_sample_canonical(lsum_ctx x, void* stream, int n_fac, int R, const double* U_dev, int ldu,
+                          const double* lam, const int N[3], double h, int n_pts, const double* xyz_dev,
+                          double* out_dev) {
+    if (!x || !U_dev || !lam || !N || (n_pts > 0 && (!xyz_dev || !out_dev))) return fail(LSUM_E_INVALID, "null argument");
+    if (n_fac < 1 || R < 1 || ldu < std::max(N[0], std::max(N[1], N[2])) || n_pts < 0) return fail(LSUM_E_INVALID, "bad sizes");
+    LSUM_HIP(hipSetDevice(x->c.device));
+    hipStream_t st = pick(x, stream);
+    DevBuf ld;
+    int rc = ld.get(x->c.pool, n_fac * 8);
+    if (rc) return rc;
+    LSUM_HIP(hipMemcpyAsync(ld.p, lam, n_fac * 8, hipMemcpyHostToDevice, st));
+    launch_sample_cp(st, n_fac, R, U_dev, ldu, ld.as<double>(), N[0], N[1], N[2], h, n_pts, xyz_dev, out_dev);
+    LSUM_HIP(hipGetLastError());
+    LSUM_HIP(hipStreamSynchronize(st));
+    return LSUM_OK;
+}
+
+int lsum_contract(lsum_ctx x, void* stream, int prec, int m, int n, int k, const void* A_dev, long sam, long sak,
+                  const void* B_dev, long sbk, long sbn, void* C_dev, long scm, long scn, double alpha,
+                  double beta) {
+    if (!x || !A_dev || !B_dev || !C_dev) return fail(LSUM_E_INVALID, "null argument");
+    if (m < 0 || n < 0 || k < 0 || prec < LSUM_FP64 || prec > LSUM_BF16X3) return fail(LSUM_E_INVALID, "bad sizes");
+    LSUM_HIP(hipSetDevice(x->c.device));
+    hipStream_t st = pick(x, stream);
+    GemmArgs a{};
+    a.m = m; a.n = n; a.k = k;
+    a.A = A_dev; a.sam = sam; a.sak = sak;
+    a.B = B_dev; a.sbk = sbk; a.sbn = sbn;
+    a.C = C_dev; a.scm = scm; a.scn = scn;
+    a.alpha = alpha; a.beta = beta; a.batch = 1;
+    launch_gemm(st, prec == LSUM_FP64 ? GEMM_F64 : (prec == LSUM_FP32 ? GEMM_F32 : GEMM_BF16X3), a);
+    LSUM_HIP(hipGetLastError());
+    LSUM_HIP(hipStreamSynchronize(st));
+    return LSUM_OK;
+}
+
+int lsum_jacobi_svd(lsum_ctx x, void* stream, int D, int N, double* A_dev, int lda, double tol, double irrelevant,
+                    int max_sweeps, double* sigma, int* sweeps) {
+    if (!x || !A_dev || !sigma || !sweeps) return fail(LSUM_E_INVALID, "null argument");
+    if (D < 1 || N < 1 || lda < N || !(tol > 0) || max_sweeps < 1) return fail(LSUM_E_INVALID, "bad sizes");
+    LSUM_HIP(hipSetDevice(x->c.device));
+    hipStream_t st = pick(x, stream);
+    DevBuf work;
+    const size_t wb = jacobi_work_bytes(D, N);
+    int rc = work.get(x->c.pool, wb);
+    if (rc) return rc;
+    std::vector<double> s;
+    rc = jacobi_svd(st, D, N, A_dev, lda, tol, irrelevant, max_sweeps, s, sweeps, work.as<double>(), wb);
+    std::copy(s.begin(), s.end(), sigma);
+    return rc;
+}
+
+}  // extern "C"

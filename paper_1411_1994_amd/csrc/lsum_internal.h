@@ -84,19 +84,30 @@ int make_plan(const lsum_problem& p, Plan& plan);
 // ------------------------------------------------------------------------------------------
 void launch_collocate(hipStream_t st, int R, const double* t_dev, const double* w13_dev, int N_ref,
                       double h, double* G, int ldg);
-// Shift-sum for a batch of (row block) jobs; see kernels_lattice.hip.
+// Shift-sum for a batch of (axis, block) jobs; see kernels_lattice.hip.  When the ascending
+// site list is `period` interleaved combs of uniform `stride` (c[k + period] - c[k] == stride),
+// P holds the reference rows' prefix sums along that stride and each output costs 2 * period
+// loads; otherwise (P == nullptr) the n_sites windows are summed directly.
 struct ShiftJob {
     const double* G;      // reference rows (R x ldg)
-    double* U;            // output rows (R x ldu)
-    const int32_t* sites; // device cell indices
+    const double* P;      // prefix rows along `stride` (R x ldg) or nullptr
+    double* U;            // vector-major output (R x ldu) or nullptr
+    double* UT;           // point-major output (N_axis x R) or nullptr
+    const int32_t* sites; // device cell indices, ascending
     int n_sites;
+    int period;
+    int stride;
     int N_axis;
     int ldu;
     int ldg;
     int N_ref;
     int R;
 };
-void launch_shift_sum(hipStream_t st, const ShiftJob* jobs_dev, int n_jobs, int max_N, int max_R);
+void launch_shift_sum(hipStream_t st, const ShiftJob* jobs_dev, int n_jobs, int max_N);
+// P[q, x] = sum_{m >= 0, x - m S >= 0} G[q, x - m S] for x < len
+void launch_prefix(hipStream_t st, int R, const double* G, int ldg, int len, int stride, double* P);
+// Host: the smallest period p <= max_p with c[k+p] - c[k] constant (its stride), or 0.
+int comb_period(const int32_t* c, int n, int max_p, int* stride);
 void launch_sample_cp(hipStream_t st, int n_fac, int R, const double* U, int ldu,
                       const double* lam_dev, int N0, int N1, int N2, double h, int n_pts,
                       const double* xyz, double* out);
@@ -104,6 +115,12 @@ void launch_sample_cp(hipStream_t st, int n_fac, int R, const double* U, int ldu
 void launch_sample_block(hipStream_t st, int R, const double* U0, const double* U1, const double* U2,
                          int N0, int N1, int N2, double h, double lam, int n_pts, const double* xyz,
                          double* out);
+// R x N (stride ldu) -> N x R
+void launch_transpose(hipStream_t st, int R, int N, const double* U, int ldu, double* UT);
+// Point-major canonical evaluation (one wave per point); accumulate = 0 overwrites out.
+void launch_sample_rows(hipStream_t st, int R, const double* T0, const double* T1, const double* T2, int N0,
+                        int N1, int N2, double h, double lam, int accumulate, int n_pts, const double* xyz,
+                        double* out);
 // Defect windows evaluated straight from the reference rows, added to out.
 void launch_sample_windows(hipStream_t st, int R, const double* G, int ldg, int N_ref,
                            int n_def, const int32_t* def_cells, const double* def_scale,
@@ -147,10 +164,12 @@ void launch_cp_norm2(hipStream_t st, int R, int n_groups, const int32_t* src1, c
                      const int32_t* src3, const double* scale, const double* C1, const double* C2,
                      const double* C3, int D1, int D2, int D3, double* partial, int n_partial);
 
-// one sweep-round of block Jacobi
-int jacobi_svd(hipStream_t st, int D, int N, double* A, int lda, double tol, int max_sweeps,
-               std::vector<double>& sigma, std::vector<int32_t>& order, int* sweeps_out,
-               double* work_dev, size_t work_bytes);
+// One-sided block-Jacobi SVD of the D rows of A (length N): rows are rotated in place and
+// written back sorted by descending norm (sigma).  Pairs involving a row whose norm is below
+// `irrelevant` are not rotated (such rows cannot move a certified tail).
+int jacobi_svd(hipStream_t st, int D, int N, double* A, int lda, double tol, double irrelevant,
+               int max_sweeps, std::vector<double>& sigma, int* sweeps_out, double* work_dev,
+               size_t work_bytes);
 size_t jacobi_work_bytes(int D, int N);
 
 // type conversions

@@ -1,0 +1,481 @@
+// Pipeline stages of the lattice-sum library, run by the request workers on a slot's stream:
+//   reference vectors (Sec. 2.1, 3.1) -> assembled shift-sums for a whole batch of requests in
+//   one launch (Thm thm:sumCaseE (A)) -> point-major copies of the factors -> for a reduction
+//   request: side-matrix columns, ||A|| and ||xi||, the certified truncation threshold, the
+//   Jacobi SVD, Tucker factors, projections, the core (Def. def:RHOSVD, Appendix theorem) and
+//   an optional tile (eq. Tucker_singePot) -> sampling at the request's points.
+#include "lsum_runtime.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+namespace lsum {
+
+static GemmPrec gemm_prec(int precision) {
+    return precision == LSUM_FP64 ? GEMM_F64 : (precision == LSUM_FP32 ? GEMM_F32 : GEMM_BF16X3);
+}
+
+// RHOSVD of one request whose canonical factors are computed (q->U, q->ref ready on st).
+static int run_tucker(Request* q, hipStream_t st, StageTimer& tm) {
+    Context* c = q->ctx;
+    Plan& P = q->plan;
+    int rc;
+    const double* G = q->ref->G.as<double>();
+    // (4) side matrices per mode: lattice sources and defect windows (unnormalised)
+    DevBuf cols[3], W[3], nrm[3], C[3], aux;
+    std::vector<double> nrm_h[3];
+    const GemmPrec prec = gemm_prec(P.precision);
+    tm.begin("columns", (double)(P.D[0] * (size_t)P.N[0] + P.D[1] * (size_t)P.N[1] + P.D[2] * (size_t)P.N[2]) * 8);
+    for (int l = 0; l < 3; ++l) {
+        const int D = P.D[l], N = P.N[l];
+        if ((rc = cols[l].get(c->pool, (size_t)D * N * 8))) return rc;
+        if ((rc = nrm[l].get(c->pool, (size_t)D * 8))) return rc;
+        std::vector<const double*> latp(P.n_lat[l]);
+        for (int s = 0; s < P.n_lat[l]; ++s) latp[s] = q->U[P.lat_block[l][s]].as<double>() + q->U_axis_off[l];
+        DevBuf lp, wc;
+        if ((rc = lp.get(c->pool, std::max<size_t>(1, latp.size()) * sizeof(void*)))) return rc;
+        if ((rc = wc.get(c->pool, std::max<size_t>(1, P.win_cell[l].size()) * 4))) return rc;
+        LSUM_HIP(hipMemcpyAsync(lp.p, latp.data(), latp.size() * sizeof(void*), hipMemcpyHostToDevice, st));
+        if (!P.win_cell[l].empty())
+            LSUM_HIP(hipMemcpyAsync(wc.p, P.win_cell[l].data(), P.win_cell[l].size() * 4, hipMemcpyHostToDevice, st));
+        launch_gather_columns(st, P.R, P.n_lat[l], lp.as<const double*>(), P.N[l], P.n_win[l],
+                              wc.as<int32_t>(), G, P.ldg, P.N_ref, N, cols[l].as<double>(), N);
+        launch_row_norms(st, D, N, cols[l].as<double>(), N, nrm[l].as<double>());
+        nrm_h[l].resize(D);
+        LSUM_HIP(hipMemcpyAsync(nrm_h[l].data(), nrm[l].p, D * 8, hipMemcpyDeviceToHost, st));
+        LSUM_HIP(hipStreamSynchronize(st));   // lp, wc released after the kernels ran
+    }
+    tm.end();
+    for (int l = 0; l < 3; ++l)
+        for (double v : nrm_h[l])
+            if (!(v > 0.0)) return fail(LSUM_E_INVALID, "a side-matrix column vanishes on the grid");
+
+    // (5) ||A|| from the column Grams, ||xi|| from the norms, truncation (host FP64)
+    tm.begin("norm", 0, 2.0 * ((double)P.D[0] * P.D[0] * P.N[0] + (double)P.D[1] * P.D[1] * P.N[1] + (double)P.D[2] * P.D[2] * P.N[2]));
+    for (int l = 0; l < 3; ++l) {
+        const int D = P.D[l], N = P.N[l];
+        if ((rc = C[l].get(c->pool, (size_t)D * D * 8))) return rc;
+        GemmArgs a{};
+        a.m = D; a.n = D; a.k = N;
+        a.A = cols[l].p; a.sam = N; a.sak = 1;
+        a.B = cols[l].p; a.sbk = 1; a.sbn = N;
+        a.C = C[l].p; a.scm = D; a.scn = 1;
+        a.alpha = 1.0; a.beta = 0.0; a.batch = 1;
+        launch_gemm(st, GEMM_F64, a);
+    }
+    DevBuf src_d, scale_d, part_d;
+    const int ng = P.n_groups;
+    std::vector<int32_t> srcs(3 * (size_t)ng);
+    for (int l = 0; l < 3; ++l) std::copy(P.g_src[l].begin(), P.g_src[l].end(), srcs.begin() + (size_t)l * ng);
+    if ((rc = src_d.get(c->pool, srcs.size() * 4))) return rc;
+    if ((rc = scale_d.get(c->pool, ng * 8))) return rc;
+    if ((rc = part_d.get(c->pool, ng * 8))) return rc;
+    LSUM_HIP(hipMemcpyAsync(src_d.p, srcs.data(), srcs.size() * 4, hipMemcpyHostToDevice, st));
+    LSUM_HIP(hipMemcpyAsync(scale_d.p, P.g_scale.data(), ng * 8, hipMemcpyHostToDevice, st));
+    const int32_t* s1 = src_d.as<int32_t>();
+    const int32_t* s2 = s1 + ng;
+    const int32_t* s3 = s2 + ng;
+    launch_cp_norm2(st, P.R, ng, s1, s2, s3, scale_d.as<double>(), C[0].as<double>(), C[1].as<double>(),
+                    C[2].as<double>(), P.D[0], P.D[1], P.D[2], part_d.as<double>(), ng);
+    std::vector<double> part(ng);
+    LSUM_HIP(hipMemcpyAsync(part.data(), part_d.p, ng * 8, hipMemcpyDeviceToHost, st));
+    LSUM_HIP(hipStreamSynchronize(st));
+    tm.end();
+    for (int l = 0; l < 3; ++l) C[l].reset();
+    double nA2 = 0.0;
+    for (double v : part) nA2 += v;
+    q->norm_A = std::sqrt(std::max(nA2, 0.0));
+    double nxi2 = 0.0;
+    for (int g = 0; g < ng; ++g)
+        for (int k = 0; k < P.R; ++k) {
+            double xi = P.g_scale[g];
+            for (int l = 0; l < 3; ++l) xi *= nrm_h[l][(size_t)P.g_src[l][g] * P.R + k];
+            nxi2 += xi * xi;
+        }
+    q->norm_xi = std::sqrt(nxi2);
+    const double thr = P.eps * q->norm_A / (3.0 * q->norm_xi);
+    // columns with norm below 1% of thr / sqrt(D) cannot change whether a tail passes thr
+    const double irrelevant = 1e-2 * thr / std::sqrt((double)std::max(P.D[0], std::max(P.D[1], P.D[2])));
+    // weighted, normalised side matrices: row j = col_j / |col_j| * sqrt(multiplicity)
+    tm.begin("svd");
+    for (int l = 0; l < 3; ++l) {
+        const int D = P.D[l], N = P.N[l];
+        std::vector<double> sc(D);
+        for (int j = 0; j < D; ++j) sc[j] = std::sqrt((double)P.src_mult[l][j / P.R]) / nrm_h[l][j];
+        DevBuf scd;
+        if ((rc = scd.get(c->pool, D * 8))) return rc;
+        if ((rc = W[l].get(c->pool, (size_t)D * N * 8))) return rc;
+        LSUM_HIP(hipMemcpyAsync(scd.p, sc.data(), D * 8, hipMemcpyHostToDevice, st));
+        launch_scale_rows(st, D, N, cols[l].as<double>(), N, scd.as<double>(), W[l].as<double>(), N);
+        DevBuf work;
+        size_t wb = jacobi_work_bytes(D, N);
+        if ((rc = work.get(c->pool, wb))) return rc;
+        rc = jacobi_svd(st, D, N, W[l].as<double>(), N, 1e-12, irrelevant, 40, q->sigma[l], &q->sweeps[l],
+                        work.as<double>(), wb);
+        if (rc) return rc;
+    }
+    tm.end();
+
+    q->bound = 0.0;
+    for (int l = 0; l < 3; ++l) {
+        const auto& sg = q->sigma[l];
+        const int D = (int)sg.size();
+        std::vector<double> tail(D + 1, 0.0);
+        for (int k = D - 1; k >= 0; --k) tail[k] = tail[k + 1] + sg[k] * sg[k];
+        int r = D;
+        for (int k = 1; k <= D; ++k)
+            if (std::sqrt(tail[k]) <= thr) { r = k; break; }
+        r = std::min(r, P.N[l]);
+        q->r[l] = r;
+        q->tails[l] = std::sqrt(tail[r]);
+        q->bound += q->tails[l];
+    }
+    q->bound *= q->norm_xi;
+
+    // Tucker factors Z_l = leading rotated columns / sigma
+    for (int l = 0; l < 3; ++l) {
+        const int r = q->r[l], N = P.N[l];
+        std::vector<double> inv(r);
+        std::vector<int32_t> ord(r);
+        for (int a = 0; a < r; ++a) { inv[a] = 1.0 / q->sigma[l][a]; ord[a] = a; }
+        DevBuf od, iv;
+        if ((rc = od.get(c->pool, r * 4))) return rc;
+        if ((rc = iv.get(c->pool, r * 8))) return rc;
+        if ((rc = q->Z[l].get(c->pool, (size_t)r * N * 8))) return rc;
+        LSUM_HIP(hipMemcpyAsync(od.p, ord.data(), r * 4, hipMemcpyHostToDevice, st));
+        LSUM_HIP(hipMemcpyAsync(iv.p, inv.data(), r * 8, hipMemcpyHostToDevice, st));
+        launch_gather_scale_rows(st, r, N, W[l].as<double>(), N, od.as<int32_t>(), iv.as<double>(),
+                                 q->Z[l].as<double>(), N);
+        LSUM_HIP(hipStreamSynchronize(st));
+        W[l].reset();
+    }
+
+    // (6) projections Y_l = Z_l cols_l^T (r_l x D_l) in the problem's precision
+    const size_t es = (prec == GEMM_F64) ? 8 : 4;
+    DevBuf Y[3];
+    tm.begin("projection", 0, 2.0 * ((double)q->r[0] * P.N[0] * P.D[0] + (double)q->r[1] * P.N[1] * P.D[1] + (double)q->r[2] * P.N[2] * P.D[2]));
+    for (int l = 0; l < 3; ++l) {
+        const int r = q->r[l], D = P.D[l], N = P.N[l];
+        if ((rc = Y[l].get(c->pool, (size_t)r * D * es))) return rc;
+        const void* Zp = q->Z[l].p;
+        const void* Cp = cols[l].p;
+        DevBuf Zf, Cf;
+        if (prec != GEMM_F64) {
+            if ((rc = Zf.get(c->pool, (size_t)r * N * 4))) return rc;
+            if ((rc = Cf.get(c->pool, (size_t)D * N * 4))) return rc;
+            launch_f64_to_f32(st, (long)r * N, q->Z[l].as<double>(), Zf.as<float>());
+            launch_f64_to_f32(st, (long)D * N, cols[l].as<double>(), Cf.as<float>());
+            Zp = Zf.p;
+            Cp = Cf.p;
+        }
+        GemmArgs a{};
+        a.m = r; a.n = D; a.k = N;
+        a.A = Zp; a.sam = N; a.sak = 1;
+        a.B = Cp; a.sbk = 1; a.sbn = N;
+        a.C = Y[l].p; a.scm = D; a.scn = 1;
+        a.alpha = 1.0; a.beta = 0.0; a.batch = 1;
+        launch_gemm(st, prec, a);
+        LSUM_HIP(hipStreamSynchronize(st));
+    }
+    tm.end();
+    for (int l = 0; l < 3; ++l) cols[l].reset();
+
+    // (7) core mu = sum_nu xi_nu y1 (x) y2 (x) y3 (eq. C-core), unnormalised columns: xi = scale
+    tm.begin("core", 0, 2.0 * (double)q->r[0] * q->r[1] * q->r[2] * (double)ng * P.R);
+    {
+        const long plane = (long)q->r[0] * q->r[1] * q->r[2];
+        if ((rc = q->core.get(c->pool, (size_t)plane * es))) return rc;
+        CoreArgs ca{};
+        ca.r1 = q->r[0]; ca.r2 = q->r[1]; ca.r3 = q->r[2]; ca.R = P.R; ca.n_groups = ng;
+        ca.Y1 = Y[0].p; ca.Y2 = Y[1].p; ca.Y3 = Y[2].p;
+        ca.ldy1 = P.D[0]; ca.ldy2 = P.D[1]; ca.ldy3 = P.D[2];
+        ca.src1 = s1; ca.src2 = s2; ca.src3 = s3;
+        ca.scale = scale_d.as<double>();
+        ca.core = q->core.p;
+        const long tiles = (long)((ca.r3 + 63) / 64) * ((ca.r1 + 7) / 8) * ((ca.r2 + 7) / 8);
+        const long K = (long)ng * P.R;
+        int ks = 1;
+        while (tiles * ks < 1024 && ks < 64 && K / (ks * 2) >= 256) ks *= 2;
+        DevBuf work;
+        if (ks > 1 && (rc = work.get(c->pool, (size_t)plane * ks * es))) return rc;
+        launch_core(st, prec, ca, ks, work.p);
+        LSUM_HIP(hipGetLastError());
+        LSUM_HIP(hipStreamSynchronize(st));
+        q->bytes["core"] = (double)plane * es;
+    }
+    tm.end();
+
+    // (8) optional tile: V = mu x_3 Z3 x_2 Z2 x_1 Z1 restricted to [lo, lo+T)
+    if (P.has_tile()) {
+        tm.begin("tile", (double)P.tile_T[0] * P.tile_T[1] * P.tile_T[2] * (P.precision == LSUM_FP64 ? 8 : 4), 2.0 * ((double)q->r[0] * q->r[1] * q->r[2] * P.tile_T[2] + (double)q->r[0] * q->r[1] * P.tile_T[1] * P.tile_T[2] + (double)q->r[0] * P.tile_T[0] * P.tile_T[1] * P.tile_T[2]));
+        const int r1 = q->r[0], r2 = q->r[1], r3 = q->r[2];
+        const int T1 = P.tile_T[0], T2 = P.tile_T[1], T3 = P.tile_T[2];
+        const void* Zp[3];
+        DevBuf Zf[3];
+        for (int l = 0; l < 3; ++l) {
+            Zp[l] = q->Z[l].p;
+            if (prec != GEMM_F64) {
+                if ((rc = Zf[l].get(c->pool, (size_t)q->r[l] * P.N[l] * 4))) return rc;
+                launch_f64_to_f32(st, (long)q->r[l] * P.N[l], q->Z[l].as<double>(), Zf[l].as<float>());
+                Zp[l] = Zf[l].p;
+            }
+        }
+        DevBuf X1, X2;
+        if ((rc = X1.get(c->pool, (size_t)r1 * r2 * T3 * es))) return rc;
+        if ((rc = X2.get(c->pool, (size_t)r1 * T2 * T3 * es))) return rc;
+        if ((rc = q->tile.get(c->pool, (size_t)T1 * T2 * T3 * es))) return rc;
+        const long e = (long)es;
+        GemmArgs a{};
+        // X1[(a,b), n] = sum_c mu[(a,b), c] Z3[c, lo3 + n]
+        a.m = r1 * r2; a.n = T3; a.k = r3;
+        a.A = q->core.p; a.sam = r3; a.sak = 1;
+        a.B = (const char*)Zp[2] + (long)P.tile_lo[2] * e; a.sbk = P.N[2]; a.sbn = 1;
+        a.C = X1.p; a.scm = T3; a.scn = 1;
+        a.alpha = 1.0; a.beta = 0.0; a.batch = 1;
+        launch_gemm(st, prec, a);
+        // X2[a][m, n] = sum_b Z2[b, lo2 + m] X1[(a,b), n]
+        a = GemmArgs{};
+        a.m = T2; a.n = T3; a.k = r2;
+        a.A = (const char*)Zp[1] + (long)P.tile_lo[1] * e; a.sam = 1; a.sak = P.N[1];
+        a.B = X1.p; a.sbk = T3; a.sbn = 1;
+        a.C = X2.p; a.scm = T3; a.scn = 1;
+        a.alpha = 1.0; a.beta = 0.0; a.batch = r1; a.bA = 0; a.bB = (long)r2 * T3; a.bC = (long)T2 * T3;
+        launch_gemm(st, prec, a);
+        // V[m, (n2,n3)] = sum_a Z1[a, lo1 + m] X2[a, (n2,n3)]
+        a = GemmArgs{};
+        a.m = T1; a.n = T2 * T3; a.k = r1;
+        a.A = (const char*)Zp[0] + (long)P.tile_lo[0] * e; a.sam = 1; a.sak = P.N[0];
+        a.B = X2.p; a.sbk = (long)T2 * T3; a.sbn = 1;
+        a.C = q->tile.p; a.scm = (long)T2 * T3; a.scn = 1;
+        a.alpha = 1.0; a.beta = 0.0; a.batch = 1;
+        launch_gemm(st, prec, a);
+        LSUM_HIP(hipGetLastError());
+        LSUM_HIP(hipStreamSynchronize(st));
+        tm.end();
+        q->bytes["tile"] = (double)T1 * T2 * T3 * es;
+        }
+    LSUM_HIP(hipStreamSynchronize(st));
+    return LSUM_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// sampling: canonical factors (point-major rows, plus defect windows from the reference), or
+// the Tucker tensor (mode-3 contraction as a GEMM per chunk of points, then modes 1 and 2)
+// ------------------------------------------------------------------------------------------
+int sample_points(Request* q, hipStream_t st, int n, const double* xyz_d, double* out_d) {
+    Context* c = q->ctx;
+    const Plan& P = q->plan;
+    int rc;
+    if (n <= 0) return LSUM_OK;
+    if (!P.tucker()) {
+        for (int b = 0; b < (int)P.blocks.size(); ++b)
+            launch_sample_rows(st, P.R, q->UT[b].as<double>(), q->UT[b].as<double>() + q->U_axis_off[1],
+                               q->UT[b].as<double>() + q->U_axis_off[2], P.N[0], P.N[1], P.N[2], P.h,
+                               P.blocks[b].charge, b > 0 ? 1 : 0, n, xyz_d, out_d);
+        if (!P.defects.empty())
+            launch_sample_windows(st, P.R, q->ref->G.as<double>(), P.ldg, P.N_ref, (int)P.defects.size(),
+                                  q->def_cells.as<int32_t>(), q->def_scale.as<double>(), P.N[0], P.N[1], P.N[2],
+                                  P.h, n, xyz_d, out_d);
+        LSUM_HIP(hipGetLastError());
+        return LSUM_OK;
+    }
+    const int r1 = q->r[0], r2 = q->r[1], r3 = q->r[2];
+    const size_t ncore = (size_t)r1 * r2 * r3;
+    DevBuf core64, idx, W, Z3s, i3c;
+    const double* core_d = q->core.as<double>();
+    if (P.precision != LSUM_FP64) {
+        if ((rc = core64.get(c->pool, ncore * 8))) return rc;
+        launch_f32_to_f64(st, (long)ncore, q->core.as<float>(), core64.as<double>());
+        core_d = core64.as<double>();
+    }
+    if ((rc = idx.get(c->pool, (size_t)n * 12))) return rc;
+    launch_snap_points(st, n, xyz_d, P.N[0], P.N[1], P.N[2], P.h, idx.as<int32_t>());
+    size_t per = std::max<size_t>(1, (size_t)r1 * r2);
+    int chunk = (int)std::max<size_t>(1, std::min<size_t>((size_t)n, ((size_t)1 << 28) / per));
+    chunk = std::min(chunk, 4096);
+    if ((rc = W.get(c->pool, per * chunk * 8))) return rc;
+    if ((rc = Z3s.get(c->pool, (size_t)r3 * chunk * 8))) return rc;
+    if ((rc = i3c.get(c->pool, (size_t)chunk * 4))) return rc;
+    std::vector<int32_t> idx_h((size_t)3 * n);
+    LSUM_HIP(hipMemcpyAsync(idx_h.data(), idx.p, (size_t)n * 12, hipMemcpyDeviceToHost, st));
+    LSUM_HIP(hipStreamSynchronize(st));
+    std::vector<int32_t> i3(chunk);
+    for (int p0 = 0; p0 < n; p0 += chunk) {
+        const int Pn = std::min(chunk, n - p0);
+        for (int p = 0; p < Pn; ++p) i3[p] = std::max(0, idx_h[(size_t)2 * n + p0 + p]);
+        LSUM_HIP(hipMemcpyAsync(i3c.p, i3.data(), Pn * 4, hipMemcpyHostToDevice, st));
+        launch_select_cols(st, r3, Pn, q->Z[2].p, P.N[2], i3c.as<int32_t>(), Z3s.p, 8);
+        GemmArgs a{};
+        a.m = r1 * r2; a.n = Pn; a.k = r3;
+        a.A = core_d; a.sam = r3; a.sak = 1;
+        a.B = Z3s.p; a.sbk = Pn; a.sbn = 1;
+        a.C = W.p; a.scm = Pn; a.scn = 1;
+        a.alpha = 1.0; a.beta = 0.0; a.batch = 1;
+        launch_gemm(st, GEMM_F64, a);
+        launch_tucker_finish(st, r1, r2, Pn, W.as<double>(), q->Z[0].as<double>(), P.N[0], q->Z[1].as<double>(),
+                             P.N[1], idx.as<int32_t>() + p0, idx.as<int32_t>() + n + p0, out_d + p0);
+        LSUM_HIP(hipStreamSynchronize(st));   // i3c is rewritten by the next chunk
+    }
+    bool any_out = false;
+    for (int p = 0; p < n; ++p) any_out |= idx_h[(size_t)2 * n + p] < 0;
+    if (any_out) {
+        std::vector<double> o(n);
+        LSUM_HIP(hipMemcpyAsync(o.data(), out_d, (size_t)n * 8, hipMemcpyDeviceToHost, st));
+        LSUM_HIP(hipStreamSynchronize(st));
+        for (int p = 0; p < n; ++p)
+            if (idx_h[(size_t)2 * n + p] < 0) o[p] = std::nan("");
+        LSUM_HIP(hipMemcpyAsync(out_d, o.data(), (size_t)n * 8, hipMemcpyHostToDevice, st));
+    }
+    LSUM_HIP(hipGetLastError());
+    return LSUM_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// a batch of requests (several canonical ones, or one reduction request)
+// ------------------------------------------------------------------------------------------
+int run_batch(std::vector<Request*>& reqs, hipStream_t st) {
+    Context* c = reqs[0]->ctx;
+    StageTimer tm(st);
+    int rc;
+    // (1)-(2) quadrature is in the plan; reference vectors from the cache
+    for (auto* q : reqs)
+        if ((rc = get_reference(c, q->plan, st, q->ref))) return rc;
+
+    // (3) assembled shift-sums of every block and axis of every request: one launch.  Canonical
+    // requests keep point-major factors (for sampling), reduction requests vector-major ones
+    // (side-matrix columns).
+    std::vector<int32_t> sites_h;
+    std::vector<ShiftJob> jobs;
+    std::vector<size_t> site_off;
+    int maxN = 0;
+    double out_bytes = 0, loads = 0;
+    std::vector<const RefEntry*> distinct;
+    for (auto* q : reqs) {
+        Plan& P = q->plan;
+        const int nb = (int)P.blocks.size();
+        const size_t sumN = (size_t)P.N[0] + P.N[1] + P.N[2];
+        const bool vector_major = P.tucker();
+        q->U_axis_off[0] = 0;
+        q->U_axis_off[1] = (size_t)P.R * P.N[0];
+        q->U_axis_off[2] = (size_t)P.R * (P.N[0] + P.N[1]);
+        q->U.resize(nb);
+        q->UT.resize(nb);
+        for (int b = 0; b < nb; ++b) {
+            DevBuf& out = vector_major ? q->U[b] : q->UT[b];
+            if ((rc = out.get(c->pool, (size_t)P.R * sumN * 8))) return rc;
+            for (int l = 0; l < 3; ++l) {
+                const auto& sites = P.offs[l][b];
+                const int n = (int)sites.size();
+                site_off.push_back(sites_h.size());
+                sites_h.insert(sites_h.end(), sites.begin(), sites.end());
+                ShiftJob j{};
+                j.G = q->ref->G.as<double>();
+                j.U = vector_major ? q->U[b].as<double>() + q->U_axis_off[l] : nullptr;
+                j.UT = vector_major ? nullptr : q->UT[b].as<double>() + q->U_axis_off[l];
+                j.n_sites = n;
+                j.N_axis = P.N[l];
+                j.ldu = P.N[l];
+                j.ldg = P.ldg;
+                j.N_ref = P.N_ref;
+                j.R = P.R;
+                int stride = 0;
+                const int period = n >= 8 ? comb_period(sites.data(), n, n / 3, &stride) : 0;
+                if (period > 0) {
+                    const double* pr = nullptr;
+                    if ((rc = get_prefix(c, *q->ref, stride, st, &pr))) return rc;
+                    j.P = pr;
+                    j.period = period;
+                    j.stride = stride;
+                }
+                jobs.push_back(j);
+                maxN = std::max(maxN, P.N[l]);
+                loads += (double)P.R * P.N[l] * (period > 0 ? 2 * period : n);
+            }
+            out_bytes += (double)P.R * sumN * 8;
+        }
+        if (std::find(distinct.begin(), distinct.end(), q->ref.get()) == distinct.end()) distinct.push_back(q->ref.get());
+        q->bytes["canonical"] = (double)nb * P.R * sumN * 8;
+    }
+    double ref_bytes = 0;
+    for (auto* e : distinct) ref_bytes += (double)e->R * (2 * e->N_ref - 1) * 8;
+    DevBuf sites_d, jobs_d;
+    if ((rc = sites_d.get(c->pool, std::max<size_t>(1, sites_h.size()) * 4))) return rc;
+    if ((rc = jobs_d.get(c->pool, jobs.size() * sizeof(ShiftJob)))) return rc;
+    for (size_t k = 0; k < jobs.size(); ++k) jobs[k].sites = sites_d.as<int32_t>() + site_off[k];
+    LSUM_HIP(hipMemcpyAsync(sites_d.p, sites_h.data(), sites_h.size() * 4, hipMemcpyHostToDevice, st));
+    LSUM_HIP(hipMemcpyAsync(jobs_d.p, jobs.data(), jobs.size() * sizeof(ShiftJob), hipMemcpyHostToDevice, st));
+    // algorithmic traffic: every distinct reference read once, every factor written once
+    tm.begin("shift_sum", ref_bytes + out_bytes, loads);
+    launch_shift_sum(st, jobs_d.as<ShiftJob>(), (int)jobs.size(), maxN);
+    tm.end();
+    LSUM_HIP(hipGetLastError());
+
+    // defect tables (canonical sampling evaluates defect windows from the reference rows)
+    for (auto* q : reqs) {
+        Plan& P = q->plan;
+        const int nd = (int)P.defects.size();
+        if (nd == 0) continue;
+        std::vector<int32_t> cells(3 * (size_t)nd);
+        std::vector<double> sc(nd);
+        for (int s = 0; s < nd; ++s) {
+            const auto& d = P.defects[s];
+            for (int l = 0; l < 3; ++l) cells[3 * s + l] = P.offs[l][d.block][d.site[l]];
+            sc[s] = d.dZ;
+        }
+        if ((rc = q->def_cells.get(c->pool, cells.size() * 4))) return rc;
+        if ((rc = q->def_scale.get(c->pool, nd * 8))) return rc;
+        LSUM_HIP(hipMemcpyAsync(q->def_cells.p, cells.data(), cells.size() * 4, hipMemcpyHostToDevice, st));
+        LSUM_HIP(hipMemcpyAsync(q->def_scale.p, sc.data(), nd * 8, hipMemcpyHostToDevice, st));
+    }
+
+    // (4)-(8) reduction requests
+    for (auto* q : reqs) {
+        if (!q->plan.tucker()) continue;
+        rc = run_tucker(q, st, tm);
+        if (rc) {
+            (void)hipStreamSynchronize(st);
+            (void)hipGetLastError();
+            q->status.store(rc);
+        }
+    }
+
+    // completion sampling at the request's points
+    for (auto* q : reqs) {
+        if (q->n_points <= 0 || q->status.load() < 0) continue;
+        const int n = q->n_points;
+        DevBuf xd, od;
+        const double* xyz_d = q->points;
+        double* out_d = q->values;
+        if (!q->points_on_device) {
+            if ((rc = xd.get(c->pool, (size_t)n * 24)) || (rc = od.get(c->pool, (size_t)n * 8))) {
+                q->status.store(rc);
+                continue;
+            }
+            LSUM_HIP(hipMemcpyAsync(xd.p, q->points, (size_t)n * 24, hipMemcpyHostToDevice, st));
+            xyz_d = xd.as<double>();
+            out_d = od.as<double>();
+        }
+        const Plan& P = q->plan;
+        double fb = 0;
+        for (int b = 0; b < (int)q->U.size(); ++b) fb += (double)P.R * (P.N[0] + P.N[1] + P.N[2]) * 8;
+        tm.begin("sample", (double)n * 32 + (P.tucker() ? 0.0 : fb), 0);
+        rc = sample_points(q, st, n, xyz_d, out_d);
+        tm.end();
+        if (rc) {
+            q->status.store(rc);
+            continue;
+        }
+        if (!q->points_on_device) {
+            LSUM_HIP(hipMemcpyAsync(q->values, out_d, (size_t)n * 8, hipMemcpyDeviceToHost, st));
+            LSUM_HIP(hipStreamSynchronize(st));
+        }
+    }
+    LSUM_HIP(hipStreamSynchronize(st));
+    std::map<std::string, double> t;
+    tm.collect(t, c);
+    for (auto* q : reqs) q->t_ms = t;
+    return LSUM_OK;
+}
+
+}  // namespace lsum

@@ -1,0 +1,212 @@
+// Runtime structures of the lattice-sum library: the device buffer pool, the reference-vector
+// cache, the stage profile, contexts and requests.  Internal (see include/lsum.h for the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <tuple>
+#include <vector>
+
+#include "lsum_internal.h"
+
+namespace lsum {
+
+using Clock = std::chrono::steady_clock;
+
+inline double ms_since(Clock::time_point a, Clock::time_point b) {
+    return std::chrono::duration<double, std::milli>(b - a).count();
+}
+
+// ------------------------------------------------------------------------------------------
+// device buffer pool: size-bucketed free lists; buffers come back only after the owning stream
+// has been synchronised, so reuse on another stream is safe
+// ------------------------------------------------------------------------------------------
+class DevPool {
+  public:
+    DevPool() = default;
+    ~DevPool();
+    static size_t round(size_t n);
+    int alloc(size_t n, void** p, size_t* got);
+    void release(void* p, size_t n);
+    void trim();
+
+  private:
+    void trim_locked();
+    std::mutex mu_;
+    std::multimap<size_t, void*> free_;
+    size_t cached_ = 0;
+    size_t cap_ = (size_t)24 << 30;
+};
+
+struct DevBuf {
+    DevPool* pool = nullptr;
+    void* p = nullptr;
+    size_t n = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    DevBuf(DevBuf&& o) noexcept { *this = std::move(o); }
+    DevBuf& operator=(DevBuf&& o) noexcept {
+        if (this != &o) {
+            reset();
+            pool = o.pool;
+            p = o.p;
+            n = o.n;
+            o.p = nullptr;
+            o.n = 0;
+        }
+        return *this;
+    }
+    ~DevBuf() { reset(); }
+    void reset() {
+        if (p && pool) pool->release(p, n);
+        p = nullptr;
+        n = 0;
+    }
+    int get(DevPool* pl, size_t bytes) {
+        reset();
+        pool = pl;
+        return pl->alloc(bytes, &p, &n);
+    }
+    template <typename T> T* as() const { return (T*)p; }
+};
+
+// reference vectors of one (kernel, quadrature, grid): "precomputed once, stored for multiple
+// use" (Sec. 2.1)
+struct PrefixRows {
+    DevBuf P;                        // strided prefix sums of the reference rows
+    hipEvent_t ready = nullptr;
+    ~PrefixRows() {
+        if (ready) (void)hipEventDestroy(ready);
+    }
+};
+
+struct RefEntry {
+    DevBuf G;
+    int R = 0, ldg = 0, N_ref = 0;
+    hipEvent_t ready = nullptr;
+    std::atomic<int> users{0};
+    size_t bytes = 0;
+    uint64_t last_use = 0;
+    bool cached = true;
+    std::mutex prefix_mu;
+    std::map<int, std::unique_ptr<PrefixRows>> prefix;   // by stride
+    ~RefEntry() {
+        prefix.clear();
+        if (ready) (void)hipEventDestroy(ready);
+    }
+};
+using RefKey = std::tuple<int, double, int, double, double, double, int>;
+
+// event-timed GPU duration and algorithmic bytes/flops of each stage, summed over launches
+struct StageStat {
+    double ms = 0, bytes = 0, flops = 0;
+    long launches = 0;
+};
+
+struct Request;
+
+struct Context {
+    int device = 0;
+    size_t budget = 0;
+    size_t used = 0;                 // bytes reserved by admitted requests and retained results
+    int n_slots = 0;
+    int max_batch = 32;              // canonical requests fused into one batch
+    std::vector<hipStream_t> streams;
+    std::vector<std::thread> workers;
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<Request*> queue;
+    size_t max_queue = 1 << 16;
+    bool stopping = false;
+    DevPool* pool = nullptr;
+    hipStream_t own_stream = nullptr;
+    // reference cache
+    std::mutex ref_mu;
+    std::map<RefKey, std::shared_ptr<RefEntry>> refs;
+    size_t ref_bytes = 0, ref_cap = (size_t)4 << 30;
+    uint64_t ref_clock = 0;
+    // stage profile
+    std::mutex prof_mu;
+    std::map<std::string, StageStat> profile;
+    ~Context();
+};
+
+// a request and its results
+struct Request {
+    std::shared_ptr<Context> ctx_ref;  // keeps the pool and streams alive until release
+    Context* ctx = nullptr;
+    Plan plan;
+    std::atomic<int> status{1};
+    std::mutex mu;
+    std::condition_variable cv;
+    bool done = false;
+    bool started = false;
+    size_t reserved = 0, retained = 0;
+    Clock::time_point t_submit, t_start, t_end;
+    int batch_size = 1;
+    std::shared_ptr<RefEntry> ref;
+    // completion sampling (caller-owned memory)
+    int n_points = 0;
+    const double* points = nullptr;
+    double* values = nullptr;
+    int points_on_device = 0;
+    // canonical factors: per block, 3 axes of R x N[l] (vector-major) and N[l] x R (point-major)
+    std::vector<DevBuf> U, UT;
+    size_t U_axis_off[3]{};
+    DevBuf def_cells, def_scale;       // defects for sampling (n_def x 3, n_def)
+    // Tucker
+    int r[3]{};
+    std::vector<double> sigma[3];
+    int sweeps[3]{};
+    double tails[3]{};
+    double norm_A = 0, norm_xi = 0, bound = 0;
+    DevBuf Z[3];                       // r_l x N_l FP64
+    DevBuf core;                       // r1 r2 r3, FP64 or FP32 (precision)
+    DevBuf tile;
+    std::map<std::string, double> t_ms;
+    std::map<std::string, double> bytes;
+};
+
+// stage timer on a stream; collects into requests and the context profile
+class StageTimer {
+  public:
+    explicit StageTimer(hipStream_t s) : st_(s) {}
+    ~StageTimer();
+    void begin(const std::string& name, double bytes = 0, double flops = 0);
+    void end();
+    // elapsed times (call after the stream has been synchronised)
+    void collect(std::map<std::string, double>& out, Context* c);
+
+  private:
+    struct Ev {
+        std::string name;
+        hipEvent_t a, b;
+        double bytes, flops;
+    };
+    hipStream_t st_;
+    std::vector<Ev> ev_;
+};
+
+void finish(Request* q, int status);
+int get_reference(Context* c, const Plan& P, hipStream_t st, std::shared_ptr<RefEntry>& out);
+// prefix rows of a reference along `stride`, computed on st on first use; ready on st on return
+int get_prefix(Context* c, RefEntry& e, int stride, hipStream_t st, const double** out);
+void drop_reference(Request* q);
+size_t retained_bytes(const Request* q);
+void worker(Context* c, int slot);
+
+// pipeline stages (lsum_pipeline.cpp)
+int run_batch(std::vector<Request*>& reqs, hipStream_t st);
+int sample_points(Request* q, hipStream_t st, int n, const double* xyz_dev, double* out_dev);
+
+}  // namespace lsum

@@ -1,0 +1,120 @@
+"""Serving behaviour on the GPU: continuous batching of canonical requests, sampling as part of
+a request, the reference cache switch, the stage profile, cancellation and admission."""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from gpu_util import dev, empty, host, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def mixed_problems(n, seed=5):
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        L = tuple(int(x) for x in rng.integers(2, 9, 3))
+        kind = int(rng.integers(0, 3))
+        param = (0.0, 0.5, 1.0)[kind]
+        N = tuple(int(2 * rng.integers(30, 70) + 1) for _ in range(3))
+        h = float(rng.uniform(0.15, 0.3))
+        blk = W.Block(L, (1.0, 1.0, 1.0), (0.0, 0.0, 0.0))
+        nd = int(rng.integers(0, 4))
+        defects = W.draw_defects(rng, [blk], nd // 2, nd - nd // 2)
+        out.append(W.Problem(f"m{i}", kind, param, 24, N, h, [blk], defects))
+    return out
+
+
+def test_batched_results_equal_alone():
+    require_gpu()
+    import torch
+    import paper_1411_1994_amd as L
+    probs = mixed_problems(24)
+    rng = np.random.default_rng(1)
+    pts = [rng.uniform(-np.array(W.half_widths(p)), np.array(W.half_widths(p)), size=(257, 3)) for p in probs]
+    alone = []
+    with L.Context(0, n_slots=1) as c1:
+        c1.set_option(L.OPT_MAX_BATCH, 1)
+        for p, x in zip(probs, pts):
+            r = c1.submit(p, points=x)
+            assert r.wait() == 0
+            assert r.stats()["batch"] == 1
+            alone.append(r.values.copy())
+            r.release()
+    with L.Context(0, n_slots=2) as c2:
+        c2.set_option(L.OPT_MAX_BATCH, 16)
+        xs = [dev(x) for x in pts]
+        outs = [empty(len(x), torch.float64) for x in pts]
+        reqs = [c2.submit(p, points=x, values=o) for p, x, o in zip(probs, xs, outs)]
+        batches = []
+        for r in reqs:
+            assert r.wait() == 0
+            batches.append(r.stats()["batch"])
+        for r, o, a in zip(reqs, outs, alone):
+            assert np.array_equal(host(o), a)            # bitwise: batch-invariant kernels
+            r.release()
+        assert max(batches) > 1                           # some requests really were fused
+        prof = c2.profile()
+        assert prof["shift_sum"]["launches"] < len(probs)
+        assert prof["shift_sum"]["bytes"] > 0 and prof["sample"]["launches"] == len(probs)
+
+
+def test_completion_sampling_matches_oracle_and_lsum_sample():
+    require_gpu()
+    import paper_1411_1994_amd as L
+    p = mixed_problems(1, seed=9)[0]
+    rng = np.random.default_rng(2)
+    cells = np.stack([rng.integers(0, n, 200) for n in p.N], axis=1)
+    xyz = np.stack([(cells[:, a] - (p.N[a] - 1) // 2) * p.h for a in range(3)], axis=1)
+    with L.Context(0) as c:
+        r = c.submit(p, points=xyz)
+        assert r.wait() == 0
+        ref = O.brute_force_points(p, cells)
+        assert np.max(np.abs(r.values - ref)) <= 1e-12 * np.max(np.abs(ref))
+        assert np.array_equal(r.sample(xyz), r.values)
+        r.release()
+
+
+def test_reference_cache_switch_gives_identical_results():
+    require_gpu()
+    import paper_1411_1994_amd as L
+    probs = mixed_problems(6, seed=3)
+    pts = np.array([[0.1, 0.2, 0.3], [-1.0, 2.0, 0.5]])
+    res = []
+    for cache in (1 << 30, 0):
+        with L.Context(0, n_slots=1) as c:
+            c.set_option(L.OPT_REF_CACHE_BYTES, cache)
+            vals = []
+            for p in probs + probs:                        # second pass hits the cache when on
+                r = c.submit(p, points=pts)
+                assert r.wait() == 0
+                vals.append(r.values.copy())
+                r.release()
+            prof = c.profile()
+            res.append((vals, prof["collocate"]["launches"]))
+    assert all(np.array_equal(a, b) for a, b in zip(res[0][0], res[1][0]))
+    assert res[0][1] < res[1][1] == 2 * len(probs)
+
+
+def test_cancel_and_release_of_queued_requests():
+    require_gpu()
+    import paper_1411_1994_amd as L
+    big = W.config(2)
+    with L.Context(0, n_slots=1) as c:
+        c.set_option(L.OPT_MAX_BATCH, 1)
+        reqs = [c.submit(big) for _ in range(6)]
+        cancelled = 0
+        for r in reqs[3:]:
+            try:
+                r.cancel()
+                cancelled += 1
+            except L.LsumError as e:
+                assert e.code == -9                       # already running
+        for r in reqs[:3]:
+            assert r.wait() == 0
+        for r in reqs[3:]:
+            assert r.wait() in (0, -6)
+        assert cancelled >= 1
+        for r in reqs:
+            r.release()
