@@ -160,7 +160,11 @@ int lsum_collocate(lsum_ctx ctx, void* stream, int R, const double* t, const dou
 
 /* Assembled 1D sums (Thm thm:sumCaseE (A)): U_dev[q*ldu + i] = sum_k G[q*ldg + i - c_k +
  * N_ref - 1] for i < N_axis, over the n_sites host cell indices c_k (0 <= c_k < N_axis <=
- * N_ref).  Summation order k = 0..n_sites-1 in FP64. */
+ * N_ref), in any order; ldg >= max(2, 2*N_ref-1).  FP64.  When the sites form p interleaved uniform combs
+ * (c_{k+p} - c_k constant), each comb is summed first (as a windowed strided sum of the row)
+ * and the p comb sums are added in order; otherwise the sites are added in order k = 0..n-1.
+ * Errors: LSUM_E_INVALID for bad sizes or null pointers, LSUM_E_OUT_OF_BOX for a site outside
+ * [0, N_axis).  Synchronous. */
 int lsum_shift_sum(lsum_ctx ctx, void* stream, int R, const double* G_dev, int ldg, int N_ref,
                    int N_axis, int n_sites, const int32_t* sites, double* U_dev, int ldu);
 

@@ -262,6 +262,19 @@ class Context:
         return Request(self, problem, nonblocking, points, values)
 
 
+class Prepared:
+    """A problem marshalled once into its C struct, for submitting many times (the library
+    deep-copies the struct at every submit, so one Prepared may back any number of requests)."""
+
+    def __init__(self, problem):
+        self.problem = problem
+        self.struct, self._keep = make_problem(problem)
+
+
+def prepare(problem) -> Prepared:
+    return Prepared(problem)
+
+
 def make_problem(p, points=None, values=None) -> tuple:
     """A C ``lsum_problem`` from any object with the fields of ``workloads.Problem``; returns
     (struct, keep-alive list)."""
@@ -292,12 +305,23 @@ class Request:
 
     def __init__(self, ctx: Context, problem, nonblocking: bool = False, points=None, values=None):
         self.ctx = ctx
-        self.problem = problem
         if points is not None and isinstance(points, np.ndarray):
             points = np.ascontiguousarray(points, dtype=np.float64)
             if values is None:
                 values = np.zeros(points.shape[0])
-        prob, keep = make_problem(problem, points, values)
+        if isinstance(problem, Prepared):
+            self.problem = problem.problem
+            prob = lsum_problem.from_buffer_copy(problem.struct)
+            keep = [problem]
+            if points is not None:
+                prob.n_points = int(points.shape[0])
+                prob.points = _ptr(points)
+                prob.values = _ptr(values)
+                prob.points_on_device = 0 if isinstance(points, np.ndarray) else 1
+                keep += [points, values]
+        else:
+            self.problem = problem
+            prob, keep = make_problem(problem, points, values)
         self._keep = keep            # caller memory must outlive the request
         self.values = values
         h = C.c_void_p()

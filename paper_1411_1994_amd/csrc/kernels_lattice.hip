@@ -3,6 +3,7 @@
 // All arithmetic is FP64.  These stages stream memory (no dense contraction), so they use
 // plain coalesced loads/stores and leave MFMA to the contraction kernels.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include "lsum_internal.h"
 
@@ -11,6 +12,12 @@ namespace lsum {
 namespace {
 
 constexpr double kSqrtPi = 1.7724538509055160273;
+
+// Pointers read from job descriptors are generic; casting them to the global (1) or constant (4)
+// address space lets the compiler use global_load / s_load instead of flat accesses, whose
+// shared counters force a full wait after every batch of loads.
+#define LSUM_GLOBAL __attribute__((address_space(1)))
+#define LSUM_CONST __attribute__((address_space(4)))
 
 // --------------------------------------------------------------------------------------------
 // Reference vectors (Sec. 2.1 b(t_k), Sec. 3.1 eq. master_pot): one thread per entry.
@@ -41,77 +48,102 @@ __global__ void __launch_bounds__(256) k_collocate(int R, const double* __restri
 }
 
 // --------------------------------------------------------------------------------------------
-// Assembled 1D sums (Thm thm:sumCaseE (A)): U[q, i] = sum_k G[q, i - c_k + N_ref - 1].
-// One workgroup per (64-cell tile, job); lane = cell, the 4 waves split the nodes q.  With a
-// comb decomposition the sum over the L sites becomes `period` differences of strided prefix
-// sums.  Results go to the vector-major rows directly and, through an LDS tile, to the
-// point-major rows, whose 64 x R block is one contiguous, coalesced store.
+// Assembled 1D sums (Thm thm:sumCaseE (A)) for a batch of jobs: out[q, i] = sum_t
+// T_tab(t)[q * ldg + i + off_t], summed in term order.  One workgroup per (64-cell tile, job).
+// Each lane owns a pair of adjacent cells and loads both with one 16-byte access (the unit that
+// bounds this kernel is the vector-memory path, not HBM: five 8-byte loads per output for the
+// cfg-2 combs); the two halves of a wavefront serve two node slots, so the 8 slots of the
+// workgroup take nodes s, s + 8, ..., s + 40 of each block of 48 nodes, and the loads of two
+// terms for all six nodes are in flight together.  Vector-major rows are stored from the lanes;
+// point-major rows go through an LDS tile so the 64 rows of a tile (padded with zeros to ldt)
+// leave as contiguous memory.  Stores are non-temporal so they do not evict the tables from L2.
 // --------------------------------------------------------------------------------------------
+typedef double dpair __attribute__((ext_vector_type(2), aligned(8)));
+
 __global__ void __launch_bounds__(256) k_shift_sum(const ShiftJob* __restrict__ jobs) {
-    __shared__ double tile[64][65];
-    const ShiftJob jb = jobs[blockIdx.y];
+    constexpr int QB = 48, NU = 6, TU = 2;
+    __shared__ double tile[64][QB + 1];
+    const ShiftJob& jb = jobs[blockIdx.y];
+    const int N = jb.N_axis;
     const int i0 = blockIdx.x * 64;
-    if (i0 >= jb.N_axis) return;
+    if (i0 >= N) return;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int i = i0 + lane;
-    const int32_t* __restrict__ c = jb.sites;
-    for (int q0 = 0; q0 < jb.R; q0 += 64) {
-        const int qn = min(64, jb.R - q0);
-        for (int qq = wave; qq < qn; qq += 4) {
-            const int q = q0 + qq;
-            double acc = 0.0;
-            if (i < jb.N_axis) {
-                const int base = i + jb.N_ref - 1;
-                if (jb.P) {
-                    const double* __restrict__ pr = jb.P + (size_t)q * jb.ldg;
-                    for (int j = 0; j < jb.period; ++j) {
-                        const int nj = (jb.n_sites - j + jb.period - 1) / jb.period;
-                        const int x1 = base - c[j];
-                        const int x2 = x1 - nj * jb.stride;
-                        acc += pr[x1] - (x2 >= 0 ? pr[x2] : 0.0);
-                    }
-                } else {
-                    const double* __restrict__ g = jb.G + (size_t)q * jb.ldg + base;
-                    const int n = jb.n_sites;
-                    int k = 0;
-                    for (; k + 4 <= n; k += 4) {
-                        const double a0 = g[-c[k]], a1 = g[-c[k + 1]], a2 = g[-c[k + 2]], a3 = g[-c[k + 3]];
-                        acc += a0;
-                        acc += a1;
-                        acc += a2;
-                        acc += a3;
-                    }
-                    for (; k < n; ++k) acc += g[-c[k]];
-                }
-                if (jb.U) jb.U[(size_t)q * jb.ldu + i] = acc;
+    const int pr = lane & 31;
+    const int slot = 2 * wave + (lane >> 5);
+    const int c0 = i0 + 2 * pr;
+    // the pair loaded is (cc, cc + 1) with cc + 1 < max(N, 2) so that every load stays inside the
+    // rows; a lane whose first cell is the last one (odd tail) takes it as the second of its pair
+    const int cc = max(0, min(c0, N - 2));
+    const bool shifted = cc != c0;
+    const LSUM_CONST int* __restrict__ terms = (const LSUM_CONST int*)jb.terms;   // (off, tab) pairs
+    const int nt = jb.n_terms;
+    const size_t ldg = (size_t)jb.ldg;
+    const LSUM_GLOBAL double* __restrict__ T0 = (const LSUM_GLOBAL double*)jb.T0 + cc;
+    const LSUM_GLOBAL double* __restrict__ T1 = (const LSUM_GLOBAL double*)(jb.T1 ? jb.T1 : jb.T0) + cc;
+    LSUM_GLOBAL double* __restrict__ U = (LSUM_GLOBAL double*)jb.U;
+    LSUM_GLOBAL double* __restrict__ UT = (LSUM_GLOBAL double*)jb.UT;
+    for (int q0 = 0; q0 < jb.R; q0 += QB) {
+        const int qn = min(QB, jb.R - q0);
+        size_t qo[NU];
+#pragma unroll
+        for (int u = 0; u < NU; ++u) qo[u] = (size_t)(q0 + min(slot + 8 * u, qn - 1)) * ldg;
+        dpair acc[NU];
+#pragma unroll
+        for (int u = 0; u < NU; ++u) acc[u] = dpair{0.0, 0.0};
+        for (int t = 0; t < nt; t += TU) {
+            dpair v[TU][NU];
+#pragma unroll
+            for (int e = 0; e < TU; ++e) {
+                const int te = min(t + e, nt - 1);
+                const LSUM_GLOBAL double* r = (terms[2 * te + 1] ? T1 : T0) + terms[2 * te];
+#pragma unroll
+                for (int u = 0; u < NU; ++u) v[e][u] = *(const LSUM_GLOBAL dpair*)(r + qo[u]);
             }
-            tile[lane][qq] = acc;
+#pragma unroll
+            for (int e = 0; e < TU; ++e)
+                if (t + e < nt)
+#pragma unroll
+                    for (int u = 0; u < NU; ++u) acc[u] += v[e][u];
         }
-        __syncthreads();
-        if (jb.UT) {
-            const int rows = min(64, jb.N_axis - i0);
-            for (int e = threadIdx.x; e < rows * qn; e += 256) {
-                const int ii = e / qn, qq = e % qn;
-                jb.UT[(size_t)(i0 + ii) * jb.R + q0 + qq] = tile[ii][qq];
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+            const int kk = slot + 8 * u;
+            if (kk >= qn) continue;
+            const double a = shifted ? acc[u].y : acc[u].x;
+            if (U) {
+                LSUM_GLOBAL double* row = U + (size_t)(q0 + kk) * jb.ldu;
+                if (c0 < N) __builtin_nontemporal_store(a, row + c0);
+                if (!shifted && c0 + 1 < N) __builtin_nontemporal_store(acc[u].y, row + c0 + 1);
+            }
+            if (UT) {
+                tile[2 * pr][kk] = a;
+                tile[2 * pr + 1][kk] = acc[u].y;
             }
         }
-        __syncthreads();
+        if (UT) {
+            __syncthreads();
+            const int rows = min(64, N - i0);
+            const int width = min(QB, jb.ldt - q0);   // includes the zero padding after R
+            for (int rr = wave; rr < rows; rr += 4)
+                for (int cl = lane; cl < width; cl += 64)
+                    __builtin_nontemporal_store(cl < qn ? tile[rr][cl] : 0.0,
+                                                &UT[(size_t)(i0 + rr) * jb.ldt + q0 + cl]);
+            __syncthreads();
+        }
     }
 }
 
-// Strided prefix sums of the reference rows: one thread per (q, residue class mod S).
-__global__ void __launch_bounds__(256) k_prefix(int R, const double* __restrict__ G, int ldg, int len, int S,
-                                                double* __restrict__ P) {
-    const long t = (long)blockIdx.x * 256 + threadIdx.x;
-    if (t >= (long)R * S) return;
-    const int q = (int)(t / S), rho = (int)(t % S);
-    const double* g = G + (size_t)q * ldg;
-    double* pr = P + (size_t)q * ldg;
+// Windowed strided sums of the reference rows: Q[q, x] = sum_{m=0}^{n-1} G[q, x - m S] (terms
+// with x - m S < 0 are absent).  A comb of n sites c, c + S, ..., c + (n-1) S adds
+// Q[q, i + N_ref - 1 - c] to cell i.
+__global__ void __launch_bounds__(256) k_window_sums(int ldg, const double* __restrict__ G, int S, int n,
+                                                     double* __restrict__ Q) {
+    const int x = blockIdx.x * 256 + threadIdx.x;
+    if (x >= ldg) return;
+    const double* g = G + (size_t)blockIdx.y * ldg;
     double acc = 0.0;
-    for (int x = rho; x < len; x += S) {
-        acc += g[x];
-        pr[x] = acc;
-    }
+    for (int m = 0, y = x; m < n && y >= 0; ++m, y -= S) acc += g[y];
+    Q[(size_t)blockIdx.y * ldg + x] = acc;
 }
 
 __device__ __forceinline__ int snap_dev(double x, double h, int N) {
@@ -190,33 +222,53 @@ __global__ void __launch_bounds__(256) k_transpose(int R, int N, const double* _
     }
 }
 
-// Canonical sum at points from point-major factors (row i holds the R values of cell i): each
-// wavefront evaluates 4 points with 16 lanes per point striding over the nodes q, so every
-// gather is a contiguous piece of a row; the partial products are reduced across the 16 lanes.
-// out[p] (+)= lam * sum_q prod_l UT_l[i_l(p), q].
-__global__ void __launch_bounds__(256) k_sample_rows(int R, const double* __restrict__ T0,
-                                                     const double* __restrict__ T1,
-                                                     const double* __restrict__ T2, int N0, int N1, int N2,
+// Canonical sum at points from point-major factors: row i of axis l holds the values of cell i
+// for every node, rows ldt apart, zero padded, ldt a multiple of 16 and rows 128-byte aligned.
+// Eight lanes serve a point and read its three rows in 16-byte pieces (NQ2 = ldt / 16 per lane
+// and row), which halves the vector-memory instructions of 8-byte gathers; the partial
+// products are reduced over the 8 lanes.  out[p] (+)= lam * sum_q prod_l T_l[i_l(p) * ldt + q].
+template <int NQ2>
+__global__ void __launch_bounds__(256) k_sample_rows(int ldt, const double2* __restrict__ T0,
+                                                     const double2* __restrict__ T1,
+                                                     const double2* __restrict__ T2, int N0, int N1, int N2,
                                                      double h, double lam, int accumulate, int n_pts,
                                                      const double* __restrict__ xyz,
                                                      double* __restrict__ out) {
-    const int l16 = threadIdx.x & 15;
-    const int p = blockIdx.x * 16 + (threadIdx.x >> 4);
-    if (p >= n_pts) return;
-    const int i0 = snap_dev(xyz[3 * (size_t)p + 0], h, N0);
-    const int i1 = snap_dev(xyz[3 * (size_t)p + 1], h, N1);
-    const int i2 = snap_dev(xyz[3 * (size_t)p + 2], h, N2);
-    const bool inside = i0 >= 0 && i1 >= 0 && i2 >= 0;
+    const int l8 = threadIdx.x & 7;
+    const int p = blockIdx.x * 32 + (threadIdx.x >> 3);
+    const bool live = p < n_pts;
+    const size_t pc = live ? p : 0;
+    const double x0 = xyz[3 * pc + 0], x1 = xyz[3 * pc + 1], x2 = xyz[3 * pc + 2];
+    const int i0 = snap_dev(x0, h, N0), i1 = snap_dev(x1, h, N1), i2 = snap_dev(x2, h, N2);
+    const bool in = live && i0 >= 0 && i1 >= 0 && i2 >= 0;
+    const size_t ld2 = (size_t)(ldt / 2);
+    const size_t r0 = (size_t)(in ? i0 : 0) * ld2 + l8;
+    const size_t r1 = (size_t)(in ? i1 : 0) * ld2 + l8;
+    const size_t r2 = (size_t)(in ? i2 : 0) * ld2 + l8;
     double acc = 0.0;
-    if (inside) {
-        const double* r0 = T0 + (size_t)i0 * R;
-        const double* r1 = T1 + (size_t)i1 * R;
-        const double* r2 = T2 + (size_t)i2 * R;
-        for (int q = l16; q < R; q += 16) acc += r0[q] * r1[q] * r2[q];
+    if (NQ2 > 0) {
+        double2 a[NQ2 > 0 ? NQ2 : 1], b[NQ2 > 0 ? NQ2 : 1], c[NQ2 > 0 ? NQ2 : 1];
+#pragma unroll
+        for (int k = 0; k < (NQ2 > 0 ? NQ2 : 1); ++k) {
+            a[k] = T0[r0 + 8 * k];
+            b[k] = T1[r1 + 8 * k];
+            c[k] = T2[r2 + 8 * k];
+        }
+#pragma unroll
+        for (int k = 0; k < (NQ2 > 0 ? NQ2 : 1); ++k) {
+            acc += a[k].x * b[k].x * c[k].x;
+            acc += a[k].y * b[k].y * c[k].y;
+        }
+    } else {
+        for (int k = 0; k < ldt / 16; ++k) {
+            const double2 a = T0[r0 + 8 * k], b = T1[r1 + 8 * k], c = T2[r2 + 8 * k];
+            acc += a.x * b.x * c.x;
+            acc += a.y * b.y * c.y;
+        }
     }
-    for (int m = 8; m > 0; m >>= 1) acc += __shfl_xor(acc, m, 16);
-    if (l16 == 0) {
-        if (!inside) out[p] = __builtin_nan("");
+    for (int m = 4; m > 0; m >>= 1) acc += __shfl_xor(acc, m, 8);
+    if (l8 == 0 && live) {
+        if (!in) out[p] = __builtin_nan("");
         else out[p] = accumulate ? out[p] + lam * acc : lam * acc;
     }
 }
@@ -379,29 +431,16 @@ void launch_collocate(hipStream_t st, int R, const double* t_dev, const double* 
     hipLaunchKernelGGL(k_collocate, grid, dim3(256), 0, st, R, t_dev, w13_dev, N_ref, h, G, ldg);
 }
 
-void launch_shift_sum(hipStream_t st, const ShiftJob* jobs_dev, int n_jobs, int max_N) {
-    if (n_jobs <= 0) return;
+void launch_shift_sum(hipStream_t st, const ShiftJob* jobs_dev, int n_jobs, int max_N, const KTime* kt) {
+    if (n_jobs <= 0 || max_N <= 0) return;
     dim3 grid(cdiv(max_N, 64), n_jobs);
-    hipLaunchKernelGGL(k_shift_sum, grid, dim3(256), 0, st, jobs_dev);
+    hipExtLaunchKernelGGL(k_shift_sum, grid, dim3(256), 0, st, kt ? kt->start : nullptr, kt ? kt->stop : nullptr,
+                          0, jobs_dev);
 }
 
-void launch_prefix(hipStream_t st, int R, const double* G, int ldg, int len, int stride, double* P) {
-    if (R <= 0 || stride <= 0) return;
-    hipLaunchKernelGGL(k_prefix, dim3(cdiv((long)R * stride, 256)), dim3(256), 0, st, R, G, ldg, len, stride, P);
-}
-
-int comb_period(const int32_t* c, int n, int max_p, int* stride) {
-    for (int p = 1; p <= max_p && p < n; ++p) {
-        const int S = c[p] - c[0];
-        if (S <= 0) continue;
-        bool ok = true;
-        for (int k = 0; k + p < n && ok; ++k) ok = (c[k + p] - c[k] == S);
-        if (ok) {
-            *stride = S;
-            return p;
-        }
-    }
-    return 0;
+void launch_window_sums(hipStream_t st, int R, const double* G, int ldg, int stride, int n, double* Q) {
+    if (R <= 0 || ldg <= 0) return;
+    hipLaunchKernelGGL(k_window_sums, dim3(cdiv(ldg, 256), R), dim3(256), 0, st, ldg, G, stride, n, Q);
 }
 
 void launch_sample_cp(hipStream_t st, int n_fac, int R, const double* U, int ldu,
@@ -425,20 +464,33 @@ void launch_transpose(hipStream_t st, int R, int N, const double* U, int ldu, do
     hipLaunchKernelGGL(k_transpose, dim3(cdiv(N, 32), cdiv(R, 32)), dim3(256), 0, st, R, N, U, ldu, UT);
 }
 
-void launch_sample_rows(hipStream_t st, int R, const double* T0, const double* T1, const double* T2, int N0,
-                        int N1, int N2, double h, double lam, int accumulate, int n_pts, const double* xyz,
-                        double* out) {
+void launch_sample_rows(hipStream_t st, int ldt, const double* T0, const double* T1, const double* T2,
+                        int N0, int N1, int N2, double h, double lam, int accumulate, int n_pts,
+                        const double* xyz, double* out, const KTime* kt) {
     if (n_pts <= 0) return;
-    hipLaunchKernelGGL(k_sample_rows, dim3(cdiv(n_pts, 16)), dim3(256), 0, st, R, T0, T1, T2, N0, N1, N2, h, lam,
-                       accumulate, n_pts, xyz, out);
+    const dim3 grid(cdiv(n_pts, 32)), blk(256);
+    hipEvent_t a = kt ? kt->start : nullptr, b = kt ? kt->stop : nullptr;
+    const double2 *t0 = (const double2*)T0, *t1 = (const double2*)T1, *t2 = (const double2*)T2;
+#define LSUM_SAMPLE_ROWS(NQ2)                                                                        \
+    hipExtLaunchKernelGGL(k_sample_rows<NQ2>, grid, blk, 0, st, a, b, 0, ldt, t0, t1, t2, N0, N1, N2, h, lam, \
+                          accumulate, n_pts, xyz, out)
+    switch (ldt) {
+        case 16: LSUM_SAMPLE_ROWS(1); break;
+        case 32: LSUM_SAMPLE_ROWS(2); break;
+        case 48: LSUM_SAMPLE_ROWS(3); break;
+        case 64: LSUM_SAMPLE_ROWS(4); break;
+        default: LSUM_SAMPLE_ROWS(0);
+    }
+#undef LSUM_SAMPLE_ROWS
 }
 
 void launch_sample_windows(hipStream_t st, int R, const double* G, int ldg, int N_ref, int n_def,
                            const int32_t* def_cells, const double* def_scale, int N0, int N1,
-                           int N2, double h, int n_pts, const double* xyz, double* out) {
+                           int N2, double h, int n_pts, const double* xyz, double* out, const KTime* kt) {
     if (n_pts <= 0 || n_def <= 0) return;
-    hipLaunchKernelGGL(k_sample_windows, dim3(cdiv(n_pts, 256)), dim3(256), 0, st, R, G, ldg,
-                       N_ref, n_def, def_cells, def_scale, N0, N1, N2, h, n_pts, xyz, out);
+    hipExtLaunchKernelGGL(k_sample_windows, dim3(cdiv(n_pts, 256)), dim3(256), 0, st, kt ? kt->start : nullptr,
+                          kt ? kt->stop : nullptr, 0, R, G, ldg, N_ref, n_def, def_cells, def_scale, N0, N1,
+                          N2, h, n_pts, xyz, out);
 }
 
 void launch_gather_columns(hipStream_t st, int R, int n_lat, const double* const* lat_U_dev, int ldu,

@@ -199,7 +199,7 @@ int lsum_get_canonical(lsum_req r, int block, double* U0, double* U1, double* U2
         const double* src = have_vm ? q.U[block].as<double>() + q.U_axis_off[l] : nullptr;
         if (!have_vm) {
             // factors are kept point-major (N x R); transpose back to R x N
-            launch_transpose(q.ctx->own_stream, P.N[l], P.R, q.UT[block].as<double>() + q.U_axis_off[l], P.R,
+            launch_transpose(q.ctx->own_stream, P.N[l], P.R, q.UT[block].as<double>() + q.UT_axis_off[l], P.ldt,
                              tmp.as<double>());
             LSUM_HIP(hipStreamSynchronize(q.ctx->own_stream));
             src = tmp.as<double>();
@@ -448,38 +448,42 @@ int lsum_collocate(lsum_ctx x, void* stream, int R, const double* t, const doubl
 int lsum_shift_sum(lsum_ctx x, void* stream, int R, const double* G_dev, int ldg, int N_ref, int N_axis,
                    int n_sites, const int32_t* sites, double* U_dev, int ldu) {
     if (!x || !G_dev || !U_dev || (n_sites > 0 && !sites)) return fail(LSUM_E_INVALID, "null argument");
-    if (R < 1 || N_axis < 1 || N_axis > N_ref || ldg < 2 * N_ref - 1 || ldu < N_axis || n_sites < 0)
+    if (R < 1 || N_axis < 1 || N_axis > N_ref || ldg < std::max(2, 2 * N_ref - 1) || ldu < N_axis || n_sites < 0)
         return fail(LSUM_E_INVALID, "bad sizes");
     for (int k = 0; k < n_sites; ++k)
         if (sites[k] < 0 || sites[k] >= N_axis) return fail(LSUM_E_OUT_OF_BOX, "site index outside the axis");
     LSUM_HIP(hipSetDevice(x->c.device));
     hipStream_t st = pick(x, stream);
-    DevBuf sd, jd;
-    int rc = sd.get(x->c.pool, std::max(1, n_sites) * 4);
+    // terms: one per site, or one per comb on windowed strided sums of the rows
+    std::vector<int2> terms;
+    int stride = 0, n_hi = 0;
+    bool two = false;
+    shift_terms(sites, n_sites, N_ref, terms, &stride, &n_hi, &two);
+    DevBuf td, jd, w0, w1;
+    int rc = td.get(x->c.pool, std::max<size_t>(1, terms.size()) * sizeof(int2));
     if (rc) return rc;
     if ((rc = jd.get(x->c.pool, sizeof(ShiftJob)))) return rc;
     ShiftJob j{};
-    j.G = G_dev;
-    j.U = U_dev;
-    j.sites = sd.as<int32_t>();
-    j.n_sites = n_sites;
-    j.N_axis = N_axis;
-    j.ldu = ldu;
-    j.ldg = ldg;
-    j.N_ref = N_ref;
-    j.R = R;
-    // sites forming interleaved uniform combs use strided prefix sums (2 loads per comb)
-    DevBuf pb;
-    int stride = 0;
-    const int period = n_sites >= 8 ? comb_period(sites, n_sites, n_sites / 3, &stride) : 0;
-    if (period > 0) {
-        if ((rc = pb.get(x->c.pool, (size_t)R * ldg * 8))) return rc;
-        launch_prefix(st, R, G_dev, ldg, 2 * N_ref - 1, stride, pb.as<double>());
-        j.P = pb.as<double>();
-        j.period = period;
-        j.stride = stride;
+    j.T0 = G_dev;
+    if (stride > 0) {
+        if ((rc = w0.get(x->c.pool, (size_t)R * ldg * 8))) return rc;
+        launch_window_sums(st, R, G_dev, ldg, stride, n_hi, w0.as<double>());
+        j.T0 = w0.as<double>();
+        if (two) {
+            if ((rc = w1.get(x->c.pool, (size_t)R * ldg * 8))) return rc;
+            launch_window_sums(st, R, G_dev, ldg, stride, n_hi - 1, w1.as<double>());
+            j.T1 = w1.as<double>();
+        }
     }
-    if (n_sites > 0) LSUM_HIP(hipMemcpyAsync(sd.p, sites, n_sites * 4, hipMemcpyHostToDevice, st));
+    j.terms = td.as<int2>();
+    j.n_terms = (int)terms.size();
+    j.U = U_dev;
+    j.ldu = ldu;
+    j.N_axis = N_axis;
+    j.ldg = ldg;
+    j.R = R;
+    if (!terms.empty())
+        LSUM_HIP(hipMemcpyAsync(td.p, terms.data(), terms.size() * sizeof(int2), hipMemcpyHostToDevice, st));
     LSUM_HIP(hipMemcpyAsync(jd.p, &j, sizeof(j), hipMemcpyHostToDevice, st));
     launch_shift_sum(st, jd.as<ShiftJob>(), 1, N_axis);
     LSUM_HIP(hipGetLastError());

@@ -108,7 +108,7 @@ size_t Plan::planned_bytes() const {
     size_t b = 0;
     size_t sumN = (size_t)N[0] + N[1] + N[2];
     b += (size_t)R * ldg * 8;                                  // reference rows (if not cached)
-    b += blocks.size() * (size_t)R * sumN * 8;                 // canonical factors
+    b += blocks.size() * (size_t)ldt * sumN * 8;               // canonical factors
     if (tucker()) {
         size_t rmax[3];
         for (int l = 0; l < 3; ++l) {
@@ -125,6 +125,46 @@ size_t Plan::planned_bytes() const {
         }
     }
     return b + (16u << 20);
+}
+
+int comb_period(const int32_t* c, int n, int max_p, int* stride) {
+    for (int p = 1; p <= max_p && p < n; ++p) {
+        const int S = c[p] - c[0];
+        if (S <= 0) continue;
+        bool ok = true;
+        for (int k = 0; k + p < n && ok; ++k) ok = (c[k + p] - c[k] == S);
+        if (ok) {
+            *stride = S;
+            return p;
+        }
+    }
+    return 0;
+}
+
+// Thm thm:sumCaseE (A) sums the reference row over every site of an axis.  Sites snapped from
+// a lattice of spacing b on a grid of step h repeat with period p whenever b/h = S/p is
+// rational: the axis is then p interleaved combs of stride S, and each comb is one window of
+// the strided sums of the reference row (one term instead of n_j).
+void shift_terms(const int32_t* c, int n, int N_ref, std::vector<int2>& terms, int* stride, int* n_hi,
+                 bool* two_tables) {
+    terms.clear();
+    *stride = 0;
+    *n_hi = 0;
+    *two_tables = false;
+    int S = 0;
+    const int period = n >= 4 ? comb_period(c, n, n / 2, &S) : 0;
+    if (period > 0) {
+        const int hi = (n + period - 1) / period;
+        for (int j = 0; j < period; ++j) {
+            const int nj = (n - j + period - 1) / period;
+            terms.push_back(make_int2(N_ref - 1 - c[j], nj == hi ? 0 : 1));
+            if (nj != hi) *two_tables = true;
+        }
+        *stride = S;
+        *n_hi = hi;
+        return;
+    }
+    for (int k = 0; k < n; ++k) terms.push_back(make_int2(N_ref - 1 - c[k], 0));
 }
 
 int make_plan(const lsum_problem& p, Plan& plan) {
@@ -166,6 +206,7 @@ int make_plan(const lsum_problem& p, Plan& plan) {
     plan.R = (int)plan.t.size();
     plan.N_ref = std::max(p.N[0], std::max(p.N[1], p.N[2]));
     plan.ldg = ((2 * plan.N_ref - 1) + 7) / 8 * 8;
+    plan.ldt = (plan.R + 15) / 16 * 16;
 
     // snapping
     const int nb = p.n_blocks;

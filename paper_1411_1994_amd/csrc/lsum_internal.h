@@ -55,6 +55,7 @@ struct Plan {
     int R = 0;
     int N_ref = 0;   // max N
     int ldg = 0;     // reference row stride
+    int ldt = 0;     // point-major factor row stride: R rounded up to 16 (128-byte rows)
 
     // per block, per axis snapped cell indices
     std::vector<std::vector<int32_t>> offs[3];   // offs[axis][block]
@@ -84,30 +85,45 @@ int make_plan(const lsum_problem& p, Plan& plan);
 // ------------------------------------------------------------------------------------------
 void launch_collocate(hipStream_t st, int R, const double* t_dev, const double* w13_dev, int N_ref,
                       double h, double* G, int ldg);
-// Shift-sum for a batch of (axis, block) jobs; see kernels_lattice.hip.  When the ascending
-// site list is `period` interleaved combs of uniform `stride` (c[k + period] - c[k] == stride),
-// P holds the reference rows' prefix sums along that stride and each output costs 2 * period
-// loads; otherwise (P == nullptr) the n_sites windows are summed directly.
-struct ShiftJob {
-    const double* G;      // reference rows (R x ldg)
-    const double* P;      // prefix rows along `stride` (R x ldg) or nullptr
-    double* U;            // vector-major output (R x ldu) or nullptr
-    double* UT;           // point-major output (N_axis x R) or nullptr
-    const int32_t* sites; // device cell indices, ascending
-    int n_sites;
-    int period;
-    int stride;
-    int N_axis;
-    int ldu;
-    int ldg;
-    int N_ref;
-    int R;
+// Optional kernel-bound timing: both events are recorded by the dispatch of the kernel itself
+// (hipExtLaunchKernel), so their difference is the kernel's own execution time.
+struct KTime {
+    hipEvent_t start = nullptr, stop = nullptr;
 };
-void launch_shift_sum(hipStream_t st, const ShiftJob* jobs_dev, int n_jobs, int max_N);
-// P[q, x] = sum_{m >= 0, x - m S >= 0} G[q, x - m S] for x < len
-void launch_prefix(hipStream_t st, int R, const double* G, int ldg, int len, int stride, double* P);
+
+// Shift-sum for a batch of (axis, block) jobs; see kernels_lattice.hip.  Each job is a list of
+// terms (off, tab): out[q, i] = sum_t T_tab[q * ldg + i + off] for i < N_axis, q < R.  With the
+// reference rows as T0 and off = N_ref - 1 - c_k per site this is the direct sum over the
+// sites; an axis whose sites form interleaved uniform combs uses windowed strided sums of the
+// reference rows (launch_window_sums) and one term per comb.
+struct ShiftJob {
+    const double* T0;      // rows of length >= ldg, R of them
+    const double* T1;      // second table (combs one site shorter) or nullptr
+    const int2* terms;     // n_terms pairs (off, tab)
+    double* U;             // vector-major output (R x ldu) or nullptr
+    double* UT;            // point-major output (N_axis x ldt, zero padded beyond R) or nullptr
+    int n_terms;
+    int N_axis;
+    int ldg;
+    int R;
+    int ldu;
+    int ldt;
+};
+// max_N: largest N_axis of the jobs; kt: optional kernel-bound timing.  Every row read must
+// extend one entry past the last cell window (ldg >= 2 * N_ref - 1 and ldg >= 2).
+void launch_shift_sum(hipStream_t st, const ShiftJob* jobs_dev, int n_jobs, int max_N,
+                      const KTime* kt = nullptr);
+// Q[q, x] = sum_{m=0}^{n-1} G[q, x - m S] over the terms with x - m S >= 0, for x < ldg.
+void launch_window_sums(hipStream_t st, int R, const double* G, int ldg, int stride, int n, double* Q);
 // Host: the smallest period p <= max_p with c[k+p] - c[k] constant (its stride), or 0.
 int comb_period(const int32_t* c, int n, int max_p, int* stride);
+// Host: the terms of one axis.  When the ascending sites c[0..n) are `period` interleaved
+// combs of uniform stride, comb j (sites c[j], c[j] + S, ...) has n_j = ceil((n - j) / period)
+// sites and one term (N_ref - 1 - c[j], tab) with tab 0 for n_j == n_hi and 1 for n_hi - 1;
+// *stride, *n_hi are set and *two_tables tells whether table 1 is used.  Otherwise one term
+// (N_ref - 1 - c[k], 0) per site on the reference rows and *stride = 0.
+void shift_terms(const int32_t* c, int n, int N_ref, std::vector<int2>& terms, int* stride, int* n_hi,
+                 bool* two_tables);
 void launch_sample_cp(hipStream_t st, int n_fac, int R, const double* U, int ldu,
                       const double* lam_dev, int N0, int N1, int N2, double h, int n_pts,
                       const double* xyz, double* out);
@@ -117,15 +133,15 @@ void launch_sample_block(hipStream_t st, int R, const double* U0, const double* 
                          double* out);
 // R x N (stride ldu) -> N x R
 void launch_transpose(hipStream_t st, int R, int N, const double* U, int ldu, double* UT);
-// Point-major canonical evaluation (one wave per point); accumulate = 0 overwrites out.
-void launch_sample_rows(hipStream_t st, int R, const double* T0, const double* T1, const double* T2, int N0,
-                        int N1, int N2, double h, double lam, int accumulate, int n_pts, const double* xyz,
-                        double* out);
+// Point-major canonical evaluation (rows ldt apart, zero padded); accumulate = 0 overwrites out.
+void launch_sample_rows(hipStream_t st, int ldt, const double* T0, const double* T1, const double* T2,
+                        int N0, int N1, int N2, double h, double lam, int accumulate, int n_pts,
+                        const double* xyz, double* out, const KTime* kt = nullptr);
 // Defect windows evaluated straight from the reference rows, added to out.
 void launch_sample_windows(hipStream_t st, int R, const double* G, int ldg, int N_ref,
                            int n_def, const int32_t* def_cells, const double* def_scale,
                            int N0, int N1, int N2, double h, int n_pts, const double* xyz,
-                           double* out);
+                           double* out, const KTime* kt = nullptr);
 // Side-matrix columns of one mode: rows [src*R + q] of cols (D x ldc).
 void launch_gather_columns(hipStream_t st, int R, int n_lat, const double* const* lat_U_dev,
                            int ldu, int n_win, const int32_t* win_cells_dev, const double* G,

@@ -263,20 +263,31 @@ static int run_tucker(Request* q, hipStream_t st, StageTimer& tm) {
 // sampling: canonical factors (point-major rows, plus defect windows from the reference), or
 // the Tucker tensor (mode-3 contraction as a GEMM per chunk of points, then modes 1 and 2)
 // ------------------------------------------------------------------------------------------
-int sample_points(Request* q, hipStream_t st, int n, const double* xyz_d, double* out_d) {
+int sample_points(Request* q, hipStream_t st, int n, const double* xyz_d, double* out_d, const KTime* kt) {
     Context* c = q->ctx;
     const Plan& P = q->plan;
     int rc;
     if (n <= 0) return LSUM_OK;
     if (!P.tucker()) {
-        for (int b = 0; b < (int)P.blocks.size(); ++b)
-            launch_sample_rows(st, P.R, q->UT[b].as<double>(), q->UT[b].as<double>() + q->U_axis_off[1],
-                               q->UT[b].as<double>() + q->U_axis_off[2], P.N[0], P.N[1], P.N[2], P.h,
-                               P.blocks[b].charge, b > 0 ? 1 : 0, n, xyz_d, out_d);
-        if (!P.defects.empty())
+        // kernel-bound timing: start on the first launch, stop on the last
+        const int nb = (int)P.blocks.size();
+        const bool windows = !P.defects.empty();
+        for (int b = 0; b < nb; ++b) {
+            KTime k;
+            if (kt && b == 0) k.start = kt->start;
+            if (kt && b == nb - 1 && !windows) k.stop = kt->stop;
+            const double* T = q->UT[b].as<double>();
+            launch_sample_rows(st, P.ldt, T, T + q->UT_axis_off[1], T + q->UT_axis_off[2], P.N[0], P.N[1],
+                               P.N[2], P.h, P.blocks[b].charge, b > 0 ? 1 : 0, n, xyz_d, out_d, &k);
+        }
+        if (windows) {
+            KTime k;
+            if (kt) k.stop = kt->stop;
+            if (kt && nb == 0) k.start = kt->start;
             launch_sample_windows(st, P.R, q->ref->G.as<double>(), P.ldg, P.N_ref, (int)P.defects.size(),
                                   q->def_cells.as<int32_t>(), q->def_scale.as<double>(), P.N[0], P.N[1], P.N[2],
-                                  P.h, n, xyz_d, out_d);
+                                  P.h, n, xyz_d, out_d, &k);
+        }
         LSUM_HIP(hipGetLastError());
         return LSUM_OK;
     }
@@ -345,70 +356,74 @@ int run_batch(std::vector<Request*>& reqs, hipStream_t st) {
     // (3) assembled shift-sums of every block and axis of every request: one launch.  Canonical
     // requests keep point-major factors (for sampling), reduction requests vector-major ones
     // (side-matrix columns).
-    std::vector<int32_t> sites_h;
+    std::vector<int2> terms_h;
     std::vector<ShiftJob> jobs;
-    std::vector<size_t> site_off;
+    std::vector<size_t> term_off;
     int maxN = 0;
     double out_bytes = 0, loads = 0;
     std::vector<const RefEntry*> distinct;
+    std::vector<int2> tv;
     for (auto* q : reqs) {
         Plan& P = q->plan;
         const int nb = (int)P.blocks.size();
         const size_t sumN = (size_t)P.N[0] + P.N[1] + P.N[2];
         const bool vector_major = P.tucker();
-        q->U_axis_off[0] = 0;
-        q->U_axis_off[1] = (size_t)P.R * P.N[0];
-        q->U_axis_off[2] = (size_t)P.R * (P.N[0] + P.N[1]);
+        for (int l = 0; l < 3; ++l) {
+            q->U_axis_off[l] = l == 0 ? 0 : q->U_axis_off[l - 1] + (size_t)P.R * P.N[l - 1];
+            q->UT_axis_off[l] = l == 0 ? 0 : q->UT_axis_off[l - 1] + (size_t)P.ldt * P.N[l - 1];
+        }
         q->U.resize(nb);
         q->UT.resize(nb);
         for (int b = 0; b < nb; ++b) {
             DevBuf& out = vector_major ? q->U[b] : q->UT[b];
-            if ((rc = out.get(c->pool, (size_t)P.R * sumN * 8))) return rc;
+            if ((rc = out.get(c->pool, (size_t)(vector_major ? P.R : P.ldt) * sumN * 8))) return rc;
             for (int l = 0; l < 3; ++l) {
                 const auto& sites = P.offs[l][b];
-                const int n = (int)sites.size();
-                site_off.push_back(sites_h.size());
-                sites_h.insert(sites_h.end(), sites.begin(), sites.end());
+                int stride = 0, n_hi = 0;
+                bool two = false;
+                shift_terms(sites.data(), (int)sites.size(), P.N_ref, tv, &stride, &n_hi, &two);
                 ShiftJob j{};
-                j.G = q->ref->G.as<double>();
-                j.U = vector_major ? q->U[b].as<double>() + q->U_axis_off[l] : nullptr;
-                j.UT = vector_major ? nullptr : q->UT[b].as<double>() + q->U_axis_off[l];
-                j.n_sites = n;
-                j.N_axis = P.N[l];
-                j.ldu = P.N[l];
-                j.ldg = P.ldg;
-                j.N_ref = P.N_ref;
-                j.R = P.R;
-                int stride = 0;
-                const int period = n >= 8 ? comb_period(sites.data(), n, n / 3, &stride) : 0;
-                if (period > 0) {
-                    const double* pr = nullptr;
-                    if ((rc = get_prefix(c, *q->ref, stride, st, &pr))) return rc;
-                    j.P = pr;
-                    j.period = period;
-                    j.stride = stride;
+                j.T0 = q->ref->G.as<double>();
+                if (stride > 0) {
+                    const double* w = nullptr;
+                    if ((rc = get_windows(c, *q->ref, stride, n_hi, st, &w))) return rc;
+                    j.T0 = w;
+                    if (two) {
+                        if ((rc = get_windows(c, *q->ref, stride, n_hi - 1, st, &w))) return rc;
+                        j.T1 = w;
+                    }
                 }
+                term_off.push_back(terms_h.size());
+                terms_h.insert(terms_h.end(), tv.begin(), tv.end());
+                j.n_terms = (int)tv.size();
+                j.U = vector_major ? q->U[b].as<double>() + q->U_axis_off[l] : nullptr;
+                j.ldu = P.N[l];
+                j.UT = vector_major ? nullptr : q->UT[b].as<double>() + q->UT_axis_off[l];
+                j.ldt = P.ldt;
+                j.N_axis = P.N[l];
+                j.ldg = P.ldg;
+                j.R = P.R;
                 jobs.push_back(j);
                 maxN = std::max(maxN, P.N[l]);
-                loads += (double)P.R * P.N[l] * (period > 0 ? 2 * period : n);
+                loads += (double)P.R * P.N[l] * tv.size();
             }
-            out_bytes += (double)P.R * sumN * 8;
+            out_bytes += (double)(vector_major ? P.R : P.ldt) * sumN * 8;
         }
         if (std::find(distinct.begin(), distinct.end(), q->ref.get()) == distinct.end()) distinct.push_back(q->ref.get());
         q->bytes["canonical"] = (double)nb * P.R * sumN * 8;
     }
     double ref_bytes = 0;
     for (auto* e : distinct) ref_bytes += (double)e->R * (2 * e->N_ref - 1) * 8;
-    DevBuf sites_d, jobs_d;
-    if ((rc = sites_d.get(c->pool, std::max<size_t>(1, sites_h.size()) * 4))) return rc;
+    DevBuf terms_d, jobs_d;
+    if ((rc = terms_d.get(c->pool, std::max<size_t>(1, terms_h.size()) * sizeof(int2)))) return rc;
     if ((rc = jobs_d.get(c->pool, jobs.size() * sizeof(ShiftJob)))) return rc;
-    for (size_t k = 0; k < jobs.size(); ++k) jobs[k].sites = sites_d.as<int32_t>() + site_off[k];
-    LSUM_HIP(hipMemcpyAsync(sites_d.p, sites_h.data(), sites_h.size() * 4, hipMemcpyHostToDevice, st));
+    for (size_t k = 0; k < jobs.size(); ++k) jobs[k].terms = terms_d.as<int2>() + term_off[k];
+    if (!terms_h.empty())
+        LSUM_HIP(hipMemcpyAsync(terms_d.p, terms_h.data(), terms_h.size() * sizeof(int2), hipMemcpyHostToDevice, st));
     LSUM_HIP(hipMemcpyAsync(jobs_d.p, jobs.data(), jobs.size() * sizeof(ShiftJob), hipMemcpyHostToDevice, st));
     // algorithmic traffic: every distinct reference read once, every factor written once
-    tm.begin("shift_sum", ref_bytes + out_bytes, loads);
-    launch_shift_sum(st, jobs_d.as<ShiftJob>(), (int)jobs.size(), maxN);
-    tm.end();
+    const KTime kt = tm.kernels("shift_sum", ref_bytes + out_bytes, loads);
+    launch_shift_sum(st, jobs_d.as<ShiftJob>(), (int)jobs.size(), maxN, &kt);
     LSUM_HIP(hipGetLastError());
 
     // defect tables (canonical sampling evaluates defect windows from the reference rows)
@@ -457,11 +472,17 @@ int run_batch(std::vector<Request*>& reqs, hipStream_t st) {
             out_d = od.as<double>();
         }
         const Plan& P = q->plan;
-        double fb = 0;
-        for (int b = 0; b < (int)q->U.size(); ++b) fb += (double)P.R * (P.N[0] + P.N[1] + P.N[2]) * 8;
-        tm.begin("sample", (double)n * 32 + (P.tucker() ? 0.0 : fb), 0);
-        rc = sample_points(q, st, n, xyz_d, out_d);
-        tm.end();
+        // factors read once (point-major rows of ldt values) + points in + values out
+        const double fb = (double)P.blocks.size() * P.ldt * (P.N[0] + P.N[1] + P.N[2]) * 8;
+        const double sb = (double)n * 32 + (P.tucker() ? 0.0 : fb);
+        if (P.tucker()) {
+            tm.begin("sample", sb, 0);
+            rc = sample_points(q, st, n, xyz_d, out_d);
+            tm.end();
+        } else {
+            const KTime kt = tm.kernels("sample", sb, 0);
+            rc = sample_points(q, st, n, xyz_d, out_d, &kt);
+        }
         if (rc) {
             q->status.store(rc);
             continue;

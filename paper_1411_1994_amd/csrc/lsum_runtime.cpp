@@ -107,6 +107,17 @@ void StageTimer::begin(const std::string& name, double bytes, double flops) {
 
 void StageTimer::end() { (void)hipEventRecord(ev_.back().b, st_); }
 
+KTime StageTimer::kernels(const std::string& name, double bytes, double flops) {
+    Ev e{name, nullptr, nullptr, bytes, flops};
+    (void)hipEventCreate(&e.a);
+    (void)hipEventCreate(&e.b);
+    ev_.push_back(e);
+    KTime k;
+    k.start = e.a;
+    k.stop = e.b;
+    return k;
+}
+
 void StageTimer::collect(std::map<std::string, double>& out, Context* c) {
     std::lock_guard<std::mutex> lk(c->prof_mu);
     for (auto& e : ev_) {
@@ -146,8 +157,7 @@ static int build_reference(Context* c, const Plan& P, hipStream_t st, RefEntry& 
     launch_collocate(st, P.R, tw.as<double>(), tw.as<double>() + P.R, P.N_ref, P.h, e.G.as<double>(), P.ldg);
     tm.end();
     LSUM_HIP(hipGetLastError());
-    LSUM_HIP(hipEventRecord(e.ready, st));
-    LSUM_HIP(hipStreamSynchronize(st));   // tw is released after this
+    LSUM_HIP(hipStreamSynchronize(st));   // the rows are complete for every stream; tw is released
     std::map<std::string, double> dummy;
     tm.collect(dummy, c);
     return LSUM_OK;
@@ -164,9 +174,9 @@ int get_reference(Context* c, const Plan& P, hipStream_t st, std::shared_ptr<Ref
         e->cached = false;
         int rc = e->G.get(c->pool, need);
         if (rc) return rc;
-        LSUM_HIP(hipEventCreateWithFlags(&e->ready, hipEventDisableTiming));
         rc = build_reference(c, P, st, *e);
         if (rc) return rc;
+        e->built.set(1);
         e->users.fetch_add(1);
         out = e;
         return LSUM_OK;
@@ -197,7 +207,6 @@ int get_reference(Context* c, const Plan& P, hipStream_t st, std::shared_ptr<Ref
             e->bytes = need;
             int rc = e->G.get(c->pool, need);
             if (rc) return rc;
-            LSUM_HIP(hipEventCreateWithFlags(&e->ready, hipEventDisableTiming));
             c->refs[key] = e;
             c->ref_bytes += need;
             build = true;
@@ -205,48 +214,66 @@ int get_reference(Context* c, const Plan& P, hipStream_t st, std::shared_ptr<Ref
         e->users.fetch_add(1);
         e->last_use = ++c->ref_clock;
     }
+    int rc;
     if (build) {
-        int rc = build_reference(c, P, st, *e);
-        if (rc) return rc;
+        rc = build_reference(c, P, st, *e);
+        if (rc) {
+            std::lock_guard<std::mutex> lk(c->ref_mu);   // a failed entry leaves the cache
+            auto it = c->refs.find(key);
+            if (it != c->refs.end() && it->second == e) {
+                c->ref_bytes -= e->bytes;
+                c->refs.erase(it);
+            }
+        }
+        e->built.set(rc ? rc : 1);
     } else {
-        LSUM_HIP(hipStreamWaitEvent(st, e->ready, 0));
+        const int s = e->built.wait();
+        rc = s < 0 ? s : LSUM_OK;
+    }
+    if (rc) {
+        e->users.fetch_sub(1);
+        return rc;
     }
     out = e;
     return LSUM_OK;
 }
 
-int get_prefix(Context* c, RefEntry& e, int stride, hipStream_t st, const double** out) {
-    PrefixRows* pr = nullptr;
+int get_windows(Context* c, RefEntry& e, int stride, int n, hipStream_t st, const double** out) {
+    WindowRows* wr = nullptr;
     bool build = false;
     {
-        std::lock_guard<std::mutex> lk(e.prefix_mu);
-        auto it = e.prefix.find(stride);
-        if (it == e.prefix.end()) {
-            auto np = std::make_unique<PrefixRows>();
-            int rc = np->P.get(c->pool, (size_t)e.R * e.ldg * 8);
+        std::lock_guard<std::mutex> lk(e.win_mu);
+        auto it = e.windows.find({stride, n});
+        if (it == e.windows.end()) {
+            auto nw = std::make_unique<WindowRows>();
+            int rc = nw->Q.get(c->pool, (size_t)e.R * e.ldg * 8);
             if (rc) return rc;
-            LSUM_HIP(hipEventCreateWithFlags(&np->ready, hipEventDisableTiming));
-            pr = np.get();
-            e.prefix.emplace(stride, std::move(np));
+            wr = nw.get();
+            e.windows.emplace(std::make_pair(stride, n), std::move(nw));
             build = true;
         } else {
-            pr = it->second.get();
+            wr = it->second.get();
         }
     }
     if (build) {
         StageTimer tm(st);
-        tm.begin("prefix", 2.0 * e.R * (2 * e.N_ref - 1) * 8, (double)e.R * (2 * e.N_ref - 1));
-        launch_prefix(st, e.R, e.G.as<double>(), e.ldg, 2 * e.N_ref - 1, stride, pr->P.as<double>());
+        tm.begin("windows", 2.0 * e.R * e.ldg * 8, (double)e.R * e.ldg * n);
+        launch_window_sums(st, e.R, e.G.as<double>(), e.ldg, stride, n, wr->Q.as<double>());
         tm.end();
-        LSUM_HIP(hipGetLastError());
-        LSUM_HIP(hipEventRecord(pr->ready, st));
-        LSUM_HIP(hipStreamSynchronize(st));
+        hipError_t err = hipGetLastError();
+        if (err == hipSuccess) err = hipStreamSynchronize(st);
+        if (err != hipSuccess) {
+            wr->built.set(LSUM_E_DEVICE);
+            return fail(LSUM_E_DEVICE, std::string("window sums: ") + hipGetErrorString(err));
+        }
         std::map<std::string, double> dummy;
         tm.collect(dummy, c);
+        wr->built.set(1);
     } else {
-        LSUM_HIP(hipStreamWaitEvent(st, pr->ready, 0));
+        const int s = wr->built.wait();
+        if (s < 0) return fail(s, "window sums failed to build");
     }
-    *out = pr->P.as<double>();
+    *out = wr->Q.as<const double>();
     return LSUM_OK;
 }
 

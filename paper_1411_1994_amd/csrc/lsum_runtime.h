@@ -80,30 +80,42 @@ struct DevBuf {
     template <typename T> T* as() const { return (T*)p; }
 };
 
-// reference vectors of one (kernel, quadrature, grid): "precomputed once, stored for multiple
-// use" (Sec. 2.1)
-struct PrefixRows {
-    DevBuf P;                        // strided prefix sums of the reference rows
-    hipEvent_t ready = nullptr;
-    ~PrefixRows() {
-        if (ready) (void)hipEventDestroy(ready);
+// Build state of a cached device table: the first user builds it on its stream and
+// synchronises; later users wait on the host until it is ready (or failed).
+struct BuildState {
+    std::mutex mu;
+    std::condition_variable cv;
+    int state = 0;                   // 0 building, 1 ready, < 0 the build's error code
+    void set(int s) {
+        std::lock_guard<std::mutex> lk(mu);
+        state = s;
+        cv.notify_all();
+    }
+    int wait() {
+        std::unique_lock<std::mutex> lk(mu);
+        cv.wait(lk, [&] { return state != 0; });
+        return state;
     }
 };
 
+// windowed strided sums of the reference rows for one (stride, comb length)
+struct WindowRows {
+    DevBuf Q;
+    BuildState built;
+};
+
+// reference vectors of one (kernel, quadrature, grid): "precomputed once, stored for multiple
+// use" (Sec. 2.1)
 struct RefEntry {
     DevBuf G;
     int R = 0, ldg = 0, N_ref = 0;
-    hipEvent_t ready = nullptr;
+    BuildState built;
     std::atomic<int> users{0};
     size_t bytes = 0;
     uint64_t last_use = 0;
     bool cached = true;
-    std::mutex prefix_mu;
-    std::map<int, std::unique_ptr<PrefixRows>> prefix;   // by stride
-    ~RefEntry() {
-        prefix.clear();
-        if (ready) (void)hipEventDestroy(ready);
-    }
+    std::mutex win_mu;
+    std::map<std::pair<int, int>, std::unique_ptr<WindowRows>> windows;   // by (stride, n)
 };
 using RefKey = std::tuple<int, double, int, double, double, double, int>;
 
@@ -162,7 +174,8 @@ struct Request {
     int points_on_device = 0;
     // canonical factors: per block, 3 axes of R x N[l] (vector-major) and N[l] x R (point-major)
     std::vector<DevBuf> U, UT;
-    size_t U_axis_off[3]{};
+    size_t U_axis_off[3]{};           // element offsets of the axes in U (R x N_l each)
+    size_t UT_axis_off[3]{};          // element offsets of the axes in UT (N_l x ldt each)
     DevBuf def_cells, def_scale;       // defects for sampling (n_def x 3, n_def)
     // Tucker
     int r[3]{};
@@ -184,6 +197,9 @@ class StageTimer {
     ~StageTimer();
     void begin(const std::string& name, double bytes = 0, double flops = 0);
     void end();
+    // a stage of kernels timed by their own dispatches: pass `start` to the first kernel's
+    // launch and `stop` to the last one's (instead of begin/end)
+    KTime kernels(const std::string& name, double bytes = 0, double flops = 0);
     // elapsed times (call after the stream has been synchronised)
     void collect(std::map<std::string, double>& out, Context* c);
 
@@ -199,14 +215,17 @@ class StageTimer {
 
 void finish(Request* q, int status);
 int get_reference(Context* c, const Plan& P, hipStream_t st, std::shared_ptr<RefEntry>& out);
-// prefix rows of a reference along `stride`, computed on st on first use; ready on st on return
-int get_prefix(Context* c, RefEntry& e, int stride, hipStream_t st, const double** out);
+// windowed strided sums of a reference (stride, comb length n), computed on st on first use;
+// complete on return
+int get_windows(Context* c, RefEntry& e, int stride, int n, hipStream_t st, const double** out);
 void drop_reference(Request* q);
 size_t retained_bytes(const Request* q);
 void worker(Context* c, int slot);
 
 // pipeline stages (lsum_pipeline.cpp)
 int run_batch(std::vector<Request*>& reqs, hipStream_t st);
-int sample_points(Request* q, hipStream_t st, int n, const double* xyz_dev, double* out_dev);
+// kt (canonical requests only): kernel-bound timing of the sampling kernels
+int sample_points(Request* q, hipStream_t st, int n, const double* xyz_dev, double* out_dev,
+                  const KTime* kt = nullptr);
 
 }  // namespace lsum
