@@ -19,6 +19,8 @@
 // Tiles: 64x64 per workgroup (4 waves in 2x2, each 32x32 = 2x2 MFMA blocks).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "lsum_internal.h"
 
 namespace lsum {
@@ -192,94 +194,248 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
 }
 
 // --------------------------------------------------------------------------------------------
-// Core contraction.  Rows of the GEMM are pairs (a, b) tiled 8 x 8, columns are c (64 per
-// tile), the reduction runs over canonical terms nu = g*R + q.  A(ab, nu) = scale_g *
-// Y1[a, s1(g)R+q] * Y2[b, s2(g)R+q] is formed at fragment time from two 8-row LDS tiles.
+// Core contraction (eq. C-core) as a GEMM with rows m = (a, b) and columns c, reduced over the
+// canonical terms nu.  A workgroup owns a 128 x 64 tile: 8 values of a times 16 of b, and 64
+// of c.  Per chunk of CK terms it stages rows of the term-major operands, forms the Khatri-Rao
+// tile K[nu][(a,b)] = x1[a] x2[b] in LDS (so the r1*r2 x K operand never exists in HBM), and
+// each wave multiplies its 32 rows by the 64 columns:
+//   FP32:   v_mfma_f32_32x32x2f32, FP32 sums within the chunk, FP64 across chunks;
+//   BF16X3: v_mfma_f32_32x32x16_bf16 on hi*hi + hi*lo + lo*hi of the split operands;
+//   FP64:   v_mfma_f64_16x16x4f64 throughout.
+// The next chunk's rows are loaded into registers while the current one is multiplied.
 // --------------------------------------------------------------------------------------------
+constexpr int CTA = 8, CTB = 16, CBM = CTA * CTB, CBN = 64;
+
+template <int P> struct CoreCfg;
+template <> struct CoreCfg<GEMM_F32> { using T = float; static constexpr int CK = 64; };
+template <> struct CoreCfg<GEMM_BF16X3> { using T = float; static constexpr int CK = 64; };
+template <> struct CoreCfg<GEMM_F64> { using T = double; static constexpr int CK = 32; };
+
+typedef float f16v __attribute__((ext_vector_type(16)));
+
+// row of the 32x32 FP32-output MFMA result held by lane `lane`, register v (column lane % 32)
+__device__ __forceinline__ int row32(int lane, int v) { return (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3); }
+
 template <int P>
-__global__ void __launch_bounds__(256) k_core(CoreArgs g, int k_split, typename GT<P>::T* work) {
-    using T = typename GT<P>::T;
-    using Acc = typename GT<P>::Acc;
-    constexpr int BK = GT<P>::BK;
-    __shared__ T Y1s[BK][8];
-    __shared__ T Y2s[BK][8];
-    __shared__ T Ks[BK][BM + 1];   // Khatri-Rao tile, formed in LDS
-    __shared__ T Bs[BK][BN + 1];
-    const T* __restrict__ Y1 = (const T*)g.Y1;
-    const T* __restrict__ Y2 = (const T*)g.Y2;
-    const T* __restrict__ Y3 = (const T*)g.Y3;
-    const int nb2 = (g.r2 + 7) / 8;
-    const int a0 = (blockIdx.y / nb2) * 8, b0 = (blockIdx.y % nb2) * 8, c0 = blockIdx.x * BN;
-    const long K = (long)g.n_groups * g.R;
-    const long chunk = ((K + k_split - 1) / k_split + BK - 1) / BK * BK;
-    const long kbeg = (long)blockIdx.z * chunk;
-    const long kend = kbeg + chunk < K ? kbeg + chunk : K;
+__global__ void __launch_bounds__(256) k_core(CoreArgs g, int kchunk, typename CoreCfg<P>::T* work) {
+    using T = typename CoreCfg<P>::T;
+    constexpr int CK = CoreCfg<P>::CK;
+    constexpr bool BF = (P == GEMM_BF16X3);
+    constexpr int KPAD = BF ? 8 : 4;
+    // staged projections; K tile [k][m] (FP32/FP64) or split bf16 [m][k] (BF16X3); B likewise
+    __shared__ T Y1s[CK][CTA];
+    __shared__ T Y2s[CK][CTB];
+    __shared__ __attribute__((aligned(16))) T Bs[BF ? 1 : CK][BF ? 1 : CBN + 4];
+    __shared__ __attribute__((aligned(16))) T Ks[BF ? 1 : CK][BF ? 1 : CBM + 4];
+    __shared__ __attribute__((aligned(16))) __bf16 Khi[BF ? CBM : 1][BF ? CK + KPAD : 1];
+    __shared__ __attribute__((aligned(16))) __bf16 Klo[BF ? CBM : 1][BF ? CK + KPAD : 1];
+    __shared__ __attribute__((aligned(16))) __bf16 Bhi[BF ? CBN : 1][BF ? CK + KPAD : 1];
+    __shared__ __attribute__((aligned(16))) __bf16 Blo[BF ? CBN : 1][BF ? CK + KPAD : 1];
+    const int nb2 = (g.r2 + CTB - 1) / CTB;
+    const int a0 = (blockIdx.y / nb2) * CTA, b0 = (blockIdx.y % nb2) * CTB, c0 = blockIdx.x * CBN;
+    const int kbeg = blockIdx.z * kchunk;
+    const int kend = min(g.K, kbeg + kchunk);
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-    Acc acc[2][2];
+    const int wm = wave * 32;
+
+    // register prefetch of one chunk: X3 rows (CK x 64, read as 16-byte vectors: the rows are
+    // 16-byte aligned since ldx is a multiple of 4) and the CK x 24 values of X1, X2
+    constexpr int VW = 16 / (int)sizeof(T);
+    using TV = T __attribute__((ext_vector_type(VW)));
+    constexpr int NB = CK * CBN / (256 * VW);                // Y3 vectors per thread
+    constexpr int NXY = (CK * (CTA + CTB) + 255) / 256;      // Y1/Y2 values per thread
+    TV pb[NB];
+    T pxy[NXY];
+    const T* __restrict__ X1 = (const T*)g.X1;
+    const T* __restrict__ X2 = (const T*)g.X2;
+    const T* __restrict__ X3 = (const T*)g.X3;
+    auto fetch = [&](int k0) {
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = Acc{0, 0, 0, 0};
-    Acc64 a64{};
-    for (long k0 = kbeg; k0 < kend; k0 += BK) {
-        // Y1 / Y2 tiles (8 rows x BK terms) with the group scale folded into Y1
-        for (int e = tid; e < 2 * 8 * BK; e += 256) {
-            const int which = e / (8 * BK);
-            const int rem = e % (8 * BK);
-            const int kk = rem % BK, rr = rem / BK;
-            const long nu = k0 + kk;
-            T v = T(0);
+        for (int t = 0; t < NB; ++t) {
+            const int e = tid + 256 * t;
+            const int kk = e / (CBN / VW), cc = (e % (CBN / VW)) * VW;
+            const int nu = k0 + kk, c = c0 + cc;
+            TV v = {};
             if (nu < kend) {
-                const int grp = (int)(nu / g.R), q = (int)(nu % g.R);
-                if (which == 0) {
-                    const int a = a0 + rr;
-                    if (a < g.r1) v = (T)g.scale[grp] * Y1[(long)a * g.ldy1 + (long)g.src1[grp] * g.R + q];
-                    Y1s[kk][rr] = v;
+                const T* row = X3 + (long)nu * g.ldx3;
+                if (c + VW <= g.r3) {
+                    v = *(const TV*)(row + c);
                 } else {
-                    const int b = b0 + rr;
-                    if (b < g.r2) v = Y2[(long)b * g.ldy2 + (long)g.src2[grp] * g.R + q];
-                    Y2s[kk][rr] = v;
+#pragma unroll
+                    for (int u = 0; u < VW; ++u)
+                        if (c + u < g.r3) v[u] = row[c + u];
                 }
-            } else {
-                if (which == 0) Y1s[kk][rr] = v; else Y2s[kk][rr] = v;
             }
+            pb[t] = v;
         }
-        for (int e = tid; e < BN * BK; e += 256) {
-            const int kk = e % BK, cc = e / BK;
-            const long nu = k0 + kk;
-            const int c = c0 + cc;
+#pragma unroll
+        for (int t = 0; t < NXY; ++t) {
+            const int e = tid + 256 * t;
             T v = T(0);
-            if (nu < kend && c < g.r3) {
-                const int grp = (int)(nu / g.R), q = (int)(nu % g.R);
-                v = Y3[(long)c * g.ldy3 + (long)g.src3[grp] * g.R + q];
+            if (e < CK * (CTA + CTB)) {
+                const int kk = e / (CTA + CTB), cc = e % (CTA + CTB);
+                const int nu = k0 + kk;
+                if (nu < kend) {
+                    if (cc < CTA) {
+                        if (a0 + cc < g.r1) v = X1[(long)nu * g.ldx1 + a0 + cc];
+                    } else if (b0 + cc - CTA < g.r2) {
+                        v = X2[(long)nu * g.ldx2 + b0 + cc - CTA];
+                    }
+                }
             }
-            Bs[kk][cc] = v;
+            pxy[t] = v;
+        }
+    };
+
+    // accumulators
+    f16v acc[2];            // FP32 / BF16X3: 32 x 64 per wave as two 32x32 blocks
+    double acc64[2][16];    // their FP64 sums across chunks
+    d4 accd[2][4];          // FP64: 2 x 4 blocks of 16x16
+    if constexpr (P == GEMM_F64) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) accd[i][j] = d4{0, 0, 0, 0};
+    } else {
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            acc[j] = f16v{};
+#pragma unroll
+            for (int v = 0; v < 16; ++v) acc64[j][v] = 0.0;
+        }
+    }
+
+    fetch(kbeg);
+    for (int k0 = kbeg; k0 < kend; k0 += CK) {
+        // registers -> LDS
+#pragma unroll
+        for (int t = 0; t < NB; ++t) {
+            const int e = tid + 256 * t;
+            const int kk = e / (CBN / VW), cc = (e % (CBN / VW)) * VW;
+#pragma unroll
+            for (int u = 0; u < VW; ++u) {
+                if constexpr (BF) {
+                    const float x = pb[t][u];
+                    const __bf16 hx = (__bf16)x;
+                    Bhi[cc + u][kk] = hx;
+                    Blo[cc + u][kk] = (__bf16)(x - (float)hx);
+                } else {
+                    Bs[kk][cc + u] = pb[t][u];
+                }
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < NXY; ++t) {
+            const int e = tid + 256 * t;
+            if (e < CK * (CTA + CTB)) {
+                const int kk = e / (CTA + CTB), cc = e % (CTA + CTB);
+                if (cc < CTA) Y1s[kk][cc] = pxy[t];
+                else Y2s[kk][cc - CTA] = pxy[t];
+            }
         }
         __syncthreads();
-        for (int e = tid; e < BM * BK; e += 256) {
-            const int mm = e % BM, kk = e / BM;
-            Ks[kk][mm] = Y1s[kk][mm >> 3] * Y2s[kk][mm & 7];
+        if (k0 + CK < kend) fetch(k0 + CK);
+        // Khatri-Rao tile
+        for (int e = tid; e < CK * CBM; e += 256) {
+            if constexpr (BF) {
+                const int m = e / CK, kk = e % CK;
+                const float x = Y1s[kk][m / CTB] * Y2s[kk][m % CTB];
+                const __bf16 hx = (__bf16)x;
+                Khi[m][kk] = hx;
+                Klo[m][kk] = (__bf16)(x - (float)hx);
+            } else {
+                const int kk = e / CBM, m = e % CBM;
+                Ks[kk][m] = Y1s[kk][m / CTB] * Y2s[kk][m % CTB];
+            }
         }
         __syncthreads();
-        mfma_chunk<P>(Ks, Bs, wm, wn, lane, acc);
-        flush<P>(acc, a64);
+        if constexpr (P == GEMM_F32) {
+#pragma unroll
+            for (int kk = 0; kk < CK; kk += 2) {
+                const float a = Ks[kk + (lane >> 5)][wm + (lane & 31)];
+                float b[2];
+#pragma unroll
+                for (int j = 0; j < 2; ++j) b[j] = Bs[kk + (lane >> 5)][j * 32 + (lane & 31)];
+#pragma unroll
+                for (int j = 0; j < 2; ++j) acc[j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b[j], acc[j], 0, 0, 0);
+            }
+        } else if constexpr (BF) {
+#pragma unroll
+            for (int kk = 0; kk < CK; kk += 16) {
+                const int ko = kk + 8 * (lane >> 5);
+                const bf8 ah = *(const bf8*)&Khi[wm + (lane & 31)][ko];
+                const bf8 al = *(const bf8*)&Klo[wm + (lane & 31)][ko];
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const bf8 bh = *(const bf8*)&Bhi[j * 32 + (lane & 31)][ko];
+                    const bf8 bl = *(const bf8*)&Blo[j * 32 + (lane & 31)][ko];
+                    acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc[j], 0, 0, 0);
+                    acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc[j], 0, 0, 0);
+                    acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc[j], 0, 0, 0);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int kk = 0; kk < CK; kk += 4) {
+                double a[2], b[4];
+#pragma unroll
+                for (int i = 0; i < 2; ++i) a[i] = Ks[kk + (lane >> 4)][wm + 16 * i + (lane & 15)];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) b[j] = Bs[kk + (lane >> 4)][16 * j + (lane & 15)];
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        accd[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], accd[i][j], 0, 0, 0);
+            }
+        }
+        if constexpr (P != GEMM_F64) {
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+#pragma unroll
+                for (int v = 0; v < 16; ++v) acc64[j][v] += (double)acc[j][v];
+                acc[j] = f16v{};
+            }
+        }
         __syncthreads();
     }
     const long plane = (long)g.r1 * g.r2 * g.r3;
-    T* out = (k_split > 1) ? work + (long)blockIdx.z * plane : (T*)g.core;
+    T* out = (gridDim.z > 1) ? work + (long)blockIdx.z * plane : (T*)g.core;
+    if constexpr (P == GEMM_F64) {
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int m = wm + 16 * i + (lane >> 4) + 4 * v;
+                    const int a = a0 + m / CTB, b = b0 + m % CTB, c = c0 + 16 * j + (lane & 15);
+                    if (a < g.r1 && b < g.r2 && c < g.r3) out[((long)a * g.r2 + b) * g.r3 + c] = accd[i][j][v];
+                }
+    } else {
 #pragma unroll
         for (int j = 0; j < 2; ++j)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int m = wm + i * 16 + acc_row<P>(lane, v);
-                const int a = a0 + (m >> 3), b = b0 + (m & 7);
-                const int c = c0 + wn + j * 16 + (lane & 15);
-                if (a < g.r1 && b < g.r2 && c < g.r3)
-                    out[((long)a * g.r2 + b) * g.r3 + c] = (T)result<P>(acc, a64, i, j, v);
+            for (int v = 0; v < 16; ++v) {
+                const int m = wm + row32(lane, v);
+                const int a = a0 + m / CTB, b = b0 + m % CTB, c = c0 + 32 * j + (lane & 31);
+                if (a < g.r1 && b < g.r2 && c < g.r3) out[((long)a * g.r2 + b) * g.r3 + c] = (float)acc64[j][v];
             }
+    }
+}
+
+// Term-major operands of the core: one 64-lane row copy per term.
+template <typename T>
+__global__ void __launch_bounds__(256) k_gather_terms(int K, int r, const T* __restrict__ Yt, long ldy,
+                                                      const int32_t* __restrict__ idx,
+                                                      const double* __restrict__ sc, T* __restrict__ X,
+                                                      long ldx) {
+    const int nu = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (nu >= K) return;
+    const T* src = Yt + (long)idx[nu] * ldy;
+    T* dst = X + (long)nu * ldx;
+    const T s = sc ? (T)sc[nu] : T(1);
+    for (int a = threadIdx.x & 63; a < ldx; a += 64) dst[a] = a < r ? s * src[a] : T(0);
 }
 
 template <typename T>
@@ -340,28 +496,42 @@ void launch_gemm(hipStream_t st, GemmPrec prec, const GemmArgs& a) {
 
 void launch_core(hipStream_t st, GemmPrec prec, const CoreArgs& a, int k_split, void* work) {
     if (a.r1 <= 0 || a.r2 <= 0 || a.r3 <= 0) return;
-    dim3 grid(cdiv(a.r3, BN), cdiv(a.r1, 8) * cdiv(a.r2, 8), k_split);
+    const int ck = prec == GEMM_F64 ? CoreCfg<GEMM_F64>::CK : CoreCfg<GEMM_F32>::CK;
+    k_split = std::max(1, k_split);
+    const int kchunk = (int)(((long)(a.K + k_split - 1) / k_split + ck - 1) / ck * ck);
+    dim3 grid(cdiv(a.r3, CBN), cdiv(a.r1, CTA) * cdiv(a.r2, CTB), k_split);
     const long plane = (long)a.r1 * a.r2 * a.r3;
     switch (prec) {
         case GEMM_F64:
-            hipLaunchKernelGGL(k_core<GEMM_F64>, grid, dim3(256), 0, st, a, k_split, (double*)work);
+            hipLaunchKernelGGL(k_core<GEMM_F64>, grid, dim3(256), 0, st, a, kchunk, (double*)work);
             if (k_split > 1)
                 hipLaunchKernelGGL(k_reduce_split<double>, dim3(cdiv(plane, 256)), dim3(256), 0, st,
                                    plane, k_split, (const double*)work, (double*)a.core);
             break;
         case GEMM_F32:
-            hipLaunchKernelGGL(k_core<GEMM_F32>, grid, dim3(256), 0, st, a, k_split, (float*)work);
+            hipLaunchKernelGGL(k_core<GEMM_F32>, grid, dim3(256), 0, st, a, kchunk, (float*)work);
             if (k_split > 1)
                 hipLaunchKernelGGL(k_reduce_split<float>, dim3(cdiv(plane, 256)), dim3(256), 0, st,
                                    plane, k_split, (const float*)work, (float*)a.core);
             break;
         case GEMM_BF16X3:
-            hipLaunchKernelGGL(k_core<GEMM_BF16X3>, grid, dim3(256), 0, st, a, k_split, (float*)work);
+            hipLaunchKernelGGL(k_core<GEMM_BF16X3>, grid, dim3(256), 0, st, a, kchunk, (float*)work);
             if (k_split > 1)
                 hipLaunchKernelGGL(k_reduce_split<float>, dim3(cdiv(plane, 256)), dim3(256), 0, st,
                                    plane, k_split, (const float*)work, (float*)a.core);
             break;
     }
+}
+
+void launch_gather_terms(hipStream_t st, int elem, int K, int r, const void* Yt, long ldy,
+                         const int32_t* idx, const double* sc, void* X, long ldx) {
+    if (K <= 0) return;
+    if (elem == 8)
+        hipLaunchKernelGGL(k_gather_terms<double>, dim3(cdiv(K, 4)), dim3(256), 0, st, K, r, (const double*)Yt,
+                           ldy, idx, sc, (double*)X, ldx);
+    else
+        hipLaunchKernelGGL(k_gather_terms<float>, dim3(cdiv(K, 4)), dim3(256), 0, st, K, r, (const float*)Yt,
+                           ldy, idx, sc, (float*)X, ldx);
 }
 
 void launch_cp_norm2(hipStream_t st, int R, int n_groups, const int32_t* src1, const int32_t* src2,

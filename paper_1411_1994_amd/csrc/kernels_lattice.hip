@@ -395,8 +395,12 @@ __global__ void __launch_bounds__(256) k_snap_points(int n, const double* __rest
     idx[2 * (size_t)n + p] = snap_dev(xyz[3 * (size_t)p + 2], h, N2);
 }
 
-// Tucker value at points after the mode-3 contraction: W[(a*r2+b)*P + p] holds
-// sum_c mu[a,b,c] Z3[c, i3(p)]; out[p] = sum_ab W Z1[a, i1(p)] Z2[b, i2(p)].
+// Tucker value at points after the mode-3 contraction: row p of W (P x r1*r2, layout [p][a*r2+b])
+// holds sum_c mu[a,b,c] Z3[c, i3(p)]; out[p] = sum_a Z1[a, i1(p)] sum_b W[p][a*r2+b] Z2[b, i2(p)].
+// One workgroup per point: the point's Z2 column is staged in LDS, each wave takes a subset of
+// the a rows and reads them contiguously (lanes over b), and the waves' totals are summed in a
+// fixed order.  (Without LDS staging, for r2 beyond the dynamic LDS limit, Z2 is read directly.)
+template <bool STAGE>
 __global__ void __launch_bounds__(256) k_tucker_finish(int r1, int r2, int P,
                                                        const double* __restrict__ W,
                                                        const double* __restrict__ Z1, int ld1,
@@ -404,21 +408,31 @@ __global__ void __launch_bounds__(256) k_tucker_finish(int r1, int r2, int P,
                                                        const int32_t* __restrict__ i1,
                                                        const int32_t* __restrict__ i2,
                                                        double* __restrict__ out) {
-    const int p = blockIdx.x * 256 + threadIdx.x;
-    if (p >= P) return;
+    extern __shared__ double z2s[];           // r2 values
+    __shared__ double part[4];
+    const int p = blockIdx.x;
     const int c1 = i1[p], c2 = i2[p];
-    if (c1 < 0 || c2 < 0) {
-        out[p] = __builtin_nan("");
+    if (c1 < 0 || c2 < 0) {                   // uniform per workgroup
+        if (threadIdx.x == 0) out[p] = __builtin_nan("");
         return;
     }
+    if (STAGE) {
+        for (int b = threadIdx.x; b < r2; b += 256) z2s[b] = Z2[(size_t)b * ld2 + c2];
+        __syncthreads();
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const double* w = W + (size_t)p * r1 * r2;
     double total = 0.0;
-    for (int a = 0; a < r1; ++a) {
+    for (int a = wave; a < r1; a += 4) {
         double acc = 0.0;
-        const double* w = W + (size_t)a * r2 * P + p;
-        for (int b = 0; b < r2; ++b) acc += w[(size_t)b * P] * Z2[(size_t)b * ld2 + c2];
+        for (int b = lane; b < r2; b += 64)
+            acc += w[(size_t)a * r2 + b] * (STAGE ? z2s[b] : Z2[(size_t)b * ld2 + c2]);
+        for (int m = 32; m > 0; m >>= 1) acc += __shfl_xor(acc, m, 64);
         total += acc * Z1[(size_t)a * ld1 + c1];
     }
-    out[p] = total;
+    if (lane == 0) part[wave] = total;
+    __syncthreads();
+    if (threadIdx.x == 0) out[p] = (part[0] + part[1]) + (part[2] + part[3]);
 }
 
 inline unsigned cdiv(long a, long b) { return (unsigned)((a + b - 1) / b); }
@@ -549,8 +563,12 @@ void launch_tucker_finish(hipStream_t st, int r1, int r2, int P, const double* W
                           int ld1, const double* Z2, int ld2, const int32_t* i1, const int32_t* i2,
                           double* out) {
     if (P <= 0) return;
-    hipLaunchKernelGGL(k_tucker_finish, dim3(cdiv(P, 256)), dim3(256), 0, st, r1, r2, P, W, Z1, ld1,
-                       Z2, ld2, i1, i2, out);
+    if (r2 <= 8192)
+        hipLaunchKernelGGL(k_tucker_finish<true>, dim3(P), dim3(256), (size_t)r2 * sizeof(double), st, r1, r2, P,
+                           W, Z1, ld1, Z2, ld2, i1, i2, out);
+    else
+        hipLaunchKernelGGL(k_tucker_finish<false>, dim3(P), dim3(256), 0, st, r1, r2, P, W, Z1, ld1, Z2, ld2, i1,
+                           i2, out);
 }
 
 void launch_snap_points(hipStream_t st, int n, const double* xyz, int N0, int N1, int N2, double h,

@@ -115,6 +115,7 @@ size_t Plan::planned_bytes() const {
             b += 2 * (size_t)D[l] * N[l] * 8;                  // raw + weighted columns
             rmax[l] = std::min<size_t>(std::min(D[l], N[l]), 1024);
             b += rmax[l] * N[l] * 8 * 2 + rmax[l] * D[l] * 8 * 2;   // Z, Y
+            b += (size_t)n_groups * R * (rmax[l] + 4) * 8;         // term-major core operand
             b += (size_t)D[l] * D[l] * 8;                      // column Gram
         }
         b += rmax[0] * rmax[1] * rmax[2] * 8;                  // core

@@ -165,15 +165,19 @@ struct GemmArgs {
 enum GemmPrec { GEMM_F64 = 0, GEMM_F32 = 1, GEMM_BF16X3 = 2 };
 void launch_gemm(hipStream_t st, GemmPrec prec, const GemmArgs& a);
 
-// Core contraction mu[a,b,c] = sum_g scale_g sum_q Y1[a, s1(g)R+q] Y2[b, s2(g)R+q] Y3[c, s3(g)R+q]
+// Core contraction (eq. C-core): mu[a,b,c] = sum_nu X1[nu, a] X2[nu, b] X3[nu, c] over the K
+// canonical terms nu = g*R + q.  X_l (K x ldx_l, row-major, FP64 or FP32 by precision) are the
+// term-major operands made by launch_gather_terms: row nu of X_l is row src_l(g)*R + q of the
+// transposed projection of mode l (times scale_g for mode 1).  ldx_l must be multiples of 4.
 struct CoreArgs {
-    int r1, r2, r3, R, n_groups;
-    const void* Y1; const void* Y2; const void* Y3;   // r_l x ldy_l
-    long ldy1, ldy2, ldy3;
-    const int32_t* src1; const int32_t* src2; const int32_t* src3;  // per group
-    const double* scale;
+    int r1, r2, r3, K;
+    const void* X1; const void* X2; const void* X3;
+    long ldx1, ldx2, ldx3;
     void* core;                                       // r1*r2*r3, last index fastest
 };
+// X[nu, a] = (sc ? sc[nu] : 1) * Yt[idx[nu], a] for a < r, zero for r <= a < ldx; elem 4 or 8 bytes
+void launch_gather_terms(hipStream_t st, int elem, int K, int r, const void* Yt, long ldy,
+                         const int32_t* idx, const double* sc, void* X, long ldx);
 void launch_core(hipStream_t st, GemmPrec prec, const CoreArgs& a, int k_split, void* work);
 // ||A||^2 from the three unnormalised column Grams (D x D) and the group table.
 void launch_cp_norm2(hipStream_t st, int R, int n_groups, const int32_t* src1, const int32_t* src2,
@@ -198,7 +202,7 @@ void launch_gather_scale_rows(hipStream_t st, int r, int n, const double* X, int
 // Rows of a factor selected by index lists: out[a * nsel + p] = Z[a * ldz + idx[p]]
 void launch_select_cols(hipStream_t st, int rows, int nsel, const void* Z, long ldz,
                         const int32_t* idx, void* out, int elem_size);
-// Tucker values at points from W (r1*r2 x P, layout [a*r2+b][p]) and Z1, Z2 rows
+// Tucker values at points from W (P x r1*r2, layout [p][a*r2+b]) and Z1, Z2 rows
 void launch_tucker_finish(hipStream_t st, int r1, int r2, int P, const double* W, const double* Z1,
                           int ld1, const double* Z2, int ld2, const int32_t* i1, const int32_t* i2,
                           double* out);

@@ -151,13 +151,16 @@ static int run_tucker(Request* q, hipStream_t st, StageTimer& tm) {
         W[l].reset();
     }
 
-    // (6) projections Y_l = Z_l cols_l^T (r_l x D_l) in the problem's precision
+    // (6) projections, stored transposed: Yt_l = cols_l Z_l^T (D_l x r_l, row stride ldy_l), in the
+    // problem's precision
     const size_t es = (prec == GEMM_F64) ? 8 : 4;
     DevBuf Y[3];
+    long ldy[3];
     tm.begin("projection", 0, 2.0 * ((double)q->r[0] * P.N[0] * P.D[0] + (double)q->r[1] * P.N[1] * P.D[1] + (double)q->r[2] * P.N[2] * P.D[2]));
     for (int l = 0; l < 3; ++l) {
         const int r = q->r[l], D = P.D[l], N = P.N[l];
-        if ((rc = Y[l].get(c->pool, (size_t)r * D * es))) return rc;
+        ldy[l] = (r + 3) / 4 * 4;
+        if ((rc = Y[l].get(c->pool, (size_t)D * ldy[l] * es))) return rc;
         const void* Zp = q->Z[l].p;
         const void* Cp = cols[l].p;
         DevBuf Zf, Cf;
@@ -170,10 +173,10 @@ static int run_tucker(Request* q, hipStream_t st, StageTimer& tm) {
             Cp = Cf.p;
         }
         GemmArgs a{};
-        a.m = r; a.n = D; a.k = N;
-        a.A = Zp; a.sam = N; a.sak = 1;
-        a.B = Cp; a.sbk = 1; a.sbn = N;
-        a.C = Y[l].p; a.scm = D; a.scn = 1;
+        a.m = D; a.n = r; a.k = N;
+        a.A = Cp; a.sam = N; a.sak = 1;
+        a.B = Zp; a.sbk = 1; a.sbn = N;
+        a.C = Y[l].p; a.scm = ldy[l]; a.scn = 1;
         a.alpha = 1.0; a.beta = 0.0; a.batch = 1;
         launch_gemm(st, prec, a);
         LSUM_HIP(hipStreamSynchronize(st));
@@ -181,22 +184,42 @@ static int run_tucker(Request* q, hipStream_t st, StageTimer& tm) {
     tm.end();
     for (int l = 0; l < 3; ++l) cols[l].reset();
 
-    // (7) core mu = sum_nu xi_nu y1 (x) y2 (x) y3 (eq. C-core), unnormalised columns: xi = scale
-    tm.begin("core", 0, 2.0 * (double)q->r[0] * q->r[1] * q->r[2] * (double)ng * P.R);
+    // (7) core mu = sum_nu xi_nu y1 (x) y2 (x) y3 (eq. C-core), unnormalised columns: xi = scale;
+    // term tables nu = g R + q -> projection rows src_l(g) R + q and the group scale
+    const long K = (long)ng * P.R;
+    tm.begin("core", 0, 2.0 * (double)q->r[0] * q->r[1] * q->r[2] * (double)K);
     {
+        std::vector<int32_t> idx(3 * (size_t)K);
+        std::vector<double> scv(K);
+        for (int g = 0; g < ng; ++g)
+            for (int k = 0; k < P.R; ++k) {
+                const long nu = (long)g * P.R + k;
+                for (int l = 0; l < 3; ++l) idx[(size_t)l * K + nu] = P.g_src[l][g] * P.R + k;
+                scv[nu] = P.g_scale[g];
+            }
+        DevBuf idx_d, sc_d;
+        if ((rc = idx_d.get(c->pool, idx.size() * 4))) return rc;
+        if ((rc = sc_d.get(c->pool, K * 8))) return rc;
+        LSUM_HIP(hipMemcpyAsync(idx_d.p, idx.data(), idx.size() * 4, hipMemcpyHostToDevice, st));
+        LSUM_HIP(hipMemcpyAsync(sc_d.p, scv.data(), K * 8, hipMemcpyHostToDevice, st));
+        // term-major operands X_l (K x ldy_l), the group scale folded into mode 1
+        DevBuf X[3];
+        for (int l = 0; l < 3; ++l) {
+            if ((rc = X[l].get(c->pool, (size_t)K * ldy[l] * es))) return rc;
+            launch_gather_terms(st, (int)es, (int)K, q->r[l], Y[l].p, ldy[l], idx_d.as<int32_t>() + (size_t)l * K,
+                                l == 0 ? sc_d.as<double>() : nullptr, X[l].p, ldy[l]);
+        }
         const long plane = (long)q->r[0] * q->r[1] * q->r[2];
         if ((rc = q->core.get(c->pool, (size_t)plane * es))) return rc;
         CoreArgs ca{};
-        ca.r1 = q->r[0]; ca.r2 = q->r[1]; ca.r3 = q->r[2]; ca.R = P.R; ca.n_groups = ng;
-        ca.Y1 = Y[0].p; ca.Y2 = Y[1].p; ca.Y3 = Y[2].p;
-        ca.ldy1 = P.D[0]; ca.ldy2 = P.D[1]; ca.ldy3 = P.D[2];
-        ca.src1 = s1; ca.src2 = s2; ca.src3 = s3;
-        ca.scale = scale_d.as<double>();
+        ca.r1 = q->r[0]; ca.r2 = q->r[1]; ca.r3 = q->r[2]; ca.K = (int)K;
+        ca.X1 = X[0].p; ca.X2 = X[1].p; ca.X3 = X[2].p;
+        ca.ldx1 = ldy[0]; ca.ldx2 = ldy[1]; ca.ldx3 = ldy[2];
         ca.core = q->core.p;
-        const long tiles = (long)((ca.r3 + 63) / 64) * ((ca.r1 + 7) / 8) * ((ca.r2 + 7) / 8);
-        const long K = (long)ng * P.R;
+        // enough workgroups for the chip: split the terms when the output has few tiles
+        const long tiles = (long)((ca.r3 + 63) / 64) * ((ca.r1 + 7) / 8) * ((ca.r2 + 15) / 16);
         int ks = 1;
-        while (tiles * ks < 1024 && ks < 64 && K / (ks * 2) >= 256) ks *= 2;
+        while (tiles * ks < 2048 && ks < 64 && K / (ks * 2) >= 512) ks *= 2;
         DevBuf work;
         if (ks > 1 && (rc = work.get(c->pool, (size_t)plane * ks * es))) return rc;
         launch_core(st, prec, ca, ks, work.p);
@@ -317,11 +340,12 @@ int sample_points(Request* q, hipStream_t st, int n, const double* xyz_d, double
         for (int p = 0; p < Pn; ++p) i3[p] = std::max(0, idx_h[(size_t)2 * n + p0 + p]);
         LSUM_HIP(hipMemcpyAsync(i3c.p, i3.data(), Pn * 4, hipMemcpyHostToDevice, st));
         launch_select_cols(st, r3, Pn, q->Z[2].p, P.N[2], i3c.as<int32_t>(), Z3s.p, 8);
+        // W[p][(a,b)] = sum_c Z3s[c][p] mu[(a,b)][c]: point-major, so each point's row is contiguous
         GemmArgs a{};
-        a.m = r1 * r2; a.n = Pn; a.k = r3;
-        a.A = core_d; a.sam = r3; a.sak = 1;
-        a.B = Z3s.p; a.sbk = Pn; a.sbn = 1;
-        a.C = W.p; a.scm = Pn; a.scn = 1;
+        a.m = Pn; a.n = r1 * r2; a.k = r3;
+        a.A = Z3s.p; a.sam = 1; a.sak = Pn;
+        a.B = core_d; a.sbk = 1; a.sbn = r3;
+        a.C = W.p; a.scm = (long)r1 * r2; a.scn = 1;
         a.alpha = 1.0; a.beta = 0.0; a.batch = 1;
         launch_gemm(st, GEMM_F64, a);
         launch_tucker_finish(st, r1, r2, Pn, W.as<double>(), q->Z[0].as<double>(), P.N[0], q->Z[1].as<double>(),
