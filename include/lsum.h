@@ -141,9 +141,13 @@ const char* lsum_last_error(void);
 /* Options: LSUM_OPT_MAX_BATCH (default 32): consecutive canonical requests (eps <= 0) a slot
  * fuses into one batch whose shift-sums run as one launch (1: no batching).
  * LSUM_OPT_REF_CACHE_BYTES (default 4 GiB): HBM kept for reference vectors shared by requests
- * with the same kernel, quadrature and grid (0: every request recomputes its own). */
+ * with the same kernel, quadrature and grid (0: every request recomputes its own).
+ * LSUM_OPT_RANGE_MIN (default 512): side matrices with min(D, N) at least this large are
+ * compressed to a randomized range basis before the Jacobi SVD (the residual outside the basis
+ * is computed exactly and enters the certified tail); 0 disables the compression. */
 #define LSUM_OPT_MAX_BATCH 1
 #define LSUM_OPT_REF_CACHE_BYTES 2
+#define LSUM_OPT_RANGE_MIN 3
 int lsum_set_option(lsum_ctx ctx, int key, double value);
 /* Per stage (collocate, shift_sum, transpose, columns, norm, svd, projection, core, tile,
  * sample): summed event-timed GPU milliseconds, number of timed launches, and the algorithmic

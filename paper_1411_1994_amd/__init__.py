@@ -30,7 +30,7 @@ SYMBOLS = ["lsum_nodes", "lsum_block_offsets", "lsum_create", "lsum_destroy", "l
            "lsum_submit", "lsum_wait", "lsum_cancel", "lsum_get_info", "lsum_get_canonical",
            "lsum_get_tucker", "lsum_get_sigma", "lsum_sample", "lsum_get_tile", "lsum_get_stats",
            "lsum_release", "lsum_set_option", "lsum_get_profile", "lsum_reset_profile"]
-OPT_MAX_BATCH, OPT_REF_CACHE_BYTES = 1, 2
+OPT_MAX_BATCH, OPT_REF_CACHE_BYTES, OPT_RANGE_MIN = 1, 2, 3
 
 
 class LsumError(RuntimeError):

@@ -46,8 +46,8 @@ __device__ __forceinline__ void pair_of(int n, int round, int i, int* a, int* b)
 __device__ __forceinline__ int pair_row(int I, int J, int k) { return k < 8 ? I * 8 + k : J * 8 + (k - 8); }
 
 // 1. Gram partials: part[(pair * nchunk + chunk) * 256 + a*16 + b]
-__global__ void __launch_bounds__(256) k_pair_gram(const double* __restrict__ X, int ldx, int nblk, int round,
-                                                   int nchunk, double* __restrict__ part) {
+__global__ void __launch_bounds__(256) k_pair_gram(const double* __restrict__ X, int ldx, int n_gram, int nblk,
+                                                   int round, int nchunk, double* __restrict__ part) {
     __shared__ double Gp[4][16][17];
     const int chunk = blockIdx.x, pair = blockIdx.y;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -60,7 +60,7 @@ __global__ void __launch_bounds__(256) k_pair_gram(const double* __restrict__ X,
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
         const int c = c0 + 4 * s + kg;
-        x[s] = c < ldx ? xr[c] : 0.0;
+        x[s] = c < n_gram ? xr[c] : 0.0;
     }
     d4 acc = {0, 0, 0, 0};
 #pragma unroll
@@ -260,11 +260,12 @@ __global__ void __launch_bounds__(256) k_permute_rows(int ldx, const int32_t* __
     Y[(size_t)row * ldy + i] = X[(size_t)perm[row] * ldx + i];
 }
 
-__global__ void __launch_bounds__(256) k_norms(int ldx, const double* __restrict__ X, double* __restrict__ nrm) {
+__global__ void __launch_bounds__(256) k_norms(int ldx, int n_gram, const double* __restrict__ X,
+                                               double* __restrict__ nrm) {
     __shared__ double red[256];
     const double* x = X + (size_t)blockIdx.x * ldx;
     double acc = 0.0;
-    for (int i = threadIdx.x; i < ldx; i += 256) acc += x[i] * x[i];
+    for (int i = threadIdx.x; i < n_gram; i += 256) acc += x[i] * x[i];
     red[threadIdx.x] = acc;
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {
@@ -274,20 +275,34 @@ __global__ void __launch_bounds__(256) k_norms(int ldx, const double* __restrict
     if (threadIdx.x == 0) nrm[blockIdx.x] = red[0];
 }
 
+// Random signs for the range sketch: out[i] = +-1 from the SplitMix64 output function of
+// seed + (i + 1) * golden-ratio increment (Steele, Lea, Flood 2014).
+__global__ void __launch_bounds__(256) k_random_signs(long n, unsigned long long seed, double* __restrict__ out) {
+    const long i = (long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    unsigned long long z = seed + (unsigned long long)(i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    out[i] = (z & 1ull) ? 1.0 : -1.0;
+}
+
 inline unsigned cdiv(long a, long b) { return (unsigned)((a + b - 1) / b); }
 
 struct JacobiLayout {
-    int Dp, ldx, nblk, npair, nchunk;
+    int Dp, ldx, nblk, npair, nchunk;   // nchunk: Gram chunks (over the first n_gram entries)
+    int nchunk_all;                      // rotation chunks (whole rows)
     size_t off_x2, off_nrm, off_perm, off_stat, off_part, off_q, off_act, total;
 };
 
-JacobiLayout layout(int D, int N) {
+JacobiLayout layout(int D, int N, int n_gram) {
     JacobiLayout L{};
     L.Dp = std::max(16, (D + 15) / 16 * 16);
     L.ldx = (N + 15) / 16 * 16;
     L.nblk = L.Dp / 8;
     L.npair = L.nblk / 2;
-    L.nchunk = (L.ldx + CW - 1) / CW;
+    L.nchunk = (n_gram + CW - 1) / CW;
+    L.nchunk_all = (L.ldx + CW - 1) / CW;
     auto al = [](size_t x) { return (x + 255) / 256 * 256; };
     const size_t xb = al((size_t)L.Dp * L.ldx * sizeof(double));
     L.off_x2 = xb;
@@ -303,13 +318,18 @@ JacobiLayout layout(int D, int N) {
 
 }  // namespace
 
-size_t jacobi_work_bytes(int D, int N) { return layout(D, N).total; }
+size_t jacobi_work_bytes(int D, int N) { return layout(D, N, N).total; }
+
+void launch_random_signs(hipStream_t st, long n, unsigned long long seed, double* out) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_random_signs, dim3(cdiv(n, 256)), dim3(256), 0, st, n, seed, out);
+}
 
 // Squared norms of the rows of X, and the permutation sorting them in descending order.
-static int sorted_norms(hipStream_t st, const JacobiLayout& L, double* X, char* base, std::vector<double>& sig2,
-                        std::vector<int32_t>& perm) {
+static int sorted_norms(hipStream_t st, const JacobiLayout& L, int n_gram, double* X, char* base,
+                        std::vector<double>& sig2, std::vector<int32_t>& perm) {
     double* nrm = (double*)(base + L.off_nrm);
-    hipLaunchKernelGGL(k_norms, dim3(L.Dp), dim3(256), 0, st, L.ldx, X, nrm);
+    hipLaunchKernelGGL(k_norms, dim3(L.Dp), dim3(256), 0, st, L.ldx, n_gram, X, nrm);
     sig2.resize(L.Dp);
     LSUM_HIP(hipMemcpyAsync(sig2.data(), nrm, L.Dp * sizeof(double), hipMemcpyDeviceToHost, st));
     LSUM_HIP(hipStreamSynchronize(st));
@@ -320,9 +340,10 @@ static int sorted_norms(hipStream_t st, const JacobiLayout& L, double* X, char* 
 }
 
 int jacobi_svd(hipStream_t st, int D, int N, double* A, int lda, double tol, double irrelevant, int max_sweeps,
-               std::vector<double>& sigma, int* sweeps_out, double* work_dev, size_t work_bytes) {
+               std::vector<double>& sigma, int* sweeps_out, double* work_dev, size_t work_bytes, int n_gram) {
+    if (n_gram <= 0 || n_gram > N) n_gram = N;
     if (D <= 0 || N <= 0) return fail(LSUM_E_INVALID, "empty side matrix");
-    const JacobiLayout L = layout(D, N);
+    const JacobiLayout L = layout(D, N, n_gram);
     if (work_bytes < L.total) return fail(LSUM_E_INVALID, "Jacobi workspace too small");
     char* base = (char*)work_dev;
     double* X = (double*)base;
@@ -335,7 +356,7 @@ int jacobi_svd(hipStream_t st, int D, int N, double* A, int lda, double tol, dou
     hipLaunchKernelGGL(k_copy_rows_in, dim3(cdiv(L.ldx, 256), L.Dp), dim3(256), 0, st, D, N, A, lda, X, L.ldx);
     std::vector<double> sig2;
     std::vector<int32_t> perm;
-    int rc = sorted_norms(st, L, X, base, sig2, perm);
+    int rc = sorted_norms(st, L, n_gram, X, base, sig2, perm);
     if (rc) return rc;
     // columns this small cannot move the certified tail; below 1e-15 sigma_max they are rounding
     const double smax2 = sig2[perm[0]];
@@ -355,15 +376,15 @@ int jacobi_svd(hipStream_t st, int D, int N, double* A, int lda, double tol, dou
         std::swap(X, X2);
         LSUM_HIP(hipMemsetAsync(stat, 0, 4 * sizeof(unsigned long long), st));
         for (int round = 0; round < nblk - 1; ++round) {
-            hipLaunchKernelGGL(k_pair_gram, dim3(L.nchunk, npair), dim3(256), 0, st, X, L.ldx, nblk, round,
-                               L.nchunk, part);
+            hipLaunchKernelGGL(k_pair_gram, dim3(L.nchunk, npair), dim3(256), 0, st, X, L.ldx, n_gram, nblk,
+                               round, L.nchunk, part);
             hipLaunchKernelGGL(k_pair_eig, dim3(npair), dim3(64), 0, st, L.nchunk, part, tol, irr2, Qd, act, stat);
-            hipLaunchKernelGGL(k_pair_rotate, dim3(L.nchunk, npair), dim3(256), 0, st, X, L.ldx, nblk, round, Qd,
-                               act);
+            hipLaunchKernelGGL(k_pair_rotate, dim3(L.nchunk_all, npair), dim3(256), 0, st, X, L.ldx, nblk, round,
+                               Qd, act);
         }
         unsigned long long st4[4] = {0, 0, 0, 0};
         LSUM_HIP(hipMemcpyAsync(st4, stat, sizeof(st4), hipMemcpyDeviceToHost, st));
-        rc = sorted_norms(st, L, X, base, sig2, perm);   // synchronises
+        rc = sorted_norms(st, L, n_gram, X, base, sig2, perm);   // synchronises
         if (rc) return rc;
         double off;
         std::memcpy(&off, &st4[0], sizeof(off));

@@ -298,7 +298,10 @@ int lsum_get_stats(lsum_req r, char* buf, size_t len) {
           << ",\"h_u\":" << P.h_u << ",\"s\":" << P.s << ",\"N\":[" << P.N[0] << "," << P.N[1] << "," << P.N[2]
           << "],\"D\":[" << P.D[0] << "," << P.D[1] << "," << P.D[2] << "],\"r\":[" << q.r[0] << "," << q.r[1]
           << "," << q.r[2] << "],\"sweeps\":[" << q.sweeps[0] << "," << q.sweeps[1] << "," << q.sweeps[2]
-          << "],\"tails\":[" << q.tails[0] << "," << q.tails[1] << "," << q.tails[2] << "],\"norm_A\":" << q.norm_A
+          << "],\"tails\":[" << q.tails[0] << "," << q.tails[1] << "," << q.tails[2]
+          << "],\"range_k\":[" << q.range_k[0] << "," << q.range_k[1] << "," << q.range_k[2]
+          << "],\"range_res\":[" << q.range_res[0] << "," << q.range_res[1] << "," << q.range_res[2]
+          << "],\"norm_A\":" << q.norm_A
           << ",\"norm_xi\":" << q.norm_xi << ",\"bound\":" << q.bound << ",\"batch\":" << q.batch_size
           << ",\"offsets\":[";
         for (int b = 0; b < (int)P.blocks.size(); ++b) {
@@ -382,6 +385,10 @@ int lsum_set_option(lsum_ctx x, int key, double value) {
             }
             return LSUM_OK;
         }
+        case LSUM_OPT_RANGE_MIN:
+            if (!(value >= 0 && value <= 1e9)) return fail(LSUM_E_INVALID, "range threshold out of range");
+            c.range_min = (int)value;
+            return LSUM_OK;
         default:
             return fail(LSUM_E_INVALID, "unknown option");
     }

@@ -186,11 +186,16 @@ void launch_cp_norm2(hipStream_t st, int R, int n_groups, const int32_t* src1, c
 
 // One-sided block-Jacobi SVD of the D rows of A (length N): rows are rotated in place and
 // written back sorted by descending norm (sigma).  Pairs involving a row whose norm is below
-// `irrelevant` are not rotated (such rows cannot move a certified tail).
+// `irrelevant` are not rotated (such rows cannot move a certified tail).  With n_gram < N only
+// the first n_gram entries of each row define the Gram matrix, the norms and the convergence;
+// the remaining entries are companion data rotated along (they receive the same orthogonal
+// transformation).
 int jacobi_svd(hipStream_t st, int D, int N, double* A, int lda, double tol, double irrelevant,
                int max_sweeps, std::vector<double>& sigma, int* sweeps_out, double* work_dev,
-               size_t work_bytes);
+               size_t work_bytes, int n_gram = 0);
 size_t jacobi_work_bytes(int D, int N);
+// out[i] = +-1, i < n, a deterministic function of (seed, i)
+void launch_random_signs(hipStream_t st, long n, unsigned long long seed, double* out);
 
 // type conversions
 void launch_f64_to_f32(hipStream_t st, long n, const double* x, float* y);

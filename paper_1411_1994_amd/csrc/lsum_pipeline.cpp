@@ -16,6 +16,131 @@ static GemmPrec gemm_prec(int precision) {
     return precision == LSUM_FP64 ? GEMM_F64 : (precision == LSUM_FP32 ? GEMM_F32 : GEMM_BF16X3);
 }
 
+// Truncated SVD of one weighted side matrix W (D rows of length N; Def. def:RHOSVD).  The
+// result is a list of singular values and rows holding the matching left singular vectors,
+// such that for every r, ||A - Z_r Z_r^T A||_F^2 <= res2 + sum_{a >= r} sigma_a^2.
+//  * direct: one-sided Jacobi on W itself (res2 = 0; rows = rotated W, sigma-scaled);
+//  * range basis, for min(D, N) >= range_min: Y = Omega^T W with k random-sign columns, its k
+//    rows orthonormalised by Jacobi (Q), B = Q W^T, and the residual E = W - B^T Q computed
+//    explicitly (res2 = ||E||_F^2, which must stay below (thr/10)^2, else the direct solve runs); then
+//    Jacobi on the k rows [B | Q] with the Gram taken over B only, so the rotated Q part holds
+//    orthonormal vectors and ||A - Z_r Z_r^T A||^2 = res2 + sum_{a >= r} sigma_a^2 exactly.
+struct ModeSVD {
+    std::vector<double> sigma;   // descending
+    double res2 = 0.0;
+    DevBuf rows;
+    long ld = 0, off = 0;        // row stride, offset of the vector part
+    bool unit = false;           // vector rows are unit (range path) or sigma-scaled (direct)
+    int k = 0, sweeps = 0;
+};
+
+static int range_svd(Context* c, hipStream_t st, int D, int N, const double* W, int k, double thr,
+                     double irrelevant, ModeSVD& out, bool* enough) {
+    int rc;
+    *enough = false;
+    DevBuf Om, Yt, work;
+    if ((rc = Om.get(c->pool, (size_t)D * k * 8))) return rc;
+    if ((rc = Yt.get(c->pool, (size_t)k * N * 8))) return rc;
+    launch_random_signs(st, (long)D * k, 0x5eed1411ull + (unsigned long long)k, Om.as<double>());
+    GemmArgs a{};
+    // Yt (k x N) = Omega^T W
+    a.m = k; a.n = N; a.k = D;
+    a.A = Om.p; a.sam = 1; a.sak = k;
+    a.B = W; a.sbk = N; a.sbn = 1;
+    a.C = Yt.p; a.scm = N; a.scn = 1;
+    a.alpha = 1.0; a.beta = 0.0; a.batch = 1;
+    launch_gemm(st, GEMM_F64, a);
+    Om.reset();
+    size_t wb = jacobi_work_bytes(k, N);
+    if ((rc = work.get(c->pool, wb))) return rc;
+    std::vector<double> sy;
+    int sw = 0;
+    rc = jacobi_svd(st, k, N, Yt.as<double>(), N, 1e-12, 0.0, 40, sy, &sw, work.as<double>(), wb);
+    if (rc) return rc;
+    int kq = 0;
+    while (kq < k && sy[kq] > 1e-12 * sy[0]) ++kq;
+    if (kq == 0) return LSUM_OK;
+    // AUG rows [B_a | Q_a], Q_a = Yt_a / sigma_a
+    const long ld = (long)D + N;
+    DevBuf AUG, iv, E, nrm;
+    if ((rc = AUG.get(c->pool, (size_t)kq * ld * 8))) return rc;
+    std::vector<double> inv(kq);
+    for (int i = 0; i < kq; ++i) inv[i] = 1.0 / sy[i];
+    if ((rc = iv.get(c->pool, kq * 8))) return rc;
+    LSUM_HIP(hipMemcpyAsync(iv.p, inv.data(), kq * 8, hipMemcpyHostToDevice, st));
+    launch_scale_rows(st, kq, N, Yt.as<double>(), N, iv.as<double>(), AUG.as<double>() + D, ld);
+    // B (kq x D) = Q W^T into the first D entries of each AUG row
+    a = GemmArgs{};
+    a.m = kq; a.n = D; a.k = N;
+    a.A = AUG.as<double>() + D; a.sam = ld; a.sak = 1;
+    a.B = W; a.sbk = 1; a.sbn = N;
+    a.C = AUG.p; a.scm = ld; a.scn = 1;
+    a.alpha = 1.0; a.beta = 0.0; a.batch = 1;
+    launch_gemm(st, GEMM_F64, a);
+    // E = W - B^T Q and its squared Frobenius norm
+    if ((rc = E.get(c->pool, (size_t)D * N * 8))) return rc;
+    if ((rc = nrm.get(c->pool, (size_t)D * 8))) return rc;
+    LSUM_HIP(hipMemcpyAsync(E.p, W, (size_t)D * N * 8, hipMemcpyDeviceToDevice, st));
+    a = GemmArgs{};
+    a.m = D; a.n = N; a.k = kq;
+    a.A = AUG.p; a.sam = 1; a.sak = ld;
+    a.B = AUG.as<double>() + D; a.sbk = ld; a.sbn = 1;
+    a.C = E.p; a.scm = N; a.scn = 1;
+    a.alpha = -1.0; a.beta = 1.0; a.batch = 1;
+    launch_gemm(st, GEMM_F64, a);
+    launch_row_norms(st, D, N, E.as<double>(), N, nrm.as<double>());
+    std::vector<double> en(D);
+    LSUM_HIP(hipMemcpyAsync(en.data(), nrm.p, D * 8, hipMemcpyDeviceToHost, st));
+    LSUM_HIP(hipStreamSynchronize(st));
+    double res2 = 0.0;
+    for (double v : en) res2 += v * v;
+    if (!(std::sqrt(res2) <= 0.1 * thr)) return LSUM_OK;   // basis too small
+    E.reset();
+    Yt.reset();
+    work.reset();
+    wb = jacobi_work_bytes(kq, (int)ld);
+    if ((rc = work.get(c->pool, wb))) return rc;
+    rc = jacobi_svd(st, kq, (int)ld, AUG.as<double>(), (int)ld, 1e-12, irrelevant, 40, out.sigma, &out.sweeps,
+                    work.as<double>(), wb, D);
+    if (rc) return rc;
+    out.res2 = res2;
+    out.rows = std::move(AUG);
+    out.ld = ld;
+    out.off = D;
+    out.unit = true;
+    out.k = kq;
+    *enough = true;
+    return LSUM_OK;
+}
+
+static int mode_svd(Context* c, hipStream_t st, int D, int N, DevBuf& W, double thr, double irrelevant,
+                    ModeSVD& out) {
+    int rc;
+    const int mn = std::min(D, N);
+    const int range_min = c->range_min;
+    if (range_min > 0 && mn >= range_min) {
+        // one basis of 256 vectors: it wins when the certified rank is well below min(D, N); when
+        // it is not enough (a few percent of a direct solve) the direct solve follows
+        const int k = std::min(256, mn / 2);
+        bool enough = false;
+        if ((rc = range_svd(c, st, D, N, W.as<double>(), k, thr, irrelevant, out, &enough))) return rc;
+        if (enough) return LSUM_OK;
+    }
+    DevBuf work;
+    const size_t wb = jacobi_work_bytes(D, N);
+    if ((rc = work.get(c->pool, wb))) return rc;
+    rc = jacobi_svd(st, D, N, W.as<double>(), N, 1e-12, irrelevant, 40, out.sigma, &out.sweeps, work.as<double>(),
+                    wb);
+    if (rc) return rc;
+    out.res2 = 0.0;
+    out.rows = std::move(W);
+    out.ld = N;
+    out.off = 0;
+    out.unit = false;
+    out.k = 0;
+    return LSUM_OK;
+}
+
 // RHOSVD of one request whose canonical factors are computed (q->U, q->ref ready on st).
 static int run_tucker(Request* q, hipStream_t st, StageTimer& tm) {
     Context* c = q->ctx;
@@ -99,6 +224,7 @@ static int run_tucker(Request* q, hipStream_t st, StageTimer& tm) {
     const double irrelevant = 1e-2 * thr / std::sqrt((double)std::max(P.D[0], std::max(P.D[1], P.D[2])));
     // weighted, normalised side matrices: row j = col_j / |col_j| * sqrt(multiplicity)
     tm.begin("svd");
+    ModeSVD ms[3];
     for (int l = 0; l < 3; ++l) {
         const int D = P.D[l], N = P.N[l];
         std::vector<double> sc(D);
@@ -108,23 +234,25 @@ static int run_tucker(Request* q, hipStream_t st, StageTimer& tm) {
         if ((rc = W[l].get(c->pool, (size_t)D * N * 8))) return rc;
         LSUM_HIP(hipMemcpyAsync(scd.p, sc.data(), D * 8, hipMemcpyHostToDevice, st));
         launch_scale_rows(st, D, N, cols[l].as<double>(), N, scd.as<double>(), W[l].as<double>(), N);
-        DevBuf work;
-        size_t wb = jacobi_work_bytes(D, N);
-        if ((rc = work.get(c->pool, wb))) return rc;
-        rc = jacobi_svd(st, D, N, W[l].as<double>(), N, 1e-12, irrelevant, 40, q->sigma[l], &q->sweeps[l],
-                        work.as<double>(), wb);
-        if (rc) return rc;
+        if ((rc = mode_svd(c, st, D, N, W[l], thr, irrelevant, ms[l]))) return rc;
+        W[l].reset();
+        q->sigma[l] = ms[l].sigma;
+        q->sweeps[l] = ms[l].sweeps;
+        q->range_k[l] = ms[l].k;
+        q->range_res[l] = std::sqrt(ms[l].res2);
     }
     tm.end();
 
+    // certified truncation: tail(r)^2 = res2 + sum_{a >= r} sigma_a^2 <= thr^2
     q->bound = 0.0;
     for (int l = 0; l < 3; ++l) {
         const auto& sg = q->sigma[l];
-        const int D = (int)sg.size();
-        std::vector<double> tail(D + 1, 0.0);
-        for (int k = D - 1; k >= 0; --k) tail[k] = tail[k + 1] + sg[k] * sg[k];
-        int r = D;
-        for (int k = 1; k <= D; ++k)
+        const int n = (int)sg.size();
+        std::vector<double> tail(n + 1, 0.0);
+        tail[n] = ms[l].res2;
+        for (int k = n - 1; k >= 0; --k) tail[k] = tail[k + 1] + sg[k] * sg[k];
+        int r = n;
+        for (int k = 1; k <= n; ++k)
             if (std::sqrt(tail[k]) <= thr) { r = k; break; }
         r = std::min(r, P.N[l]);
         q->r[l] = r;
@@ -133,22 +261,22 @@ static int run_tucker(Request* q, hipStream_t st, StageTimer& tm) {
     }
     q->bound *= q->norm_xi;
 
-    // Tucker factors Z_l = leading rotated columns / sigma
+    // Tucker factors: the leading r singular vectors (rotated rows / sigma, or unit rows)
     for (int l = 0; l < 3; ++l) {
         const int r = q->r[l], N = P.N[l];
         std::vector<double> inv(r);
         std::vector<int32_t> ord(r);
-        for (int a = 0; a < r; ++a) { inv[a] = 1.0 / q->sigma[l][a]; ord[a] = a; }
+        for (int a = 0; a < r; ++a) { inv[a] = ms[l].unit ? 1.0 : 1.0 / q->sigma[l][a]; ord[a] = a; }
         DevBuf od, iv;
         if ((rc = od.get(c->pool, r * 4))) return rc;
         if ((rc = iv.get(c->pool, r * 8))) return rc;
         if ((rc = q->Z[l].get(c->pool, (size_t)r * N * 8))) return rc;
         LSUM_HIP(hipMemcpyAsync(od.p, ord.data(), r * 4, hipMemcpyHostToDevice, st));
         LSUM_HIP(hipMemcpyAsync(iv.p, inv.data(), r * 8, hipMemcpyHostToDevice, st));
-        launch_gather_scale_rows(st, r, N, W[l].as<double>(), N, od.as<int32_t>(), iv.as<double>(),
-                                 q->Z[l].as<double>(), N);
+        launch_gather_scale_rows(st, r, N, ms[l].rows.as<double>() + ms[l].off, (int)ms[l].ld, od.as<int32_t>(),
+                                 iv.as<double>(), q->Z[l].as<double>(), N);
         LSUM_HIP(hipStreamSynchronize(st));
-        W[l].reset();
+        ms[l].rows.reset();
     }
 
     // (6) projections, stored transposed: Yt_l = cols_l Z_l^T (D_l x r_l, row stride ldy_l), in the

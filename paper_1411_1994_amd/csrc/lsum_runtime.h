@@ -133,6 +133,7 @@ struct Context {
     size_t used = 0;                 // bytes reserved by admitted requests and retained results
     int n_slots = 0;
     int max_batch = 32;              // canonical requests fused into one batch
+    int range_min = 512;             // min(D, N) from which side matrices use the range basis
     std::vector<hipStream_t> streams;
     std::vector<std::thread> workers;
     std::mutex mu;
@@ -183,6 +184,8 @@ struct Request {
     int sweeps[3]{};
     double tails[3]{};
     double norm_A = 0, norm_xi = 0, bound = 0;
+    double range_res[3]{};             // residual outside the range basis per mode (0: direct)
+    int range_k[3]{};                  // size of the range basis per mode (0: direct)
     DevBuf Z[3];                       // r_l x N_l FP64
     DevBuf core;                       // r1 r2 r3, FP64 or FP32 (precision)
     DevBuf tile;

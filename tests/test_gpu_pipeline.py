@@ -200,3 +200,57 @@ def test_invalid_problems_are_rejected(ctx):
         small.submit(good)
     assert e.value.code == -4
     small.close()
+
+
+def _medium_defected(seed=11, eps=1e-2):
+    # side matrices with min(D, N) above 512: D = R * (1 + distinct defect cells per axis); the
+    # loose eps keeps the certified ranks well under the 256-vector range basis
+    # (assert max(range_k) > 0 below)
+    rng = np.random.default_rng(seed)
+    blocks = [W.Block((24, 24, 24), (1.0, 1.0, 1.0), (0.0, 0.0, 0.0))]
+    defects = W.draw_defects(rng, blocks, 40, 30)
+    return W.Problem("med", W.NEWTON, 0.0, 24, (601, 601, 601), 1.0 / 15, blocks, defects, eps=eps)
+
+
+def test_range_basis_svd_matches_direct_jacobi():
+    # the randomized range basis (large side matrices) against the plain one-sided Jacobi on the
+    # same request: same leading singular values, certified bounds, orthonormal factors, and
+    # potentials that agree with each other and with the oracle's direct sum
+    require_gpu()
+    import paper_1411_1994_amd as L
+    p = _medium_defected()
+    out = {}
+    for name, rmin in (("range", 512), ("direct", 0)):
+        with L.Context(0, n_slots=1) as c:
+            c.set_option(L.OPT_RANGE_MIN, rmin)
+            r = c.submit(p)
+            assert r.wait() == 0, r.stats()
+            inf, st = r.info(), r.stats()
+            rng = np.random.default_rng(4)
+            cells = np.stack([rng.integers(0, n, 24) for n in p.N], axis=1)
+            Z, _ = r.tucker()
+            out[name] = dict(inf=inf, st=st, sig=r.sigma(), Z=Z, v=r.sample(cells_xyz(p, cells)), cells=cells)
+            r.release()
+    a, b = out["range"], out["direct"]
+    assert max(a["st"]["range_k"]) > 0 and max(b["st"]["range_k"]) == 0
+    nA = a["inf"].norm_A
+    thr = p.eps * nA / (3 * a["inf"].norm_xi)
+    for o in (a, b):
+        assert o["inf"].bound <= p.eps * nA * (1 + 1e-12)
+        for l in range(3):
+            assert np.max(np.abs(o["Z"][l] @ o["Z"][l].T - np.eye(o["Z"][l].shape[0]))) < 1e-11
+    for l in range(3):
+        res = a["st"]["range_res"][l]
+        assert res <= 0.1 * thr
+        if a["st"]["range_k"][l] == 0:       # this mode took the direct solve
+            assert a["inf"].r[l] == b["inf"].r[l]
+            continue
+        # the basis keeps the leading values; a few more vectors can be needed to absorb res
+        assert b["inf"].r[l] <= a["inf"].r[l] <= b["inf"].r[l] + max(3, b["inf"].r[l] // 50)
+        sa, sb = a["sig"][l], b["sig"][l]
+        big = sb[:len(sa)] > 10 * thr
+        assert np.all(np.abs(sa[big] - sb[:len(sa)][big]) <= 1e-10 * sb[0] + res)
+    # pointwise errors are bounded by the certified Frobenius error eps * ||A||
+    ref = O.brute_force_points(p, a["cells"])
+    assert np.max(np.abs(a["v"] - ref)) <= p.eps * nA
+    assert np.max(np.abs(b["v"] - ref)) <= p.eps * nA

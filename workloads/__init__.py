@@ -187,7 +187,9 @@ def served_request(rng: np.random.Generator, idx: int, L_range=(8, 96), n_choice
     n_vac = int(kinds.sum())
     defects = draw_defects(rng, blocks, n_vac, nd - n_vac)
     eps = float(rng.choice([1e-4, 1e-6]))
-    return Problem(f"serve-{idx}", kind, param, 40, N, h, blocks, defects, eps=eps, precision=FP32)
+    # mixed precision where its arithmetic error (a few 1e-7 relative) is far below eps
+    prec = FP32 if eps >= 1e-4 else FP64
+    return Problem(f"serve-{idx}", kind, param, 40, N, h, blocks, defects, eps=eps, precision=prec)
 
 
 def served_stream(n: int, rate_per_s: float, seed_offset: int = 5, **kw):
