@@ -332,6 +332,12 @@ def main():
     stage, roof = dominant_roofline(prof, dtype)
     if roof is not None:
         roof["traffic"] = traffic_from_profiles(stage)
+    # the shift-sum kernel's own roofline beside the dominant one
+    roof_ss = None
+    if "shift_sum" in prof and prof["shift_sum"]["launches"] > 0:
+        _, roof_ss = dominant_roofline({"shift_sum": prof["shift_sum"]}, dtype)
+        if roof_ss is not None:
+            roof_ss["traffic"] = traffic_from_profiles("shift_sum")
     out = {
         "metric": METRIC,
         "value": served,
@@ -355,6 +361,7 @@ def main():
         "served_over_plain": served / plain,
         "max_rel_err_vs_oracle": rel_err,
         "roofline": roof,
+        "roofline_shift_sum": roof_ss,
         "stages": {k: {"ms_per_launch": v["ms"] / max(1, v["launches"]), "launches": v["launches"]}
                    for k, v in prof.items()},
     }

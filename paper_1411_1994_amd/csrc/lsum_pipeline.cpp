@@ -559,7 +559,7 @@ int run_batch(std::vector<Request*>& reqs, hipStream_t st) {
                 maxN = std::max(maxN, P.N[l]);
                 loads += (double)P.R * P.N[l] * tv.size();
             }
-            out_bytes += (double)(vector_major ? P.R : P.ldt) * sumN * 8;
+            out_bytes += (double)P.R * sumN * 8;   // algorithmic: the R values per cell, not the padding
         }
         if (std::find(distinct.begin(), distinct.end(), q->ref.get()) == distinct.end()) distinct.push_back(q->ref.get());
         q->bytes["canonical"] = (double)nb * P.R * sumN * 8;
@@ -624,8 +624,8 @@ int run_batch(std::vector<Request*>& reqs, hipStream_t st) {
             out_d = od.as<double>();
         }
         const Plan& P = q->plan;
-        // factors read once (point-major rows of ldt values) + points in + values out
-        const double fb = (double)P.blocks.size() * P.ldt * (P.N[0] + P.N[1] + P.N[2]) * 8;
+        // factors read once (R values per cell) + points in + values out
+        const double fb = (double)P.blocks.size() * P.R * (P.N[0] + P.N[1] + P.N[2]) * 8;
         const double sb = (double)n * 32 + (P.tucker() ? 0.0 : fb);
         if (P.tucker()) {
             tm.begin("sample", sb, 0);
