@@ -29,6 +29,10 @@ import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+# One hardware queue per stream: the library runs several slot streams plus three per-mode SVD
+# streams per slot, and HIP's default of 4 queues per process would serialise them.  Must be set
+# before the HIP runtime starts (torch import).
+os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
 
 HBM_PEAK_GBS = 8000.0
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16x3": 2500.0 / 3}

@@ -50,6 +50,16 @@ int lsum_create(lsum_ctx* out, int device, size_t budget, int n_slots) {
         }
         c.streams.push_back(s);
     }
+    // auxiliary streams after the slot streams: HIP spreads streams over its hardware queues in
+    // creation order, so the slots take distinct queues first
+    for (int i = 0; i < 3 * c.n_slots; ++i) {
+        hipStream_t a = nullptr;
+        if (hipStreamCreateWithFlags(&a, hipStreamNonBlocking) != hipSuccess) {
+            delete x;
+            return fail(LSUM_E_DEVICE, "stream creation failed");
+        }
+        c.aux.push_back(a);
+    }
     for (int i = 0; i < c.n_slots; ++i) c.workers.emplace_back(worker, &c, i);
     *out = x;
     return LSUM_OK;
@@ -299,6 +309,7 @@ int lsum_get_stats(lsum_req r, char* buf, size_t len) {
           << "],\"D\":[" << P.D[0] << "," << P.D[1] << "," << P.D[2] << "],\"r\":[" << q.r[0] << "," << q.r[1]
           << "," << q.r[2] << "],\"sweeps\":[" << q.sweeps[0] << "," << q.sweeps[1] << "," << q.sweeps[2]
           << "],\"tails\":[" << q.tails[0] << "," << q.tails[1] << "," << q.tails[2]
+          << "],\"axis_src\":[" << q.axis_src[0] << "," << q.axis_src[1] << "," << q.axis_src[2]
           << "],\"range_k\":[" << q.range_k[0] << "," << q.range_k[1] << "," << q.range_k[2]
           << "],\"range_res\":[" << q.range_res[0] << "," << q.range_res[1] << "," << q.range_res[2]
           << "],\"norm_A\":" << q.norm_A

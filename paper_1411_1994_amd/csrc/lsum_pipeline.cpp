@@ -9,6 +9,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <string>
+#include <thread>
 
 namespace lsum {
 
@@ -50,13 +52,13 @@ static int range_svd(Context* c, hipStream_t st, int D, int N, const double* W, 
     a.C = Yt.p; a.scm = N; a.scn = 1;
     a.alpha = 1.0; a.beta = 0.0; a.batch = 1;
     launch_gemm(st, GEMM_F64, a);
-    Om.reset();
     size_t wb = jacobi_work_bytes(k, N);
     if ((rc = work.get(c->pool, wb))) return rc;
     std::vector<double> sy;
     int sw = 0;
     rc = jacobi_svd(st, k, N, Yt.as<double>(), N, 1e-12, 0.0, 40, sy, &sw, work.as<double>(), wb);
     if (rc) return rc;
+    Om.reset();   // the sketch GEMM has run (jacobi_svd synchronises st)
     int kq = 0;
     while (kq < k && sy[kq] > 1e-12 * sy[0]) ++kq;
     if (kq == 0) return LSUM_OK;
@@ -142,13 +144,13 @@ static int mode_svd(Context* c, hipStream_t st, int D, int N, DevBuf& W, double 
 }
 
 // RHOSVD of one request whose canonical factors are computed (q->U, q->ref ready on st).
-static int run_tucker(Request* q, hipStream_t st, StageTimer& tm) {
+static int run_tucker(Request* q, hipStream_t st, const hipStream_t* aux, StageTimer& tm) {
     Context* c = q->ctx;
     Plan& P = q->plan;
     int rc;
     const double* G = q->ref->G.as<double>();
     // (4) side matrices per mode: lattice sources and defect windows (unnormalised)
-    DevBuf cols[3], W[3], nrm[3], C[3], aux;
+    DevBuf cols[3], W[3], nrm[3], C[3];
     std::vector<double> nrm_h[3];
     const GemmPrec prec = gemm_prec(P.precision);
     tm.begin("columns", (double)(P.D[0] * (size_t)P.N[0] + P.D[1] * (size_t)P.N[1] + P.D[2] * (size_t)P.N[2]) * 8);
@@ -225,17 +227,37 @@ static int run_tucker(Request* q, hipStream_t st, StageTimer& tm) {
     // weighted, normalised side matrices: row j = col_j / |col_j| * sqrt(multiplicity)
     tm.begin("svd");
     ModeSVD ms[3];
-    for (int l = 0; l < 3; ++l) {
+    // the three modes are independent: with auxiliary streams they run concurrently (the block
+    // Jacobi launches are far too small to fill the chip on their own)
+    auto svd_one = [&](int l, hipStream_t s) -> int {
+        int rc1;
         const int D = P.D[l], N = P.N[l];
         std::vector<double> sc(D);
         for (int j = 0; j < D; ++j) sc[j] = std::sqrt((double)P.src_mult[l][j / P.R]) / nrm_h[l][j];
         DevBuf scd;
-        if ((rc = scd.get(c->pool, D * 8))) return rc;
-        if ((rc = W[l].get(c->pool, (size_t)D * N * 8))) return rc;
-        LSUM_HIP(hipMemcpyAsync(scd.p, sc.data(), D * 8, hipMemcpyHostToDevice, st));
-        launch_scale_rows(st, D, N, cols[l].as<double>(), N, scd.as<double>(), W[l].as<double>(), N);
-        if ((rc = mode_svd(c, st, D, N, W[l], thr, irrelevant, ms[l]))) return rc;
+        if ((rc1 = scd.get(c->pool, D * 8))) return rc1;
+        if ((rc1 = W[l].get(c->pool, (size_t)D * N * 8))) return rc1;
+        LSUM_HIP(hipMemcpyAsync(scd.p, sc.data(), D * 8, hipMemcpyHostToDevice, s));
+        launch_scale_rows(s, D, N, cols[l].as<double>(), N, scd.as<double>(), W[l].as<double>(), N);
+        if ((rc1 = mode_svd(c, s, D, N, W[l], thr, irrelevant, ms[l]))) return rc1;
+        LSUM_HIP(hipStreamSynchronize(s));
         W[l].reset();
+        return LSUM_OK;
+    };
+    int mrc[3] = {LSUM_OK, LSUM_OK, LSUM_OK};
+    if (aux) {
+        std::thread th[3];
+        for (int l = 0; l < 3; ++l)
+            th[l] = std::thread([&, l] {
+                (void)hipSetDevice(c->device);
+                mrc[l] = svd_one(l, aux[l]);
+            });
+        for (auto& t : th) t.join();
+    } else {
+        for (int l = 0; l < 3; ++l) mrc[l] = svd_one(l, st);
+    }
+    for (int l = 0; l < 3; ++l) {
+        if (mrc[l]) return fail(mrc[l], "SVD of mode " + std::to_string(l) + " failed");
         q->sigma[l] = ms[l].sigma;
         q->sweeps[l] = ms[l].sweeps;
         q->range_k[l] = ms[l].k;
@@ -497,7 +519,7 @@ int sample_points(Request* q, hipStream_t st, int n, const double* xyz_d, double
 // ------------------------------------------------------------------------------------------
 // a batch of requests (several canonical ones, or one reduction request)
 // ------------------------------------------------------------------------------------------
-int run_batch(std::vector<Request*>& reqs, hipStream_t st) {
+int run_batch(std::vector<Request*>& reqs, hipStream_t st, const hipStream_t* aux) {
     Context* c = reqs[0]->ctx;
     StageTimer tm(st);
     int rc;
@@ -518,18 +540,37 @@ int run_batch(std::vector<Request*>& reqs, hipStream_t st) {
     for (auto* q : reqs) {
         Plan& P = q->plan;
         const int nb = (int)P.blocks.size();
-        const size_t sumN = (size_t)P.N[0] + P.N[1] + P.N[2];
         const bool vector_major = P.tucker();
+        // Axes with the same cell count and the same snapped sites in every block (a cubic lattice
+        // on a cubic grid) have identical factors: they are summed and stored once and shared.
+        size_t uN = 0, uoff = 0, utoff = 0;
         for (int l = 0; l < 3; ++l) {
-            q->U_axis_off[l] = l == 0 ? 0 : q->U_axis_off[l - 1] + (size_t)P.R * P.N[l - 1];
-            q->UT_axis_off[l] = l == 0 ? 0 : q->UT_axis_off[l - 1] + (size_t)P.ldt * P.N[l - 1];
+            int src = l;
+            for (int k = 0; k < l && src == l; ++k) {
+                if (q->axis_src[k] != k || P.N[k] != P.N[l]) continue;
+                bool same = true;
+                for (int b = 0; b < nb && same; ++b) same = P.offs[k][b] == P.offs[l][b];
+                if (same) src = k;
+            }
+            q->axis_src[l] = src;
+            if (src == l) {
+                q->U_axis_off[l] = uoff;
+                q->UT_axis_off[l] = utoff;
+                uoff += (size_t)P.R * P.N[l];
+                utoff += (size_t)P.ldt * P.N[l];
+                uN += P.N[l];
+            } else {
+                q->U_axis_off[l] = q->U_axis_off[src];
+                q->UT_axis_off[l] = q->UT_axis_off[src];
+            }
         }
         q->U.resize(nb);
         q->UT.resize(nb);
         for (int b = 0; b < nb; ++b) {
             DevBuf& out = vector_major ? q->U[b] : q->UT[b];
-            if ((rc = out.get(c->pool, (size_t)(vector_major ? P.R : P.ldt) * sumN * 8))) return rc;
+            if ((rc = out.get(c->pool, (size_t)(vector_major ? P.R : P.ldt) * uN * 8))) return rc;
             for (int l = 0; l < 3; ++l) {
+                if (q->axis_src[l] != l) continue;
                 const auto& sites = P.offs[l][b];
                 int stride = 0, n_hi = 0;
                 bool two = false;
@@ -559,10 +600,10 @@ int run_batch(std::vector<Request*>& reqs, hipStream_t st) {
                 maxN = std::max(maxN, P.N[l]);
                 loads += (double)P.R * P.N[l] * tv.size();
             }
-            out_bytes += (double)P.R * sumN * 8;   // algorithmic: the R values per cell, not the padding
+            out_bytes += (double)P.R * uN * 8;   // algorithmic: the R values per distinct cell, no padding
         }
         if (std::find(distinct.begin(), distinct.end(), q->ref.get()) == distinct.end()) distinct.push_back(q->ref.get());
-        q->bytes["canonical"] = (double)nb * P.R * sumN * 8;
+        q->bytes["canonical"] = (double)nb * P.R * uN * 8;
     }
     double ref_bytes = 0;
     for (auto* e : distinct) ref_bytes += (double)e->R * (2 * e->N_ref - 1) * 8;
@@ -599,7 +640,7 @@ int run_batch(std::vector<Request*>& reqs, hipStream_t st) {
     // (4)-(8) reduction requests
     for (auto* q : reqs) {
         if (!q->plan.tucker()) continue;
-        rc = run_tucker(q, st, tm);
+        rc = run_tucker(q, st, aux, tm);
         if (rc) {
             (void)hipStreamSynchronize(st);
             (void)hipGetLastError();
@@ -624,8 +665,11 @@ int run_batch(std::vector<Request*>& reqs, hipStream_t st) {
             out_d = od.as<double>();
         }
         const Plan& P = q->plan;
-        // factors read once (R values per cell) + points in + values out
-        const double fb = (double)P.blocks.size() * P.R * (P.N[0] + P.N[1] + P.N[2]) * 8;
+        // factors read once (R values per distinct cell) + points in + values out
+        double uN = 0;
+        for (int l = 0; l < 3; ++l)
+            if (q->axis_src[l] == l) uN += P.N[l];
+        const double fb = (double)P.blocks.size() * P.R * uN * 8;
         const double sb = (double)n * 32 + (P.tucker() ? 0.0 : fb);
         if (P.tucker()) {
             tm.begin("sample", sb, 0);

@@ -80,9 +80,11 @@ void DevPool::trim_locked() {
 Context::~Context() {
     (void)hipSetDevice(device);
     for (auto s : streams) (void)hipStreamSynchronize(s);
+    for (auto s : aux) (void)hipStreamSynchronize(s);
     if (own_stream) (void)hipStreamSynchronize(own_stream);
     refs.clear();
     for (auto s : streams) (void)hipStreamDestroy(s);
+    for (auto s : aux) (void)hipStreamDestroy(s);
     if (own_stream) (void)hipStreamDestroy(own_stream);
     delete pool;
 }
@@ -338,7 +340,7 @@ void worker(Context* c, int slot) {
         }
         int rc;
         try {
-            rc = run_batch(batch, st);
+            rc = run_batch(batch, st, c->aux.size() >= 3 * (size_t)(slot + 1) ? &c->aux[3 * slot] : nullptr);
         } catch (const std::exception& ex) {
             rc = fail(LSUM_E_DEVICE, std::string("exception: ") + ex.what());
         }

@@ -135,6 +135,7 @@ struct Context {
     int max_batch = 32;              // canonical requests fused into one batch
     int range_min = 512;             // min(D, N) from which side matrices use the range basis
     std::vector<hipStream_t> streams;
+    std::vector<hipStream_t> aux;    // three per slot: the per-mode SVDs of a request run concurrently
     std::vector<std::thread> workers;
     std::mutex mu;
     std::condition_variable cv;
@@ -177,6 +178,7 @@ struct Request {
     std::vector<DevBuf> U, UT;
     size_t U_axis_off[3]{};           // element offsets of the axes in U (R x N_l each)
     size_t UT_axis_off[3]{};          // element offsets of the axes in UT (N_l x ldt each)
+    int axis_src[3]{0, 1, 2};         // axis whose factors this axis shares (itself if distinct)
     DevBuf def_cells, def_scale;       // defects for sampling (n_def x 3, n_def)
     // Tucker
     int r[3]{};
@@ -226,7 +228,8 @@ size_t retained_bytes(const Request* q);
 void worker(Context* c, int slot);
 
 // pipeline stages (lsum_pipeline.cpp)
-int run_batch(std::vector<Request*>& reqs, hipStream_t st);
+// aux: three streams for the concurrent per-mode SVDs (nullptr: everything on st)
+int run_batch(std::vector<Request*>& reqs, hipStream_t st, const hipStream_t* aux = nullptr);
 // kt (canonical requests only): kernel-bound timing of the sampling kernels
 int sample_points(Request* q, hipStream_t st, int n, const double* xyz_dev, double* out_dev,
                   const KTime* kt = nullptr);

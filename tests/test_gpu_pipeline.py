@@ -254,3 +254,20 @@ def test_range_basis_svd_matches_direct_jacobi():
     ref = O.brute_force_points(p, a["cells"])
     assert np.max(np.abs(a["v"] - ref)) <= p.eps * nA
     assert np.max(np.abs(b["v"] - ref)) <= p.eps * nA
+
+
+@pytest.mark.parametrize("L,N,src", [((4, 4, 4), (65, 65, 65), [0, 0, 0]),
+                                     ((4, 4, 5), (65, 65, 67), [0, 0, 2]),
+                                     ((3, 4, 3), (65, 65, 65), [0, 1, 0])])
+def test_identical_axes_share_factors(ctx, L, N, src):
+    # axes with the same cell count and snapped sites are summed once and shared; every axis's
+    # factors still equal the oracle's assembled sums
+    blocks = [W.Block(L, (1.0, 1.0, 1.0), (0.0, 0.0, 0.0))]
+    p = W.Problem("ax", W.NEWTON, 0.0, 20, N, 0.25, blocks)
+    r = run(ctx, p)
+    assert r.stats()["axis_src"] == src
+    got = r.canonical(0)
+    ref = O.assembled_canonical(p)[0]
+    for a in range(3):
+        assert np.max(np.abs(got[a] - ref[a])) <= 1e-13 * np.max(np.abs(ref[a]))
+    r.release()
