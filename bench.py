@@ -325,6 +325,30 @@ def main():
     plain = psteps / psecs
     pctx.close()
 
+    # ---- the shift-sum over one batched launch of >= 1000 jobs (submitted together) ------
+    ss_batched = None
+    if cfg == 2:
+        bctx = L.Context(0, n_slots=1)
+        bctx.set_option(L.OPT_MAX_BATCH, 1024)
+        reqs = bctx.submit_many([prepared] * 8)               # warm the reference and window cache
+        for r in reqs:
+            r.wait()
+            r.release()
+        bctx.reset_profile()
+        reqs = bctx.submit_many([prepared] * 1024)
+        for r in reqs:
+            if r.wait() != 0:
+                raise RuntimeError("batched shift-sum request failed")
+        jobs = sum(1 for l in range(3) if reqs[0].stats()["axis_src"][l] == l) * len(reqs)
+        for r in reqs:
+            r.release()
+        bprof = bctx.profile()
+        bctx.close()
+        _, ss_batched = dominant_roofline({"shift_sum": bprof["shift_sum"]}, "f64")
+        if ss_batched is not None:
+            ss_batched["jobs_per_launch"] = jobs / max(1, bprof["shift_sum"]["launches"])
+            ss_batched["traffic"] = None
+
     # ---- accuracy of the served result against the oracle's brute-force sum ------------
     vals = outs[(steps - 1) % len(outs)].cpu().numpy()
     sel = np.random.default_rng(7).choice(n_pts, 12, replace=False)
@@ -366,6 +390,7 @@ def main():
         "max_rel_err_vs_oracle": rel_err,
         "roofline": roof,
         "roofline_shift_sum": roof_ss,
+        "roofline_shift_sum_batched": ss_batched,
         "stages": {k: {"ms_per_launch": v["ms"] / max(1, v["launches"]), "launches": v["launches"]}
                    for k, v in prof.items()},
     }

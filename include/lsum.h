@@ -209,6 +209,11 @@ int lsum_contract(lsum_ctx ctx, void* stream, int prec, int m, int n, int k, con
  * admitted when its planned HBM footprint fits the free budget (LSUM_E_NOMEM if it can never
  * fit).  Requests run concurrently on the context's slots. */
 int lsum_submit(lsum_ctx ctx, const lsum_problem* p, int nonblocking, lsum_req* req);
+/* Submit n problems p[0..n-1] at once (req[i] receives request i).  All are validated first
+ * (on any error none is queued and the error of the first bad problem is returned); they enter
+ * the queue together, so a slot can fuse consecutive canonical ones into one batch of up to
+ * LSUM_OPT_MAX_BATCH requests (one shift-sum launch). */
+int lsum_submit_many(lsum_ctx ctx, int n, const lsum_problem* p, int nonblocking, lsum_req* req);
 /* Wait up to timeout_ms (< 0: forever); returns the request's final status or LSUM_E_TIMEOUT. */
 int lsum_wait(lsum_req req, int timeout_ms);
 /* Cancel a request that has not started (LSUM_E_STATE once it runs). */

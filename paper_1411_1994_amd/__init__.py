@@ -27,7 +27,7 @@ FP64, FP32, BF16X3 = 0, 1, 2
 SYMBOLS = ["lsum_nodes", "lsum_block_offsets", "lsum_create", "lsum_destroy", "lsum_last_error",
            "lsum_collocate", "lsum_shift_sum", "lsum_sample_canonical", "lsum_jacobi_svd",
            "lsum_contract",
-           "lsum_submit", "lsum_wait", "lsum_cancel", "lsum_get_info", "lsum_get_canonical",
+           "lsum_submit", "lsum_submit_many", "lsum_wait", "lsum_cancel", "lsum_get_info", "lsum_get_canonical",
            "lsum_get_tucker", "lsum_get_sigma", "lsum_sample", "lsum_get_tile", "lsum_get_stats",
            "lsum_release", "lsum_set_option", "lsum_get_profile", "lsum_reset_profile"]
 OPT_MAX_BATCH, OPT_REF_CACHE_BYTES, OPT_RANGE_MIN = 1, 2, 3
@@ -95,6 +95,7 @@ def _load():
         "lsum_contract": (I, [VP, VP, I, I, I, I, VP, C.c_long, C.c_long, VP, C.c_long, C.c_long, VP,
                               C.c_long, C.c_long, D, D]),
         "lsum_submit": (I, [VP, P(lsum_problem), I, P(VP)]),
+        "lsum_submit_many": (I, [VP, I, P(lsum_problem), I, P(VP)]),
         "lsum_wait": (I, [VP, I]),
         "lsum_cancel": (I, [VP]),
         "lsum_get_info": (I, [VP, P(lsum_info)]),
@@ -260,6 +261,33 @@ class Context:
         """Submit a problem; optional sample points (n x 3) and an output array (n) -- numpy arrays
         (host) or device tensors -- are evaluated as part of the request."""
         return Request(self, problem, nonblocking, points, values)
+
+    def submit_many(self, problems, nonblocking: bool = False) -> list:
+        """Submit several problems at once (no sample points); they enter the queue together, so a
+        slot fuses consecutive canonical ones into one batch."""
+        structs, keeps = [], []
+        for p in problems:
+            if isinstance(p, Prepared):
+                structs.append(p.struct)
+                keeps.append(p)
+            else:
+                st, kp = make_problem(p)
+                structs.append(st)
+                keeps.append(kp)
+        n = len(structs)
+        arr = (lsum_problem * n)(*structs)
+        handles = (C.c_void_p * n)()
+        _check(_lib.lsum_submit_many(self.handle, n, arr, 1 if nonblocking else 0, handles))
+        out = []
+        for i, p in enumerate(problems):
+            r = Request.__new__(Request)
+            r.ctx = self
+            r.problem = p.problem if isinstance(p, Prepared) else p
+            r._keep = [keeps[i]]
+            r.values = None
+            r.handle = C.c_void_p(handles[i])
+            out.append(r)
+        return out
 
 
 class Prepared:

@@ -80,8 +80,8 @@ int lsum_destroy(lsum_ctx x) {
     return LSUM_OK;
 }
 
-int lsum_submit(lsum_ctx x, const lsum_problem* p, int nonblocking, lsum_req* out) {
-    if (!x || !p || !out) return fail(LSUM_E_INVALID, "null argument");
+// a validated, planned request that is not queued yet
+static int prepare_request(lsum_ctx x, const lsum_problem* p, lsum_req_s** out) {
     auto* r = new lsum_req_s();
     Request& q = r->q;
     q.ctx_ref = x->sp;
@@ -100,28 +100,47 @@ int lsum_submit(lsum_ctx x, const lsum_problem* p, int nonblocking, lsum_req* ou
     q.values = p->values;
     q.points_on_device = p->points_on_device;
     q.reserved = q.plan.planned_bytes() + (q.points_on_device ? 0 : (size_t)q.n_points * 32);
-    Context& c = x->c;
-    if (q.reserved > c.budget) {
+    if (q.reserved > x->c.budget) {
         delete r;
         return fail(LSUM_E_NOMEM, "the request can never fit the HBM budget");
     }
+    *out = r;
+    return LSUM_OK;
+}
+
+int lsum_submit(lsum_ctx x, const lsum_problem* p, int nonblocking, lsum_req* out) {
+    return lsum_submit_many(x, 1, p, nonblocking, out);
+}
+
+int lsum_submit_many(lsum_ctx x, int n, const lsum_problem* p, int nonblocking, lsum_req* out) {
+    if (!x || (n > 0 && (!p || !out)) || n < 0) return fail(LSUM_E_INVALID, "null argument");
+    std::vector<lsum_req_s*> rs(n, nullptr);
+    for (int i = 0; i < n; ++i) {
+        const int rc = prepare_request(x, p + i, &rs[i]);
+        if (rc != LSUM_OK) {
+            for (int k = 0; k < i; ++k) delete rs[k];
+            return rc;
+        }
+    }
+    Context& c = x->c;
     {
         std::lock_guard<std::mutex> lk(c.mu);
         if (c.stopping) {
-            delete r;
+            for (auto* r : rs) delete r;
             return fail(LSUM_E_STATE, "context is shutting down");
         }
-        if (c.queue.size() >= c.max_queue) {
-            if (nonblocking) {
-                delete r;
-                return fail(LSUM_E_BUSY, "queue full");
-            }
+        if (nonblocking && c.queue.size() + n > c.max_queue) {
+            for (auto* r : rs) delete r;
+            return fail(LSUM_E_BUSY, "queue full");
         }
-        q.t_submit = Clock::now();
-        c.queue.push_back(&q);
+        const auto now = Clock::now();
+        for (auto* r : rs) {
+            r->q.t_submit = now;
+            c.queue.push_back(&r->q);
+        }
     }
     c.cv.notify_all();
-    *out = r;
+    for (int i = 0; i < n; ++i) out[i] = rs[i];
     return LSUM_OK;
 }
 

@@ -118,3 +118,32 @@ def test_cancel_and_release_of_queued_requests():
         assert cancelled >= 1
         for r in reqs:
             r.release()
+
+
+def test_submit_many_fuses_one_batch_and_matches_single_submits():
+    require_gpu()
+    import paper_1411_1994_amd as L
+    probs = mixed_problems(10, seed=21)
+    singles = []
+    with L.Context(0, n_slots=1) as c:
+        c.set_option(L.OPT_MAX_BATCH, 1)
+        for p in probs:
+            r = c.submit(p)
+            assert r.wait() == 0
+            singles.append([r.canonical(0), r.stats()["batch"]])
+            r.release()
+    with L.Context(0, n_slots=1) as c:
+        c.set_option(L.OPT_MAX_BATCH, 64)
+        reqs = c.submit_many(probs)
+        for r, (U, _) in zip(reqs, singles):
+            assert r.wait() == 0
+            assert r.stats()["batch"] == len(probs)            # the whole set ran as one batch
+            got = r.canonical(0)
+            assert all(np.array_equal(a, b) for a, b in zip(got, U))
+            r.release()
+        assert c.profile()["shift_sum"]["launches"] == 1
+        # an invalid problem anywhere rejects the whole set and queues nothing
+        bad = W.Problem(**{**probs[0].__dict__, "N": (20, 21, 21)})
+        with pytest.raises(L.LsumError):
+            c.submit_many([probs[1], bad, probs[2]])
+        assert c.profile()["shift_sum"]["launches"] == 1
