@@ -1,22 +1,23 @@
 // MFMA contraction kernels (gfx950): the dense steps of the RHOSVD and Tucker evaluation.
 //
-//  * k_gemm: strided GEMM C = alpha A B + beta C on v_mfma_f64_16x16x4 (FP64),
-//    v_mfma_f32_16x16x4 (FP32) or split-BF16x3 on v_mfma_f32_16x16x32_bf16 (x = hi + lo,
-//    hi*hi + hi*lo + lo*hi).  The FP32 and BF16x3 variants accumulate in FP32 inside each
-//    k-tile (16 or 32 terms) and add the tile's partial sums into FP64 registers, so the
-//    accumulation error stays near 2^-24 sqrt(16) instead of growing like 2^-24 sqrt(K).  Used for the side-matrix column Grams,
-//    the projections Z^T A (Appendix theorem (c)) and the mode products of eq.
-//    Tucker_singePot.
+//  * k_gemm: strided GEMM C = alpha A B + beta C (column Grams, the projections of Appendix
+//    theorem (c), the mode products of eq. Tucker_singePot, Tucker values at points);
 //  * k_core: the RHOSVD core mu = sum_nu xi_nu y1_nu (x) y2_nu (x) y3_nu (eq. C-core) as a GEMM
 //    whose left operand, the Khatri-Rao product of the mode-1 and mode-2 projections, is formed
-//    on the fly from LDS so it never touches HBM.
-//  * k_cp_norm2: ||A||_F^2 of the canonical sum from the column Grams (used by the truncation
-//    rule).
+//    on the fly in LDS so it never touches HBM;
+//  * k_cp_norm2: ||A||_F^2 of the canonical sum from the column Grams (truncation rule).
 //
-// MFMA operand layout (16x16xK, wave64): lane l supplies A[row l%16][k-group l/16] and
-// B[k-group l/16][col l%16]; the 16x16 result sits in lane l, register v at column l%16 and
-// row 4*(l/16)+v for the FP32-output instructions but row l/16+4*v for the FP64 one.
-// Tiles: 64x64 per workgroup (4 waves in 2x2, each 32x32 = 2x2 MFMA blocks).
+// Both GEMM-shaped kernels use 128 x 64 workgroup tiles with 32 rows per wave:
+// v_mfma_f32_32x32x2f32 (FP32), v_mfma_f32_32x32x16_bf16 three times (split BF16x3: x = hi +
+// lo, hi*hi + hi*lo + lo*hi) or v_mfma_f64_16x16x4f64 (FP64).  FP32 and BF16x3 partial sums are
+// added into FP64 registers every chunk of 32 (GEMM) or 64 (core) terms, so the summation error stays near the
+// operand rounding instead of growing with the contraction length.
+//
+// MFMA lane layouts: 16x16x4 (f64) takes A[row lane%16][k lane/16], B[k lane/16][col lane%16]
+// and leaves row lane/16 + 4v, column lane%16 in register v.  32x32x2 (f32) takes A[row
+// lane%32][k lane/32] and leaves row 8(v/4) + 4(lane/32) + v%4, column lane%32 in register v;
+// 32x32x16 (bf16) takes 8 consecutive k per lane, k = 8(lane/32) + e, with the same output
+// layout.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -31,166 +32,186 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
-template <int P> struct GT;
-template <> struct GT<GEMM_F64> { using T = double; using Acc = d4; static constexpr int BK = 16; };
-template <> struct GT<GEMM_F32> { using T = float; using Acc = f4; static constexpr int BK = 16; };
-template <> struct GT<GEMM_BF16X3> { using T = float; using Acc = f4; static constexpr int BK = 32; };
+// --------------------------------------------------------------------------------------------
+// General strided GEMM, C = alpha A B + beta C, on a 128 x 64 workgroup tile: wave w owns rows
+// 32w..32w+31 and the 64 columns, multiplied in chunks of GK terms staged in LDS.
+//   FP32:   v_mfma_f32_32x32x2f32, FP32 sums within the chunk, FP64 across chunks;
+//   BF16X3: v_mfma_f32_32x32x16_bf16 on hi*hi + hi*lo + lo*hi (operands split when staged);
+//   FP64:   v_mfma_f64_16x16x4f64 throughout.
+// Operands are read with the element strides given (threads walk the unit-stride direction when
+// there is one, so loads coalesce), and the next chunk is fetched into registers while the
+// current one is multiplied.
+// --------------------------------------------------------------------------------------------
+constexpr int GBM = 128, GBN = 64;
+template <int P> struct GemmCfg;
+template <> struct GemmCfg<GEMM_F32> { using T = float; static constexpr int GK = 32; };
+template <> struct GemmCfg<GEMM_BF16X3> { using T = float; static constexpr int GK = 32; };
+template <> struct GemmCfg<GEMM_F64> { using T = double; static constexpr int GK = 16; };
 
-constexpr int BM = 64, BN = 64;
+typedef float f16v_g __attribute__((ext_vector_type(16)));
 
-// row of the 16x16 MFMA result held by lane `lane`, accumulator register v
-template <int P>
-__device__ __forceinline__ int acc_row(int lane, int v) {
-    if constexpr (P == GEMM_F64) return (lane >> 4) + 4 * v;
-    else return 4 * (lane >> 4) + v;
-}
-
-// FP64 partial sums of the FP32-accumulating variants
-struct Acc64 {
-    double v[2][2][4];
-};
-
-template <int P>
-__device__ __forceinline__ void flush(typename GT<P>::Acc (&acc)[2][2], Acc64& a64) {
-    if constexpr (P != GEMM_F64) {
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int j = 0; j < 2; ++j) {
-#pragma unroll
-                for (int v = 0; v < 4; ++v) a64.v[i][j][v] += (double)acc[i][j][v];
-                acc[i][j] = typename GT<P>::Acc{0, 0, 0, 0};
-            }
-    }
-}
-
-template <int P>
-__device__ __forceinline__ double result(const typename GT<P>::Acc (&acc)[2][2], const Acc64& a64, int i,
-                                         int j, int v) {
-    if constexpr (P == GEMM_F64) return acc[i][j][v];
-    else return a64.v[i][j][v];
-}
-
-// One k-chunk of MFMAs over the LDS tiles As[k][m], Bs[k][n] for this wave's 32x32 block.
-template <int P>
-__device__ __forceinline__ void mfma_chunk(const typename GT<P>::T (*As)[BM + 1],
-                                           const typename GT<P>::T (*Bs)[BN + 1], int wm, int wn,
-                                           int lane, typename GT<P>::Acc (&acc)[2][2]) {
-    constexpr int BK = GT<P>::BK;
-    const int r = lane & 15, kg = lane >> 4;
-    if constexpr (P == GEMM_F64) {
-#pragma unroll
-        for (int kk = 0; kk < BK; kk += 4) {
-            double a[2], b[2];
-#pragma unroll
-            for (int i = 0; i < 2; ++i) a[i] = As[kk + kg][wm + i * 16 + r];
-#pragma unroll
-            for (int j = 0; j < 2; ++j) b[j] = Bs[kk + kg][wn + j * 16 + r];
-#pragma unroll
-            for (int i = 0; i < 2; ++i)
-#pragma unroll
-                for (int j = 0; j < 2; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
-        }
-    } else if constexpr (P == GEMM_F32) {
-#pragma unroll
-        for (int kk = 0; kk < BK; kk += 4) {
-            float a[2], b[2];
-#pragma unroll
-            for (int i = 0; i < 2; ++i) a[i] = As[kk + kg][wm + i * 16 + r];
-#pragma unroll
-            for (int j = 0; j < 2; ++j) b[j] = Bs[kk + kg][wn + j * 16 + r];
-#pragma unroll
-            for (int i = 0; i < 2; ++i)
-#pragma unroll
-                for (int j = 0; j < 2; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
-        }
-    } else {
-        bf8 ahi[2], alo[2], bhi[2], blo[2];
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const float x = As[kg * 8 + e][wm + i * 16 + r];
-                const __bf16 hx = (__bf16)x;
-                ahi[i][e] = hx;
-                alo[i][e] = (__bf16)(x - (float)hx);
-            }
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const float x = Bs[kg * 8 + e][wn + j * 16 + r];
-                const __bf16 hx = (__bf16)x;
-                bhi[j][e] = hx;
-                blo[j][e] = (__bf16)(x - (float)hx);
-            }
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[i], bhi[j], acc[i][j], 0, 0, 0);
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[i], blo[j], acc[i][j], 0, 0, 0);
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[i], bhi[j], acc[i][j], 0, 0, 0);
-            }
-    }
-}
+__device__ __forceinline__ int row32g(int lane, int v) { return (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3); }
 
 template <int P>
 __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
-    using T = typename GT<P>::T;
-    using Acc = typename GT<P>::Acc;
-    constexpr int BK = GT<P>::BK;
-    __shared__ T As[BK][BM + 1];
-    __shared__ T Bs[BK][BN + 1];
+    using T = typename GemmCfg<P>::T;
+    constexpr int GK = GemmCfg<P>::GK;
+    constexpr bool BF = (P == GEMM_BF16X3);
+    constexpr int KPAD = 8;
+    __shared__ __attribute__((aligned(16))) T As[BF ? 1 : GK][BF ? 1 : GBM + 4];
+    __shared__ __attribute__((aligned(16))) T Bs[BF ? 1 : GK][BF ? 1 : GBN + 4];
+    __shared__ __attribute__((aligned(16))) __bf16 Ahi[BF ? GBM : 1][BF ? GK + KPAD : 1];
+    __shared__ __attribute__((aligned(16))) __bf16 Alo[BF ? GBM : 1][BF ? GK + KPAD : 1];
+    __shared__ __attribute__((aligned(16))) __bf16 Bhi[BF ? GBN : 1][BF ? GK + KPAD : 1];
+    __shared__ __attribute__((aligned(16))) __bf16 Blo[BF ? GBN : 1][BF ? GK + KPAD : 1];
     const long bz = blockIdx.z;
     const T* __restrict__ A = (const T*)g.A + bz * g.bA;
     const T* __restrict__ B = (const T*)g.B + bz * g.bB;
     T* __restrict__ C = (T*)g.C + bz * g.bC;
-    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+    const int m0 = blockIdx.y * GBM, n0 = blockIdx.x * GBN;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-    Acc acc[2][2];
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = Acc{0, 0, 0, 0};
-    Acc64 a64{};
+    const int wm = wave * 32;
     const bool a_kfast = (g.sak == 1);
     const bool b_nfast = (g.sbn == 1);
-    for (int k0 = 0; k0 < g.k; k0 += BK) {
-        for (int e = tid; e < BM * BK; e += 256) {
-            int mm, kk;
-            if (a_kfast) { kk = e % BK; mm = e / BK; } else { mm = e % BM; kk = e / BM; }
-            const int gm = m0 + mm, gk = k0 + kk;
-            As[kk][mm] = (gm < g.m && gk < g.k) ? A[(long)gm * g.sam + (long)gk * g.sak] : T(0);
+    constexpr int NA = GBM * GK / 256, NB = GBN * GK / 256;   // staged elements per thread
+    // Each thread keeps one position along the unit-stride direction and steps along the other:
+    // element t of A is (mA + t * dmA, kA + t * dkA), of B (kB + t * dkB, nB + t * dnB).
+    const int mA = a_kfast ? tid / GK : tid % GBM, kA = a_kfast ? tid % GK : tid / GBM;
+    const int dmA = a_kfast ? 256 / GK : 0, dkA = a_kfast ? 0 : 256 / GBM;
+    const int nB = b_nfast ? tid % GBN : tid / GK, kB = b_nfast ? tid / GBN : tid % GK;
+    const int dnB = b_nfast ? 0 : 256 / GK, dkB = b_nfast ? 256 / GBN : 0;
+    const long stepA = (long)dmA * g.sam + (long)dkA * g.sak;
+    const long stepB = (long)dkB * g.sbk + (long)dnB * g.sbn;
+    T pa[NA], pb[NB];
+    auto fetch = [&](int k0) {
+        const T* a = A + (long)(m0 + mA) * g.sam + (long)(k0 + kA) * g.sak;
+#pragma unroll
+        for (int t = 0; t < NA; ++t) {
+            const bool ok = m0 + mA + t * dmA < g.m && k0 + kA + t * dkA < g.k;
+            pa[t] = ok ? a[t * stepA] : T(0);
         }
-        for (int e = tid; e < BN * BK; e += 256) {
-            int nn, kk;
-            if (b_nfast) { nn = e % BN; kk = e / BN; } else { kk = e % BK; nn = e / BK; }
-            const int gn = n0 + nn, gk = k0 + kk;
-            Bs[kk][nn] = (gn < g.n && gk < g.k) ? B[(long)gk * g.sbk + (long)gn * g.sbn] : T(0);
+        const T* b = B + (long)(k0 + kB) * g.sbk + (long)(n0 + nB) * g.sbn;
+#pragma unroll
+        for (int t = 0; t < NB; ++t) {
+            const bool ok = n0 + nB + t * dnB < g.n && k0 + kB + t * dkB < g.k;
+            pb[t] = ok ? b[t * stepB] : T(0);
+        }
+    };
+    f16v_g acc[2];
+    double acc64[2][16];
+    d4 accd[2][4];
+    if constexpr (P == GEMM_F64) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) accd[i][j] = d4{0, 0, 0, 0};
+    } else {
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            acc[j] = f16v_g{};
+#pragma unroll
+            for (int v = 0; v < 16; ++v) acc64[j][v] = 0.0;
+        }
+    }
+    fetch(0);
+    for (int k0 = 0; k0 < g.k; k0 += GK) {
+#pragma unroll
+        for (int t = 0; t < NA; ++t) {
+            const int mm = mA + t * dmA, kk = kA + t * dkA;
+            if constexpr (BF) {
+                const float x = pa[t];
+                const __bf16 hx = (__bf16)x;
+                Ahi[mm][kk] = hx;
+                Alo[mm][kk] = (__bf16)(x - (float)hx);
+            } else {
+                As[kk][mm] = pa[t];
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < NB; ++t) {
+            const int nn = nB + t * dnB, kk = kB + t * dkB;
+            if constexpr (BF) {
+                const float x = pb[t];
+                const __bf16 hx = (__bf16)x;
+                Bhi[nn][kk] = hx;
+                Blo[nn][kk] = (__bf16)(x - (float)hx);
+            } else {
+                Bs[kk][nn] = pb[t];
+            }
         }
         __syncthreads();
-        mfma_chunk<P>(As, Bs, wm, wn, lane, acc);
-        flush<P>(acc, a64);
+        if (k0 + GK < g.k) fetch(k0 + GK);
+        if constexpr (P == GEMM_F32) {
+#pragma unroll
+            for (int kk = 0; kk < GK; kk += 2) {
+                const float a = As[kk + (lane >> 5)][wm + (lane & 31)];
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, Bs[kk + (lane >> 5)][32 * j + (lane & 31)], acc[j],
+                                                                  0, 0, 0);
+            }
+        } else if constexpr (BF) {
+#pragma unroll
+            for (int kk = 0; kk < GK; kk += 16) {
+                const int ko = kk + 8 * (lane >> 5);
+                const bf8 ah = *(const bf8*)&Ahi[wm + (lane & 31)][ko];
+                const bf8 al = *(const bf8*)&Alo[wm + (lane & 31)][ko];
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const bf8 bh = *(const bf8*)&Bhi[32 * j + (lane & 31)][ko];
+                    const bf8 bl = *(const bf8*)&Blo[32 * j + (lane & 31)][ko];
+                    acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc[j], 0, 0, 0);
+                    acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc[j], 0, 0, 0);
+                    acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc[j], 0, 0, 0);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int kk = 0; kk < GK; kk += 4) {
+                double a[2], b[4];
+#pragma unroll
+                for (int i = 0; i < 2; ++i) a[i] = As[kk + (lane >> 4)][wm + 16 * i + (lane & 15)];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) b[j] = Bs[kk + (lane >> 4)][16 * j + (lane & 15)];
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        accd[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], accd[i][j], 0, 0, 0);
+            }
+        }
+        if constexpr (P != GEMM_F64) {
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+#pragma unroll
+                for (int v = 0; v < 16; ++v) acc64[j][v] += (double)acc[j][v];
+                acc[j] = f16v_g{};
+            }
+        }
         __syncthreads();
     }
+    auto store = [&](int row, int col, double val) {
+        if (row < g.m && col < g.n) {
+            T* c = C + (long)row * g.scm + (long)col * g.scn;
+            const double v = g.alpha * val;
+            *c = (T)((g.beta != 0.0) ? v + g.beta * (double)*c : v);
+        }
+    };
+    if constexpr (P == GEMM_F64) {
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    store(m0 + wm + 16 * i + (lane >> 4) + 4 * v, n0 + 16 * j + (lane & 15), accd[i][j][v]);
+    } else {
 #pragma unroll
         for (int j = 0; j < 2; ++j)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int row = m0 + wm + i * 16 + acc_row<P>(lane, v);
-                const int col = n0 + wn + j * 16 + (lane & 15);
-                if (row < g.m && col < g.n) {
-                    T* c = C + (long)row * g.scm + (long)col * g.scn;
-                    const double val = g.alpha * result<P>(acc, a64, i, j, v);
-                    *c = (T)((g.beta != 0.0) ? val + g.beta * (double)*c : val);
-                }
-            }
+            for (int v = 0; v < 16; ++v)
+                store(m0 + wm + row32g(lane, v), n0 + 32 * j + (lane & 31), acc64[j][v]);
+    }
 }
 
 // --------------------------------------------------------------------------------------------
@@ -486,7 +507,7 @@ inline unsigned cdiv(long a, long b) { return (unsigned)((a + b - 1) / b); }
 
 void launch_gemm(hipStream_t st, GemmPrec prec, const GemmArgs& a) {
     if (a.m <= 0 || a.n <= 0 || a.batch <= 0) return;
-    dim3 grid(cdiv(a.n, BN), cdiv(a.m, BM), a.batch);
+    dim3 grid(cdiv(a.n, GBN), cdiv(a.m, GBM), a.batch);
     switch (prec) {
         case GEMM_F64: hipLaunchKernelGGL(k_gemm<GEMM_F64>, grid, dim3(256), 0, st, a); break;
         case GEMM_F32: hipLaunchKernelGGL(k_gemm<GEMM_F32>, grid, dim3(256), 0, st, a); break;
