@@ -273,6 +273,33 @@ def run_mix(args):
     print(json.dumps(out))
 
 
+def per_precision(L, W, problem, xyz):
+    """The reduction request in FP64, FP32 and split-BF16x3: MFMA rate of the core and of the
+    tile's mode products (event-timed stage time, algorithmic flops), and each result's deviation
+    from the FP64 one (the tile if the request has one, else the values at the sample points)."""
+    res, ref = {}, None
+    for name, prec in (("f64", W.FP64), ("f32", W.FP32), ("bf16x3", W.BF16X3)):
+        ctx = L.Context(0, n_slots=1)
+        r = ctx.submit(W.Problem(**{**problem.__dict__, "precision": prec}), points=xyz)
+        if r.wait() != 0:
+            raise RuntimeError(f"{name} request failed")
+        prof = ctx.profile()
+        vals = r.tile().astype(np.float64) if problem.tile_T[0] > 0 else r.values.copy()
+        r.release()
+        ctx.close()
+        if ref is None:
+            ref = vals
+        entry = {"max_rel_dev_vs_f64": float(np.max(np.abs(vals - ref)) / np.max(np.abs(ref)))}
+        peak = PEAK_TFLOPS[name]
+        for stage in ("core", "tile", "projection"):
+            if stage in prof and prof[stage]["ms"] > 0:
+                tf = prof[stage]["flops"] / (prof[stage]["ms"] * 1e-3) / 1e12
+                entry[stage] = {"ms": prof[stage]["ms"], "tflops": tf, "peak": peak, "frac": tf / peak}
+        res[name] = entry
+        del vals
+    return res
+
+
 def main():
     args = parse()
     if args.copy_calibration:
@@ -394,6 +421,8 @@ def main():
         "stages": {k: {"ms_per_launch": v["ms"] / max(1, v["launches"]), "launches": v["launches"]}
                    for k, v in prof.items()},
     }
+    if cfg in (3, 4):
+        out["precisions"] = per_precision(L, W, problem, xyz)
     if not args.no_cpu:
         cxyz = xyz if cfg == 2 else xyz[:1000]
         out["cpu_baseline"] = cpu_baseline(problem if cfg == 2 else W.Problem(**{**problem.__dict__, "defects": [], "eps": 0.0}),
