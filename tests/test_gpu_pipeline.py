@@ -125,8 +125,10 @@ def test_rhosvd_fp64_matches_oracle(ctx, kind, param, eps):
     assert err <= inf.bound * (1 + 1e-9) + 1e-12 * nA
     assert err <= eps * nA * (1 + 1e-9) + 1e-12 * nA
     if tuple(inf.r) == ref.ranks:
+        # same ranks: the two rank-r projections differ by the subspace angle left by the Jacobi
+        # stopping rule (relative coupling <= 1e-12), amplified by sigma_1 / gap (Davis-Kahan)
         Tref = O.tucker_full(ref.core, ref.Z)
-        assert np.max(np.abs(tile - Tref)) <= 1e-11 * np.max(np.abs(Tref))
+        assert np.max(np.abs(tile - Tref)) <= 1e-10 * np.max(np.abs(Tref))
     # the Tucker factors are orthonormal and the core is their projection of the canonical sum
     Z, core = r.tucker()
     for a in range(3):
