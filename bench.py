@@ -319,6 +319,13 @@ def main():
 
     cfg = {"cfg2": 2, "cfg3": 3, "cfg4": 4}[args.workload]
     problem = W.config(cfg)
+    fp64_rows = None
+    if cfg == 2:
+        # served policy for canonical output: FP32 factor rows (FP64 products and sums), whose
+        # error (<= 3 roundings of 2^-24 per term for these positive sums) is far below 1e-6;
+        # the same stream with FP64 rows is measured beside it
+        fp64_rows = problem
+        problem = W.Problem(**{**problem.__dict__, "precision": W.FP32})
     n_pts = 100_000 if cfg == 2 else 4096
     xyz = W.sample_points(cfg, n_pts, W.half_widths(problem))
     xyz_d = torch.from_numpy(xyz).cuda()
@@ -338,6 +345,15 @@ def main():
     secs, lat = run_stream(L, ctx, prepared, xyz_d, outs, steps, args.inflight)
     prof = ctx.profile()
     served = steps / secs
+    served64 = None
+    if fp64_rows is not None:
+        vals32 = outs[(steps - 1) % len(outs)].cpu().numpy()
+        p64 = L.prepare(fp64_rows)
+        run_stream(L, ctx, p64, xyz_d, outs, warmup, args.inflight)
+        s64, lat64 = run_stream(L, ctx, p64, xyz_d, outs, steps, args.inflight)
+        vals64 = outs[(steps - 1) % len(outs)].cpu().numpy()
+        served64 = {"value": steps / s64, "unit": "lattice sums/s",
+                    "latency_ms": {"p50": percentile(lat64, 50), "p99": percentile(lat64, 99)}}
     ctx.close()
 
     # ---- plain FP64 path: one at a time, no batching, no reference cache ----------------
@@ -357,12 +373,13 @@ def main():
     if cfg == 2:
         bctx = L.Context(0, n_slots=1)
         bctx.set_option(L.OPT_MAX_BATCH, 1024)
-        reqs = bctx.submit_many([prepared] * 8)               # warm the reference and window cache
+        ss_prob = L.prepare(fp64_rows)                        # FP64 point-major output
+        reqs = bctx.submit_many([ss_prob] * 8)                # warm the reference and window cache
         for r in reqs:
             r.wait()
             r.release()
         bctx.reset_profile()
-        reqs = bctx.submit_many([prepared] * 1024)
+        reqs = bctx.submit_many([ss_prob] * 1024)
         for r in reqs:
             if r.wait() != 0:
                 raise RuntimeError("batched shift-sum request failed")
@@ -377,13 +394,17 @@ def main():
             ss_batched["traffic"] = None
 
     # ---- accuracy of the served result against the oracle's brute-force sum ------------
-    vals = outs[(steps - 1) % len(outs)].cpu().numpy()
-    sel = np.random.default_rng(7).choice(n_pts, 12, replace=False)
+    vals = vals32 if fp64_rows is not None else outs[(steps - 1) % len(outs)].cpu().numpy()
+    sel = np.random.default_rng(7).choice(n_pts, 32, replace=False)
     cells = O.points_to_cells(xyz[sel], problem.h, problem.N)
     ref = O.brute_force_points(problem, cells)
     rel_err = float(np.max(np.abs(vals[sel] - ref)) / np.max(np.abs(ref)))
+    if served64 is not None:
+        served64["max_rel_err_vs_oracle"] = float(np.max(np.abs(vals64[sel] - ref)) / np.max(np.abs(ref)))
+        served64["max_rel_dev_f32_rows"] = float(np.max(np.abs(vals - vals64)) / np.max(np.abs(vals64)))
 
-    dtype = "f64" if problem.precision == W.FP64 or cfg == 2 else ("f32" if problem.precision == W.FP32 else "bf16x3")
+    # canonical output at FP32 precision: FP32-rounded factor rows, FP64 products and sums
+    dtype = "f64" if problem.precision == W.FP64 else ("f32" if problem.precision == W.FP32 or cfg == 2 else "bf16x3")
     stage, roof = dominant_roofline(prof, dtype)
     if roof is not None:
         roof["traffic"] = traffic_from_profiles(stage)
@@ -414,6 +435,7 @@ def main():
         "plain_fp64": {"value": plain, "unit": "lattice sums/s",
                        "latency_ms": {"p50": percentile(plat, 50), "p99": percentile(plat, 99)}},
         "served_over_plain": served / plain,
+        "served_fp64_rows": served64,
         "max_rel_err_vs_oracle": rel_err,
         "roofline": roof,
         "roofline_shift_sum": roof_ss,

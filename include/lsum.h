@@ -100,6 +100,8 @@ typedef struct {
     double eps;               /* > 0: RHOSVD to a Tucker tensor with relative Frobenius error
                                  <= eps (certified); <= 0: canonical output, no reduction     */
     int precision;            /* arithmetic of projection, core and tile (LSUM_FP64/FP32/BF16X3);
+                                 for canonical output (eps <= 0) FP32/BF16X3 keep the factors
+                                 that sampling reads rounded to FP32 (products and sums FP64);
                                  quadrature, collocation, shift-sums, SVD and truncation are
                                  always FP64                                                   */
     int tile_lo[3];           /* optional reconstruction tile: cells [lo, lo+T) per axis      */
@@ -235,7 +237,8 @@ typedef struct {
 int lsum_get_info(lsum_req req, lsum_info* info);
 
 /* Canonical factors of block `block` (vector-major, R rows of N[l] each) into U[3][R*N[l]]
- * (host, or device if on_device) and the weight of the block (its charge). */
+ * (host, or device if on_device) and the weight of the block (its charge).  Factors kept in
+ * FP32 (canonical output at FP32/BF16X3 precision) are returned widened to double. */
 int lsum_get_canonical(lsum_req req, int block, double* U0, double* U1, double* U2, int on_device);
 /* Tucker factors Z_l (r_l rows of N[l]) and core (r1*r2*r3, last index fastest), FP64. */
 int lsum_get_tucker(lsum_req req, double* Z0, double* Z1, double* Z2, double* core, int on_device);

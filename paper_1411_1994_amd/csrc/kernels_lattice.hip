@@ -52,11 +52,12 @@ __global__ void __launch_bounds__(256) k_collocate(int R, const double* __restri
 // T_tab(t)[q * ldg + i + off_t], summed in term order.  One workgroup per (64-cell tile, job).
 // Each lane owns a pair of adjacent cells and loads both with one 16-byte access (the unit that
 // bounds this kernel is the vector-memory path, not HBM: five 8-byte loads per output for the
-// cfg-2 combs); the two halves of a wavefront serve two node slots, so the 8 slots of the
-// workgroup take nodes s, s + 8, ..., s + 40 of each block of 48 nodes, and the loads of two
-// terms for all six nodes are in flight together.  Vector-major rows are stored from the lanes;
-// point-major rows go through an LDS tile so the 64 rows of a tile (padded with zeros to ldt)
-// leave as contiguous memory.  Stores are non-temporal so they do not evict the tables from L2.
+// period-5 combs of a 64-site axis); the two halves of a wavefront serve two node slots, so the
+// 8 slots of the workgroup take nodes s, s + 8, ..., s + 40 of each block of 48 nodes, and the
+// loads of two terms for all six nodes are in flight together.  Vector-major rows are stored
+// from the lanes; point-major rows (FP64, or rounded to FP32) go through an LDS tile so the 64
+// rows of a tile (padded with zeros to ldt) leave as contiguous memory.  Stores are
+// non-temporal so they do not evict the tables from L2.
 // --------------------------------------------------------------------------------------------
 typedef double dpair __attribute__((ext_vector_type(2), aligned(8)));
 
@@ -82,6 +83,8 @@ __global__ void __launch_bounds__(256) k_shift_sum(const ShiftJob* __restrict__ 
     const LSUM_GLOBAL double* __restrict__ T1 = (const LSUM_GLOBAL double*)(jb.T1 ? jb.T1 : jb.T0) + cc;
     LSUM_GLOBAL double* __restrict__ U = (LSUM_GLOBAL double*)jb.U;
     LSUM_GLOBAL double* __restrict__ UT = (LSUM_GLOBAL double*)jb.UT;
+    LSUM_GLOBAL float* __restrict__ UT32 = (LSUM_GLOBAL float*)jb.UT32;
+    const bool rows = UT || UT32;
     for (int q0 = 0; q0 < jb.R; q0 += QB) {
         const int qn = min(QB, jb.R - q0);
         size_t qo[NU];
@@ -115,19 +118,26 @@ __global__ void __launch_bounds__(256) k_shift_sum(const ShiftJob* __restrict__ 
                 if (c0 < N) __builtin_nontemporal_store(a, row + c0);
                 if (!shifted && c0 + 1 < N) __builtin_nontemporal_store(acc[u].y, row + c0 + 1);
             }
-            if (UT) {
+            if (rows) {
                 tile[2 * pr][kk] = a;
                 tile[2 * pr + 1][kk] = acc[u].y;
             }
         }
-        if (UT) {
+        if (rows) {
             __syncthreads();
-            const int rows = min(64, N - i0);
+            const int nr = min(64, N - i0);
             const int width = min(QB, jb.ldt - q0);   // includes the zero padding after R
-            for (int rr = wave; rr < rows; rr += 4)
-                for (int cl = lane; cl < width; cl += 64)
-                    __builtin_nontemporal_store(cl < qn ? tile[rr][cl] : 0.0,
-                                                &UT[(size_t)(i0 + rr) * jb.ldt + q0 + cl]);
+            if (UT) {
+                for (int rr = wave; rr < nr; rr += 4)
+                    for (int cl = lane; cl < width; cl += 64)
+                        __builtin_nontemporal_store(cl < qn ? tile[rr][cl] : 0.0,
+                                                    &UT[(size_t)(i0 + rr) * jb.ldt + q0 + cl]);
+            } else {
+                for (int rr = wave; rr < nr; rr += 4)
+                    for (int cl = lane; cl < width; cl += 64)
+                        __builtin_nontemporal_store(cl < qn ? (float)tile[rr][cl] : 0.0f,
+                                                    &UT32[(size_t)(i0 + rr) * jb.ldt + q0 + cl]);
+            }
             __syncthreads();
         }
     }
@@ -206,14 +216,15 @@ __global__ void __launch_bounds__(256) k_sample_block(int R, const double* __res
 }
 
 // Vector-major R x N rows -> point-major N x R rows, through a 32 x 32 LDS tile.
-__global__ void __launch_bounds__(256) k_transpose(int R, int N, const double* __restrict__ U, int ldu,
+template <typename T>
+__global__ void __launch_bounds__(256) k_transpose(int R, int N, const T* __restrict__ U, int ldu,
                                                    double* __restrict__ UT) {
     __shared__ double tile[32][33];
     const int i0 = blockIdx.x * 32, q0 = blockIdx.y * 32;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
     for (int k = ty; k < 32; k += 8) {
         const int q = q0 + k, i = i0 + tx;
-        tile[k][tx] = (q < R && i < N) ? U[(size_t)q * ldu + i] : 0.0;
+        tile[k][tx] = (q < R && i < N) ? (double)U[(size_t)q * ldu + i] : 0.0;
     }
     __syncthreads();
     for (int k = ty; k < 32; k += 8) {
@@ -222,55 +233,87 @@ __global__ void __launch_bounds__(256) k_transpose(int R, int N, const double* _
     }
 }
 
-// Canonical sum at points from point-major factors: row i of axis l holds the values of cell i
-// for every node, rows ldt apart, zero padded, ldt a multiple of 16 and rows 128-byte aligned.
-// Eight lanes serve a point and read its three rows in 16-byte pieces (NQ2 = ldt / 16 per lane
-// and row), which halves the vector-memory instructions of 8-byte gathers; the partial
-// products are reduced over the 8 lanes.  out[p] (+)= lam * sum_q prod_l T_l[i_l(p) * ldt + q].
-template <int NQ2>
-__global__ void __launch_bounds__(256) k_sample_rows(int ldt, const double2* __restrict__ T0,
-                                                     const double2* __restrict__ T1,
-                                                     const double2* __restrict__ T2, int N0, int N1, int N2,
-                                                     double h, double lam, int accumulate, int n_pts,
-                                                     const double* __restrict__ xyz,
-                                                     double* __restrict__ out) {
-    const int l8 = threadIdx.x & 7;
-    const int p = blockIdx.x * 32 + (threadIdx.x >> 3);
-    const bool live = p < n_pts;
-    const size_t pc = live ? p : 0;
-    const double x0 = xyz[3 * pc + 0], x1 = xyz[3 * pc + 1], x2 = xyz[3 * pc + 2];
-    const int i0 = snap_dev(x0, h, N0), i1 = snap_dev(x1, h, N1), i2 = snap_dev(x2, h, N2);
+// Canonical sums at points from point-major factors, for a batch of requests in one launch.
+// Row i of axis l holds the values of cell i for every node, rows ldt apart, zero padded, ldt a
+// multiple of 16 elements.  A point's row is read in 16-byte pieces by LP lanes (8 for FP64
+// rows, 4 for FP32 rows; NQ = ldt / 16 pieces per lane and row), so one wave instruction moves
+// 64 full 16-byte lanes; products and sums are formed in FP64, reduced over the LP lanes, and
+// the blocks' charges applied in block order: out[p] = sum_b lam_b sum_q prod_l T_bl[i_l(p)][q].
+// Work-groups are numbered so that consecutive numbers stay on one XCD (the hardware deals
+// work-groups round-robin over the 8 XCDs): each request's work-groups are contiguous in that
+// numbering, so its factor rows are fetched into one or two XCD L2 caches instead of all eight.
+typedef float fquad __attribute__((ext_vector_type(4)));
+template <typename T> struct RowPiece;
+template <> struct RowPiece<double> {
+    using V = dpair;
+    static constexpr int E = 2;
+    __device__ static double dot3(V x, V y, V z) {
+        return x.x * y.x * z.x + x.y * y.y * z.y;
+    }
+};
+template <> struct RowPiece<float> {
+    using V = fquad;
+    static constexpr int E = 4;
+    __device__ static double dot3(V x, V y, V z) {
+        double a = (double)x.x * (double)y.x * (double)z.x;
+        a += (double)x.y * (double)y.y * (double)z.y;
+        a += (double)x.z * (double)y.z * (double)z.z;
+        a += (double)x.w * (double)y.w * (double)z.w;
+        return a;
+    }
+};
+
+template <int NQ, typename T>
+__global__ void __launch_bounds__(256) k_sample_batch(int ldt, const SampleJob* __restrict__ jobs_in,
+                                                      int n_jobs, int n_wg) {
+    using RP = RowPiece<T>;
+    using V = typename RP::V;
+    constexpr int LP = 16 / RP::E, PPW = 256 / LP;
+    const int per_xcd = gridDim.x / 8;
+    const int w = (int)(blockIdx.x % 8) * per_xcd + (int)(blockIdx.x / 8);
+    if (w >= n_wg) return;
+    const LSUM_CONST SampleJob* jobs = (const LSUM_CONST SampleJob*)jobs_in;
+    int lo = 0, hi = n_jobs - 1;   // last job whose first work-group is <= w
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].wg0 <= w) lo = mid;
+        else hi = mid - 1;
+    }
+    const LSUM_CONST SampleJob& jb = jobs[lo];
+    const int lp = threadIdx.x % LP;
+    const int p = (w - jb.wg0) * PPW + (int)(threadIdx.x / LP);
+    const bool live = p < jb.n_pts;
+    const LSUM_GLOBAL double* xyz = (const LSUM_GLOBAL double*)jb.xyz + 3 * (size_t)(live ? p : 0);
+    const double h = jb.h;
+    const int i0 = snap_dev(xyz[0], h, jb.N0), i1 = snap_dev(xyz[1], h, jb.N1), i2 = snap_dev(xyz[2], h, jb.N2);
     const bool in = live && i0 >= 0 && i1 >= 0 && i2 >= 0;
-    const size_t ld2 = (size_t)(ldt / 2);
-    const size_t r0 = (size_t)(in ? i0 : 0) * ld2 + l8;
-    const size_t r1 = (size_t)(in ? i1 : 0) * ld2 + l8;
-    const size_t r2 = (size_t)(in ? i2 : 0) * ld2 + l8;
-    double acc = 0.0;
-    if (NQ2 > 0) {
-        double2 a[NQ2 > 0 ? NQ2 : 1], b[NQ2 > 0 ? NQ2 : 1], c[NQ2 > 0 ? NQ2 : 1];
+    const size_t r0 = (size_t)(in ? i0 : 0) * ldt + RP::E * lp;
+    const size_t r1 = (size_t)(in ? i1 : 0) * ldt + RP::E * lp + jb.off1;
+    const size_t r2 = (size_t)(in ? i2 : 0) * ldt + RP::E * lp + jb.off2;
+    const LSUM_CONST SampleBlock* blk = (const LSUM_CONST SampleBlock*)jb.blk;
+    double total = 0.0;
+    for (int b = 0; b < jb.n_blocks; ++b) {
+        const LSUM_GLOBAL T* tb = (const LSUM_GLOBAL T*)blk[b].T;
+        double acc = 0.0;
+        if (NQ > 0) {
+            V x[NQ > 0 ? NQ : 1], y[NQ > 0 ? NQ : 1], z[NQ > 0 ? NQ : 1];
 #pragma unroll
-        for (int k = 0; k < (NQ2 > 0 ? NQ2 : 1); ++k) {
-            a[k] = T0[r0 + 8 * k];
-            b[k] = T1[r1 + 8 * k];
-            c[k] = T2[r2 + 8 * k];
-        }
+            for (int k = 0; k < (NQ > 0 ? NQ : 1); ++k) {
+                x[k] = *(const LSUM_GLOBAL V*)(tb + r0 + 16 * k);
+                y[k] = *(const LSUM_GLOBAL V*)(tb + r1 + 16 * k);
+                z[k] = *(const LSUM_GLOBAL V*)(tb + r2 + 16 * k);
+            }
 #pragma unroll
-        for (int k = 0; k < (NQ2 > 0 ? NQ2 : 1); ++k) {
-            acc += a[k].x * b[k].x * c[k].x;
-            acc += a[k].y * b[k].y * c[k].y;
+            for (int k = 0; k < (NQ > 0 ? NQ : 1); ++k) acc += RP::dot3(x[k], y[k], z[k]);
+        } else {
+            for (int k = 0; k < ldt / 16; ++k)
+                acc += RP::dot3(*(const LSUM_GLOBAL V*)(tb + r0 + 16 * k), *(const LSUM_GLOBAL V*)(tb + r1 + 16 * k),
+                                *(const LSUM_GLOBAL V*)(tb + r2 + 16 * k));
         }
-    } else {
-        for (int k = 0; k < ldt / 16; ++k) {
-            const double2 a = T0[r0 + 8 * k], b = T1[r1 + 8 * k], c = T2[r2 + 8 * k];
-            acc += a.x * b.x * c.x;
-            acc += a.y * b.y * c.y;
-        }
+        for (int m = LP / 2; m > 0; m >>= 1) acc += __shfl_xor(acc, m, LP);
+        total += blk[b].lam * acc;
     }
-    for (int m = 4; m > 0; m >>= 1) acc += __shfl_xor(acc, m, 8);
-    if (l8 == 0 && live) {
-        if (!in) out[p] = __builtin_nan("");
-        else out[p] = accumulate ? out[p] + lam * acc : lam * acc;
-    }
+    if (lp == 0 && live) ((LSUM_GLOBAL double*)jb.out)[p] = in ? total : __builtin_nan("");
 }
 
 // Defect terms straight from the reference rows: out[p] += sum_s dZ_s sum_q prod_l
@@ -475,27 +518,38 @@ void launch_sample_block(hipStream_t st, int R, const double* U0, const double* 
 
 void launch_transpose(hipStream_t st, int R, int N, const double* U, int ldu, double* UT) {
     if (R <= 0 || N <= 0) return;
-    hipLaunchKernelGGL(k_transpose, dim3(cdiv(N, 32), cdiv(R, 32)), dim3(256), 0, st, R, N, U, ldu, UT);
+    hipLaunchKernelGGL(k_transpose<double>, dim3(cdiv(N, 32), cdiv(R, 32)), dim3(256), 0, st, R, N, U, ldu, UT);
 }
 
-void launch_sample_rows(hipStream_t st, int ldt, const double* T0, const double* T1, const double* T2,
-                        int N0, int N1, int N2, double h, double lam, int accumulate, int n_pts,
-                        const double* xyz, double* out, const KTime* kt) {
-    if (n_pts <= 0) return;
-    const dim3 grid(cdiv(n_pts, 32)), blk(256);
+void launch_transpose(hipStream_t st, int R, int N, const float* U, int ldu, double* UT) {
+    if (R <= 0 || N <= 0) return;
+    hipLaunchKernelGGL(k_transpose<float>, dim3(cdiv(N, 32), cdiv(R, 32)), dim3(256), 0, st, R, N, U, ldu, UT);
+}
+
+int sample_points_per_wg(bool f32) { return f32 ? 64 : 32; }
+
+void launch_sample_batch(hipStream_t st, int ldt, bool f32, const SampleJob* jobs, int n_jobs, int n_wg,
+                         const KTime* kt) {
+    if (n_jobs <= 0 || n_wg <= 0) return;
+    const dim3 grid(cdiv(n_wg, 8) * 8), blk(256);
     hipEvent_t a = kt ? kt->start : nullptr, b = kt ? kt->stop : nullptr;
-    const double2 *t0 = (const double2*)T0, *t1 = (const double2*)T1, *t2 = (const double2*)T2;
-#define LSUM_SAMPLE_ROWS(NQ2)                                                                        \
-    hipExtLaunchKernelGGL(k_sample_rows<NQ2>, grid, blk, 0, st, a, b, 0, ldt, t0, t1, t2, N0, N1, N2, h, lam, \
-                          accumulate, n_pts, xyz, out)
-    switch (ldt) {
-        case 16: LSUM_SAMPLE_ROWS(1); break;
-        case 32: LSUM_SAMPLE_ROWS(2); break;
-        case 48: LSUM_SAMPLE_ROWS(3); break;
-        case 64: LSUM_SAMPLE_ROWS(4); break;
-        default: LSUM_SAMPLE_ROWS(0);
+#define LSUM_SAMPLE_BATCH(NQ, T) \
+    hipExtLaunchKernelGGL((k_sample_batch<NQ, T>), grid, blk, 0, st, a, b, 0, ldt, jobs, n_jobs, n_wg)
+#define LSUM_SAMPLE_BATCH_LDT(T)              \
+    switch (ldt) {                            \
+        case 16: LSUM_SAMPLE_BATCH(1, T); break; \
+        case 32: LSUM_SAMPLE_BATCH(2, T); break; \
+        case 48: LSUM_SAMPLE_BATCH(3, T); break; \
+        case 64: LSUM_SAMPLE_BATCH(4, T); break; \
+        default: LSUM_SAMPLE_BATCH(0, T);     \
     }
-#undef LSUM_SAMPLE_ROWS
+    if (f32) {
+        LSUM_SAMPLE_BATCH_LDT(float)
+    } else {
+        LSUM_SAMPLE_BATCH_LDT(double)
+    }
+#undef LSUM_SAMPLE_BATCH_LDT
+#undef LSUM_SAMPLE_BATCH
 }
 
 void launch_sample_windows(hipStream_t st, int R, const double* G, int ldg, int N_ref, int n_def,

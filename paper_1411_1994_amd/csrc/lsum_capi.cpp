@@ -228,8 +228,12 @@ int lsum_get_canonical(lsum_req r, int block, double* U0, double* U1, double* U2
         const double* src = have_vm ? q.U[block].as<double>() + q.U_axis_off[l] : nullptr;
         if (!have_vm) {
             // factors are kept point-major (N x R); transpose back to R x N
-            launch_transpose(q.ctx->own_stream, P.N[l], P.R, q.UT[block].as<double>() + q.UT_axis_off[l], P.ldt,
-                             tmp.as<double>());
+            if (P.rows_f32())
+                launch_transpose(q.ctx->own_stream, P.N[l], P.R, q.UT[block].as<float>() + q.UT_axis_off[l], P.ldt,
+                                 tmp.as<double>());
+            else
+                launch_transpose(q.ctx->own_stream, P.N[l], P.R, q.UT[block].as<double>() + q.UT_axis_off[l], P.ldt,
+                                 tmp.as<double>());
             LSUM_HIP(hipStreamSynchronize(q.ctx->own_stream));
             src = tmp.as<double>();
         }

@@ -108,7 +108,7 @@ size_t Plan::planned_bytes() const {
     size_t b = 0;
     size_t sumN = (size_t)N[0] + N[1] + N[2];
     b += (size_t)R * ldg * 8;                                  // reference rows (if not cached)
-    b += blocks.size() * (size_t)ldt * sumN * 8;               // canonical factors
+    b += blocks.size() * (size_t)ldt * sumN * 8;               // canonical factors (FP64 bound)
     if (tucker()) {
         size_t rmax[3];
         for (int l = 0; l < 3; ++l) {

@@ -55,7 +55,7 @@ struct Plan {
     int R = 0;
     int N_ref = 0;   // max N
     int ldg = 0;     // reference row stride
-    int ldt = 0;     // point-major factor row stride: R rounded up to 16 (128-byte rows)
+    int ldt = 0;     // point-major factor row stride: R rounded up to 16 (64- or 128-byte rows)
 
     // per block, per axis snapped cell indices
     std::vector<std::vector<int32_t>> offs[3];   // offs[axis][block]
@@ -73,6 +73,10 @@ struct Plan {
     int D[3]{};                          // R * (n_lat + n_win)
 
     bool tucker() const { return eps > 0; }
+    // canonical output with FP32 precision keeps its point-major factors in FP32 (sampling
+    // multiplies and sums them in FP64); everything else is FP64
+    bool rows_f32() const { return !tucker() && precision != LSUM_FP64; }
+    size_t row_elem() const { return rows_f32() ? 4 : 8; }
     bool has_tile() const { return tile_T[0] > 0 && tile_T[1] > 0 && tile_T[2] > 0; }
     size_t planned_bytes() const;        // HBM footprint estimate of the request
 };
@@ -102,6 +106,7 @@ struct ShiftJob {
     const int2* terms;     // n_terms pairs (off, tab)
     double* U;             // vector-major output (R x ldu) or nullptr
     double* UT;            // point-major output (N_axis x ldt, zero padded beyond R) or nullptr
+    float* UT32;           // the same, rounded to FP32, or nullptr
     int n_terms;
     int N_axis;
     int ldg;
@@ -133,10 +138,32 @@ void launch_sample_block(hipStream_t st, int R, const double* U0, const double* 
                          double* out);
 // R x N (stride ldu) -> N x R
 void launch_transpose(hipStream_t st, int R, int N, const double* U, int ldu, double* UT);
-// Point-major canonical evaluation (rows ldt apart, zero padded); accumulate = 0 overwrites out.
-void launch_sample_rows(hipStream_t st, int ldt, const double* T0, const double* T1, const double* T2,
-                        int N0, int N1, int N2, double h, double lam, int accumulate, int n_pts,
-                        const double* xyz, double* out, const KTime* kt = nullptr);
+void launch_transpose(hipStream_t st, int R, int N, const float* U, int ldu, double* UT);
+// One block of a canonical request in a batched sampling launch: its factor base (axis 0 rows;
+// axes 1 and 2 at the job's offsets) and its charge.
+struct SampleBlock {
+    const void* T;            // double, or float for a job with f32 set
+    double lam;
+};
+// One canonical request in a batched sampling launch: n_pts points (x, y, z interleaved) whose
+// values are written to out (NaN for a point outside the grid); work-groups wg0 .. wg0 +
+// ceil(n_pts / 32) - 1 serve it, in increasing wg0 over the job array.
+struct SampleJob {
+    const double* xyz;
+    double* out;
+    const SampleBlock* blk;   // n_blocks entries, device
+    double h;
+    int n_blocks, n_pts, wg0;
+    int N0, N1, N2;
+    int off1, off2;           // axis offsets (elements) of axes 1 and 2 from each block's base
+    int f32;                  // factors stored as FP32
+};
+// Point-major canonical evaluation of a batch of requests whose rows are ldt apart (zero
+// padded) and all FP64 or all FP32 (f32); n_wg = total work-groups of the job array (device),
+// sample_points_per_wg(f32) points each.
+int sample_points_per_wg(bool f32);
+void launch_sample_batch(hipStream_t st, int ldt, bool f32, const SampleJob* jobs_dev, int n_jobs, int n_wg,
+                         const KTime* kt = nullptr);
 // Defect windows evaluated straight from the reference rows, added to out.
 void launch_sample_windows(hipStream_t st, int R, const double* G, int ldg, int N_ref,
                            int n_def, const int32_t* def_cells, const double* def_scale,

@@ -436,34 +436,98 @@ static int run_tucker(Request* q, hipStream_t st, const hipStream_t* aux, StageT
 // sampling: canonical factors (point-major rows, plus defect windows from the reference), or
 // the Tucker tensor (mode-3 contraction as a GEMM per chunk of points, then modes 1 and 2)
 // ------------------------------------------------------------------------------------------
+// Canonical requests of a batch: one launch per factor row width (usually one), then each
+// request's defect windows.  Timing: start on the first launch, stop on the last.
+int sample_canonical(Context* c, hipStream_t st, const std::vector<CanonSample>& items, const KTime* kt) {
+    std::vector<std::vector<size_t>> by_ldt;
+    std::vector<int> ldts;   // one group per (row stride, FP32 rows); FP32 groups as -ldt
+    size_t n_blk = 0, n_win = 0;
+    for (size_t k = 0; k < items.size(); ++k) {
+        const Plan& P = items[k].q->plan;
+        if (items[k].n <= 0) continue;
+        const int key = P.rows_f32() ? -P.ldt : P.ldt;
+        auto it = std::find(ldts.begin(), ldts.end(), key);
+        if (it == ldts.end()) {
+            ldts.push_back(key);
+            by_ldt.emplace_back();
+            it = ldts.end() - 1;
+        }
+        by_ldt[it - ldts.begin()].push_back(k);
+        n_blk += P.blocks.size();
+        n_win += P.defects.empty() ? 0 : 1;
+    }
+    if (ldts.empty()) return LSUM_OK;
+    std::vector<SampleBlock> blk_h;
+    std::vector<SampleJob> jobs_h;
+    blk_h.reserve(n_blk);
+    jobs_h.reserve(items.size());
+    DevBuf blk_d, jobs_d;
+    int rc;
+    if ((rc = blk_d.get(c->pool, std::max<size_t>(1, n_blk) * sizeof(SampleBlock)))) return rc;
+    if ((rc = jobs_d.get(c->pool, items.size() * sizeof(SampleJob)))) return rc;
+    std::vector<int> first_job, n_jobs, n_wg;
+    for (size_t g = 0; g < by_ldt.size(); ++g) {
+        const auto& grp = by_ldt[g];
+        const int ppw = sample_points_per_wg(ldts[g] < 0);
+        first_job.push_back((int)jobs_h.size());
+        int wg = 0;
+        for (size_t k : grp) {
+            const CanonSample& it = items[k];
+            const Request* q = it.q;
+            const Plan& P = q->plan;
+            SampleJob j{};
+            j.xyz = it.xyz;
+            j.out = it.out;
+            j.blk = blk_d.as<SampleBlock>() + blk_h.size();
+            j.h = P.h;
+            j.n_blocks = (int)P.blocks.size();
+            j.n_pts = it.n;
+            j.wg0 = wg;
+            j.N0 = P.N[0];
+            j.N1 = P.N[1];
+            j.N2 = P.N[2];
+            j.off1 = (int)q->UT_axis_off[1];
+            j.off2 = (int)q->UT_axis_off[2];
+            j.f32 = P.rows_f32() ? 1 : 0;
+            for (size_t b = 0; b < P.blocks.size(); ++b) blk_h.push_back(SampleBlock{q->UT[b].p, P.blocks[b].charge});
+            jobs_h.push_back(j);
+            wg += (it.n + ppw - 1) / ppw;
+        }
+        n_jobs.push_back((int)grp.size());
+        n_wg.push_back(wg);
+    }
+    LSUM_HIP(hipMemcpyAsync(blk_d.p, blk_h.data(), blk_h.size() * sizeof(SampleBlock), hipMemcpyHostToDevice, st));
+    LSUM_HIP(hipMemcpyAsync(jobs_d.p, jobs_h.data(), jobs_h.size() * sizeof(SampleJob), hipMemcpyHostToDevice, st));
+    size_t wins_left = n_win;
+    for (size_t g = 0; g < ldts.size(); ++g) {
+        KTime k;
+        if (kt && g == 0) k.start = kt->start;
+        if (kt && g + 1 == ldts.size() && wins_left == 0) k.stop = kt->stop;
+        launch_sample_batch(st, std::abs(ldts[g]), ldts[g] < 0, jobs_d.as<SampleJob>() + first_job[g], n_jobs[g],
+                            n_wg[g], &k);
+    }
+    for (const auto& it : items) {
+        const Request* q = it.q;
+        const Plan& P = q->plan;
+        if (it.n <= 0 || P.defects.empty()) continue;
+        KTime k;
+        if (kt && --wins_left == 0) k.stop = kt->stop;
+        launch_sample_windows(st, P.R, q->ref->G.as<double>(), P.ldg, P.N_ref, (int)P.defects.size(),
+                              q->def_cells.as<int32_t>(), q->def_scale.as<double>(), P.N[0], P.N[1], P.N[2],
+                              P.h, it.n, it.xyz, it.out, &k);
+    }
+    LSUM_HIP(hipGetLastError());
+    // the job and block arrays go back to the pool, whose next user may run on another stream
+    LSUM_HIP(hipStreamSynchronize(st));
+    return LSUM_OK;
+}
+
 int sample_points(Request* q, hipStream_t st, int n, const double* xyz_d, double* out_d, const KTime* kt) {
     Context* c = q->ctx;
     const Plan& P = q->plan;
     int rc;
     if (n <= 0) return LSUM_OK;
-    if (!P.tucker()) {
-        // kernel-bound timing: start on the first launch, stop on the last
-        const int nb = (int)P.blocks.size();
-        const bool windows = !P.defects.empty();
-        for (int b = 0; b < nb; ++b) {
-            KTime k;
-            if (kt && b == 0) k.start = kt->start;
-            if (kt && b == nb - 1 && !windows) k.stop = kt->stop;
-            const double* T = q->UT[b].as<double>();
-            launch_sample_rows(st, P.ldt, T, T + q->UT_axis_off[1], T + q->UT_axis_off[2], P.N[0], P.N[1],
-                               P.N[2], P.h, P.blocks[b].charge, b > 0 ? 1 : 0, n, xyz_d, out_d, &k);
-        }
-        if (windows) {
-            KTime k;
-            if (kt) k.stop = kt->stop;
-            if (kt && nb == 0) k.start = kt->start;
-            launch_sample_windows(st, P.R, q->ref->G.as<double>(), P.ldg, P.N_ref, (int)P.defects.size(),
-                                  q->def_cells.as<int32_t>(), q->def_scale.as<double>(), P.N[0], P.N[1], P.N[2],
-                                  P.h, n, xyz_d, out_d, &k);
-        }
-        LSUM_HIP(hipGetLastError());
-        return LSUM_OK;
-    }
+    if (!P.tucker()) return sample_canonical(c, st, {CanonSample{q, n, xyz_d, out_d}}, kt);
     const int r1 = q->r[0], r2 = q->r[1], r3 = q->r[2];
     const size_t ncore = (size_t)r1 * r2 * r3;
     DevBuf core64, idx, W, Z3s, i3c;
@@ -568,7 +632,7 @@ int run_batch(std::vector<Request*>& reqs, hipStream_t st, const hipStream_t* au
         q->UT.resize(nb);
         for (int b = 0; b < nb; ++b) {
             DevBuf& out = vector_major ? q->U[b] : q->UT[b];
-            if ((rc = out.get(c->pool, (size_t)(vector_major ? P.R : P.ldt) * uN * 8))) return rc;
+            if ((rc = out.get(c->pool, vector_major ? (size_t)P.R * uN * 8 : (size_t)P.ldt * uN * P.row_elem()))) return rc;
             for (int l = 0; l < 3; ++l) {
                 if (q->axis_src[l] != l) continue;
                 const auto& sites = P.offs[l][b];
@@ -591,7 +655,8 @@ int run_batch(std::vector<Request*>& reqs, hipStream_t st, const hipStream_t* au
                 j.n_terms = (int)tv.size();
                 j.U = vector_major ? q->U[b].as<double>() + q->U_axis_off[l] : nullptr;
                 j.ldu = P.N[l];
-                j.UT = vector_major ? nullptr : q->UT[b].as<double>() + q->UT_axis_off[l];
+                if (!vector_major && P.rows_f32()) j.UT32 = q->UT[b].as<float>() + q->UT_axis_off[l];
+                else if (!vector_major) j.UT = q->UT[b].as<double>() + q->UT_axis_off[l];
                 j.ldt = P.ldt;
                 j.N_axis = P.N[l];
                 j.ldg = P.ldg;
@@ -600,10 +665,11 @@ int run_batch(std::vector<Request*>& reqs, hipStream_t st, const hipStream_t* au
                 maxN = std::max(maxN, P.N[l]);
                 loads += (double)P.R * P.N[l] * tv.size();
             }
-            out_bytes += (double)P.R * uN * 8;   // algorithmic: the R values per distinct cell, no padding
+            // algorithmic: the R values per distinct cell, no padding
+            out_bytes += (double)P.R * uN * (vector_major ? 8 : P.row_elem());
         }
         if (std::find(distinct.begin(), distinct.end(), q->ref.get()) == distinct.end()) distinct.push_back(q->ref.get());
-        q->bytes["canonical"] = (double)nb * P.R * uN * 8;
+        q->bytes["canonical"] = (double)nb * P.R * uN * (vector_major ? 8 : P.row_elem());
     }
     double ref_bytes = 0;
     for (auto* e : distinct) ref_bytes += (double)e->R * (2 * e->N_ref - 1) * 8;
@@ -648,14 +714,20 @@ int run_batch(std::vector<Request*>& reqs, hipStream_t st, const hipStream_t* au
         }
     }
 
-    // completion sampling at the request's points
+    // completion sampling at the request's points: the canonical requests of the batch in one
+    // launch, reduction requests one by one
+    std::vector<DevBuf> staged;
+    staged.reserve(2 * reqs.size());
+    std::vector<CanonSample> canon;
+    std::vector<Request*> canon_q;
+    double canon_bytes = 0;
     for (auto* q : reqs) {
         if (q->n_points <= 0 || q->status.load() < 0) continue;
         const int n = q->n_points;
-        DevBuf xd, od;
         const double* xyz_d = q->points;
         double* out_d = q->values;
         if (!q->points_on_device) {
+            DevBuf xd, od;
             if ((rc = xd.get(c->pool, (size_t)n * 24)) || (rc = od.get(c->pool, (size_t)n * 8))) {
                 q->status.store(rc);
                 continue;
@@ -663,29 +735,39 @@ int run_batch(std::vector<Request*>& reqs, hipStream_t st, const hipStream_t* au
             LSUM_HIP(hipMemcpyAsync(xd.p, q->points, (size_t)n * 24, hipMemcpyHostToDevice, st));
             xyz_d = xd.as<double>();
             out_d = od.as<double>();
+            staged.push_back(std::move(xd));
+            staged.push_back(std::move(od));
         }
         const Plan& P = q->plan;
         // factors read once (R values per distinct cell) + points in + values out
         double uN = 0;
         for (int l = 0; l < 3; ++l)
             if (q->axis_src[l] == l) uN += P.N[l];
-        const double fb = (double)P.blocks.size() * P.R * uN * 8;
-        const double sb = (double)n * 32 + (P.tucker() ? 0.0 : fb);
+        const double fb = (double)P.blocks.size() * P.R * uN * P.row_elem();
         if (P.tucker()) {
-            tm.begin("sample", sb, 0);
+            tm.begin("sample", (double)n * 32, 0);
             rc = sample_points(q, st, n, xyz_d, out_d);
             tm.end();
+            if (rc) {
+                q->status.store(rc);
+                continue;
+            }
+            if (!q->points_on_device)
+                LSUM_HIP(hipMemcpyAsync(q->values, out_d, (size_t)n * 8, hipMemcpyDeviceToHost, st));
         } else {
-            const KTime kt = tm.kernels("sample", sb, 0);
-            rc = sample_points(q, st, n, xyz_d, out_d, &kt);
+            canon.push_back(CanonSample{q, n, xyz_d, out_d});
+            canon_q.push_back(q);
+            canon_bytes += (double)n * 32 + fb;
         }
-        if (rc) {
-            q->status.store(rc);
-            continue;
-        }
-        if (!q->points_on_device) {
-            LSUM_HIP(hipMemcpyAsync(q->values, out_d, (size_t)n * 8, hipMemcpyDeviceToHost, st));
-            LSUM_HIP(hipStreamSynchronize(st));
+    }
+    if (!canon.empty()) {
+        const KTime kt = tm.kernels("sample", canon_bytes, 0);
+        rc = sample_canonical(c, st, canon, &kt);
+        for (size_t k = 0; k < canon.size(); ++k) {
+            Request* q = canon_q[k];
+            if (rc) q->status.store(rc);
+            else if (!q->points_on_device)
+                LSUM_HIP(hipMemcpyAsync(q->values, canon[k].out, (size_t)canon[k].n * 8, hipMemcpyDeviceToHost, st));
         }
     }
     LSUM_HIP(hipStreamSynchronize(st));

@@ -230,6 +230,14 @@ void worker(Context* c, int slot);
 // pipeline stages (lsum_pipeline.cpp)
 // aux: three streams for the concurrent per-mode SVDs (nullptr: everything on st)
 int run_batch(std::vector<Request*>& reqs, hipStream_t st, const hipStream_t* aux = nullptr);
+// one canonical request's points for a batched sampling launch (device pointers)
+struct CanonSample {
+    Request* q;
+    int n;
+    const double* xyz;
+    double* out;
+};
+int sample_canonical(Context* c, hipStream_t st, const std::vector<CanonSample>& items, const KTime* kt);
 // kt (canonical requests only): kernel-bound timing of the sampling kernels
 int sample_points(Request* q, hipStream_t st, int n, const double* xyz_dev, double* out_dev,
                   const KTime* kt = nullptr);

@@ -67,6 +67,44 @@ def test_defects_and_blocks_canonical(ctx, kind, param):
     r.release()
 
 
+@pytest.mark.parametrize("kind,param", [(W.NEWTON, 0.0), (W.SLATER, 1.0)])
+def test_fp32_canonical_factors(ctx, kind, param):
+    # FP32 precision on canonical output keeps the point-major factors rounded to FP32 and forms
+    # products and sums in FP64.  Every factor entry is then within one rounding (2^-24 relative,
+    # or the FP32 underflow threshold) of the oracle's assembled sums, and a sampled value is off
+    # by at most 3 roundings per term: |err| <= 3.01 * 2^-24 * sum_b |lam_b| sum_q prod_l |U|,
+    # which for these positive kernels and charges is the defect-free potential itself.  The
+    # defect windows come from the FP64 reference rows and add only FP64 rounding.
+    rng = np.random.default_rng(31 + kind)
+    big = W.Block((6, 5, 4), (1.0, 1.1, 0.9), (0.13, -0.2, 0.07))
+    second = W.Block((3, 3, 2), (1.0, 1.0, 1.0), (-1.5, 4.4, 3.1), charge=0.5)
+    defects = W.draw_defects(rng, [big, second], 6, 4)
+    p = W.Problem("f32", kind, param, 28, (61, 67, 55), 0.21, [big, second], defects, precision=W.FP32)
+    r = run(ctx, p)
+    u = 2.0 ** -24
+    Uo = O.assembled_canonical(p)
+    for b in range(2):
+        U = r.canonical(b)
+        for a in range(3):
+            # the FP64 sums agree with the oracle to 1e-12 (per-row floor for underflowing tails)
+            floor = 1e-13 * np.max(np.abs(Uo[b][a]), axis=1, keepdims=True) + 2.0 ** -126
+            assert np.all(np.abs(U[a] - Uo[b][a]) <= (u + 1e-12) * np.abs(Uo[b][a]) + floor)
+    pts = np.stack([rng.integers(0, n, 400) for n in p.N], axis=1)
+    got = r.sample(cells_xyz(p, pts))
+    ref = O.brute_force_points(p, pts)
+    clean = O.brute_force_points(W.Problem(**{**p.__dict__, "defects": []}), pts)
+    assert np.all(clean > 0)
+    err = np.abs(got - ref)
+    assert np.all(err <= 3.01 * u * clean + 1e-12 * np.max(np.abs(ref))), np.max(err / clean)
+    assert np.max(err / np.abs(ref)) <= 1e-6
+    # FP32 factors take half the resident bytes of FP64 ones
+    p64 = W.Problem(**{**p.__dict__, "precision": W.FP64})
+    r64 = run(ctx, p64)
+    assert r.stats()["bytes"]["canonical"] * 2 == r64.stats()["bytes"]["canonical"]
+    r64.release()
+    r.release()
+
+
 def test_points_outside_grid_are_nan(ctx):
     p = W.Problem("nan", W.NEWTON, 0.0, 10, (21, 21, 21), 0.5, [W.cubic_block(2)])
     r = run(ctx, p)

@@ -22,7 +22,9 @@ def mixed_problems(n, seed=5):
         blk = W.Block(L, (1.0, 1.0, 1.0), (0.0, 0.0, 0.0))
         nd = int(rng.integers(0, 4))
         defects = W.draw_defects(rng, [blk], nd // 2, nd - nd // 2)
-        out.append(W.Problem(f"m{i}", kind, param, 24, N, h, [blk], defects))
+        # odd requests keep FP32 factors, so batches mix the two sampling groups
+        prec = W.FP32 if i % 2 else W.FP64
+        out.append(W.Problem(f"m{i}", kind, param, 24, N, h, [blk], defects, precision=prec))
     return out
 
 
@@ -57,7 +59,8 @@ def test_batched_results_equal_alone():
         assert max(batches) > 1                           # some requests really were fused
         prof = c2.profile()
         assert prof["shift_sum"]["launches"] < len(probs)
-        assert prof["shift_sum"]["bytes"] > 0 and prof["sample"]["launches"] == len(probs)
+        assert prof["shift_sum"]["bytes"] > 0
+        assert prof["sample"]["launches"] < len(probs)          # canonical sampling fused per batch too
 
 
 def test_completion_sampling_matches_oracle_and_lsum_sample():
