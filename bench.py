@@ -30,9 +30,11 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 # One hardware queue per stream: the library runs several slot streams plus three per-mode SVD
-# streams per slot, and HIP's default of 4 queues per process would serialise them.  Must be set
-# before the HIP runtime starts (torch import).
-os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
+# streams per slot, and HIP's default of 4 queues per process makes some of them share a queue
+# (the three concurrent SVDs of the first context then take 1.6x longer).  An environment that
+# already exports the default is raised too.  Must be set before the HIP runtime starts.
+if int(os.environ.get("GPU_MAX_HW_QUEUES", "0") or 0) < 16:
+    os.environ["GPU_MAX_HW_QUEUES"] = "16"
 
 HBM_PEAK_GBS = 8000.0
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16x3": 2500.0 / 3}
@@ -49,6 +51,7 @@ def parse():
     ap.add_argument("--inflight", type=int, default=64)
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--batch", type=int, default=16)
+    ap.add_argument("--chunk", type=int, default=1, help="requests per submit call of the served stream")
     ap.add_argument("--plain-steps", type=int, default=256)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
@@ -72,26 +75,17 @@ def percentile(x, q):
     return float(np.percentile(np.asarray(x), q)) if len(x) else None
 
 
-def run_stream(L, ctx, problem, points, outs, steps, inflight):
-    """Submit `steps` requests keeping at most `inflight` in flight; returns (seconds, latencies).
-    `problem` is marshalled once (L.prepare); the library copies it at every submit."""
+def run_stream(L, ctx, problem, points, outs, steps, inflight, chunk=1):
+    """Submit `steps` requests keeping at most `inflight` in flight, `chunk` at a time (one
+    lsum_submit_many call per chunk once that many have finished); returns (seconds,
+    latencies).  `problem` is marshalled once (L.prepare); the library copies it at every
+    submit."""
     import torch
     from collections import deque
     q = deque()
     lat = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(steps):
-        if len(q) >= inflight:
-            r = q.popleft()
-            rc = r.wait()
-            if rc != 0:
-                raise RuntimeError(f"request failed: {rc}")
-            inf = r.info()
-            lat.append(inf.t_queue_ms + inf.t_run_ms)
-            r.release()
-        q.append(ctx.submit(problem, points=points, values=outs[i % len(outs)]))
-    while q:
+
+    def harvest():
         r = q.popleft()
         rc = r.wait()
         if rc != 0:
@@ -99,6 +93,22 @@ def run_stream(L, ctx, problem, points, outs, steps, inflight):
         inf = r.info()
         lat.append(inf.t_queue_ms + inf.t_run_ms)
         r.release()
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    i = 0
+    while i < steps:
+        k = min(chunk, steps - i, inflight)
+        while len(q) + k > inflight:
+            harvest()
+        if k == 1:
+            q.append(ctx.submit(problem, points=points, values=outs[i % len(outs)]))
+        else:
+            q.extend(ctx.submit_many([problem] * k, points=[points] * k,
+                                     values=[outs[(i + j) % len(outs)] for j in range(k)]))
+        i += k
+    while q:
+        harvest()
     torch.cuda.synchronize()
     return time.perf_counter() - t0, lat
 
@@ -340,17 +350,17 @@ def main():
     ctx = L.Context(0, n_slots=args.slots if cfg == 2 else 1)
     ctx.set_option(L.OPT_MAX_BATCH, args.batch)
     prepared = L.prepare(problem)
-    run_stream(L, ctx, prepared, xyz_d, outs, warmup, args.inflight)
+    run_stream(L, ctx, prepared, xyz_d, outs, warmup, args.inflight, args.chunk)
     ctx.reset_profile()
-    secs, lat = run_stream(L, ctx, prepared, xyz_d, outs, steps, args.inflight)
+    secs, lat = run_stream(L, ctx, prepared, xyz_d, outs, steps, args.inflight, args.chunk)
     prof = ctx.profile()
     served = steps / secs
     served64 = None
     if fp64_rows is not None:
         vals32 = outs[(steps - 1) % len(outs)].cpu().numpy()
         p64 = L.prepare(fp64_rows)
-        run_stream(L, ctx, p64, xyz_d, outs, warmup, args.inflight)
-        s64, lat64 = run_stream(L, ctx, p64, xyz_d, outs, steps, args.inflight)
+        run_stream(L, ctx, p64, xyz_d, outs, warmup, args.inflight, args.chunk)
+        s64, lat64 = run_stream(L, ctx, p64, xyz_d, outs, steps, args.inflight, args.chunk)
         vals64 = outs[(steps - 1) % len(outs)].cpu().numpy()
         served64 = {"value": steps / s64, "unit": "lattice sums/s",
                     "latency_ms": {"p50": percentile(lat64, 50), "p99": percentile(lat64, 99)}}
@@ -430,7 +440,8 @@ def main():
         "config": {"workload": problem.name, "kernel": "newton" if problem.kind == 0 else "yukawa",
                    "lattice_sites": problem.n_sites, "N": list(problem.N), "M": problem.M,
                    "sample_points": n_pts, "defects": len(problem.defects), "eps": problem.eps,
-                   "slots": args.slots, "max_batch": args.batch, "inflight": args.inflight},
+                   "slots": args.slots, "max_batch": args.batch, "inflight": args.inflight,
+                   "submit_chunk": args.chunk},
         "latency_ms": {"p50": percentile(lat, 50), "p99": percentile(lat, 99)},
         "plain_fp64": {"value": plain, "unit": "lattice sums/s",
                        "latency_ms": {"p50": percentile(plat, 50), "p99": percentile(plat, 99)}},

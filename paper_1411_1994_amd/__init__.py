@@ -262,31 +262,46 @@ class Context:
         (host) or device tensors -- are evaluated as part of the request."""
         return Request(self, problem, nonblocking, points, values)
 
-    def submit_many(self, problems, nonblocking: bool = False) -> list:
-        """Submit several problems at once (no sample points); they enter the queue together, so a
-        slot fuses consecutive canonical ones into one batch."""
-        structs, keeps = [], []
-        for p in problems:
-            if isinstance(p, Prepared):
-                structs.append(p.struct)
-                keeps.append(p)
-            else:
-                st, kp = make_problem(p)
-                structs.append(st)
-                keeps.append(kp)
-        n = len(structs)
-        arr = (lsum_problem * n)(*structs)
-        handles = (C.c_void_p * n)()
-        _check(_lib.lsum_submit_many(self.handle, n, arr, 1 if nonblocking else 0, handles))
+    def submit_many(self, problems, nonblocking: bool = False, points=None, values=None) -> list:
+        """Submit several problems at once; they enter the queue together, so a slot fuses
+        consecutive canonical ones into one batch.  points / values: optional per-problem lists
+        (as for submit; None entries allowed)."""
+        n = len(problems)
+        arr = (lsum_problem * n)()
+        size = C.sizeof(lsum_problem)
         out = []
         for i, p in enumerate(problems):
+            if isinstance(p, Prepared):
+                C.memmove(C.addressof(arr[i]), C.addressof(p.struct), size)
+                keep = [p]
+                prob = p.problem
+            else:
+                st, kp = make_problem(p)
+                C.memmove(C.addressof(arr[i]), C.addressof(st), size)
+                keep = [kp]
+                prob = p
+            pts = points[i] if points is not None else None
+            vals = values[i] if values is not None else None
+            if pts is not None:
+                if isinstance(pts, np.ndarray):
+                    pts = np.ascontiguousarray(pts, dtype=np.float64)
+                    if vals is None:
+                        vals = np.zeros(pts.shape[0])
+                arr[i].n_points = int(pts.shape[0])
+                arr[i].points = _ptr(pts)
+                arr[i].values = _ptr(vals)
+                arr[i].points_on_device = 0 if isinstance(pts, np.ndarray) else 1
+                keep += [pts, vals]
             r = Request.__new__(Request)
             r.ctx = self
-            r.problem = p.problem if isinstance(p, Prepared) else p
-            r._keep = [keeps[i]]
-            r.values = None
-            r.handle = C.c_void_p(handles[i])
+            r.problem = prob
+            r._keep = keep
+            r.values = vals
             out.append(r)
+        handles = (C.c_void_p * n)()
+        _check(_lib.lsum_submit_many(self.handle, n, arr, 1 if nonblocking else 0, handles))
+        for i, r in enumerate(out):
+            r.handle = C.c_void_p(handles[i])
         return out
 
 

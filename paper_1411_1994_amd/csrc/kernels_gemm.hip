@@ -83,18 +83,24 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
     const long stepA = (long)dmA * g.sam + (long)dkA * g.sak;
     const long stepB = (long)dkB * g.sbk + (long)dnB * g.sbn;
     T pa[NA], pb[NB];
+    // Loads are unconditional, so no lane overwrites a register that a load is still filling and
+    // the next chunk stays in flight while the current one is multiplied: an element outside the
+    // operand reads the operand's first element instead (rows and columns past m, n only reach
+    // outputs that are never stored; terms past k are zeroed when staged).
     auto fetch = [&](int k0) {
         const T* a = A + (long)(m0 + mA) * g.sam + (long)(k0 + kA) * g.sak;
+        const bool a_in = m0 + GBM <= g.m && k0 + GK <= g.k;
 #pragma unroll
         for (int t = 0; t < NA; ++t) {
-            const bool ok = m0 + mA + t * dmA < g.m && k0 + kA + t * dkA < g.k;
-            pa[t] = ok ? a[t * stepA] : T(0);
+            const bool ok = a_in || (m0 + mA + t * dmA < g.m && k0 + kA + t * dkA < g.k);
+            pa[t] = *(ok ? a + t * stepA : A);
         }
         const T* b = B + (long)(k0 + kB) * g.sbk + (long)(n0 + nB) * g.sbn;
+        const bool b_in = n0 + GBN <= g.n && k0 + GK <= g.k;
 #pragma unroll
         for (int t = 0; t < NB; ++t) {
-            const bool ok = n0 + nB + t * dnB < g.n && k0 + kB + t * dkB < g.k;
-            pb[t] = ok ? b[t * stepB] : T(0);
+            const bool ok = b_in || (n0 + nB + t * dnB < g.n && k0 + kB + t * dkB < g.k);
+            pb[t] = *(ok ? b + t * stepB : B);
         }
     };
     f16v_g acc[2];
@@ -113,30 +119,32 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
             for (int v = 0; v < 16; ++v) acc64[j][v] = 0.0;
         }
     }
-    fetch(0);
+    if (g.k > 0) fetch(0);   // k = 0: only the beta C epilogue
     for (int k0 = 0; k0 < g.k; k0 += GK) {
 #pragma unroll
         for (int t = 0; t < NA; ++t) {
             const int mm = mA + t * dmA, kk = kA + t * dkA;
+            const T xa = k0 + kk < g.k ? pa[t] : T(0);
             if constexpr (BF) {
-                const float x = pa[t];
+                const float x = xa;
                 const __bf16 hx = (__bf16)x;
                 Ahi[mm][kk] = hx;
                 Alo[mm][kk] = (__bf16)(x - (float)hx);
             } else {
-                As[kk][mm] = pa[t];
+                As[kk][mm] = xa;
             }
         }
 #pragma unroll
         for (int t = 0; t < NB; ++t) {
             const int nn = nB + t * dnB, kk = kB + t * dkB;
+            const T xb = k0 + kk < g.k ? pb[t] : T(0);
             if constexpr (BF) {
-                const float x = pb[t];
+                const float x = xb;
                 const __bf16 hx = (__bf16)x;
                 Bhi[nn][kk] = hx;
                 Blo[nn][kk] = (__bf16)(x - (float)hx);
             } else {
-                Bs[kk][nn] = pb[t];
+                Bs[kk][nn] = xb;
             }
         }
         __syncthreads();
@@ -259,52 +267,40 @@ __global__ void __launch_bounds__(256) k_core(CoreArgs g, int kchunk, typename C
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int wm = wave * 32;
 
-    // register prefetch of one chunk: X3 rows (CK x 64, read as 16-byte vectors: the rows are
-    // 16-byte aligned since ldx is a multiple of 4) and the CK x 24 values of X1, X2
+    // register prefetch of one chunk: X3 rows (CK x 64, read as 16-byte vectors) and the CK x 24
+    // values of X1, X2.  Every load is unconditional from a clamped address inside the operands
+    // (rows past the chunk repeat its last row; columns past r3 stay in the row: ldx3 is a
+    // multiple of 4 and its padding is zero), so no lane overwrites a register a load is still
+    // filling and the loads stay in flight across the multiplication of the current chunk.
+    // Rows past the chunk are zeroed when staged in LDS; out-of-range a, b, c only reach outputs
+    // that are never stored.
     constexpr int VW = 16 / (int)sizeof(T);
     using TV = T __attribute__((ext_vector_type(VW)));
     constexpr int NB = CK * CBN / (256 * VW);                // Y3 vectors per thread
-    constexpr int NXY = (CK * (CTA + CTB) + 255) / 256;      // Y1/Y2 values per thread
+    constexpr int NXY = CK * (CTA + CTB) / 256;              // Y1/Y2 values per thread
+    static_assert(CK * (CTA + CTB) % 256 == 0 && CK * CBN % (256 * VW) == 0, "chunk must tile the workgroup");
     TV pb[NB];
     T pxy[NXY];
     const T* __restrict__ X1 = (const T*)g.X1;
     const T* __restrict__ X2 = (const T*)g.X2;
     const T* __restrict__ X3 = (const T*)g.X3;
+    const int ld1 = (int)g.ldx1, ld2 = (int)g.ldx2, ld3 = (int)g.ldx3;
     auto fetch = [&](int k0) {
 #pragma unroll
         for (int t = 0; t < NB; ++t) {
             const int e = tid + 256 * t;
             const int kk = e / (CBN / VW), cc = (e % (CBN / VW)) * VW;
-            const int nu = k0 + kk, c = c0 + cc;
-            TV v = {};
-            if (nu < kend) {
-                const T* row = X3 + (long)nu * g.ldx3;
-                if (c + VW <= g.r3) {
-                    v = *(const TV*)(row + c);
-                } else {
-#pragma unroll
-                    for (int u = 0; u < VW; ++u)
-                        if (c + u < g.r3) v[u] = row[c + u];
-                }
-            }
-            pb[t] = v;
+            const int nu = min(k0 + kk, kend - 1), c = min(c0 + cc, ld3 - VW);
+            pb[t] = *(const TV*)(X3 + (size_t)nu * ld3 + c);
         }
 #pragma unroll
         for (int t = 0; t < NXY; ++t) {
             const int e = tid + 256 * t;
-            T v = T(0);
-            if (e < CK * (CTA + CTB)) {
-                const int kk = e / (CTA + CTB), cc = e % (CTA + CTB);
-                const int nu = k0 + kk;
-                if (nu < kend) {
-                    if (cc < CTA) {
-                        if (a0 + cc < g.r1) v = X1[(long)nu * g.ldx1 + a0 + cc];
-                    } else if (b0 + cc - CTA < g.r2) {
-                        v = X2[(long)nu * g.ldx2 + b0 + cc - CTA];
-                    }
-                }
-            }
-            pxy[t] = v;
+            const int kk = e / (CTA + CTB), cc = e % (CTA + CTB);
+            const int nu = min(k0 + kk, kend - 1);
+            const T* src = cc < CTA ? X1 + (size_t)nu * ld1 + min(a0 + cc, g.r1 - 1)
+                                    : X2 + (size_t)nu * ld2 + min(b0 + cc - CTA, g.r2 - 1);
+            pxy[t] = *src;
         }
     };
 
@@ -326,33 +322,33 @@ __global__ void __launch_bounds__(256) k_core(CoreArgs g, int kchunk, typename C
         }
     }
 
-    fetch(kbeg);
+    if (kbeg < kend) fetch(kbeg);   // an empty split chunk stores zeros
     for (int k0 = kbeg; k0 < kend; k0 += CK) {
         // registers -> LDS
 #pragma unroll
         for (int t = 0; t < NB; ++t) {
             const int e = tid + 256 * t;
             const int kk = e / (CBN / VW), cc = (e % (CBN / VW)) * VW;
+            const bool live = k0 + kk < kend;
 #pragma unroll
             for (int u = 0; u < VW; ++u) {
                 if constexpr (BF) {
-                    const float x = pb[t][u];
+                    const float x = live ? pb[t][u] : 0.0f;
                     const __bf16 hx = (__bf16)x;
                     Bhi[cc + u][kk] = hx;
                     Blo[cc + u][kk] = (__bf16)(x - (float)hx);
                 } else {
-                    Bs[kk][cc + u] = pb[t][u];
+                    Bs[kk][cc + u] = live ? pb[t][u] : T(0);
                 }
             }
         }
 #pragma unroll
         for (int t = 0; t < NXY; ++t) {
             const int e = tid + 256 * t;
-            if (e < CK * (CTA + CTB)) {
-                const int kk = e / (CTA + CTB), cc = e % (CTA + CTB);
-                if (cc < CTA) Y1s[kk][cc] = pxy[t];
-                else Y2s[kk][cc - CTA] = pxy[t];
-            }
+            const int kk = e / (CTA + CTB), cc = e % (CTA + CTB);
+            const T v = k0 + kk < kend ? pxy[t] : T(0);
+            if (cc < CTA) Y1s[kk][cc] = v;
+            else Y2s[kk][cc - CTA] = v;
         }
         __syncthreads();
         if (k0 + CK < kend) fetch(k0 + CK);

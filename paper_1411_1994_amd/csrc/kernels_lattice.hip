@@ -61,8 +61,9 @@ __global__ void __launch_bounds__(256) k_collocate(int R, const double* __restri
 // --------------------------------------------------------------------------------------------
 typedef double dpair __attribute__((ext_vector_type(2), aligned(8)));
 
+template <int NU>
 __global__ void __launch_bounds__(256) k_shift_sum(const ShiftJob* __restrict__ jobs) {
-    constexpr int QB = 48, NU = 6, TU = 2;
+    constexpr int QB = 8 * NU, TU = 2;
     __shared__ double tile[64][QB + 1];
     const ShiftJob& jb = jobs[blockIdx.y];
     const int N = jb.N_axis;
@@ -85,7 +86,7 @@ __global__ void __launch_bounds__(256) k_shift_sum(const ShiftJob* __restrict__ 
     LSUM_GLOBAL double* __restrict__ UT = (LSUM_GLOBAL double*)jb.UT;
     LSUM_GLOBAL float* __restrict__ UT32 = (LSUM_GLOBAL float*)jb.UT32;
     const bool rows = UT || UT32;
-    for (int q0 = 0; q0 < jb.R; q0 += QB) {
+    for (int q0 = blockIdx.z * QB; q0 < jb.R; q0 += gridDim.z * QB) {
         const int qn = min(QB, jb.R - q0);
         size_t qo[NU];
 #pragma unroll
@@ -127,16 +128,14 @@ __global__ void __launch_bounds__(256) k_shift_sum(const ShiftJob* __restrict__ 
             __syncthreads();
             const int nr = min(64, N - i0);
             const int width = min(QB, jb.ldt - q0);   // includes the zero padding after R
-            if (UT) {
-                for (int rr = wave; rr < nr; rr += 4)
-                    for (int cl = lane; cl < width; cl += 64)
-                        __builtin_nontemporal_store(cl < qn ? tile[rr][cl] : 0.0,
-                                                    &UT[(size_t)(i0 + rr) * jb.ldt + q0 + cl]);
-            } else {
-                for (int rr = wave; rr < nr; rr += 4)
-                    for (int cl = lane; cl < width; cl += 64)
-                        __builtin_nontemporal_store(cl < qn ? (float)tile[rr][cl] : 0.0f,
-                                                    &UT32[(size_t)(i0 + rr) * jb.ldt + q0 + cl]);
+            // (row, column) of the tile flattened over the workgroup, QB columns per row
+            for (int e = threadIdx.x; e < nr * QB; e += 256) {
+                const int rr = e / QB, cl = e - rr * QB;
+                if (cl >= width) continue;
+                const double v = cl < qn ? tile[rr][cl] : 0.0;
+                const size_t o = (size_t)(i0 + rr) * jb.ldt + q0 + cl;
+                if (UT) __builtin_nontemporal_store(v, &UT[o]);
+                else __builtin_nontemporal_store((float)v, &UT32[o]);
             }
             __syncthreads();
         }
@@ -488,11 +487,20 @@ void launch_collocate(hipStream_t st, int R, const double* t_dev, const double* 
     hipLaunchKernelGGL(k_collocate, grid, dim3(256), 0, st, R, t_dev, w13_dev, N_ref, h, G, ldg);
 }
 
-void launch_shift_sum(hipStream_t st, const ShiftJob* jobs_dev, int n_jobs, int max_N, const KTime* kt) {
+void launch_shift_sum(hipStream_t st, const ShiftJob* jobs_dev, int n_jobs, int max_N, int max_R,
+                      const KTime* kt) {
     if (n_jobs <= 0 || max_N <= 0) return;
-    dim3 grid(cdiv(max_N, 64), n_jobs);
-    hipExtLaunchKernelGGL(k_shift_sum, grid, dim3(256), 0, st, kt ? kt->start : nullptr, kt ? kt->stop : nullptr,
-                          0, jobs_dev);
+    // a small batch splits the nodes over the grid's z dimension (blocks of 16) so that the chip
+    // has enough workgroups to cover the L2 latency; a large one takes 48 nodes per workgroup
+    const int tiles = cdiv(max_N, 64) * n_jobs;
+    hipEvent_t a = kt ? kt->start : nullptr, b = kt ? kt->stop : nullptr;
+    if (tiles < 1024 && max_R > 16) {
+        const dim3 grid(cdiv(max_N, 64), n_jobs, cdiv(max_R, 16));
+        hipExtLaunchKernelGGL(k_shift_sum<2>, grid, dim3(256), 0, st, a, b, 0, jobs_dev);
+    } else {
+        const dim3 grid(cdiv(max_N, 64), n_jobs);
+        hipExtLaunchKernelGGL(k_shift_sum<6>, grid, dim3(256), 0, st, a, b, 0, jobs_dev);
+    }
 }
 
 void launch_window_sums(hipStream_t st, int R, const double* G, int ldg, int stride, int n, double* Q) {

@@ -526,7 +526,7 @@ int lsum_shift_sum(lsum_ctx x, void* stream, int R, const double* G_dev, int ldg
     if (!terms.empty())
         LSUM_HIP(hipMemcpyAsync(td.p, terms.data(), terms.size() * sizeof(int2), hipMemcpyHostToDevice, st));
     LSUM_HIP(hipMemcpyAsync(jd.p, &j, sizeof(j), hipMemcpyHostToDevice, st));
-    launch_shift_sum(st, jd.as<ShiftJob>(), 1, N_axis);
+    launch_shift_sum(st, jd.as<ShiftJob>(), 1, N_axis, R);
     LSUM_HIP(hipGetLastError());
     LSUM_HIP(hipStreamSynchronize(st));
     return LSUM_OK;

@@ -114,9 +114,9 @@ struct ShiftJob {
     int ldu;
     int ldt;
 };
-// max_N: largest N_axis of the jobs; kt: optional kernel-bound timing.  Every row read must
+// max_N, max_R: largest N_axis and R of the jobs; kt: optional kernel-bound timing.  Every row read must
 // extend one entry past the last cell window (ldg >= 2 * N_ref - 1 and ldg >= 2).
-void launch_shift_sum(hipStream_t st, const ShiftJob* jobs_dev, int n_jobs, int max_N,
+void launch_shift_sum(hipStream_t st, const ShiftJob* jobs_dev, int n_jobs, int max_N, int max_R,
                       const KTime* kt = nullptr);
 // Q[q, x] = sum_{m=0}^{n-1} G[q, x - m S] over the terms with x - m S >= 0, for x < ldg.
 void launch_window_sums(hipStream_t st, int R, const double* G, int ldg, int stride, int n, double* Q);

@@ -597,7 +597,7 @@ int run_batch(std::vector<Request*>& reqs, hipStream_t st, const hipStream_t* au
     std::vector<int2> terms_h;
     std::vector<ShiftJob> jobs;
     std::vector<size_t> term_off;
-    int maxN = 0;
+    int maxN = 0, maxR = 0;
     double out_bytes = 0, loads = 0;
     std::vector<const RefEntry*> distinct;
     std::vector<int2> tv;
@@ -663,6 +663,7 @@ int run_batch(std::vector<Request*>& reqs, hipStream_t st, const hipStream_t* au
                 j.R = P.R;
                 jobs.push_back(j);
                 maxN = std::max(maxN, P.N[l]);
+                maxR = std::max(maxR, P.R);
                 loads += (double)P.R * P.N[l] * tv.size();
             }
             // algorithmic: the R values per distinct cell, no padding
@@ -682,7 +683,7 @@ int run_batch(std::vector<Request*>& reqs, hipStream_t st, const hipStream_t* au
     LSUM_HIP(hipMemcpyAsync(jobs_d.p, jobs.data(), jobs.size() * sizeof(ShiftJob), hipMemcpyHostToDevice, st));
     // algorithmic traffic: every distinct reference read once, every factor written once
     const KTime kt = tm.kernels("shift_sum", ref_bytes + out_bytes, loads);
-    launch_shift_sum(st, jobs_d.as<ShiftJob>(), (int)jobs.size(), maxN, &kt);
+    launch_shift_sum(st, jobs_d.as<ShiftJob>(), (int)jobs.size(), maxN, maxR, &kt);
     LSUM_HIP(hipGetLastError());
 
     // defect tables (canonical sampling evaluates defect windows from the reference rows)

@@ -150,3 +150,29 @@ def test_submit_many_fuses_one_batch_and_matches_single_submits():
         with pytest.raises(L.LsumError):
             c.submit_many([probs[1], bad, probs[2]])
         assert c.profile()["shift_sum"]["launches"] == 1
+
+
+def test_large_batch_shift_sum_equals_small_batch():
+    # a batch of >= 1024 (64-cell tile, job) pairs takes 48 nodes per workgroup, a small one
+    # splits the nodes over the grid; both add the same terms in the same order per entry
+    require_gpu()
+    import paper_1411_1994_amd as L
+    blk = W.Block((5, 4, 3), (1.0, 1.0, 1.0), (0.0, 0.0, 0.0))
+    p = W.Problem("big", W.NEWTON, 0.0, 30, (2049, 2047, 2045), 0.02, [blk])
+    with L.Context(0, n_slots=1) as c:
+        c.set_option(L.OPT_MAX_BATCH, 1)
+        r = c.submit(p)
+        assert r.wait() == 0
+        alone = r.canonical(0)
+        r.release()
+        c.set_option(L.OPT_MAX_BATCH, 64)
+        reqs = c.submit_many([p] * 12)                   # 12 x 3 jobs x 32 tiles
+        for r in reqs:
+            assert r.wait() == 0
+            assert r.stats()["batch"] == 12
+            assert all(np.array_equal(a, b) for a, b in zip(r.canonical(0), alone))
+            r.release()
+    ref = O.assembled_canonical(p)[0]
+    for a in range(3):
+        floor = 1e-13 * np.max(np.abs(ref[a]), axis=1, keepdims=True)
+        assert np.all(np.abs(alone[a] - ref[a]) <= 1e-12 * np.abs(ref[a]) + floor)
