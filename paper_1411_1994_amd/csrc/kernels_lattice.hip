@@ -437,11 +437,12 @@ __global__ void __launch_bounds__(256) k_snap_points(int n, const double* __rest
     idx[2 * (size_t)n + p] = snap_dev(xyz[3 * (size_t)p + 2], h, N2);
 }
 
-// Tucker value at points after the mode-3 contraction: row p of W (P x r1*r2, layout [p][a*r2+b])
-// holds sum_c mu[a,b,c] Z3[c, i3(p)]; out[p] = sum_a Z1[a, i1(p)] sum_b W[p][a*r2+b] Z2[b, i2(p)].
-// One workgroup per point: the point's Z2 column is staged in LDS, each wave takes a subset of
-// the a rows and reads them contiguously (lanes over b), and the waves' totals are summed in a
-// fixed order.  (Without LDS staging, for r2 beyond the dynamic LDS limit, Z2 is read directly.)
+// Tucker value at points after the mode-3 contraction: row w(t) of W (layout [row][a*r2+b]) holds
+// sum_c mu[a,b,c] Z3[c, i3] for point t's mode-3 cell, and out[o(t)] = sum_a Z1[a, i1(t)] sum_b
+// W[w(t)][a*r2+b] Z2[b, i2(t)] (w, o: identity when null).  One workgroup per point: the point's
+// Z2 column is staged in LDS, each wave takes a subset of the a rows and reads them contiguously
+// (lanes over b), and the waves' totals are summed in a fixed order.  (Without LDS staging, for
+// r2 beyond the dynamic LDS limit, Z2 is read directly.)
 template <bool STAGE>
 __global__ void __launch_bounds__(256) k_tucker_finish(int r1, int r2, int P,
                                                        const double* __restrict__ W,
@@ -449,11 +450,14 @@ __global__ void __launch_bounds__(256) k_tucker_finish(int r1, int r2, int P,
                                                        const double* __restrict__ Z2, int ld2,
                                                        const int32_t* __restrict__ i1,
                                                        const int32_t* __restrict__ i2,
+                                                       const int32_t* __restrict__ wrow,
+                                                       const int32_t* __restrict__ oidx,
                                                        double* __restrict__ out) {
     extern __shared__ double z2s[];           // r2 values
     __shared__ double part[4];
-    const int p = blockIdx.x;
-    const int c1 = i1[p], c2 = i2[p];
+    const int t = blockIdx.x;
+    const int c1 = i1[t], c2 = i2[t];
+    const int p = oidx ? oidx[t] : t;
     if (c1 < 0 || c2 < 0) {                   // uniform per workgroup
         if (threadIdx.x == 0) out[p] = __builtin_nan("");
         return;
@@ -463,7 +467,7 @@ __global__ void __launch_bounds__(256) k_tucker_finish(int r1, int r2, int P,
         __syncthreads();
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const double* w = W + (size_t)p * r1 * r2;
+    const double* w = W + (size_t)(wrow ? wrow[t] : t) * r1 * r2;
     double total = 0.0;
     for (int a = wave; a < r1; a += 4) {
         double acc = 0.0;
@@ -623,14 +627,14 @@ void launch_select_cols(hipStream_t st, int rows, int nsel, const void* Z, long 
 
 void launch_tucker_finish(hipStream_t st, int r1, int r2, int P, const double* W, const double* Z1,
                           int ld1, const double* Z2, int ld2, const int32_t* i1, const int32_t* i2,
-                          double* out) {
+                          const int32_t* wrow, const int32_t* oidx, double* out) {
     if (P <= 0) return;
     if (r2 <= 8192)
         hipLaunchKernelGGL(k_tucker_finish<true>, dim3(P), dim3(256), (size_t)r2 * sizeof(double), st, r1, r2, P,
-                           W, Z1, ld1, Z2, ld2, i1, i2, out);
+                           W, Z1, ld1, Z2, ld2, i1, i2, wrow, oidx, out);
     else
         hipLaunchKernelGGL(k_tucker_finish<false>, dim3(P), dim3(256), 0, st, r1, r2, P, W, Z1, ld1, Z2, ld2, i1,
-                           i2, out);
+                           i2, wrow, oidx, out);
 }
 
 void launch_snap_points(hipStream_t st, int n, const double* xyz, int N0, int N1, int N2, double h,

@@ -234,10 +234,11 @@ void launch_gather_scale_rows(hipStream_t st, int r, int n, const double* X, int
 // Rows of a factor selected by index lists: out[a * nsel + p] = Z[a * ldz + idx[p]]
 void launch_select_cols(hipStream_t st, int rows, int nsel, const void* Z, long ldz,
                         const int32_t* idx, void* out, int elem_size);
-// Tucker values at points from W (P x r1*r2, layout [p][a*r2+b]) and Z1, Z2 rows
+// Tucker values of P points from W (rows r1*r2, layout [row][a*r2+b]) and Z1, Z2 rows: point t
+// reads row wrow[t] and writes out[oidx[t]] (identity where the list is null)
 void launch_tucker_finish(hipStream_t st, int r1, int r2, int P, const double* W, const double* Z1,
                           int ld1, const double* Z2, int ld2, const int32_t* i1, const int32_t* i2,
-                          double* out);
+                          const int32_t* wrow, const int32_t* oidx, double* out);
 void launch_snap_points(hipStream_t st, int n, const double* xyz, int N0, int N1, int N2, double h,
                         int32_t* idx /* 3 x n */);
 

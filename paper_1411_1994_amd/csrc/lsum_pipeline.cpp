@@ -539,42 +539,79 @@ int sample_points(Request* q, hipStream_t st, int n, const double* xyz_d, double
     }
     if ((rc = idx.get(c->pool, (size_t)n * 12))) return rc;
     launch_snap_points(st, n, xyz_d, P.N[0], P.N[1], P.N[2], P.h, idx.as<int32_t>());
-    size_t per = std::max<size_t>(1, (size_t)r1 * r2);
-    int chunk = (int)std::max<size_t>(1, std::min<size_t>((size_t)n, ((size_t)1 << 28) / per));
+    std::vector<int32_t> idx_h((size_t)3 * n);
+    LSUM_HIP(hipMemcpyAsync(idx_h.data(), idx.p, (size_t)n * 12, hipMemcpyDeviceToHost, st));
+    LSUM_HIP(hipStreamSynchronize(st));
+    // The mode-3 contraction W[u][(a,b)] = sum_c mu[(a,b)][c] Z3[c, u] dominates (r1 r2 r3 per
+    // row): it is formed once per distinct mode-3 cell u of the points, in chunks of cells, and
+    // each point then reads its cell's row.  Points are taken in order of their mode-3 cell.
+    std::vector<int32_t> order;
+    order.reserve(n);
+    for (int p = 0; p < n; ++p)
+        if (idx_h[(size_t)2 * n + p] >= 0) order.push_back(p);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+        return idx_h[(size_t)2 * n + x] < idx_h[(size_t)2 * n + y];
+    });
+    std::vector<int32_t> cells;   // distinct mode-3 cells in increasing order
+    std::vector<int32_t> slot(order.size());
+    for (size_t t = 0; t < order.size(); ++t) {
+        const int32_t u = idx_h[(size_t)2 * n + order[t]];
+        if (cells.empty() || cells.back() != u) cells.push_back(u);
+        slot[t] = (int32_t)cells.size() - 1;
+    }
+    const size_t per = std::max<size_t>(1, (size_t)r1 * r2);
+    int chunk = (int)std::max<size_t>(1, std::min<size_t>(cells.size(), ((size_t)1 << 28) / per));
     chunk = std::min(chunk, 4096);
     if ((rc = W.get(c->pool, per * chunk * 8))) return rc;
     if ((rc = Z3s.get(c->pool, (size_t)r3 * chunk * 8))) return rc;
     if ((rc = i3c.get(c->pool, (size_t)chunk * 4))) return rc;
-    std::vector<int32_t> idx_h((size_t)3 * n);
-    LSUM_HIP(hipMemcpyAsync(idx_h.data(), idx.p, (size_t)n * 12, hipMemcpyDeviceToHost, st));
-    LSUM_HIP(hipStreamSynchronize(st));
-    std::vector<int32_t> i3(chunk);
-    for (int p0 = 0; p0 < n; p0 += chunk) {
-        const int Pn = std::min(chunk, n - p0);
-        for (int p = 0; p < Pn; ++p) i3[p] = std::max(0, idx_h[(size_t)2 * n + p0 + p]);
-        LSUM_HIP(hipMemcpyAsync(i3c.p, i3.data(), Pn * 4, hipMemcpyHostToDevice, st));
-        launch_select_cols(st, r3, Pn, q->Z[2].p, P.N[2], i3c.as<int32_t>(), Z3s.p, 8);
-        // W[p][(a,b)] = sum_c Z3s[c][p] mu[(a,b)][c]: point-major, so each point's row is contiguous
+    DevBuf lists;
+    if ((rc = lists.get(c->pool, std::max<size_t>(1, order.size()) * 16))) return rc;
+    std::vector<int32_t> lh(4 * std::max<size_t>(1, order.size()));
+    size_t t0 = 0;
+    for (size_t u0 = 0; u0 < cells.size(); u0 += chunk) {
+        const int Un = (int)std::min<size_t>(chunk, cells.size() - u0);
+        size_t t1 = t0;
+        while (t1 < order.size() && slot[t1] < (int32_t)(u0 + Un)) ++t1;
+        const int Pn = (int)(t1 - t0);
+        // per point of the chunk: i1, i2, row of W, output index
+        int32_t* i1h = lh.data();
+        int32_t* i2h = i1h + Pn;
+        int32_t* wrh = i2h + Pn;
+        int32_t* ooh = wrh + Pn;
+        for (int k = 0; k < Pn; ++k) {
+            const int32_t p = order[t0 + k];
+            i1h[k] = idx_h[p];
+            i2h[k] = idx_h[(size_t)n + p];
+            wrh[k] = slot[t0 + k] - (int32_t)u0;
+            ooh[k] = p;
+        }
+        LSUM_HIP(hipMemcpyAsync(i3c.p, cells.data() + u0, (size_t)Un * 4, hipMemcpyHostToDevice, st));
+        LSUM_HIP(hipMemcpyAsync(lists.p, lh.data(), (size_t)Pn * 16, hipMemcpyHostToDevice, st));
+        launch_select_cols(st, r3, Un, q->Z[2].p, P.N[2], i3c.as<int32_t>(), Z3s.p, 8);
+        // W[u][(a,b)] = sum_c Z3s[c][u] mu[(a,b)][c]: row-major per cell, so each row is contiguous
         GemmArgs a{};
-        a.m = Pn; a.n = r1 * r2; a.k = r3;
-        a.A = Z3s.p; a.sam = 1; a.sak = Pn;
+        a.m = Un; a.n = r1 * r2; a.k = r3;
+        a.A = Z3s.p; a.sam = 1; a.sak = Un;
         a.B = core_d; a.sbk = 1; a.sbn = r3;
         a.C = W.p; a.scm = (long)r1 * r2; a.scn = 1;
         a.alpha = 1.0; a.beta = 0.0; a.batch = 1;
         launch_gemm(st, GEMM_F64, a);
+        const int32_t* ld = lists.as<int32_t>();
         launch_tucker_finish(st, r1, r2, Pn, W.as<double>(), q->Z[0].as<double>(), P.N[0], q->Z[1].as<double>(),
-                             P.N[1], idx.as<int32_t>() + p0, idx.as<int32_t>() + n + p0, out_d + p0);
-        LSUM_HIP(hipStreamSynchronize(st));   // i3c is rewritten by the next chunk
+                             P.N[1], ld, ld + Pn, ld + 2 * Pn, ld + 3 * Pn, out_d);
+        LSUM_HIP(hipStreamSynchronize(st));   // i3c and the lists are rewritten by the next chunk
+        t0 = t1;
     }
-    bool any_out = false;
-    for (int p = 0; p < n; ++p) any_out |= idx_h[(size_t)2 * n + p] < 0;
-    if (any_out) {
+    if (order.size() < (size_t)n) {
+        // points outside the grid along axis 3 (axes 1 and 2 are marked by the finishing kernel)
         std::vector<double> o(n);
         LSUM_HIP(hipMemcpyAsync(o.data(), out_d, (size_t)n * 8, hipMemcpyDeviceToHost, st));
         LSUM_HIP(hipStreamSynchronize(st));
         for (int p = 0; p < n; ++p)
             if (idx_h[(size_t)2 * n + p] < 0) o[p] = std::nan("");
         LSUM_HIP(hipMemcpyAsync(out_d, o.data(), (size_t)n * 8, hipMemcpyHostToDevice, st));
+        LSUM_HIP(hipStreamSynchronize(st));
     }
     LSUM_HIP(hipGetLastError());
     return LSUM_OK;

@@ -173,10 +173,17 @@ def test_rhosvd_fp64_matches_oracle(ctx, kind, param, eps):
         assert np.max(np.abs(Z[a] @ Z[a].T - np.eye(Z[a].shape[0]))) < 1e-11
     mu = np.einsum("ijk,ai,bj,ck->abc", full, *Z, optimize=True)
     assert np.max(np.abs(mu - core)) <= 1e-11 * np.max(np.abs(mu))
-    # points: Tucker sampling equals the tile values
+    # points: Tucker sampling equals the tile values, for points in any order that share
+    # mode-3 cells (each distinct cell is contracted once) or repeat, and points outside the
+    # grid along any axis are NaN
     rng = np.random.default_rng(1)
     pts = np.stack([rng.integers(0, n, 64) for n in p.N], axis=1)
-    v = r.sample(cells_xyz(p, pts))
+    pts = np.concatenate([pts, pts[::7]])
+    far = np.array([[0.0, 0.0, 1e3], [1e3, 0.0, 0.0], [0.0, -1e3, 0.0]])
+    xyz = np.concatenate([cells_xyz(p, pts)[:40], far, cells_xyz(p, pts)[40:]])
+    v = r.sample(xyz)
+    assert np.all(np.isnan(v[40:43]))
+    v = np.concatenate([v[:40], v[43:]])
     assert np.allclose(v, tile[pts[:, 0], pts[:, 1], pts[:, 2]], rtol=1e-12, atol=1e-12 * np.max(np.abs(tile)))
     r.release()
 
