@@ -7,8 +7,10 @@ point-major factors and the 1e5-point evaluation, submitted as one request whose
 already resident in HBM.
 
 Two paths on the same GPU:
-  * served: requests kept in flight on several stream slots; consecutive requests are fused
-    into batches whose shift-sums run as one launch; reference vectors shared through the cache;
+  * served: requests submitted in chunks (one lsum_submit_many call each) and kept in flight on
+    several stream slots; a chunk is one batch whose shift-sums run as one launch and whose
+    points are sampled in one launch; reference vectors shared through the cache; canonical
+    factors stored in FP32 for sampling (FP64 products and sums);
   * plain FP64: one request at a time, one slot, no batching, no reference cache.
 `value` is the served throughput (lattice sums/s); p50/p99 latency, the plain throughput, the
 error against the CPU oracle's brute-force sum, the roofline of the dominant kernel (event-timed
@@ -48,10 +50,11 @@ def parse():
     ap.add_argument("--warmup", type=int, default=128)
     ap.add_argument("--workload", default="cfg2", choices=["cfg2", "cfg3", "cfg4", "mix"])
     ap.add_argument("--requests", type=int, default=32, help="requests of the served mix")
-    ap.add_argument("--inflight", type=int, default=64)
+    ap.add_argument("--inflight", type=int, default=128)
     ap.add_argument("--slots", type=int, default=4)
-    ap.add_argument("--batch", type=int, default=16)
-    ap.add_argument("--chunk", type=int, default=1, help="requests per submit call of the served stream")
+    ap.add_argument("--batch", type=int, default=32)
+    ap.add_argument("--chunk", type=int, default=32,
+                    help="requests per submit call of the served stream (one batch each)")
     ap.add_argument("--plain-steps", type=int, default=256)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
@@ -135,10 +138,12 @@ def dominant_roofline(prof: dict, dtype_peak: str):
                   "avg_launch_ms": ms, "launches": st["launches"], "bytes_per_launch": st["bytes"] / n}
 
 
-def traffic_from_profiles(stage: str):
-    """HBM bytes per launch from committed rocprofv3 --pmc summaries, if they were taken on the
-    current kernel source (their recorded source hash must match)."""
-    path = os.path.join(ROOT, "profiles", f"pmc_{stage}.json")
+def traffic_from_profiles(name: str, units_per_launch: float):
+    """HBM bytes per launch from committed rocprofv3 --pmc summaries: FETCH_SIZE and WRITE_SIZE
+    per unit of work (a request's points, a shift-sum job), each scaled by what the counter reads
+    for a plain copy of known size, times the units one launch of this run processes.  None
+    unless the counters were taken on the current kernel source (the recorded hash matches)."""
+    path = os.path.join(ROOT, "profiles", f"pmc_{name}.json")
     if not os.path.exists(path):
         return None
     try:
@@ -147,7 +152,7 @@ def traffic_from_profiles(stage: str):
         sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
         if sha != rec.get("source_sha256"):
             return None
-        return rec["hbm_bytes_per_launch"]
+        return rec["hbm_bytes_per_unit"] * units_per_launch
     except Exception:
         return None
 
@@ -401,7 +406,7 @@ def main():
         _, ss_batched = dominant_roofline({"shift_sum": bprof["shift_sum"]}, "f64")
         if ss_batched is not None:
             ss_batched["jobs_per_launch"] = jobs / max(1, bprof["shift_sum"]["launches"])
-            ss_batched["traffic"] = None
+            ss_batched["traffic"] = traffic_from_profiles("shift_sum_batched", ss_batched["jobs_per_launch"])
 
     # ---- accuracy of the served result against the oracle's brute-force sum ------------
     vals = vals32 if fp64_rows is not None else outs[(steps - 1) % len(outs)].cpu().numpy()
@@ -416,14 +421,14 @@ def main():
     # canonical output at FP32 precision: FP32-rounded factor rows, FP64 products and sums
     dtype = "f64" if problem.precision == W.FP64 else ("f32" if problem.precision == W.FP32 or cfg == 2 else "bf16x3")
     stage, roof = dominant_roofline(prof, dtype)
-    if roof is not None:
-        roof["traffic"] = traffic_from_profiles(stage)
-    # the shift-sum kernel's own roofline beside the dominant one
+    if roof is not None and cfg == 2 and stage == "sample":
+        # the counters were taken per request of 1e5 points on FP32 rows (the served policy)
+        roof["traffic"] = traffic_from_profiles("sample", steps / max(1, prof["sample"]["launches"]))
+    # the shift-sum kernel's own roofline beside the dominant one (small served batches: the
+    # per-launch table reads make a per-job traffic figure meaningless, so none is given)
     roof_ss = None
     if "shift_sum" in prof and prof["shift_sum"]["launches"] > 0:
         _, roof_ss = dominant_roofline({"shift_sum": prof["shift_sum"]}, dtype)
-        if roof_ss is not None:
-            roof_ss["traffic"] = traffic_from_profiles("shift_sum")
     out = {
         "metric": METRIC,
         "value": served,

@@ -287,10 +287,11 @@ class Context:
                     pts = np.ascontiguousarray(pts, dtype=np.float64)
                     if vals is None:
                         vals = np.zeros(pts.shape[0])
-                arr[i].n_points = int(pts.shape[0])
-                arr[i].points = _ptr(pts)
-                arr[i].values = _ptr(vals)
-                arr[i].points_on_device = 0 if isinstance(pts, np.ndarray) else 1
+                e = arr[i]
+                e.n_points = int(pts.shape[0])
+                e.points = _ptr(pts)
+                e.values = _ptr(vals)
+                e.points_on_device = 0 if isinstance(pts, np.ndarray) else 1
                 keep += [pts, vals]
             r = Request.__new__(Request)
             r.ctx = self

@@ -81,12 +81,67 @@ int lsum_destroy(lsum_ctx x) {
 }
 
 // a validated, planned request that is not queued yet
+// The fields make_plan reads, appended one by one (no struct padding), as a cache key.
+static bool plan_key(const lsum_problem& p, std::string& key) {
+    if (p.n_blocks < 1 || !p.blocks || p.n_blocks > 64 || p.n_defects < 0 || p.n_defects > 4096 ||
+        (p.n_defects > 0 && !p.defects))
+        return false;
+    auto put = [&](const void* v, size_t n) { key.append((const char*)v, n); };
+    put(&p.kernel.kind, sizeof(int));
+    put(&p.kernel.param, sizeof(double));
+    put(&p.kernel.M, sizeof(int));
+    put(&p.kernel.h_u, sizeof(double));
+    put(&p.kernel.s, sizeof(double));
+    put(p.N, sizeof(p.N));
+    put(&p.h, sizeof(double));
+    put(&p.eps, sizeof(double));
+    put(&p.precision, sizeof(int));
+    put(p.tile_lo, sizeof(p.tile_lo));
+    put(p.tile_T, sizeof(p.tile_T));
+    put(&p.n_blocks, sizeof(int));
+    for (int b = 0; b < p.n_blocks; ++b) {
+        const lsum_block& k = p.blocks[b];
+        put(k.L, sizeof(k.L));
+        put(k.b, sizeof(k.b));
+        put(k.center, sizeof(k.center));
+        put(&k.charge, sizeof(double));
+    }
+    put(&p.n_defects, sizeof(int));
+    for (int d = 0; d < p.n_defects; ++d) {
+        const lsum_defect& k = p.defects[d];
+        put(&k.block, sizeof(int));
+        put(k.site, sizeof(k.site));
+        put(&k.dZ, sizeof(double));
+    }
+    return true;
+}
+
+// The plan of a problem: from the context's cache when the same problem was planned before.
+static int plan_for(Context& c, const lsum_problem& p, Plan& out) {
+    std::string key;
+    const bool cacheable = plan_key(p, key);
+    if (cacheable) {
+        std::lock_guard<std::mutex> lk(c.plan_mu);
+        auto it = c.plans.find(key);
+        if (it != c.plans.end()) {
+            out = *it->second;
+            return LSUM_OK;
+        }
+    }
+    const int rc = make_plan(p, out);
+    if (rc != LSUM_OK || !cacheable) return rc;
+    std::lock_guard<std::mutex> lk(c.plan_mu);
+    if (c.plans.size() >= 256) c.plans.clear();
+    c.plans.emplace(std::move(key), std::make_shared<const Plan>(out));
+    return LSUM_OK;
+}
+
 static int prepare_request(lsum_ctx x, const lsum_problem* p, lsum_req_s** out) {
     auto* r = new lsum_req_s();
     Request& q = r->q;
     q.ctx_ref = x->sp;
     q.ctx = &x->c;
-    int rc = make_plan(*p, q.plan);
+    int rc = plan_for(x->c, *p, q.plan);
     if (rc != LSUM_OK) {
         delete r;
         return rc;
@@ -386,11 +441,13 @@ int lsum_release(lsum_req r) {
     Context& c = *q.ctx;
     (void)hipSetDevice(c.device);
     drop_reference(&q);
+    bool waiting;   // queued requests may be waiting for the memory this one frees
     {
         std::lock_guard<std::mutex> lk(c.mu);
         c.used -= std::min(c.used, q.retained);
+        waiting = !c.queue.empty() && q.retained > 0;
     }
-    c.cv.notify_all();
+    if (waiting) c.cv.notify_all();
     delete r;
     return LSUM_OK;
 }

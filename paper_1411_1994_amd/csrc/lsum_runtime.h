@@ -9,6 +9,7 @@
 #include <condition_variable>
 #include <deque>
 #include <map>
+#include <unordered_map>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -149,6 +150,10 @@ struct Context {
     std::map<RefKey, std::shared_ptr<RefEntry>> refs;
     size_t ref_bytes = 0, ref_cap = (size_t)4 << 30;
     uint64_t ref_clock = 0;
+    // plans of recently submitted problems, keyed by the problem's contents (a server sees the
+    // same lattice many times); a plan depends on nothing else
+    std::mutex plan_mu;
+    std::unordered_map<std::string, std::shared_ptr<const Plan>> plans;
     // stage profile
     std::mutex prof_mu;
     std::map<std::string, StageStat> profile;
