@@ -80,21 +80,10 @@ __device__ __forceinline__ bool coupled(double gaa, double gbb, double gab, doub
 }
 
 // Round-robin pairing of the 16 columns for the 15 steps of an inner sweep: step t pairs
-// (15, t) and ((t + i) % 15, (t - i + 15) % 15) for i = 1..7.
-struct InnerPairs {
-    int8_t p[15][8], q[15][8];
-    constexpr InnerPairs() : p{}, q{} {
-        for (int t = 0; t < 15; ++t) {
-            p[t][0] = 15;
-            q[t][0] = (int8_t)t;
-            for (int i = 1; i < 8; ++i) {
-                p[t][i] = (int8_t)((t + i) % 15);
-                q[t][i] = (int8_t)((t - i + 15) % 15);
-            }
-        }
-    }
-};
-__constant__ constexpr InnerPairs kInner{};
+// (15, t) and ((t + i) % 15, (t - i + 15) % 15) for i = 1..7.  Computed in registers (a table in
+// memory would cost a load round trip per step).
+__device__ __forceinline__ int inner_p(int t, int i) { return i == 0 ? 15 : (t + i >= 15 ? t + i - 15 : t + i); }
+__device__ __forceinline__ int inner_q(int t, int i) { return i == 0 ? t : (t - i < 0 ? t - i + 15 : t - i); }
 
 __global__ void __launch_bounds__(64) k_pair_eig(int nchunk, const double* __restrict__ part, double tol,
                                                  double irr2, int max_inner, double* __restrict__ Qout,
@@ -141,7 +130,7 @@ __global__ void __launch_bounds__(64) k_pair_eig(int nchunk, const double* __res
         double mx = 0.0;
         for (int step = 0; step < 15; ++step) {
             if (lane < 8) {
-                const int p = kInner.p[step][lane], q = kInner.q[step][lane];
+                const int p = inner_p(step, lane), q = inner_q(step, lane);
                 const double a = G[p][p], d = G[q][q], b = G[p][q];
                 double c = 1.0, s = 0.0;
                 if (coupled(a, d, b, irr2)) {
@@ -170,8 +159,8 @@ __global__ void __launch_bounds__(64) k_pair_eig(int nchunk, const double* __res
             }
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            const int pi = kInner.p[step][bi], qi = kInner.q[step][bi];
-            const int pj = kInner.p[step][bj], qj = kInner.q[step][bj];
+            const int pi = inner_p(step, bi), qi = inner_q(step, bi);
+            const int pj = inner_p(step, bj), qj = inner_q(step, bj);
             const double ci = cs[bi][0], si = cs[bi][1], cj = cs[bj][0], sj = cs[bj][1];
             // G block [pi qi] x [pj qj]
             const double g00 = G[pi][pj], g01 = G[pi][qj], g10 = G[qi][pj], g11 = G[qi][qj];
