@@ -80,22 +80,21 @@ def percentile(x, q):
 
 def run_stream(L, ctx, problem, points, outs, steps, inflight, chunk=1):
     """Submit `steps` requests keeping at most `inflight` in flight, `chunk` at a time (one
-    lsum_submit_many call per chunk once that many have finished); returns (seconds,
-    latencies).  `problem` is marshalled once (L.prepare); the library copies it at every
+    lsum_submit_many call per chunk once that many have finished, which are harvested with one
+    lsum_finish_many call); returns (seconds, latencies).  `problem` is marshalled once (L.prepare); the library copies it at every
     submit."""
     import torch
     from collections import deque
     q = deque()
     lat = []
 
-    def harvest():
-        r = q.popleft()
-        rc = r.wait()
-        if rc != 0:
-            raise RuntimeError(f"request failed: {rc}")
-        inf = r.info()
-        lat.append(inf.t_queue_ms + inf.t_run_ms)
-        r.release()
+    def harvest(k=1):
+        # the k oldest requests, finished with one library call (wait, info, release)
+        done = [q.popleft() for _ in range(min(k, len(q)))]
+        for rc, inf in L.finish_many(done):
+            if rc != 0:
+                raise RuntimeError(f"request failed: {rc}")
+            lat.append(inf.t_queue_ms + inf.t_run_ms)
 
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -103,7 +102,7 @@ def run_stream(L, ctx, problem, points, outs, steps, inflight, chunk=1):
     while i < steps:
         k = min(chunk, steps - i, inflight)
         while len(q) + k > inflight:
-            harvest()
+            harvest(len(q) + k - inflight)
         if k == 1:
             q.append(ctx.submit(problem, points=points, values=outs[i % len(outs)]))
         else:
@@ -111,7 +110,7 @@ def run_stream(L, ctx, problem, points, outs, steps, inflight, chunk=1):
                                      values=[outs[(i + j) % len(outs)] for j in range(k)]))
         i += k
     while q:
-        harvest()
+        harvest(len(q))
     torch.cuda.synchronize()
     return time.perf_counter() - t0, lat
 

@@ -254,6 +254,11 @@ int lsum_get_tile(lsum_req req, void* out, int elem_size, int on_device);
 int lsum_get_stats(lsum_req req, char* buf, size_t len);
 /* Free the request's device results and the handle. */
 int lsum_release(lsum_req req);
+/* Finish n requests in order: wait for each (no time limit), write its final status to
+ * status[i] and, if info is not null, its lsum_info to info[i], then release it.  One call for
+ * a client that harvests a batch of requests at once; the handles are invalid afterwards.
+ * Returns LSUM_E_INVALID for a null request array or a null entry (nothing is released then). */
+int lsum_finish_many(int n, lsum_req* req, int* status, lsum_info* info);
 
 #ifdef __cplusplus
 }

@@ -29,7 +29,7 @@ SYMBOLS = ["lsum_nodes", "lsum_block_offsets", "lsum_create", "lsum_destroy", "l
            "lsum_contract",
            "lsum_submit", "lsum_submit_many", "lsum_wait", "lsum_cancel", "lsum_get_info", "lsum_get_canonical",
            "lsum_get_tucker", "lsum_get_sigma", "lsum_sample", "lsum_get_tile", "lsum_get_stats",
-           "lsum_release", "lsum_set_option", "lsum_get_profile", "lsum_reset_profile"]
+           "lsum_release", "lsum_finish_many", "lsum_set_option", "lsum_get_profile", "lsum_reset_profile"]
 OPT_MAX_BATCH, OPT_REF_CACHE_BYTES, OPT_RANGE_MIN = 1, 2, 3
 
 
@@ -106,6 +106,7 @@ def _load():
         "lsum_get_tile": (I, [VP, VP, I, I]),
         "lsum_get_stats": (I, [VP, C.c_char_p, C.c_size_t]),
         "lsum_release": (I, [VP]),
+        "lsum_finish_many": (I, [I, P(VP), P(I), P(lsum_info)]),
         "lsum_set_option": (I, [VP, I, D]),
         "lsum_get_profile": (I, [VP, C.c_char_p, C.c_size_t]),
         "lsum_reset_profile": (I, [VP]),
@@ -304,6 +305,19 @@ class Context:
         for i, r in enumerate(out):
             r.handle = C.c_void_p(handles[i])
         return out
+
+
+def finish_many(requests):
+    """Wait for, describe and release several requests with one library call
+    (``lsum_finish_many``); returns [(status, lsum_info)] in order.  The requests are released."""
+    n = len(requests)
+    handles = (C.c_void_p * n)(*[r.handle for r in requests])
+    status = (C.c_int * n)()
+    infos = (lsum_info * n)()
+    _check(_lib.lsum_finish_many(n, handles, status, infos))
+    for r in requests:
+        r.handle = None
+    return [(status[i], infos[i]) for i in range(n)]
 
 
 class Prepared:

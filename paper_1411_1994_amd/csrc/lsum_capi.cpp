@@ -452,6 +452,19 @@ int lsum_release(lsum_req r) {
     return LSUM_OK;
 }
 
+int lsum_finish_many(int n, lsum_req* r, int* status, lsum_info* info) {
+    if (n < 0 || (n > 0 && (!r || !status))) return fail(LSUM_E_INVALID, "null argument");
+    for (int i = 0; i < n; ++i)
+        if (!r[i]) return fail(LSUM_E_INVALID, "null request");
+    for (int i = 0; i < n; ++i) {
+        status[i] = lsum_wait(r[i], -1);
+        if (info) lsum_get_info(r[i], info + i);
+        lsum_release(r[i]);
+        r[i] = nullptr;
+    }
+    return LSUM_OK;
+}
+
 int lsum_set_option(lsum_ctx x, int key, double value) {
     if (!x) return fail(LSUM_E_INVALID, "null ctx");
     Context& c = x->c;

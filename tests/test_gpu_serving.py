@@ -176,3 +176,27 @@ def test_large_batch_shift_sum_equals_small_batch():
     for a in range(3):
         floor = 1e-13 * np.max(np.abs(ref[a]), axis=1, keepdims=True)
         assert np.all(np.abs(alone[a] - ref[a]) <= 1e-12 * np.abs(ref[a]) + floor)
+
+
+def test_finish_many_matches_one_by_one():
+    # lsum_finish_many waits, reports and releases a set of requests in one call; the values and
+    # the reported info are those of waiting on each request
+    require_gpu()
+    import paper_1411_1994_amd as L
+    probs = mixed_problems(6, seed=33)
+    rng = np.random.default_rng(4)
+    pts = [rng.uniform(-np.array(W.half_widths(p)), np.array(W.half_widths(p)), size=(97, 3)) for p in probs]
+    with L.Context(0, n_slots=2) as c:
+        one = []
+        for p, x in zip(probs, pts):
+            r = c.submit(p, points=x)
+            assert r.wait() == 0
+            one.append((r.values.copy(), r.info().R))
+            r.release()
+        reqs = c.submit_many(probs, points=pts)
+        res = L.finish_many(reqs)
+        assert all(r.handle is None for r in reqs)
+        for (rc, inf), r, (v, R) in zip(res, reqs, one):
+            assert rc == 0 and inf.status == 0 and inf.R == R and inf.t_run_ms >= 0.0
+            assert np.array_equal(r.values, v)
+        assert L.finish_many([]) == []
