@@ -177,9 +177,18 @@ def cpu_baseline(problem, xyz, seconds):
     if proc:
         c1 = proc.cpu_times()
         cores = round(((c1.user - c0.user) + (c1.system - c0.system)) / wall, 2)
+    # the oracle's direct sum (every charge at every point, no factorisation over the axes)
+    t, _ = O.quadrature_of(problem)
+    n_charges = len(O.charges(problem)[0])
+    cells = O.points_to_cells(xyz[:8], problem.h, problem.N)
+    d0 = time.perf_counter()
+    O.brute_force_points(problem, cells)
+    dwall = time.perf_counter() - d0
     return {"value": n / wall, "unit": "lattice sums/s", "cores": cores, "kind": "oracle",
             "sample": f"{n} full lattice sums of the same workload (nodes, collocation, 1D shift-sums, "
-                      f"{len(xyz)} sampled points) in {wall:.1f} s", "host_cpus": os.cpu_count()}
+                      f"{len(xyz)} sampled points) in {wall:.1f} s", "host_cpus": os.cpu_count(),
+            "direct_sum": {"value": len(cells) * n_charges * len(t) / dwall, "unit": "point-charge-node terms/s",
+                           "sample": f"{len(cells)} points x {n_charges} charges x {len(t)} nodes in {dwall:.2f} s"}}
 
 
 def run_mix(args):
