@@ -79,38 +79,38 @@ def percentile(x, q):
 
 
 def run_stream(L, ctx, problem, points, outs, steps, inflight, chunk=1):
-    """Submit `steps` requests keeping at most `inflight` in flight, `chunk` at a time (one
-    lsum_submit_many call per chunk once that many have finished, which are harvested with one
-    lsum_finish_many call); returns (seconds, latencies).  `problem` is marshalled once (L.prepare); the library copies it at every
-    submit."""
+    """Submit `steps` requests keeping at most `inflight` in flight, `chunk` at a time: each chunk
+    is a RequestSet (one lsum_submit_many call), submitted once that many have finished and
+    harvested with one lsum_finish_many call; returns (seconds, latencies).  `problem` is
+    marshalled once (L.prepare); the library copies it at every submit."""
     import torch
     from collections import deque
     q = deque()
     lat = []
+    n_in = 0
 
-    def harvest(k=1):
-        # the k oldest requests, finished with one library call (wait, info, release)
-        done = [q.popleft() for _ in range(min(k, len(q)))]
-        for rc, inf in L.finish_many(done):
-            if rc != 0:
-                raise RuntimeError(f"request failed: {rc}")
-            lat.append(inf.t_queue_ms + inf.t_run_ms)
+    def harvest():
+        nonlocal n_in
+        rs = q.popleft()
+        status, infos = rs.finish()
+        for k in range(rs.n):
+            if status[k] != 0:
+                raise RuntimeError(f"request failed: {status[k]}")
+            lat.append(infos[k].t_queue_ms + infos[k].t_run_ms)
+        n_in -= rs.n
 
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     i = 0
     while i < steps:
         k = min(chunk, steps - i, inflight)
-        while len(q) + k > inflight:
-            harvest(len(q) + k - inflight)
-        if k == 1:
-            q.append(ctx.submit(problem, points=points, values=outs[i % len(outs)]))
-        else:
-            q.extend(ctx.submit_many([problem] * k, points=[points] * k,
-                                     values=[outs[(i + j) % len(outs)] for j in range(k)]))
+        while n_in + k > inflight:
+            harvest()
+        q.append(ctx.submit_set(problem, k, points=points, values=[outs[(i + j) % len(outs)] for j in range(k)]))
+        n_in += k
         i += k
     while q:
-        harvest(len(q))
+        harvest()
     torch.cuda.synchronize()
     return time.perf_counter() - t0, lat
 

@@ -263,6 +263,10 @@ class Context:
         (host) or device tensors -- are evaluated as part of the request."""
         return Request(self, problem, nonblocking, points, values)
 
+    def submit_set(self, prepared, n, points=None, values=None, nonblocking: bool = False) -> "RequestSet":
+        """n requests of one problem as a RequestSet (one library call to submit, one to finish)."""
+        return RequestSet(self, prepared, n, points, values, nonblocking)
+
     def submit_many(self, problems, nonblocking: bool = False, points=None, values=None) -> list:
         """Submit several problems at once; they enter the queue together, so a slot fuses
         consecutive canonical ones into one batch.  points / values: optional per-problem lists
@@ -318,6 +322,63 @@ def finish_many(requests):
     for r in requests:
         r.handle = None
     return [(status[i], infos[i]) for i in range(n)]
+
+
+def problem_array(prepared, n, points=None, values=None):
+    """n copies of a prepared problem's C struct in one array (one copy), with request k's point
+    and value pointers written in by vectorised stores (pure marshalling, no library call)."""
+    size = C.sizeof(lsum_problem)
+    arr = (lsum_problem * n).from_buffer_copy(bytes(prepared.struct) * n)
+    if points is not None:
+        pts = points if isinstance(points, (list, tuple)) else [points] * n
+        if values is None or len(values) != n or len(pts) != n:
+            raise ValueError("points need n output arrays")
+        rows = np.frombuffer(arr, dtype=np.uint8).reshape(n, size)
+
+        def put(field, vals, dtype):
+            off = getattr(lsum_problem, field).offset
+            width = np.dtype(dtype).itemsize
+            rows[:, off:off + width] = np.asarray(vals, dtype=dtype).view(np.uint8).reshape(n, width)
+
+        put("n_points", [int(x.shape[0]) for x in pts], np.int32)
+        put("points", [_ptr(x) for x in pts], np.uint64)
+        put("values", [_ptr(v) for v in values], np.uint64)
+        put("points_on_device", [0 if isinstance(x, np.ndarray) else 1 for x in pts], np.int32)
+    return arr
+
+
+class RequestSet:
+    """n requests of one prepared problem, submitted with one ``lsum_submit_many`` call and finished
+    with one ``lsum_finish_many`` call; for clients that submit and collect in batches.  points: one
+    array/tensor shared by all requests or a list of n; values: a list of n outputs (device tensors
+    or numpy arrays, caller-owned until the set is finished)."""
+
+    def __init__(self, ctx, prepared, n, points=None, values=None, nonblocking=False):
+        if not isinstance(prepared, Prepared):
+            prepared = Prepared(prepared)
+        self.ctx, self.n, self.problem = ctx, n, prepared.problem
+        self._arr = problem_array(prepared, n, points, values)
+        self._keep = [prepared, points, values]
+        self._handles = None
+        handles = (C.c_void_p * n)()
+        _check(_lib.lsum_submit_many(ctx.handle, n, self._arr, 1 if nonblocking else 0, handles))
+        self._handles = handles
+        self.values = values
+
+    def finish(self):
+        """Wait for, report and release every request: (status array, lsum_info array)."""
+        status = (C.c_int * self.n)()
+        infos = (lsum_info * self.n)()
+        _check(_lib.lsum_finish_many(self.n, self._handles, status, infos))
+        self._handles = None
+        return status, infos
+
+    def __del__(self):
+        try:
+            if self._handles is not None:
+                self.finish()
+        except Exception:
+            pass
 
 
 class Prepared:

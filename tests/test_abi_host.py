@@ -107,3 +107,29 @@ def test_host_errors():
     with pytest.raises(L.LsumError) as e:
         L.lsum_block_offsets(W.cubic_block(30, 1.0), (21, 21, 21), 0.1)  # outside the grid
     assert e.value.code == -2
+
+
+def test_problem_array_marshals_points_and_values():
+    # a RequestSet's struct array: n copies of the prepared problem with request k's point and
+    # value pointers written in; every other field equals the prepared struct's
+    import ctypes as C
+    import numpy as np
+    import paper_1411_1994_amd as L
+    import workloads as W
+    p = W.Problem("pa", W.NEWTON, 0.0, 12, (33, 35, 37), 0.25, [W.cubic_block(3)], eps=1e-5, precision=W.FP32)
+    prep = L.prepare(p)
+    pts = [np.zeros((5 + k, 3)) for k in range(4)]
+    vals = [np.zeros(5 + k) for k in range(4)]
+    arr = L.problem_array(prep, 4, pts, vals)
+    base = bytes(prep.struct)
+    for k in range(4):
+        e = arr[k]
+        assert e.n_points == 5 + k and e.points_on_device == 0
+        assert e.points == pts[k].ctypes.data and e.values == vals[k].ctypes.data
+        assert tuple(e.N) == (33, 35, 37) and e.eps == 1e-5 and e.precision == W.FP32
+        raw = C.string_at(C.addressof(e), C.sizeof(L.lsum_problem))
+        pts_off = L.lsum_problem.n_points.offset
+        assert raw[:pts_off] == base[:pts_off]   # everything before the point fields is the prepared struct
+    shared = L.problem_array(prep, 3, pts[0], vals[:3])
+    assert all(shared[k].points == pts[0].ctypes.data for k in range(3))
+    assert L.problem_array(prep, 2)[1].n_points == prep.struct.n_points

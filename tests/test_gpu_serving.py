@@ -200,3 +200,26 @@ def test_finish_many_matches_one_by_one():
             assert rc == 0 and inf.status == 0 and inf.R == R and inf.t_run_ms >= 0.0
             assert np.array_equal(r.values, v)
         assert L.finish_many([]) == []
+
+
+def test_request_set_matches_single_submits():
+    # a RequestSet (one submit call, one finish call for n requests of one problem) gives each
+    # request the values of submitting it alone
+    require_gpu()
+    import torch
+    import paper_1411_1994_amd as L
+    p = mixed_problems(1, seed=44)[0]
+    rng = np.random.default_rng(8)
+    x = rng.uniform(-np.array(W.half_widths(p)), np.array(W.half_widths(p)), size=(301, 3))
+    with L.Context(0, n_slots=2) as c:
+        r = c.submit(p, points=x)
+        assert r.wait() == 0
+        alone = r.values.copy()
+        r.release()
+        xd = dev(x)
+        outs = [empty(len(x), torch.float64) for _ in range(5)]
+        rs = c.submit_set(L.prepare(p), 5, points=xd, values=outs)
+        status, infos = rs.finish()
+        assert list(status) == [0] * 5 and all(infos[k].status == 0 for k in range(5))
+        for o in outs:
+            assert np.array_equal(host(o), alone)
