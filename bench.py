@@ -50,7 +50,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=128)
     ap.add_argument("--workload", default="cfg2", choices=["cfg2", "cfg3", "cfg4", "mix"])
     ap.add_argument("--requests", type=int, default=32, help="requests of the served mix")
-    ap.add_argument("--inflight", type=int, default=96)
+    ap.add_argument("--inflight", type=int, default=64)
     ap.add_argument("--slots", type=int, default=3)
     ap.add_argument("--batch", type=int, default=32)
     ap.add_argument("--chunk", type=int, default=32,
