@@ -61,10 +61,11 @@ __global__ void __launch_bounds__(256) k_collocate(int R, const double* __restri
 // --------------------------------------------------------------------------------------------
 typedef double dpair __attribute__((ext_vector_type(2), aligned(8)));
 
-// The register budget is set for 8 waves per SIMD (the LDS tile then allows 6): more waves in
-// flight hide more of the gather latency (1023 jobs: 7-8 % faster than the default budget).
+// A register budget for 6 waves per SIMD (the limit the LDS tile sets anyway): more waves in
+// flight hide more of the gather latency (1024 jobs: 11 % faster than the compiler's own budget,
+// which leaves 5).
 template <int NU>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) k_shift_sum(const ShiftJob* __restrict__ jobs) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) k_shift_sum(const ShiftJob* __restrict__ jobs) {
     constexpr int QB = 8 * NU, TU = 2;
     __shared__ double tile[64][QB + 1];
     const ShiftJob& jb = jobs[blockIdx.y];
