@@ -195,28 +195,6 @@ __global__ void __launch_bounds__(256) k_sample_cp(int n_fac, int R, const doubl
     out[p] = total;
 }
 
-// One block: out[p] += lam * sum_q U0[q, i0] U1[q, i1] U2[q, i2] (per-axis row strides N_l).
-__global__ void __launch_bounds__(256) k_sample_block(int R, const double* __restrict__ U0,
-                                                      const double* __restrict__ U1,
-                                                      const double* __restrict__ U2, int N0, int N1,
-                                                      int N2, double h, double lam, int n_pts,
-                                                      const double* __restrict__ xyz,
-                                                      double* __restrict__ out) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n_pts) return;
-    const int i0 = snap_dev(xyz[3 * (size_t)p + 0], h, N0);
-    const int i1 = snap_dev(xyz[3 * (size_t)p + 1], h, N1);
-    const int i2 = snap_dev(xyz[3 * (size_t)p + 2], h, N2);
-    if (i0 < 0 || i1 < 0 || i2 < 0) {
-        out[p] = __builtin_nan("");
-        return;
-    }
-    double acc = 0.0;
-    for (int q = 0; q < R; ++q)
-        acc += U0[(size_t)q * N0 + i0] * U1[(size_t)q * N1 + i1] * U2[(size_t)q * N2 + i2];
-    out[p] += lam * acc;
-}
-
 // Vector-major R x N rows -> point-major N x R rows, through a 32 x 32 LDS tile.
 template <typename T>
 __global__ void __launch_bounds__(256) k_transpose(int R, int N, const T* __restrict__ U, int ldu,
@@ -521,14 +499,6 @@ void launch_sample_cp(hipStream_t st, int n_fac, int R, const double* U, int ldu
     if (n_pts <= 0) return;
     hipLaunchKernelGGL(k_sample_cp, dim3(cdiv(n_pts, 256)), dim3(256), 0, st, n_fac, R, U, ldu,
                        lam_dev, N0, N1, N2, h, n_pts, xyz, out);
-}
-
-void launch_sample_block(hipStream_t st, int R, const double* U0, const double* U1, const double* U2,
-                         int N0, int N1, int N2, double h, double lam, int n_pts, const double* xyz,
-                         double* out) {
-    if (n_pts <= 0) return;
-    hipLaunchKernelGGL(k_sample_block, dim3(cdiv(n_pts, 256)), dim3(256), 0, st, R, U0, U1, U2, N0,
-                       N1, N2, h, lam, n_pts, xyz, out);
 }
 
 void launch_transpose(hipStream_t st, int R, int N, const double* U, int ldu, double* UT) {

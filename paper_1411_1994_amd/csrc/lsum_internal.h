@@ -129,13 +129,11 @@ int comb_period(const int32_t* c, int n, int max_p, int* stride);
 // (N_ref - 1 - c[k], 0) per site on the reference rows and *stride = 0.
 void shift_terms(const int32_t* c, int n, int N_ref, std::vector<int2>& terms, int* stride, int* n_hi,
                  bool* two_tables);
+// Canonical sum at points from n_fac factor sets given vector-major (the sample stage of the
+// C ABI): out[p] = sum_f lam[f] sum_q prod_l U_f,l[q, i_l(p)], NaN outside the grid.
 void launch_sample_cp(hipStream_t st, int n_fac, int R, const double* U, int ldu,
                       const double* lam_dev, int N0, int N1, int N2, double h, int n_pts,
                       const double* xyz, double* out);
-// One block's canonical factors (axis l: R rows of N_l, stride N_l): out[p] += lam * sum_q prod.
-void launch_sample_block(hipStream_t st, int R, const double* U0, const double* U1, const double* U2,
-                         int N0, int N1, int N2, double h, double lam, int n_pts, const double* xyz,
-                         double* out);
 // R x N (stride ldu) -> N x R
 void launch_transpose(hipStream_t st, int R, int N, const double* U, int ldu, double* UT);
 void launch_transpose(hipStream_t st, int R, int N, const float* U, int ldu, double* UT);
