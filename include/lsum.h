@@ -56,7 +56,8 @@ extern "C" {
 #define LSUM_E_DEVICE (-7)     /* a HIP runtime error                                         */
 #define LSUM_E_TIMEOUT (-8)    /* lsum_wait ran out of time (the request keeps running)       */
 #define LSUM_E_STATE (-9)      /* result not available in this state / format                 */
-#define LSUM_E_NOCONV (-10)    /* the Jacobi SVD did not converge within its sweep limit      */
+#define LSUM_E_NOCONV (-10)    /* an iteration or search did not reach its target (Jacobi SVD
+                                  sweeps, lsum_choose_M)                                       */
 
 /* ---- problem description ---------------------------------------------------------------- */
 enum { LSUM_NEWTON = 0, LSUM_YUKAWA = 1, LSUM_SLATER = 2 };
@@ -126,6 +127,23 @@ int lsum_nodes(const lsum_kernel* k, const int N[3], double h, double* t, double
  * centred lattice of Sec. 3.2): offs[0..L0-1] axis 0, then L1 for axis 1, then L2 for axis 2.
  * Bit-exact IEEE FP64 arithmetic: x = (k - (L-1)/2) * b + center; u = x / h. */
 int lsum_block_offsets(const lsum_block* blk, const int N[3], double h, int32_t* offs);
+
+/* Error control of the sinc rule (Sec. 2.1, the max-norm bound after eq. sinc_general).
+ * P is the Galerkin tensor (cell averages) of one unit charge on the doubled reference box that
+ * shift-and-windowing reads: displacements (i, j, k) h with |i| <= N_1 - 1, |j| <= N_2 - 1,
+ * |k| <= N_3 - 1.  P_R is the rule of `k` (its M, h_u, s; defaults as for lsum_nodes).
+ * *err = max |P - P_R| / max |P|, the maxima taken over probe cells: every displacement with
+ * all |components| <= 4, and log-spaced cells (ratio 3/2) out to the box corner along six
+ * directions (entries depend only on the sorted |components|).  The exact entries are
+ * integrated on the host in FP64 to far below rounding.  Host only; a few ms for N ~ 4097. */
+int lsum_sinc_error(const lsum_kernel* k, const int N[3], double h, double* err);
+
+/* The smallest M in [1, M_max] (M_max <= 4096) whose rule (the kernel's h_u and s; k->M is
+ * ignored) has lsum_sinc_error <= eps: *M and its *err.  When none does, returns LSUM_E_NOCONV
+ * with the M of the smallest error in *M and that error in *err: the step h_u, not M, then
+ * limits the accuracy (a smaller h_u lowers that floor). */
+int lsum_choose_M(const lsum_kernel* k, const int N[3], double h, double eps, int M_max, int* M,
+                  double* err);
 
 /* ---- context ----------------------------------------------------------------------------- */
 typedef struct lsum_ctx_s* lsum_ctx;

@@ -428,6 +428,86 @@ def exact_cell_average(kind: int, param: float, d: Sequence[float], h: float) ->
     return total
 
 
+def exact_cell_averages(kind: int, param: float, disps, h: float) -> np.ndarray:
+    """``exact_cell_average`` for many cells at once: the same integral in v = log t, done by
+    scipy's adaptive vector quadrature (one subdivision shared by all cells).  ``disps`` holds
+    displacements in units of h, one row per cell."""
+    from scipy.integrate import quad_vec
+
+    D = np.asarray(disps, dtype=np.float64) * h
+
+    def f(v):
+        t = math.exp(v)
+        a = float(transform_density(kind, param, np.array([t]))[0])
+        if a == 0.0:
+            return np.zeros(len(D))
+        return a * np.prod(cell_average_gauss(t, D, h), axis=1) * t
+
+    return quad_vec(f, -40.0, 40.0, epsabs=0.0, epsrel=1e-13, limit=20000,
+                    points=np.linspace(-40.0, 40.0, 81))[0]
+
+
+# ---------------------------------------------------------------------------------------
+# Sec. 2.1: error control of the sinc rule (max-norm bound after eq. sinc_general)
+# ---------------------------------------------------------------------------------------
+
+def sinc_probe_cells(N: Sequence[int]) -> List[Tuple[int, int, int]]:
+    """Cells at which the max norm of P - P_R is taken (reading: the maximum over the whole
+    doubled reference box, |i_l| <= N_l - 1, is estimated on these).  An entry depends only on
+    the sorted absolute displacements, so cells are sorted triples a >= b >= c within the
+    sorted limits: all with a <= 4, and along the directions (1, 0, 0), (1, 1, 0), (1, 1, 1),
+    (1, 1/2, 0), (1, 1/2, 1/2), (1, 1, 1/2) the cells (m, floor(m d_2), floor(m d_3)), clipped
+    to the limits, for m = 5, 8, 12, 18, ... (ceil(3m/2)) below the largest limit and at it."""
+    lim = sorted((n - 1 for n in N), reverse=True)
+    cells = set()
+    for a in range(min(4, lim[0]) + 1):
+        for b in range(min(a, lim[1]) + 1):
+            for c in range(min(b, lim[2]) + 1):
+                cells.add((a, b, c))
+    ms = []
+    m = 5
+    while m < lim[0]:
+        ms.append(m)
+        m = math.ceil(3 * m / 2)
+    ms.append(lim[0])
+    halves = [(0, 0), (2, 0), (2, 2), (1, 0), (1, 1), (2, 1)]
+    for m in ms:
+        for d2, d3 in halves:
+            cells.add((min(m, lim[0]), min(m * d2 // 2, lim[1]), min(m * d3 // 2, lim[2])))
+    return sorted(cells)
+
+
+def sinc_error(kind: int, param: float, M: int, N: Sequence[int], h: float, h_u=None, s=None,
+               cells=None, exact=None) -> float:
+    """max |P - P_R| / max |P| over ``cells`` (default: the probe cells), P the exact Galerkin
+    entries of one unit charge, P_R the rule with M (Sec. 2.1 eq. sinc_general)."""
+    du, ds = default_quadrature(kind, N, h)
+    h_u = du if h_u is None else h_u
+    s = ds if s is None else s
+    cells = np.asarray(sinc_probe_cells(N) if cells is None else cells, dtype=np.float64)
+    if exact is None:
+        exact = exact_cell_averages(kind, param, cells, h)
+    t, w = sinc_nodes(kind, param, M, h_u, s)
+    approx = np.array([np.sum(w * np.prod(cell_average_gauss(t[:, None], c[None, :] * h, h), axis=1))
+                       for c in cells])
+    return float(np.max(np.abs(exact - approx)) / np.max(np.abs(exact)))
+
+
+def choose_M(kind: int, param: float, N: Sequence[int], h: float, eps: float, M_max: int = 256,
+             h_u=None, s=None):
+    """The minimal M with sinc_error <= eps (Sec. 2.1), found by trying M = 1, 2, ...; returns
+    (M, error), or (None, smallest error seen) when no M <= M_max reaches eps."""
+    cells = sinc_probe_cells(N)
+    exact = exact_cell_averages(kind, param, cells, h)
+    best = math.inf
+    for M in range(1, M_max + 1):
+        e = sinc_error(kind, param, M, N, h, h_u, s, cells, exact)
+        if e <= eps:
+            return M, e
+        best = min(best, e)
+    return None, best
+
+
 # ---------------------------------------------------------------------------------------
 # the same method end to end (CPU, FP64)
 # ---------------------------------------------------------------------------------------

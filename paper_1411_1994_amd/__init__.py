@@ -24,7 +24,7 @@ NEWTON, YUKAWA, SLATER = 0, 1, 2
 FP64, FP32, BF16X3 = 0, 1, 2
 
 # every symbol declared in include/lsum.h
-SYMBOLS = ["lsum_nodes", "lsum_block_offsets", "lsum_create", "lsum_destroy", "lsum_last_error",
+SYMBOLS = ["lsum_nodes", "lsum_block_offsets", "lsum_sinc_error", "lsum_choose_M", "lsum_create", "lsum_destroy", "lsum_last_error",
            "lsum_collocate", "lsum_shift_sum", "lsum_sample_canonical", "lsum_jacobi_svd",
            "lsum_contract",
            "lsum_submit", "lsum_submit_many", "lsum_wait", "lsum_cancel", "lsum_get_info", "lsum_get_canonical",
@@ -85,6 +85,8 @@ def _load():
     sig = {
         "lsum_nodes": (I, [P(lsum_kernel), P(I), D, P(D), P(D), I, P(I)]),
         "lsum_block_offsets": (I, [P(lsum_block), P(I), D, P(C.c_int32)]),
+        "lsum_sinc_error": (I, [P(lsum_kernel), P(I), D, P(D)]),
+        "lsum_choose_M": (I, [P(lsum_kernel), P(I), D, D, I, P(I), P(D)]),
         "lsum_create": (I, [P(VP), I, C.c_size_t, I]),
         "lsum_destroy": (I, [VP]),
         "lsum_last_error": (C.c_char_p, []),
@@ -164,6 +166,25 @@ def lsum_nodes(kind: int, param: float, M: int, N: Sequence[int], h: float, h_u:
     R = C.c_int(0)
     _check(_lib.lsum_nodes(C.byref(k), (C.c_int * 3)(*N), h, _dptr(t), _dptr(w), M + 1, C.byref(R)))
     return t[:R.value].copy(), w[:R.value].copy()
+
+
+def lsum_sinc_error(kind: int, param: float, M: int, N: Sequence[int], h: float, h_u: float = 0.0,
+                    s: float = 0.0) -> float:
+    """Max-norm relative error of the sinc rule against the exact Galerkin tensor of one charge."""
+    k = lsum_kernel(kind, param, M, h_u, s)
+    err = C.c_double(0.0)
+    _check(_lib.lsum_sinc_error(C.byref(k), (C.c_int * 3)(*N), h, C.byref(err)))
+    return err.value
+
+
+def lsum_choose_M(kind: int, param: float, N: Sequence[int], h: float, eps: float, M_max: int = 256,
+                  h_u: float = 0.0, s: float = 0.0):
+    """(M, err): the smallest M whose rule meets eps in the max norm; LsumError NOCONV if none."""
+    k = lsum_kernel(kind, param, 0, h_u, s)
+    M = C.c_int(0)
+    err = C.c_double(0.0)
+    _check(_lib.lsum_choose_M(C.byref(k), (C.c_int * 3)(*N), h, eps, M_max, C.byref(M), C.byref(err)))
+    return M.value, err.value
 
 
 def _block(b) -> lsum_block:

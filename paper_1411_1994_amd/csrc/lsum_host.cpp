@@ -38,13 +38,22 @@ void default_quadrature(int kind, const int N[3], double h, double* h_u, double*
 
 // Laplace-Gauss density a(t), p(z) = int_0^inf a(t) exp(-t^2 z^2) dt (Sec. 2.2):
 // Newton 2/sqrt(pi); Yukawa 2/sqrt(pi) exp(-k^2/(4t^2)); Slater l/sqrt(pi) t^-2 exp(-l^2/(4t^2)).
-static double density(int kind, double param, double t) {
+double laplace_density(int kind, double param, double t) {
     const double two_over_sqrt_pi = 2.0 / std::sqrt(M_PI);
     if (kind == LSUM_NEWTON || (kind == LSUM_YUKAWA && param == 0.0)) return two_over_sqrt_pi;
     if (t <= 0.0) return 0.0;
     double e = std::exp(-param * param / (4.0 * (t * t)));
     if (kind == LSUM_YUKAWA) return two_over_sqrt_pi * e;
     return param / std::sqrt(M_PI) / (t * t) * e;   // Slater
+}
+
+void sinc_rule(int kind, double param, int M, double h_u, double s, double* t, double* w) {
+    for (int k = 0; k <= M; ++k) {
+        double u = (double)k * h_u;
+        t[k] = std::sinh(u) / s;
+        double step = (k == 0) ? 0.5 * h_u : h_u;
+        w[k] = step * laplace_density(kind, param, t[k]) * (std::cosh(u) / s);
+    }
 }
 
 // Sinc quadrature (Sec. 2.1, eqs. laplace, hM): trapezoid rule with step h_u in u after the
@@ -57,16 +66,9 @@ int sinc_nodes(int kind, double param, int M, double h_u, double s, std::vector<
     if (kind != LSUM_NEWTON && !(param >= 0.0)) return fail(LSUM_E_INVALID, "negative kernel parameter");
     if (kind == LSUM_SLATER && !(param > 0.0)) return fail(LSUM_E_INVALID, "Slater needs param > 0");
     std::vector<double> tt(M + 1), ww(M + 1);
+    sinc_rule(kind, param, M, h_u, s, tt.data(), ww.data());
     double wmax = 0.0;
-    for (int k = 0; k <= M; ++k) {
-        double u = (double)k * h_u;
-        double tk = std::sinh(u) / s;
-        double dtdu = std::cosh(u) / s;
-        double step = (k == 0) ? 0.5 * h_u : h_u;
-        tt[k] = tk;
-        ww[k] = step * density(kind, param, tk) * dtdu;
-        wmax = std::max(wmax, ww[k]);
-    }
+    for (int k = 0; k <= M; ++k) wmax = std::max(wmax, ww[k]);
     t.clear();
     w.clear();
     for (int k = 0; k <= M; ++k) {

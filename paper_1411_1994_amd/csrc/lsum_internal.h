@@ -29,10 +29,18 @@ int fail(int code, const std::string& msg);
 // host-side steps (FP64 / integer)
 // ------------------------------------------------------------------------------------------
 void default_quadrature(int kind, const int N[3], double h, double* h_u, double* s);
+// Laplace-Gauss density a(t) of the kernel (Sec. 2.2).
+double laplace_density(int kind, double param, double t);
+// The folded rule before dropping: t[k] = sinh(k h_u)/s, w[k], k = 0..M (no validation).
+void sinc_rule(int kind, double param, int M, double h_u, double s, double* t, double* w);
 // Returns LSUM_OK or an error; t/w receive R <= M+1 nodes.
 int sinc_nodes(int kind, double param, int M, double h_u, double s, std::vector<double>& t,
                std::vector<double>& w);
 int snap_coord(double x, double h, int N, int32_t* idx);
+// Sinc error control: scans M = M_lo..M_hi for the first max-norm relative error <= eps (see
+// lsum_sinc_error.cpp); LSUM_E_NOCONV with the best M when none (eps < 0: always LSUM_OK).
+int sinc_error_scan(const lsum_kernel& k, const int N[3], double h, double eps, int M_lo, int M_hi, int* M_out,
+                    double* err_out);
 int block_offsets(const lsum_block& blk, const int N[3], double h, std::vector<int32_t> offs[3]);
 
 // ------------------------------------------------------------------------------------------

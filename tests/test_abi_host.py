@@ -17,7 +17,7 @@ HEADER = os.path.join(ROOT, "include", "lsum.h")
 def declared_symbols():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(lsum_[a-z_0-9]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(lsum_[A-Za-z_0-9]+)\s*\(", text)))
 
 
 def test_library_exports_every_declared_symbol():
@@ -133,3 +133,61 @@ def test_problem_array_marshals_points_and_values():
     shared = L.problem_array(prep, 3, pts[0], vals[:3])
     assert all(shared[k].points == pts[0].ctypes.data for k in range(3))
     assert L.problem_array(prep, 2)[1].n_points == prep.struct.n_points
+
+
+# ---------------------------------------------------------------------------------------
+# error control of the sinc rule: the library's host search against the oracle's
+# ---------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("kind,param", [(W.NEWTON, 0.0), (W.YUKAWA, 0.5), (W.SLATER, 1.0)])
+@pytest.mark.parametrize("c", [1, 2])
+def test_sinc_error_matches_oracle(kind, param, c):
+    import paper_1411_1994_amd as L
+    p = W.config(c)
+    cells = O.sinc_probe_cells(p.N)
+    ex = O.exact_cell_averages(kind, param, cells, p.h)
+    for M in (12, 24, p.M):
+        e = L.lsum_sinc_error(kind, param, M, p.N, p.h)
+        eo = O.sinc_error(kind, param, M, p.N, p.h, cells=cells, exact=ex)
+        # both are differences of FP64 entries normalised by the largest: absolute agreement
+        assert abs(e - eo) < 1e-12, (M, e, eo)
+
+
+@pytest.mark.parametrize("kind,param,N,h,eps", [
+    (W.NEWTON, 0.0, (129, 129, 129), 3 / 32, 1e-5),
+    (W.NEWTON, 0.0, (4097, 4097, 4097), 5 / 256, 1e-6),
+    (W.YUKAWA, 0.5, (1025, 513, 257), 1 / 32, 1e-4),
+    (W.SLATER, 1.0, (129, 129, 129), 3 / 32, 1e-3),
+    (W.NEWTON, 0.0, (257, 129, 65), 1 / 16, 1e-7),
+])
+def test_choose_M_matches_oracle(kind, param, N, h, eps):
+    import paper_1411_1994_amd as L
+    Mo, eo = O.choose_M(kind, param, N, h, eps, 128, h_u=0.25)
+    M, e = L.lsum_choose_M(kind, param, N, h, eps, 128, h_u=0.25)
+    assert M == Mo and abs(e - eo) < 1e-12
+    # minimal: one node fewer misses eps
+    assert L.lsum_sinc_error(kind, param, M - 1, N, h, h_u=0.25) > eps
+    # the chosen M is the one the plan uses: its nodes are the oracle's rule
+    t, _ = L.lsum_nodes(kind, param, M, N, h, h_u=0.25)
+    assert len(t) == len(O.sinc_nodes(kind, param, M, 0.25, O.default_quadrature(kind, N, h)[1])[0])
+
+
+def test_choose_M_errors():
+    import paper_1411_1994_amd as L
+    N, h = (257, 257, 257), 1 / 16
+    with pytest.raises(L.LsumError) as e:       # below the floor of the default step
+        L.lsum_choose_M(W.NEWTON, 0.0, N, h, 1e-9, 96)
+    assert e.value.code == -10
+    assert O.choose_M(W.NEWTON, 0.0, N, h, 1e-9, 96)[0] is None
+    for bad in [dict(eps=0.0), dict(M_max=0), dict(M_max=5000)]:
+        kw = dict(eps=1e-6, M_max=64)
+        kw.update(bad)
+        with pytest.raises(L.LsumError) as e:
+            L.lsum_choose_M(W.NEWTON, 0.0, N, h, kw["eps"], kw["M_max"])
+        assert e.value.code == -1
+    with pytest.raises(L.LsumError) as e:
+        L.lsum_choose_M(W.NEWTON, 0.0, (256, 257, 257), h, 1e-6)
+    assert e.value.code == -1
+    with pytest.raises(L.LsumError) as e:
+        L.lsum_sinc_error(W.SLATER, 0.0, 10, N, h)
+    assert e.value.code == -1

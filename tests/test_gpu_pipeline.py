@@ -318,3 +318,30 @@ def test_identical_axes_share_factors(ctx, L, N, src):
     for a in range(3):
         assert np.max(np.abs(got[a] - ref[a])) <= 1e-13 * np.max(np.abs(ref[a]))
     r.release()
+
+
+@pytest.mark.parametrize("kind,param,eps", [(W.NEWTON, 0.0, 1e-7), (W.YUKAWA, 0.5, 1e-6)])
+def test_chosen_M_meets_its_tolerance_end_to_end(ctx, kind, param, eps):
+    # Sec. 2.1 error control: M from the library's search; the potential of one unit charge
+    # computed by the device path (collocation, shift-sum, sampling) against the exact
+    # Galerkin entries of the oracle, in the max norm, at cells that are not probe cells
+    import paper_1411_1994_amd as L
+    N, h, hu = (257, 129, 129), 1 / 16, 0.25
+    M, e = L.lsum_choose_M(kind, param, N, h, eps, 128, h_u=hu)
+    assert e <= eps
+    p = W.Problem("one-charge", kind, param, M, N, h, [W.Block((1, 1, 1), (1.0, 1.0, 1.0), (0.0, 0.0, 0.0))],
+                  h_u=hu)
+    rng = np.random.default_rng(W.SEED_BASE + 31)
+    c = np.array([(n - 1) // 2 for n in N])
+    near = np.array([[i, j, k] for i in range(-3, 4) for j in range(-3, 4) for k in range(-3, 4)]) + c
+    far = np.stack([rng.integers(0, n, 400) for n in N], axis=1)
+    pts = np.concatenate([near, far, [[0, 0, 0], [N[0] - 1, N[1] - 1, N[2] - 1]]])
+    r = run(ctx, p)
+    got = r.sample(cells_xyz(p, pts))
+    r.release()
+    exact = O.exact_cell_averages(kind, param, np.abs(pts - c), h)
+    err = np.max(np.abs(got - exact)) / np.max(exact)
+    assert err <= 1.05 * eps, (M, e, err)
+    # the error at these cells is of the size the probes estimate (its peak, the charge's own
+    # cell, is among them)
+    assert err >= 0.5 * e

@@ -182,3 +182,80 @@ def test_golden_paper_ranks_are_in_range():
     # our M = 40 Newton rule is inside that range
     t, _ = O.sinc_nodes(O.NEWTON, 0.0, 40, 0.35, 10.0)
     assert R[0] <= len(t) <= R[-1]
+
+
+# ---------------------------------------------------------------------------------------
+# error control of the sinc rule (Sec. 2.1, max-norm bound after eq. sinc_general)
+# ---------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("kind,p", [(O.NEWTON, 0.0), (O.YUKAWA, 0.5), (O.SLATER, 1.0)])
+def test_vector_exact_averages_match_scalar(kind, p):
+    # the shared-subdivision vector quadrature against the per-cell adaptive one (pinned above
+    # by the cube constant)
+    h = 0.1
+    disps = [(0, 0, 0), (1, 0, 0), (2, 1, 1), (7, 3, 0), (40, 20, 10)]
+    vec = O.exact_cell_averages(kind, p, disps, h)
+    one = np.array([O.exact_cell_average(kind, p, [x * h for x in d], h) for d in disps])
+    assert np.max(np.abs(vec - one) / np.abs(one)) < 1e-11
+
+
+def _signed_box(N):
+    lim = [n - 1 for n in N]
+    return [(i, j, k) for i in range(-lim[0], lim[0] + 1) for j in range(-lim[1], lim[1] + 1)
+            for k in range(-lim[2], lim[2] + 1)]
+
+
+@pytest.mark.parametrize("kind,p", [(O.NEWTON, 0.0), (O.SLATER, 2.0)])
+def test_probe_cells_hold_every_entry_of_a_small_box(kind, p):
+    # with N <= 5 per axis every entry of the signed doubled box (2N-1 per axis, both signs and
+    # all axis orders) has a probe cell with the same sorted |displacements|: same maximum
+    N, h = (5, 5, 3), 0.3
+    full = _signed_box(N)
+    ex = O.exact_cell_averages(kind, p, full, h)
+    for M in (4, 8, 16):
+        e_full = O.sinc_error(kind, p, M, N, h, cells=full, exact=ex)
+        e_probe = O.sinc_error(kind, p, M, N, h)
+        assert e_probe == pytest.approx(e_full, rel=1e-9)
+
+
+@pytest.mark.parametrize("kind,p", [(O.NEWTON, 0.0), (O.SLATER, 1.0)])
+def test_probe_cells_find_the_box_maximum(kind, p):
+    # a non-cubic box where the probes are a small subset (66 of the 5049 cells of the positive
+    # octant, which holds every entry up to sign): their maximum reaches the box maximum
+    N, h = (33, 17, 9), 0.1
+    lim = [n - 1 for n in N]
+    full = [(i, j, k) for i in range(lim[0] + 1) for j in range(lim[1] + 1) for k in range(lim[2] + 1)]
+    ex = O.exact_cell_averages(kind, p, full, h)
+    for M in (8, 16, 24):
+        e_full = O.sinc_error(kind, p, M, N, h, cells=full, exact=ex)
+        e_probe = O.sinc_error(kind, p, M, N, h)
+        assert 0.999 * e_full <= e_probe <= e_full * (1 + 1e-12)
+
+
+def test_chosen_rank_grows_like_the_papers_table():
+    # soft pin, Table Table_Times: at eps = 1e-6 the canonical rank of one Newton kernel grows
+    # by 2-3 per doubling of n (34, 37, 39, 41, 43 for n = 4608..73728).  Our rule (fixed step
+    # h_u, s a quarter of the box diagonal) needs about 1.2x the paper's rank and grows alike.
+    with open(os.path.join(GOLDEN, "paper_numbers.json")) as f:
+        g = json.load(f)["table_times"]
+    ranks = []
+    for n, R_paper in zip(g["grid_n"], g["canonical_rank"]):
+        N = (n + 1,) * 3
+        M, e = O.choose_M(O.NEWTON, 0.0, N, 10.0 / n, 1e-6, 128)
+        assert M is not None and e <= 1e-6
+        assert O.sinc_error(O.NEWTON, 0.0, M - 1, N, 10.0 / n) > 1e-6
+        R = len(O.sinc_nodes(O.NEWTON, 0.0, M, *O.default_quadrature(O.NEWTON, N, 10.0 / n))[0])
+        assert R_paper <= R <= 1.35 * R_paper
+        ranks.append(R)
+    steps = np.diff(ranks)
+    assert np.all(steps >= 1) and np.all(steps <= 3)
+
+
+def test_choose_M_reports_the_floor_of_the_step():
+    # the step h_u bounds the accuracy (discretisation error of the trapezoid rule, Sec. 2.1
+    # eq. sinc_conv): below that floor no M suffices; a finer step lowers it
+    N, h = (257,) * 3, 1 / 16
+    M, e = O.choose_M(O.NEWTON, 0.0, N, h, 1e-9, 96)
+    assert M is None and e > 1e-9
+    M2, e2 = O.choose_M(O.NEWTON, 0.0, N, h, 1e-9, 160, h_u=0.2)
+    assert M2 is not None and e2 <= 1e-9
