@@ -112,6 +112,16 @@ typedef struct {
                                  must stay valid until the request finishes                   */
     double* values;           /* n_points results, written before the request finishes        */
     int points_on_device;     /* 1: points/values are device pointers on the context's device */
+    int exact_sites;          /* 0: every site (and defect) is snapped to the centre of its cell
+                                 (Sec. 3.2, error O(h)).  1: sites keep their exact positions:
+                                 along each axis a site at (j + f) h, |f| <= 1/2, takes reference
+                                 rows collocated at the sub-cell offset f (Galerkin entries of the
+                                 shifted charge), and sites with the same f share them, so a
+                                 lattice with b/h = p/q needs at most q row sets per axis.
+                                 Offsets within 2^-30 of each other share the rows of the smallest
+                                 (|f| <= 2^-30: the cell centre), which absorbs the rounding of
+                                 x/h; a problem whose row sets exceed 2^30 doubles is rejected
+                                 (LSUM_E_INVALID)                                               */
 } lsum_problem;
 
 /* ---- host-side steps (FP64 / integer, no device work) ----------------------------------- */

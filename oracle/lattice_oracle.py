@@ -28,7 +28,9 @@ Readings of passages that are silent, ambiguous or garbled (each one is tested):
   inconsistent with the index set I_0).
 * lattice (Sec. 3.2): site k of an axis sits at (k - (L-1)/2) b + centre; sites that do
   not fall on a cell centre are snapped to the nearest one, rounding halves away from
-  zero (the paper assumes on-grid sites and accepts O(h) error otherwise).
+  zero (the paper assumes on-grid sites and accepts O(h) error otherwise).  With exact
+  sites (``brute_force_points_exact``) each charge keeps its position: its Galerkin entries
+  are the cell averages of its own shifted Gaussians (Sec. 3.1 footnote: nuclei anywhere).
 * RHOSVD truncation (Sec. 4.3 allows a threshold instead of fixed ranks): per mode the
   smallest r with (sum_{k>r} sigma_k^2)^{1/2} <= eps ||A|| / (3 ||xi||), which by the
   bound of the Appendix theorem (d) certifies ||A - A0|| <= eps ||A|| in Frobenius norm.
@@ -224,6 +226,44 @@ def brute_force_points(problem, pts: np.ndarray, t=None, w=None) -> np.ndarray:
                 * table[:, p[2] - cidx[:, 2] + Nr - 1])          # (R, C)
         per_charge = w @ prod                                    # q inside
         out[n] = np.sum(Z * per_charge)                          # charges outside
+    return out
+
+
+def charge_positions(problem) -> Tuple[np.ndarray, np.ndarray]:
+    """All charges at their exact coordinates (C,3), without snapping, with their charges Z (C,)
+    (the same order and defect changes as ``charges``)."""
+    pos, Z = [], []
+    for bi, blk in enumerate(problem.blocks):
+        axes = [site_coords(blk.L[a], blk.b[a], blk.center[a]) for a in range(3)]
+        g = np.stack(np.meshgrid(*axes, indexing="ij"), axis=-1).reshape(-1, 3)
+        z = np.full(g.shape[0], float(blk.charge))
+        L = blk.L
+        for d in problem.defects:
+            if d.block == bi:
+                z[(d.site[0] * L[1] + d.site[1]) * L[2] + d.site[2]] += d.dZ
+        pos.append(g)
+        Z.append(z)
+    return np.concatenate(pos), np.concatenate(Z)
+
+
+def brute_force_points_exact(problem, pts: np.ndarray, t=None, w=None) -> np.ndarray:
+    """Charges at their exact positions y_c (the paper's nuclei anywhere in the box, Sec. 3.1):
+    V[p] = sum_c Z_c sum_q w_q prod_l b(t_q; x_l(p) - y_c,l), x(p) the centre of cell p, i.e.
+    the cell averages of eq. ``galten`` of the sinc sum of every charge, one charge at a time.
+    Every site must still lie in a cell of the grid (as for snapping)."""
+    if t is None:
+        t, w = quadrature_of(problem)
+    for blk in problem.blocks:
+        block_offsets(blk, problem.h, problem.N)          # raises OutOfBox like the snapped path
+    pos, Z = charge_positions(problem)
+    h = problem.h
+    out = np.empty(len(pts))
+    for n, p in enumerate(np.asarray(pts)):
+        x = np.array([(p[a] - (problem.N[a] - 1) // 2) * h for a in range(3)])
+        prod = np.ones((len(t), len(Z)))
+        for a in range(3):
+            prod *= cell_average_gauss(t[:, None], (x[a] - pos[:, a])[None, :], h)
+        out[n] = np.sum(Z * (w @ prod))
     return out
 
 

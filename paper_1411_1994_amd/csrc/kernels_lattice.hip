@@ -21,19 +21,21 @@ constexpr double kSqrtPi = 1.7724538509055160273;
 
 // --------------------------------------------------------------------------------------------
 // Reference vectors (Sec. 2.1 b(t_k), Sec. 3.1 eq. master_pot): one thread per entry.
-// Entry m of row q: w_q^(1/3) * (1/h) int over the cell at displacement d = (m-(N_ref-1)) h of
-// exp(-t_q^2 x^2) dx = w_q^(1/3) sqrt(pi)/(2 t h) [erf(t(|d|+h/2)) - erf(t(|d|-h/2))], with the
-// complementary form when both ends are in the tail.  Padding entries are zero.
+// Entry m of row q: w_q^(1/3) * (1/h) int over the cell at displacement d = (m-(N_ref-1)) h -
+// shift of exp(-t_q^2 x^2) dx = w_q^(1/3) sqrt(pi)/(2 t h) [erf(t(|d|+h/2)) - erf(t(|d|-h/2))],
+// with the complementary form when both ends are in the tail.  `shift` is the charge's offset
+// from its cell centre (0 for a charge on the centre).  Padding entries are zero.
 // --------------------------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_collocate(int R, const double* __restrict__ t,
                                                    const double* __restrict__ w13, int N_ref,
-                                                   double h, double* __restrict__ G, int ldg) {
+                                                   double h, double shift, double* __restrict__ G,
+                                                   int ldg) {
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
     const int q = blockIdx.y;
     if (m >= ldg || q >= R) return;
     double v = 0.0;
     if (m < 2 * N_ref - 1) {
-        const double d = fabs((double)(m - (N_ref - 1)) * h);
+        const double d = fabs((double)(m - (N_ref - 1)) * h - shift);
         const double tq = t[q];
         double b = 1.0;
         if (tq > 0.0) {
@@ -297,10 +299,11 @@ __global__ void __launch_bounds__(256) k_sample_batch(int ldt, const SampleJob* 
 }
 
 // Defect terms straight from the reference rows: out[p] += sum_s dZ_s sum_q prod_l
-// G[q, i_l(p) - c_s,l + N_ref - 1] (the windowed reference tensor of Sec. 3.1 per defect).
+// G[q, i_l(p) + off_s,l] (the windowed reference tensor of Sec. 3.1 per defect; off = N_ref - 1
+// - c for a defect in cell c, plus the offset of its row table when sites are off grid).
 __global__ void __launch_bounds__(256) k_sample_windows(int R, const double* __restrict__ G, int ldg,
-                                                        int N_ref, int n_def,
-                                                        const int32_t* __restrict__ cells,
+                                                        int n_def,
+                                                        const int32_t* __restrict__ offs,
                                                         const double* __restrict__ scale, int N0,
                                                         int N1, int N2, double h, int n_pts,
                                                         const double* __restrict__ xyz,
@@ -313,9 +316,9 @@ __global__ void __launch_bounds__(256) k_sample_windows(int R, const double* __r
     if (i0 < 0 || i1 < 0 || i2 < 0) return;
     double total = 0.0;
     for (int s = 0; s < n_def; ++s) {
-        const int m0 = i0 - cells[3 * s + 0] + N_ref - 1;
-        const int m1 = i1 - cells[3 * s + 1] + N_ref - 1;
-        const int m2 = i2 - cells[3 * s + 2] + N_ref - 1;
+        const int m0 = i0 + offs[3 * s + 0];
+        const int m1 = i1 + offs[3 * s + 1];
+        const int m2 = i2 + offs[3 * s + 2];
         double acc = 0.0;
         for (int q = 0; q < R; ++q) {
             const double* g = G + (size_t)q * ldg;
@@ -328,12 +331,12 @@ __global__ void __launch_bounds__(256) k_sample_windows(int R, const double* __r
 
 // Side-matrix columns of one mode (Sec. 4.2 side matrices; rows = columns of the paper's A):
 // row src*R + q is the lattice sum of source src (src < n_lat) or the window of reference
-// row q at the source's defect cell.
+// row q of the source's defect: entry i is G[q * ldg + i + win_offs[src - n_lat]].
 __global__ void __launch_bounds__(256) k_gather_columns(int R, int n_lat,
                                                         const double* const* __restrict__ lat_U,
-                                                        int ldu, const int32_t* __restrict__ win_cells,
+                                                        int ldu, const int32_t* __restrict__ win_offs,
                                                         const double* __restrict__ G, int ldg,
-                                                        int N_ref, int N_axis,
+                                                        int N_axis,
                                                         double* __restrict__ cols, int ldc) {
     const int i = blockIdx.x * 256 + threadIdx.x;
     const int row = blockIdx.y;
@@ -344,8 +347,7 @@ __global__ void __launch_bounds__(256) k_gather_columns(int R, int n_lat,
         if (src < n_lat) {
             v = lat_U[src][(size_t)q * ldu + i];
         } else {
-            const int c = win_cells[src - n_lat];
-            v = G[(size_t)q * ldg + (i - c + N_ref - 1)];
+            v = G[(size_t)q * ldg + (i + win_offs[src - n_lat])];
         }
     }
     cols[(size_t)row * ldc + i] = v;
@@ -467,9 +469,9 @@ inline unsigned cdiv(long a, long b) { return (unsigned)((a + b - 1) / b); }
 }  // namespace
 
 void launch_collocate(hipStream_t st, int R, const double* t_dev, const double* w13_dev, int N_ref,
-                      double h, double* G, int ldg) {
+                      double h, double* G, int ldg, double shift) {
     dim3 grid(cdiv(ldg, 256), R);
-    hipLaunchKernelGGL(k_collocate, grid, dim3(256), 0, st, R, t_dev, w13_dev, N_ref, h, G, ldg);
+    hipLaunchKernelGGL(k_collocate, grid, dim3(256), 0, st, R, t_dev, w13_dev, N_ref, h, shift, G, ldg);
 }
 
 void launch_shift_sum(hipStream_t st, const ShiftJob* jobs_dev, int n_jobs, int max_N, int max_R,
@@ -537,23 +539,23 @@ void launch_sample_batch(hipStream_t st, int ldt, bool f32, const SampleJob* job
 #undef LSUM_SAMPLE_BATCH
 }
 
-void launch_sample_windows(hipStream_t st, int R, const double* G, int ldg, int N_ref, int n_def,
-                           const int32_t* def_cells, const double* def_scale, int N0, int N1,
+void launch_sample_windows(hipStream_t st, int R, const double* G, int ldg, int n_def,
+                           const int32_t* def_offs, const double* def_scale, int N0, int N1,
                            int N2, double h, int n_pts, const double* xyz, double* out, const KTime* kt) {
     if (n_pts <= 0 || n_def <= 0) return;
     hipExtLaunchKernelGGL(k_sample_windows, dim3(cdiv(n_pts, 256)), dim3(256), 0, st, kt ? kt->start : nullptr,
-                          kt ? kt->stop : nullptr, 0, R, G, ldg, N_ref, n_def, def_cells, def_scale, N0, N1,
+                          kt ? kt->stop : nullptr, 0, R, G, ldg, n_def, def_offs, def_scale, N0, N1,
                           N2, h, n_pts, xyz, out);
 }
 
 void launch_gather_columns(hipStream_t st, int R, int n_lat, const double* const* lat_U_dev, int ldu,
-                           int n_win, const int32_t* win_cells_dev, const double* G, int ldg,
-                           int N_ref, int N_axis, double* cols, int ldc) {
+                           int n_win, const int32_t* win_offs_dev, const double* G, int ldg,
+                           int N_axis, double* cols, int ldc) {
     const int rows = R * (n_lat + n_win);
     if (rows <= 0) return;
     dim3 grid(cdiv(ldc, 256), rows);
     hipLaunchKernelGGL(k_gather_columns, grid, dim3(256), 0, st, R, n_lat, lat_U_dev, ldu,
-                       win_cells_dev, G, ldg, N_ref, N_axis, cols, ldc);
+                       win_offs_dev, G, ldg, N_axis, cols, ldc);
 }
 
 void launch_row_norms(hipStream_t st, int rows, int n, const double* X, int ldx, double* nrm) {

@@ -106,10 +106,25 @@ int block_offsets(const lsum_block& blk, const int N[3], double h, std::vector<i
     return LSUM_OK;
 }
 
+void block_subcell(const lsum_block& blk, double h, std::vector<double> f[3]) {
+    for (int l = 0; l < 3; ++l) {
+        f[l].resize(blk.L[l]);
+        double half = (double)(blk.L[l] - 1) / 2.0;
+        for (int k = 0; k < blk.L[l]; ++k) {
+            double x = ((double)k - half) * blk.b[l] + blk.center[l];
+            double u = x / h;
+            double j = std::floor(std::fabs(u) + 0.5);
+            if (u < 0.0) j = -j;
+            f[l][k] = u - j;
+        }
+    }
+}
+
 size_t Plan::planned_bytes() const {
     size_t b = 0;
     size_t sumN = (size_t)N[0] + N[1] + N[2];
     b += (size_t)R * ldg * 8;                                  // reference rows (if not cached)
+    if (off_grid()) b += 3 * cls_f.size() * (size_t)R * ldg * 8;   // class rows and their window sums
     b += blocks.size() * (size_t)ldt * sumN * 8;               // canonical factors (FP64 bound)
     if (tucker()) {
         size_t rmax[3];
@@ -221,6 +236,49 @@ int make_plan(const lsum_problem& p, Plan& plan) {
         if (rc != LSUM_OK) return rc;
         for (int l = 0; l < 3; ++l) plan.offs[l][b] = std::move(o[l]);
     }
+    // exact sites: classes of sub-cell offsets, shared by all axes (the rows depend on f only).
+    // Offsets within kClassTol of 0 are on the cell centre (class 0); the others, sorted, form
+    // classes that start at their smallest offset and take every offset within kClassTol of it,
+    // so sites that differ only by the rounding of x / h share rows (the class's first offset).
+    plan.exact_sites = p.exact_sites ? 1 : 0;
+    if (plan.exact_sites) {
+        const double kClassTol = 1.0 / 1073741824.0;   // 2^-30
+        std::vector<std::vector<double>> f[3];
+        for (int l = 0; l < 3; ++l) f[l].resize(nb);
+        std::vector<double> all;
+        for (int b = 0; b < nb; ++b) {
+            std::vector<double> fb[3];
+            block_subcell(p.blocks[b], p.h, fb);
+            for (int l = 0; l < 3; ++l) {
+                for (double v : fb[l])
+                    if (std::fabs(v) > kClassTol) all.push_back(v);
+                f[l][b] = std::move(fb[l]);
+            }
+        }
+        std::sort(all.begin(), all.end());
+        std::vector<double> starts;
+        for (double v : all)
+            if (starts.empty() || v - starts.back() > kClassTol) starts.push_back(v);
+        if (!starts.empty()) {
+            plan.cls_f.assign(1, 0.0);
+            plan.cls_f.insert(plan.cls_f.end(), starts.begin(), starts.end());
+            if ((double)plan.cls_f.size() * plan.R * plan.ldg > (double)(1 << 30))
+                return fail(LSUM_E_INVALID, "too many sub-cell offset classes for the row tables");
+            for (int l = 0; l < 3; ++l) {
+                plan.cls[l].resize(nb);
+                for (int b = 0; b < nb; ++b) {
+                    plan.cls[l][b].resize(f[l][b].size());
+                    for (size_t k = 0; k < f[l][b].size(); ++k) {
+                        const double v = f[l][b][k];
+                        plan.cls[l][b][k] =
+                            std::fabs(v) <= kClassTol
+                                ? 0
+                                : (int)(std::upper_bound(starts.begin(), starts.end(), v) - starts.begin());
+                    }
+                }
+            }
+        }
+    }
     // defects: validation and duplicate detection
     std::set<std::tuple<int, int, int, int>> seen;
     for (const auto& d : plan.defects) {
@@ -240,13 +298,15 @@ int make_plan(const lsum_problem& p, Plan& plan) {
     for (size_t s2 = 0; s2 < plan.defects.size(); ++s2) plan.g_scale[nb + s2] = plan.defects[s2].dZ;
     for (int l = 0; l < 3; ++l) {
         plan.g_src[l].assign(plan.n_groups, -1);
-        // lattice sources: distinct offset lists
+        // lattice sources: distinct offset lists (cells, then classes when off grid)
         std::map<std::vector<int32_t>, int> lat;
         for (int b = 0; b < nb; ++b) {
-            auto it = lat.find(plan.offs[l][b]);
+            std::vector<int32_t> key = plan.offs[l][b];
+            if (plan.off_grid()) key.insert(key.end(), plan.cls[l][b].begin(), plan.cls[l][b].end());
+            auto it = lat.find(key);
             if (it == lat.end()) {
                 int id = (int)plan.lat_block[l].size();
-                lat.emplace(plan.offs[l][b], id);
+                lat.emplace(std::move(key), id);
                 plan.lat_block[l].push_back(b);
                 plan.g_src[l][b] = id;
             } else {
@@ -254,17 +314,19 @@ int make_plan(const lsum_problem& p, Plan& plan) {
             }
         }
         plan.n_lat[l] = (int)plan.lat_block[l].size();
-        // window sources: distinct defect cells
-        std::map<int32_t, int> win;
+        // window sources: distinct defect (cell, class) pairs
+        std::map<std::pair<int32_t, int32_t>, int> win;
         for (size_t s2 = 0; s2 < plan.defects.size(); ++s2) {
             const auto& d = plan.defects[s2];
             int32_t cell = plan.offs[l][d.block][d.site[l]];
-            auto it = win.find(cell);
+            int32_t cl = plan.site_cls(l, d.block, d.site[l]);
+            auto it = win.find({cell, cl});
             int id;
             if (it == win.end()) {
                 id = (int)plan.win_cell[l].size();
-                win.emplace(cell, id);
+                win.emplace(std::make_pair(cell, cl), id);
                 plan.win_cell[l].push_back(cell);
+                plan.win_cls[l].push_back(cl);
             } else {
                 id = it->second;
             }

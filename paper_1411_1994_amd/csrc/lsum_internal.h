@@ -42,6 +42,8 @@ int snap_coord(double x, double h, int N, int32_t* idx);
 int sinc_error_scan(const lsum_kernel& k, const int N[3], double h, double eps, int M_lo, int M_hi, int* M_out,
                     double* err_out);
 int block_offsets(const lsum_block& blk, const int N[3], double h, std::vector<int32_t> offs[3]);
+// Sub-cell offsets of a block's sites (exact sites): f = x/h - j for the snapped cell j.
+void block_subcell(const lsum_block& blk, double h, std::vector<double> f[3]);
 
 // ------------------------------------------------------------------------------------------
 // plan of one problem: bookkeeping shared by every stage
@@ -67,12 +69,22 @@ struct Plan {
 
     // per block, per axis snapped cell indices
     std::vector<std::vector<int32_t>> offs[3];   // offs[axis][block]
+    // exact sites: a site at (j + f) h along an axis sits in cell j with sub-cell offset f.  The
+    // distinct offsets are the classes (class 0 is f = 0); cls[axis][block][site] is the class
+    // of each site, empty unless some site is off its cell centre (then every class has its own
+    // reference rows, class c at element c * R * ldg of the request's row tables).
+    int exact_sites = 0;
+    std::vector<double> cls_f{0.0};
+    std::vector<std::vector<int32_t>> cls[3];
+    bool off_grid() const { return cls_f.size() > 1; }
+    int site_cls(int l, int b, int k) const { return off_grid() ? cls[l][b][k] : 0; }
 
     // Side-matrix columns per mode, grouped in "sources" of R columns (one per node q):
     // sources [0, n_lat[l]) are distinct lattice offset lists, the rest distinct defect cells.
     int n_lat[3]{}, n_win[3]{};
     std::vector<int32_t> lat_block[3];   // representative block of each lattice source
     std::vector<int32_t> win_cell[3];    // cell index of each window source
+    std::vector<int32_t> win_cls[3];     // class of each window source
     // term groups: blocks first, then defects; scale = block charge or dZ
     int n_groups = 0;
     std::vector<double> g_scale;
@@ -91,12 +103,18 @@ struct Plan {
 
 // Validates the problem and fills the plan (host only).  Returns LSUM_OK or an error.
 int make_plan(const lsum_problem& p, Plan& plan);
+// Element offset of the window of a charge in cell `cell` of class `cls` into the row tables
+// (the reference rows when on grid): entry i of the window is rows[q * ldg + i + win_off].
+inline int64_t win_off(const Plan& P, int cls, int cell) {
+    return (int64_t)cls * P.R * P.ldg + (P.N_ref - 1 - cell);
+}
 
 // ------------------------------------------------------------------------------------------
 // kernel launchers (defined in the .hip files); all asynchronous on `st`
 // ------------------------------------------------------------------------------------------
+// shift: the charge's offset from its cell centre (exact sites), 0 on the centre.
 void launch_collocate(hipStream_t st, int R, const double* t_dev, const double* w13_dev, int N_ref,
-                      double h, double* G, int ldg);
+                      double h, double* G, int ldg, double shift = 0.0);
 // Optional kernel-bound timing: both events are recorded by the dispatch of the kernel itself
 // (hipExtLaunchKernel), so their difference is the kernel's own execution time.
 struct KTime {
@@ -171,14 +189,16 @@ int sample_points_per_wg(bool f32);
 void launch_sample_batch(hipStream_t st, int ldt, bool f32, const SampleJob* jobs_dev, int n_jobs, int n_wg,
                          const KTime* kt = nullptr);
 // Defect windows evaluated straight from the reference rows, added to out.
-void launch_sample_windows(hipStream_t st, int R, const double* G, int ldg, int N_ref,
-                           int n_def, const int32_t* def_cells, const double* def_scale,
+// def_offs: per defect and axis the window offset (win_off) into the rows G.
+void launch_sample_windows(hipStream_t st, int R, const double* G, int ldg,
+                           int n_def, const int32_t* def_offs, const double* def_scale,
                            int N0, int N1, int N2, double h, int n_pts, const double* xyz,
                            double* out, const KTime* kt = nullptr);
-// Side-matrix columns of one mode: rows [src*R + q] of cols (D x ldc).
+// Side-matrix columns of one mode: rows [src*R + q] of cols (D x ldc); win_offs: the window
+// offset (win_off) of each window source into the rows G.
 void launch_gather_columns(hipStream_t st, int R, int n_lat, const double* const* lat_U_dev,
-                           int ldu, int n_win, const int32_t* win_cells_dev, const double* G,
-                           int ldg, int N_ref, int N_axis, double* cols, int ldc);
+                           int ldu, int n_win, const int32_t* win_offs_dev, const double* G,
+                           int ldg, int N_axis, double* cols, int ldc);
 void launch_row_norms(hipStream_t st, int rows, int n, const double* X, int ldx, double* nrm);
 // Y[j, :] = X[j, :] * scale[j]
 void launch_scale_rows(hipStream_t st, int rows, int n, const double* X, int ldx,

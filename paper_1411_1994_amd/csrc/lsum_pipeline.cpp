@@ -148,7 +148,7 @@ static int run_tucker(Request* q, hipStream_t st, const hipStream_t* aux, StageT
     Context* c = q->ctx;
     Plan& P = q->plan;
     int rc;
-    const double* G = q->ref->G.as<double>();
+    const double* G = q->rows();
     // (4) side matrices per mode: lattice sources and defect windows (unnormalised)
     DevBuf cols[3], W[3], nrm[3], C[3];
     std::vector<double> nrm_h[3];
@@ -162,12 +162,13 @@ static int run_tucker(Request* q, hipStream_t st, const hipStream_t* aux, StageT
         for (int s = 0; s < P.n_lat[l]; ++s) latp[s] = q->U[P.lat_block[l][s]].as<double>() + q->U_axis_off[l];
         DevBuf lp, wc;
         if ((rc = lp.get(c->pool, std::max<size_t>(1, latp.size()) * sizeof(void*)))) return rc;
-        if ((rc = wc.get(c->pool, std::max<size_t>(1, P.win_cell[l].size()) * 4))) return rc;
+        std::vector<int32_t> wo(P.win_cell[l].size());
+        for (size_t w = 0; w < wo.size(); ++w) wo[w] = (int32_t)win_off(P, P.win_cls[l][w], P.win_cell[l][w]);
+        if ((rc = wc.get(c->pool, std::max<size_t>(1, wo.size()) * 4))) return rc;
         LSUM_HIP(hipMemcpyAsync(lp.p, latp.data(), latp.size() * sizeof(void*), hipMemcpyHostToDevice, st));
-        if (!P.win_cell[l].empty())
-            LSUM_HIP(hipMemcpyAsync(wc.p, P.win_cell[l].data(), P.win_cell[l].size() * 4, hipMemcpyHostToDevice, st));
+        if (!wo.empty()) LSUM_HIP(hipMemcpyAsync(wc.p, wo.data(), wo.size() * 4, hipMemcpyHostToDevice, st));
         launch_gather_columns(st, P.R, P.n_lat[l], lp.as<const double*>(), P.N[l], P.n_win[l],
-                              wc.as<int32_t>(), G, P.ldg, P.N_ref, N, cols[l].as<double>(), N);
+                              wc.as<int32_t>(), G, P.ldg, N, cols[l].as<double>(), N);
         launch_row_norms(st, D, N, cols[l].as<double>(), N, nrm[l].as<double>());
         nrm_h[l].resize(D);
         LSUM_HIP(hipMemcpyAsync(nrm_h[l].data(), nrm[l].p, D * 8, hipMemcpyDeviceToHost, st));
@@ -512,8 +513,8 @@ int sample_canonical(Context* c, hipStream_t st, const std::vector<CanonSample>&
         if (it.n <= 0 || P.defects.empty()) continue;
         KTime k;
         if (kt && --wins_left == 0) k.stop = kt->stop;
-        launch_sample_windows(st, P.R, q->ref->G.as<double>(), P.ldg, P.N_ref, (int)P.defects.size(),
-                              q->def_cells.as<int32_t>(), q->def_scale.as<double>(), P.N[0], P.N[1], P.N[2],
+        launch_sample_windows(st, P.R, q->rows(), P.ldg, (int)P.defects.size(),
+                              q->def_offs.as<int32_t>(), q->def_scale.as<double>(), P.N[0], P.N[1], P.N[2],
                               P.h, it.n, it.xyz, it.out, &k);
     }
     LSUM_HIP(hipGetLastError());
@@ -618,6 +619,73 @@ int sample_points(Request* q, hipStream_t st, int n, const double* xyz_d, double
 }
 
 // ------------------------------------------------------------------------------------------
+// exact sites off their cell centres: the request's own row tables
+// ------------------------------------------------------------------------------------------
+// The terms of every (block, axis) job of an off-grid request, keyed by block * 3 + axis.  Per
+// sub-cell class the job's sites of that class are summed from the class's rows (directly, or
+// through the window sums of their combs, as on grid).  All tables are R x ldg with stride
+// R * ldg in q->tabs (the class rows first, then each (class, stride, n) window table), and a
+// term's offset carries its table's element offset, so every job reads T0 = q->tabs.  The
+// tables are built here, on st, before the shift-sum launch.
+static int offgrid_terms(Context* c, Request* q, hipStream_t st, std::map<int, std::vector<int2>>& out,
+                         double* table_bytes) {
+    const Plan& P = q->plan;
+    const int nb = (int)P.blocks.size();
+    const int C = (int)P.cls_f.size();
+    const int64_t tab = (int64_t)P.R * P.ldg;
+    std::map<std::tuple<int, int, int>, int> wins;   // (class, stride, n) -> table
+    std::vector<std::tuple<int, int, int>> win_list;
+    auto table_of = [&](int cl, int S, int n) {
+        auto it = wins.emplace(std::make_tuple(cl, S, n), C + (int)win_list.size());
+        if (it.second) win_list.push_back(std::make_tuple(cl, S, n));
+        return it.first->second;
+    };
+    std::vector<int32_t> cs;
+    std::vector<int2> tv;
+    for (int b = 0; b < nb; ++b)
+        for (int l = 0; l < 3; ++l) {
+            if (q->axis_src[l] != l) continue;
+            const auto& sites = P.offs[l][b];
+            const auto& cls = P.cls[l][b];
+            std::vector<int2>& terms = out[b * 3 + l];
+            for (int cl = 0; cl < C; ++cl) {
+                cs.clear();
+                for (size_t k = 0; k < sites.size(); ++k)
+                    if (cls[k] == cl) cs.push_back(sites[k]);
+                if (cs.empty()) continue;
+                int stride = 0, n_hi = 0;
+                bool two = false;
+                shift_terms(cs.data(), (int)cs.size(), P.N_ref, tv, &stride, &n_hi, &two);
+                for (const int2& t : tv) {
+                    const int table = stride == 0 ? cl : table_of(cl, stride, t.y == 0 ? n_hi : n_hi - 1);
+                    terms.push_back(make_int2((int)(t.x + table * tab), 0));
+                }
+            }
+        }
+    const int n_tab = C + (int)win_list.size();
+    if ((double)n_tab * (double)tab + P.ldg >= 2147483647.0)
+        return fail(LSUM_E_INVALID, "too many sub-cell offset tables");
+    int rc;
+    if ((rc = q->tabs.get(c->pool, ((size_t)n_tab * tab + 2 * (size_t)P.R) * 8))) return rc;
+    double* T = q->tabs.as<double>();
+    double* tw = T + (size_t)n_tab * tab;
+    std::vector<double> w13(P.R);
+    for (int k = 0; k < P.R; ++k) w13[k] = std::cbrt(P.w[k]);
+    LSUM_HIP(hipMemcpyAsync(tw, P.t.data(), P.R * 8, hipMemcpyHostToDevice, st));
+    LSUM_HIP(hipMemcpyAsync(tw + P.R, w13.data(), P.R * 8, hipMemcpyHostToDevice, st));
+    for (int cl = 0; cl < C; ++cl)
+        launch_collocate(st, P.R, tw, tw + P.R, P.N_ref, P.h, T + (size_t)cl * tab, P.ldg, P.cls_f[cl] * P.h);
+    for (size_t w = 0; w < win_list.size(); ++w) {
+        const int cl = std::get<0>(win_list[w]);
+        launch_window_sums(st, P.R, T + (size_t)cl * tab, P.ldg, std::get<1>(win_list[w]), std::get<2>(win_list[w]),
+                           T + (size_t)(C + w) * tab);
+    }
+    LSUM_HIP(hipGetLastError());
+    *table_bytes = (double)n_tab * P.R * (2 * P.N_ref - 1) * 8;
+    return LSUM_OK;
+}
+
+// ------------------------------------------------------------------------------------------
 // a batch of requests (several canonical ones, or one reduction request)
 // ------------------------------------------------------------------------------------------
 int run_batch(std::vector<Request*>& reqs, hipStream_t st, const hipStream_t* aux) {
@@ -635,7 +703,7 @@ int run_batch(std::vector<Request*>& reqs, hipStream_t st, const hipStream_t* au
     std::vector<ShiftJob> jobs;
     std::vector<size_t> term_off;
     int maxN = 0, maxR = 0;
-    double out_bytes = 0, loads = 0;
+    double out_bytes = 0, loads = 0, ref_extra = 0;
     std::vector<const RefEntry*> distinct;
     std::vector<int2> tv;
     for (auto* q : reqs) {
@@ -650,7 +718,8 @@ int run_batch(std::vector<Request*>& reqs, hipStream_t st, const hipStream_t* au
             for (int k = 0; k < l && src == l; ++k) {
                 if (q->axis_src[k] != k || P.N[k] != P.N[l]) continue;
                 bool same = true;
-                for (int b = 0; b < nb && same; ++b) same = P.offs[k][b] == P.offs[l][b];
+                for (int b = 0; b < nb && same; ++b)
+                    same = P.offs[k][b] == P.offs[l][b] && (!P.off_grid() || P.cls[k][b] == P.cls[l][b]);
                 if (same) src = k;
             }
             q->axis_src[l] = src;
@@ -667,6 +736,12 @@ int run_batch(std::vector<Request*>& reqs, hipStream_t st, const hipStream_t* au
         }
         q->U.resize(nb);
         q->UT.resize(nb);
+        std::map<int, std::vector<int2>> og;
+        if (P.off_grid()) {
+            double tb = 0;
+            if ((rc = offgrid_terms(c, q, st, og, &tb))) return rc;
+            ref_extra += tb;
+        }
         for (int b = 0; b < nb; ++b) {
             DevBuf& out = vector_major ? q->U[b] : q->UT[b];
             if ((rc = out.get(c->pool, vector_major ? (size_t)P.R * uN * 8 : (size_t)P.ldt * uN * P.row_elem()))) return rc;
@@ -675,9 +750,14 @@ int run_batch(std::vector<Request*>& reqs, hipStream_t st, const hipStream_t* au
                 const auto& sites = P.offs[l][b];
                 int stride = 0, n_hi = 0;
                 bool two = false;
-                shift_terms(sites.data(), (int)sites.size(), P.N_ref, tv, &stride, &n_hi, &two);
                 ShiftJob j{};
-                j.T0 = q->ref->G.as<double>();
+                if (P.off_grid()) {
+                    tv = og[b * 3 + l];
+                    j.T0 = q->tabs.as<double>();
+                } else {
+                    shift_terms(sites.data(), (int)sites.size(), P.N_ref, tv, &stride, &n_hi, &two);
+                    j.T0 = q->ref->G.as<double>();
+                }
                 if (stride > 0) {
                     const double* w = nullptr;
                     if ((rc = get_windows(c, *q->ref, stride, n_hi, st, &w))) return rc;
@@ -709,7 +789,7 @@ int run_batch(std::vector<Request*>& reqs, hipStream_t st, const hipStream_t* au
         if (std::find(distinct.begin(), distinct.end(), q->ref.get()) == distinct.end()) distinct.push_back(q->ref.get());
         q->bytes["canonical"] = (double)nb * P.R * uN * (vector_major ? 8 : P.row_elem());
     }
-    double ref_bytes = 0;
+    double ref_bytes = ref_extra;
     for (auto* e : distinct) ref_bytes += (double)e->R * (2 * e->N_ref - 1) * 8;
     DevBuf terms_d, jobs_d;
     if ((rc = terms_d.get(c->pool, std::max<size_t>(1, terms_h.size()) * sizeof(int2)))) return rc;
@@ -728,16 +808,17 @@ int run_batch(std::vector<Request*>& reqs, hipStream_t st, const hipStream_t* au
         Plan& P = q->plan;
         const int nd = (int)P.defects.size();
         if (nd == 0) continue;
-        std::vector<int32_t> cells(3 * (size_t)nd);
+        std::vector<int32_t> offs(3 * (size_t)nd);
         std::vector<double> sc(nd);
         for (int s = 0; s < nd; ++s) {
             const auto& d = P.defects[s];
-            for (int l = 0; l < 3; ++l) cells[3 * s + l] = P.offs[l][d.block][d.site[l]];
+            for (int l = 0; l < 3; ++l)
+                offs[3 * s + l] = (int32_t)win_off(P, P.site_cls(l, d.block, d.site[l]), P.offs[l][d.block][d.site[l]]);
             sc[s] = d.dZ;
         }
-        if ((rc = q->def_cells.get(c->pool, cells.size() * 4))) return rc;
+        if ((rc = q->def_offs.get(c->pool, offs.size() * 4))) return rc;
         if ((rc = q->def_scale.get(c->pool, nd * 8))) return rc;
-        LSUM_HIP(hipMemcpyAsync(q->def_cells.p, cells.data(), cells.size() * 4, hipMemcpyHostToDevice, st));
+        LSUM_HIP(hipMemcpyAsync(q->def_offs.p, offs.data(), offs.size() * 4, hipMemcpyHostToDevice, st));
         LSUM_HIP(hipMemcpyAsync(q->def_scale.p, sc.data(), nd * 8, hipMemcpyHostToDevice, st));
     }
 

@@ -291,7 +291,7 @@ size_t retained_bytes(const Request* q) {
     for (const auto& u : q->U) b += u.n;
     for (const auto& u : q->UT) b += u.n;
     for (int l = 0; l < 3; ++l) b += q->Z[l].n;
-    return b + q->core.n + q->tile.n + q->def_cells.n + q->def_scale.n;
+    return b + q->core.n + q->tile.n + q->def_offs.n + q->def_scale.n + q->tabs.n;
 }
 
 // ------------------------------------------------------------------------------------------

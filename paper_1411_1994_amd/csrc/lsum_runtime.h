@@ -184,7 +184,11 @@ struct Request {
     size_t U_axis_off[3]{};           // element offsets of the axes in U (R x N_l each)
     size_t UT_axis_off[3]{};          // element offsets of the axes in UT (N_l x ldt each)
     int axis_src[3]{0, 1, 2};         // axis whose factors this axis shares (itself if distinct)
-    DevBuf def_cells, def_scale;       // defects for sampling (n_def x 3, n_def)
+    DevBuf def_offs, def_scale;        // defects for sampling: window offsets (n_def x 3), dZ
+    // exact sites off their cell centres: the request's row tables (the class rows, then the
+    // window sums of its combs), R x ldg each with stride R * ldg, then t and w^(1/3)
+    DevBuf tabs;
+    const double* rows() const { return plan.off_grid() ? tabs.as<double>() : ref->G.as<double>(); }
     // Tucker
     int r[3]{};
     std::vector<double> sigma[3];

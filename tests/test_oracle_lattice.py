@@ -299,3 +299,68 @@ def test_truncation_rule_is_smallest_certified_rank():
             r = res.ranks[a]
             assert tail(r) <= thr * (1 + 1e-6) + 1e-12
             assert r == 1 or tail(r - 1) > thr * (1 - 1e-6)
+
+
+# ---------------------------------------------------------------------------------------
+# exact sites: every charge at its own position (no snapping)
+# ---------------------------------------------------------------------------------------
+
+def _cells(rng, N, n):
+    return np.stack([rng.integers(0, N[a], n) for a in range(3)], axis=1)
+
+
+def test_exact_sites_on_cell_centres_equal_snapped():
+    # b/h even (so (k - (L-1)/2) b is a whole number of cells for even L too) and a centre on a
+    # cell centre: the exact positions are the snapped ones
+    h = 0.25
+    p = W.Problem("on-grid", W.NEWTON, 0.0, 24, (41, 41, 41), h,
+                  [W.Block((3, 4, 2), (1.0, 0.5, 1.5), (0.25, -0.5, 0.0)),
+                   W.Block((2, 2, 3), (0.5, 1.0, 0.5), (-1.0, 1.25, 0.75), charge=-2.0)])
+    pts = _cells(np.random.default_rng(3), p.N, 60)
+    a = O.brute_force_points(p, pts)
+    b = O.brute_force_points_exact(p, pts)
+    assert np.max(np.abs(a - b)) <= 1e-13 * np.max(np.abs(a))
+
+
+def test_exact_site_single_charge_against_exact_galerkin():
+    # one charge at a sub-cell position: its entries are the exact cell averages of the kernel
+    # about that position (eq. galten), up to the sinc error of the rule (M = 48: < 1e-6)
+    N, h = (65, 65, 65), 0.25
+    y = np.array([0.3, -0.45, 0.1]) * h + np.array([2, -1, 0]) * h
+    p = W.Problem("one", W.NEWTON, 0.0, 48, N, h, [W.Block((1, 1, 1), (1.0, 1.0, 1.0), tuple(y))])
+    pts = np.concatenate([np.array([[32 + i, 32 + j, 32 + k] for i in (1, 2, 3) for j in (-2, -1, 0)
+                                    for k in (-1, 0, 1)]), _cells(np.random.default_rng(4), N, 20)])
+    v = O.brute_force_points_exact(p, pts)
+    centres = (pts - 32) * h
+    exact = O.exact_cell_averages(W.NEWTON, 0.0, (centres - y) / h, h)
+    assert np.max(np.abs(v - exact)) <= 1e-6 * np.max(exact)
+    # the snapped charge (cell (2, -1, 0)) is off by O(h) near the charge
+    snapped = O.brute_force_points(p, pts)
+    assert np.max(np.abs(snapped - exact)) > 1e-2 * np.max(exact)
+
+
+def test_exact_sites_far_field_matches_point_charges():
+    # b/h = 22/5 and a sub-cell centre: far from the lattice every cell average is the point value
+    h = 0.25
+    blk = W.Block((3, 3, 3), (1.1, 1.1, 1.1), (0.07, -0.11, 0.13))
+    p = W.Problem("far", W.NEWTON, 0.0, 40, (161, 161, 161), h, [blk])
+    pos, Z = O.charge_positions(p)
+    pts = np.array([[150, 80, 80], [10, 10, 150], [80, 155, 5], [2, 158, 79]])
+    v = O.brute_force_points_exact(p, pts)
+    x = (pts - 80) * h
+    direct = np.array([np.sum(Z / np.linalg.norm(pos - xi, axis=1)) for xi in x])
+    assert np.max(np.abs(v - direct) / direct) < 2e-5
+
+
+def test_exact_sites_mirror_and_whole_cell_shift():
+    # a lattice centred at +d and its mirror at -d give mirrored fields; moving the centre by one
+    # whole cell moves the field by one cell (both exact up to rounding)
+    h, N = 0.25, (45, 45, 45)
+    d = (0.31, -0.17, 0.09)
+    mk = lambda c: W.Problem("m", W.NEWTON, 0.0, 32, N, h, [W.Block((4, 3, 2), (0.8, 0.65, 1.1), c)])
+    pts = _cells(np.random.default_rng(5), (40, 40, 40), 40) + 2
+    v = O.brute_force_points_exact(mk(d), pts)
+    vm = O.brute_force_points_exact(mk(tuple(-x for x in d)), (np.array(N) - 1) - pts)
+    assert np.max(np.abs(v - vm)) <= 1e-12 * np.max(np.abs(v))
+    vs = O.brute_force_points_exact(mk((d[0] + h, d[1], d[2])), pts + np.array([1, 0, 0]))
+    assert np.max(np.abs(v - vs)) <= 1e-12 * np.max(np.abs(v))

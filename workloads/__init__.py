@@ -65,6 +65,7 @@ class Problem:
     s: float = 0.0              # 0: library/oracle default
     tile_lo: Tuple[int, int, int] = (0, 0, 0)
     tile_T: Tuple[int, int, int] = (0, 0, 0)
+    exact_sites: bool = False   # True: sites at exact positions (no snapping to cell centres)
 
     @property
     def n_sites(self) -> int:
