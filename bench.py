@@ -14,7 +14,9 @@ Two paths on the same GPU:
   * plain FP64: one request at a time, one slot, no batching, no reference cache.
 `value` is the served throughput (lattice sums/s); p50/p99 latency, the plain throughput, the
 error against the CPU oracle's brute-force sum, the roofline of the dominant kernel (event-timed
-inside the library over the timed region) and the oracle's own CPU rate are reported beside it.
+inside the library over the timed region) and the oracle's own CPU rate are reported beside it,
+with the same served stream on FP64 rows and with the sites at their exact positions (no
+snapping; `served_exact_sites`).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cfg2|cfg3|cfg4|mix]
 """
@@ -377,6 +379,17 @@ def main():
         vals64 = outs[(steps - 1) % len(outs)].cpu().numpy()
         served64 = {"value": steps / s64, "unit": "lattice sums/s",
                     "latency_ms": {"p50": percentile(lat64, 50), "p99": percentile(lat64, 99)}}
+    # the same stream with the sites at their exact positions (b/h = 51.2: five sub-cell classes
+    # per axis, each with its own cached rows) instead of snapped to cell centres
+    served_x = None
+    if fp64_rows is not None:
+        exact_problem = W.Problem(**{**problem.__dict__, "exact_sites": True})
+        px = L.prepare(exact_problem)
+        run_stream(L, ctx, px, xyz_d, outs, warmup, args.inflight, args.chunk)
+        sx, latx = run_stream(L, ctx, px, xyz_d, outs, steps, args.inflight, args.chunk)
+        valsx = outs[(steps - 1) % len(outs)].cpu().numpy()
+        served_x = {"value": steps / sx, "unit": "lattice sums/s",
+                    "latency_ms": {"p50": percentile(latx, 50), "p99": percentile(latx, 99)}}
     ctx.close()
 
     # ---- plain FP64 path: one at a time, no batching, no reference cache ----------------
@@ -425,6 +438,14 @@ def main():
     if served64 is not None:
         served64["max_rel_err_vs_oracle"] = float(np.max(np.abs(vals64[sel] - ref)) / np.max(np.abs(ref)))
         served64["max_rel_dev_f32_rows"] = float(np.max(np.abs(vals - vals64)) / np.max(np.abs(vals64)))
+    if served_x is not None:
+        # the oracle's charge-by-charge sum at the exact positions, at 12 of the points; beside it
+        # the distance of the snapped served result from that sum (the snapping error)
+        sx_sel = sel[:12]
+        refx = O.brute_force_points_exact(exact_problem, cells[:12])
+        scale = np.max(np.abs(refx))
+        served_x["max_rel_err_vs_oracle"] = float(np.max(np.abs(valsx[sx_sel] - refx)) / scale)
+        served_x["snapped_rel_dev_from_exact"] = float(np.max(np.abs(vals[sx_sel] - refx)) / scale)
 
     # canonical output at FP32 precision: FP32-rounded factor rows, FP64 products and sums
     dtype = "f64" if problem.precision == W.FP64 else ("f32" if problem.precision == W.FP32 or cfg == 2 else "bf16x3")
@@ -460,6 +481,7 @@ def main():
                        "latency_ms": {"p50": percentile(plat, 50), "p99": percentile(plat, 99)}},
         "served_over_plain": served / plain,
         "served_fp64_rows": served64,
+        "served_exact_sites": served_x,
         "max_rel_err_vs_oracle": rel_err,
         "roofline": roof,
         "roofline_shift_sum": roof_ss,

@@ -257,12 +257,15 @@ def brute_force_points_exact(problem, pts: np.ndarray, t=None, w=None) -> np.nda
         block_offsets(blk, problem.h, problem.N)          # raises OutOfBox like the snapped path
     pos, Z = charge_positions(problem)
     h = problem.h
+    # the distinct coordinates of each axis, and each charge's index into them
+    axes = [np.unique(pos[:, a], return_inverse=True) for a in range(3)]
     out = np.empty(len(pts))
     for n, p in enumerate(np.asarray(pts)):
-        x = np.array([(p[a] - (problem.N[a] - 1) // 2) * h for a in range(3)])
         prod = np.ones((len(t), len(Z)))
         for a in range(3):
-            prod *= cell_average_gauss(t[:, None], (x[a] - pos[:, a])[None, :], h)
+            xa = (p[a] - (problem.N[a] - 1) // 2) * h
+            ya, inv = axes[a]
+            prod *= cell_average_gauss(t[:, None], (xa - ya)[None, :], h)[:, inv.reshape(-1)]
         out[n] = np.sum(Z * (w @ prod))
     return out
 

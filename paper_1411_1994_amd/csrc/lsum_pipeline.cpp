@@ -625,8 +625,8 @@ int sample_points(Request* q, hipStream_t st, int n, const double* xyz_d, double
 // sub-cell class the job's sites of that class are summed from the class's rows (directly, or
 // through the window sums of their combs, as on grid).  All tables are R x ldg with stride
 // R * ldg in q->tabs (the class rows first, then each (class, stride, n) window table), and a
-// term's offset carries its table's element offset, so every job reads T0 = q->tabs.  The
-// tables are built here, on st, before the shift-sum launch.
+// term's offset carries its table's element offset, so every job reads T0 = q->tabs (from the
+// context's row cache, built on st on a miss).
 static int offgrid_terms(Context* c, Request* q, hipStream_t st, std::map<int, std::vector<int2>>& out,
                          double* table_bytes) {
     const Plan& P = q->plan;
@@ -665,22 +665,8 @@ static int offgrid_terms(Context* c, Request* q, hipStream_t st, std::map<int, s
     const int n_tab = C + (int)win_list.size();
     if ((double)n_tab * (double)tab + P.ldg >= 2147483647.0)
         return fail(LSUM_E_INVALID, "too many sub-cell offset tables");
-    int rc;
-    if ((rc = q->tabs.get(c->pool, ((size_t)n_tab * tab + 2 * (size_t)P.R) * 8))) return rc;
-    double* T = q->tabs.as<double>();
-    double* tw = T + (size_t)n_tab * tab;
-    std::vector<double> w13(P.R);
-    for (int k = 0; k < P.R; ++k) w13[k] = std::cbrt(P.w[k]);
-    LSUM_HIP(hipMemcpyAsync(tw, P.t.data(), P.R * 8, hipMemcpyHostToDevice, st));
-    LSUM_HIP(hipMemcpyAsync(tw + P.R, w13.data(), P.R * 8, hipMemcpyHostToDevice, st));
-    for (int cl = 0; cl < C; ++cl)
-        launch_collocate(st, P.R, tw, tw + P.R, P.N_ref, P.h, T + (size_t)cl * tab, P.ldg, P.cls_f[cl] * P.h);
-    for (size_t w = 0; w < win_list.size(); ++w) {
-        const int cl = std::get<0>(win_list[w]);
-        launch_window_sums(st, P.R, T + (size_t)cl * tab, P.ldg, std::get<1>(win_list[w]), std::get<2>(win_list[w]),
-                           T + (size_t)(C + w) * tab);
-    }
-    LSUM_HIP(hipGetLastError());
+    int rc = get_tables(c, P, win_list, st, q->tabs);
+    if (rc) return rc;
     *table_bytes = (double)n_tab * P.R * (2 * P.N_ref - 1) * 8;
     return LSUM_OK;
 }
@@ -753,7 +739,7 @@ int run_batch(std::vector<Request*>& reqs, hipStream_t st, const hipStream_t* au
                 ShiftJob j{};
                 if (P.off_grid()) {
                     tv = og[b * 3 + l];
-                    j.T0 = q->tabs.as<double>();
+                    j.T0 = q->tabs->G.as<double>();
                 } else {
                     shift_terms(sites.data(), (int)sites.size(), P.N_ref, tv, &stride, &n_hi, &two);
                     j.T0 = q->ref->G.as<double>();

@@ -5,6 +5,8 @@
 // their shift-sums run as a single launch.  Requests on different slots overlap on the device.
 #include "lsum_runtime.h"
 
+#include <functional>
+
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -165,8 +167,23 @@ static int build_reference(Context* c, const Plan& P, hipStream_t st, RefEntry& 
     return LSUM_OK;
 }
 
-int get_reference(Context* c, const Plan& P, hipStream_t st, std::shared_ptr<RefEntry>& out) {
-    const size_t need = (size_t)P.R * P.ldg * 8;
+static RefKey ref_key(const Plan& P) {
+    RefKey k;
+    auto put = [&](const void* v, size_t n) { k.append((const char*)v, n); };
+    put(&P.kernel.kind, sizeof(int));
+    put(&P.kernel.param, sizeof(double));
+    put(&P.kernel.M, sizeof(int));
+    put(&P.h_u, sizeof(double));
+    put(&P.s, sizeof(double));
+    put(&P.h, sizeof(double));
+    put(&P.N_ref, sizeof(int));
+    return k;
+}
+
+// A cached set of R x ldg row tables under `key` (need bytes), built by `build` on st the first
+// time; uncached (owned by the caller alone) when the cache is disabled.
+static int cached_rows(Context* c, const RefKey& key, const Plan& P, size_t need, hipStream_t st,
+                       const std::function<int(RefEntry&)>& build_fn, std::shared_ptr<RefEntry>& out) {
     if (c->ref_cap == 0) {
         auto e = std::make_shared<RefEntry>();
         e->R = P.R;
@@ -176,14 +193,13 @@ int get_reference(Context* c, const Plan& P, hipStream_t st, std::shared_ptr<Ref
         e->cached = false;
         int rc = e->G.get(c->pool, need);
         if (rc) return rc;
-        rc = build_reference(c, P, st, *e);
+        rc = build_fn(*e);
         if (rc) return rc;
         e->built.set(1);
         e->users.fetch_add(1);
         out = e;
         return LSUM_OK;
     }
-    RefKey key{P.kernel.kind, P.kernel.param, P.kernel.M, P.h_u, P.s, P.h, P.N_ref};
     std::shared_ptr<RefEntry> e;
     bool build = false;
     {
@@ -218,7 +234,7 @@ int get_reference(Context* c, const Plan& P, hipStream_t st, std::shared_ptr<Ref
     }
     int rc;
     if (build) {
-        rc = build_reference(c, P, st, *e);
+        rc = build_fn(*e);
         if (rc) {
             std::lock_guard<std::mutex> lk(c->ref_mu);   // a failed entry leaves the cache
             auto it = c->refs.find(key);
@@ -238,6 +254,58 @@ int get_reference(Context* c, const Plan& P, hipStream_t st, std::shared_ptr<Ref
     }
     out = e;
     return LSUM_OK;
+}
+
+int get_reference(Context* c, const Plan& P, hipStream_t st, std::shared_ptr<RefEntry>& out) {
+    return cached_rows(c, ref_key(P), P, (size_t)P.R * P.ldg * 8, st,
+                       [&](RefEntry& e) { return build_reference(c, P, st, e); }, out);
+}
+
+// The class rows (k_collocate at each class's sub-cell offset) and their window sums.
+static int build_tables(Context* c, const Plan& P, const std::vector<std::tuple<int, int, int>>& wins,
+                        hipStream_t st, RefEntry& e) {
+    const int C = (int)P.cls_f.size();
+    const size_t tab = (size_t)P.R * P.ldg;
+    std::vector<double> tw(2 * (size_t)P.R);
+    for (int q = 0; q < P.R; ++q) {
+        tw[q] = P.t[q];
+        tw[P.R + q] = std::cbrt(P.w[q]);
+    }
+    DevBuf twd;
+    int rc = twd.get(c->pool, tw.size() * 8);
+    if (rc) return rc;
+    LSUM_HIP(hipMemcpyAsync(twd.p, tw.data(), tw.size() * 8, hipMemcpyHostToDevice, st));
+    double* T = e.G.as<double>();
+    StageTimer tm(st);
+    tm.begin("collocate", (double)(C + wins.size()) * P.R * (2 * P.N_ref - 1) * 8, 0);
+    for (int cl = 0; cl < C; ++cl)
+        launch_collocate(st, P.R, twd.as<double>(), twd.as<double>() + P.R, P.N_ref, P.h, T + cl * tab, P.ldg,
+                         P.cls_f[cl] * P.h);
+    for (size_t w = 0; w < wins.size(); ++w)
+        launch_window_sums(st, P.R, T + std::get<0>(wins[w]) * tab, P.ldg, std::get<1>(wins[w]),
+                           std::get<2>(wins[w]), T + (C + w) * tab);
+    tm.end();
+    LSUM_HIP(hipGetLastError());
+    LSUM_HIP(hipStreamSynchronize(st));   // complete for every stream; twd is released
+    std::map<std::string, double> dummy;
+    tm.collect(dummy, c);
+    return LSUM_OK;
+}
+
+int get_tables(Context* c, const Plan& P, const std::vector<std::tuple<int, int, int>>& wins, hipStream_t st,
+               std::shared_ptr<RefEntry>& out) {
+    RefKey key = ref_key(P);
+    auto put = [&](const void* v, size_t n) { key.append((const char*)v, n); };
+    const int C = (int)P.cls_f.size(), nw = (int)wins.size();
+    put(&C, sizeof(int));
+    put(P.cls_f.data(), P.cls_f.size() * sizeof(double));
+    put(&nw, sizeof(int));
+    for (const auto& w : wins) {
+        const int v[3] = {std::get<0>(w), std::get<1>(w), std::get<2>(w)};
+        put(v, sizeof(v));
+    }
+    const size_t need = (size_t)(C + nw) * P.R * P.ldg * 8;
+    return cached_rows(c, key, P, need, st, [&](RefEntry& e) { return build_tables(c, P, wins, st, e); }, out);
 }
 
 int get_windows(Context* c, RefEntry& e, int stride, int n, hipStream_t st, const double** out) {
@@ -284,6 +352,10 @@ void drop_reference(Request* q) {
         q->ref->users.fetch_sub(1);
         q->ref.reset();
     }
+    if (q->tabs) {
+        q->tabs->users.fetch_sub(1);
+        q->tabs.reset();
+    }
 }
 
 size_t retained_bytes(const Request* q) {
@@ -291,7 +363,8 @@ size_t retained_bytes(const Request* q) {
     for (const auto& u : q->U) b += u.n;
     for (const auto& u : q->UT) b += u.n;
     for (int l = 0; l < 3; ++l) b += q->Z[l].n;
-    return b + q->core.n + q->tile.n + q->def_offs.n + q->def_scale.n + q->tabs.n;
+    return b + q->core.n + q->tile.n + q->def_offs.n + q->def_scale.n +
+           (q->tabs && !q->tabs->cached ? q->tabs->bytes : 0);
 }
 
 // ------------------------------------------------------------------------------------------

@@ -118,7 +118,8 @@ struct RefEntry {
     std::mutex win_mu;
     std::map<std::pair<int, int>, std::unique_ptr<WindowRows>> windows;   // by (stride, n)
 };
-using RefKey = std::tuple<int, double, int, double, double, double, int>;
+// bytes of (kind, param, M, h_u, s, h, N_ref), followed for class tables by their layout
+using RefKey = std::string;
 
 // event-timed GPU duration and algorithmic bytes/flops of each stage, summed over launches
 struct StageStat {
@@ -187,8 +188,8 @@ struct Request {
     DevBuf def_offs, def_scale;        // defects for sampling: window offsets (n_def x 3), dZ
     // exact sites off their cell centres: the request's row tables (the class rows, then the
     // window sums of its combs), R x ldg each with stride R * ldg, then t and w^(1/3)
-    DevBuf tabs;
-    const double* rows() const { return plan.off_grid() ? tabs.as<double>() : ref->G.as<double>(); }
+    std::shared_ptr<RefEntry> tabs;
+    const double* rows() const { return plan.off_grid() ? tabs->G.as<double>() : ref->G.as<double>(); }
     // Tucker
     int r[3]{};
     std::vector<double> sigma[3];
@@ -229,6 +230,11 @@ class StageTimer {
 
 void finish(Request* q, int status);
 int get_reference(Context* c, const Plan& P, hipStream_t st, std::shared_ptr<RefEntry>& out);
+// Row tables of an off-grid plan, cached like the reference rows: the rows of every sub-cell
+// class (R x ldg each, stride R * ldg, in class order), then the window sums (class, stride, n)
+// of `wins` in order, each R x ldg.
+int get_tables(Context* c, const Plan& P, const std::vector<std::tuple<int, int, int>>& wins, hipStream_t st,
+               std::shared_ptr<RefEntry>& out);
 // windowed strided sums of a reference (stride, comb length n), computed on st on first use;
 // complete on return
 int get_windows(Context* c, RefEntry& e, int stride, int n, hipStream_t st, const double** out);

@@ -140,3 +140,27 @@ def test_mixed_batch_of_exact_and_snapped_requests(ctx):
         ref = O.brute_force_points_exact(p, pts) if p.exact_sites else O.brute_force_points(p, pts)
         assert rel_err(got[k], ref) <= 1e-12
     assert np.array_equal(got[0], got[2]) and np.array_equal(got[1], got[3])
+
+
+def test_exact_sites_table_cache_switch_gives_identical_results():
+    # class rows and window sums from the context's row cache (shared by repeated problems) or
+    # built for each request (cache disabled): the same bits
+    require_gpu()
+    import paper_1411_1994_amd as L
+    rng = np.random.default_rng(51)
+    defects = W.draw_defects(rng, [BIG, SECOND], 3, 2)
+    p = W.Problem("cache", W.NEWTON, 0.0, 28, (61, 67, 55), H, [BIG, SECOND], defects, exact_sites=True)
+    xyz = cells_xyz(p, points(p, 200, 52))
+    got = []
+    for cap in (None, 0):
+        with L.Context(0) as c:
+            if cap is not None:
+                c.set_option(L.OPT_REF_CACHE_BYTES, cap)
+            rs = [c.submit(p) for _ in range(3)]
+            for r in rs:
+                assert r.wait() == 0
+            got += [r.sample(xyz) for r in rs]
+            for r in rs:
+                r.release()
+    for g in got[1:]:
+        assert np.array_equal(g, got[0])
