@@ -445,6 +445,48 @@ def tucker_points(core: np.ndarray, Z: Sequence[np.ndarray], pts: np.ndarray) ->
 
 
 # ---------------------------------------------------------------------------------------
+# Thm ``thm:sumCaseE`` (B): the lattice sum from the Tucker form of the reference
+# ---------------------------------------------------------------------------------------
+
+def tucker_reference(problem) -> TuckerResult:
+    """The rank-r Tucker form of the reference tensor on the doubled box (eq. ``TuckRef_sum``):
+    RHOSVD at ``problem.eps`` of its canonical form (eq. ``CanMastSumNL``, the same R weighted
+    reference vectors in every mode) written as in eq. ``CP_form``: unit columns, their norms
+    in xi (as ``canonical_terms`` writes the lattice sum)."""
+    t, w = quadrature_of(problem)
+    B = reference_vectors(t, w, max(problem.N), problem.h)           # R x (2 N_ref - 1)
+    nrm = np.linalg.norm(B, axis=1)
+    A = (B / nrm[:, None]).T
+    return rhosvd(nrm ** 3, [A, A, A], eps=problem.eps)
+
+
+def tucker_lattice_sum(problem):
+    """eq. ``Tuck_LatticeSum``: per block and axis the windowed sums of the reference Tucker
+    vectors over the block's sites, stacked block after block; per mode Gram-Schmidt (QR) of the
+    stacked vectors, the triangular factors carried into the core with each block's charge.
+    Returns (core, [Q_1, Q_2, Q_3]), Q_l (N_l x k_l) with orthonormal columns."""
+    ref = tucker_reference(problem)
+    Nr = max(problem.N)
+    stacked = [[], [], []]
+    for blk in problem.blocks:
+        offs = block_offsets(blk, problem.h, problem.N)
+        for a in range(3):
+            stacked[a].append(shift_sum(ref.Z[a].T, offs[a], problem.N[a], Nr))   # r_a x N_a
+    Q, Rt = [], []
+    for a in range(3):
+        q, rr = np.linalg.qr(np.concatenate(stacked[a], axis=0).T)
+        Q.append(q)
+        Rt.append(rr)
+    r1, r2, r3 = ref.ranks
+    core = np.zeros((Rt[0].shape[0], Rt[1].shape[0], Rt[2].shape[0]))
+    for b, blk in enumerate(problem.blocks):
+        core += blk.charge * np.einsum("ijk,ai,bj,ck->abc", ref.core, Rt[0][:, b * r1:(b + 1) * r1],
+                                       Rt[1][:, b * r2:(b + 1) * r2], Rt[2][:, b * r3:(b + 1) * r3],
+                                       optimize=True)
+    return core, Q
+
+
+# ---------------------------------------------------------------------------------------
 # O3: the exact Galerkin entry (no sinc quadrature), by adaptive Gauss-Kronrod
 # ---------------------------------------------------------------------------------------
 

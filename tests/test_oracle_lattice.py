@@ -364,3 +364,58 @@ def test_exact_sites_mirror_and_whole_cell_shift():
     assert np.max(np.abs(v - vm)) <= 1e-12 * np.max(np.abs(v))
     vs = O.brute_force_points_exact(mk((d[0] + h, d[1], d[2])), pts + np.array([1, 0, 0]))
     assert np.max(np.abs(v - vs)) <= 1e-12 * np.max(np.abs(v))
+
+
+# ---------------------------------------------------------------------------------------
+# Thm thm:sumCaseE (B): the Tucker-reference sum
+# ---------------------------------------------------------------------------------------
+
+def _tref_problem(blocks, N=(33, 29, 25), h=0.25, eps=1e-6, M=24):
+    return W.Problem("tref", W.NEWTON, 0.0, M, N, h, blocks, eps=eps, method=1)
+
+
+def test_tucker_reference_sum_of_one_charge_is_the_windowed_reference():
+    # one site: the assembled vectors are the reference vectors' windows, so the sum is the
+    # reference Tucker tensor read at the displacements
+    p = _tref_problem([W.Block((1, 1, 1), (1.0, 1.0, 1.0), (0.5, -0.75, 0.25))])
+    core, Q = O.tucker_lattice_sum(p)
+    ref = O.tucker_reference(p)
+    c = np.array([O.block_offsets(p.blocks[0], p.h, p.N)[a][0] for a in range(3)])
+    pts = np.stack([np.random.default_rng(6).integers(0, n, 50) for n in p.N], axis=1)
+    Nr = max(p.N)
+    got = O.tucker_points(core, Q, pts)
+    want = O.tucker_points(ref.core, ref.Z, pts - c + Nr - 1)
+    assert np.max(np.abs(got - want)) <= 1e-12 * np.max(np.abs(want))
+    for a in range(3):
+        assert np.allclose(Q[a].T @ Q[a], np.eye(Q[a].shape[1]), atol=1e-12)
+
+
+def test_tucker_reference_sum_error_is_bounded_by_the_reference_error():
+    # T_cL - P_cL = sum_k W_k (T_ref - P_ref): each window is a sub-box of the reference, so
+    # ||T_cL - P_cL||_F <= (number of sites) ||T_ref - P_ref||_F, on the full (small) grid
+    blocks = [W.Block((3, 3, 2), (1.0, 1.25, 1.5), (0.0, 0.25, -0.5)),
+              W.Block((2, 1, 2), (0.75, 1.0, 1.0), (-2.0, 1.5, 1.0), charge=-0.5)]
+    p = _tref_problem(blocks)
+    core, Q = O.tucker_lattice_sum(p)
+    T = O.tucker_full(core, Q)
+    P = O.brute_force_grid(p)
+    ref = O.tucker_reference(p)
+    t, w = O.quadrature_of(p)
+    Bv = O.reference_vectors(t, w, max(p.N), p.h)
+    Pref = np.einsum("qi,qj,qk->ijk", Bv, Bv, Bv, optimize=True)
+    e_ref = np.linalg.norm(O.tucker_full(ref.core, ref.Z) - Pref)
+    n_sites = sum(abs(b.charge) * np.prod(b.L) for b in blocks)
+    assert np.linalg.norm(T - P) <= n_sites * e_ref * (1 + 1e-9)
+    assert np.linalg.norm(T - P) <= 1e-5 * np.linalg.norm(P)
+    # and the reference's own error obeys its certified RHOSVD bound
+    assert e_ref <= ref.bound * (1 + 1e-9) and ref.bound <= p.eps * np.linalg.norm(Pref) * (1 + 1e-9)
+
+
+def test_tucker_reference_sum_keeps_the_reference_ranks_for_every_L():
+    # the rank of the assembled sum is the reference's whatever the lattice size (Thm (B))
+    ranks = set()
+    for L in (1, 2, 4, 8):
+        p = _tref_problem([W.Block((L, L, L), (1.0, 1.0, 1.0), (0.0, 0.0, 0.0))], N=(41, 41, 41))
+        core, Q = O.tucker_lattice_sum(p)
+        ranks.add(core.shape)
+    assert len(ranks) == 1 and ranks.pop() == O.tucker_reference(p).ranks
