@@ -62,6 +62,7 @@ extern "C" {
 /* ---- problem description ---------------------------------------------------------------- */
 enum { LSUM_NEWTON = 0, LSUM_YUKAWA = 1, LSUM_SLATER = 2 };
 enum { LSUM_FP64 = 0, LSUM_FP32 = 1, LSUM_BF16X3 = 2 };
+enum { LSUM_SUM_CANONICAL = 0, LSUM_SUM_TUCKER_REF = 1 };
 
 /* Kernel p(r): Newton 1/r, Yukawa exp(-param r)/r, Slater exp(-param r) (Sec. 2.2).
  * Quadrature: u_k = k h_u, t_k = sinh(u_k)/s, k = 0..M (trapezoid rule of eq. hM after the
@@ -122,6 +123,14 @@ typedef struct {
                                  (|f| <= 2^-30: the cell centre), which absorbs the rounding of
                                  x/h; a problem whose row sets exceed 2^30 doubles is rejected
                                  (LSUM_E_INVALID)                                               */
+    int method;               /* with eps > 0: LSUM_SUM_CANONICAL (0) assembles the canonical sum
+                                 and reduces it by RHOSVD (Sec. 4); LSUM_SUM_TUCKER_REF (1) takes
+                                 the rank-r Tucker form of the reference (RHOSVD of one charge on
+                                 the doubled box at eps) and assembles its vectors over the lattice
+                                 (Thm thm:sumCaseE (B)), then orthonormalises them per mode: the
+                                 sum keeps the reference's ranks for every L (one block; a union
+                                 of blocks concatenates).  Needs eps > 0, FP64, no defects and
+                                 exact_sites = 0 (LSUM_E_INVALID otherwise)                     */
 } lsum_problem;
 
 /* ---- host-side steps (FP64 / integer, no device work) ----------------------------------- */

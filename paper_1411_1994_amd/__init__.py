@@ -22,6 +22,7 @@ ERRORS = {-1: "INVALID", -2: "OUT_OF_BOX", -3: "DUP_DEFECT", -4: "NOMEM", -5: "B
           -7: "DEVICE", -8: "TIMEOUT", -9: "STATE", -10: "NOCONV"}
 NEWTON, YUKAWA, SLATER = 0, 1, 2
 FP64, FP32, BF16X3 = 0, 1, 2
+SUM_CANONICAL, SUM_TUCKER_REF = 0, 1
 
 # every symbol declared in include/lsum.h
 SYMBOLS = ["lsum_nodes", "lsum_block_offsets", "lsum_sinc_error", "lsum_choose_M", "lsum_create", "lsum_destroy", "lsum_last_error",
@@ -59,7 +60,8 @@ class lsum_problem(C.Structure):
                 ("n_defects", C.c_int), ("defects", C.POINTER(lsum_defect)),
                 ("eps", C.c_double), ("precision", C.c_int), ("tile_lo", C.c_int * 3),
                 ("tile_T", C.c_int * 3), ("n_points", C.c_int), ("points", C.c_void_p),
-                ("values", C.c_void_p), ("points_on_device", C.c_int), ("exact_sites", C.c_int)]
+                ("values", C.c_void_p), ("points_on_device", C.c_int), ("exact_sites", C.c_int),
+                ("method", C.c_int)]
 
 
 class lsum_info(C.Structure):
@@ -430,6 +432,7 @@ def make_problem(p, points=None, values=None) -> tuple:
                         float(p.eps), int(p.precision), (C.c_int * 3)(*p.tile_lo),
                         (C.c_int * 3)(*p.tile_T))
     prob.exact_sites = 1 if getattr(p, "exact_sites", False) else 0
+    prob.method = int(getattr(p, "method", SUM_CANONICAL))
     keep = [blocks, defects]
     if points is not None:
         on_dev = not isinstance(points, np.ndarray)

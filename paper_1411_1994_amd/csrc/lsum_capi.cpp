@@ -99,6 +99,7 @@ static bool plan_key(const lsum_problem& p, std::string& key) {
     put(p.tile_lo, sizeof(p.tile_lo));
     put(p.tile_T, sizeof(p.tile_T));
     put(&p.exact_sites, sizeof(int));
+    put(&p.method, sizeof(int));
     put(&p.n_blocks, sizeof(int));
     for (int b = 0; b < p.n_blocks; ++b) {
         const lsum_block& k = p.blocks[b];

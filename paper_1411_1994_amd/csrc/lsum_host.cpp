@@ -125,6 +125,7 @@ size_t Plan::planned_bytes() const {
     size_t sumN = (size_t)N[0] + N[1] + N[2];
     b += (size_t)R * ldg * 8;                                  // reference rows (if not cached)
     if (off_grid()) b += 3 * cls_f.size() * (size_t)R * ldg * 8;   // class rows and their window sums
+    if (tucker_ref()) b += 16 * (size_t)R * (4 * (size_t)N_ref) * 8;   // the reference's own RHOSVD
     b += blocks.size() * (size_t)ldt * sumN * 8;               // canonical factors (FP64 bound)
     if (tucker()) {
         size_t rmax[3];
@@ -203,6 +204,11 @@ int make_plan(const lsum_problem& p, Plan& plan) {
     if (p.precision < LSUM_FP64 || p.precision > LSUM_BF16X3) return fail(LSUM_E_INVALID, "bad precision");
     plan.eps = p.eps;
     plan.precision = p.precision;
+    if (p.method != LSUM_SUM_CANONICAL && p.method != LSUM_SUM_TUCKER_REF) return fail(LSUM_E_INVALID, "unknown method");
+    plan.method = p.method;
+    if (p.method == LSUM_SUM_TUCKER_REF &&
+        (!(p.eps > 0.0) || p.precision != LSUM_FP64 || p.n_defects > 0 || p.exact_sites))
+        return fail(LSUM_E_INVALID, "the Tucker-reference sum needs eps > 0, FP64, no defects and snapped sites");
     plan.blocks.assign(p.blocks, p.blocks + p.n_blocks);
     plan.defects.assign(p.defects, p.defects + p.n_defects);
     if (plan.has_tile()) {

@@ -92,7 +92,9 @@ struct Plan {
     std::vector<int32_t> src_mult[3];    // multiplicity of each source (groups using it)
     int D[3]{};                          // R * (n_lat + n_win)
 
+    int method = LSUM_SUM_CANONICAL;
     bool tucker() const { return eps > 0; }
+    bool tucker_ref() const { return tucker() && method == LSUM_SUM_TUCKER_REF; }
     // canonical output with FP32 precision keeps its point-major factors in FP32 (sampling
     // multiplies and sums them in FP64); everything else is FP64
     bool rows_f32() const { return !tucker() && precision != LSUM_FP64; }

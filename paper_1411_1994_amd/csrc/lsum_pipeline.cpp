@@ -143,6 +143,63 @@ static int mode_svd(Context* c, hipStream_t st, int D, int N, DevBuf& W, double 
     return LSUM_OK;
 }
 
+// Optional tile of a Tucker result: V = mu x_3 Z3 x_2 Z2 x_1 Z1 restricted to [lo, lo+T), in the
+// request's precision (eq. Tucker_singePot).
+static int make_tile(Request* q, hipStream_t st, StageTimer& tm) {
+    Context* c = q->ctx;
+    const Plan& P = q->plan;
+    const GemmPrec prec = gemm_prec(P.precision);
+    const size_t es = (prec == GEMM_F64) ? 8 : 4;
+    int rc;
+    tm.begin("tile", (double)P.tile_T[0] * P.tile_T[1] * P.tile_T[2] * (P.precision == LSUM_FP64 ? 8 : 4), 2.0 * ((double)q->r[0] * q->r[1] * q->r[2] * P.tile_T[2] + (double)q->r[0] * q->r[1] * P.tile_T[1] * P.tile_T[2] + (double)q->r[0] * P.tile_T[0] * P.tile_T[1] * P.tile_T[2]));
+    const int r1 = q->r[0], r2 = q->r[1], r3 = q->r[2];
+    const int T1 = P.tile_T[0], T2 = P.tile_T[1], T3 = P.tile_T[2];
+    const void* Zp[3];
+    DevBuf Zf[3];
+    for (int l = 0; l < 3; ++l) {
+        Zp[l] = q->Z[l].p;
+        if (prec != GEMM_F64) {
+            if ((rc = Zf[l].get(c->pool, (size_t)q->r[l] * P.N[l] * 4))) return rc;
+            launch_f64_to_f32(st, (long)q->r[l] * P.N[l], q->Z[l].as<double>(), Zf[l].as<float>());
+            Zp[l] = Zf[l].p;
+        }
+    }
+    DevBuf X1, X2;
+    if ((rc = X1.get(c->pool, (size_t)r1 * r2 * T3 * es))) return rc;
+    if ((rc = X2.get(c->pool, (size_t)r1 * T2 * T3 * es))) return rc;
+    if ((rc = q->tile.get(c->pool, (size_t)T1 * T2 * T3 * es))) return rc;
+    const long e = (long)es;
+    GemmArgs a{};
+    // X1[(a,b), n] = sum_c mu[(a,b), c] Z3[c, lo3 + n]
+    a.m = r1 * r2; a.n = T3; a.k = r3;
+    a.A = q->core.p; a.sam = r3; a.sak = 1;
+    a.B = (const char*)Zp[2] + (long)P.tile_lo[2] * e; a.sbk = P.N[2]; a.sbn = 1;
+    a.C = X1.p; a.scm = T3; a.scn = 1;
+    a.alpha = 1.0; a.beta = 0.0; a.batch = 1;
+    launch_gemm(st, prec, a);
+    // X2[a][m, n] = sum_b Z2[b, lo2 + m] X1[(a,b), n]
+    a = GemmArgs{};
+    a.m = T2; a.n = T3; a.k = r2;
+    a.A = (const char*)Zp[1] + (long)P.tile_lo[1] * e; a.sam = 1; a.sak = P.N[1];
+    a.B = X1.p; a.sbk = T3; a.sbn = 1;
+    a.C = X2.p; a.scm = T3; a.scn = 1;
+    a.alpha = 1.0; a.beta = 0.0; a.batch = r1; a.bA = 0; a.bB = (long)r2 * T3; a.bC = (long)T2 * T3;
+    launch_gemm(st, prec, a);
+    // V[m, (n2,n3)] = sum_a Z1[a, lo1 + m] X2[a, (n2,n3)]
+    a = GemmArgs{};
+    a.m = T1; a.n = T2 * T3; a.k = r1;
+    a.A = (const char*)Zp[0] + (long)P.tile_lo[0] * e; a.sam = 1; a.sak = P.N[0];
+    a.B = X2.p; a.sbk = (long)T2 * T3; a.sbn = 1;
+    a.C = q->tile.p; a.scm = (long)T2 * T3; a.scn = 1;
+    a.alpha = 1.0; a.beta = 0.0; a.batch = 1;
+    launch_gemm(st, prec, a);
+    LSUM_HIP(hipGetLastError());
+    LSUM_HIP(hipStreamSynchronize(st));
+    tm.end();
+    q->bytes["tile"] = (double)T1 * T2 * T3 * es;
+    return LSUM_OK;
+}
+
 // RHOSVD of one request whose canonical factors are computed (q->U, q->ref ready on st).
 static int run_tucker(Request* q, hipStream_t st, const hipStream_t* aux, StageTimer& tm) {
     Context* c = q->ctx;
@@ -380,56 +437,236 @@ static int run_tucker(Request* q, hipStream_t st, const hipStream_t* aux, StageT
     }
     tm.end();
 
-    // (8) optional tile: V = mu x_3 Z3 x_2 Z2 x_1 Z1 restricted to [lo, lo+T)
-    if (P.has_tile()) {
-        tm.begin("tile", (double)P.tile_T[0] * P.tile_T[1] * P.tile_T[2] * (P.precision == LSUM_FP64 ? 8 : 4), 2.0 * ((double)q->r[0] * q->r[1] * q->r[2] * P.tile_T[2] + (double)q->r[0] * q->r[1] * P.tile_T[1] * P.tile_T[2] + (double)q->r[0] * P.tile_T[0] * P.tile_T[1] * P.tile_T[2]));
-        const int r1 = q->r[0], r2 = q->r[1], r3 = q->r[2];
-        const int T1 = P.tile_T[0], T2 = P.tile_T[1], T3 = P.tile_T[2];
-        const void* Zp[3];
-        DevBuf Zf[3];
-        for (int l = 0; l < 3; ++l) {
-            Zp[l] = q->Z[l].p;
-            if (prec != GEMM_F64) {
-                if ((rc = Zf[l].get(c->pool, (size_t)q->r[l] * P.N[l] * 4))) return rc;
-                launch_f64_to_f32(st, (long)q->r[l] * P.N[l], q->Z[l].as<double>(), Zf[l].as<float>());
-                Zp[l] = Zf[l].p;
-            }
-        }
-        DevBuf X1, X2;
-        if ((rc = X1.get(c->pool, (size_t)r1 * r2 * T3 * es))) return rc;
-        if ((rc = X2.get(c->pool, (size_t)r1 * T2 * T3 * es))) return rc;
-        if ((rc = q->tile.get(c->pool, (size_t)T1 * T2 * T3 * es))) return rc;
-        const long e = (long)es;
-        GemmArgs a{};
-        // X1[(a,b), n] = sum_c mu[(a,b), c] Z3[c, lo3 + n]
-        a.m = r1 * r2; a.n = T3; a.k = r3;
-        a.A = q->core.p; a.sam = r3; a.sak = 1;
-        a.B = (const char*)Zp[2] + (long)P.tile_lo[2] * e; a.sbk = P.N[2]; a.sbn = 1;
-        a.C = X1.p; a.scm = T3; a.scn = 1;
-        a.alpha = 1.0; a.beta = 0.0; a.batch = 1;
-        launch_gemm(st, prec, a);
-        // X2[a][m, n] = sum_b Z2[b, lo2 + m] X1[(a,b), n]
-        a = GemmArgs{};
-        a.m = T2; a.n = T3; a.k = r2;
-        a.A = (const char*)Zp[1] + (long)P.tile_lo[1] * e; a.sam = 1; a.sak = P.N[1];
-        a.B = X1.p; a.sbk = T3; a.sbn = 1;
-        a.C = X2.p; a.scm = T3; a.scn = 1;
-        a.alpha = 1.0; a.beta = 0.0; a.batch = r1; a.bA = 0; a.bB = (long)r2 * T3; a.bC = (long)T2 * T3;
-        launch_gemm(st, prec, a);
-        // V[m, (n2,n3)] = sum_a Z1[a, lo1 + m] X2[a, (n2,n3)]
-        a = GemmArgs{};
-        a.m = T1; a.n = T2 * T3; a.k = r1;
-        a.A = (const char*)Zp[0] + (long)P.tile_lo[0] * e; a.sam = 1; a.sak = P.N[0];
-        a.B = X2.p; a.sbk = (long)T2 * T3; a.sbn = 1;
-        a.C = q->tile.p; a.scm = (long)T2 * T3; a.scn = 1;
-        a.alpha = 1.0; a.beta = 0.0; a.batch = 1;
-        launch_gemm(st, prec, a);
-        LSUM_HIP(hipGetLastError());
-        LSUM_HIP(hipStreamSynchronize(st));
-        tm.end();
-        q->bytes["tile"] = (double)T1 * T2 * T3 * es;
-        }
+    // (8) optional tile
+    if (P.has_tile() && (rc = make_tile(q, st, tm))) return rc;
     LSUM_HIP(hipStreamSynchronize(st));
+    return LSUM_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// Tucker-reference sum (Thm thm:sumCaseE (B)): the rank-r Tucker form of the reference, its
+// vectors assembled over the lattice, orthonormalised per mode
+// ------------------------------------------------------------------------------------------
+static int run_tucker_ref(Request* q, hipStream_t st, const hipStream_t* aux, StageTimer& tm) {
+    Context* c = q->ctx;
+    const Plan& P = q->plan;
+    const int nb = (int)P.blocks.size();
+    int rc;
+    // (1) the reference's Tucker form: RHOSVD at eps of one unit charge in the centre cell of the
+    // doubled box (2 N_ref - 1 cells per axis, cell m at displacement (m - (N_ref - 1)) h), with
+    // this plan's kernel, step and scale
+    Request rq;
+    rq.ctx = c;
+    {
+        lsum_problem rp{};
+        rp.kernel = P.kernel;
+        rp.kernel.h_u = P.h_u;
+        rp.kernel.s = P.s;
+        const int Nd = 2 * P.N_ref - 1;
+        rp.N[0] = rp.N[1] = rp.N[2] = Nd;
+        rp.h = P.h;
+        lsum_block one{};
+        for (int l = 0; l < 3; ++l) one.L[l] = 1, one.b[l] = 1.0, one.center[l] = 0.0;
+        one.charge = 1.0;
+        rp.n_blocks = 1;
+        rp.blocks = &one;
+        rp.eps = P.eps;
+        rp.precision = LSUM_FP64;
+        if ((rc = make_plan(rp, rq.plan))) return rc;
+    }
+    std::vector<Request*> rb{&rq};
+    rc = run_batch(rb, st, aux);
+    drop_reference(&rq);
+    if (rc) return rc;
+    if (rq.status.load() < 0) return rq.status.load();
+    const int Nd = rq.plan.N[0];
+    q->norm_A = rq.norm_A;              // of the reference tensor: the certified bound is the reference's
+    q->norm_xi = rq.norm_xi;
+    q->bound = rq.bound;
+
+    // (2) the reference vectors as zero-padded rows of ldg (>= 2 N_ref) for the shift-sum
+    tm.begin("assemble");
+    DevBuf Zr[3];
+    for (int l = 0; l < 3; ++l) {
+        const int r = rq.r[l];
+        if ((rc = Zr[l].get(c->pool, (size_t)r * P.ldg * 8))) return rc;
+        LSUM_HIP(hipMemsetAsync(Zr[l].p, 0, (size_t)r * P.ldg * 8, st));
+        LSUM_HIP(hipMemcpy2DAsync(Zr[l].p, (size_t)P.ldg * 8, rq.Z[l].p, (size_t)Nd * 8, (size_t)Nd * 8, r,
+                                  hipMemcpyDeviceToDevice, st));
+    }
+    // (3) assembled Tucker vectors: per block and axis the shift-sum of the r_l reference rows
+    // over the block's sites (combs through window sums of those rows), stacked block after block
+    // as the rows of F_l ((nb r_l) x N_l)
+    DevBuf F[3];
+    for (int l = 0; l < 3; ++l)
+        if ((rc = F[l].get(c->pool, (size_t)nb * rq.r[l] * P.N[l] * 8))) return rc;
+    std::map<std::tuple<int, int, int>, DevBuf> wins;   // (axis, stride, n) -> window sums
+    auto windows = [&](int l, int S, int n, const double** out) -> int {
+        auto key = std::make_tuple(l, S, n);
+        auto it = wins.find(key);
+        if (it == wins.end()) {
+            DevBuf w;
+            int rc1 = w.get(c->pool, (size_t)rq.r[l] * P.ldg * 8);
+            if (rc1) return rc1;
+            launch_window_sums(st, rq.r[l], Zr[l].as<double>(), P.ldg, S, n, w.as<double>());
+            it = wins.emplace(key, std::move(w)).first;
+        }
+        *out = it->second.as<double>();
+        return LSUM_OK;
+    };
+    std::vector<ShiftJob> jobs;
+    std::vector<int2> terms_h, tv;
+    std::vector<size_t> term_off;
+    int maxN = 0, maxR = 0;
+    for (int b = 0; b < nb; ++b)
+        for (int l = 0; l < 3; ++l) {
+            const auto& sites = P.offs[l][b];
+            int stride = 0, n_hi = 0;
+            bool two = false;
+            shift_terms(sites.data(), (int)sites.size(), P.N_ref, tv, &stride, &n_hi, &two);
+            ShiftJob j{};
+            j.T0 = Zr[l].as<double>();
+            if (stride > 0) {
+                if ((rc = windows(l, stride, n_hi, &j.T0))) return rc;
+                if (two && (rc = windows(l, stride, n_hi - 1, &j.T1))) return rc;
+            }
+            term_off.push_back(terms_h.size());
+            terms_h.insert(terms_h.end(), tv.begin(), tv.end());
+            j.n_terms = (int)tv.size();
+            j.U = F[l].as<double>() + (size_t)b * rq.r[l] * P.N[l];
+            j.ldu = P.N[l];
+            j.N_axis = P.N[l];
+            j.ldg = P.ldg;
+            j.R = rq.r[l];
+            jobs.push_back(j);
+            maxN = std::max(maxN, P.N[l]);
+            maxR = std::max(maxR, rq.r[l]);
+        }
+    DevBuf terms_d, jobs_d;
+    if ((rc = terms_d.get(c->pool, std::max<size_t>(1, terms_h.size()) * sizeof(int2)))) return rc;
+    if ((rc = jobs_d.get(c->pool, jobs.size() * sizeof(ShiftJob)))) return rc;
+    for (size_t k = 0; k < jobs.size(); ++k) jobs[k].terms = terms_d.as<int2>() + term_off[k];
+    LSUM_HIP(hipMemcpyAsync(terms_d.p, terms_h.data(), terms_h.size() * sizeof(int2), hipMemcpyHostToDevice, st));
+    LSUM_HIP(hipMemcpyAsync(jobs_d.p, jobs.data(), jobs.size() * sizeof(ShiftJob), hipMemcpyHostToDevice, st));
+    launch_shift_sum(st, jobs_d.as<ShiftJob>(), (int)jobs.size(), maxN, maxR);
+    LSUM_HIP(hipGetLastError());
+    LSUM_HIP(hipStreamSynchronize(st));   // the job tables and window sums are released below
+    tm.end();
+
+    // (4) per mode an orthonormal basis of the assembled vectors (the Gram-Schmidt step after
+    // Thm thm:sumCaseE): SVD of F_l's rows, every direction above 1e-13 of the largest kept
+    tm.begin("svd");
+    ModeSVD ms[3];
+    for (int l = 0; l < 3; ++l) {
+        const int D = nb * rq.r[l], N = P.N[l];
+        DevBuf W;
+        if ((rc = W.get(c->pool, (size_t)D * N * 8))) return rc;
+        LSUM_HIP(hipMemcpyAsync(W.p, F[l].p, (size_t)D * N * 8, hipMemcpyDeviceToDevice, st));
+        DevBuf nrm;
+        if ((rc = nrm.get(c->pool, (size_t)D * 8))) return rc;
+        launch_row_norms(st, D, N, F[l].as<double>(), N, nrm.as<double>());
+        std::vector<double> nh(D);
+        LSUM_HIP(hipMemcpyAsync(nh.data(), nrm.p, D * 8, hipMemcpyDeviceToHost, st));
+        LSUM_HIP(hipStreamSynchronize(st));
+        double f2 = 0.0;
+        for (double v : nh) f2 += v * v;
+        const double thr = 1e-13 * std::sqrt(f2);
+        if ((rc = mode_svd(c, st, D, N, W, thr, 1e-2 * thr / std::sqrt((double)D), ms[l]))) return rc;
+        LSUM_HIP(hipStreamSynchronize(st));
+        const auto& sg = ms[l].sigma;
+        const int n = (int)sg.size();
+        std::vector<double> tail(n + 1, 0.0);
+        tail[n] = ms[l].res2;
+        for (int k = n - 1; k >= 0; --k) tail[k] = tail[k + 1] + sg[k] * sg[k];
+        int r = n;
+        for (int k = 1; k <= n; ++k)
+            if (std::sqrt(tail[k]) <= thr) { r = k; break; }
+        r = std::max(1, std::min(r, N));
+        q->r[l] = r;
+        q->sigma[l] = sg;
+        q->sweeps[l] = ms[l].sweeps;
+        q->tails[l] = std::sqrt(tail[r]);
+        std::vector<double> inv(r);
+        std::vector<int32_t> ord(r);
+        for (int a = 0; a < r; ++a) { inv[a] = ms[l].unit ? 1.0 : 1.0 / sg[a]; ord[a] = a; }
+        DevBuf od, iv;
+        if ((rc = od.get(c->pool, r * 4))) return rc;
+        if ((rc = iv.get(c->pool, r * 8))) return rc;
+        if ((rc = q->Z[l].get(c->pool, (size_t)r * N * 8))) return rc;
+        LSUM_HIP(hipMemcpyAsync(od.p, ord.data(), r * 4, hipMemcpyHostToDevice, st));
+        LSUM_HIP(hipMemcpyAsync(iv.p, inv.data(), r * 8, hipMemcpyHostToDevice, st));
+        launch_gather_scale_rows(st, r, N, ms[l].rows.as<double>() + ms[l].off, (int)ms[l].ld, od.as<int32_t>(),
+                                 iv.as<double>(), q->Z[l].as<double>(), N);
+        LSUM_HIP(hipStreamSynchronize(st));
+        ms[l].rows.reset();
+    }
+    tm.end();
+
+    // (5) core: with C_l = Z_l F_l^T (r_l x nb r_l^ref), mu = sum_b charge_b B x_1 C_1,b x_2 C_2,b
+    // x_3 C_3,b over the reference core B and block b's columns of C_l (host FP64; the sizes are
+    // a few tens per mode)
+    tm.begin("core");
+    std::vector<double> Ch[3];
+    for (int l = 0; l < 3; ++l) {
+        const int r = q->r[l], D = nb * rq.r[l], N = P.N[l];
+        DevBuf Cd;
+        if ((rc = Cd.get(c->pool, (size_t)r * D * 8))) return rc;
+        GemmArgs a{};
+        a.m = r; a.n = D; a.k = N;
+        a.A = q->Z[l].p; a.sam = N; a.sak = 1;
+        a.B = F[l].p; a.sbk = 1; a.sbn = N;
+        a.C = Cd.p; a.scm = D; a.scn = 1;
+        a.alpha = 1.0; a.beta = 0.0; a.batch = 1;
+        launch_gemm(st, GEMM_F64, a);
+        Ch[l].resize((size_t)r * D);
+        LSUM_HIP(hipMemcpyAsync(Ch[l].data(), Cd.p, (size_t)r * D * 8, hipMemcpyDeviceToHost, st));
+        LSUM_HIP(hipStreamSynchronize(st));
+    }
+    const int s1 = rq.r[0], s2 = rq.r[1], s3 = rq.r[2];
+    std::vector<double> Bh((size_t)s1 * s2 * s3);
+    LSUM_HIP(hipMemcpyAsync(Bh.data(), rq.core.p, Bh.size() * 8, hipMemcpyDeviceToHost, st));
+    LSUM_HIP(hipStreamSynchronize(st));
+    const int k1 = q->r[0], k2 = q->r[1], k3 = q->r[2];
+    std::vector<double> mu((size_t)k1 * k2 * k3, 0.0);
+    std::vector<double> X((size_t)k1 * s2 * s3), Y((size_t)k1 * k2 * s3);
+    for (int b = 0; b < nb; ++b) {
+        const double lam = P.blocks[b].charge;
+        const int D1 = nb * s1, D2 = nb * s2, D3 = nb * s3;
+        // X[a, j, k] = sum_i C1[a, b s1 + i] B[i, j, k]
+        std::fill(X.begin(), X.end(), 0.0);
+        for (int a = 0; a < k1; ++a)
+            for (int i = 0; i < s1; ++i) {
+                const double cf = Ch[0][(size_t)a * D1 + b * s1 + i];
+                const double* Bi = &Bh[(size_t)i * s2 * s3];
+                double* Xa = &X[(size_t)a * s2 * s3];
+                for (int jk = 0; jk < s2 * s3; ++jk) Xa[jk] += cf * Bi[jk];
+            }
+        // Y[a, e, k] = sum_j C2[e, b s2 + j] X[a, j, k]
+        std::fill(Y.begin(), Y.end(), 0.0);
+        for (int a = 0; a < k1; ++a)
+            for (int e = 0; e < k2; ++e)
+                for (int j = 0; j < s2; ++j) {
+                    const double cf = Ch[1][(size_t)e * D2 + b * s2 + j];
+                    const double* Xj = &X[((size_t)a * s2 + j) * s3];
+                    double* Ye = &Y[((size_t)a * k2 + e) * s3];
+                    for (int k = 0; k < s3; ++k) Ye[k] += cf * Xj[k];
+                }
+        // mu[a, e, f] += lam sum_k C3[f, b s3 + k] Y[a, e, k]
+        for (size_t ae = 0; ae < (size_t)k1 * k2; ++ae)
+            for (int f = 0; f < k3; ++f) {
+                const double* C3 = &Ch[2][(size_t)f * D3 + b * s3];
+                const double* Ya = &Y[ae * s3];
+                double acc = 0.0;
+                for (int k = 0; k < s3; ++k) acc += C3[k] * Ya[k];
+                mu[ae * k3 + f] += lam * acc;
+            }
+    }
+    if ((rc = q->core.get(c->pool, mu.size() * 8))) return rc;
+    LSUM_HIP(hipMemcpyAsync(q->core.p, mu.data(), mu.size() * 8, hipMemcpyHostToDevice, st));
+    LSUM_HIP(hipStreamSynchronize(st));
+    tm.end();
+    q->bytes["core"] = (double)mu.size() * 8;
+    if (P.has_tile() && (rc = make_tile(q, st, tm))) return rc;
     return LSUM_OK;
 }
 
@@ -671,6 +908,43 @@ static int offgrid_terms(Context* c, Request* q, hipStream_t st, std::map<int, s
     return LSUM_OK;
 }
 
+// One Tucker-reference request: the sum, then its completion sampling; stage times as for a batch.
+static int run_tucker_ref_batch(Request* q, hipStream_t st, const hipStream_t* aux) {
+    Context* c = q->ctx;
+    StageTimer tm(st);
+    int rc = run_tucker_ref(q, st, aux, tm);
+    if (rc) {
+        (void)hipStreamSynchronize(st);
+        (void)hipGetLastError();
+        q->status.store(rc);
+    } else if (q->n_points > 0) {
+        const int n = q->n_points;
+        const double* xyz_d = q->points;
+        double* out_d = q->values;
+        DevBuf xd, od;
+        if (!q->points_on_device) {
+            if ((rc = xd.get(c->pool, (size_t)n * 24)) || (rc = od.get(c->pool, (size_t)n * 8))) {
+                q->status.store(rc);
+                return LSUM_OK;
+            }
+            LSUM_HIP(hipMemcpyAsync(xd.p, q->points, (size_t)n * 24, hipMemcpyHostToDevice, st));
+            xyz_d = xd.as<double>();
+            out_d = od.as<double>();
+        }
+        tm.begin("sample", (double)n * 32, 0);
+        rc = sample_points(q, st, n, xyz_d, out_d);
+        tm.end();
+        if (rc) q->status.store(rc);
+        else if (!q->points_on_device)
+            LSUM_HIP(hipMemcpyAsync(q->values, out_d, (size_t)n * 8, hipMemcpyDeviceToHost, st));
+    }
+    LSUM_HIP(hipStreamSynchronize(st));
+    std::map<std::string, double> t;
+    tm.collect(t, c);
+    q->t_ms = t;
+    return LSUM_OK;
+}
+
 // ------------------------------------------------------------------------------------------
 // a batch of requests (several canonical ones, or one reduction request)
 // ------------------------------------------------------------------------------------------
@@ -678,6 +952,7 @@ int run_batch(std::vector<Request*>& reqs, hipStream_t st, const hipStream_t* au
     Context* c = reqs[0]->ctx;
     StageTimer tm(st);
     int rc;
+    if (reqs.size() == 1 && reqs[0]->plan.tucker_ref()) return run_tucker_ref_batch(reqs[0], st, aux);
     // (1)-(2) quadrature is in the plan; reference vectors from the cache
     for (auto* q : reqs)
         if ((rc = get_reference(c, q->plan, st, q->ref))) return rc;

@@ -66,6 +66,7 @@ class Problem:
     tile_lo: Tuple[int, int, int] = (0, 0, 0)
     tile_T: Tuple[int, int, int] = (0, 0, 0)
     exact_sites: bool = False   # True: sites at exact positions (no snapping to cell centres)
+    method: int = 0             # 1: Tucker-reference summation (eps > 0, no defects)
 
     @property
     def n_sites(self) -> int:
