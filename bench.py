@@ -18,7 +18,7 @@ inside the library over the timed region) and the oracle's own CPU rate are repo
 with the same served stream on FP64 rows and with the sites at their exact positions (no
 snapping; `served_exact_sites`).
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cfg2|cfg3|cfg4|mix]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cfg2|cfg3|cfg4|mix|timesL]
 """
 from __future__ import annotations
 
@@ -50,7 +50,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2048)
     ap.add_argument("--warmup", type=int, default=128)
-    ap.add_argument("--workload", default="cfg2", choices=["cfg2", "cfg3", "cfg4", "mix"])
+    ap.add_argument("--workload", default="cfg2", choices=["cfg2", "cfg3", "cfg4", "mix", "timesL"])
     ap.add_argument("--requests", type=int, default=32, help="requests of the served mix")
     ap.add_argument("--inflight", type=int, default=64)
     ap.add_argument("--slots", type=int, default=3)
@@ -298,6 +298,82 @@ def run_mix(args):
     print(json.dumps(out))
 
 
+# The sizes of Table Table_timesL: L^3 unit charges on an L x L x L lattice, grid N_L per axis
+# (N_L / L cells per lattice spacing), mesh size 0.0034, Tucker output at eps = 1e-6.
+TIMES_L = [(16, 5632), (32, 9728), (64, 17920), (128, 34304)]
+
+
+def run_times_l(args):
+    """Time per lattice sum in Tucker format for the lattice sizes of Table Table_timesL, by the
+    Tucker-reference sum (Thm thm:sumCaseE (B)) and by canonical assembly + RHOSVD, with M the
+    smallest meeting 1e-6 in the max norm; values checked against the plain sum at a few cells."""
+    import oracle as O
+    import paper_1411_1994_amd as L
+    import workloads as W
+
+    h, eps = 0.0034, 1e-6
+    steps = max(1, min(args.steps, 5))
+    rows = []
+    with L.Context(0, n_slots=1) as ctx:
+        for Lsz, NL in TIMES_L:
+            N = (NL + 1,) * 3
+            M, m_err = L.lsum_choose_M(W.NEWTON, 0.0, N, h, 1e-6, 128)
+            blk = W.Block((Lsz,) * 3, ((NL // Lsz) * h,) * 3, (0.0, 0.0, 0.0))
+            rng = np.random.default_rng(W.SEED_BASE + Lsz)
+            cells = np.stack([rng.integers(0, n, 4) for n in N], axis=1)
+            xyz = np.stack([(cells[:, a] - (N[a] - 1) // 2) * h for a in range(3)], axis=1)
+            row = {"L": Lsz, "sites": Lsz ** 3, "N": N[0], "M": M, "sinc_max_norm_err": m_err}
+            for name, method in (("tucker_ref", 1), ("canonical_rhosvd", 0)):
+                p = W.Problem("timesL", W.NEWTON, 0.0, M, N, h, [blk], eps=eps, method=method)
+                prepared = L.prepare(p)
+                r = ctx.submit(prepared)                       # warm-up (reference caches)
+                if r.wait() != 0:
+                    raise RuntimeError(f"{name} L={Lsz} failed: {r.stats()}")
+                r.release()
+                t = []
+                for _ in range(steps):
+                    t0 = time.perf_counter()
+                    r = ctx.submit(prepared)
+                    rc = r.wait()
+                    t.append(time.perf_counter() - t0)
+                    if rc != 0:
+                        raise RuntimeError(f"{name} L={Lsz} failed")
+                    vals = r.sample(xyz)
+                    ranks = tuple(r.info().r)
+                    stages = r.stats().get("t_ms", {})
+                    r.release()
+                row[name] = {"s_per_sum": float(np.median(t)), "ranks": ranks, "vals": vals,
+                             "stages_ms": stages}
+            ref = O.brute_force_points(W.Problem("timesL", W.NEWTON, 0.0, M, N, h, [blk]), cells)
+            for name in ("tucker_ref", "canonical_rhosvd"):
+                v = row[name].pop("vals")
+                row[name]["max_rel_err_vs_oracle"] = float(np.max(np.abs(v - ref)) / np.max(np.abs(ref)))
+            rows.append(row)
+            print(json.dumps({"progress": "timesL", "L": Lsz, "tucker_ref_s": row["tucker_ref"]["s_per_sum"],
+                              "canonical_rhosvd_s": row["canonical_rhosvd"]["s_per_sum"]}), file=sys.stderr,
+                  flush=True)
+    last = rows[-1]["tucker_ref"]["s_per_sum"]
+    out = {
+        "metric": "time per Tucker lattice sum vs L^3 (Table Table_timesL)",
+        "value": 1.0 / last,
+        "unit": "lattice sums/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": 1,
+        "ms_per_step": 1000.0 * last,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "timesL", "largest": "128^3 sites, N = 34305, h = 0.0034", "eps": eps,
+                   "method": "tucker_ref"},
+        "sizes": rows,
+        "paper_seconds_matlab_cpu": [1.8, 0.8, 3.1, 15.8],
+    }
+    print(json.dumps(out))
+
+
 def per_precision(L, W, problem, xyz):
     """The reduction request in FP64, FP32 and split-BF16x3: MFMA rate of the core and of the
     tile's mode products (event-timed stage time, algorithmic flops), and each result's deviation
@@ -336,6 +412,9 @@ def main():
         sys.exit(2)
     if args.workload == "mix":
         run_mix(args)
+        return
+    if args.workload == "timesL":
+        run_times_l(args)
         return
     import torch
     import oracle as O

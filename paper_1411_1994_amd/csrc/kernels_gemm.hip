@@ -465,6 +465,20 @@ __global__ void __launch_bounds__(256) k_reduce_split(long n, int k_split, const
     out[i] = (T)s;
 }
 
+// C = alpha * sum_z work_z + beta * C for an m x n output with strides (scm, scn): the partial
+// products of a GEMM whose reduction was split into slices, summed in slice order.
+__global__ void __launch_bounds__(256) k_sum_split(int m, int n, int split, const double* __restrict__ work,
+                                                   double alpha, double beta, double* __restrict__ C, long scm,
+                                                   long scn) {
+    const long i = (long)blockIdx.x * 256 + threadIdx.x;
+    const long mn = (long)m * n;
+    if (i >= mn) return;
+    double s = 0.0;
+    for (int z = 0; z < split; ++z) s += work[(long)z * mn + i];
+    double* c = C + (i / n) * scm + (i % n) * scn;
+    *c = (beta != 0.0) ? alpha * s + beta * *c : alpha * s;
+}
+
 // ||A||^2 = sum_{g,g'} s_g s_g' sum_{q,q'} prod_l C_l[s_l(g)R+q, s_l(g')R+q'] (unnormalised
 // columns, so xi_nu = scale_g).  One workgroup per g; partial[g] written, summed on the host.
 __global__ void __launch_bounds__(256) k_cp_norm2(int R, int n_groups, const int32_t* __restrict__ s1,
@@ -509,6 +523,46 @@ void launch_gemm(hipStream_t st, GemmPrec prec, const GemmArgs& a) {
         case GEMM_F32: hipLaunchKernelGGL(k_gemm<GEMM_F32>, grid, dim3(256), 0, st, a); break;
         case GEMM_BF16X3: hipLaunchKernelGGL(k_gemm<GEMM_BF16X3>, grid, dim3(256), 0, st, a); break;
     }
+}
+
+int gemm_split_slices(const GemmArgs& a, int split) {
+    constexpr int GKf = GemmCfg<GEMM_F64>::GK;
+    const long kslice = ((long)(a.k + split - 1) / split + GKf - 1) / GKf * GKf;
+    return (int)((a.k + kslice - 1) / kslice);
+}
+
+void launch_gemm_split_f64(hipStream_t st, const GemmArgs& a, int split, double* work) {
+    if (a.m <= 0 || a.n <= 0 || a.batch != 1) return;
+    constexpr int GKf = GemmCfg<GEMM_F64>::GK;
+    const long kslice = ((long)(a.k + split - 1) / split + GKf - 1) / GKf * GKf;
+    const int slices = (int)((a.k + kslice - 1) / kslice);
+    const int full = (int)(a.k / kslice);                 // slices of kslice terms; the rest is shorter
+    const long mn = (long)a.m * a.n;
+    GemmArgs b = a;
+    b.C = work;
+    b.scm = a.n;
+    b.scn = 1;
+    b.alpha = 1.0;
+    b.beta = 0.0;
+    b.bA = kslice * a.sak;
+    b.bB = kslice * a.sbk;
+    b.bC = mn;
+    if (full > 0) {
+        b.k = (int)kslice;
+        b.batch = full;
+        hipLaunchKernelGGL(k_gemm<GEMM_F64>, dim3(cdiv(a.n, GBN), cdiv(a.m, GBM), full), dim3(256), 0, st, b);
+    }
+    if (full < slices) {
+        GemmArgs r = b;
+        r.k = (int)(a.k - (long)full * kslice);
+        r.batch = 1;
+        r.A = (const double*)a.A + (long)full * kslice * a.sak;
+        r.B = (const double*)a.B + (long)full * kslice * a.sbk;
+        r.C = work + (long)full * mn;
+        hipLaunchKernelGGL(k_gemm<GEMM_F64>, dim3(cdiv(a.n, GBN), cdiv(a.m, GBM), 1), dim3(256), 0, st, r);
+    }
+    hipLaunchKernelGGL(k_sum_split, dim3(cdiv(mn, 256)), dim3(256), 0, st, a.m, a.n, slices, work, a.alpha,
+                       a.beta, (double*)a.C, a.scm, a.scn);
 }
 
 void launch_core(hipStream_t st, GemmPrec prec, const CoreArgs& a, int k_split, void* work) {

@@ -634,7 +634,8 @@ int lsum_contract(lsum_ctx x, void* stream, int prec, int m, int n, int k, const
     a.B = B_dev; a.sbk = sbk; a.sbn = sbn;
     a.C = C_dev; a.scm = scm; a.scn = scn;
     a.alpha = alpha; a.beta = beta; a.batch = 1;
-    launch_gemm(st, prec == LSUM_FP64 ? GEMM_F64 : (prec == LSUM_FP32 ? GEMM_F32 : GEMM_BF16X3), a);
+    int rc = gemm_auto(&x->c, st, prec == LSUM_FP64 ? GEMM_F64 : (prec == LSUM_FP32 ? GEMM_F32 : GEMM_BF16X3), a);
+    if (rc) return rc;
     LSUM_HIP(hipGetLastError());
     LSUM_HIP(hipStreamSynchronize(st));
     return LSUM_OK;

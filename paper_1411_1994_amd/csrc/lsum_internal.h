@@ -219,6 +219,11 @@ struct GemmArgs {
 };
 enum GemmPrec { GEMM_F64 = 0, GEMM_F32 = 1, GEMM_BF16X3 = 2 };
 void launch_gemm(hipStream_t st, GemmPrec prec, const GemmArgs& a);
+// FP64 GEMM (batch 1) with the reduction split into about `split` slices of a multiple of the
+// staging depth: the slices' products go to work (gemm_split_slices(a, split) x m x n doubles),
+// then C = alpha * (their sum in slice order) + beta * C.
+int gemm_split_slices(const GemmArgs& a, int split);
+void launch_gemm_split_f64(hipStream_t st, const GemmArgs& a, int split, double* work);
 
 // Core contraction (eq. C-core): mu[a,b,c] = sum_nu X1[nu, a] X2[nu, b] X3[nu, c] over the K
 // canonical terms nu = g*R + q.  X_l (K x ldx_l, row-major, FP64 or FP32 by precision) are the

@@ -27,6 +27,26 @@ static GemmPrec gemm_prec(int precision) {
 //    explicitly (res2 = ||E||_F^2, which must stay below (thr/10)^2, else the direct solve runs); then
 //    Jacobi on the k rows [B | Q] with the Gram taken over B only, so the rotated Q part holds
 //    orthonormal vectors and ||A - Z_r Z_r^T A||^2 = res2 + sum_{a >= r} sigma_a^2 exactly.
+// A GEMM launch that splits a long FP64 reduction over many workgroups when the output has few
+// tiles (Grams of a few tens of columns over N_l cells, projections onto a few tens of vectors):
+// one tile would otherwise walk all N_l terms alone.  Synchronous when split (the workspace goes
+// back to the pool).
+int gemm_auto(Context* c, hipStream_t st, GemmPrec prec, const GemmArgs& a) {
+    const long tiles = (long)((a.n + 63) / 64) * ((a.m + 127) / 128) * a.batch;
+    if (prec != GEMM_F64 || a.batch != 1 || tiles >= 64 || a.k < 2048) {
+        launch_gemm(st, prec, a);
+        return LSUM_OK;
+    }
+    const int split = (int)std::max<long>(2, std::min<long>(std::min<long>(512 / tiles, a.k / 128), 512));
+    const int slices = gemm_split_slices(a, split);
+    DevBuf work;
+    int rc = work.get(c->pool, (size_t)slices * a.m * a.n * 8);
+    if (rc) return rc;
+    launch_gemm_split_f64(st, a, split, work.as<double>());
+    LSUM_HIP(hipStreamSynchronize(st));
+    return LSUM_OK;
+}
+
 struct ModeSVD {
     std::vector<double> sigma;   // descending
     double res2 = 0.0;
@@ -247,7 +267,7 @@ static int run_tucker(Request* q, hipStream_t st, const hipStream_t* aux, StageT
         a.B = cols[l].p; a.sbk = 1; a.sbn = N;
         a.C = C[l].p; a.scm = D; a.scn = 1;
         a.alpha = 1.0; a.beta = 0.0; a.batch = 1;
-        launch_gemm(st, GEMM_F64, a);
+        if ((rc = gemm_auto(c, st, GEMM_F64, a))) return rc;
     }
     DevBuf src_d, scale_d, part_d;
     const int ng = P.n_groups;
@@ -386,7 +406,7 @@ static int run_tucker(Request* q, hipStream_t st, const hipStream_t* aux, StageT
         a.B = Zp; a.sbk = 1; a.sbn = N;
         a.C = Y[l].p; a.scm = ldy[l]; a.scn = 1;
         a.alpha = 1.0; a.beta = 0.0; a.batch = 1;
-        launch_gemm(st, prec, a);
+        if ((rc = gemm_auto(c, st, prec, a))) return rc;
         LSUM_HIP(hipStreamSynchronize(st));
     }
     tm.end();
@@ -443,6 +463,70 @@ static int run_tucker(Request* q, hipStream_t st, const hipStream_t* aux, StageT
     return LSUM_OK;
 }
 
+// Orthonormal rows Q (D x N) spanning the rows of F by CholeskyQR2: twice G = F F^T (MFMA GEMM),
+// G = L L^T (host), F <- L^-1 F.  *ok is false (and Q unset) when a Cholesky pivot ratio falls
+// below 1e-7 (F too close to rank deficient for this route).
+static int chol_qr2(Context* c, hipStream_t st, int D, int N, const double* F, DevBuf& Q, bool* ok) {
+    int rc;
+    *ok = false;
+    DevBuf Gd, Ld, Q1;
+    if ((rc = Gd.get(c->pool, (size_t)D * D * 8)) || (rc = Ld.get(c->pool, (size_t)D * D * 8))) return rc;
+    if ((rc = Q1.get(c->pool, (size_t)D * N * 8))) return rc;
+    const double* src = F;
+    std::vector<double> G((size_t)D * D), Li((size_t)D * D);
+    for (int pass = 0; pass < 2; ++pass) {
+        GemmArgs a{};
+        a.m = D; a.n = D; a.k = N;
+        a.A = src; a.sam = N; a.sak = 1;
+        a.B = src; a.sbk = 1; a.sbn = N;
+        a.C = Gd.p; a.scm = D; a.scn = 1;
+        a.alpha = 1.0; a.beta = 0.0; a.batch = 1;
+        if ((rc = gemm_auto(c, st, GEMM_F64, a))) return rc;
+        LSUM_HIP(hipMemcpyAsync(G.data(), Gd.p, G.size() * 8, hipMemcpyDeviceToHost, st));
+        LSUM_HIP(hipStreamSynchronize(st));
+        // Cholesky in place (lower), then the inverse of L by forward substitution
+        double dmax = 0.0, dmin = INFINITY;
+        for (int j = 0; j < D; ++j) {
+            double d = G[(size_t)j * D + j];
+            for (int k = 0; k < j; ++k) d -= G[(size_t)j * D + k] * G[(size_t)j * D + k];
+            if (!(d > 0.0)) return LSUM_OK;
+            d = std::sqrt(d);
+            G[(size_t)j * D + j] = d;
+            dmax = std::max(dmax, d);
+            dmin = std::min(dmin, d);
+            for (int i = j + 1; i < D; ++i) {
+                double v = G[(size_t)i * D + j];
+                for (int k = 0; k < j; ++k) v -= G[(size_t)i * D + k] * G[(size_t)j * D + k];
+                G[(size_t)i * D + j] = v / d;
+            }
+        }
+        if (dmin < 1e-7 * dmax) return LSUM_OK;
+        std::fill(Li.begin(), Li.end(), 0.0);
+        for (int j = 0; j < D; ++j) {
+            Li[(size_t)j * D + j] = 1.0 / G[(size_t)j * D + j];
+            for (int i = j + 1; i < D; ++i) {
+                double v = 0.0;
+                for (int k = j; k < i; ++k) v -= G[(size_t)i * D + k] * Li[(size_t)k * D + j];
+                Li[(size_t)i * D + j] = v / G[(size_t)i * D + i];
+            }
+        }
+        LSUM_HIP(hipMemcpyAsync(Ld.p, Li.data(), Li.size() * 8, hipMemcpyHostToDevice, st));
+        DevBuf& dst = pass == 0 ? Q1 : Q;
+        if (pass == 1 && (rc = Q.get(c->pool, (size_t)D * N * 8))) return rc;
+        a = GemmArgs{};
+        a.m = D; a.n = N; a.k = D;
+        a.A = Ld.p; a.sam = D; a.sak = 1;
+        a.B = src; a.sbk = N; a.sbn = 1;
+        a.C = dst.p; a.scm = N; a.scn = 1;
+        a.alpha = 1.0; a.beta = 0.0; a.batch = 1;
+        launch_gemm(st, GEMM_F64, a);
+        LSUM_HIP(hipStreamSynchronize(st));   // Ld is rewritten by the next pass
+        src = Q1.as<double>();
+    }
+    *ok = true;
+    return LSUM_OK;
+}
+
 // ------------------------------------------------------------------------------------------
 // Tucker-reference sum (Thm thm:sumCaseE (B)): the rank-r Tucker form of the reference, its
 // vectors assembled over the lattice, orthonormalised per mode
@@ -452,12 +536,13 @@ static int run_tucker_ref(Request* q, hipStream_t st, const hipStream_t* aux, St
     const Plan& P = q->plan;
     const int nb = (int)P.blocks.size();
     int rc;
-    // (1) the reference's Tucker form: RHOSVD at eps of one unit charge in the centre cell of the
-    // doubled box (2 N_ref - 1 cells per axis, cell m at displacement (m - (N_ref - 1)) h), with
-    // this plan's kernel, step and scale
-    Request rq;
-    rq.ctx = c;
-    {
+    // (1)-(2) the reference's Tucker form (cached per kernel, quadrature, grid and eps): RHOSVD at
+    // eps of one unit charge in the centre cell of the doubled box (2 N_ref - 1 cells per axis,
+    // cell m at displacement (m - (N_ref - 1)) h), with this plan's kernel, step and scale; its
+    // vectors kept as zero-padded rows of ldg (>= 2 N_ref) for the shift-sum
+    auto make = [&](RefEntry& e) -> int {
+        Request rq;
+        rq.ctx = c;
         lsum_problem rp{};
         rp.kernel = P.kernel;
         rp.kernel.h_u = P.h_u;
@@ -472,43 +557,56 @@ static int run_tucker_ref(Request* q, hipStream_t st, const hipStream_t* aux, St
         rp.blocks = &one;
         rp.eps = P.eps;
         rp.precision = LSUM_FP64;
-        if ((rc = make_plan(rp, rq.plan))) return rc;
-    }
-    std::vector<Request*> rb{&rq};
-    rc = run_batch(rb, st, aux);
-    drop_reference(&rq);
-    if (rc) return rc;
-    if (rq.status.load() < 0) return rq.status.load();
-    const int Nd = rq.plan.N[0];
-    q->norm_A = rq.norm_A;              // of the reference tensor: the certified bound is the reference's
-    q->norm_xi = rq.norm_xi;
-    q->bound = rq.bound;
-
-    // (2) the reference vectors as zero-padded rows of ldg (>= 2 N_ref) for the shift-sum
+        int rc1 = make_plan(rp, rq.plan);
+        if (rc1) return rc1;
+        std::vector<Request*> rb{&rq};
+        rc1 = run_batch(rb, st, aux);
+        drop_reference(&rq);
+        if (rc1) return rc1;
+        if (rq.status.load() < 0) return rq.status.load();
+        const size_t tab = (size_t)P.R * P.ldg;
+        LSUM_HIP(hipMemsetAsync(e.G.p, 0, 3 * tab * 8, st));
+        for (int l = 0; l < 3; ++l) {
+            e.r[l] = rq.r[l];
+            LSUM_HIP(hipMemcpy2DAsync(e.G.as<double>() + l * tab, (size_t)P.ldg * 8, rq.Z[l].p, (size_t)Nd * 8,
+                                      (size_t)Nd * 8, rq.r[l], hipMemcpyDeviceToDevice, st));
+        }
+        e.core.resize((size_t)rq.r[0] * rq.r[1] * rq.r[2]);
+        LSUM_HIP(hipMemcpyAsync(e.core.data(), rq.core.p, e.core.size() * 8, hipMemcpyDeviceToHost, st));
+        LSUM_HIP(hipStreamSynchronize(st));
+        e.norm_A = rq.norm_A;
+        e.norm_xi = rq.norm_xi;
+        e.bound = rq.bound;
+        return LSUM_OK;
+    };
+    std::shared_ptr<RefEntry> tr;
+    if ((rc = get_tucker_ref(c, P, st, make, tr))) return rc;
+    struct Unuse {
+        std::shared_ptr<RefEntry>& e;
+        ~Unuse() { e->users.fetch_sub(1); }
+    } unuse{tr};
+    const int rr[3] = {tr->r[0], tr->r[1], tr->r[2]};
+    q->norm_A = tr->norm_A;               // of the reference tensor: the certified bound is the reference's
+    q->norm_xi = tr->norm_xi;
+    q->bound = tr->bound;
     tm.begin("assemble");
-    DevBuf Zr[3];
-    for (int l = 0; l < 3; ++l) {
-        const int r = rq.r[l];
-        if ((rc = Zr[l].get(c->pool, (size_t)r * P.ldg * 8))) return rc;
-        LSUM_HIP(hipMemsetAsync(Zr[l].p, 0, (size_t)r * P.ldg * 8, st));
-        LSUM_HIP(hipMemcpy2DAsync(Zr[l].p, (size_t)P.ldg * 8, rq.Z[l].p, (size_t)Nd * 8, (size_t)Nd * 8, r,
-                                  hipMemcpyDeviceToDevice, st));
-    }
+    const double* Zr[3];
+    for (int l = 0; l < 3; ++l) Zr[l] = tr->G.as<double>() + (size_t)l * P.R * P.ldg;
     // (3) assembled Tucker vectors: per block and axis the shift-sum of the r_l reference rows
     // over the block's sites (combs through window sums of those rows), stacked block after block
     // as the rows of F_l ((nb r_l) x N_l)
     DevBuf F[3];
     for (int l = 0; l < 3; ++l)
-        if ((rc = F[l].get(c->pool, (size_t)nb * rq.r[l] * P.N[l] * 8))) return rc;
+        if ((rc = F[l].get(c->pool, (size_t)nb * rr[l] * P.N[l] * 8))) return rc;
     std::map<std::tuple<int, int, int>, DevBuf> wins;   // (axis, stride, n) -> window sums
     auto windows = [&](int l, int S, int n, const double** out) -> int {
         auto key = std::make_tuple(l, S, n);
         auto it = wins.find(key);
         if (it == wins.end()) {
             DevBuf w;
-            int rc1 = w.get(c->pool, (size_t)rq.r[l] * P.ldg * 8);
+            int rc1 = w.get(c->pool, (size_t)rr[l] * P.ldg * 8);
             if (rc1) return rc1;
-            launch_window_sums(st, rq.r[l], Zr[l].as<double>(), P.ldg, S, n, w.as<double>());
+            launch_window_sums(st, rr[l], Zr[l], P.ldg, S, n, w.as<double>());
             it = wins.emplace(key, std::move(w)).first;
         }
         *out = it->second.as<double>();
@@ -525,7 +623,7 @@ static int run_tucker_ref(Request* q, hipStream_t st, const hipStream_t* aux, St
             bool two = false;
             shift_terms(sites.data(), (int)sites.size(), P.N_ref, tv, &stride, &n_hi, &two);
             ShiftJob j{};
-            j.T0 = Zr[l].as<double>();
+            j.T0 = Zr[l];
             if (stride > 0) {
                 if ((rc = windows(l, stride, n_hi, &j.T0))) return rc;
                 if (two && (rc = windows(l, stride, n_hi - 1, &j.T1))) return rc;
@@ -533,14 +631,14 @@ static int run_tucker_ref(Request* q, hipStream_t st, const hipStream_t* aux, St
             term_off.push_back(terms_h.size());
             terms_h.insert(terms_h.end(), tv.begin(), tv.end());
             j.n_terms = (int)tv.size();
-            j.U = F[l].as<double>() + (size_t)b * rq.r[l] * P.N[l];
+            j.U = F[l].as<double>() + (size_t)b * rr[l] * P.N[l];
             j.ldu = P.N[l];
             j.N_axis = P.N[l];
             j.ldg = P.ldg;
-            j.R = rq.r[l];
+            j.R = rr[l];
             jobs.push_back(j);
             maxN = std::max(maxN, P.N[l]);
-            maxR = std::max(maxR, rq.r[l]);
+            maxR = std::max(maxR, rr[l]);
         }
     DevBuf terms_d, jobs_d;
     if ((rc = terms_d.get(c->pool, std::max<size_t>(1, terms_h.size()) * sizeof(int2)))) return rc;
@@ -554,11 +652,22 @@ static int run_tucker_ref(Request* q, hipStream_t st, const hipStream_t* aux, St
     tm.end();
 
     // (4) per mode an orthonormal basis of the assembled vectors (the Gram-Schmidt step after
-    // Thm thm:sumCaseE): SVD of F_l's rows, every direction above 1e-13 of the largest kept
+    // Thm thm:sumCaseE): CholeskyQR2 of F_l's rows, or, when they are close to dependent (a union
+    // of blocks sharing an axis), the SVD of F_l's rows with every direction above 1e-13 of the
+    // largest kept
     tm.begin("svd");
     ModeSVD ms[3];
     for (int l = 0; l < 3; ++l) {
-        const int D = nb * rq.r[l], N = P.N[l];
+        const int D = nb * rr[l], N = P.N[l];
+        bool ok = false;
+        if ((rc = chol_qr2(c, st, D, N, F[l].as<double>(), q->Z[l], &ok))) return rc;
+        if (ok) {
+            q->r[l] = D;
+            q->sigma[l].clear();
+            q->sweeps[l] = 0;
+            q->tails[l] = 0.0;
+            continue;
+        }
         DevBuf W;
         if ((rc = W.get(c->pool, (size_t)D * N * 8))) return rc;
         LSUM_HIP(hipMemcpyAsync(W.p, F[l].p, (size_t)D * N * 8, hipMemcpyDeviceToDevice, st));
@@ -608,7 +717,7 @@ static int run_tucker_ref(Request* q, hipStream_t st, const hipStream_t* aux, St
     tm.begin("core");
     std::vector<double> Ch[3];
     for (int l = 0; l < 3; ++l) {
-        const int r = q->r[l], D = nb * rq.r[l], N = P.N[l];
+        const int r = q->r[l], D = nb * rr[l], N = P.N[l];
         DevBuf Cd;
         if ((rc = Cd.get(c->pool, (size_t)r * D * 8))) return rc;
         GemmArgs a{};
@@ -617,15 +726,13 @@ static int run_tucker_ref(Request* q, hipStream_t st, const hipStream_t* aux, St
         a.B = F[l].p; a.sbk = 1; a.sbn = N;
         a.C = Cd.p; a.scm = D; a.scn = 1;
         a.alpha = 1.0; a.beta = 0.0; a.batch = 1;
-        launch_gemm(st, GEMM_F64, a);
+        if ((rc = gemm_auto(c, st, GEMM_F64, a))) return rc;
         Ch[l].resize((size_t)r * D);
         LSUM_HIP(hipMemcpyAsync(Ch[l].data(), Cd.p, (size_t)r * D * 8, hipMemcpyDeviceToHost, st));
         LSUM_HIP(hipStreamSynchronize(st));
     }
-    const int s1 = rq.r[0], s2 = rq.r[1], s3 = rq.r[2];
-    std::vector<double> Bh((size_t)s1 * s2 * s3);
-    LSUM_HIP(hipMemcpyAsync(Bh.data(), rq.core.p, Bh.size() * 8, hipMemcpyDeviceToHost, st));
-    LSUM_HIP(hipStreamSynchronize(st));
+    const int s1 = rr[0], s2 = rr[1], s3 = rr[2];
+    const std::vector<double>& Bh = tr->core;
     const int k1 = q->r[0], k2 = q->r[1], k3 = q->r[2];
     std::vector<double> mu((size_t)k1 * k2 * k3, 0.0);
     std::vector<double> X((size_t)k1 * s2 * s3), Y((size_t)k1 * k2 * s3);

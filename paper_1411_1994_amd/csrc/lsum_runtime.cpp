@@ -292,6 +292,14 @@ static int build_tables(Context* c, const Plan& P, const std::vector<std::tuple<
     return LSUM_OK;
 }
 
+int get_tucker_ref(Context* c, const Plan& P, hipStream_t st, const std::function<int(RefEntry&)>& make,
+                   std::shared_ptr<RefEntry>& out) {
+    RefKey key = ref_key(P);
+    key += "tucker";
+    key.append((const char*)&P.eps, sizeof(double));
+    return cached_rows(c, key, P, 3 * (size_t)P.R * P.ldg * 8, st, make, out);
+}
+
 int get_tables(Context* c, const Plan& P, const std::vector<std::tuple<int, int, int>>& wins, hipStream_t st,
                std::shared_ptr<RefEntry>& out) {
     RefKey key = ref_key(P);

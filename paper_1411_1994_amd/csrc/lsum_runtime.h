@@ -8,6 +8,7 @@
 #include <chrono>
 #include <condition_variable>
 #include <deque>
+#include <functional>
 #include <map>
 #include <unordered_map>
 #include <memory>
@@ -117,6 +118,11 @@ struct RefEntry {
     bool cached = true;
     std::mutex win_mu;
     std::map<std::pair<int, int>, std::unique_ptr<WindowRows>> windows;   // by (stride, n)
+    // a reference Tucker form: G holds the three modes' vectors as zero-padded rows (mode l at
+    // element l * R * ldg, r[l] rows of ldg), `core` its r1 r2 r3 core (host FP64)
+    int r[3]{};
+    std::vector<double> core;
+    double norm_A = 0, norm_xi = 0, bound = 0;
 };
 // bytes of (kind, param, M, h_u, s, h, N_ref), followed for class tables by their layout
 using RefKey = std::string;
@@ -235,6 +241,10 @@ int get_reference(Context* c, const Plan& P, hipStream_t st, std::shared_ptr<Ref
 // of `wins` in order, each R x ldg.
 int get_tables(Context* c, const Plan& P, const std::vector<std::tuple<int, int, int>>& wins, hipStream_t st,
                std::shared_ptr<RefEntry>& out);
+// The rank-r Tucker form of a plan's reference (RHOSVD at the plan's eps of one unit charge on
+// the doubled box), cached like the reference rows; `make` computes it on a miss.
+int get_tucker_ref(Context* c, const Plan& P, hipStream_t st, const std::function<int(RefEntry&)>& make,
+                   std::shared_ptr<RefEntry>& out);
 // windowed strided sums of a reference (stride, comb length n), computed on st on first use;
 // complete on return
 int get_windows(Context* c, RefEntry& e, int stride, int n, hipStream_t st, const double** out);
@@ -245,6 +255,9 @@ void worker(Context* c, int slot);
 // pipeline stages (lsum_pipeline.cpp)
 // aux: three streams for the concurrent per-mode SVDs (nullptr: everything on st)
 int run_batch(std::vector<Request*>& reqs, hipStream_t st, const hipStream_t* aux = nullptr);
+// A GEMM that splits a long FP64 reduction over many workgroups when the output has few tiles
+// (synchronous in that case); otherwise one asynchronous launch.
+int gemm_auto(Context* c, hipStream_t st, GemmPrec prec, const GemmArgs& a);
 // one canonical request's points for a batched sampling launch (device pointers)
 struct CanonSample {
     Request* q;

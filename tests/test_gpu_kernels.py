@@ -47,6 +47,32 @@ def test_contract_fp64(ctx, m, n, k, layout):
     assert np.all(np.abs(got - ref) <= bound)
 
 
+@pytest.mark.parametrize("m,n,k", [(33, 33, 34305), (50, 50, 4099), (7, 200, 5000), (128, 64, 2048),
+                                   (1, 1, 100003)])
+@pytest.mark.parametrize("layout", ["nn", "tn", "nt", "tt"])
+def test_contract_fp64_split_reduction(ctx, m, n, k, layout):
+    # few output tiles and a long reduction: the reduction is split over workgroups and the slices'
+    # products summed in order; C has a row stride wider than n (only its m x n part is written)
+    import paper_1411_1994_amd as L
+    rng = np.random.default_rng(m * 7 + n * 3 + k)
+    A = rng.standard_normal((m, k))
+    B = rng.standard_normal((k, n))
+    ldc = n + 5
+    Cin = rng.standard_normal((m, ldc))
+    As = A if layout[0] == "n" else np.ascontiguousarray(A.T)
+    Bs = B if layout[1] == "n" else np.ascontiguousarray(B.T)
+    sam, sak = (k, 1) if layout[0] == "n" else (1, m)
+    sbk, sbn = (n, 1) if layout[1] == "n" else (1, k)
+    dA, dB, dC = dev(As), dev(Bs), dev(Cin)
+    ctx.contract(L.FP64, m, n, k, dA, sam, sak, dB, sbk, sbn, dC, ldc, 1, alpha=0.5, beta=2.0)
+    got = host(dC)
+    ref = Cin.copy()
+    ref[:, :n] = 0.5 * (A @ B) + 2.0 * Cin[:, :n]
+    bound = k * 2.0 ** -53 * (0.5 * np.abs(A) @ np.abs(B) + 2 * np.abs(Cin[:, :n])) * 4 + 1e-300
+    assert np.all(np.abs(got[:, :n] - ref[:, :n]) <= bound)
+    assert np.array_equal(got[:, n:], Cin[:, n:])
+
+
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
 @pytest.mark.parametrize("m,n,k", [(16, 16, 32), (70, 33, 129), (130, 257, 700)])
 def test_contract_fp32_and_split_bf16(ctx, prec, m, n, k):
