@@ -461,29 +461,50 @@ def tucker_reference(problem) -> TuckerResult:
 
 
 def tucker_lattice_sum(problem):
-    """eq. ``Tuck_LatticeSum``: per block and axis the windowed sums of the reference Tucker
-    vectors over the block's sites, stacked block after block; per mode Gram-Schmidt (QR) of the
-    stacked vectors, the triangular factors carried into the core with each block's charge.
-    Returns (core, [Q_1, Q_2, Q_3]), Q_l (N_l x k_l) with orthonormal columns."""
+    """eq. ``Tuck_LatticeSum`` per block: the windowed sums of the reference Tucker vectors over
+    the block's sites, made orthonormal by Gram-Schmidt (QR) with the triangular factors carried
+    into the block's core (times its charge).  One block: that Tucker tensor.  Several blocks
+    (the sum of Tucker tensors of eq. ``WindowTuck_sum``): the generalised RHOSVD of Thm
+    ``thm:TSum2Tucker``, i.e. per mode the truncated SVD of the blocks' stacked factor columns
+    (eq. ``SideMTuckS``), the smallest rank whose tail is <= eps ||U|| / (3 |B|) with
+    |B|^2 = sum_b ||B_b||^2, so that the bound |B| sum_l tail_l of the theorem is <= eps ||U||,
+    and the core by projection.  Returns (core, [Z_1, Z_2, Z_3], bound, norm), Z_l (N_l x k_l)
+    with orthonormal columns, norm = ||U|| of the untruncated sum."""
     ref = tucker_reference(problem)
     Nr = max(problem.N)
-    stacked = [[], [], []]
+    terms = []                                         # (core B_b, [Q_1, Q_2, Q_3])
     for blk in problem.blocks:
         offs = block_offsets(blk, problem.h, problem.N)
+        Q, Rt = [], []
         for a in range(3):
-            stacked[a].append(shift_sum(ref.Z[a].T, offs[a], problem.N[a], Nr))   # r_a x N_a
-    Q, Rt = [], []
+            F = shift_sum(ref.Z[a].T, offs[a], problem.N[a], Nr)      # r_a x N_a
+            q, rr = np.linalg.qr(F.T)
+            Q.append(q)
+            Rt.append(rr)
+        B = blk.charge * np.einsum("ijk,ai,bj,ck->abc", ref.core, Rt[0], Rt[1], Rt[2], optimize=True)
+        terms.append((B, Q))
+    if len(terms) == 1:
+        B, Q = terms[0]
+        return B, Q, 0.0, float(np.linalg.norm(B))
+    # ||U||^2 = sum_{b,b'} <T_b, T_b'>, each from the cross Grams of the factors
+    norm2 = 0.0
+    for Bb, Qb in terms:
+        for Bc, Qc in terms:
+            G = [Qb[a].T @ Qc[a] for a in range(3)]
+            norm2 += float(np.einsum("ijk,abc,ia,jb,kc->", Bb, Bc, G[0], G[1], G[2], optimize=True))
+    norm = math.sqrt(max(norm2, 0.0))
+    Bhat = math.sqrt(sum(float(np.linalg.norm(B)) ** 2 for B, _ in terms))
+    thr = problem.eps * norm / (3.0 * Bhat)
+    Z, tails = [], []
     for a in range(3):
-        q, rr = np.linalg.qr(np.concatenate(stacked[a], axis=0).T)
-        Q.append(q)
-        Rt.append(rr)
-    r1, r2, r3 = ref.ranks
-    core = np.zeros((Rt[0].shape[0], Rt[1].shape[0], Rt[2].shape[0]))
-    for b, blk in enumerate(problem.blocks):
-        core += blk.charge * np.einsum("ijk,ai,bj,ck->abc", ref.core, Rt[0][:, b * r1:(b + 1) * r1],
-                                       Rt[1][:, b * r2:(b + 1) * r2], Rt[2][:, b * r3:(b + 1) * r3],
-                                       optimize=True)
-    return core, Q
+        U, S, _ = np.linalg.svd(np.concatenate([Q[a] for _, Q in terms], axis=1), full_matrices=False)
+        tl = tail_norms(S)
+        r = max(int(np.argmax(tl <= thr)), 1)
+        Z.append(U[:, :r])
+        tails.append(float(tl[r]))
+    core = sum(np.einsum("ijk,ai,bj,ck->abc", B, Z[0].T @ Q[0], Z[1].T @ Q[1], Z[2].T @ Q[2], optimize=True)
+               for B, Q in terms)
+    return core, Z, Bhat * sum(tails), norm
 
 
 # ---------------------------------------------------------------------------------------

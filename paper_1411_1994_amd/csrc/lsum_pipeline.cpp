@@ -527,6 +527,93 @@ static int chol_qr2(Context* c, hipStream_t st, int D, int N, const double* F, D
     return LSUM_OK;
 }
 
+// mu (k1 x k2 x k3) += scale * B x_1 C1 x_2 C2 x_3 C3 for B (s1 x s2 x s3, last index fastest):
+// mu[a,e,f] += scale sum_{i,j,k} B[i,j,k] C1[a, o1 + i] C2[e, o2 + j] C3[f, o3 + k], C_l row-major
+// with row stride ld_l (host FP64; the sizes are a few tens per mode).
+static void add_mode_products(const double* B, int s1, int s2, int s3, const double* C1, int ld1, int o1,
+                              const double* C2, int ld2, int o2, const double* C3, int ld3, int o3, int k1, int k2,
+                              int k3, double scale, double* mu) {
+    std::vector<double> X((size_t)k1 * s2 * s3, 0.0), Y((size_t)k1 * k2 * s3, 0.0);
+    for (int a = 0; a < k1; ++a)
+        for (int i = 0; i < s1; ++i) {
+            const double cf = C1[(size_t)a * ld1 + o1 + i];
+            const double* Bi = B + (size_t)i * s2 * s3;
+            double* Xa = &X[(size_t)a * s2 * s3];
+            for (int jk = 0; jk < s2 * s3; ++jk) Xa[jk] += cf * Bi[jk];
+        }
+    for (int a = 0; a < k1; ++a)
+        for (int e = 0; e < k2; ++e)
+            for (int j = 0; j < s2; ++j) {
+                const double cf = C2[(size_t)e * ld2 + o2 + j];
+                const double* Xj = &X[((size_t)a * s2 + j) * s3];
+                double* Ye = &Y[((size_t)a * k2 + e) * s3];
+                for (int k = 0; k < s3; ++k) Ye[k] += cf * Xj[k];
+            }
+    for (size_t ae = 0; ae < (size_t)k1 * k2; ++ae)
+        for (int f = 0; f < k3; ++f) {
+            const double* c3 = C3 + (size_t)f * ld3 + o3;
+            const double* Ya = &Y[ae * s3];
+            double acc = 0.0;
+            for (int k = 0; k < s3; ++k) acc += c3[k] * Ya[k];
+            mu[ae * k3 + f] += scale * acc;
+        }
+}
+
+// The leading r singular vectors of an SVD as factor rows (r x N): rotated rows / sigma, or the
+// unit rows of the range path.
+static int rows_to_factor(Context* c, hipStream_t st, ModeSVD& ms, int r, int N, DevBuf& Z) {
+    int rc;
+    std::vector<double> inv(r);
+    std::vector<int32_t> ord(r);
+    for (int a = 0; a < r; ++a) { inv[a] = ms.unit ? 1.0 : 1.0 / ms.sigma[a]; ord[a] = a; }
+    DevBuf od, iv;
+    if ((rc = od.get(c->pool, r * 4))) return rc;
+    if ((rc = iv.get(c->pool, r * 8))) return rc;
+    if ((rc = Z.get(c->pool, (size_t)r * N * 8))) return rc;
+    LSUM_HIP(hipMemcpyAsync(od.p, ord.data(), r * 4, hipMemcpyHostToDevice, st));
+    LSUM_HIP(hipMemcpyAsync(iv.p, inv.data(), r * 8, hipMemcpyHostToDevice, st));
+    launch_gather_scale_rows(st, r, N, ms.rows.as<double>() + ms.off, (int)ms.ld, od.as<int32_t>(), iv.as<double>(),
+                             Z.as<double>(), N);
+    LSUM_HIP(hipStreamSynchronize(st));
+    ms.rows.reset();
+    return LSUM_OK;
+}
+
+// Orthonormal rows Q (k x N) spanning the D rows of F: CholeskyQR2 (k = D), or, when the rows are
+// close to dependent, the SVD with every direction above 1e-13 of ||F|| kept.
+static int orthonormal_rows(Context* c, hipStream_t st, int D, int N, const double* F, DevBuf& Q, int* k) {
+    int rc;
+    bool ok = false;
+    if ((rc = chol_qr2(c, st, D, N, F, Q, &ok))) return rc;
+    if (ok) {
+        *k = D;
+        return LSUM_OK;
+    }
+    DevBuf W, nrm;
+    if ((rc = W.get(c->pool, (size_t)D * N * 8)) || (rc = nrm.get(c->pool, (size_t)D * 8))) return rc;
+    LSUM_HIP(hipMemcpyAsync(W.p, F, (size_t)D * N * 8, hipMemcpyDeviceToDevice, st));
+    launch_row_norms(st, D, N, F, N, nrm.as<double>());
+    std::vector<double> nh(D);
+    LSUM_HIP(hipMemcpyAsync(nh.data(), nrm.p, D * 8, hipMemcpyDeviceToHost, st));
+    LSUM_HIP(hipStreamSynchronize(st));
+    double f2 = 0.0;
+    for (double v : nh) f2 += v * v;
+    const double thr = 1e-13 * std::sqrt(f2);
+    ModeSVD ms;
+    if ((rc = mode_svd(c, st, D, N, W, thr, 1e-2 * thr / std::sqrt((double)D), ms))) return rc;
+    LSUM_HIP(hipStreamSynchronize(st));
+    const int n = (int)ms.sigma.size();
+    std::vector<double> tail(n + 1, 0.0);
+    tail[n] = ms.res2;
+    for (int j = n - 1; j >= 0; --j) tail[j] = tail[j + 1] + ms.sigma[j] * ms.sigma[j];
+    int r = n;
+    for (int j = 1; j <= n; ++j)
+        if (std::sqrt(tail[j]) <= thr) { r = j; break; }
+    r = std::max(1, std::min(r, N));
+    *k = r;
+    return rows_to_factor(c, st, ms, r, N, Q);
+}
+
 // ------------------------------------------------------------------------------------------
 // Tucker-reference sum (Thm thm:sumCaseE (B)): the rank-r Tucker form of the reference, its
 // vectors assembled over the lattice, orthonormalised per mode
@@ -651,127 +738,158 @@ static int run_tucker_ref(Request* q, hipStream_t st, const hipStream_t* aux, St
     LSUM_HIP(hipStreamSynchronize(st));   // the job tables and window sums are released below
     tm.end();
 
-    // (4) per mode an orthonormal basis of the assembled vectors (the Gram-Schmidt step after
-    // Thm thm:sumCaseE): CholeskyQR2 of F_l's rows, or, when they are close to dependent (a union
-    // of blocks sharing an axis), the SVD of F_l's rows with every direction above 1e-13 of the
-    // largest kept
+    // (4) per block and mode an orthonormal basis Q_b,l of the assembled vectors (the Gram-Schmidt
+    // step after Thm thm:sumCaseE), and the block's core B_b = charge_b B x_l C_b,l with
+    // C_b,l = Q_b,l F_b,l^T (its triangular factor)
     tm.begin("svd");
-    ModeSVD ms[3];
-    for (int l = 0; l < 3; ++l) {
-        const int D = nb * rr[l], N = P.N[l];
-        bool ok = false;
-        if ((rc = chol_qr2(c, st, D, N, F[l].as<double>(), q->Z[l], &ok))) return rc;
-        if (ok) {
-            q->r[l] = D;
-            q->sigma[l].clear();
-            q->sweeps[l] = 0;
-            q->tails[l] = 0.0;
-            continue;
-        }
-        DevBuf W;
-        if ((rc = W.get(c->pool, (size_t)D * N * 8))) return rc;
-        LSUM_HIP(hipMemcpyAsync(W.p, F[l].p, (size_t)D * N * 8, hipMemcpyDeviceToDevice, st));
-        DevBuf nrm;
-        if ((rc = nrm.get(c->pool, (size_t)D * 8))) return rc;
-        launch_row_norms(st, D, N, F[l].as<double>(), N, nrm.as<double>());
-        std::vector<double> nh(D);
-        LSUM_HIP(hipMemcpyAsync(nh.data(), nrm.p, D * 8, hipMemcpyDeviceToHost, st));
-        LSUM_HIP(hipStreamSynchronize(st));
-        double f2 = 0.0;
-        for (double v : nh) f2 += v * v;
-        const double thr = 1e-13 * std::sqrt(f2);
-        if ((rc = mode_svd(c, st, D, N, W, thr, 1e-2 * thr / std::sqrt((double)D), ms[l]))) return rc;
-        LSUM_HIP(hipStreamSynchronize(st));
-        const auto& sg = ms[l].sigma;
-        const int n = (int)sg.size();
-        std::vector<double> tail(n + 1, 0.0);
-        tail[n] = ms[l].res2;
-        for (int k = n - 1; k >= 0; --k) tail[k] = tail[k + 1] + sg[k] * sg[k];
-        int r = n;
-        for (int k = 1; k <= n; ++k)
-            if (std::sqrt(tail[k]) <= thr) { r = k; break; }
-        r = std::max(1, std::min(r, N));
-        q->r[l] = r;
-        q->sigma[l] = sg;
-        q->sweeps[l] = ms[l].sweeps;
-        q->tails[l] = std::sqrt(tail[r]);
-        std::vector<double> inv(r);
-        std::vector<int32_t> ord(r);
-        for (int a = 0; a < r; ++a) { inv[a] = ms[l].unit ? 1.0 : 1.0 / sg[a]; ord[a] = a; }
-        DevBuf od, iv;
-        if ((rc = od.get(c->pool, r * 4))) return rc;
-        if ((rc = iv.get(c->pool, r * 8))) return rc;
-        if ((rc = q->Z[l].get(c->pool, (size_t)r * N * 8))) return rc;
-        LSUM_HIP(hipMemcpyAsync(od.p, ord.data(), r * 4, hipMemcpyHostToDevice, st));
-        LSUM_HIP(hipMemcpyAsync(iv.p, inv.data(), r * 8, hipMemcpyHostToDevice, st));
-        launch_gather_scale_rows(st, r, N, ms[l].rows.as<double>() + ms[l].off, (int)ms[l].ld, od.as<int32_t>(),
-                                 iv.as<double>(), q->Z[l].as<double>(), N);
-        LSUM_HIP(hipStreamSynchronize(st));
-        ms[l].rows.reset();
-    }
-    tm.end();
-
-    // (5) core: with C_l = Z_l F_l^T (r_l x nb r_l^ref), mu = sum_b charge_b B x_1 C_1,b x_2 C_2,b
-    // x_3 C_3,b over the reference core B and block b's columns of C_l (host FP64; the sizes are
-    // a few tens per mode)
-    tm.begin("core");
-    std::vector<double> Ch[3];
-    for (int l = 0; l < 3; ++l) {
-        const int r = q->r[l], D = nb * rr[l], N = P.N[l];
-        DevBuf Cd;
-        if ((rc = Cd.get(c->pool, (size_t)r * D * 8))) return rc;
-        GemmArgs a{};
-        a.m = r; a.n = D; a.k = N;
-        a.A = q->Z[l].p; a.sam = N; a.sak = 1;
-        a.B = F[l].p; a.sbk = 1; a.sbn = N;
-        a.C = Cd.p; a.scm = D; a.scn = 1;
-        a.alpha = 1.0; a.beta = 0.0; a.batch = 1;
-        if ((rc = gemm_auto(c, st, GEMM_F64, a))) return rc;
-        Ch[l].resize((size_t)r * D);
-        LSUM_HIP(hipMemcpyAsync(Ch[l].data(), Cd.p, (size_t)r * D * 8, hipMemcpyDeviceToHost, st));
-        LSUM_HIP(hipStreamSynchronize(st));
-    }
-    const int s1 = rr[0], s2 = rr[1], s3 = rr[2];
-    const std::vector<double>& Bh = tr->core;
-    const int k1 = q->r[0], k2 = q->r[1], k3 = q->r[2];
-    std::vector<double> mu((size_t)k1 * k2 * k3, 0.0);
-    std::vector<double> X((size_t)k1 * s2 * s3), Y((size_t)k1 * k2 * s3);
+    const double* Bref = tr->core.data();
+    std::vector<DevBuf> Qb((size_t)nb * 3);
+    std::vector<int> kb((size_t)nb * 3);
+    std::vector<std::vector<double>> Bb(nb);
+    int kbl[3] = {0, 0, 0};          // stacked rows per mode
     for (int b = 0; b < nb; ++b) {
-        const double lam = P.blocks[b].charge;
-        const int D1 = nb * s1, D2 = nb * s2, D3 = nb * s3;
-        // X[a, j, k] = sum_i C1[a, b s1 + i] B[i, j, k]
-        std::fill(X.begin(), X.end(), 0.0);
-        for (int a = 0; a < k1; ++a)
-            for (int i = 0; i < s1; ++i) {
-                const double cf = Ch[0][(size_t)a * D1 + b * s1 + i];
-                const double* Bi = &Bh[(size_t)i * s2 * s3];
-                double* Xa = &X[(size_t)a * s2 * s3];
-                for (int jk = 0; jk < s2 * s3; ++jk) Xa[jk] += cf * Bi[jk];
+        std::vector<double> Cb[3];
+        for (int l = 0; l < 3; ++l) {
+            const int N = P.N[l];
+            const double* Fb = F[l].as<double>() + (size_t)b * rr[l] * N;
+            int k = 0;
+            if ((rc = orthonormal_rows(c, st, rr[l], N, Fb, Qb[b * 3 + l], &k))) return rc;
+            kb[b * 3 + l] = k;
+            kbl[l] += k;
+            DevBuf Cd;
+            if ((rc = Cd.get(c->pool, (size_t)k * rr[l] * 8))) return rc;
+            GemmArgs a{};
+            a.m = k; a.n = rr[l]; a.k = N;
+            a.A = Qb[b * 3 + l].p; a.sam = N; a.sak = 1;
+            a.B = Fb; a.sbk = 1; a.sbn = N;
+            a.C = Cd.p; a.scm = rr[l]; a.scn = 1;
+            a.alpha = 1.0; a.beta = 0.0; a.batch = 1;
+            if ((rc = gemm_auto(c, st, GEMM_F64, a))) return rc;
+            Cb[l].resize((size_t)k * rr[l]);
+            LSUM_HIP(hipMemcpyAsync(Cb[l].data(), Cd.p, Cb[l].size() * 8, hipMemcpyDeviceToHost, st));
+            LSUM_HIP(hipStreamSynchronize(st));
+        }
+        const int k1 = kb[b * 3], k2 = kb[b * 3 + 1], k3 = kb[b * 3 + 2];
+        Bb[b].assign((size_t)k1 * k2 * k3, 0.0);
+        add_mode_products(Bref, rr[0], rr[1], rr[2], Cb[0].data(), rr[0], 0, Cb[1].data(), rr[1], 0, Cb[2].data(),
+                          rr[2], 0, k1, k2, k3, P.blocks[b].charge, Bb[b].data());
+    }
+    std::vector<double> mu;
+    if (nb == 1) {
+        for (int l = 0; l < 3; ++l) {
+            q->r[l] = kb[l];
+            q->Z[l] = std::move(Qb[l]);
+            q->sigma[l].clear();
+            q->tails[l] = 0.0;
+        }
+        mu = std::move(Bb[0]);
+        double n2 = 0.0;
+        for (double v : mu) n2 += v * v;
+        q->norm_A = std::sqrt(n2);
+        q->norm_xi = q->norm_A;
+        q->bound = 0.0;
+        tm.end();
+    } else {
+        // (5) several blocks: the generalised RHOSVD of their Tucker sum (Thm thm:TSum2Tucker).
+        // Stacked side rows per mode (eq. SideMTuckS), their Gram, ||U||^2 = sum_{b,b'} <T_b, T_b'>
+        // from the cross Grams, |B|^2 = sum_b ||B_b||^2, per mode the smallest rank whose tail is
+        // <= eps ||U|| / (3 |B|), and the core by projection: mu = sum_b B_b x_l (Z_l Q_b,l^T)
+        DevBuf S[3];
+        std::vector<int> off((size_t)nb * 3);
+        std::vector<double> G[3];
+        for (int l = 0; l < 3; ++l) {
+            const int N = P.N[l], K = kbl[l];
+            if ((rc = S[l].get(c->pool, (size_t)K * N * 8))) return rc;
+            int o = 0;
+            for (int b = 0; b < nb; ++b) {
+                off[b * 3 + l] = o;
+                LSUM_HIP(hipMemcpyAsync(S[l].as<double>() + (size_t)o * N, Qb[b * 3 + l].p,
+                                        (size_t)kb[b * 3 + l] * N * 8, hipMemcpyDeviceToDevice, st));
+                o += kb[b * 3 + l];
             }
-        // Y[a, e, k] = sum_j C2[e, b s2 + j] X[a, j, k]
-        std::fill(Y.begin(), Y.end(), 0.0);
-        for (int a = 0; a < k1; ++a)
-            for (int e = 0; e < k2; ++e)
-                for (int j = 0; j < s2; ++j) {
-                    const double cf = Ch[1][(size_t)e * D2 + b * s2 + j];
-                    const double* Xj = &X[((size_t)a * s2 + j) * s3];
-                    double* Ye = &Y[((size_t)a * k2 + e) * s3];
-                    for (int k = 0; k < s3; ++k) Ye[k] += cf * Xj[k];
-                }
-        // mu[a, e, f] += lam sum_k C3[f, b s3 + k] Y[a, e, k]
-        for (size_t ae = 0; ae < (size_t)k1 * k2; ++ae)
-            for (int f = 0; f < k3; ++f) {
-                const double* C3 = &Ch[2][(size_t)f * D3 + b * s3];
-                const double* Ya = &Y[ae * s3];
-                double acc = 0.0;
-                for (int k = 0; k < s3; ++k) acc += C3[k] * Ya[k];
-                mu[ae * k3 + f] += lam * acc;
+            DevBuf Gd;
+            if ((rc = Gd.get(c->pool, (size_t)K * K * 8))) return rc;
+            GemmArgs a{};
+            a.m = K; a.n = K; a.k = N;
+            a.A = S[l].p; a.sam = N; a.sak = 1;
+            a.B = S[l].p; a.sbk = 1; a.sbn = N;
+            a.C = Gd.p; a.scm = K; a.scn = 1;
+            a.alpha = 1.0; a.beta = 0.0; a.batch = 1;
+            if ((rc = gemm_auto(c, st, GEMM_F64, a))) return rc;
+            G[l].resize((size_t)K * K);
+            LSUM_HIP(hipMemcpyAsync(G[l].data(), Gd.p, G[l].size() * 8, hipMemcpyDeviceToHost, st));
+            LSUM_HIP(hipStreamSynchronize(st));
+        }
+        double n2 = 0.0, bh2 = 0.0;
+        for (int b = 0; b < nb; ++b) {
+            for (double v : Bb[b]) bh2 += v * v;
+            for (int e = 0; e < nb; ++e) {
+                // <T_b, T_e> = sum B_b[i,j,k] B_e[i',j',k'] G1[i,i'] G2[j,j'] G3[k,k']: B_e x_l (G_l blocks)
+                const int i1 = kb[b * 3], i2 = kb[b * 3 + 1], i3 = kb[b * 3 + 2];
+                std::vector<double> T((size_t)i1 * i2 * i3, 0.0);
+                add_mode_products(Bb[e].data(), kb[e * 3], kb[e * 3 + 1], kb[e * 3 + 2],
+                                  G[0].data() + (size_t)off[b * 3] * kbl[0], kbl[0], off[e * 3],
+                                  G[1].data() + (size_t)off[b * 3 + 1] * kbl[1], kbl[1], off[e * 3 + 1],
+                                  G[2].data() + (size_t)off[b * 3 + 2] * kbl[2], kbl[2], off[e * 3 + 2], i1, i2, i3,
+                                  1.0, T.data());
+                for (size_t x = 0; x < T.size(); ++x) n2 += Bb[b][x] * T[x];
             }
+        }
+        const double normU = std::sqrt(std::max(n2, 0.0)), Bhat = std::sqrt(bh2);
+        const double thr = P.eps * normU / (3.0 * Bhat);
+        q->norm_A = normU;
+        q->norm_xi = Bhat;
+        q->bound = 0.0;
+        std::vector<double> Cp[3];
+        for (int l = 0; l < 3; ++l) {
+            const int N = P.N[l], K = kbl[l];
+            DevBuf W;
+            if ((rc = W.get(c->pool, (size_t)K * N * 8))) return rc;
+            LSUM_HIP(hipMemcpyAsync(W.p, S[l].p, (size_t)K * N * 8, hipMemcpyDeviceToDevice, st));
+            ModeSVD ms;
+            if ((rc = mode_svd(c, st, K, N, W, thr, 1e-2 * thr / std::sqrt((double)K), ms))) return rc;
+            LSUM_HIP(hipStreamSynchronize(st));
+            const auto& sg = ms.sigma;
+            const int n = (int)sg.size();
+            std::vector<double> tail(n + 1, 0.0);
+            tail[n] = ms.res2;
+            for (int k = n - 1; k >= 0; --k) tail[k] = tail[k + 1] + sg[k] * sg[k];
+            int r = n;
+            for (int k = 1; k <= n; ++k)
+                if (std::sqrt(tail[k]) <= thr) { r = k; break; }
+            r = std::max(1, std::min(r, N));
+            q->r[l] = r;
+            q->sigma[l] = sg;
+            q->sweeps[l] = ms.sweeps;
+            q->tails[l] = std::sqrt(tail[r]);
+            q->bound += q->tails[l];
+            if ((rc = rows_to_factor(c, st, ms, r, N, q->Z[l]))) return rc;
+            DevBuf Cd;
+            if ((rc = Cd.get(c->pool, (size_t)r * K * 8))) return rc;
+            GemmArgs a{};
+            a.m = r; a.n = K; a.k = N;
+            a.A = q->Z[l].p; a.sam = N; a.sak = 1;
+            a.B = S[l].p; a.sbk = 1; a.sbn = N;
+            a.C = Cd.p; a.scm = K; a.scn = 1;
+            a.alpha = 1.0; a.beta = 0.0; a.batch = 1;
+            if ((rc = gemm_auto(c, st, GEMM_F64, a))) return rc;
+            Cp[l].resize((size_t)r * K);
+            LSUM_HIP(hipMemcpyAsync(Cp[l].data(), Cd.p, Cp[l].size() * 8, hipMemcpyDeviceToHost, st));
+            LSUM_HIP(hipStreamSynchronize(st));
+        }
+        q->bound *= Bhat;
+        tm.end();
+        tm.begin("core");
+        mu.assign((size_t)q->r[0] * q->r[1] * q->r[2], 0.0);
+        for (int b = 0; b < nb; ++b)
+            add_mode_products(Bb[b].data(), kb[b * 3], kb[b * 3 + 1], kb[b * 3 + 2], Cp[0].data(), kbl[0],
+                              off[b * 3], Cp[1].data(), kbl[1], off[b * 3 + 1], Cp[2].data(), kbl[2], off[b * 3 + 2],
+                              q->r[0], q->r[1], q->r[2], 1.0, mu.data());
+        tm.end();
     }
     if ((rc = q->core.get(c->pool, mu.size() * 8))) return rc;
     LSUM_HIP(hipMemcpyAsync(q->core.p, mu.data(), mu.size() * 8, hipMemcpyHostToDevice, st));
     LSUM_HIP(hipStreamSynchronize(st));
-    tm.end();
     q->bytes["core"] = (double)mu.size() * 8;
     if (P.has_tile() && (rc = make_tile(q, st, tm))) return rc;
     return LSUM_OK;

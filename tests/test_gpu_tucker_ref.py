@@ -44,7 +44,7 @@ def test_tucker_reference_sum_matches_oracle(ctx, kind, param, eps):
     blk = W.Block((6, 5, 4), (1.0, 1.25, 0.75), (0.25, -0.5, 0.0))
     p = W.Problem("tref", kind, param, 28, (81, 75, 69), 0.25, [blk], eps=eps, method=1)
     r = run(ctx, p)
-    core_o, Q_o = O.tucker_lattice_sum(p)
+    core_o, Q_o, _, _ = O.tucker_lattice_sum(p)
     assert tuple(r.info().r) == core_o.shape          # the reference's ranks (Thm (B))
     pts = points(p, 300, 61)
     got = r.sample(cells_xyz(p, pts))
@@ -61,7 +61,7 @@ def test_tucker_reference_union_of_blocks_and_tile(ctx):
     p = W.Problem("tref2", W.NEWTON, 0.0, 28, (65, 61, 57), 0.25, blocks, eps=1e-7, method=1,
                   tile_lo=(10, 12, 14), tile_T=(24, 20, 16))
     r = run(ctx, p)
-    core_o, Q_o = O.tucker_lattice_sum(p)
+    core_o, Q_o, _, _ = O.tucker_lattice_sum(p)
     pts = points(p, 300, 62)
     got = r.sample(cells_xyz(p, pts))
     assert rel(got, O.tucker_points(core_o, Q_o, pts)) <= 1e-10
@@ -95,3 +95,27 @@ def test_tucker_reference_rejects_what_it_does_not_cover(ctx):
         with pytest.raises(L.LsumError) as e:
             ctx.submit(p)
         assert e.value.code == -1
+
+
+def test_generalised_rhosvd_of_blocks_with_vacancy_and_impurity_blocks(ctx):
+    # the setting of Fig. fig:Tuck_vac: a 16 x 16 x 1 lattice with a 2 x 2 x 1 block of vacancies
+    # (charge -1) and a 2 x 2 x 1 block of impurities (Z = 1.5: charge change 0.5), summed as Tucker
+    # tensors and truncated by the generalised RHOSVD (Thm thm:TSum2Tucker) at eps
+    eps = 1e-6
+    blocks = [W.Block((16, 16, 1), (1.0, 1.0, 1.0), (0.0, 0.0, 0.0)),
+              W.Block((2, 2, 1), (1.0, 1.0, 1.0), (-3.0, 2.0, 0.0), charge=-1.0),
+              W.Block((2, 2, 1), (1.0, 1.0, 1.0), (4.0, -5.0, 0.0), charge=0.5)]
+    p = W.Problem("tref-vac", W.NEWTON, 0.0, 28, (161, 161, 65), 0.125, blocks, eps=eps, method=1)
+    r = run(ctx, p)
+    core_o, Z_o, bound_o, norm_o = O.tucker_lattice_sum(p)
+    info = r.info()
+    assert tuple(info.r) == core_o.shape
+    assert info.rel_bound <= eps and abs(info.norm_A - norm_o) <= 1e-10 * norm_o
+    # the device's tail is ||W||^2 less the retained rows' norms after its Jacobi rotations, never
+    # below the exact tail (Ky Fan) and looser where rows below the irrelevance floor stay unrotated
+    assert bound_o * (1 - 1e-9) <= info.bound <= 2 * bound_o
+    pts = points(p, 300, 64)
+    got = r.sample(cells_xyz(p, pts))
+    r.release()
+    assert rel(got, O.tucker_points(core_o, Z_o, pts)) <= 1e-9
+    assert rel(got, O.brute_force_points(p, pts)) <= 10 * eps

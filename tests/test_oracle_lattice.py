@@ -378,7 +378,7 @@ def test_tucker_reference_sum_of_one_charge_is_the_windowed_reference():
     # one site: the assembled vectors are the reference vectors' windows, so the sum is the
     # reference Tucker tensor read at the displacements
     p = _tref_problem([W.Block((1, 1, 1), (1.0, 1.0, 1.0), (0.5, -0.75, 0.25))])
-    core, Q = O.tucker_lattice_sum(p)
+    core, Q, _, _ = O.tucker_lattice_sum(p)
     ref = O.tucker_reference(p)
     c = np.array([O.block_offsets(p.blocks[0], p.h, p.N)[a][0] for a in range(3)])
     pts = np.stack([np.random.default_rng(6).integers(0, n, 50) for n in p.N], axis=1)
@@ -392,11 +392,12 @@ def test_tucker_reference_sum_of_one_charge_is_the_windowed_reference():
 
 def test_tucker_reference_sum_error_is_bounded_by_the_reference_error():
     # T_cL - P_cL = sum_k W_k (T_ref - P_ref): each window is a sub-box of the reference, so
-    # ||T_cL - P_cL||_F <= (number of sites) ||T_ref - P_ref||_F, on the full (small) grid
+    # ||T_cL - P_cL||_F <= (number of sites) ||T_ref - P_ref||_F (plus, for two blocks, the
+    # certified truncation of their sum), on the full (small) grid
     blocks = [W.Block((3, 3, 2), (1.0, 1.25, 1.5), (0.0, 0.25, -0.5)),
               W.Block((2, 1, 2), (0.75, 1.0, 1.0), (-2.0, 1.5, 1.0), charge=-0.5)]
     p = _tref_problem(blocks)
-    core, Q = O.tucker_lattice_sum(p)
+    core, Q, bound, _ = O.tucker_lattice_sum(p)
     T = O.tucker_full(core, Q)
     P = O.brute_force_grid(p)
     ref = O.tucker_reference(p)
@@ -405,7 +406,7 @@ def test_tucker_reference_sum_error_is_bounded_by_the_reference_error():
     Pref = np.einsum("qi,qj,qk->ijk", Bv, Bv, Bv, optimize=True)
     e_ref = np.linalg.norm(O.tucker_full(ref.core, ref.Z) - Pref)
     n_sites = sum(abs(b.charge) * np.prod(b.L) for b in blocks)
-    assert np.linalg.norm(T - P) <= n_sites * e_ref * (1 + 1e-9)
+    assert np.linalg.norm(T - P) <= n_sites * e_ref * (1 + 1e-9) + bound
     assert np.linalg.norm(T - P) <= 1e-5 * np.linalg.norm(P)
     # and the reference's own error obeys its certified RHOSVD bound
     assert e_ref <= ref.bound * (1 + 1e-9) and ref.bound <= p.eps * np.linalg.norm(Pref) * (1 + 1e-9)
@@ -416,6 +417,24 @@ def test_tucker_reference_sum_keeps_the_reference_ranks_for_every_L():
     ranks = set()
     for L in (1, 2, 4, 8):
         p = _tref_problem([W.Block((L, L, L), (1.0, 1.0, 1.0), (0.0, 0.0, 0.0))], N=(41, 41, 41))
-        core, Q = O.tucker_lattice_sum(p)
+        core, Q, _, _ = O.tucker_lattice_sum(p)
         ranks.add(core.shape)
     assert len(ranks) == 1 and ranks.pop() == O.tucker_reference(p).ranks
+
+
+def test_generalised_rhosvd_of_a_union_of_blocks():
+    # Thm thm:TSum2Tucker on the sum of two blocks' Tucker tensors: the truncated result is within
+    # its certified bound of the untruncated sum, the bound is <= eps ||U||, ||U|| is the full
+    # tensor's norm, and the ranks drop below the stacked 2 r
+    blocks = [W.Block((4, 4, 2), (1.0, 1.0, 1.0), (0.0, 0.0, 0.0)),
+              W.Block((2, 2, 1), (1.0, 1.0, 1.0), (0.5, 0.5, 0.0), charge=-1.0)]
+    p = _tref_problem(blocks, eps=1e-4)
+    core, Z, bound, norm = O.tucker_lattice_sum(p)
+    parts = [O.tucker_lattice_sum(_tref_problem([b], eps=1e-4)) for b in blocks]
+    U = sum(O.tucker_full(c, q) for c, q, _, _ in parts)
+    T = O.tucker_full(core, Z)
+    assert abs(np.linalg.norm(U) - norm) <= 1e-10 * norm
+    assert np.linalg.norm(T - U) <= bound * (1 + 1e-9)
+    assert 0 < bound <= p.eps * norm * (1 + 1e-9)
+    r_ref = O.tucker_reference(p).ranks
+    assert all(core.shape[a] < 2 * r_ref[a] for a in range(3))
