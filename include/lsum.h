@@ -127,10 +127,14 @@ typedef struct {
                                  and reduces it by RHOSVD (Sec. 4); LSUM_SUM_TUCKER_REF (1) takes
                                  the rank-r Tucker form of the reference (RHOSVD of one charge on
                                  the doubled box at eps) and assembles its vectors over the lattice
-                                 (Thm thm:sumCaseE (B)), then orthonormalises them per mode: the
-                                 sum keeps the reference's ranks for every L (one block; a union
-                                 of blocks concatenates).  Needs eps > 0, FP64, no defects and
-                                 exact_sites = 0 (LSUM_E_INVALID otherwise)                     */
+                                 (Thm thm:sumCaseE (B)), then orthonormalises them per mode: one
+                                 block keeps the reference's ranks for every L; a union of blocks
+                                 (e.g. vacancy or impurity sub-lattices as blocks of charge -1 or
+                                 Z - 1) is reduced by the generalised RHOSVD of Thm
+                                 thm:TSum2Tucker at eps (lsum_info: norm_A = ||U|| of the sum,
+                                 bound = its certified truncation bound, 0 for one block).  Needs
+                                 eps > 0, FP64, no defects and exact_sites = 0 (LSUM_E_INVALID
+                                 otherwise)                                                     */
 } lsum_problem;
 
 /* ---- host-side steps (FP64 / integer, no device work) ----------------------------------- */
