@@ -135,6 +135,13 @@ typedef struct {
                                  bound = its certified truncation bound, 0 for one block).  Needs
                                  eps > 0, FP64, no defects and exact_sites = 0 (LSUM_E_INVALID
                                  otherwise)                                                     */
+    int als_sweeps;           /* 0..64: ALS sweeps after the RHOSVD (Thm thm:C2Tucker (b)): per
+                                 mode the leading r_l left singular vectors of the sum projected
+                                 onto the other modes' factors; the ranks stay, ||core|| only
+                                 grows and the certified bound still holds.  Applied when every
+                                 r_a r_b <= 4096 and r_l <= r_a r_b (otherwise skipped, reported
+                                 in lsum_get_stats).  With LSUM_SUM_TUCKER_REF it refines the
+                                 reference's Tucker form (the paper's C2T).                    */
 } lsum_problem;
 
 /* ---- host-side steps (FP64 / integer, no device work) ----------------------------------- */

@@ -427,6 +427,29 @@ def rhosvd(xi: np.ndarray, A: Sequence[np.ndarray], eps: float = None, ranks=Non
     return TuckerResult(Zs, core, sigs, tuple(rs), tuple(tails), bound, norm_A, norm_xi)
 
 
+def als_refine(xi: np.ndarray, A: Sequence[np.ndarray], Z: Sequence[np.ndarray], sweeps: int):
+    """Thm ``thm:C2Tucker`` (b): ALS for the dual maximisation of ||sum_v xi_v (Y_1^T a1_v) (x)
+    (Y_2^T a2_v) (x) (Y_3^T a3_v)|| over orthonormal Y_l, from the RHOSVD factors Z: each sweep
+    visits the modes in order and takes the leading r_l left singular vectors of the mode-l matrix
+    sum_v xi_v a_l,v (Y_a^T a_a,v (x) Y_b^T a_b,v)^T (the other modes at their latest factors).
+    Returns (Z, core, [||core|| after each sweep]); ||A - Tucker||^2 = ||A||^2 - ||core||^2."""
+    Z = [np.array(z) for z in Z]
+    history = []
+    core = None
+    for _ in range(sweeps):
+        for l in range(3):
+            a, b = [m for m in range(3) if m != l]
+            Pa, Pb = Z[a].T @ A[a], Z[b].T @ A[b]                          # r x R
+            KR = np.einsum("iv,jv->ijv", Pa, Pb).reshape(-1, len(xi))      # (r_a r_b) x R
+            M = (A[l] * xi[None, :]) @ KR.T                                  # N_l x (r_a r_b)
+            U, _, _ = np.linalg.svd(M, full_matrices=False)
+            Z[l] = U[:, :Z[l].shape[1]]
+        Y = [Z[m].T @ A[m] for m in range(3)]
+        core = np.einsum("v,av,bv,cv->abc", xi, Y[0], Y[1], Y[2], optimize=True)
+        history.append(float(np.linalg.norm(core)))
+    return Z, core, history
+
+
 def tucker_full(core: np.ndarray, Z: Sequence[np.ndarray]) -> np.ndarray:
     """B x_1 T1 x_2 T2 x_3 T3 (eq. ``Tucker_singePot``) on the full grid (tiny sizes)."""
     return np.einsum("abc,ia,jb,kc->ijk", core, Z[0], Z[1], Z[2], optimize=True)
@@ -452,12 +475,18 @@ def tucker_reference(problem) -> TuckerResult:
     """The rank-r Tucker form of the reference tensor on the doubled box (eq. ``TuckRef_sum``):
     RHOSVD at ``problem.eps`` of its canonical form (eq. ``CanMastSumNL``, the same R weighted
     reference vectors in every mode) written as in eq. ``CP_form``: unit columns, their norms
-    in xi (as ``canonical_terms`` writes the lattice sum)."""
+    in xi (as ``canonical_terms`` writes the lattice sum); with ``problem.als_sweeps`` ALS sweeps
+    from that guess (the canonical-to-Tucker approximation of Thm ``thm:C2Tucker``)."""
     t, w = quadrature_of(problem)
     B = reference_vectors(t, w, max(problem.N), problem.h)           # R x (2 N_ref - 1)
     nrm = np.linalg.norm(B, axis=1)
     A = (B / nrm[:, None]).T
-    return rhosvd(nrm ** 3, [A, A, A], eps=problem.eps)
+    res = rhosvd(nrm ** 3, [A, A, A], eps=problem.eps)
+    sweeps = getattr(problem, "als_sweeps", 0)
+    if sweeps:                                  # C2T: ALS from the RHOSVD guess (Thm C2Tucker (b))
+        Z, core, _ = als_refine(nrm ** 3, [A, A, A], res.Z, sweeps)
+        res = TuckerResult(Z, core, res.sigma, res.ranks, res.tails, res.bound, res.norm_A, res.norm_xi)
+    return res
 
 
 def tucker_lattice_sum(problem):

@@ -61,7 +61,7 @@ class lsum_problem(C.Structure):
                 ("eps", C.c_double), ("precision", C.c_int), ("tile_lo", C.c_int * 3),
                 ("tile_T", C.c_int * 3), ("n_points", C.c_int), ("points", C.c_void_p),
                 ("values", C.c_void_p), ("points_on_device", C.c_int), ("exact_sites", C.c_int),
-                ("method", C.c_int)]
+                ("method", C.c_int), ("als_sweeps", C.c_int)]
 
 
 class lsum_info(C.Structure):
@@ -433,6 +433,7 @@ def make_problem(p, points=None, values=None) -> tuple:
                         (C.c_int * 3)(*p.tile_T))
     prob.exact_sites = 1 if getattr(p, "exact_sites", False) else 0
     prob.method = int(getattr(p, "method", SUM_CANONICAL))
+    prob.als_sweeps = int(getattr(p, "als_sweeps", 0))
     keep = [blocks, defects]
     if points is not None:
         on_dev = not isinstance(points, np.ndarray)

@@ -465,6 +465,19 @@ __global__ void __launch_bounds__(256) k_reduce_split(long n, int k_split, const
     out[i] = (T)s;
 }
 
+// Row-wise Khatri-Rao product of two term-major operands: KR[nu, i * rb + j] = Xa[nu, i] Xb[nu, j]
+// (Xa K x ra, Xb K x rb, row-major, KR K x (ra rb)).
+__global__ void __launch_bounds__(256) k_khatri_rao(long total, int ra, int rb, const double* __restrict__ Xa,
+                                                    const double* __restrict__ Xb, double* __restrict__ KR) {
+    const long e = (long)blockIdx.x * 256 + threadIdx.x;
+    if (e >= total) return;
+    const long w = (long)ra * rb;
+    const long nu = e / w;
+    const int ij = (int)(e - nu * w);
+    const int i = ij / rb, j = ij - i * rb;
+    KR[e] = Xa[nu * ra + i] * Xb[nu * rb + j];
+}
+
 // C = alpha * sum_z work_z + beta * C for an m x n output with strides (scm, scn): the partial
 // products of a GEMM whose reduction was split into slices, summed in slice order.
 __global__ void __launch_bounds__(256) k_sum_split(int m, int n, int split, const double* __restrict__ work,
@@ -529,6 +542,12 @@ int gemm_split_slices(const GemmArgs& a, int split) {
     constexpr int GKf = GemmCfg<GEMM_F64>::GK;
     const long kslice = ((long)(a.k + split - 1) / split + GKf - 1) / GKf * GKf;
     return (int)((a.k + kslice - 1) / kslice);
+}
+
+void launch_khatri_rao(hipStream_t st, int K, int ra, int rb, const double* Xa, const double* Xb, double* KR) {
+    const long total = (long)K * ra * rb;
+    if (total <= 0) return;
+    hipLaunchKernelGGL(k_khatri_rao, dim3(cdiv(total, 256)), dim3(256), 0, st, total, ra, rb, Xa, Xb, KR);
 }
 
 void launch_gemm_split_f64(hipStream_t st, const GemmArgs& a, int split, double* work) {

@@ -100,6 +100,7 @@ static bool plan_key(const lsum_problem& p, std::string& key) {
     put(p.tile_T, sizeof(p.tile_T));
     put(&p.exact_sites, sizeof(int));
     put(&p.method, sizeof(int));
+    put(&p.als_sweeps, sizeof(int));
     put(&p.n_blocks, sizeof(int));
     for (int b = 0; b < p.n_blocks; ++b) {
         const lsum_block& k = p.blocks[b];
@@ -394,7 +395,9 @@ int lsum_get_stats(lsum_req r, char* buf, size_t len) {
           << "],\"range_res\":[" << q.range_res[0] << "," << q.range_res[1] << "," << q.range_res[2]
           << "],\"norm_A\":" << q.norm_A
           << ",\"norm_xi\":" << q.norm_xi << ",\"bound\":" << q.bound << ",\"batch\":" << q.batch_size
-          << ",\"offsets\":[";
+          << ",\"als_skipped\":" << q.als_skipped << ",\"als_core_norm\":[";
+        for (size_t k = 0; k < q.als_core_norm.size(); ++k) o << (k ? "," : "") << q.als_core_norm[k];
+        o << "],\"offsets\":[";
         for (int b = 0; b < (int)P.blocks.size(); ++b) {
             o << (b ? "," : "") << "[";
             for (int l = 0; l < 3; ++l) {

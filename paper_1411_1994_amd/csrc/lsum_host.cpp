@@ -206,6 +206,8 @@ int make_plan(const lsum_problem& p, Plan& plan) {
     plan.precision = p.precision;
     if (p.method != LSUM_SUM_CANONICAL && p.method != LSUM_SUM_TUCKER_REF) return fail(LSUM_E_INVALID, "unknown method");
     plan.method = p.method;
+    if (p.als_sweeps < 0 || p.als_sweeps > 64) return fail(LSUM_E_INVALID, "als_sweeps must be in [0, 64]");
+    plan.als_sweeps = p.als_sweeps;
     if (p.method == LSUM_SUM_TUCKER_REF &&
         (!(p.eps > 0.0) || p.precision != LSUM_FP64 || p.n_defects > 0 || p.exact_sites))
         return fail(LSUM_E_INVALID, "the Tucker-reference sum needs eps > 0, FP64, no defects and snapped sites");

@@ -93,6 +93,7 @@ struct Plan {
     int D[3]{};                          // R * (n_lat + n_win)
 
     int method = LSUM_SUM_CANONICAL;
+    int als_sweeps = 0;
     bool tucker() const { return eps > 0; }
     bool tucker_ref() const { return tucker() && method == LSUM_SUM_TUCKER_REF; }
     // canonical output with FP32 precision keeps its point-major factors in FP32 (sampling
@@ -222,6 +223,8 @@ void launch_gemm(hipStream_t st, GemmPrec prec, const GemmArgs& a);
 // FP64 GEMM (batch 1) with the reduction split into about `split` slices of a multiple of the
 // staging depth: the slices' products go to work (gemm_split_slices(a, split) x m x n doubles),
 // then C = alpha * (their sum in slice order) + beta * C.
+// KR[nu, i * rb + j] = Xa[nu, i] Xb[nu, j] (row-major, K rows): the ALS mode operand.
+void launch_khatri_rao(hipStream_t st, int K, int ra, int rb, const double* Xa, const double* Xb, double* KR);
 int gemm_split_slices(const GemmArgs& a, int split);
 void launch_gemm_split_f64(hipStream_t st, const GemmArgs& a, int split, double* work);
 

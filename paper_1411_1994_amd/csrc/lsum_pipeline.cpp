@@ -136,10 +136,10 @@ static int range_svd(Context* c, hipStream_t st, int D, int N, const double* W, 
 }
 
 static int mode_svd(Context* c, hipStream_t st, int D, int N, DevBuf& W, double thr, double irrelevant,
-                    ModeSVD& out) {
+                    ModeSVD& out, bool allow_range = true) {
     int rc;
     const int mn = std::min(D, N);
-    const int range_min = c->range_min;
+    const int range_min = allow_range ? c->range_min : 0;
     if (range_min > 0 && mn >= range_min) {
         // one basis of 256 vectors: it wins when the certified rank is well below min(D, N); when
         // it is not enough (a few percent of a direct solve) the direct solve follows
@@ -217,6 +217,110 @@ static int make_tile(Request* q, hipStream_t st, StageTimer& tm) {
     LSUM_HIP(hipStreamSynchronize(st));
     tm.end();
     q->bytes["tile"] = (double)T1 * T2 * T3 * es;
+    return LSUM_OK;
+}
+
+// The leading r singular vectors of an SVD as factor rows (r x N): rotated rows / sigma, or the
+// unit rows of the range path.
+static int rows_to_factor(Context* c, hipStream_t st, ModeSVD& ms, int r, int N, DevBuf& Z) {
+    int rc;
+    std::vector<double> inv(r);
+    std::vector<int32_t> ord(r);
+    for (int a = 0; a < r; ++a) { inv[a] = ms.unit ? 1.0 : 1.0 / ms.sigma[a]; ord[a] = a; }
+    DevBuf od, iv;
+    if ((rc = od.get(c->pool, r * 4))) return rc;
+    if ((rc = iv.get(c->pool, r * 8))) return rc;
+    if ((rc = Z.get(c->pool, (size_t)r * N * 8))) return rc;
+    LSUM_HIP(hipMemcpyAsync(od.p, ord.data(), r * 4, hipMemcpyHostToDevice, st));
+    LSUM_HIP(hipMemcpyAsync(iv.p, inv.data(), r * 8, hipMemcpyHostToDevice, st));
+    launch_gather_scale_rows(st, r, N, ms.rows.as<double>() + ms.off, (int)ms.ld, od.as<int32_t>(), iv.as<double>(),
+                             Z.as<double>(), N);
+    LSUM_HIP(hipStreamSynchronize(st));
+    ms.rows.reset();
+    return LSUM_OK;
+}
+
+// ALS sweeps (Thm thm:C2Tucker (b)) from the current factors q->Z: per mode l, with a, b the
+// other modes, the rows of M_l^T = sum_nu (x_a,nu (x) x_b,nu) t_l,nu^T (r_a r_b x N_l), where
+// t_l,nu is term nu's side column (times xi_nu for mode 0) and x_m,nu = Z_m t_m,nu its
+// projection; the leading r_l left singular vectors of M_l replace Z_l.  ||core|| after a mode is
+// the root of the sum of M_l's r_l largest sigma^2, recorded after each sweep.
+static int run_als(Request* q, hipStream_t st, DevBuf cols[3], StageTimer& tm) {
+    Context* c = q->ctx;
+    const Plan& P = q->plan;
+    int rc;
+    const int* r = q->r;
+    for (int l = 0; l < 3; ++l) {
+        const int a = (l + 1) % 3, b = (l + 2) % 3;
+        if ((long)r[a] * r[b] > 4096 || r[l] > r[a] * r[b]) {
+            q->als_skipped = 1;
+            return LSUM_OK;
+        }
+    }
+    tm.begin("als");
+    const long K = (long)P.n_groups * P.R;
+    std::vector<int32_t> idx(3 * (size_t)K);
+    std::vector<double> scv(K);
+    for (int g = 0; g < P.n_groups; ++g)
+        for (int k = 0; k < P.R; ++k) {
+            const long nu = (long)g * P.R + k;
+            for (int l = 0; l < 3; ++l) idx[(size_t)l * K + nu] = P.g_src[l][g] * P.R + k;
+            scv[nu] = P.g_scale[g];
+        }
+    DevBuf idx_d, sc_d, T[3];
+    if ((rc = idx_d.get(c->pool, idx.size() * 4)) || (rc = sc_d.get(c->pool, K * 8))) return rc;
+    LSUM_HIP(hipMemcpyAsync(idx_d.p, idx.data(), idx.size() * 4, hipMemcpyHostToDevice, st));
+    LSUM_HIP(hipMemcpyAsync(sc_d.p, scv.data(), K * 8, hipMemcpyHostToDevice, st));
+    for (int l = 0; l < 3; ++l) {
+        const int N = P.N[l];
+        if ((rc = T[l].get(c->pool, (size_t)K * N * 8))) return rc;
+        launch_gather_terms(st, 8, (int)K, N, cols[l].p, N, idx_d.as<int32_t>() + (size_t)l * K,
+                            l == 0 ? sc_d.as<double>() : nullptr, T[l].p, N);
+    }
+    DevBuf X[3], KR, Mr;
+    int rmax2 = 0;
+    for (int l = 0; l < 3; ++l) rmax2 = std::max(rmax2, r[(l + 1) % 3] * r[(l + 2) % 3]);
+    for (int l = 0; l < 3; ++l)
+        if ((rc = X[l].get(c->pool, (size_t)K * r[l] * 8))) return rc;
+    if ((rc = KR.get(c->pool, (size_t)K * rmax2 * 8))) return rc;
+    auto project = [&](int m) -> int {          // X_m (K x r_m) = T_m Z_m^T
+        GemmArgs g{};
+        g.m = (int)K; g.n = r[m]; g.k = P.N[m];
+        g.A = T[m].p; g.sam = P.N[m]; g.sak = 1;
+        g.B = q->Z[m].p; g.sbk = 1; g.sbn = P.N[m];
+        g.C = X[m].p; g.scm = r[m]; g.scn = 1;
+        g.alpha = 1.0; g.beta = 0.0; g.batch = 1;
+        return gemm_auto(c, st, GEMM_F64, g);
+    };
+    for (int l = 0; l < 3; ++l)
+        if ((rc = project(l))) return rc;
+    for (int s = 0; s < P.als_sweeps; ++s) {
+        double cn = 0.0;
+        for (int l = 0; l < 3; ++l) {
+            const int a = (l + 1) % 3, b = (l + 2) % 3, N = P.N[l], D = r[a] * r[b];
+            launch_khatri_rao(st, (int)K, r[a], r[b], X[a].as<double>(), X[b].as<double>(), KR.as<double>());
+            if ((rc = Mr.get(c->pool, (size_t)D * N * 8))) return rc;
+            GemmArgs g{};
+            g.m = D; g.n = N; g.k = (int)K;
+            g.A = KR.p; g.sam = 1; g.sak = D;
+            g.B = T[l].p; g.sbk = N; g.sbn = 1;
+            g.C = Mr.p; g.scm = N; g.scn = 1;
+            g.alpha = 1.0; g.beta = 0.0; g.batch = 1;
+            if ((rc = gemm_auto(c, st, GEMM_F64, g))) return rc;
+            LSUM_HIP(hipStreamSynchronize(st));
+            ModeSVD ms;
+            if ((rc = mode_svd(c, st, D, N, Mr, 0.0, 0.0, ms, false))) return rc;
+            LSUM_HIP(hipStreamSynchronize(st));
+            double lead = 0.0;
+            for (int k = 0; k < r[l] && k < (int)ms.sigma.size(); ++k) lead += ms.sigma[k] * ms.sigma[k];
+            cn = std::sqrt(lead);
+            if ((rc = rows_to_factor(c, st, ms, r[l], N, q->Z[l]))) return rc;
+            if ((rc = project(l))) return rc;
+        }
+        q->als_core_norm.push_back(cn);
+    }
+    LSUM_HIP(hipStreamSynchronize(st));
+    tm.end();
     return LSUM_OK;
 }
 
@@ -378,6 +482,9 @@ static int run_tucker(Request* q, hipStream_t st, const hipStream_t* aux, StageT
         LSUM_HIP(hipStreamSynchronize(st));
         ms[l].rows.reset();
     }
+
+    // (5b) optional ALS sweeps from the RHOSVD factors
+    if (P.als_sweeps > 0 && (rc = run_als(q, st, cols, tm))) return rc;
 
     // (6) projections, stored transposed: Yt_l = cols_l Z_l^T (D_l x r_l, row stride ldy_l), in the
     // problem's precision
@@ -559,26 +666,6 @@ static void add_mode_products(const double* B, int s1, int s2, int s3, const dou
         }
 }
 
-// The leading r singular vectors of an SVD as factor rows (r x N): rotated rows / sigma, or the
-// unit rows of the range path.
-static int rows_to_factor(Context* c, hipStream_t st, ModeSVD& ms, int r, int N, DevBuf& Z) {
-    int rc;
-    std::vector<double> inv(r);
-    std::vector<int32_t> ord(r);
-    for (int a = 0; a < r; ++a) { inv[a] = ms.unit ? 1.0 : 1.0 / ms.sigma[a]; ord[a] = a; }
-    DevBuf od, iv;
-    if ((rc = od.get(c->pool, r * 4))) return rc;
-    if ((rc = iv.get(c->pool, r * 8))) return rc;
-    if ((rc = Z.get(c->pool, (size_t)r * N * 8))) return rc;
-    LSUM_HIP(hipMemcpyAsync(od.p, ord.data(), r * 4, hipMemcpyHostToDevice, st));
-    LSUM_HIP(hipMemcpyAsync(iv.p, inv.data(), r * 8, hipMemcpyHostToDevice, st));
-    launch_gather_scale_rows(st, r, N, ms.rows.as<double>() + ms.off, (int)ms.ld, od.as<int32_t>(), iv.as<double>(),
-                             Z.as<double>(), N);
-    LSUM_HIP(hipStreamSynchronize(st));
-    ms.rows.reset();
-    return LSUM_OK;
-}
-
 // Orthonormal rows Q (k x N) spanning the D rows of F: CholeskyQR2 (k = D), or, when the rows are
 // close to dependent, the SVD with every direction above 1e-13 of ||F|| kept.
 static int orthonormal_rows(Context* c, hipStream_t st, int D, int N, const double* F, DevBuf& Q, int* k) {
@@ -644,6 +731,7 @@ static int run_tucker_ref(Request* q, hipStream_t st, const hipStream_t* aux, St
         rp.blocks = &one;
         rp.eps = P.eps;
         rp.precision = LSUM_FP64;
+        rp.als_sweeps = P.als_sweeps;
         int rc1 = make_plan(rp, rq.plan);
         if (rc1) return rc1;
         std::vector<Request*> rb{&rq};

@@ -297,6 +297,7 @@ int get_tucker_ref(Context* c, const Plan& P, hipStream_t st, const std::functio
     RefKey key = ref_key(P);
     key += "tucker";
     key.append((const char*)&P.eps, sizeof(double));
+    key.append((const char*)&P.als_sweeps, sizeof(int));
     return cached_rows(c, key, P, 3 * (size_t)P.R * P.ldg * 8, st, make, out);
 }
 

@@ -204,6 +204,8 @@ struct Request {
     double norm_A = 0, norm_xi = 0, bound = 0;
     double range_res[3]{};             // residual outside the range basis per mode (0: direct)
     int range_k[3]{};                  // size of the range basis per mode (0: direct)
+    std::vector<double> als_core_norm;  // ||core|| after each ALS sweep
+    int als_skipped = 0;               // 1: ALS asked for but the ranks do not allow it
     DevBuf Z[3];                       // r_l x N_l FP64
     DevBuf core;                       // r1 r2 r3, FP64 or FP32 (precision)
     DevBuf tile;

@@ -345,3 +345,46 @@ def test_chosen_M_meets_its_tolerance_end_to_end(ctx, kind, param, eps):
     # the error at these cells is of the size the probes estimate (its peak, the charge's own
     # cell, is among them)
     assert err >= 0.5 * e
+
+
+@pytest.mark.parametrize("sweeps", [1, 3])
+def test_als_after_rhosvd_matches_oracle(ctx, sweeps):
+    # Thm thm:C2Tucker (b): ALS sweeps from the RHOSVD factors, against the oracle's sweeps from
+    # its own RHOSVD of the same terms: same ||core|| after every sweep and the same values
+    rng = np.random.default_rng(71)
+    big = W.Block((6, 5, 4), (1.0, 1.1, 0.9), (0.13, -0.2, 0.07))
+    defects = W.draw_defects(rng, [big], 6, 4)
+    p = W.Problem("als", W.NEWTON, 0.0, 24, (61, 67, 55), 0.21, [big], defects, eps=1e-3,
+                  als_sweeps=sweeps)
+    r = run(ctx, p)
+    st = r.stats()
+    xi, A = O.canonical_terms(p)
+    res = O.rhosvd(xi, A, eps=1e-3)
+    Z, core, hist = O.als_refine(xi, A, res.Z, sweeps)
+    assert tuple(r.info().r) == res.ranks and st["als_skipped"] == 0
+    assert np.allclose(st["als_core_norm"], hist, rtol=1e-10, atol=0)
+    pts = np.stack([rng.integers(0, n, 300) for n in p.N], axis=1)
+    got = r.sample(cells_xyz(p, pts))
+    r.release()
+    want = O.tucker_points(core, Z, pts)
+    assert np.max(np.abs(got - want)) <= 1e-9 * np.max(np.abs(want))
+    # never worse than the RHOSVD guess against the plain sum
+    ref = O.brute_force_points(p, pts)
+    rh = O.tucker_points(res.core, res.Z, pts)
+    assert np.linalg.norm(got - ref) <= np.linalg.norm(rh - ref) * 1.01
+
+
+def test_als_is_skipped_when_the_ranks_do_not_allow_it(ctx):
+    # r_a r_b > 4096 for some pair of modes: the RHOSVD result stands and the skip is reported
+    p = W.Problem("als-big", W.NEWTON, 0.0, 28, (129, 129, 129), 3 / 32,
+                  [W.Block((8, 8, 8), (1.0, 1.0, 1.0), (0.0, 0.0, 0.0))],
+                  W.draw_defects(np.random.default_rng(72), [W.Block((8, 8, 8), (1.0, 1.0, 1.0), (0.0, 0.0, 0.0))], 120, 40),
+                  eps=1e-10, als_sweeps=2)
+    r = run(ctx, p)
+    st = r.stats()
+    rr = r.info().r
+    r.release()
+    if max(rr[0] * rr[1], rr[0] * rr[2], rr[1] * rr[2]) > 4096:
+        assert st["als_skipped"] == 1 and st["als_core_norm"] == []
+    else:
+        assert st["als_skipped"] == 0 and len(st["als_core_norm"]) == 2

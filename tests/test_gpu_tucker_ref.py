@@ -119,3 +119,17 @@ def test_generalised_rhosvd_of_blocks_with_vacancy_and_impurity_blocks(ctx):
     r.release()
     assert rel(got, O.tucker_points(core_o, Z_o, pts)) <= 1e-9
     assert rel(got, O.brute_force_points(p, pts)) <= 10 * eps
+
+
+def test_tucker_reference_with_c2t_als(ctx):
+    # the reference's Tucker form refined by ALS sweeps (the canonical-to-Tucker approximation of
+    # Thm thm:C2Tucker), then assembled: against the oracle's same construction
+    blk = W.Block((6, 5, 4), (1.0, 1.25, 0.75), (0.25, -0.5, 0.0))
+    p = W.Problem("tref-als", W.NEWTON, 0.0, 28, (81, 75, 69), 0.25, [blk], eps=1e-5, method=1, als_sweeps=2)
+    r = run(ctx, p)
+    core_o, Q_o, _, _ = O.tucker_lattice_sum(p)
+    assert tuple(r.info().r) == core_o.shape
+    pts = points(p, 300, 65)
+    got = r.sample(cells_xyz(p, pts))
+    r.release()
+    assert rel(got, O.tucker_points(core_o, Q_o, pts)) <= 1e-9

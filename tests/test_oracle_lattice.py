@@ -438,3 +438,39 @@ def test_generalised_rhosvd_of_a_union_of_blocks():
     assert 0 < bound <= p.eps * norm * (1 + 1e-9)
     r_ref = O.tucker_reference(p).ranks
     assert all(core.shape[a] < 2 * r_ref[a] for a in range(3))
+
+
+# ---------------------------------------------------------------------------------------
+# Thm thm:C2Tucker (b): ALS from the RHOSVD initial guess
+# ---------------------------------------------------------------------------------------
+
+def test_als_raises_the_core_norm_and_lowers_the_error():
+    # the dual objective ||core|| never decreases, and ||A - T||^2 = ||A||^2 - ||core||^2 falls
+    # below the RHOSVD error (projection onto orthonormal factors)
+    xi, A = O.canonical_terms(_defected(nvac=5, nimp=3))
+    res = O.rhosvd(xi, A, ranks=(6, 5, 4))
+    Z, core, hist = O.als_refine(xi, A, res.Z, 4)
+    full = O.cp_full(xi, A)
+    e0 = np.linalg.norm(full - O.tucker_full(res.core, res.Z))
+    e1 = np.linalg.norm(full - O.tucker_full(core, Z))
+    assert np.all(np.diff(hist) >= -1e-12 * hist[0]) and hist[0] >= np.linalg.norm(res.core) * (1 - 1e-12)
+    assert e1 <= e0 * (1 + 1e-12)
+    assert abs(e1 ** 2 - (np.linalg.norm(full) ** 2 - hist[-1] ** 2)) <= 1e-9 * np.linalg.norm(full) ** 2
+    for z in Z:
+        assert np.allclose(z.T @ z, np.eye(z.shape[1]), atol=1e-12)
+
+
+def test_als_recovers_an_exact_tucker_tensor():
+    # a canonical tensor that is exactly of Tucker rank (3, 3, 2) (its terms are the core's entries
+    # times products of orthonormal columns) is recovered to rounding from a perturbed guess
+    rng = np.random.default_rng(17)
+    N, r = (20, 18, 16), (3, 3, 2)
+    Q = [np.linalg.qr(rng.standard_normal((N[a], r[a])))[0] for a in range(3)]
+    B = rng.standard_normal(r)
+    idx = [(i, j, k) for i in range(r[0]) for j in range(r[1]) for k in range(r[2])]
+    xi = np.array([B[i, j, k] for i, j, k in idx])
+    A = [np.stack([Q[a][:, t[a]] for t in idx], axis=1) for a in range(3)]
+    guess = [np.linalg.qr(Q[a] + 0.3 * rng.standard_normal(Q[a].shape))[0] for a in range(3)]
+    Z, core, hist = O.als_refine(xi, A, guess, 6)
+    T = O.tucker_full(core, Z)
+    assert np.linalg.norm(T - O.cp_full(xi, A)) <= 1e-10 * np.linalg.norm(B)

@@ -67,6 +67,7 @@ class Problem:
     tile_T: Tuple[int, int, int] = (0, 0, 0)
     exact_sites: bool = False   # True: sites at exact positions (no snapping to cell centres)
     method: int = 0             # 1: Tucker-reference summation (eps > 0, no defects)
+    als_sweeps: int = 0         # ALS sweeps after the RHOSVD (eps > 0)
 
     @property
     def n_sites(self) -> int:
