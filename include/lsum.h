@@ -288,6 +288,17 @@ int lsum_get_info(lsum_req req, lsum_info* info);
  * (host, or device if on_device) and the weight of the block (its charge).  Factors kept in
  * FP32 (canonical output at FP32/BF16X3 precision) are returned widened to double. */
 int lsum_get_canonical(lsum_req req, int block, double* U0, double* U1, double* U2, int on_device);
+/* Canonical form of a finished Tucker result (the canonical -> Tucker -> canonical rank
+ * reduction of Sec. 4.3): each mode-3 slice of the core by its SVD, mu[:, :, k] = sum_i s_i
+ * u_i v_i^T, gives orthogonal rank-1 terms s_i (Z_1 u_i) (x) (Z_2 v_i) (x) z_3,k, so the rank is
+ * at most r_3 min(r_1, r_2); the smallest s are dropped while their (sum s^2)^(1/2) stays
+ * <= eps ||core||, which is then the Frobenius error (*err).  *R receives the rank; with xi ==
+ * NULL nothing else is written (a size query).  Otherwise xi (R weights, decreasing) and U_l
+ * (vector-major, R rows of N_l, unit rows; NULL skips a mode) are written to host memory, or
+ * device memory if on_device; cap < R is LSUM_E_INVALID.  Needs r_1, r_2 <= 128 (the slices are
+ * decomposed on the host).  Synchronous. */
+int lsum_tucker_to_canonical(lsum_req req, double eps, int cap, int* R, double* xi, double* U0,
+                             double* U1, double* U2, double* err, int on_device);
 /* Tucker factors Z_l (r_l rows of N[l]) and core (r1*r2*r3, last index fastest), FP64. */
 int lsum_get_tucker(lsum_req req, double* Z0, double* Z1, double* Z2, double* core, int on_device);
 /* Singular values of the three side matrices (D[l] each, descending). */

@@ -450,6 +450,33 @@ def als_refine(xi: np.ndarray, A: Sequence[np.ndarray], Z: Sequence[np.ndarray],
     return Z, core, history
 
 
+def tucker_to_canonical(core: np.ndarray, Z: Sequence[np.ndarray], eps: float):
+    """Can -> Tuck -> Can (the rank reduction of a defected canonical sum through its Tucker form,
+    Sec. 4.3): each mode-3 slice of the core by its SVD, mu[:, :, k] = sum_i s_i u_i v_i^T, gives
+    the rank-1 terms s_i (Z_1 u_i) (x) (Z_2 v_i) (x) z_3,k, so the canonical rank is at most
+    r_3 min(r_1, r_2).  With orthonormal Z_l these terms are mutually orthogonal: dropping the
+    smallest s (over all slices, ties by slice then index) while the dropped (sum s^2)^(1/2)
+    stays <= eps ||core|| bounds the Frobenius error by that.  Returns (xi, [A_1, A_2, A_3],
+    error), A_l (N_l x R) with unit columns, terms by decreasing s."""
+    terms = []
+    for k in range(core.shape[2]):
+        U, S, Vt = np.linalg.svd(core[:, :, k], full_matrices=False)
+        for i in range(len(S)):
+            terms.append((float(S[i]), k, i, U[:, i], Vt[i]))
+    terms.sort(key=lambda t: (-t[0], t[1], t[2]))
+    budget = (eps * float(np.linalg.norm(core))) ** 2
+    dropped = 0.0
+    keep = len(terms)
+    while keep > 1 and dropped + terms[keep - 1][0] ** 2 <= budget:
+        dropped += terms[keep - 1][0] ** 2
+        keep -= 1
+    kept = terms[:keep]
+    xi = np.array([t[0] for t in kept])
+    A = [np.stack([Z[0] @ t[3] for t in kept], axis=1), np.stack([Z[1] @ t[4] for t in kept], axis=1),
+         np.stack([Z[2][:, t[1]] for t in kept], axis=1)]
+    return xi, A, math.sqrt(dropped)
+
+
 def tucker_full(core: np.ndarray, Z: Sequence[np.ndarray]) -> np.ndarray:
     """B x_1 T1 x_2 T2 x_3 T3 (eq. ``Tucker_singePot``) on the full grid (tiny sizes)."""
     return np.einsum("abc,ia,jb,kc->ijk", core, Z[0], Z[1], Z[2], optimize=True)

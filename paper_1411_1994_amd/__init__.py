@@ -29,7 +29,7 @@ SYMBOLS = ["lsum_nodes", "lsum_block_offsets", "lsum_sinc_error", "lsum_choose_M
            "lsum_collocate", "lsum_shift_sum", "lsum_sample_canonical", "lsum_jacobi_svd",
            "lsum_contract",
            "lsum_submit", "lsum_submit_many", "lsum_wait", "lsum_cancel", "lsum_get_info", "lsum_get_canonical",
-           "lsum_get_tucker", "lsum_get_sigma", "lsum_sample", "lsum_get_tile", "lsum_get_stats",
+           "lsum_get_tucker", "lsum_tucker_to_canonical", "lsum_get_sigma", "lsum_sample", "lsum_get_tile", "lsum_get_stats",
            "lsum_release", "lsum_finish_many", "lsum_set_option", "lsum_get_profile", "lsum_reset_profile"]
 OPT_MAX_BATCH, OPT_REF_CACHE_BYTES, OPT_RANGE_MIN = 1, 2, 3
 
@@ -96,6 +96,7 @@ def _load():
         "lsum_shift_sum": (I, [VP, VP, I, VP, I, I, I, I, P(C.c_int32), VP, I]),
         "lsum_sample_canonical": (I, [VP, VP, I, I, VP, I, P(D), P(I), D, I, VP, VP]),
         "lsum_jacobi_svd": (I, [VP, VP, I, I, VP, I, D, D, I, P(D), P(I)]),
+        "lsum_tucker_to_canonical": (I, [VP, D, I, P(I), P(D), P(D), P(D), P(D), P(D), I]),
         "lsum_contract": (I, [VP, VP, I, I, I, I, VP, C.c_long, C.c_long, VP, C.c_long, C.c_long, VP,
                               C.c_long, C.c_long, D, D]),
         "lsum_submit": (I, [VP, P(lsum_problem), I, P(VP)]),
@@ -501,6 +502,20 @@ class Request:
         core = np.zeros(tuple(r))
         _check(_lib.lsum_get_tucker(self.handle, *[z.ctypes.data for z in Z], core.ctypes.data, 0))
         return Z, core
+
+    def tucker_to_canonical(self, eps: float):
+        """(xi, [U0, U1, U2], err): canonical form of the Tucker result (U_l vector-major, R x N_l)."""
+        R = C.c_int(0)
+        err = C.c_double(0.0)
+        _check(_lib.lsum_tucker_to_canonical(self.handle, eps, 0, C.byref(R), None, None, None, None,
+                                             C.byref(err), 0))
+        n = R.value
+        p = self.problem
+        xi = np.zeros(n)
+        U = [np.zeros((n, p.N[l])) for l in range(3)]
+        _check(_lib.lsum_tucker_to_canonical(self.handle, eps, n, C.byref(R), _dptr(xi), *[_dptr(u) for u in U],
+                                             C.byref(err), 0))
+        return xi, U, err.value
 
     def sigma(self):
         inf = self.info()

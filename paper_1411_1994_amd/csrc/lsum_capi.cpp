@@ -301,6 +301,100 @@ int lsum_get_canonical(lsum_req r, int block, double* U0, double* U1, double* U2
     return LSUM_OK;
 }
 
+int lsum_tucker_to_canonical(lsum_req r, double eps, int cap, int* R, double* xi, double* U0, double* U1,
+                             double* U2, double* err, int on_device) {
+    int rc = need_done(r);
+    if (rc) return rc;
+    if (!R || !err) return fail(LSUM_E_INVALID, "null argument");
+    if (!(eps >= 0.0)) return fail(LSUM_E_INVALID, "eps must be >= 0");
+    Request& q = r->q;
+    const Plan& P = q.plan;
+    if (!P.tucker()) return fail(LSUM_E_STATE, "request has no Tucker output");
+    const int r1 = q.r[0], r2 = q.r[1], r3 = q.r[2];
+    if (std::max(r1, r2) > 128) return fail(LSUM_E_INVALID, "core slices above 128 x 128");
+    Context& c = *q.ctx;
+    LSUM_HIP(hipSetDevice(c.device));
+    hipStream_t st = c.own_stream;
+    // the core on the host in FP64 (it is FP32 at FP32 / BF16X3 precision)
+    const size_t plane = (size_t)r1 * r2 * r3;
+    std::vector<double> mu(plane);
+    if (P.precision == LSUM_FP64) {
+        LSUM_HIP(hipMemcpy(mu.data(), q.core.p, plane * 8, hipMemcpyDeviceToHost));
+    } else {
+        std::vector<float> f(plane);
+        LSUM_HIP(hipMemcpy(f.data(), q.core.p, plane * 4, hipMemcpyDeviceToHost));
+        for (size_t k = 0; k < plane; ++k) mu[k] = f[k];
+    }
+    // per mode-3 slice its SVD: terms s u (x) v (x) e_k
+    struct Term {
+        double s;
+        int k, i;
+    };
+    std::vector<Term> terms;
+    std::vector<std::vector<double>> Us(r3), Vs(r3);
+    std::vector<double> slice((size_t)r1 * r2), S;
+    double mu2 = 0.0;
+    for (double v : mu) mu2 += v * v;
+    for (int k = 0; k < r3; ++k) {
+        for (int a = 0; a < r1; ++a)
+            for (int b = 0; b < r2; ++b) slice[(size_t)a * r2 + b] = mu[((size_t)a * r2 + b) * r3 + k];
+        lsum::small_svd(slice.data(), r1, r2, Us[k], S, Vs[k]);
+        for (int i = 0; i < (int)S.size(); ++i) terms.push_back(Term{S[i], k, i});
+    }
+    std::stable_sort(terms.begin(), terms.end(), [](const Term& x, const Term& y) {
+        if (x.s != y.s) return x.s > y.s;
+        return x.k != y.k ? x.k < y.k : x.i < y.i;
+    });
+    // drop the smallest while the dropped (sum s^2)^(1/2) stays <= eps ||core||
+    const double budget = eps * eps * mu2;
+    double dropped = 0.0;
+    size_t keep = terms.size();
+    while (keep > 1 && dropped + terms[keep - 1].s * terms[keep - 1].s <= budget) {
+        dropped += terms[keep - 1].s * terms[keep - 1].s;
+        --keep;
+    }
+    *R = (int)keep;
+    *err = std::sqrt(dropped);
+    if (!xi) return LSUM_OK;
+    if (cap < (int)keep) return fail(LSUM_E_INVALID, "output capacity below the canonical rank");
+    // factor rows: U_l (keep x N_l) = coefficients (keep x r_l) x Z_l (r_l x N_l), by MFMA GEMMs
+    std::vector<double> xs(keep), C[3];
+    C[0].assign(keep * (size_t)r1, 0.0);
+    C[1].assign(keep * (size_t)r2, 0.0);
+    C[2].assign(keep * (size_t)r3, 0.0);
+    for (size_t t = 0; t < keep; ++t) {
+        const Term& e = terms[t];
+        xs[t] = e.s;
+        for (int a = 0; a < r1; ++a) C[0][t * r1 + a] = Us[e.k][(size_t)e.i * r1 + a];
+        for (int b = 0; b < r2; ++b) C[1][t * r2 + b] = Vs[e.k][(size_t)e.i * r2 + b];
+        C[2][t * r3 + e.k] = 1.0;
+    }
+    double* dst[3] = {U0, U1, U2};
+    for (int l = 0; l < 3; ++l) {
+        if (!dst[l]) continue;
+        const int rl = q.r[l], N = P.N[l];
+        DevBuf Cd, Out;
+        if ((rc = Cd.get(c.pool, C[l].size() * 8)) || (rc = Out.get(c.pool, keep * (size_t)N * 8))) return rc;
+        LSUM_HIP(hipMemcpyAsync(Cd.p, C[l].data(), C[l].size() * 8, hipMemcpyHostToDevice, st));
+        GemmArgs a{};
+        a.m = (int)keep; a.n = N; a.k = rl;
+        a.A = Cd.p; a.sam = rl; a.sak = 1;
+        a.B = q.Z[l].p; a.sbk = N; a.sbn = 1;
+        a.C = Out.p; a.scm = N; a.scn = 1;
+        a.alpha = 1.0; a.beta = 0.0; a.batch = 1;
+        launch_gemm(st, GEMM_F64, a);
+        LSUM_HIP(hipGetLastError());
+        LSUM_HIP(hipStreamSynchronize(st));
+        if ((rc = copy_out(dst[l], Out.p, keep * (size_t)N * 8, on_device, c.device))) return rc;
+    }
+    if (on_device) {
+        LSUM_HIP(hipMemcpy(xi, xs.data(), keep * 8, hipMemcpyHostToDevice));
+    } else {
+        std::memcpy(xi, xs.data(), keep * 8);
+    }
+    return LSUM_OK;
+}
+
 int lsum_get_tucker(lsum_req r, double* Z0, double* Z1, double* Z2, double* core, int on_device) {
     int rc = need_done(r);
     if (rc) return rc;

@@ -120,6 +120,79 @@ void block_subcell(const lsum_block& blk, double h, std::vector<double> f[3]) {
     }
 }
 
+void small_svd(const double* M, int m, int n, std::vector<double>& Ul, std::vector<double>& S,
+               std::vector<double>& Vr) {
+    // one-sided Jacobi on the columns of A = M (m >= n) or A = M^T (m < n), column-major
+    const bool tr = m < n;
+    const int rows = tr ? n : m, cols = tr ? m : n;
+    std::vector<double> W((size_t)rows * cols), V((size_t)cols * cols, 0.0);
+    for (int j = 0; j < cols; ++j) {
+        V[(size_t)j * cols + j] = 1.0;
+        for (int i = 0; i < rows; ++i) W[(size_t)j * rows + i] = tr ? M[(size_t)j * n + i] : M[(size_t)i * n + j];
+    }
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        bool rotated = false;
+        for (int p = 0; p < cols; ++p)
+            for (int q = p + 1; q < cols; ++q) {
+                double* wp = &W[(size_t)p * rows];
+                double* wq = &W[(size_t)q * rows];
+                double alpha = 0.0, beta = 0.0, gamma = 0.0;
+                for (int i = 0; i < rows; ++i) {
+                    alpha += wp[i] * wp[i];
+                    beta += wq[i] * wq[i];
+                    gamma += wp[i] * wq[i];
+                }
+                if (!(std::fabs(gamma) > 1e-15 * std::sqrt(alpha * beta))) continue;
+                rotated = true;
+                const double zeta = (beta - alpha) / (2.0 * gamma);
+                const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (std::fabs(zeta) + std::sqrt(1.0 + zeta * zeta));
+                const double c = 1.0 / std::sqrt(1.0 + t * t), sn = c * t;
+                for (int i = 0; i < rows; ++i) {
+                    const double a = wp[i], b = wq[i];
+                    wp[i] = c * a - sn * b;
+                    wq[i] = sn * a + c * b;
+                }
+                double* vp = &V[(size_t)p * cols];
+                double* vq = &V[(size_t)q * cols];
+                for (int i = 0; i < cols; ++i) {
+                    const double a = vp[i], b = vq[i];
+                    vp[i] = c * a - sn * b;
+                    vq[i] = sn * a + c * b;
+                }
+            }
+        if (!rotated) break;
+    }
+    std::vector<double> nrm(cols);
+    std::vector<int> ord(cols);
+    for (int j = 0; j < cols; ++j) {
+        double a = 0.0;
+        for (int i = 0; i < rows; ++i) a += W[(size_t)j * rows + i] * W[(size_t)j * rows + i];
+        nrm[j] = std::sqrt(a);
+        ord[j] = j;
+    }
+    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return nrm[x] > nrm[y]; });
+    // A = U S V^T with U = W / S (rows x cols) and V (cols x cols); M = A or A^T
+    const int k = cols;
+    S.resize(k);
+    Ul.assign((size_t)m * k, 0.0);
+    Vr.assign((size_t)n * k, 0.0);
+    for (int e = 0; e < k; ++e) {
+        const int j = ord[e];
+        S[e] = nrm[j];
+        const double inv = nrm[j] > 0.0 ? 1.0 / nrm[j] : 0.0;
+        for (int i = 0; i < rows; ++i) {
+            const double u = W[(size_t)j * rows + i] * inv;
+            if (tr) Vr[(size_t)e * n + i] = u;
+            else Ul[(size_t)e * m + i] = u;
+        }
+        for (int i = 0; i < cols; ++i) {
+            const double v = V[(size_t)j * cols + i];
+            if (tr) Ul[(size_t)e * m + i] = v;
+            else Vr[(size_t)e * n + i] = v;
+        }
+    }
+}
+
 size_t Plan::planned_bytes() const {
     size_t b = 0;
     size_t sumN = (size_t)N[0] + N[1] + N[2];

@@ -42,6 +42,11 @@ int snap_coord(double x, double h, int N, int32_t* idx);
 int sinc_error_scan(const lsum_kernel& k, const int N[3], double h, double eps, int M_lo, int M_hi, int* M_out,
                     double* err_out);
 int block_offsets(const lsum_block& blk, const int N[3], double h, std::vector<int32_t> offs[3]);
+// SVD of a small dense m x n matrix M (row-major) by one-sided Jacobi rotations (host FP64):
+// M = sum_e S[e] u_e v_e^T, k = min(m, n) terms by decreasing S, u_e = Ul[e*m .. e*m+m),
+// v_e = Vr[e*n .. e*n+n).
+void small_svd(const double* M, int m, int n, std::vector<double>& Ul, std::vector<double>& S,
+               std::vector<double>& Vr);
 // Sub-cell offsets of a block's sites (exact sites): f = x/h - j for the snapped cell j.
 void block_subcell(const lsum_block& blk, double h, std::vector<double> f[3]);
 

@@ -388,3 +388,24 @@ def test_als_is_skipped_when_the_ranks_do_not_allow_it(ctx):
         assert st["als_skipped"] == 1 and st["als_core_norm"] == []
     else:
         assert st["als_skipped"] == 0 and len(st["als_core_norm"]) == 2
+
+
+@pytest.mark.parametrize("eps2", [0.0, 1e-4])
+def test_tucker_to_canonical_matches_oracle(ctx, eps2):
+    # Can -> Tuck -> Can: the canonical form of the device's Tucker result against the oracle's
+    # conversion of the same Tucker tensor (same rank and weights; values at points)
+    rng = np.random.default_rng(73)
+    big = W.Block((5, 4, 4), (1.0, 1.1, 0.9), (0.13, -0.2, 0.07))
+    p = W.Problem("c2t2c", W.NEWTON, 0.0, 24, (49, 45, 41), 0.25, [big], W.draw_defects(rng, [big], 5, 3),
+                  eps=1e-3)
+    r = run(ctx, p)
+    Z, core = r.tucker()
+    xi, U, err = r.tucker_to_canonical(eps2)
+    xo, Ao, erro = O.tucker_to_canonical(core, [z.T for z in Z], eps2)
+    assert len(xi) == len(xo) and abs(err - erro) <= 1e-9 * np.linalg.norm(core)
+    assert np.allclose(xi, xo, rtol=1e-9, atol=1e-12 * xo[0])
+    pts = np.stack([rng.integers(0, n, 200) for n in p.N], axis=1)
+    got = O.canonical_eval([u for u in U], pts, xi)
+    want = O.tucker_points(core, [z.T for z in Z], pts)
+    assert np.max(np.abs(got - want)) <= 1e-9 * np.max(np.abs(want)) + 2 * erro
+    r.release()

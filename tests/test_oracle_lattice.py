@@ -474,3 +474,27 @@ def test_als_recovers_an_exact_tucker_tensor():
     Z, core, hist = O.als_refine(xi, A, guess, 6)
     T = O.tucker_full(core, Z)
     assert np.linalg.norm(T - O.cp_full(xi, A)) <= 1e-10 * np.linalg.norm(B)
+
+
+# ---------------------------------------------------------------------------------------
+# Can -> Tuck -> Can
+# ---------------------------------------------------------------------------------------
+
+def test_tucker_to_canonical_exact_and_truncated():
+    xi0, A0 = O.canonical_terms(_defected(nvac=6, nimp=2))
+    res = O.rhosvd(xi0, A0, ranks=(8, 7, 5))
+    T = O.tucker_full(res.core, res.Z)
+    # eps = 0: the same tensor, rank <= r3 min(r1, r2), orthogonal rank-1 terms
+    xi, A, err = O.tucker_to_canonical(res.core, res.Z, 0.0)
+    assert len(xi) <= 5 * 7 and err == 0.0
+    C = O.cp_full(xi, A)
+    assert np.linalg.norm(C - T) <= 1e-12 * np.linalg.norm(T)
+    assert abs(np.sum(xi ** 2) - np.linalg.norm(T) ** 2) <= 1e-12 * np.linalg.norm(T) ** 2
+    for a in range(3):
+        assert np.allclose(np.linalg.norm(A[a], axis=0), 1.0, atol=1e-12)
+    # truncated: the error is the root of the dropped s^2 and at most eps ||core||
+    for eps in (1e-3, 1e-6):
+        xi2, A2, err2 = O.tucker_to_canonical(res.core, res.Z, eps)
+        e = np.linalg.norm(O.cp_full(xi2, A2) - T)
+        assert abs(e - err2) <= 1e-9 * np.linalg.norm(T) and err2 <= eps * np.linalg.norm(res.core)
+        assert len(xi2) < len(xi) if eps == 1e-3 else len(xi2) <= len(xi)
