@@ -81,6 +81,10 @@ typedef struct {
     double b[3];
     double center[3];
     double charge;   /* charge of every site; -1 describes a tensor sub-lattice of vacancies */
+    const double* x[3];   /* optional: the L[l] site coordinates of axis l (a non-equidistant
+                             tensor lattice, e.g. clusters on a coarse lattice, Sec. 5 case (D));
+                             NULL: (k - (L-1)/2) b[l] + center[l].  Read while the request is
+                             submitted (or by lsum_block_offsets); caller-owned              */
 } lsum_block;
 
 /* A change dZ of the charge at site `site` (indices 0..L-1 per axis) of block `block`:
@@ -152,6 +156,14 @@ typedef struct {
  * the rank R = number written.  Needs N and h only for the default (h_u, s). */
 int lsum_nodes(const lsum_kernel* k, const int N[3], double h, double* t, double* w, int cap,
                int* R);
+
+/* Parallelogram-type lattice (Sec. 5 case (B)): the sites of `base` with coordinate
+ * `shear_axis` moved by (k - (L-1)/2) * shear, k the site index along `along_axis` (the two axes
+ * differ).  Written as the base->L[along_axis] rectangular blocks of one site along that axis
+ * (out[0..*n), cap at least that many), whose sum the canonical route assembles with its
+ * shared axes once.  base->x[shear_axis] must be NULL.  Host only. */
+int lsum_shear_blocks(const lsum_block* base, int shear_axis, int along_axis, double shear, int cap,
+                      lsum_block* out, int* n);
 
 /* Snapped cell indices of a block's sites (windowing offsets of Sec. 3.1 eq. sub_tens for the
  * centred lattice of Sec. 3.2): offs[0..L0-1] axis 0, then L1 for axis 1, then L2 for axis 2.

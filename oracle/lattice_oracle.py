@@ -175,9 +175,45 @@ def site_coords(L: int, b: float, center: float) -> np.ndarray:
     return (k - (L - 1) / 2.0) * b + center
 
 
+def block_axis_coords(block, a: int) -> np.ndarray:
+    """The coordinates of the block's sites along axis a: its explicit list when it has one (a
+    non-equidistant tensor lattice, Sec. 5 case (D)), else the centred equidistant sites."""
+    coords = getattr(block, "coords", None)
+    if coords is not None and coords[a] is not None:
+        return np.asarray(coords[a], dtype=np.float64)
+    return site_coords(block.L[a], block.b[a], block.center[a])
+
+
 def block_offsets(block, h: float, N: Sequence[int]) -> List[np.ndarray]:
     """Per axis, the snapped cell indices of the block's sites."""
-    return [snap(site_coords(block.L[a], block.b[a], block.center[a]), h, N[a]) for a in range(3)]
+    return [snap(block_axis_coords(block, a), h, N[a]) for a in range(3)]
+
+
+def shear_sites(base, shear_axis: int, along_axis: int, shear: float) -> np.ndarray:
+    """All sites (C,3) of a parallelogram-type lattice (Sec. 5 case (B)): the sites of ``base``
+    with coordinate ``shear_axis`` moved by (k - (L-1)/2) shear, k the index along ``along_axis``."""
+    axes = [block_axis_coords(base, a) for a in range(3)]
+    idx = np.stack(np.meshgrid(*[np.arange(len(x)) for x in axes], indexing="ij"), axis=-1).reshape(-1, 3)
+    pos = np.stack([axes[a][idx[:, a]] for a in range(3)], axis=1)
+    half = (base.L[along_axis] - 1) / 2.0
+    pos[:, shear_axis] += (idx[:, along_axis] - half) * shear
+    return pos
+
+
+def brute_force_points_at(problem, pts: np.ndarray, pos: np.ndarray, Z: np.ndarray) -> np.ndarray:
+    """The plain sum of eq. ``EwaldSumE`` projected on the grid for an explicit list of charges:
+    each charge snapped to its cell (as for blocks), V[p] = sum_c Z_c sum_q w_q prod_l
+    b(t_q; (p_l - c_l) h)."""
+    t, w = quadrature_of(problem)
+    Nr = max(problem.N)
+    table = reference_vectors(t, w, Nr, problem.h, weighted=False)
+    cidx = np.stack([snap(pos[:, a], problem.h, problem.N[a]) for a in range(3)], axis=1)
+    out = np.empty(len(pts))
+    for n, p in enumerate(np.asarray(pts)):
+        prod = (table[:, p[0] - cidx[:, 0] + Nr - 1] * table[:, p[1] - cidx[:, 1] + Nr - 1]
+                * table[:, p[2] - cidx[:, 2] + Nr - 1])
+        out[n] = np.sum(Z * (w @ prod))
+    return out
 
 
 def charges(problem) -> Tuple[np.ndarray, np.ndarray]:
@@ -234,7 +270,7 @@ def charge_positions(problem) -> Tuple[np.ndarray, np.ndarray]:
     (the same order and defect changes as ``charges``)."""
     pos, Z = [], []
     for bi, blk in enumerate(problem.blocks):
-        axes = [site_coords(blk.L[a], blk.b[a], blk.center[a]) for a in range(3)]
+        axes = [block_axis_coords(blk, a) for a in range(3)]
         g = np.stack(np.meshgrid(*axes, indexing="ij"), axis=-1).reshape(-1, 3)
         z = np.full(g.shape[0], float(blk.charge))
         L = blk.L

@@ -25,7 +25,7 @@ FP64, FP32, BF16X3 = 0, 1, 2
 SUM_CANONICAL, SUM_TUCKER_REF = 0, 1
 
 # every symbol declared in include/lsum.h
-SYMBOLS = ["lsum_nodes", "lsum_block_offsets", "lsum_sinc_error", "lsum_choose_M", "lsum_create", "lsum_destroy", "lsum_last_error",
+SYMBOLS = ["lsum_nodes", "lsum_block_offsets", "lsum_shear_blocks", "lsum_sinc_error", "lsum_choose_M", "lsum_create", "lsum_destroy", "lsum_last_error",
            "lsum_collocate", "lsum_shift_sum", "lsum_sample_canonical", "lsum_jacobi_svd",
            "lsum_contract",
            "lsum_submit", "lsum_submit_many", "lsum_wait", "lsum_cancel", "lsum_get_info", "lsum_get_canonical",
@@ -47,7 +47,7 @@ class lsum_kernel(C.Structure):
 
 class lsum_block(C.Structure):
     _fields_ = [("L", C.c_int * 3), ("b", C.c_double * 3), ("center", C.c_double * 3),
-                ("charge", C.c_double)]
+                ("charge", C.c_double), ("x", C.c_void_p * 3)]
 
 
 class lsum_defect(C.Structure):
@@ -88,6 +88,7 @@ def _load():
         "lsum_nodes": (I, [P(lsum_kernel), P(I), D, P(D), P(D), I, P(I)]),
         "lsum_block_offsets": (I, [P(lsum_block), P(I), D, P(C.c_int32)]),
         "lsum_sinc_error": (I, [P(lsum_kernel), P(I), D, P(D)]),
+        "lsum_shear_blocks": (I, [P(lsum_block), I, I, D, I, P(lsum_block), P(I)]),
         "lsum_choose_M": (I, [P(lsum_kernel), P(I), D, D, I, P(I), P(D)]),
         "lsum_create": (I, [P(VP), I, C.c_size_t, I]),
         "lsum_destroy": (I, [VP]),
@@ -190,13 +191,48 @@ def lsum_choose_M(kind: int, param: float, N: Sequence[int], h: float, eps: floa
     return M.value, err.value
 
 
-def _block(b) -> lsum_block:
-    return lsum_block((C.c_int * 3)(*b.L), (C.c_double * 3)(*b.b), (C.c_double * 3)(*b.center),
-                      float(getattr(b, "charge", 1.0)))
+def _block(b, keep=None) -> lsum_block:
+    """The C block of a workloads.Block; explicit per-axis coordinates (``coords``) are passed by
+    pointer, and their arrays appended to ``keep`` so they outlive the call."""
+    st = lsum_block((C.c_int * 3)(*b.L), (C.c_double * 3)(*b.b), (C.c_double * 3)(*b.center),
+                    float(getattr(b, "charge", 1.0)))
+    coords = getattr(b, "coords", None)
+    if coords is not None:
+        for l in range(3):
+            if coords[l] is None:
+                continue
+            arr = np.ascontiguousarray(coords[l], dtype=np.float64)
+            if arr.shape != (b.L[l],):
+                raise ValueError("coords[l] must hold L[l] coordinates")
+            st.x[l] = arr.ctypes.data
+            if keep is None:
+                raise ValueError("explicit coordinates need a keep-alive list")
+            keep.append(arr)
+    return st
+
+
+def lsum_shear_blocks(base, shear_axis: int, along_axis: int, shear: float) -> list:
+    """A parallelogram-type lattice as rectangular blocks (``lsum_shear_blocks``): objects with the
+    fields of workloads.Block (L, b, center, charge, coords)."""
+    import types
+    keep = []
+    bst = _block(base, keep)
+    n = C.c_int(0)
+    _check(_lib.lsum_shear_blocks(C.byref(bst), shear_axis, along_axis, shear, 0, None, C.byref(n)))
+    out = (lsum_block * n.value)()
+    _check(_lib.lsum_shear_blocks(C.byref(bst), shear_axis, along_axis, shear, n.value, out, C.byref(n)))
+    base_coords = getattr(base, "coords", None) or (None, None, None)
+    res = []
+    for b in out:
+        coords = tuple(None if l == along_axis else base_coords[l] for l in range(3))
+        res.append(types.SimpleNamespace(L=tuple(b.L), b=tuple(b.b), center=tuple(b.center), charge=b.charge,
+                                         coords=coords if any(c is not None for c in coords) else None))
+    return res
 
 
 def lsum_block_offsets(block, N: Sequence[int], h: float):
-    blk = _block(block)
+    keep = []
+    blk = _block(block, keep)
     out = np.zeros(sum(block.L), dtype=np.int32)
     _check(_lib.lsum_block_offsets(C.byref(blk), (C.c_int * 3)(*N), h,
                                    out.ctypes.data_as(C.POINTER(C.c_int32))))
@@ -421,7 +457,8 @@ def prepare(problem) -> Prepared:
 def make_problem(p, points=None, values=None) -> tuple:
     """A C ``lsum_problem`` from any object with the fields of ``workloads.Problem``; returns
     (struct, keep-alive list)."""
-    blocks = (lsum_block * len(p.blocks))(*[_block(b) for b in p.blocks])
+    coord_keep = []
+    blocks = (lsum_block * len(p.blocks))(*[_block(b, coord_keep) for b in p.blocks])
     nd = len(p.defects)
     defects = (lsum_defect * max(nd, 1))(*[lsum_defect(d.block, (C.c_int * 3)(*d.site), float(d.dZ))
                                           for d in p.defects])
@@ -435,7 +472,7 @@ def make_problem(p, points=None, values=None) -> tuple:
     prob.exact_sites = 1 if getattr(p, "exact_sites", False) else 0
     prob.method = int(getattr(p, "method", SUM_CANONICAL))
     prob.als_sweeps = int(getattr(p, "als_sweeps", 0))
-    keep = [blocks, defects]
+    keep = [blocks, defects, coord_keep]
     if points is not None:
         on_dev = not isinstance(points, np.ndarray)
         prob.n_points = int(points.shape[0])

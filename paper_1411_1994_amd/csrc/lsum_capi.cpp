@@ -108,6 +108,11 @@ static bool plan_key(const lsum_problem& p, std::string& key) {
         put(k.b, sizeof(k.b));
         put(k.center, sizeof(k.center));
         put(&k.charge, sizeof(double));
+        for (int l = 0; l < 3; ++l) {
+            const char f = k.x[l] ? 1 : 0;
+            put(&f, 1);
+            if (k.x[l]) put(k.x[l], (size_t)std::max(0, k.L[l]) * sizeof(double));
+        }
     }
     put(&p.n_defects, sizeof(int));
     for (int d = 0; d < p.n_defects; ++d) {

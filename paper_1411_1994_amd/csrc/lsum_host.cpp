@@ -92,13 +92,19 @@ int snap_coord(double x, double h, int N, int32_t* idx) {
     return LSUM_OK;
 }
 
+double site_x(const lsum_block& blk, int l, int k) {
+    if (blk.x[l]) return blk.x[l][k];
+    double half = (double)(blk.L[l] - 1) / 2.0;
+    return ((double)k - half) * blk.b[l] + blk.center[l];
+}
+
 int block_offsets(const lsum_block& blk, const int N[3], double h, std::vector<int32_t> offs[3]) {
     for (int l = 0; l < 3; ++l) {
         if (blk.L[l] < 1) return fail(LSUM_E_INVALID, "block with L < 1");
         offs[l].resize(blk.L[l]);
-        double half = (double)(blk.L[l] - 1) / 2.0;
         for (int k = 0; k < blk.L[l]; ++k) {
-            double x = ((double)k - half) * blk.b[l] + blk.center[l];
+            double x = site_x(blk, l, k);
+            if (!std::isfinite(x)) return fail(LSUM_E_INVALID, "site coordinate is not finite");
             int rc = snap_coord(x, h, N[l], &offs[l][k]);
             if (rc != LSUM_OK) return fail(rc, "lattice site outside the grid");
         }
@@ -109,9 +115,8 @@ int block_offsets(const lsum_block& blk, const int N[3], double h, std::vector<i
 void block_subcell(const lsum_block& blk, double h, std::vector<double> f[3]) {
     for (int l = 0; l < 3; ++l) {
         f[l].resize(blk.L[l]);
-        double half = (double)(blk.L[l] - 1) / 2.0;
         for (int k = 0; k < blk.L[l]; ++k) {
-            double x = ((double)k - half) * blk.b[l] + blk.center[l];
+            double x = site_x(blk, l, k);
             double u = x / h;
             double j = std::floor(std::fabs(u) + 0.5);
             if (u < 0.0) j = -j;
@@ -285,6 +290,8 @@ int make_plan(const lsum_problem& p, Plan& plan) {
         (!(p.eps > 0.0) || p.precision != LSUM_FP64 || p.n_defects > 0 || p.exact_sites))
         return fail(LSUM_E_INVALID, "the Tucker-reference sum needs eps > 0, FP64, no defects and snapped sites");
     plan.blocks.assign(p.blocks, p.blocks + p.n_blocks);
+    for (auto& b : plan.blocks)   // explicit coordinates are read below, while the caller's arrays live
+        for (int l = 0; l < 3; ++l) b.x[l] = nullptr;
     plan.defects.assign(p.defects, p.defects + p.n_defects);
     if (plan.has_tile()) {
         if (!plan.tucker()) return fail(LSUM_E_INVALID, "a tile needs eps > 0 (Tucker output)");
@@ -443,6 +450,30 @@ int lsum_nodes(const lsum_kernel* k, const int N[3], double h, double* t, double
     std::memcpy(t, tt.data(), tt.size() * sizeof(double));
     std::memcpy(w, ww.data(), ww.size() * sizeof(double));
     *R = (int)tt.size();
+    return LSUM_OK;
+}
+
+int lsum_shear_blocks(const lsum_block* base, int shear_axis, int along_axis, double shear, int cap,
+                      lsum_block* out, int* n) {
+    if (!base || !n) return lsum::fail(LSUM_E_INVALID, "null argument");
+    if (shear_axis < 0 || shear_axis > 2 || along_axis < 0 || along_axis > 2 || shear_axis == along_axis)
+        return lsum::fail(LSUM_E_INVALID, "the shear and along axes must be two different axes");
+    if (base->x[shear_axis]) return lsum::fail(LSUM_E_INVALID, "explicit coordinates on the sheared axis");
+    if (!std::isfinite(shear)) return lsum::fail(LSUM_E_INVALID, "shear is not finite");
+    const int La = base->L[along_axis];
+    if (La < 1) return lsum::fail(LSUM_E_INVALID, "block with L < 1");
+    *n = La;
+    if (!out) return LSUM_OK;
+    if (cap < La) return lsum::fail(LSUM_E_INVALID, "output capacity below the number of blocks");
+    const double half = (double)(La - 1) / 2.0;
+    for (int k = 0; k < La; ++k) {
+        lsum_block b = *base;
+        b.L[along_axis] = 1;
+        b.center[along_axis] = lsum::site_x(*base, along_axis, k);
+        b.x[along_axis] = nullptr;
+        b.center[shear_axis] = base->center[shear_axis] + ((double)k - half) * shear;
+        out[k] = b;
+    }
     return LSUM_OK;
 }
 

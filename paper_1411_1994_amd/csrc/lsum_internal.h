@@ -41,6 +41,8 @@ int snap_coord(double x, double h, int N, int32_t* idx);
 // lsum_sinc_error.cpp); LSUM_E_NOCONV with the best M when none (eps < 0: always LSUM_OK).
 int sinc_error_scan(const lsum_kernel& k, const int N[3], double h, double eps, int M_lo, int M_hi, int* M_out,
                     double* err_out);
+// Coordinate of site k of axis l: the block's explicit list, or (k - (L-1)/2) b + center.
+double site_x(const lsum_block& blk, int l, int k);
 int block_offsets(const lsum_block& blk, const int N[3], double h, std::vector<int32_t> offs[3]);
 // SVD of a small dense m x n matrix M (row-major) by one-sided Jacobi rotations (host FP64):
 // M = sum_e S[e] u_e v_e^T, k = min(m, n) terms by decreasing S, u_e = Ul[e*m .. e*m+m),

@@ -191,3 +191,48 @@ def test_choose_M_errors():
     with pytest.raises(L.LsumError) as e:
         L.lsum_sinc_error(W.SLATER, 0.0, 10, N, h)
     assert e.value.code == -1
+
+
+# ---------------------------------------------------------------------------------------
+# lattice classes beyond one rectangular block (Sec. 5 cases (B) and (D))
+# ---------------------------------------------------------------------------------------
+
+def test_shear_blocks_enumerate_the_parallelogram_sites():
+    import paper_1411_1994_amd as L
+    base = W.Block((6, 5, 4), (1.0, 0.8, 1.2), (0.3, -0.1, 0.2))
+    for shear_axis, along_axis, shear in [(0, 1, 0.5), (2, 0, -0.35), (1, 2, 0.0)]:
+        blocks = L.lsum_shear_blocks(base, shear_axis, along_axis, shear)
+        assert len(blocks) == base.L[along_axis]
+        got = np.concatenate([O.charge_positions(W.Problem("s", 0, 0.0, 8, (5, 5, 5), 1.0, [b]))[0] for b in blocks])
+        want = O.shear_sites(base, shear_axis, along_axis, shear)
+        key = lambda a: a[np.lexsort(np.round(a, 9).T[::-1])]
+        assert np.allclose(key(got), key(want), atol=1e-12, rtol=0)
+    with pytest.raises(L.LsumError):
+        L.lsum_shear_blocks(base, 1, 1, 0.5)
+
+
+def test_explicit_coordinates_match_equidistant_sites_bit_for_bit():
+    import paper_1411_1994_amd as L
+    blk = W.Block((7, 4, 5), (0.9, 1.3, 0.7), (0.21, -0.4, 0.05))
+    coords = tuple(O.site_coords(blk.L[a], blk.b[a], blk.center[a]) for a in range(3))
+    ex = W.Block(blk.L, blk.b, blk.center, coords=coords)
+    N, h = (61, 61, 61), 0.17
+    a = L.lsum_block_offsets(blk, N, h)
+    b = L.lsum_block_offsets(ex, N, h)
+    o = O.block_offsets(ex, h, N)
+    for k in range(3):
+        assert np.array_equal(a[k], b[k]) and np.array_equal(b[k], o[k])
+
+
+def test_cluster_lattice_is_one_non_equidistant_block():
+    # clusters of 2 x 2 x 1 sites on a 3 x 3 x 2 coarse lattice (case (D)): the per-axis sets
+    # {coarse + fine} give one tensor block whose sites are exactly the union of the clusters
+    coarse = [np.array([-4.0, 0.0, 4.0]), np.array([-3.0, 1.0, 5.0]), np.array([-1.0, 2.0])]
+    fine = [np.array([0.0, 1.0]), np.array([0.0, 1.0]), np.array([0.0])]
+    coords = tuple(np.sort((c[:, None] + f[None, :]).ravel()) for c, f in zip(coarse, fine))
+    blk = W.Block(tuple(len(x) for x in coords), (1.0, 1.0, 1.0), (0.0, 0.0, 0.0), charge=-1.0, coords=coords)
+    pos, Z = O.charge_positions(W.Problem("c", 0, 0.0, 8, (5, 5, 5), 1.0, [blk]))
+    union = np.array([[c0 + f0, c1 + f1, c2 + f2] for c0 in coarse[0] for c1 in coarse[1] for c2 in coarse[2]
+                      for f0 in fine[0] for f1 in fine[1] for f2 in fine[2]])
+    key = lambda a: a[np.lexsort(a.T[::-1])]
+    assert np.array_equal(key(pos), key(union)) and np.all(Z == -1.0)

@@ -409,3 +409,47 @@ def test_tucker_to_canonical_matches_oracle(ctx, eps2):
     want = O.tucker_points(core, [z.T for z in Z], pts)
     assert np.max(np.abs(got - want)) <= 1e-9 * np.max(np.abs(want)) + 2 * erro
     r.release()
+
+
+@pytest.mark.parametrize("eps", [0.0, 1e-6])
+def test_parallelogram_lattice(ctx, eps):
+    # case (B): x moves by 0.45 per step along y; the library's block decomposition, summed on the
+    # canonical route (and reduced by RHOSVD), against the plain sum over the sheared sites
+    import paper_1411_1994_amd as L
+    base = W.Block((6, 5, 4), (1.0, 1.0, 1.0), (0.0, 0.0, 0.0))
+    blocks = [W.Block(b.L, b.b, b.center, b.charge) for b in L.lsum_shear_blocks(base, 0, 1, 0.45)]
+    p = W.Problem("shear", W.NEWTON, 0.0, 28, (81, 65, 57), 0.25, blocks, eps=eps)
+    r = run(ctx, p)
+    rng = np.random.default_rng(81)
+    pts = np.stack([rng.integers(0, n, 300) for n in p.N], axis=1)
+    got = r.sample(cells_xyz(p, pts))
+    inf = r.info()
+    r.release()
+    pos = O.shear_sites(base, 0, 1, 0.45)
+    ref = O.brute_force_points_at(p, pts, pos, np.ones(len(pos)))
+    tol = 1e-12 if eps == 0.0 else 10 * eps
+    assert np.max(np.abs(got - ref)) <= tol * np.max(np.abs(ref))
+    # axis 2 is the same in every sub-block: one lattice source there, one per sub-block on axis 1
+    if eps > 0:
+        assert inf.D[2] == inf.R and inf.D[1] == inf.R * base.L[1]
+
+
+def test_vacancy_clusters_as_one_non_equidistant_block(ctx):
+    # case (D): vacancy clusters of 2 x 2 x 2 sites on a 3 x 3 x 2 coarse lattice inside an
+    # 8 x 8 x 6 lattice, as one block of charge -1 with explicit coordinates
+    lat = W.Block((8, 8, 6), (1.0, 1.0, 1.0), (0.0, 0.0, 0.0))
+    sites = [O.site_coords(lat.L[a], 1.0, 0.0) for a in range(3)]
+    pick = [np.array([0, 1, 3, 4, 6, 7]), np.array([1, 2, 4, 5, 6, 7]), np.array([0, 1, 3, 4])]
+    coords = tuple(sites[a][pick[a]] for a in range(3))
+    vac = W.Block(tuple(len(c) for c in coords), (1.0, 1.0, 1.0), (0.0, 0.0, 0.0), charge=-1.0, coords=coords)
+    for eps in (0.0, 1e-6):
+        p = W.Problem("clusters", W.NEWTON, 0.0, 28, (65, 65, 57), 0.25, [lat, vac], eps=eps)
+        r = run(ctx, p)
+        rng = np.random.default_rng(82)
+        pts = np.stack([rng.integers(0, n, 300) for n in p.N], axis=1)
+        got = r.sample(cells_xyz(p, pts))
+        r.release()
+        pos, Z = O.charge_positions(p)
+        ref = O.brute_force_points_at(p, pts, pos, Z)
+        tol = 1e-12 if eps == 0.0 else 10 * eps
+        assert np.max(np.abs(got - ref)) <= tol * np.max(np.abs(ref))

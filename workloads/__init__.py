@@ -40,6 +40,7 @@ class Block:
     b: Tuple[float, float, float]
     center: Tuple[float, float, float]
     charge: float = 1.0         # charge of every site (-1: a sub-lattice of vacancies)
+    coords: Optional[Tuple] = None   # optional explicit site coordinates per axis (None: b, center)
 
 
 @dataclass
