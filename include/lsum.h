@@ -300,6 +300,15 @@ int lsum_get_info(lsum_req req, lsum_info* info);
  * (host, or device if on_device) and the weight of the block (its charge).  Factors kept in
  * FP32 (canonical output at FP32/BF16X3 precision) are returned widened to double. */
 int lsum_get_canonical(lsum_req req, int block, double* U0, double* U1, double* U2, int on_device);
+/* Galerkin matrix of a finished Tucker result in a separable basis (eq. nuc_pot): basis function
+ * k is g_k(x) = g_k^(1)(x_1) g_k^(2)(x_2) g_k^(3)(x_3), given by its values at the cell centres,
+ * G_l (nb x N_l, row k = g_k^(l), row-major).  V[k * nb + m] = h^3 sum_i T_i g_k(x_i) g_m(x_i),
+ * the midpoint rule for the integral of v g_k g_m, computed from 1D Hadamard products and the
+ * Tucker factors and core (MFMA products).  nb <= 255; G and V in host memory, or device memory
+ * if on_device.  Synchronous. */
+int lsum_galerkin(lsum_req req, int nb, const double* G0, const double* G1, const double* G2,
+                  double* V, int on_device);
+
 /* Canonical form of a finished Tucker result (the canonical -> Tucker -> canonical rank
  * reduction of Sec. 4.3): each mode-3 slice of the core by its SVD, mu[:, :, k] = sum_i s_i
  * u_i v_i^T, gives orthogonal rank-1 terms s_i (Z_1 u_i) (x) (Z_2 v_i) (x) z_3,k, so the rank is

@@ -600,6 +600,23 @@ def tucker_lattice_sum(problem):
 
 
 # ---------------------------------------------------------------------------------------
+# eq. ``nuc_pot``: the Galerkin matrix of the summed potential in a separable basis
+# ---------------------------------------------------------------------------------------
+
+def galerkin_matrix(T: np.ndarray, G: Sequence[np.ndarray], h: float) -> np.ndarray:
+    """V[k, m] = h^3 sum_i T_i g_k(x_i) g_m(x_i) over every cell i of the full tensor T, with the
+    separable basis functions given by their per-axis values at the cell centres, G[l]
+    (nb x N_l): eq. ``nuc_pot`` read as the midpoint rule for the integral of v g_k g_m."""
+    nb = G[0].shape[0]
+    V = np.zeros((nb, nb))
+    for k in range(nb):
+        for m in range(nb):
+            gkm = np.einsum("i,j,k->ijk", G[0][k] * G[0][m], G[1][k] * G[1][m], G[2][k] * G[2][m])
+            V[k, m] = h ** 3 * float(np.sum(T * gkm))
+    return V
+
+
+# ---------------------------------------------------------------------------------------
 # O3: the exact Galerkin entry (no sinc quadrature), by adaptive Gauss-Kronrod
 # ---------------------------------------------------------------------------------------
 

@@ -29,7 +29,7 @@ SYMBOLS = ["lsum_nodes", "lsum_block_offsets", "lsum_shear_blocks", "lsum_sinc_e
            "lsum_collocate", "lsum_shift_sum", "lsum_sample_canonical", "lsum_jacobi_svd",
            "lsum_contract",
            "lsum_submit", "lsum_submit_many", "lsum_wait", "lsum_cancel", "lsum_get_info", "lsum_get_canonical",
-           "lsum_get_tucker", "lsum_tucker_to_canonical", "lsum_get_sigma", "lsum_sample", "lsum_get_tile", "lsum_get_stats",
+           "lsum_get_tucker", "lsum_tucker_to_canonical", "lsum_galerkin", "lsum_get_sigma", "lsum_sample", "lsum_get_tile", "lsum_get_stats",
            "lsum_release", "lsum_finish_many", "lsum_set_option", "lsum_get_profile", "lsum_reset_profile"]
 OPT_MAX_BATCH, OPT_REF_CACHE_BYTES, OPT_RANGE_MIN = 1, 2, 3
 
@@ -97,6 +97,7 @@ def _load():
         "lsum_shift_sum": (I, [VP, VP, I, VP, I, I, I, I, P(C.c_int32), VP, I]),
         "lsum_sample_canonical": (I, [VP, VP, I, I, VP, I, P(D), P(I), D, I, VP, VP]),
         "lsum_jacobi_svd": (I, [VP, VP, I, I, VP, I, D, D, I, P(D), P(I)]),
+        "lsum_galerkin": (I, [VP, I, VP, VP, VP, VP, I]),
         "lsum_tucker_to_canonical": (I, [VP, D, I, P(I), P(D), P(D), P(D), P(D), P(D), I]),
         "lsum_contract": (I, [VP, VP, I, I, I, I, VP, C.c_long, C.c_long, VP, C.c_long, C.c_long, VP,
                               C.c_long, C.c_long, D, D]),
@@ -539,6 +540,16 @@ class Request:
         core = np.zeros(tuple(r))
         _check(_lib.lsum_get_tucker(self.handle, *[z.ctypes.data for z in Z], core.ctypes.data, 0))
         return Z, core
+
+    def galerkin(self, G):
+        """V (nb x nb): the Galerkin matrix of the Tucker result in the separable basis whose
+        per-axis values at the cell centres are G[l] (nb x N_l)."""
+        G = [np.ascontiguousarray(g, dtype=np.float64) for g in G]
+        nb = G[0].shape[0]
+        V = np.zeros((nb, nb))
+        _check(_lib.lsum_galerkin(self.handle, nb, G[0].ctypes.data, G[1].ctypes.data, G[2].ctypes.data,
+                                  V.ctypes.data, 0))
+        return V
 
     def tucker_to_canonical(self, eps: float):
         """(xi, [U0, U1, U2], err): canonical form of the Tucker result (U_l vector-major, R x N_l)."""

@@ -478,6 +478,36 @@ __global__ void __launch_bounds__(256) k_khatri_rao(long total, int ra, int rb, 
     KR[e] = Xa[nu * ra + i] * Xb[nu * rb + j];
 }
 
+// Galerkin functional (eq. nuc_pot): H[k * nb + m, x] = G[k, x] G[m, x], the 1D Hadamard products
+// of every pair of basis vectors of one mode (G nb x n, row-major).
+__global__ void __launch_bounds__(256) k_hadamard_pairs(int nb, int n, const double* __restrict__ G,
+                                                        double* __restrict__ H) {
+    const int x = blockIdx.x * 256 + threadIdx.x;
+    const int pr = blockIdx.y;
+    if (x >= n) return;
+    const int k = pr / nb, m = pr - k * nb;
+    H[(long)pr * n + x] = G[(long)k * n + x] * G[(long)m * n + x];
+}
+
+// v[p] = scale * sum_{a,b} X[p, a r2 + b] Y1[p, a] Y2[p, b]: the last two mode contractions of the
+// Tucker core with the pairs' projections; one wavefront per pair, fixed summation order.
+__global__ void __launch_bounds__(256) k_galerkin_finish(int P, int r1, int r2, const double* __restrict__ X,
+                                                         const double* __restrict__ Y1,
+                                                         const double* __restrict__ Y2, double scale,
+                                                         double* __restrict__ v) {
+    const int p = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (p >= P) return;
+    const double* x = X + (long)p * r1 * r2;
+    double acc = 0.0;
+    for (int e = lane; e < r1 * r2; e += 64) {
+        const int a = e / r2, b = e - a * r2;
+        acc += x[e] * Y1[(long)p * r1 + a] * Y2[(long)p * r2 + b];
+    }
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if (lane == 0) v[p] = scale * acc;
+}
+
 // C = alpha * sum_z work_z + beta * C for an m x n output with strides (scm, scn): the partial
 // products of a GEMM whose reduction was split into slices, summed in slice order.
 __global__ void __launch_bounds__(256) k_sum_split(int m, int n, int split, const double* __restrict__ work,
@@ -548,6 +578,17 @@ void launch_khatri_rao(hipStream_t st, int K, int ra, int rb, const double* Xa, 
     const long total = (long)K * ra * rb;
     if (total <= 0) return;
     hipLaunchKernelGGL(k_khatri_rao, dim3(cdiv(total, 256)), dim3(256), 0, st, total, ra, rb, Xa, Xb, KR);
+}
+
+void launch_hadamard_pairs(hipStream_t st, int nb, int n, const double* G, double* H) {
+    if (nb <= 0 || n <= 0) return;
+    hipLaunchKernelGGL(k_hadamard_pairs, dim3(cdiv(n, 256), (unsigned)nb * nb), dim3(256), 0, st, nb, n, G, H);
+}
+
+void launch_galerkin_finish(hipStream_t st, int P, int r1, int r2, const double* X, const double* Y1,
+                            const double* Y2, double scale, double* v) {
+    if (P <= 0) return;
+    hipLaunchKernelGGL(k_galerkin_finish, dim3(cdiv(P, 4)), dim3(256), 0, st, P, r1, r2, X, Y1, Y2, scale, v);
 }
 
 void launch_gemm_split_f64(hipStream_t st, const GemmArgs& a, int split, double* work) {

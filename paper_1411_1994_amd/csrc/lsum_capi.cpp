@@ -400,6 +400,73 @@ int lsum_tucker_to_canonical(lsum_req r, double eps, int cap, int* R, double* xi
     return LSUM_OK;
 }
 
+int lsum_galerkin(lsum_req r, int nb, const double* G0, const double* G1, const double* G2, double* V,
+                  int on_device) {
+    int rc = need_done(r);
+    if (rc) return rc;
+    if (!G0 || !G1 || !G2 || !V) return fail(LSUM_E_INVALID, "null argument");
+    if (nb < 1 || nb > 255) return fail(LSUM_E_INVALID, "nb must be in [1, 255]");
+    Request& q = r->q;
+    const Plan& P = q.plan;
+    if (!P.tucker()) return fail(LSUM_E_STATE, "the Galerkin functional needs a Tucker result");
+    Context& c = *q.ctx;
+    LSUM_HIP(hipSetDevice(c.device));
+    hipStream_t st = c.own_stream;
+    const int r1 = q.r[0], r2 = q.r[1], r3 = q.r[2];
+    const long Pn = (long)nb * nb;
+    const double* G[3] = {G0, G1, G2};
+    DevBuf Gd[3], H, Y[3], X, mu, v;
+    // per mode: the pairs' Hadamard rows and their projections Y_l = H_l Z_l^T (Pn x r_l)
+    for (int l = 0; l < 3; ++l) {
+        const int N = P.N[l], rl = q.r[l];
+        const double* g = G[l];
+        if (!on_device) {
+            if ((rc = Gd[l].get(c.pool, (size_t)nb * N * 8))) return rc;
+            LSUM_HIP(hipMemcpyAsync(Gd[l].p, G[l], (size_t)nb * N * 8, hipMemcpyHostToDevice, st));
+            g = Gd[l].as<double>();
+        }
+        if ((rc = H.get(c.pool, (size_t)Pn * N * 8))) return rc;
+        launch_hadamard_pairs(st, nb, N, g, H.as<double>());
+        if ((rc = Y[l].get(c.pool, (size_t)Pn * rl * 8))) return rc;
+        GemmArgs a{};
+        a.m = (int)Pn; a.n = rl; a.k = N;
+        a.A = H.p; a.sam = N; a.sak = 1;
+        a.B = q.Z[l].p; a.sbk = 1; a.sbn = N;
+        a.C = Y[l].p; a.scm = rl; a.scn = 1;
+        a.alpha = 1.0; a.beta = 0.0; a.batch = 1;
+        if ((rc = gemm_auto(&c, st, GEMM_F64, a))) return rc;
+        LSUM_HIP(hipStreamSynchronize(st));   // H is reused by the next mode
+        H.reset();
+    }
+    // the core in FP64 (FP32 at FP32 / BF16X3 precision), then X = Y_3 mu^T (Pn x r1 r2)
+    const long plane = (long)r1 * r2 * r3;
+    const double* mud = q.core.as<double>();
+    if (P.precision != LSUM_FP64) {
+        if ((rc = mu.get(c.pool, (size_t)plane * 8))) return rc;
+        launch_f32_to_f64(st, plane, q.core.as<float>(), mu.as<double>());
+        mud = mu.as<double>();
+    }
+    if ((rc = X.get(c.pool, (size_t)Pn * r1 * r2 * 8))) return rc;
+    GemmArgs a{};
+    a.m = (int)Pn; a.n = r1 * r2; a.k = r3;
+    a.A = Y[2].p; a.sam = r3; a.sak = 1;
+    a.B = mud; a.sbk = 1; a.sbn = r3;
+    a.C = X.p; a.scm = (long)r1 * r2; a.scn = 1;
+    a.alpha = 1.0; a.beta = 0.0; a.batch = 1;
+    if ((rc = gemm_auto(&c, st, GEMM_F64, a))) return rc;
+    double* out = V;
+    if (!on_device) {
+        if ((rc = v.get(c.pool, (size_t)Pn * 8))) return rc;
+        out = v.as<double>();
+    }
+    launch_galerkin_finish(st, (int)Pn, r1, r2, X.as<double>(), Y[0].as<double>(), Y[1].as<double>(),
+                           P.h * P.h * P.h, out);
+    LSUM_HIP(hipGetLastError());
+    if (!on_device) LSUM_HIP(hipMemcpyAsync(V, out, (size_t)Pn * 8, hipMemcpyDeviceToHost, st));
+    LSUM_HIP(hipStreamSynchronize(st));
+    return LSUM_OK;
+}
+
 int lsum_get_tucker(lsum_req r, double* Z0, double* Z1, double* Z2, double* core, int on_device) {
     int rc = need_done(r);
     if (rc) return rc;

@@ -232,6 +232,11 @@ void launch_gemm(hipStream_t st, GemmPrec prec, const GemmArgs& a);
 // then C = alpha * (their sum in slice order) + beta * C.
 // KR[nu, i * rb + j] = Xa[nu, i] Xb[nu, j] (row-major, K rows): the ALS mode operand.
 void launch_khatri_rao(hipStream_t st, int K, int ra, int rb, const double* Xa, const double* Xb, double* KR);
+// Galerkin functional: H[k nb + m, :] = G[k, :] G[m, :] (nb^2 rows of n), and
+// v[p] = scale sum_{a,b} X[p, a r2 + b] Y1[p, a] Y2[p, b].
+void launch_hadamard_pairs(hipStream_t st, int nb, int n, const double* G, double* H);
+void launch_galerkin_finish(hipStream_t st, int P, int r1, int r2, const double* X, const double* Y1,
+                            const double* Y2, double scale, double* v);
 int gemm_split_slices(const GemmArgs& a, int split);
 void launch_gemm_split_f64(hipStream_t st, const GemmArgs& a, int split, double* work);
 

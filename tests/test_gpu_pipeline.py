@@ -453,3 +453,22 @@ def test_vacancy_clusters_as_one_non_equidistant_block(ctx):
         ref = O.brute_force_points_at(p, pts, pos, Z)
         tol = 1e-12 if eps == 0.0 else 10 * eps
         assert np.max(np.abs(got - ref)) <= tol * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("lattice", [False, True])
+def test_galerkin_matrix_matches_oracle(ctx, lattice):
+    # eq. nuc_pot on the device's own Tucker result against the oracle's sum over its full tensor
+    alpha = np.array([1.0, 2.0, 1.5, 0.8])
+    A = np.array([[0.3, -0.2, 0.1], [-0.4, 0.5, 0.0], [0.0, 0.0, 0.6], [0.5, 0.5, -0.5]])
+    N, h = (49, 45, 41), 1 / 6
+    blk = W.Block((3, 2, 2), (1.0, 1.0, 1.0), (0.0, 0.0, 0.0)) if lattice else W.Block((1, 1, 1), (1, 1, 1), (0, 0, 0))
+    p = W.Problem("galerkin", W.NEWTON, 0.0, 32, N, h, [blk], eps=1e-9)
+    r = run(ctx, p)
+    x = [(np.arange(n) - (n - 1) // 2) * h for n in N]
+    G = [np.exp(-alpha[:, None] * (x[l][None, :] - A[:, l][:, None]) ** 2) for l in range(3)]
+    V = r.galerkin(G)
+    Z, core = r.tucker()
+    r.release()
+    Vo = O.galerkin_matrix(O.tucker_full(core, [z.T for z in Z]), G, h)
+    assert np.max(np.abs(V - Vo)) <= 1e-10 * np.max(np.abs(Vo))
+    assert np.max(np.abs(V - V.T)) <= 1e-12 * np.max(np.abs(V))

@@ -259,3 +259,40 @@ def test_choose_M_reports_the_floor_of_the_step():
     assert M is None and e > 1e-9
     M2, e2 = O.choose_M(O.NEWTON, 0.0, N, h, 1e-9, 160, h_u=0.2)
     assert M2 is not None and e2 <= 1e-9
+
+
+# ---------------------------------------------------------------------------------------
+# eq. nuc_pot: Galerkin matrix in a Gaussian basis against its closed form
+# ---------------------------------------------------------------------------------------
+
+def _gauss_coulomb(alpha, A, C):
+    # int exp(-a|x-A|^2) exp(-b|x-B|^2) / |x - C| dx = exp(-ab/p |A-B|^2) (2 pi / p) F0(p |P-C|^2),
+    # p = a + b, P = (a A + b B) / p, F0(t) = sqrt(pi / t) erf(sqrt t) / 2
+    nb = len(alpha)
+    V = np.zeros((nb, nb))
+    for k in range(nb):
+        for m in range(nb):
+            p = alpha[k] + alpha[m]
+            P = (alpha[k] * A[k] + alpha[m] * A[m]) / p
+            t = p * float(np.sum((P - C) ** 2))
+            F0 = 1.0 if t < 1e-14 else 0.5 * math.sqrt(math.pi / t) * erf(math.sqrt(t))
+            V[k, m] = math.exp(-alpha[k] * alpha[m] / p * float(np.sum((A[k] - A[m]) ** 2))) * 2 * math.pi / p * F0
+    return V
+
+
+def test_galerkin_matrix_converges_to_the_gaussian_closed_form():
+    # one Newton charge: the grid functional with the basis at cell centres converges at O(h^2)
+    import workloads as W
+    alpha = np.array([1.0, 2.0, 1.5])
+    A = np.array([[0.3, -0.2, 0.1], [-0.4, 0.5, 0.0], [0.0, 0.0, 0.6]])
+    Vc = _gauss_coulomb(alpha, A, np.zeros(3))
+    errs = []
+    for N, h in [(49, 1 / 6), (97, 1 / 12)]:
+        c = (N - 1) // 2
+        p = W.Problem("g", W.NEWTON, 0.0, 40, (N, N, N), h, [W.Block((1, 1, 1), (1, 1, 1), (0, 0, 0))])
+        x = (np.arange(N) - c) * h
+        G = [np.exp(-alpha[:, None] * (x[None, :] - A[:, l][:, None]) ** 2) for l in range(3)]
+        V = O.galerkin_matrix(O.brute_force_grid(p), G, h)
+        assert np.array_equal(V, V.T)
+        errs.append(np.max(np.abs(V - Vc) / np.abs(Vc)))
+    assert errs[1] < 2e-3 and 3.0 < errs[0] / errs[1] < 5.0
