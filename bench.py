@@ -18,7 +18,7 @@ inside the library over the timed region) and the oracle's own CPU rate are repo
 with the same served stream on FP64 rows and with the sites at their exact positions (no
 snapping; `served_exact_sites`).
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cfg2|cfg3|cfg4|mix|timesL]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cfg2|cfg3|cfg4|mix|timesL|extras]
 """
 from __future__ import annotations
 
@@ -50,7 +50,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2048)
     ap.add_argument("--warmup", type=int, default=128)
-    ap.add_argument("--workload", default="cfg2", choices=["cfg2", "cfg3", "cfg4", "mix", "timesL"])
+    ap.add_argument("--workload", default="cfg2", choices=["cfg2", "cfg3", "cfg4", "mix", "timesL", "extras"])
     ap.add_argument("--requests", type=int, default=32, help="requests of the served mix")
     ap.add_argument("--inflight", type=int, default=64)
     ap.add_argument("--slots", type=int, default=3)
@@ -374,6 +374,98 @@ def run_times_l(args):
     print(json.dumps(out))
 
 
+def _timed(fn, reps=3):
+    best = None
+    out = None
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        out = fn()
+        dt = time.perf_counter() - t0
+        best = dt if best is None else min(best, dt)
+    return best, out
+
+
+def run_extras(args):
+    """Timings of the paths beyond the served lattice sum, each with an accuracy check: the choice
+    of M, a parallelogram lattice (Sec. 5 case (B)), ALS after the RHOSVD (Thm thm:C2Tucker (b)),
+    the canonical form of a Tucker result (Can -> Tuck -> Can) and the Galerkin matrix (eq.
+    nuc_pot)."""
+    import oracle as O
+    import paper_1411_1994_amd as L
+    import workloads as W
+
+    out = {"metric": "extra paths: time per call", "n_gpus": 1, "data": "synthetic", "dtype": "f64",
+           "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "warmup": 1}
+    rng = np.random.default_rng(W.SEED_BASE + 900)
+    # choice of M (host): N = 4097, eps = 1e-6
+    t, (M, err) = _timed(lambda: L.lsum_choose_M(W.NEWTON, 0.0, (4097,) * 3, 5 / 256, 1e-6, 128))
+    out["choose_M"] = {"ms": 1e3 * t, "M": M, "max_norm_err": err, "N": 4097}
+    with L.Context(0, n_slots=1) as ctx:
+        # parallelogram lattice: 32 x 32 x 8 sites, x moving 0.4 per step along y, N = 1025
+        base = W.Block((32, 32, 8), (1.0, 1.0, 1.0), (0.0, 0.0, 0.0))
+        blocks = [W.Block(b.L, b.b, b.center, b.charge) for b in L.lsum_shear_blocks(base, 0, 1, 0.4)]
+        p = W.Problem("shear", W.NEWTON, 0.0, 36, (1025, 1025, 513), 1 / 16, blocks)
+        pts = np.stack([rng.integers(0, n, 100_000) for n in p.N], axis=1)
+        xyz = np.stack([(pts[:, a] - (p.N[a] - 1) // 2) * p.h for a in range(3)], axis=1)
+        prep = L.prepare(p)
+
+        def shear_run():
+            r = ctx.submit(prep, points=xyz, values=np.zeros(len(xyz)))
+            assert r.wait() == 0
+            v = r.values.copy()
+            r.release()
+            return v
+        t, v = _timed(shear_run)
+        pos = O.shear_sites(base, 0, 1, 0.4)
+        ref = O.brute_force_points_at(p, pts[:4], pos, np.ones(len(pos)))
+        out["parallelogram"] = {"ms_per_sum": 1e3 * t, "sites": len(pos), "sub_blocks": len(blocks),
+                                "sample_points": len(xyz),
+                                "max_rel_err_vs_oracle": float(np.max(np.abs(v[:4] - ref)) / np.max(np.abs(ref)))}
+        # ALS after the RHOSVD: 12^3 lattice with 10 defects, eps = 1e-3, N = 129 (ranks about 60,
+        # inside the ALS limit r_a r_b <= 4096 and the 128 x 128 core slices of Can -> Tuck -> Can)
+        blk = W.Block((12, 12, 12), (1.0, 1.0, 1.0), (0.0, 0.0, 0.0))
+        defects = W.draw_defects(np.random.default_rng(5), [blk], 5, 5)
+        res = {}
+        for sweeps in (0, 2):
+            q = W.Problem("als", W.NEWTON, 0.0, 32, (129, 129, 129), 1 / 4, [blk], defects, eps=1e-3,
+                          als_sweeps=sweeps)
+            prep = L.prepare(q)
+
+            def tucker_run():
+                r = ctx.submit(prep)
+                assert r.wait() == 0
+                return r
+            t, r = _timed(tucker_run, 2)
+            st = r.stats()
+            cells = np.stack([rng.integers(0, n, 4) for n in q.N], axis=1)
+            vals = r.sample(np.stack([(cells[:, a] - 64) * q.h for a in range(3)], axis=1))
+            ref = O.brute_force_points(q, cells)
+            res[sweeps] = {"ms": 1e3 * t, "ranks": list(r.info().r), "als_ms": st["t_ms"].get("als", 0.0),
+                           "als_core_norm": st["als_core_norm"],
+                           "max_rel_err_vs_oracle": float(np.max(np.abs(vals - ref)) / np.max(np.abs(ref)))}
+            if sweeps == 2:
+                # the same Tucker result in canonical form at eps = 1e-6
+                tc, (xi, U, e) = _timed(lambda: r.tucker_to_canonical(1e-6), 2)
+                out["tucker_to_canonical"] = {"ms": 1e3 * tc, "rank": len(xi), "frobenius_err": e}
+                # Galerkin matrix in 64 Gaussians
+                alpha = rng.uniform(0.5, 2.0, 64)
+                A = rng.uniform(-6.0, 6.0, (64, 3))
+                x = (np.arange(129) - 64) * q.h
+                G = [np.exp(-alpha[:, None] * (x[None, :] - A[:, l][:, None]) ** 2) for l in range(3)]
+                tg, V = _timed(lambda: r.galerkin(G), 2)
+                out["galerkin"] = {"ms": 1e3 * tg, "basis": 64, "N": 129, "symmetric_dev":
+                                   float(np.max(np.abs(V - V.T)) / np.max(np.abs(V)))}
+            r.release()
+        out["rhosvd"] = res[0]
+        out["rhosvd_als2"] = res[2]
+    out["value"] = out["parallelogram"]["ms_per_sum"]
+    out["unit"] = "ms per parallelogram lattice sum"
+    out["steps"] = 3
+    out["ms_per_step"] = out["value"]
+    out["config"] = {"workload": "extras"}
+    print(json.dumps(out))
+
+
 def per_precision(L, W, problem, xyz):
     """The reduction request in FP64, FP32 and split-BF16x3: MFMA rate of the core and of the
     tile's mode products (event-timed stage time, algorithmic flops), and each result's deviation
@@ -415,6 +507,9 @@ def main():
         return
     if args.workload == "timesL":
         run_times_l(args)
+        return
+    if args.workload == "extras":
+        run_extras(args)
         return
     import torch
     import oracle as O

@@ -508,6 +508,12 @@ __global__ void __launch_bounds__(256) k_galerkin_finish(int P, int r1, int r2, 
     if (lane == 0) v[p] = scale * acc;
 }
 
+// A[i * ld + off + i] = 1 for i < n: the identity block of an augmented matrix.
+__global__ void __launch_bounds__(256) k_unit_diag(int n, long ld, long off, double* __restrict__ A) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) A[(long)i * ld + off + i] = 1.0;
+}
+
 // C = alpha * sum_z work_z + beta * C for an m x n output with strides (scm, scn): the partial
 // products of a GEMM whose reduction was split into slices, summed in slice order.
 __global__ void __launch_bounds__(256) k_sum_split(int m, int n, int split, const double* __restrict__ work,
@@ -589,6 +595,11 @@ void launch_galerkin_finish(hipStream_t st, int P, int r1, int r2, const double*
                             const double* Y2, double scale, double* v) {
     if (P <= 0) return;
     hipLaunchKernelGGL(k_galerkin_finish, dim3(cdiv(P, 4)), dim3(256), 0, st, P, r1, r2, X, Y1, Y2, scale, v);
+}
+
+void launch_unit_diag(hipStream_t st, int n, long ld, long off, double* A) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_unit_diag, dim3(cdiv(n, 256)), dim3(256), 0, st, n, ld, off, A);
 }
 
 void launch_gemm_split_f64(hipStream_t st, const GemmArgs& a, int split, double* work) {

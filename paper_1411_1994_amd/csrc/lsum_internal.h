@@ -237,6 +237,8 @@ void launch_khatri_rao(hipStream_t st, int K, int ra, int rb, const double* Xa, 
 void launch_hadamard_pairs(hipStream_t st, int nb, int n, const double* G, double* H);
 void launch_galerkin_finish(hipStream_t st, int P, int r1, int r2, const double* X, const double* Y1,
                             const double* Y2, double scale, double* v);
+// A[i * ld + off + i] = 1 for i < n (the rest untouched).
+void launch_unit_diag(hipStream_t st, int n, long ld, long off, double* A);
 int gemm_split_slices(const GemmArgs& a, int split);
 void launch_gemm_split_f64(hipStream_t st, const GemmArgs& a, int split, double* work);
 

@@ -299,17 +299,43 @@ static int run_als(Request* q, hipStream_t st, DevBuf cols[3], StageTimer& tm) {
         for (int l = 0; l < 3; ++l) {
             const int a = (l + 1) % 3, b = (l + 2) % 3, N = P.N[l], D = r[a] * r[b];
             launch_khatri_rao(st, (int)K, r[a], r[b], X[a].as<double>(), X[b].as<double>(), KR.as<double>());
-            if ((rc = Mr.get(c->pool, (size_t)D * N * 8))) return rc;
-            GemmArgs g{};
-            g.m = D; g.n = N; g.k = (int)K;
-            g.A = KR.p; g.sam = 1; g.sak = D;
-            g.B = T[l].p; g.sbk = N; g.sbn = 1;
-            g.C = Mr.p; g.scm = N; g.scn = 1;
-            g.alpha = 1.0; g.beta = 0.0; g.batch = 1;
-            if ((rc = gemm_auto(c, st, GEMM_F64, g))) return rc;
-            LSUM_HIP(hipStreamSynchronize(st));
             ModeSVD ms;
-            if ((rc = mode_svd(c, st, D, N, Mr, 0.0, 0.0, ms, false))) return rc;
+            if (N < D) {
+                // Jacobi on the N rows of [M_l | I] with the Gram over M_l's columns: the rotated
+                // identity block holds M_l's left singular vectors (unit rows)
+                const long ld = (long)D + N;
+                if ((rc = Mr.get(c->pool, (size_t)N * ld * 8))) return rc;
+                LSUM_HIP(hipMemsetAsync(Mr.p, 0, (size_t)N * ld * 8, st));
+                GemmArgs g{};
+                g.m = N; g.n = D; g.k = (int)K;
+                g.A = T[l].p; g.sam = 1; g.sak = N;
+                g.B = KR.p; g.sbk = D; g.sbn = 1;
+                g.C = Mr.p; g.scm = ld; g.scn = 1;
+                g.alpha = 1.0; g.beta = 0.0; g.batch = 1;
+                if ((rc = gemm_auto(c, st, GEMM_F64, g))) return rc;
+                launch_unit_diag(st, N, ld, D, Mr.as<double>());
+                DevBuf work;
+                const size_t wb = jacobi_work_bytes(N, (int)ld);
+                if ((rc = work.get(c->pool, wb))) return rc;
+                rc = jacobi_svd(st, N, (int)ld, Mr.as<double>(), (int)ld, 1e-12, 0.0, 40, ms.sigma, &ms.sweeps,
+                                work.as<double>(), wb, D);
+                if (rc) return rc;
+                ms.rows = std::move(Mr);
+                ms.ld = ld;
+                ms.off = D;
+                ms.unit = true;
+            } else {
+                if ((rc = Mr.get(c->pool, (size_t)D * N * 8))) return rc;
+                GemmArgs g{};
+                g.m = D; g.n = N; g.k = (int)K;
+                g.A = KR.p; g.sam = 1; g.sak = D;
+                g.B = T[l].p; g.sbk = N; g.sbn = 1;
+                g.C = Mr.p; g.scm = N; g.scn = 1;
+                g.alpha = 1.0; g.beta = 0.0; g.batch = 1;
+                if ((rc = gemm_auto(c, st, GEMM_F64, g))) return rc;
+                LSUM_HIP(hipStreamSynchronize(st));
+                if ((rc = mode_svd(c, st, D, N, Mr, 0.0, 0.0, ms, false))) return rc;
+            }
             LSUM_HIP(hipStreamSynchronize(st));
             double lead = 0.0;
             for (int k = 0; k < r[l] && k < (int)ms.sigma.size(); ++k) lead += ms.sigma[k] * ms.sigma[k];
