@@ -165,6 +165,14 @@ int lsum_nodes(const lsum_kernel* k, const int N[3], double h, double* t, double
 int lsum_shear_blocks(const lsum_block* base, int shear_axis, int along_axis, double shear, int cap,
                       lsum_block* out, int* n);
 
+/* Lattice with the tensor structure in one axis only (Sec. 5 case (C)): the sites of `base`
+ * along `axis` (its L, b, center or explicit coordinates), repeated at each of the n points of
+ * the plane of the two other axes (pts: n pairs in increasing axis order).  Written as n blocks
+ * of one site in those two axes (out[0..n), cap at least n), which the canonical route sums with
+ * the column axis once; the rank grows with n, as the paper notes.  Host only. */
+int lsum_column_blocks(const lsum_block* base, int axis, int n, const double* pts, int cap,
+                       lsum_block* out);
+
 /* Snapped cell indices of a block's sites (windowing offsets of Sec. 3.1 eq. sub_tens for the
  * centred lattice of Sec. 3.2): offs[0..L0-1] axis 0, then L1 for axis 1, then L2 for axis 2.
  * Bit-exact IEEE FP64 arithmetic: x = (k - (L-1)/2) * b + center; u = x / h. */

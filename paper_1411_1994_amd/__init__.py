@@ -25,7 +25,7 @@ FP64, FP32, BF16X3 = 0, 1, 2
 SUM_CANONICAL, SUM_TUCKER_REF = 0, 1
 
 # every symbol declared in include/lsum.h
-SYMBOLS = ["lsum_nodes", "lsum_block_offsets", "lsum_shear_blocks", "lsum_sinc_error", "lsum_choose_M", "lsum_create", "lsum_destroy", "lsum_last_error",
+SYMBOLS = ["lsum_nodes", "lsum_block_offsets", "lsum_shear_blocks", "lsum_column_blocks", "lsum_sinc_error", "lsum_choose_M", "lsum_create", "lsum_destroy", "lsum_last_error",
            "lsum_collocate", "lsum_shift_sum", "lsum_sample_canonical", "lsum_jacobi_svd",
            "lsum_contract",
            "lsum_submit", "lsum_submit_many", "lsum_wait", "lsum_cancel", "lsum_get_info", "lsum_get_canonical",
@@ -89,6 +89,7 @@ def _load():
         "lsum_block_offsets": (I, [P(lsum_block), P(I), D, P(C.c_int32)]),
         "lsum_sinc_error": (I, [P(lsum_kernel), P(I), D, P(D)]),
         "lsum_shear_blocks": (I, [P(lsum_block), I, I, D, I, P(lsum_block), P(I)]),
+        "lsum_column_blocks": (I, [P(lsum_block), I, I, P(D), I, P(lsum_block)]),
         "lsum_choose_M": (I, [P(lsum_kernel), P(I), D, D, I, P(I), P(D)]),
         "lsum_create": (I, [P(VP), I, C.c_size_t, I]),
         "lsum_destroy": (I, [VP]),
@@ -228,6 +229,25 @@ def lsum_shear_blocks(base, shear_axis: int, along_axis: int, shear: float) -> l
         coords = tuple(None if l == along_axis else base_coords[l] for l in range(3))
         res.append(types.SimpleNamespace(L=tuple(b.L), b=tuple(b.b), center=tuple(b.center), charge=b.charge,
                                          coords=coords if any(c is not None for c in coords) else None))
+    return res
+
+
+def lsum_column_blocks(base, axis: int, pts) -> list:
+    """A lattice with tensor structure along one axis only (``lsum_column_blocks``): one block per
+    point of the other two axes' plane; objects with the fields of workloads.Block."""
+    import types
+    keep = []
+    bst = _block(base, keep)
+    pts = np.ascontiguousarray(pts, dtype=np.float64).reshape(-1, 2)
+    n = pts.shape[0]
+    out = (lsum_block * max(n, 1))()
+    _check(_lib.lsum_column_blocks(C.byref(bst), axis, n, _dptr(pts), n, out))
+    coords = getattr(base, "coords", None)
+    res = []
+    for b in out[:n]:
+        c = tuple(coords[l] if (coords is not None and l == axis) else None for l in range(3))
+        res.append(types.SimpleNamespace(L=tuple(b.L), b=tuple(b.b), center=tuple(b.center), charge=b.charge,
+                                         coords=c if any(x is not None for x in c) else None))
     return res
 
 

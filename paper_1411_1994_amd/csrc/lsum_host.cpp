@@ -477,6 +477,24 @@ int lsum_shear_blocks(const lsum_block* base, int shear_axis, int along_axis, do
     return LSUM_OK;
 }
 
+int lsum_column_blocks(const lsum_block* base, int axis, int n, const double* pts, int cap, lsum_block* out) {
+    if (!base || (n > 0 && (!pts || !out))) return lsum::fail(LSUM_E_INVALID, "null argument");
+    if (axis < 0 || axis > 2) return lsum::fail(LSUM_E_INVALID, "bad axis");
+    if (n < 0 || cap < n) return lsum::fail(LSUM_E_INVALID, "output capacity below the number of points");
+    const int a = axis == 0 ? 1 : 0, b = axis == 2 ? 1 : 2;
+    for (int k = 0; k < n; ++k) {
+        if (!std::isfinite(pts[2 * k]) || !std::isfinite(pts[2 * k + 1]))
+            return lsum::fail(LSUM_E_INVALID, "point coordinate is not finite");
+        lsum_block blk = *base;
+        blk.L[a] = blk.L[b] = 1;
+        blk.x[a] = blk.x[b] = nullptr;
+        blk.center[a] = pts[2 * k];
+        blk.center[b] = pts[2 * k + 1];
+        out[k] = blk;
+    }
+    return LSUM_OK;
+}
+
 int lsum_block_offsets(const lsum_block* blk, const int N[3], double h, int32_t* offs) {
     if (!blk || !N || !offs) return lsum::fail(LSUM_E_INVALID, "null argument");
     for (int l = 0; l < 3; ++l)

@@ -236,3 +236,18 @@ def test_cluster_lattice_is_one_non_equidistant_block():
                       for f0 in fine[0] for f1 in fine[1] for f2 in fine[2]])
     key = lambda a: a[np.lexsort(a.T[::-1])]
     assert np.array_equal(key(pos), key(union)) and np.all(Z == -1.0)
+
+
+def test_column_blocks_enumerate_the_columns():
+    # case (C): a column of 5 sites along axis 2 repeated at 7 scattered points of the (x, y) plane
+    import paper_1411_1994_amd as L
+    rng = np.random.default_rng(9)
+    base = W.Block((3, 3, 5), (1.0, 1.0, 0.8), (0.0, 0.0, 0.4))
+    pts = rng.uniform(-3.0, 3.0, (7, 2))
+    blocks = L.lsum_column_blocks(base, 2, pts)
+    assert len(blocks) == 7 and all(b.L == (1, 1, 5) for b in blocks)
+    got = np.concatenate([O.charge_positions(W.Problem("c", 0, 0.0, 8, (5, 5, 5), 1.0, [b]))[0] for b in blocks])
+    zs = O.site_coords(5, 0.8, 0.4)
+    want = np.array([[x, y, z] for x, y in pts for z in zs])
+    key = lambda a: a[np.lexsort(np.round(a, 9).T[::-1])]
+    assert np.allclose(key(got), key(want), atol=1e-12, rtol=0)

@@ -472,3 +472,21 @@ def test_galerkin_matrix_matches_oracle(ctx, lattice):
     Vo = O.galerkin_matrix(O.tucker_full(core, [z.T for z in Z]), G, h)
     assert np.max(np.abs(V - Vo)) <= 1e-10 * np.max(np.abs(Vo))
     assert np.max(np.abs(V - V.T)) <= 1e-12 * np.max(np.abs(V))
+
+
+def test_column_lattice(ctx):
+    # case (C): columns of 6 sites along z at 20 scattered (x, y) points; canonical route against
+    # the plain sum over the explicit sites
+    import paper_1411_1994_amd as L
+    rng = np.random.default_rng(83)
+    base = W.Block((1, 1, 6), (1.0, 1.0, 1.0), (0.0, 0.0, 0.0))
+    xy = rng.uniform(-5.0, 5.0, (20, 2))
+    blocks = [W.Block(b.L, b.b, b.center, b.charge) for b in L.lsum_column_blocks(base, 2, xy)]
+    p = W.Problem("columns", W.NEWTON, 0.0, 28, (65, 65, 41), 0.25, blocks)
+    r = run(ctx, p)
+    pts = np.stack([rng.integers(0, n, 300) for n in p.N], axis=1)
+    got = r.sample(cells_xyz(p, pts))
+    r.release()
+    pos, Z = O.charge_positions(p)
+    ref = O.brute_force_points_at(p, pts, pos, Z)
+    assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
