@@ -490,3 +490,37 @@ def test_column_lattice(ctx):
     pos, Z = O.charge_positions(p)
     ref = O.brute_force_points_at(p, pts, pos, Z)
     assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def test_galerkin_and_canonical_form_with_device_buffers(ctx):
+    # the on_device variants read the basis from and write the results to device memory; they
+    # equal the host variants bit for bit
+    import ctypes
+    import paper_1411_1994_amd as L
+    from gpu_util import dev, host
+    alpha = np.array([1.0, 2.0, 1.5])
+    A = np.array([[0.3, -0.2, 0.1], [-0.4, 0.5, 0.0], [0.0, 0.0, 0.6]])
+    N, h = (49, 45, 41), 1 / 6
+    p = W.Problem("dev", W.NEWTON, 0.0, 32, N, h, [W.Block((3, 2, 2), (1.0, 1.0, 1.0), (0.0, 0.0, 0.0))],
+                  eps=1e-6)
+    r = run(ctx, p)
+    x = [(np.arange(n) - (n - 1) // 2) * h for n in N]
+    G = [np.exp(-alpha[:, None] * (x[l][None, :] - A[:, l][:, None]) ** 2) for l in range(3)]
+    Vh = r.galerkin(G)
+    Gd = [dev(g) for g in G]
+    Vd = dev(np.zeros((3, 3)))
+    rc = L._lib.lsum_galerkin(r.handle, 3, Gd[0].data_ptr(), Gd[1].data_ptr(), Gd[2].data_ptr(),
+                              Vd.data_ptr(), 1)
+    assert rc == 0 and np.array_equal(host(Vd), Vh)
+    xi, U, err = r.tucker_to_canonical(1e-8)
+    R = len(xi)
+    xd = dev(np.zeros(R))
+    Ud = [dev(np.zeros((R, n))) for n in N]
+    Rc, ec = ctypes.c_int(0), ctypes.c_double(0.0)
+    rc = L._lib.lsum_tucker_to_canonical(r.handle, 1e-8, R, ctypes.byref(Rc),
+                                         ctypes.cast(xd.data_ptr(), ctypes.POINTER(ctypes.c_double)),
+                                         *[ctypes.cast(u.data_ptr(), ctypes.POINTER(ctypes.c_double)) for u in Ud],
+                                         ctypes.byref(ec), 1)
+    r.release()
+    assert rc == 0 and Rc.value == R and ec.value == err
+    assert np.array_equal(host(xd), xi) and all(np.array_equal(host(Ud[l]), U[l]) for l in range(3))
