@@ -125,22 +125,25 @@ static bool plan_key(const lsum_problem& p, std::string& key) {
 }
 
 // The plan of a problem: from the context's cache when the same problem was planned before.
-static int plan_for(Context& c, const lsum_problem& p, Plan& out) {
+static int plan_for(Context& c, const lsum_problem& p, std::shared_ptr<const Plan>& out) {
     std::string key;
     const bool cacheable = plan_key(p, key);
     if (cacheable) {
         std::lock_guard<std::mutex> lk(c.plan_mu);
         auto it = c.plans.find(key);
         if (it != c.plans.end()) {
-            out = *it->second;
+            out = it->second;
             return LSUM_OK;
         }
     }
-    const int rc = make_plan(p, out);
-    if (rc != LSUM_OK || !cacheable) return rc;
+    auto made = std::make_shared<Plan>();
+    const int rc = make_plan(p, *made);
+    if (rc != LSUM_OK) return rc;
+    out = made;
+    if (!cacheable) return LSUM_OK;
     std::lock_guard<std::mutex> lk(c.plan_mu);
     if (c.plans.size() >= 256) c.plans.clear();
-    c.plans.emplace(std::move(key), std::make_shared<const Plan>(out));
+    c.plans.emplace(std::move(key), out);
     return LSUM_OK;
 }
 
@@ -149,7 +152,7 @@ static int prepare_request(lsum_ctx x, const lsum_problem* p, lsum_req_s** out) 
     Request& q = r->q;
     q.ctx_ref = x->sp;
     q.ctx = &x->c;
-    int rc = plan_for(x->c, *p, q.plan);
+    int rc = plan_for(x->c, *p, q.plan_sp);
     if (rc != LSUM_OK) {
         delete r;
         return rc;
@@ -162,7 +165,7 @@ static int prepare_request(lsum_ctx x, const lsum_problem* p, lsum_req_s** out) 
     q.points = p->points;
     q.values = p->values;
     q.points_on_device = p->points_on_device;
-    q.reserved = q.plan.planned_bytes() + (q.points_on_device ? 0 : (size_t)q.n_points * 32);
+    q.reserved = q.plan().planned_bytes() + (q.points_on_device ? 0 : (size_t)q.n_points * 32);
     if (q.reserved > x->c.budget) {
         delete r;
         return fail(LSUM_E_NOMEM, "the request can never fit the HBM budget");
@@ -250,7 +253,7 @@ int lsum_get_info(lsum_req r, lsum_info* info) {
     std::lock_guard<std::mutex> lk(q.mu);
     std::memset(info, 0, sizeof(*info));
     info->status = q.done ? q.status.load() : 1;
-    const Plan& P = q.plan;
+    const Plan& P = q.plan();
     info->R = P.R;
     info->n_terms = P.R * P.n_groups;
     info->is_tucker = P.tucker() ? 1 : 0;
@@ -277,7 +280,7 @@ int lsum_get_canonical(lsum_req r, int block, double* U0, double* U1, double* U2
     int rc = need_done(r);
     if (rc) return rc;
     Request& q = r->q;
-    const Plan& P = q.plan;
+    const Plan& P = q.plan();
     if (block < 0 || block >= (int)P.blocks.size()) return fail(LSUM_E_INVALID, "bad block index");
     double* dst[3] = {U0, U1, U2};
     const bool have_vm = q.U[block].p != nullptr;
@@ -313,7 +316,7 @@ int lsum_tucker_to_canonical(lsum_req r, double eps, int cap, int* R, double* xi
     if (!R || !err) return fail(LSUM_E_INVALID, "null argument");
     if (!(eps >= 0.0)) return fail(LSUM_E_INVALID, "eps must be >= 0");
     Request& q = r->q;
-    const Plan& P = q.plan;
+    const Plan& P = q.plan();
     if (!P.tucker()) return fail(LSUM_E_STATE, "request has no Tucker output");
     const int r1 = q.r[0], r2 = q.r[1], r3 = q.r[2];
     if (std::max(r1, r2) > 128) return fail(LSUM_E_INVALID, "core slices above 128 x 128");
@@ -407,7 +410,7 @@ int lsum_galerkin(lsum_req r, int nb, const double* G0, const double* G1, const 
     if (!G0 || !G1 || !G2 || !V) return fail(LSUM_E_INVALID, "null argument");
     if (nb < 1 || nb > 255) return fail(LSUM_E_INVALID, "nb must be in [1, 255]");
     Request& q = r->q;
-    const Plan& P = q.plan;
+    const Plan& P = q.plan();
     if (!P.tucker()) return fail(LSUM_E_STATE, "the Galerkin functional needs a Tucker result");
     Context& c = *q.ctx;
     LSUM_HIP(hipSetDevice(c.device));
@@ -471,7 +474,7 @@ int lsum_get_tucker(lsum_req r, double* Z0, double* Z1, double* Z2, double* core
     int rc = need_done(r);
     if (rc) return rc;
     Request& q = r->q;
-    const Plan& P = q.plan;
+    const Plan& P = q.plan();
     if (!P.tucker()) return fail(LSUM_E_STATE, "request has no Tucker output");
     double* dst[3] = {Z0, Z1, Z2};
     for (int l = 0; l < 3; ++l) {
@@ -509,7 +512,7 @@ int lsum_sample(lsum_req r, int n, const double* xyz, double* out, int on_device
     if (n == 0) return LSUM_OK;
     Request& q = r->q;
     Context& c = *q.ctx;
-    const Plan& P = q.plan;
+    const Plan& P = q.plan();
     LSUM_HIP(hipSetDevice(c.device));
     hipStream_t st = c.own_stream;
     DevBuf xd, od;
@@ -535,7 +538,7 @@ int lsum_get_tile(lsum_req r, void* out, int elem_size, int on_device) {
     int rc = need_done(r);
     if (rc) return rc;
     Request& q = r->q;
-    const Plan& P = q.plan;
+    const Plan& P = q.plan();
     if (!P.has_tile()) return fail(LSUM_E_STATE, "request has no tile");
     const int want = P.precision == LSUM_FP64 ? 8 : 4;
     if (elem_size != want) return fail(LSUM_E_INVALID, "tile element size does not match the precision");
@@ -548,7 +551,7 @@ int lsum_get_stats(lsum_req r, char* buf, size_t len) {
     Request& q = r->q;
     std::ostringstream o;
     o.precision(17);
-    const Plan& P = q.plan;
+    const Plan& P = q.plan();
     {
         std::lock_guard<std::mutex> lk(q.mu);
         o << "{\"status\":" << (q.done ? q.status.load() : 1) << ",\"R\":" << P.R << ",\"n_groups\":" << P.n_groups

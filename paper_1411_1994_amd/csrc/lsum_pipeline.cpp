@@ -167,7 +167,7 @@ static int mode_svd(Context* c, hipStream_t st, int D, int N, DevBuf& W, double 
 // request's precision (eq. Tucker_singePot).
 static int make_tile(Request* q, hipStream_t st, StageTimer& tm) {
     Context* c = q->ctx;
-    const Plan& P = q->plan;
+    const Plan& P = q->plan();
     const GemmPrec prec = gemm_prec(P.precision);
     const size_t es = (prec == GEMM_F64) ? 8 : 4;
     int rc;
@@ -247,7 +247,7 @@ static int rows_to_factor(Context* c, hipStream_t st, ModeSVD& ms, int r, int N,
 // the root of the sum of M_l's r_l largest sigma^2, recorded after each sweep.
 static int run_als(Request* q, hipStream_t st, DevBuf cols[3], StageTimer& tm) {
     Context* c = q->ctx;
-    const Plan& P = q->plan;
+    const Plan& P = q->plan();
     int rc;
     const int* r = q->r;
     for (int l = 0; l < 3; ++l) {
@@ -353,7 +353,7 @@ static int run_als(Request* q, hipStream_t st, DevBuf cols[3], StageTimer& tm) {
 // RHOSVD of one request whose canonical factors are computed (q->U, q->ref ready on st).
 static int run_tucker(Request* q, hipStream_t st, const hipStream_t* aux, StageTimer& tm) {
     Context* c = q->ctx;
-    Plan& P = q->plan;
+    const Plan& P = q->plan();
     int rc;
     const double* G = q->rows();
     // (4) side matrices per mode: lattice sources and defect windows (unnormalised)
@@ -733,7 +733,7 @@ static int orthonormal_rows(Context* c, hipStream_t st, int D, int N, const doub
 // ------------------------------------------------------------------------------------------
 static int run_tucker_ref(Request* q, hipStream_t st, const hipStream_t* aux, StageTimer& tm) {
     Context* c = q->ctx;
-    const Plan& P = q->plan;
+    const Plan& P = q->plan();
     const int nb = (int)P.blocks.size();
     int rc;
     // (1)-(2) the reference's Tucker form (cached per kernel, quadrature, grid and eps): RHOSVD at
@@ -758,8 +758,10 @@ static int run_tucker_ref(Request* q, hipStream_t st, const hipStream_t* aux, St
         rp.eps = P.eps;
         rp.precision = LSUM_FP64;
         rp.als_sweeps = P.als_sweeps;
-        int rc1 = make_plan(rp, rq.plan);
+        auto rplan = std::make_shared<Plan>();
+        int rc1 = make_plan(rp, *rplan);
         if (rc1) return rc1;
+        rq.plan_sp = rplan;
         std::vector<Request*> rb{&rq};
         rc1 = run_batch(rb, st, aux);
         drop_reference(&rq);
@@ -1020,7 +1022,7 @@ int sample_canonical(Context* c, hipStream_t st, const std::vector<CanonSample>&
     std::vector<int> ldts;   // one group per (row stride, FP32 rows); FP32 groups as -ldt
     size_t n_blk = 0, n_win = 0;
     for (size_t k = 0; k < items.size(); ++k) {
-        const Plan& P = items[k].q->plan;
+        const Plan& P = items[k].q->plan();
         if (items[k].n <= 0) continue;
         const int key = P.rows_f32() ? -P.ldt : P.ldt;
         auto it = std::find(ldts.begin(), ldts.end(), key);
@@ -1051,7 +1053,7 @@ int sample_canonical(Context* c, hipStream_t st, const std::vector<CanonSample>&
         for (size_t k : grp) {
             const CanonSample& it = items[k];
             const Request* q = it.q;
-            const Plan& P = q->plan;
+            const Plan& P = q->plan();
             SampleJob j{};
             j.xyz = it.xyz;
             j.out = it.out;
@@ -1085,7 +1087,7 @@ int sample_canonical(Context* c, hipStream_t st, const std::vector<CanonSample>&
     }
     for (const auto& it : items) {
         const Request* q = it.q;
-        const Plan& P = q->plan;
+        const Plan& P = q->plan();
         if (it.n <= 0 || P.defects.empty()) continue;
         KTime k;
         if (kt && --wins_left == 0) k.stop = kt->stop;
@@ -1101,7 +1103,7 @@ int sample_canonical(Context* c, hipStream_t st, const std::vector<CanonSample>&
 
 int sample_points(Request* q, hipStream_t st, int n, const double* xyz_d, double* out_d, const KTime* kt) {
     Context* c = q->ctx;
-    const Plan& P = q->plan;
+    const Plan& P = q->plan();
     int rc;
     if (n <= 0) return LSUM_OK;
     if (!P.tucker()) return sample_canonical(c, st, {CanonSample{q, n, xyz_d, out_d}}, kt);
@@ -1205,7 +1207,7 @@ int sample_points(Request* q, hipStream_t st, int n, const double* xyz_d, double
 // context's row cache, built on st on a miss).
 static int offgrid_terms(Context* c, Request* q, hipStream_t st, std::map<int, std::vector<int2>>& out,
                          double* table_bytes) {
-    const Plan& P = q->plan;
+    const Plan& P = q->plan();
     const int nb = (int)P.blocks.size();
     const int C = (int)P.cls_f.size();
     const int64_t tab = (int64_t)P.R * P.ldg;
@@ -1291,10 +1293,10 @@ int run_batch(std::vector<Request*>& reqs, hipStream_t st, const hipStream_t* au
     Context* c = reqs[0]->ctx;
     StageTimer tm(st);
     int rc;
-    if (reqs.size() == 1 && reqs[0]->plan.tucker_ref()) return run_tucker_ref_batch(reqs[0], st, aux);
+    if (reqs.size() == 1 && reqs[0]->plan().tucker_ref()) return run_tucker_ref_batch(reqs[0], st, aux);
     // (1)-(2) quadrature is in the plan; reference vectors from the cache
     for (auto* q : reqs)
-        if ((rc = get_reference(c, q->plan, st, q->ref))) return rc;
+        if ((rc = get_reference(c, q->plan(), st, q->ref))) return rc;
 
     // (3) assembled shift-sums of every block and axis of every request: one launch.  Canonical
     // requests keep point-major factors (for sampling), reduction requests vector-major ones
@@ -1307,7 +1309,7 @@ int run_batch(std::vector<Request*>& reqs, hipStream_t st, const hipStream_t* au
     std::vector<const RefEntry*> distinct;
     std::vector<int2> tv;
     for (auto* q : reqs) {
-        Plan& P = q->plan;
+        const Plan& P = q->plan();
         const int nb = (int)P.blocks.size();
         const bool vector_major = P.tucker();
         // Axes with the same cell count and the same snapped sites in every block (a cubic lattice
@@ -1405,7 +1407,7 @@ int run_batch(std::vector<Request*>& reqs, hipStream_t st, const hipStream_t* au
 
     // defect tables (canonical sampling evaluates defect windows from the reference rows)
     for (auto* q : reqs) {
-        Plan& P = q->plan;
+        const Plan& P = q->plan();
         const int nd = (int)P.defects.size();
         if (nd == 0) continue;
         std::vector<int32_t> offs(3 * (size_t)nd);
@@ -1424,7 +1426,7 @@ int run_batch(std::vector<Request*>& reqs, hipStream_t st, const hipStream_t* au
 
     // (4)-(8) reduction requests
     for (auto* q : reqs) {
-        if (!q->plan.tucker()) continue;
+        if (!q->plan().tucker()) continue;
         rc = run_tucker(q, st, aux, tm);
         if (rc) {
             (void)hipStreamSynchronize(st);
@@ -1457,7 +1459,7 @@ int run_batch(std::vector<Request*>& reqs, hipStream_t st, const hipStream_t* au
             staged.push_back(std::move(xd));
             staged.push_back(std::move(od));
         }
-        const Plan& P = q->plan;
+        const Plan& P = q->plan();
         // factors read once (R values per distinct cell) + points in + values out
         double uN = 0;
         for (int l = 0; l < 3; ++l)

@@ -405,9 +405,9 @@ void worker(Context* c, int slot) {
             c->used += h->reserved;
             h->started = true;
             batch.push_back(h);
-            while (!h->plan.tucker() && (int)batch.size() < c->max_batch && !c->queue.empty()) {
+            while (!h->plan().tucker() && (int)batch.size() < c->max_batch && !c->queue.empty()) {
                 Request* n = c->queue.front();
-                if (n->plan.tucker() || !fits(c, n)) break;
+                if (n->plan().tucker() || !fits(c, n)) break;
                 c->queue.pop_front();
                 c->used += n->reserved;
                 n->started = true;

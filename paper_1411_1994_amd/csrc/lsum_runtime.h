@@ -171,7 +171,9 @@ struct Context {
 struct Request {
     std::shared_ptr<Context> ctx_ref;  // keeps the pool and streams alive until release
     Context* ctx = nullptr;
-    Plan plan;
+    // the plan, shared with the context's plan cache (immutable once made)
+    std::shared_ptr<const Plan> plan_sp;
+    const Plan& plan() const { return *plan_sp; }
     std::atomic<int> status{1};
     std::mutex mu;
     std::condition_variable cv;
@@ -195,7 +197,7 @@ struct Request {
     // exact sites off their cell centres: the request's row tables (the class rows, then the
     // window sums of its combs), R x ldg each with stride R * ldg, then t and w^(1/3)
     std::shared_ptr<RefEntry> tabs;
-    const double* rows() const { return plan.off_grid() ? tabs->G.as<double>() : ref->G.as<double>(); }
+    const double* rows() const { return plan().off_grid() ? tabs->G.as<double>() : ref->G.as<double>(); }
     // Tucker
     int r[3]{};
     std::vector<double> sigma[3];
