@@ -498,3 +498,20 @@ def test_tucker_to_canonical_exact_and_truncated():
         e = np.linalg.norm(O.cp_full(xi2, A2) - T)
         assert abs(e - err2) <= 1e-9 * np.linalg.norm(T) and err2 <= eps * np.linalg.norm(res.core)
         assert len(xi2) < len(xi) if eps == 1e-3 else len(xi2) <= len(xi)
+
+
+def test_shear_sites_and_explicit_charge_sum_pins():
+    # zero shear: the rectangular block itself; a shear moves each site by (k - (L-1)/2) shear
+    base = W.Block((4, 3, 2), (1.0, 0.7, 1.3), (0.2, -0.1, 0.4))
+    pos0 = O.shear_sites(base, 0, 1, 0.0)
+    rect, _ = O.charge_positions(W.Problem("r", 0, 0.0, 8, (5, 5, 5), 1.0, [base]))
+    assert np.array_equal(pos0, rect)
+    pos = O.shear_sites(base, 0, 1, 0.5)
+    k1 = np.repeat(np.tile(np.arange(3), 4), 2)           # the axis-1 index of each site (C order)
+    assert np.allclose(pos[:, 0] - rect[:, 0], (k1 - 1.0) * 0.5) and np.array_equal(pos[:, 1:], rect[:, 1:])
+    # the explicit-list sum over a block's own sites and charges is the block sum
+    blocks = [base, W.Block((2, 2, 2), (1.0, 1.0, 1.0), (1.5, 1.0, -1.0), charge=-0.5)]
+    p = W.Problem("e", W.NEWTON, 0.0, 24, (33, 33, 33), 0.25, blocks)
+    pts = np.stack([np.random.default_rng(12).integers(0, 33, 40) for _ in range(3)], axis=1)
+    posb, Z = O.charge_positions(p)
+    assert np.allclose(O.brute_force_points_at(p, pts, posb, Z), O.brute_force_points(p, pts), rtol=1e-13, atol=0)
