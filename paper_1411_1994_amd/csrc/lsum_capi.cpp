@@ -578,12 +578,17 @@ int lsum_get_stats(lsum_req r, char* buf, size_t len) {
         }
         o << "],\"t_ms\":{";
         bool first = true;
-        for (auto& kv : q.t_ms) {
+        static const std::map<std::string, double> none;
+        for (auto& kv : (q.t_ms ? *q.t_ms : none)) {
             o << (first ? "" : ",") << "\"" << kv.first << "\":" << kv.second;
             first = false;
         }
         o << "},\"bytes\":{";
         first = true;
+        if (q.canonical_bytes > 0) {
+            o << "\"canonical\":" << q.canonical_bytes;
+            first = false;
+        }
         for (auto& kv : q.bytes) {
             o << (first ? "" : ",") << "\"" << kv.first << "\":" << kv.second;
             first = false;

@@ -1282,7 +1282,7 @@ static int run_tucker_ref_batch(Request* q, hipStream_t st, const hipStream_t* a
     LSUM_HIP(hipStreamSynchronize(st));
     std::map<std::string, double> t;
     tm.collect(t, c);
-    q->t_ms = t;
+    q->t_ms = std::make_shared<const std::map<std::string, double>>(std::move(t));
     return LSUM_OK;
 }
 
@@ -1389,7 +1389,7 @@ int run_batch(std::vector<Request*>& reqs, hipStream_t st, const hipStream_t* au
             out_bytes += (double)P.R * uN * (vector_major ? 8 : P.row_elem());
         }
         if (std::find(distinct.begin(), distinct.end(), q->ref.get()) == distinct.end()) distinct.push_back(q->ref.get());
-        q->bytes["canonical"] = (double)nb * P.R * uN * (vector_major ? 8 : P.row_elem());
+        q->canonical_bytes = (double)nb * P.R * uN * (vector_major ? 8 : P.row_elem());
     }
     double ref_bytes = ref_extra;
     for (auto* e : distinct) ref_bytes += (double)e->R * (2 * e->N_ref - 1) * 8;
@@ -1494,7 +1494,8 @@ int run_batch(std::vector<Request*>& reqs, hipStream_t st, const hipStream_t* au
     LSUM_HIP(hipStreamSynchronize(st));
     std::map<std::string, double> t;
     tm.collect(t, c);
-    for (auto* q : reqs) q->t_ms = t;
+    auto shared_t = std::make_shared<const std::map<std::string, double>>(std::move(t));
+    for (auto* q : reqs) q->t_ms = shared_t;
     return LSUM_OK;
 }
 

@@ -211,7 +211,9 @@ struct Request {
     DevBuf Z[3];                       // r_l x N_l FP64
     DevBuf core;                       // r1 r2 r3, FP64 or FP32 (precision)
     DevBuf tile;
-    std::map<std::string, double> t_ms;
+    // stage times of the request's batch (shared by its requests) and result sizes by name
+    std::shared_ptr<const std::map<std::string, double>> t_ms;
+    double canonical_bytes = 0;
     std::map<std::string, double> bytes;
 };
 
