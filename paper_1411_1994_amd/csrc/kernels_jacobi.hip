@@ -5,10 +5,10 @@
 // One round is three wide launches:
 //   1. k_pair_gram:   16x16 Gram partials of every pair's 16 columns over chunks of 256 cells,
 //                     on v_mfma_f64_16x16x4 (grid: chunks x pairs);
-//   2. k_pair_eig:    per pair, the chunk partials are summed in a fixed order, the coupling
-//                     max |g_ij| / sqrt(g_ii g_jj) is measured and, unless the pair is already
-//                     orthogonal, two sweeps of cyclic two-sided Jacobi on the Gram run in one
-//                     wavefront (the outer sweeps converge as fast as with full inner solves);
+//   2. k_pair_eig:    per pair, the chunk partials are summed in a fixed order (256 threads), the
+//                     coupling max |g_ij| / sqrt(g_ii g_jj) is measured and, unless the pair is
+//                     already orthogonal, two sweeps of cyclic two-sided Jacobi on the Gram run in
+//                     one wavefront (the outer sweeps converge as fast as with full inner solves);
 //   3. k_pair_rotate: X_pair <- Q^T X_pair over the same chunks, again on MFMA.
 // Columns are never squared against each other globally, so singular values keep an absolute
 // accuracy of a few eps * sigma_max -- the RHOSVD threshold at eps = 1e-6 sits near 1e-8 sigma_1,
@@ -85,22 +85,62 @@ __device__ __forceinline__ bool coupled(double gaa, double gbb, double gab, doub
 __device__ __forceinline__ int inner_p(int t, int i) { return i == 0 ? 15 : (t + i >= 15 ? t + i - 15 : t + i); }
 __device__ __forceinline__ int inner_q(int t, int i) { return i == 0 ? t : (t - i < 0 ? t - i + 15 : t - i); }
 
-__global__ void __launch_bounds__(64) k_pair_eig(int nchunk, const double* __restrict__ part, double tol,
-                                                 double irr2, int max_inner, double* __restrict__ Qout,
-                                                 int* __restrict__ active, unsigned long long* __restrict__ stat) {
+// The rotation (c, s) that annihilates the coupling b of two columns with squared norms a and d,
+// and the squared relative coupling b^2 / (a d) it removes (0 for a pair that is left alone).
+__device__ __forceinline__ void rotation(double a, double d, double b, double irr2, double* c, double* s,
+                                         double* rel2) {
+    *c = 1.0;
+    *s = 0.0;
+    *rel2 = 0.0;
+    if (!coupled(a, d, b, irr2)) return;
+    // the coupling only steers decisions: an approximate reciprocal suffices
+    const double r2 = (b * b) * __builtin_amdgcn_rcp(a * d);
+    *rel2 = r2;
+    if (!(r2 > 1e-32)) return;
+    // tan of the angle that annihilates b: t = 2b / (z + sign(z) sqrt(z^2 + 4 b^2)), z = d - a (the
+    // smaller root, |t| <= 1).  t may be approximate (the rotation is then slightly short of
+    // optimal but still orthogonal); c = (1 + t^2)^(-1/2) is refined to full precision so that
+    // c^2 + s^2 = 1 to rounding.
+    const double z = d - a;
+    const double x = z * z + 4.0 * b * b;
+    const double r = x * __builtin_amdgcn_rsq(x);
+    const double t = 2.0 * b * __builtin_amdgcn_rcp(z >= 0.0 ? z + r : z - r);
+    const double u = 1.0 + t * t;
+    double y = __builtin_amdgcn_rsq(u);
+    y = y * (1.5 - 0.5 * u * y * y);
+    y = y * (1.5 - 0.5 * u * y * y);
+    *c = y;
+    *s = t * y;
+}
+
+constexpr int EIG_LOADS = 16;   // chunk partials in flight per thread
+
+// 256 threads sum the chunk partials (one Gram entry each); one wavefront then solves.
+__global__ void __launch_bounds__(256) k_pair_eig(int nchunk, const double* __restrict__ part, double tol,
+                                                  double irr2, int max_inner, double* __restrict__ Qout,
+                                                  int* __restrict__ active, unsigned long long* __restrict__ stat) {
     __shared__ double G[16][17];
     __shared__ double Q[16][17];
-    __shared__ double cs[8][2];
-    const int pair = blockIdx.x, lane = threadIdx.x;
-    const double* __restrict__ pp = part + (size_t)pair * nchunk * 256;
-    for (int e = lane; e < 256; e += 64) {
+    const int pair = blockIdx.x, tid = threadIdx.x;
+    {
+        // entry tid over the chunks in chunk order; the loads of a group are issued together so
+        // that the sum waits on one memory latency per EIG_LOADS chunks (indices past the last
+        // chunk repeat it and add 0)
+        const double* __restrict__ pp = part + (size_t)pair * nchunk * 256 + tid;
         double s = 0.0;
-        for (int c = 0; c < nchunk; ++c) s += pp[(size_t)c * 256 + e];
-        G[e >> 4][e & 15] = s;
-        Q[e >> 4][e & 15] = ((e >> 4) == (e & 15)) ? 1.0 : 0.0;
+        for (int c = 0; c < nchunk; c += EIG_LOADS) {
+            double v[EIG_LOADS];
+#pragma unroll
+            for (int k = 0; k < EIG_LOADS; ++k) v[k] = pp[(size_t)min(c + k, nchunk - 1) * 256];
+#pragma unroll
+            for (int k = 0; k < EIG_LOADS; ++k) s += c + k < nchunk ? v[k] : 0.0;
+        }
+        G[tid >> 4][tid & 15] = s;
+        Q[tid >> 4][tid & 15] = ((tid >> 4) == (tid & 15)) ? 1.0 : 0.0;
     }
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __syncthreads();
+    if (tid >= 64) return;   // the solve below uses wavefront barriers only
+    const int lane = tid;
     // coupling of relevant pairs (both squared norms above the irrelevance floor)
     double off = 0.0;
     for (int e = lane; e < 256; e += 64) {
@@ -121,7 +161,9 @@ __global__ void __launch_bounds__(64) k_pair_eig(int nchunk, const double* __res
     // Each step applies 8 disjoint rotations at once: G <- J^T G J, Q <- Q J.  With the step's
     // pairing, index i of pair (p, q) maps to alpha_i row_i + beta_i row_partner, (alpha, beta) =
     // (c, -s) for p and (c, s) for q; lane (bi, bj) owns the 2x2 blocks {p_bi, q_bi} x {p_bj, q_bj}
-    // of G and of Q, so it reads and writes only its own entries.
+    // of G and of Q, so it writes only its own entries.  It computes the rotations of pairs bi and
+    // bj itself from the step's entering G (the same values on every lane that needs them): all
+    // reads of a step precede its writes in the wavefront's program order.
     const int bi = lane >> 3, bj = lane & 7;
     double prev = 2.0;
     int nsw = 0;
@@ -129,39 +171,12 @@ __global__ void __launch_bounds__(64) k_pair_eig(int nchunk, const double* __res
         nsw = sw + 1;
         double mx = 0.0;
         for (int step = 0; step < 15; ++step) {
-            if (lane < 8) {
-                const int p = inner_p(step, lane), q = inner_q(step, lane);
-                const double a = G[p][p], d = G[q][q], b = G[p][q];
-                double c = 1.0, s = 0.0;
-                if (coupled(a, d, b, irr2)) {
-                    // the coupling only steers decisions: an approximate reciprocal suffices
-                    const double rel2 = (b * b) * __builtin_amdgcn_rcp(a * d);
-                    mx = fmax(mx, rel2);
-                    if (rel2 > 1e-32) {
-                        // tan of the angle that annihilates b: t = 2b / (z + sign(z) sqrt(z^2 + 4 b^2)),
-                        // z = d - a (the smaller root, |t| <= 1).  t may be approximate (the rotation
-                        // is then slightly short of optimal but still orthogonal); c = (1 + t^2)^(-1/2)
-                        // is refined to full precision so that c^2 + s^2 = 1 to rounding.
-                        const double z = d - a;
-                        const double x = z * z + 4.0 * b * b;
-                        const double r = x * __builtin_amdgcn_rsq(x);
-                        const double t = 2.0 * b * __builtin_amdgcn_rcp(z >= 0.0 ? z + r : z - r);
-                        const double u = 1.0 + t * t;
-                        double y = __builtin_amdgcn_rsq(u);
-                        y = y * (1.5 - 0.5 * u * y * y);
-                        y = y * (1.5 - 0.5 * u * y * y);
-                        c = y;
-                        s = t * y;
-                    }
-                }
-                cs[lane][0] = c;
-                cs[lane][1] = s;
-            }
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             const int pi = inner_p(step, bi), qi = inner_q(step, bi);
             const int pj = inner_p(step, bj), qj = inner_q(step, bj);
-            const double ci = cs[bi][0], si = cs[bi][1], cj = cs[bj][0], sj = cs[bj][1];
+            double ci, si, cj, sj, ri, rj;
+            rotation(G[pi][pi], G[qi][qi], G[pi][qi], irr2, &ci, &si, &ri);
+            rotation(G[pj][pj], G[qj][qj], G[pj][qj], irr2, &cj, &sj, &rj);
+            mx = fmax(mx, ri);
             // G block [pi qi] x [pj qj]
             const double g00 = G[pi][pj], g01 = G[pi][qj], g10 = G[qi][pj], g11 = G[qi][qj];
             // rows: J^T
@@ -379,7 +394,7 @@ int jacobi_svd(hipStream_t st, int D, int N, double* A, int lda, double tol, dou
         for (int round = 0; round < nblk - 1; ++round) {
             hipLaunchKernelGGL(k_pair_gram, dim3(L.nchunk, npair), dim3(256), 0, st, X, L.ldx, n_gram, nblk,
                                round, L.nchunk, part);
-            hipLaunchKernelGGL(k_pair_eig, dim3(npair), dim3(64), 0, st, L.nchunk, part, tol, irr2, max_inner, Qd,
+            hipLaunchKernelGGL(k_pair_eig, dim3(npair), dim3(256), 0, st, L.nchunk, part, tol, irr2, max_inner, Qd,
                                act, stat);
             hipLaunchKernelGGL(k_pair_rotate, dim3(L.nchunk_all, npair), dim3(256), 0, st, X, L.ldx, nblk, round,
                                Qd, act);
