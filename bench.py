@@ -478,11 +478,13 @@ def per_precision(L, W, problem, xyz):
             raise RuntimeError(f"{name} request failed")
         prof = ctx.profile()
         vals = r.tile().astype(np.float64) if problem.tile_T[0] > 0 else r.values.copy()
+        st = r.stats()
+        svd = {"ranks": list(r.info().r), "range_basis": st["range_k"], "jacobi_sweeps": st["sweeps"]}
         r.release()
         ctx.close()
         if ref is None:
             ref = vals
-        entry = {"max_rel_dev_vs_f64": float(np.max(np.abs(vals - ref)) / np.max(np.abs(ref)))}
+        entry = {"max_rel_dev_vs_f64": float(np.max(np.abs(vals - ref)) / np.max(np.abs(ref))), "svd": svd}
         peak = PEAK_TFLOPS[name]
         for stage in ("core", "tile", "projection"):
             if stage in prof and prof[stage]["ms"] > 0:

@@ -213,11 +213,18 @@ const char* lsum_last_error(void);
  * LSUM_OPT_REF_CACHE_BYTES (default 4 GiB): HBM kept for reference vectors shared by requests
  * with the same kernel, quadrature and grid (0: every request recomputes its own).
  * LSUM_OPT_RANGE_MIN (default 512): side matrices with min(D, N) at least this large are
- * compressed to a randomized range basis before the Jacobi SVD (the residual outside the basis
- * is computed exactly and enters the certified tail); 0 disables the compression. */
+ * compressed to a randomized range basis, grown in blocks of 256 vectors up to min(D, N) / 2,
+ * before the Jacobi SVD (the residual outside the basis
+ * is computed exactly and enters the certified tail); 0 disables the compression.
+ * LSUM_OPT_JACOBI_STOP (default 1): the Jacobi SVD of a side matrix (Def. def:RHOSVD) ends as
+ * soon as the certified truncation rank is the same after two sweeps and the rows kept for it
+ * are orthogonal; the reported sigma beyond that rank are then row norms whose squared sum
+ * bounds the true tail from above (the error bound of Thm thm:C2Tucker (d) still holds).  0: sweep to
+ * full convergence, every sigma a singular value to the Jacobi tolerance. */
 #define LSUM_OPT_MAX_BATCH 1
 #define LSUM_OPT_REF_CACHE_BYTES 2
 #define LSUM_OPT_RANGE_MIN 3
+#define LSUM_OPT_JACOBI_STOP 4
 int lsum_set_option(lsum_ctx ctx, int key, double value);
 /* Per stage (collocate, shift_sum, transpose, columns, norm, svd, projection, core, tile,
  * sample): summed event-timed GPU milliseconds, number of timed launches, and the algorithmic

@@ -116,8 +116,11 @@ __device__ __forceinline__ void rotation(double a, double d, double b, double ir
 constexpr int EIG_LOADS = 16;   // chunk partials in flight per thread
 
 // 256 threads sum the chunk partials (one Gram entry each); one wavefront then solves.
+// Besides the coupling of the pair (stat[0]) it records the largest coupling among columns whose
+// squared norms both exceed keep2 (stat[4]).
 __global__ void __launch_bounds__(256) k_pair_eig(int nchunk, const double* __restrict__ part, double tol,
-                                                  double irr2, int max_inner, double* __restrict__ Qout,
+                                                  double irr2, double keep2, int max_inner,
+                                                  double* __restrict__ Qout,
                                                   int* __restrict__ active, unsigned long long* __restrict__ stat) {
     __shared__ double G[16][17];
     __shared__ double Q[16][17];
@@ -142,19 +145,28 @@ __global__ void __launch_bounds__(256) k_pair_eig(int nchunk, const double* __re
     if (tid >= 64) return;   // the solve below uses wavefront barriers only
     const int lane = tid;
     // coupling of relevant pairs (both squared norms above the irrelevance floor)
-    double off = 0.0;
+    double off = 0.0, offk = 0.0;
     for (int e = lane; e < 256; e += 64) {
         const int a = e >> 4, b = e & 15;
         if (a < b) {
             const double gaa = G[a][a], gbb = G[b][b];
-            if (coupled(gaa, gbb, G[a][b], irr2)) off = fmax(off, fabs(G[a][b]) / sqrt(gaa * gbb));
+            if (coupled(gaa, gbb, G[a][b], irr2)) {
+                const double cab = fabs(G[a][b]) / sqrt(gaa * gbb);
+                off = fmax(off, cab);
+                if (gaa > keep2 && gbb > keep2) offk = fmax(offk, cab);
+            }
         }
     }
-    for (int m = 32; m > 0; m >>= 1) off = fmax(off, __shfl_xor(off, m));
+    for (int m = 32; m > 0; m >>= 1) {
+        off = fmax(off, __shfl_xor(off, m));
+        offk = fmax(offk, __shfl_xor(offk, m));
+    }
     if (lane == 0) {
         unsigned long long bits;
         std::memcpy(&bits, &off, sizeof(bits));
         atomicMax(stat, bits);   // non-negative doubles order like their bit patterns
+        std::memcpy(&bits, &offk, sizeof(bits));
+        atomicMax(stat + 4, bits);
         active[pair] = off > tol ? 1 : 0;
     }
     if (!(off > tol)) return;
@@ -352,7 +364,8 @@ static int sorted_norms(hipStream_t st, const JacobiLayout& L, int n_gram, doubl
 }
 
 int jacobi_svd(hipStream_t st, int D, int N, double* A, int lda, double tol, double irrelevant, int max_sweeps,
-               std::vector<double>& sigma, int* sweeps_out, double* work_dev, size_t work_bytes, int n_gram) {
+               std::vector<double>& sigma, int* sweeps_out, double* work_dev, size_t work_bytes, int n_gram,
+               double stop_tail2) {
     if (n_gram <= 0 || n_gram > N) n_gram = N;
     if (D <= 0 || N <= 0) return fail(LSUM_E_INVALID, "empty side matrix");
     const JacobiLayout L = layout(D, N, n_gram);
@@ -380,6 +393,10 @@ int jacobi_svd(hipStream_t st, int D, int N, double* A, int lda, double tol, dou
     constexpr int max_inner = 2;
     int sweeps = 0;
     bool converged = false;
+    // rank stop: the certified rank of the current rows, and the squared norm above which rows
+    // count as kept (the rank plus a margin of max(16, r/8) rows; 0: every row)
+    int r_prev = -1;
+    double keep2 = 0.0;
     for (; sweeps < max_sweeps && !converged; ++sweeps) {
         // only columns above the floor take part (sorted first); the rest are never rotated
         int d_act = 0;
@@ -390,25 +407,48 @@ int jacobi_svd(hipStream_t st, int D, int N, double* A, int lda, double tol, dou
         hipLaunchKernelGGL(k_permute_rows, dim3(cdiv(L.ldx, 256), L.Dp), dim3(256), 0, st, L.ldx, perm_dev, X, X2,
                            L.ldx, L.ldx);
         std::swap(X, X2);
-        LSUM_HIP(hipMemsetAsync(stat, 0, 4 * sizeof(unsigned long long), st));
+        LSUM_HIP(hipMemsetAsync(stat, 0, 5 * sizeof(unsigned long long), st));
         for (int round = 0; round < nblk - 1; ++round) {
             hipLaunchKernelGGL(k_pair_gram, dim3(L.nchunk, npair), dim3(256), 0, st, X, L.ldx, n_gram, nblk,
                                round, L.nchunk, part);
-            hipLaunchKernelGGL(k_pair_eig, dim3(npair), dim3(256), 0, st, L.nchunk, part, tol, irr2, max_inner, Qd,
-                               act, stat);
+            hipLaunchKernelGGL(k_pair_eig, dim3(npair), dim3(256), 0, st, L.nchunk, part, tol, irr2, keep2,
+                               max_inner, Qd, act, stat);
             hipLaunchKernelGGL(k_pair_rotate, dim3(L.nchunk_all, npair), dim3(256), 0, st, X, L.ldx, nblk, round,
                                Qd, act);
         }
-        unsigned long long st4[4] = {0, 0, 0, 0};
+        unsigned long long st4[5] = {0, 0, 0, 0, 0};
         LSUM_HIP(hipMemcpyAsync(st4, stat, sizeof(st4), hipMemcpyDeviceToHost, st));
         rc = sorted_norms(st, L, n_gram, X, base, sig2, perm);   // synchronises
         if (rc) return rc;
-        double off;
+        double off, offk;
         std::memcpy(&off, &st4[0], sizeof(off));
-        if (trace)
-            std::fprintf(stderr, "jacobi D=%d N=%d sweep %d active %d max coupling %.3e inner sweeps %.2f avg %llu max over %llu pairs\n",
-                         D, N, sweeps, d_act, off, st4[3] ? (double)st4[1] / (double)st4[3] : 0.0, st4[2], st4[3]);
+        std::memcpy(&offk, &st4[4], sizeof(offk));
         if (off <= tol) converged = true;
+        int r_now = -1;
+        if (stop_tail2 > 0.0 && !converged) {
+            // The rows stay an orthogonal transform of the input, so for any r the projection on
+            // the span of the r largest rows leaves at most the energy of the other rows: that
+            // tail is certified in every sweep, and the sweeps that follow only tighten it.  Stop
+            // once the smallest certified r is the same as after the previous sweep and the rows
+            // that were kept in this sweep (r + margin) were orthogonal to tol when visited: the
+            // kept rows then normalise to an orthonormal basis, and the remaining sweeps would only
+            // rotate rows of the tail against each other and against the basis.
+            double t = 0.0;
+            r_now = L.Dp;
+            for (int k = L.Dp - 1; k >= 0; --k) {
+                t += sig2[perm[k]];
+                if (t > stop_tail2) break;
+                r_now = k;
+            }
+            if (r_now == r_prev && offk <= tol) converged = true;
+            r_prev = r_now;
+            const int m = r_now + std::max(16, r_now / 8);
+            keep2 = m < L.Dp ? sig2[perm[m]] : 0.0;
+        }
+        if (trace)
+            std::fprintf(stderr, "jacobi D=%d N=%d sweep %d active %d max coupling %.3e kept %.3e rank %d inner sweeps %.2f avg %llu max over %llu pairs\n",
+                         D, N, sweeps, d_act, off, offk, r_now, st4[3] ? (double)st4[1] / (double)st4[3] : 0.0, st4[2],
+                         st4[3]);
     }
     LSUM_HIP(hipGetLastError());
     // write back the D largest columns in descending order

@@ -672,6 +672,10 @@ int lsum_set_option(lsum_ctx x, int key, double value) {
             if (!(value >= 0 && value <= 1e9)) return fail(LSUM_E_INVALID, "range threshold out of range");
             c.range_min = (int)value;
             return LSUM_OK;
+        case LSUM_OPT_JACOBI_STOP:
+            if (!(value == 0 || value == 1)) return fail(LSUM_E_INVALID, "Jacobi stop rule must be 0 or 1");
+            c.jacobi_rank_stop = value == 1;
+            return LSUM_OK;
         default:
             return fail(LSUM_E_INVALID, "unknown option");
     }

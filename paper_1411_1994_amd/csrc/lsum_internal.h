@@ -266,10 +266,13 @@ void launch_cp_norm2(hipStream_t st, int R, int n_groups, const int32_t* src1, c
 // `irrelevant` are not rotated (such rows cannot move a certified tail).  With n_gram < N only
 // the first n_gram entries of each row define the Gram matrix, the norms and the convergence;
 // the remaining entries are companion data rotated along (they receive the same orthogonal
-// transformation).
+// transformation).  With stop_tail2 > 0 the sweeps also end once the smallest r whose tail
+// (sum of the squared norms of rows r, r+1, ...) is at most stop_tail2 repeats between two
+// sweeps and the r largest rows (plus a margin) are orthogonal to tol; the norms of the tail
+// rows are then bounds, not singular values (their squared sum bounds the true tail from above).
 int jacobi_svd(hipStream_t st, int D, int N, double* A, int lda, double tol, double irrelevant,
                int max_sweeps, std::vector<double>& sigma, int* sweeps_out, double* work_dev,
-               size_t work_bytes, int n_gram = 0);
+               size_t work_bytes, int n_gram = 0, double stop_tail2 = 0.0);
 size_t jacobi_work_bytes(int D, int N);
 // out[i] = +-1, i < n, a deterministic function of (seed, i)
 void launch_random_signs(hipStream_t st, long n, unsigned long long seed, double* out);

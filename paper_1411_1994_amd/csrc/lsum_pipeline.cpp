@@ -22,11 +22,12 @@ static GemmPrec gemm_prec(int precision) {
 // result is a list of singular values and rows holding the matching left singular vectors,
 // such that for every r, ||A - Z_r Z_r^T A||_F^2 <= res2 + sum_{a >= r} sigma_a^2.
 //  * direct: one-sided Jacobi on W itself (res2 = 0; rows = rotated W, sigma-scaled);
-//  * range basis, for min(D, N) >= range_min: Y = Omega^T W with k random-sign columns, its k
-//    rows orthonormalised by Jacobi (Q), B = Q W^T, and the residual E = W - B^T Q computed
-//    explicitly (res2 = ||E||_F^2, which must stay below (thr/10)^2, else the direct solve runs); then
-//    Jacobi on the k rows [B | Q] with the Gram taken over B only, so the rotated Q part holds
-//    orthonormal vectors and ||A - Z_r Z_r^T A||^2 = res2 + sum_{a >= r} sigma_a^2 exactly.
+//  * range basis, for min(D, N) >= range_min: an orthonormal basis Q of k <= min(D, N) / 2 rows
+//    grown in blocks of random-sign sketches of the residual, B = Q W^T, and the residual
+//    E = W - B^T Q computed explicitly (res2 = ||E||_F^2, which must stay below (thr/10)^2, else
+//    the direct solve runs); then Jacobi on the k rows [B | Q] with the Gram taken over B only, so
+//    the rotated Q part holds orthonormal vectors and ||A - Z_r Z_r^T A||^2 = res2 +
+//    sum_{a >= r} sigma_a^2 exactly.
 // A GEMM launch that splits a long FP64 reduction over many workgroups when the output has few
 // tiles (Grams of a few tens of columns over N_l cells, projections onto a few tens of vectors):
 // one tile would otherwise walk all N_l terms alone.  Synchronous when split (the workspace goes
@@ -56,74 +57,114 @@ struct ModeSVD {
     int k = 0, sweeps = 0;
 };
 
-static int range_svd(Context* c, hipStream_t st, int D, int N, const double* W, int k, double thr,
-                     double irrelevant, ModeSVD& out, bool* enough) {
+// C (m x n) = alpha * X Y + beta * C over row-major operands; tX / tY: use the transpose.
+static void gemm_rm(hipStream_t st, int m, int n, int k, const double* X, long ldx, bool tX, const double* Y,
+                    long ldy, bool tY, double* C, long ldc, double alpha, double beta) {
+    GemmArgs a{};
+    a.m = m; a.n = n; a.k = k;
+    a.A = X; a.sam = tX ? 1 : ldx; a.sak = tX ? ldx : 1;
+    a.B = Y; a.sbk = tY ? 1 : ldy; a.sbn = tY ? ldy : 1;
+    a.C = C; a.scm = ldc; a.scn = 1;
+    a.alpha = alpha; a.beta = beta; a.batch = 1;
+    launch_gemm(st, GEMM_F64, a);
+}
+
+// Squared Frobenius norm of a rows x n row-major matrix (synchronises st).
+static int frob2(Context* c, hipStream_t st, int rows, int n, const double* X, double* out) {
+    DevBuf nrm;
+    int rc = nrm.get(c->pool, (size_t)rows * 8);
+    if (rc) return rc;
+    launch_row_norms(st, rows, n, X, n, nrm.as<double>());
+    std::vector<double> en(rows);
+    LSUM_HIP(hipMemcpyAsync(en.data(), nrm.p, (size_t)rows * 8, hipMemcpyDeviceToHost, st));
+    LSUM_HIP(hipStreamSynchronize(st));
+    double s = 0.0;
+    for (double v : en) s += v * v;
+    *out = s;
+    return LSUM_OK;
+}
+
+// Range basis grown in blocks (a blocked form of the adaptive randomized range finder): each
+// block sketches the current residual E (Y = Omega^T E, random signs), is orthogonalised twice
+// against the basis so far and orthonormalised by Jacobi; E loses the block's directions, and
+// the growth stops once ||E||_F <= thr / 10 or the basis would exceed k_max rows.  The first
+// block keeps every sketch row above 1e-12 of its largest; later blocks keep rows above 1e-2 of
+// theirs, so that the rounding left by the re-orthogonalisation stays at the Jacobi tolerance
+// relative to every kept row.  B = Q W^T and E = W - B^T Q are then recomputed from W, and
+// Jacobi on the rows [B | Q] (Gram over B) gives the singular vectors.
+static int range_svd(Context* c, hipStream_t st, int D, int N, const double* W, int k_block, int k_max,
+                     double thr, double irrelevant, ModeSVD& out, bool* enough) {
     int rc;
     *enough = false;
-    DevBuf Om, Yt, work;
-    if ((rc = Om.get(c->pool, (size_t)D * k * 8))) return rc;
-    if ((rc = Yt.get(c->pool, (size_t)k * N * 8))) return rc;
-    launch_random_signs(st, (long)D * k, 0x5eed1411ull + (unsigned long long)k, Om.as<double>());
-    GemmArgs a{};
-    // Yt (k x N) = Omega^T W
-    a.m = k; a.n = N; a.k = D;
-    a.A = Om.p; a.sam = 1; a.sak = k;
-    a.B = W; a.sbk = N; a.sbn = 1;
-    a.C = Yt.p; a.scm = N; a.scn = 1;
-    a.alpha = 1.0; a.beta = 0.0; a.batch = 1;
-    launch_gemm(st, GEMM_F64, a);
-    size_t wb = jacobi_work_bytes(k, N);
-    if ((rc = work.get(c->pool, wb))) return rc;
-    std::vector<double> sy;
-    int sw = 0;
-    rc = jacobi_svd(st, k, N, Yt.as<double>(), N, 1e-12, 0.0, 40, sy, &sw, work.as<double>(), wb);
-    if (rc) return rc;
-    Om.reset();   // the sketch GEMM has run (jacobi_svd synchronises st)
-    int kq = 0;
-    while (kq < k && sy[kq] > 1e-12 * sy[0]) ++kq;
-    if (kq == 0) return LSUM_OK;
-    // AUG rows [B_a | Q_a], Q_a = Yt_a / sigma_a
-    const long ld = (long)D + N;
-    DevBuf AUG, iv, E, nrm;
-    if ((rc = AUG.get(c->pool, (size_t)kq * ld * 8))) return rc;
-    std::vector<double> inv(kq);
-    for (int i = 0; i < kq; ++i) inv[i] = 1.0 / sy[i];
-    if ((rc = iv.get(c->pool, kq * 8))) return rc;
-    LSUM_HIP(hipMemcpyAsync(iv.p, inv.data(), kq * 8, hipMemcpyHostToDevice, st));
-    launch_scale_rows(st, kq, N, Yt.as<double>(), N, iv.as<double>(), AUG.as<double>() + D, ld);
-    // B (kq x D) = Q W^T into the first D entries of each AUG row
-    a = GemmArgs{};
-    a.m = kq; a.n = D; a.k = N;
-    a.A = AUG.as<double>() + D; a.sam = ld; a.sak = 1;
-    a.B = W; a.sbk = 1; a.sbn = N;
-    a.C = AUG.p; a.scm = ld; a.scn = 1;
-    a.alpha = 1.0; a.beta = 0.0; a.batch = 1;
-    launch_gemm(st, GEMM_F64, a);
-    // E = W - B^T Q and its squared Frobenius norm
+    if (k_block < 16 || k_max < k_block) return LSUM_OK;
+    DevBuf Qall, E, Om, Yt, P, work;
+    if ((rc = Qall.get(c->pool, (size_t)k_max * N * 8))) return rc;
     if ((rc = E.get(c->pool, (size_t)D * N * 8))) return rc;
-    if ((rc = nrm.get(c->pool, (size_t)D * 8))) return rc;
+    if ((rc = Om.get(c->pool, (size_t)D * k_block * 8))) return rc;
+    if ((rc = Yt.get(c->pool, (size_t)k_block * N * 8))) return rc;
+    if ((rc = P.get(c->pool, (size_t)std::max(D, k_block) * k_max * 8))) return rc;
+    const size_t wb = jacobi_work_bytes(k_block, N);
+    if ((rc = work.get(c->pool, wb))) return rc;
     LSUM_HIP(hipMemcpyAsync(E.p, W, (size_t)D * N * 8, hipMemcpyDeviceToDevice, st));
-    a = GemmArgs{};
-    a.m = D; a.n = N; a.k = kq;
-    a.A = AUG.p; a.sam = 1; a.sak = ld;
-    a.B = AUG.as<double>() + D; a.sbk = ld; a.sbn = 1;
-    a.C = E.p; a.scm = N; a.scn = 1;
-    a.alpha = -1.0; a.beta = 1.0; a.batch = 1;
-    launch_gemm(st, GEMM_F64, a);
-    launch_row_norms(st, D, N, E.as<double>(), N, nrm.as<double>());
-    std::vector<double> en(D);
-    LSUM_HIP(hipMemcpyAsync(en.data(), nrm.p, D * 8, hipMemcpyDeviceToHost, st));
-    LSUM_HIP(hipStreamSynchronize(st));
+    double* Q = Qall.as<double>();
+    int kq = 0, blocks = 0;
     double res2 = 0.0;
-    for (double v : en) res2 += v * v;
+    for (;;) {
+        const int kb = std::min(k_block, k_max - kq);
+        if (kb < 16) return LSUM_OK;   // the basis would grow past k_max
+        launch_random_signs(st, (long)D * kb, 0x5eed1411ull + 7919ull * (unsigned long long)blocks + (unsigned long long)kb,
+                            Om.as<double>());
+        // Yt (kb x N) = Omega^T E
+        gemm_rm(st, kb, N, D, Om.as<double>(), kb, true, E.as<double>(), N, false, Yt.as<double>(), N, 1.0, 0.0);
+        for (int pass = 0; kq > 0 && pass < 2; ++pass) {
+            // Yt -= (Yt Q^T) Q
+            gemm_rm(st, kb, kq, N, Yt.as<double>(), N, false, Q, N, true, P.as<double>(), kq, 1.0, 0.0);
+            gemm_rm(st, kb, N, kq, P.as<double>(), kq, false, Q, N, false, Yt.as<double>(), N, -1.0, 1.0);
+        }
+        std::vector<double> sy;
+        int sw = 0;
+        if ((rc = jacobi_svd(st, kb, N, Yt.as<double>(), N, 1e-12, 0.0, 40, sy, &sw, work.as<double>(), wb))) return rc;
+        const double keep_rel = blocks == 0 ? 1e-12 : 1e-2;
+        int keep = 0;
+        while (keep < kb && sy[keep] > keep_rel * sy[0]) ++keep;
+        if (keep == 0) return LSUM_OK;
+        std::vector<double> inv(keep);
+        for (int i = 0; i < keep; ++i) inv[i] = 1.0 / sy[i];
+        DevBuf iv;
+        if ((rc = iv.get(c->pool, (size_t)keep * 8))) return rc;
+        LSUM_HIP(hipMemcpyAsync(iv.p, inv.data(), (size_t)keep * 8, hipMemcpyHostToDevice, st));
+        double* Qb = Q + (size_t)kq * N;
+        launch_scale_rows(st, keep, N, Yt.as<double>(), N, iv.as<double>(), Qb, N);
+        // E -= (E Qb^T) Qb
+        gemm_rm(st, D, keep, N, E.as<double>(), N, false, Qb, N, true, P.as<double>(), keep, 1.0, 0.0);
+        gemm_rm(st, D, N, keep, P.as<double>(), keep, false, Qb, N, false, E.as<double>(), N, -1.0, 1.0);
+        kq += keep;
+        ++blocks;
+        if ((rc = frob2(c, st, D, N, E.as<double>(), &res2))) return rc;   // synchronises (iv may go)
+        if (std::sqrt(res2) <= 0.1 * thr) break;
+    }
+    Om.reset();
+    Yt.reset();
+    P.reset();
+    work.reset();
+    // AUG rows [B_a | Q_a]: B (kq x D) = Q W^T, and the exact residual E = W - B^T Q
+    const long ld = (long)D + N;
+    DevBuf AUG;
+    if ((rc = AUG.get(c->pool, (size_t)kq * ld * 8))) return rc;
+    LSUM_HIP(hipMemcpy2DAsync(AUG.as<double>() + D, ld * 8, Q, (size_t)N * 8, (size_t)N * 8, kq,
+                              hipMemcpyDeviceToDevice, st));
+    gemm_rm(st, kq, D, N, Q, N, false, W, N, true, AUG.as<double>(), ld, 1.0, 0.0);
+    LSUM_HIP(hipMemcpyAsync(E.p, W, (size_t)D * N * 8, hipMemcpyDeviceToDevice, st));
+    gemm_rm(st, D, N, kq, AUG.as<double>(), ld, true, AUG.as<double>() + D, ld, false, E.as<double>(), N, -1.0, 1.0);
+    if ((rc = frob2(c, st, D, N, E.as<double>(), &res2))) return rc;
     if (!(std::sqrt(res2) <= 0.1 * thr)) return LSUM_OK;   // basis too small
     E.reset();
-    Yt.reset();
-    work.reset();
-    wb = jacobi_work_bytes(kq, (int)ld);
-    if ((rc = work.get(c->pool, wb))) return rc;
+    Qall.reset();
+    const size_t wb2 = jacobi_work_bytes(kq, (int)ld);
+    if ((rc = work.get(c->pool, wb2))) return rc;
+    // the rotated Q rows stay orthonormal in any sweep, so the rank stop needs no extra step here
     rc = jacobi_svd(st, kq, (int)ld, AUG.as<double>(), (int)ld, 1e-12, irrelevant, 40, out.sigma, &out.sweeps,
-                    work.as<double>(), wb, D);
+                    work.as<double>(), wb2, D, c->jacobi_rank_stop ? thr * thr - res2 : 0.0);
     if (rc) return rc;
     out.res2 = res2;
     out.rows = std::move(AUG);
@@ -141,18 +182,19 @@ static int mode_svd(Context* c, hipStream_t st, int D, int N, DevBuf& W, double 
     const int mn = std::min(D, N);
     const int range_min = allow_range ? c->range_min : 0;
     if (range_min > 0 && mn >= range_min) {
-        // one basis of 256 vectors: it wins when the certified rank is well below min(D, N); when
-        // it is not enough (a few percent of a direct solve) the direct solve follows
-        const int k = std::min(256, mn / 2);
+        // a basis grown in blocks of 256 vectors up to min(D, N) / 2: it wins when the certified
+        // rank is below about half of min(D, N); past that the direct solve follows
+        const int k_max = mn / 2;
+        const int k_block = std::min(256, k_max);
         bool enough = false;
-        if ((rc = range_svd(c, st, D, N, W.as<double>(), k, thr, irrelevant, out, &enough))) return rc;
+        if ((rc = range_svd(c, st, D, N, W.as<double>(), k_block, k_max, thr, irrelevant, out, &enough))) return rc;
         if (enough) return LSUM_OK;
     }
     DevBuf work;
     const size_t wb = jacobi_work_bytes(D, N);
     if ((rc = work.get(c->pool, wb))) return rc;
     rc = jacobi_svd(st, D, N, W.as<double>(), N, 1e-12, irrelevant, 40, out.sigma, &out.sweeps, work.as<double>(),
-                    wb);
+                    wb, 0, c->jacobi_rank_stop ? thr * thr : 0.0);
     if (rc) return rc;
     out.res2 = 0.0;
     out.rows = std::move(W);

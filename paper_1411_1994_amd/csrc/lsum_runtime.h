@@ -142,6 +142,7 @@ struct Context {
     int n_slots = 0;
     int max_batch = 32;              // canonical requests fused into one batch
     int range_min = 512;             // min(D, N) from which side matrices use the range basis
+    bool jacobi_rank_stop = true;    // Jacobi SVDs of side matrices end once the certified rank is settled
     std::vector<hipStream_t> streams;
     std::vector<hipStream_t> aux;    // three per slot: the per-mode SVDs of a request run concurrently
     std::vector<std::thread> workers;

@@ -259,13 +259,23 @@ def _medium_defected(seed=11, eps=1e-2):
     return W.Problem("med", W.NEWTON, 0.0, 24, (601, 601, 601), 1.0 / 15, blocks, defects, eps=eps)
 
 
-def test_range_basis_svd_matches_direct_jacobi():
+def _large_defected(seed=12, eps=1e-2):
+    # D ~ 900-990 distinct columns, N = 1025, certified ranks 344-366 (oracle): above one block
+    # of 256 basis vectors and below min(D, N) / 2, so the range basis grows over two blocks
+    rng = np.random.default_rng(seed)
+    blocks = [W.Block((40, 40, 40), (1.0, 1.0, 1.0), (0.0, 0.0, 0.0))]
+    defects = W.draw_defects(rng, blocks, 60, 30)
+    return W.Problem("large", W.NEWTON, 0.0, 24, (1025, 1025, 1025), 56.0 / 1024, blocks, defects, eps=eps)
+
+
+@pytest.mark.parametrize("problem", ["medium", "large"])
+def test_range_basis_svd_matches_direct_jacobi(problem):
     # the randomized range basis (large side matrices) against the plain one-sided Jacobi on the
     # same request: same leading singular values, certified bounds, orthonormal factors, and
     # potentials that agree with each other and with the oracle's direct sum
     require_gpu()
     import paper_1411_1994_amd as L
-    p = _medium_defected()
+    p = _medium_defected() if problem == "medium" else _large_defected()
     out = {}
     for name, rmin in (("range", 512), ("direct", 0)):
         with L.Context(0, n_slots=1) as c:
@@ -279,7 +289,9 @@ def test_range_basis_svd_matches_direct_jacobi():
             out[name] = dict(inf=inf, st=st, sig=r.sigma(), Z=Z, v=r.sample(cells_xyz(p, cells)), cells=cells)
             r.release()
     a, b = out["range"], out["direct"]
-    assert max(a["st"]["range_k"]) > 0 and max(b["st"]["range_k"]) == 0
+    assert max(a["st"]["range_k"]) > 0 and max(b["st"]["range_k"]) == 0, (a["st"]["range_k"], a["inf"].r, a["inf"].D)
+    if problem == "large":
+        assert min(a["st"]["range_k"]) > 256 and min(b["inf"].r) > 256, (a["st"]["range_k"], b["inf"].r)
     nA = a["inf"].norm_A
     thr = p.eps * nA / (3 * a["inf"].norm_xi)
     for o in (a, b):
@@ -301,6 +313,48 @@ def test_range_basis_svd_matches_direct_jacobi():
     ref = O.brute_force_points(p, a["cells"])
     assert np.max(np.abs(a["v"] - ref)) <= p.eps * nA
     assert np.max(np.abs(b["v"] - ref)) <= p.eps * nA
+
+
+def test_jacobi_rank_stop_matches_full_convergence():
+    # the Jacobi stop rule (end once the certified rank repeats and the kept rows are orthogonal)
+    # against sweeping to full convergence, on the direct solve of the same request: certified
+    # bounds, orthonormal factors, the same leading singular values, ranks within a few, and
+    # potentials that agree with the oracle's direct sum
+    require_gpu()
+    import paper_1411_1994_amd as L
+    p = _medium_defected(eps=1e-4)
+    out = {}
+    for stop in (1, 0):
+        with L.Context(0, n_slots=1) as c:
+            c.set_option(L.OPT_RANGE_MIN, 0)
+            c.set_option(L.OPT_JACOBI_STOP, stop)
+            r = c.submit(p)
+            assert r.wait() == 0, r.stats()
+            rng = np.random.default_rng(5)
+            cells = np.stack([rng.integers(0, n, 24) for n in p.N], axis=1)
+            Z, _ = r.tucker()
+            out[stop] = dict(inf=r.info(), st=r.stats(), sig=r.sigma(), Z=Z, v=r.sample(cells_xyz(p, cells)),
+                             cells=cells)
+            r.release()
+    a, b = out[1], out[0]
+    nA = b["inf"].norm_A
+    thr = p.eps * nA / (3 * b["inf"].norm_xi)
+    for o in (a, b):
+        assert o["inf"].bound <= p.eps * nA * (1 + 1e-12)
+        for l in range(3):
+            assert np.max(np.abs(o["Z"][l] @ o["Z"][l].T - np.eye(o["Z"][l].shape[0]))) < 1e-11
+    for l in range(3):
+        assert a["st"]["sweeps"][l] <= b["st"]["sweeps"][l]
+        # column norms in any sweep give tails that bound the converged ones from above
+        assert b["inf"].r[l] <= a["inf"].r[l] <= b["inf"].r[l] + max(3, b["inf"].r[l] // 50)
+        # the kept rows are orthogonal among themselves; what they still share with the tail rows
+        # (at most the tail energy, <= thr^2) moves their norms by far less than thr
+        sa, sb = a["sig"][l], b["sig"][l]
+        big = sb > 10 * thr
+        assert np.all(np.abs(sa[big] - sb[big]) <= 1e-10 * sb[0] + thr)
+    ref = O.brute_force_points(p, a["cells"])
+    for o in (a, b):
+        assert np.max(np.abs(o["v"] - ref)) <= p.eps * nA
 
 
 @pytest.mark.parametrize("L,N,src", [((4, 4, 4), (65, 65, 65), [0, 0, 0]),
