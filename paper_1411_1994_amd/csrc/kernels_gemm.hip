@@ -5,6 +5,8 @@
 //  * k_core: the RHOSVD core mu = sum_nu xi_nu y1_nu (x) y2_nu (x) y3_nu (eq. C-core) as a GEMM
 //    whose left operand, the Khatri-Rao product of the mode-1 and mode-2 projections, is formed
 //    on the fly in LDS so it never touches HBM;
+//  * k_core_groups: the same sum with the terms that share a mode-3 column added first (the
+//    mode-3 contraction is then a k_gemm over the distinct columns);
 //  * k_cp_norm2: ||A||_F^2 of the canonical sum from the column Grams (truncation rule).
 //
 // Both GEMM-shaped kernels use 128 x 64 workgroup tiles with 32 rows per wave:
@@ -455,6 +457,69 @@ __global__ void __launch_bounds__(256) k_gather_terms(int K, int r, const T* __r
     for (int a = threadIdx.x & 63; a < ldx; a += 64) dst[a] = a < r ? s * src[a] : T(0);
 }
 
+// Grouped core terms: the canonical terms that share a mode-3 column j are summed before the
+// mode-3 contraction, T[j][a][b] = sum_{nu in j} s_nu Y1[i1(nu), a] Y2[i2(nu), b], so that the
+// core becomes mu = T x_3 Y3 (a plain GEMM over the D3 columns instead of the K terms).  A
+// workgroup owns a 64 x 64 tile of (a, b) for one j; the terms of j are staged through LDS 32 at
+// a time (the scale folded into the mode-1 row) and summed in FP64 in term order.
+constexpr int CG_T = 32;
+template <typename T>
+__global__ void __launch_bounds__(256) k_core_groups(int r1, int r2, int j0, const int32_t* __restrict__ off,
+                                                     const int32_t* __restrict__ i1, const int32_t* __restrict__ i2,
+                                                     const double* __restrict__ sc, const T* __restrict__ Y1,
+                                                     long ldy1, const T* __restrict__ Y2, long ldy2,
+                                                     T* __restrict__ out) {
+    __shared__ double s1[CG_T][64];
+    __shared__ double s2[CG_T][64];
+    const int a0 = blockIdx.y * 64, b0 = blockIdx.x * 64, jl = blockIdx.z, j = j0 + jl;
+    const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
+    const int t0 = off[j], t1 = off[j + 1];
+    double acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc[i][k] = 0.0;
+    for (int tb = t0; tb < t1; tb += CG_T) {
+        const int nt = min(CG_T, t1 - tb);
+        for (int e = tid; e < CG_T * 64; e += 256) {
+            const int t = e >> 6, c = e & 63;
+            double v1 = 0.0, v2 = 0.0;
+            if (t < nt) {
+                const int a = a0 + c, b = b0 + c;
+                if (a < r1) v1 = sc[tb + t] * (double)Y1[(long)i1[tb + t] * ldy1 + a];
+                if (b < r2) v2 = (double)Y2[(long)i2[tb + t] * ldy2 + b];
+            }
+            s1[t][c] = v1;
+            s2[t][c] = v2;
+        }
+        __syncthreads();
+        for (int t = 0; t < nt; ++t) {
+            double x[4], y[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                x[i] = s1[t][ty * 4 + i];
+                y[i] = s2[t][tx * 4 + i];
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int k = 0; k < 4; ++k) acc[i][k] = fma(x[i], y[k], acc[i][k]);
+        }
+        __syncthreads();
+    }
+    T* o = out + (long)jl * r1 * r2;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int a = a0 + ty * 4 + i;
+        if (a >= r1) continue;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int b = b0 + tx * 4 + k;
+            if (b < r2) o[(long)a * r2 + b] = (T)acc[i][k];
+        }
+    }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_reduce_split(long n, int k_split, const T* __restrict__ work,
                                                       T* __restrict__ out) {
@@ -674,6 +739,19 @@ void launch_gather_terms(hipStream_t st, int elem, int K, int r, const void* Yt,
     else
         hipLaunchKernelGGL(k_gather_terms<float>, dim3(cdiv(K, 4)), dim3(256), 0, st, K, r, (const float*)Yt,
                            ldy, idx, sc, (float*)X, ldx);
+}
+
+void launch_core_groups(hipStream_t st, int elem, int r1, int r2, int j0, int nj, const int32_t* off,
+                        const int32_t* i1, const int32_t* i2, const double* sc, const void* Y1, long ldy1,
+                        const void* Y2, long ldy2, void* out) {
+    if (nj <= 0 || r1 <= 0 || r2 <= 0) return;
+    const dim3 grid(cdiv(r2, 64), cdiv(r1, 64), nj);
+    if (elem == 8)
+        hipLaunchKernelGGL(k_core_groups<double>, grid, dim3(256), 0, st, r1, r2, j0, off, i1, i2, sc,
+                           (const double*)Y1, ldy1, (const double*)Y2, ldy2, (double*)out);
+    else
+        hipLaunchKernelGGL(k_core_groups<float>, grid, dim3(256), 0, st, r1, r2, j0, off, i1, i2, sc,
+                           (const float*)Y1, ldy1, (const float*)Y2, ldy2, (float*)out);
 }
 
 void launch_cp_norm2(hipStream_t st, int R, int n_groups, const int32_t* src1, const int32_t* src2,

@@ -588,10 +588,61 @@ static int run_tucker(Request* q, hipStream_t st, const hipStream_t* aux, StageT
     for (int l = 0; l < 3; ++l) cols[l].reset();
 
     // (7) core mu = sum_nu xi_nu y1 (x) y2 (x) y3 (eq. C-core), unnormalised columns: xi = scale;
-    // term tables nu = g R + q -> projection rows src_l(g) R + q and the group scale
+    // term tables nu = g R + q -> projection rows src_l(g) R + q and the group scale.  When the
+    // terms share mode-3 columns (defects on common lattice planes: D3 <= K / 2), the terms of
+    // each column are summed first, T[j] = sum_{nu: src_3 = j} xi y1 (x) y2, and the core is the
+    // GEMM T x_3 Y3 over the D3 columns: 2 r1 r2 (K + D3 r3) flops instead of 2 r1 r2 r3 K.
     const long K = (long)ng * P.R;
-    tm.begin("core", 0, 2.0 * (double)q->r[0] * q->r[1] * q->r[2] * (double)K);
-    {
+    const int D3 = P.D[2];
+    const bool grouped = 2L * D3 <= K;
+    const double r12 = (double)q->r[0] * q->r[1];
+    tm.begin("core", 0, grouped ? 2.0 * r12 * ((double)K + (double)D3 * q->r[2]) : 2.0 * r12 * q->r[2] * (double)K);
+    if (grouped) {
+        std::vector<int32_t> off(D3 + 1, 0), i1(K), i2(K);
+        std::vector<double> scv(K);
+        for (int g = 0; g < ng; ++g)
+            for (int k = 0; k < P.R; ++k) ++off[P.g_src[2][g] * P.R + k + 1];
+        for (int j = 0; j < D3; ++j) off[j + 1] += off[j];
+        std::vector<int32_t> pos(off.begin(), off.end() - 1);
+        for (int g = 0; g < ng; ++g)
+            for (int k = 0; k < P.R; ++k) {
+                const int t = pos[P.g_src[2][g] * P.R + k]++;
+                i1[t] = P.g_src[0][g] * P.R + k;
+                i2[t] = P.g_src[1][g] * P.R + k;
+                scv[t] = P.g_scale[g];
+            }
+        DevBuf off_d, i1_d, i2_d, sc_d;
+        if ((rc = off_d.get(c->pool, off.size() * 4)) || (rc = i1_d.get(c->pool, (size_t)K * 4)) ||
+            (rc = i2_d.get(c->pool, (size_t)K * 4)) || (rc = sc_d.get(c->pool, (size_t)K * 8)))
+            return rc;
+        LSUM_HIP(hipMemcpyAsync(off_d.p, off.data(), off.size() * 4, hipMemcpyHostToDevice, st));
+        LSUM_HIP(hipMemcpyAsync(i1_d.p, i1.data(), (size_t)K * 4, hipMemcpyHostToDevice, st));
+        LSUM_HIP(hipMemcpyAsync(i2_d.p, i2.data(), (size_t)K * 4, hipMemcpyHostToDevice, st));
+        LSUM_HIP(hipMemcpyAsync(sc_d.p, scv.data(), (size_t)K * 8, hipMemcpyHostToDevice, st));
+        const int r1 = q->r[0], r2 = q->r[1], r3 = q->r[2];
+        const long plane = (long)r1 * r2 * r3;
+        if ((rc = q->core.get(c->pool, (size_t)plane * es))) return rc;
+        // T in chunks of columns of at most 2 GiB; the chunks' GEMMs accumulate into the core
+        const long per_col = (long)r1 * r2 * (long)es;
+        const int chunk = (int)std::max<long>(1, std::min<long>({(long)D3, (2L << 30) / per_col, 65535L}));
+        DevBuf Tb;
+        if ((rc = Tb.get(c->pool, (size_t)per_col * chunk))) return rc;
+        for (int j0 = 0; j0 < D3; j0 += chunk) {
+            const int nj = std::min(chunk, D3 - j0);
+            launch_core_groups(st, (int)es, r1, r2, j0, nj, off_d.as<int32_t>(), i1_d.as<int32_t>(),
+                               i2_d.as<int32_t>(), sc_d.as<double>(), Y[0].p, ldy[0], Y[1].p, ldy[1], Tb.p);
+            GemmArgs a{};
+            a.m = r1 * r2; a.n = r3; a.k = nj;
+            a.A = Tb.p; a.sam = 1; a.sak = (long)r1 * r2;
+            a.B = (const char*)Y[2].p + (size_t)j0 * ldy[2] * es; a.sbk = ldy[2]; a.sbn = 1;
+            a.C = q->core.p; a.scm = r3; a.scn = 1;
+            a.alpha = 1.0; a.beta = j0 == 0 ? 0.0 : 1.0; a.batch = 1;
+            launch_gemm(st, prec, a);
+        }
+        LSUM_HIP(hipGetLastError());
+        LSUM_HIP(hipStreamSynchronize(st));
+        q->bytes["core"] = (double)plane * es;
+    } else {
         std::vector<int32_t> idx(3 * (size_t)K);
         std::vector<double> scv(K);
         for (int g = 0; g < ng; ++g)
@@ -1143,7 +1194,8 @@ int sample_canonical(Context* c, hipStream_t st, const std::vector<CanonSample>&
     return LSUM_OK;
 }
 
-int sample_points(Request* q, hipStream_t st, int n, const double* xyz_d, double* out_d, const KTime* kt) {
+int sample_points(Request* q, hipStream_t st, int n, const double* xyz_d, double* out_d, const KTime* kt,
+                  double* flops) {
     Context* c = q->ctx;
     const Plan& P = q->plan();
     int rc;
@@ -1218,6 +1270,7 @@ int sample_points(Request* q, hipStream_t st, int n, const double* xyz_d, double
         a.C = W.p; a.scm = (long)r1 * r2; a.scn = 1;
         a.alpha = 1.0; a.beta = 0.0; a.batch = 1;
         launch_gemm(st, GEMM_F64, a);
+        if (flops) *flops += 2.0 * Un * (double)r1 * r2 * r3 + 2.0 * (double)r1 * r2 * Pn;
         const int32_t* ld = lists.as<int32_t>();
         launch_tucker_finish(st, r1, r2, Pn, W.as<double>(), q->Z[0].as<double>(), P.N[0], q->Z[1].as<double>(),
                              P.N[1], ld, ld + Pn, ld + 2 * Pn, ld + 3 * Pn, out_d);
@@ -1314,8 +1367,10 @@ static int run_tucker_ref_batch(Request* q, hipStream_t st, const hipStream_t* a
             xyz_d = xd.as<double>();
             out_d = od.as<double>();
         }
+        double fl = 0.0;
         tm.begin("sample", (double)n * 32, 0);
-        rc = sample_points(q, st, n, xyz_d, out_d);
+        rc = sample_points(q, st, n, xyz_d, out_d, nullptr, &fl);
+        if (fl > 0.0) tm.work(0, fl);   // a Tucker result: an FP64 contraction
         tm.end();
         if (rc) q->status.store(rc);
         else if (!q->points_on_device)
@@ -1508,8 +1563,10 @@ int run_batch(std::vector<Request*>& reqs, hipStream_t st, const hipStream_t* au
             if (q->axis_src[l] == l) uN += P.N[l];
         const double fb = (double)P.blocks.size() * P.R * uN * P.row_elem();
         if (P.tucker()) {
+            double fl = 0.0;
             tm.begin("sample", (double)n * 32, 0);
-            rc = sample_points(q, st, n, xyz_d, out_d);
+            rc = sample_points(q, st, n, xyz_d, out_d, nullptr, &fl);
+            if (fl > 0.0) tm.work(0, fl);   // an FP64 contraction
             tm.end();
             if (rc) {
                 q->status.store(rc);

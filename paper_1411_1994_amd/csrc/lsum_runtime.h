@@ -224,6 +224,13 @@ class StageTimer {
     explicit StageTimer(hipStream_t s) : st_(s) {}
     ~StageTimer();
     void begin(const std::string& name, double bytes = 0, double flops = 0);
+    // the algorithmic work of the open stage, when it is known only once its kernels are queued
+    void work(double bytes, double flops) {
+        if (!ev_.empty()) {
+            ev_.back().bytes = bytes;
+            ev_.back().flops = flops;
+        }
+    }
     void end();
     // a stage of kernels timed by their own dispatches: pass `start` to the first kernel's
     // launch and `stop` to the last one's (instead of begin/end)
@@ -273,8 +280,9 @@ struct CanonSample {
     double* out;
 };
 int sample_canonical(Context* c, hipStream_t st, const std::vector<CanonSample>& items, const KTime* kt);
-// kt (canonical requests only): kernel-bound timing of the sampling kernels
+// kt (canonical requests only): kernel-bound timing of the sampling kernels; flops (Tucker
+// requests): the algorithmic flops of the contraction with the points' factor rows
 int sample_points(Request* q, hipStream_t st, int n, const double* xyz_dev, double* out_dev,
-                  const KTime* kt = nullptr);
+                  const KTime* kt = nullptr, double* flops = nullptr);
 
 }  // namespace lsum

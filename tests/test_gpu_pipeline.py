@@ -113,10 +113,10 @@ def test_points_outside_grid_are_nan(ctx):
     r.release()
 
 
-def _small_defected(kind=W.NEWTON, param=0.0, eps=1e-6, precision=W.FP64, seed=11, tile=True):
+def _small_defected(kind=W.NEWTON, param=0.0, eps=1e-6, precision=W.FP64, seed=11, tile=True, n_vac=5, n_imp=3):
     rng = np.random.default_rng(seed)
     blocks = [W.Block((5, 4, 4), (1.0, 1.0, 1.0), (0.1, -0.2, 0.05))]
-    defects = W.draw_defects(rng, blocks, 5, 3)
+    defects = W.draw_defects(rng, blocks, n_vac, n_imp)
     N = (33, 37, 31)
     p = W.Problem("rh", kind, param, 20, N, 0.37, blocks, defects, eps=eps, precision=precision)
     if tile:
@@ -205,6 +205,34 @@ def test_rhosvd_mixed_precision_error(ctx, prec):
     assert rel < tol, rel
     r64.release()
     rm.release()
+
+
+@pytest.mark.parametrize("prec", [W.FP64, W.FP32, W.BF16X3])
+def test_grouped_core_matches_oracle(ctx, prec):
+    # 20 defects on the 5 x 4 x 4 lattice share at most 4 mode-3 planes: the terms of each mode-3
+    # column are summed before the mode-3 contraction (D3 <= K / 2).  The core against the
+    # oracle's projection of the full tensor onto the GPU's factors, and the tile against the
+    # full tensor within the certified bound
+    p = _small_defected(eps=1e-8, precision=prec, n_vac=12, n_imp=8)
+    assert 2 * (len(p.blocks) + len({(d.block, d.site[2]) for d in p.defects})) <= len(p.blocks) + len(p.defects)
+    r = run(ctx, p)
+    inf = r.info()
+    xi, A = O.canonical_terms(p)
+    full = O.cp_full(xi, A)
+    nA = np.linalg.norm(full)
+    Z, core = r.tucker()
+    mu = np.einsum("ijk,ai,bj,ck->abc", full, *Z, optimize=True)
+    tile = r.tile().astype(np.float64)
+    err = np.linalg.norm(tile - full)
+    r.release()
+    if prec == W.FP64:
+        assert np.max(np.abs(mu - core)) <= 1e-11 * np.max(np.abs(mu))
+        assert err <= inf.bound * (1 + 1e-9) + 1e-12 * nA
+    else:
+        # FP32 operands (projections, Z) and an FP32 core; BF16x3 products good to about 2^-16
+        tol = 1e-5 if prec == W.FP32 else 1e-4
+        assert np.max(np.abs(mu - core.astype(np.float64))) <= tol * np.max(np.abs(mu))
+        assert err <= inf.bound * (1 + 1e-9) + tol * nA
 
 
 def test_concurrent_requests_equal_alone(ctx):
