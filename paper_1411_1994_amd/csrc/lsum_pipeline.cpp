@@ -8,6 +8,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <thread>
@@ -141,6 +143,9 @@ static int range_svd(Context* c, hipStream_t st, int D, int N, const double* W, 
         kq += keep;
         ++blocks;
         if ((rc = frob2(c, st, D, N, E.as<double>(), &res2))) return rc;   // synchronises (iv may go)
+        if (std::getenv("LSUM_JACOBI_TRACE"))
+            std::fprintf(stderr, "range D=%d N=%d block %d kept %d of %d basis %d of %d residual/thr %.3e\n", D, N,
+                         blocks, keep, kb, kq, k_max, std::sqrt(res2) / thr);
         if (std::sqrt(res2) <= 0.1 * thr) break;
     }
     Om.reset();
