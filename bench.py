@@ -117,9 +117,8 @@ def run_stream(L, ctx, problem, points, outs, steps, inflight, chunk=1):
     return time.perf_counter() - t0, lat
 
 
-def dominant_roofline(prof: dict, dtype_peak: str, stage_dtype: dict = None):
-    """The stage with the largest GPU time: achieved = algorithmic work per launch / mean launch time.
-    stage_dtype: stages whose arithmetic type is not the request's (their MFMA peak is taken for it)."""
+def dominant_roofline(prof: dict, dtype_peak: str):
+    """The stage with the largest GPU time: achieved = algorithmic work per launch / mean launch time."""
     # stages with an algorithmic byte or flop count (the iterative SVD has its own limit: time only)
     prof = {k: v for k, v in (prof or {}).items() if v["bytes"] > 0 or v["flops"] > 0}
     if not prof:
@@ -129,7 +128,7 @@ def dominant_roofline(prof: dict, dtype_peak: str, stage_dtype: dict = None):
     ms = st["ms"] / n
     if st["flops"] > 0 and st["bytes"] == 0 or name in ("core", "tile", "projection", "norm"):
         achieved = st["flops"] / n / (ms * 1e-3) / 1e12
-        peak = PEAK_TFLOPS[(stage_dtype or {}).get(name, dtype_peak)]
+        peak = PEAK_TFLOPS[dtype_peak]
         return name, {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                       "frac": achieved / peak, "traffic": None, "kernel_stage": name,
                       "avg_launch_ms": ms, "launches": st["launches"],
@@ -268,7 +267,7 @@ def run_mix(args):
         errs.append(float(np.max(np.abs(s_vals[k][:4] - ref)) / np.max(np.abs(ref))))
     sizes = {"L_max": max(max(p.blocks[0].L) for p in probs), "N_max": max(max(p.N) for p in probs),
              "defects_max": max(len(p.defects) for p in probs)}
-    stage, roof = dominant_roofline(prof, "f32", {"sample": "f64"})
+    stage, roof = dominant_roofline(prof, "f32")
     out = {
         "metric": METRIC,
         "value": served,
@@ -626,8 +625,7 @@ def main():
 
     # canonical output at FP32 precision: FP32-rounded factor rows, FP64 products and sums
     dtype = "f64" if problem.precision == W.FP64 else ("f32" if problem.precision == W.FP32 or cfg == 2 else "bf16x3")
-    # a Tucker result is sampled by an FP64 contraction of the core whatever the request's precision
-    stage, roof = dominant_roofline(prof, dtype, {"sample": "f64"})
+    stage, roof = dominant_roofline(prof, dtype)
     if roof is not None and cfg == 2 and stage == "sample":
         # the counters were taken per request of 1e5 points on FP32 rows (the served policy)
         roof["traffic"] = traffic_from_profiles("sample", steps / max(1, prof["sample"]["launches"]))

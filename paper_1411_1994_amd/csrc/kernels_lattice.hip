@@ -426,9 +426,9 @@ __global__ void __launch_bounds__(256) k_snap_points(int n, const double* __rest
 // Z2 column is staged in LDS, each wave takes a subset of the a rows and reads them contiguously
 // (lanes over b), and the waves' totals are summed in a fixed order.  (Without LDS staging, for
 // r2 beyond the dynamic LDS limit, Z2 is read directly.)
-template <bool STAGE>
+template <bool STAGE, typename TW>
 __global__ void __launch_bounds__(256) k_tucker_finish(int r1, int r2, int P,
-                                                       const double* __restrict__ W,
+                                                       const TW* __restrict__ W,
                                                        const double* __restrict__ Z1, int ld1,
                                                        const double* __restrict__ Z2, int ld2,
                                                        const int32_t* __restrict__ i1,
@@ -450,12 +450,12 @@ __global__ void __launch_bounds__(256) k_tucker_finish(int r1, int r2, int P,
         __syncthreads();
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const double* w = W + (size_t)(wrow ? wrow[t] : t) * r1 * r2;
+    const TW* w = W + (size_t)(wrow ? wrow[t] : t) * r1 * r2;
     double total = 0.0;
     for (int a = wave; a < r1; a += 4) {
         double acc = 0.0;
         for (int b = lane; b < r2; b += 64)
-            acc += w[(size_t)a * r2 + b] * (STAGE ? z2s[b] : Z2[(size_t)b * ld2 + c2]);
+            acc += (double)w[(size_t)a * r2 + b] * (STAGE ? z2s[b] : Z2[(size_t)b * ld2 + c2]);
         for (int m = 32; m > 0; m >>= 1) acc += __shfl_xor(acc, m, 64);
         total += acc * Z1[(size_t)a * ld1 + c1];
     }
@@ -600,16 +600,26 @@ void launch_select_cols(hipStream_t st, int rows, int nsel, const void* Z, long 
                            ldz, idx, (float*)out);
 }
 
-void launch_tucker_finish(hipStream_t st, int r1, int r2, int P, const double* W, const double* Z1,
+void launch_tucker_finish(hipStream_t st, int r1, int r2, int P, const void* W, int w_elem, const double* Z1,
                           int ld1, const double* Z2, int ld2, const int32_t* i1, const int32_t* i2,
                           const int32_t* wrow, const int32_t* oidx, double* out) {
     if (P <= 0) return;
-    if (r2 <= 8192)
-        hipLaunchKernelGGL(k_tucker_finish<true>, dim3(P), dim3(256), (size_t)r2 * sizeof(double), st, r1, r2, P,
-                           W, Z1, ld1, Z2, ld2, i1, i2, wrow, oidx, out);
-    else
-        hipLaunchKernelGGL(k_tucker_finish<false>, dim3(P), dim3(256), 0, st, r1, r2, P, W, Z1, ld1, Z2, ld2, i1,
-                           i2, wrow, oidx, out);
+    const size_t lds = r2 <= 8192 ? (size_t)r2 * sizeof(double) : 0;
+    if (w_elem == 8) {
+        if (lds)
+            hipLaunchKernelGGL((k_tucker_finish<true, double>), dim3(P), dim3(256), lds, st, r1, r2, P,
+                               (const double*)W, Z1, ld1, Z2, ld2, i1, i2, wrow, oidx, out);
+        else
+            hipLaunchKernelGGL((k_tucker_finish<false, double>), dim3(P), dim3(256), 0, st, r1, r2, P,
+                               (const double*)W, Z1, ld1, Z2, ld2, i1, i2, wrow, oidx, out);
+    } else {
+        if (lds)
+            hipLaunchKernelGGL((k_tucker_finish<true, float>), dim3(P), dim3(256), lds, st, r1, r2, P,
+                               (const float*)W, Z1, ld1, Z2, ld2, i1, i2, wrow, oidx, out);
+        else
+            hipLaunchKernelGGL((k_tucker_finish<false, float>), dim3(P), dim3(256), 0, st, r1, r2, P,
+                               (const float*)W, Z1, ld1, Z2, ld2, i1, i2, wrow, oidx, out);
+    }
 }
 
 void launch_snap_points(hipStream_t st, int n, const double* xyz, int N0, int N1, int N2, double h,

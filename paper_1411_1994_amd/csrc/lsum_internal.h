@@ -292,9 +292,10 @@ void launch_gather_scale_rows(hipStream_t st, int r, int n, const double* X, int
 // Rows of a factor selected by index lists: out[a * nsel + p] = Z[a * ldz + idx[p]]
 void launch_select_cols(hipStream_t st, int rows, int nsel, const void* Z, long ldz,
                         const int32_t* idx, void* out, int elem_size);
-// Tucker values of P points from W (rows r1*r2, layout [row][a*r2+b]) and Z1, Z2 rows: point t
-// reads row wrow[t] and writes out[oidx[t]] (identity where the list is null)
-void launch_tucker_finish(hipStream_t st, int r1, int r2, int P, const double* W, const double* Z1,
+// Tucker values of P points from W (rows r1*r2, layout [row][a*r2+b], elements of w_elem bytes)
+// and Z1, Z2 rows: point t reads row wrow[t] and writes out[oidx[t]] (identity where the list is
+// null); FP64 sums
+void launch_tucker_finish(hipStream_t st, int r1, int r2, int P, const void* W, int w_elem, const double* Z1,
                           int ld1, const double* Z2, int ld2, const int32_t* i1, const int32_t* i2,
                           const int32_t* wrow, const int32_t* oidx, double* out);
 void launch_snap_points(hipStream_t st, int n, const double* xyz, int N0, int N1, int N2, double h,

@@ -1208,12 +1208,17 @@ int sample_points(Request* q, hipStream_t st, int n, const double* xyz_d, double
     if (!P.tucker()) return sample_canonical(c, st, {CanonSample{q, n, xyz_d, out_d}}, kt);
     const int r1 = q->r[0], r2 = q->r[1], r3 = q->r[2];
     const size_t ncore = (size_t)r1 * r2 * r3;
-    DevBuf core64, idx, W, Z3s, i3c;
-    const double* core_d = q->core.as<double>();
-    if (P.precision != LSUM_FP64) {
-        if ((rc = core64.get(c->pool, ncore * 8))) return rc;
-        launch_f32_to_f64(st, (long)ncore, q->core.as<float>(), core64.as<double>());
-        core_d = core64.as<double>();
+    // the mode-3 contraction runs in the request's precision on the core as stored (FP32
+    // elements unless FP64, with FP64 sums across chunks); the finishing sums are FP64
+    (void)ncore;
+    DevBuf Z3f, idx, W, Z3s, i3c;
+    const GemmPrec gp = gemm_prec(P.precision);
+    const size_t we = P.precision == LSUM_FP64 ? 8 : 4;
+    const void* Z3p = q->Z[2].p;
+    if (we == 4) {
+        if ((rc = Z3f.get(c->pool, (size_t)r3 * P.N[2] * 4))) return rc;
+        launch_f64_to_f32(st, (long)r3 * P.N[2], q->Z[2].as<double>(), Z3f.as<float>());
+        Z3p = Z3f.p;
     }
     if ((rc = idx.get(c->pool, (size_t)n * 12))) return rc;
     launch_snap_points(st, n, xyz_d, P.N[0], P.N[1], P.N[2], P.h, idx.as<int32_t>());
@@ -1240,8 +1245,8 @@ int sample_points(Request* q, hipStream_t st, int n, const double* xyz_d, double
     const size_t per = std::max<size_t>(1, (size_t)r1 * r2);
     int chunk = (int)std::max<size_t>(1, std::min<size_t>(cells.size(), ((size_t)1 << 28) / per));
     chunk = std::min(chunk, 4096);
-    if ((rc = W.get(c->pool, per * chunk * 8))) return rc;
-    if ((rc = Z3s.get(c->pool, (size_t)r3 * chunk * 8))) return rc;
+    if ((rc = W.get(c->pool, per * chunk * we))) return rc;
+    if ((rc = Z3s.get(c->pool, (size_t)r3 * chunk * we))) return rc;
     if ((rc = i3c.get(c->pool, (size_t)chunk * 4))) return rc;
     DevBuf lists;
     if ((rc = lists.get(c->pool, std::max<size_t>(1, order.size()) * 16))) return rc;
@@ -1266,18 +1271,18 @@ int sample_points(Request* q, hipStream_t st, int n, const double* xyz_d, double
         }
         LSUM_HIP(hipMemcpyAsync(i3c.p, cells.data() + u0, (size_t)Un * 4, hipMemcpyHostToDevice, st));
         LSUM_HIP(hipMemcpyAsync(lists.p, lh.data(), (size_t)Pn * 16, hipMemcpyHostToDevice, st));
-        launch_select_cols(st, r3, Un, q->Z[2].p, P.N[2], i3c.as<int32_t>(), Z3s.p, 8);
+        launch_select_cols(st, r3, Un, Z3p, P.N[2], i3c.as<int32_t>(), Z3s.p, (int)we);
         // W[u][(a,b)] = sum_c Z3s[c][u] mu[(a,b)][c]: row-major per cell, so each row is contiguous
         GemmArgs a{};
         a.m = Un; a.n = r1 * r2; a.k = r3;
         a.A = Z3s.p; a.sam = 1; a.sak = Un;
-        a.B = core_d; a.sbk = 1; a.sbn = r3;
+        a.B = q->core.p; a.sbk = 1; a.sbn = r3;
         a.C = W.p; a.scm = (long)r1 * r2; a.scn = 1;
         a.alpha = 1.0; a.beta = 0.0; a.batch = 1;
-        launch_gemm(st, GEMM_F64, a);
+        launch_gemm(st, gp, a);
         if (flops) *flops += 2.0 * Un * (double)r1 * r2 * r3 + 2.0 * (double)r1 * r2 * Pn;
         const int32_t* ld = lists.as<int32_t>();
-        launch_tucker_finish(st, r1, r2, Pn, W.as<double>(), q->Z[0].as<double>(), P.N[0], q->Z[1].as<double>(),
+        launch_tucker_finish(st, r1, r2, Pn, W.p, (int)we, q->Z[0].as<double>(), P.N[0], q->Z[1].as<double>(),
                              P.N[1], ld, ld + Pn, ld + 2 * Pn, ld + 3 * Pn, out_d);
         LSUM_HIP(hipStreamSynchronize(st));   // i3c and the lists are rewritten by the next chunk
         t0 = t1;
@@ -1375,7 +1380,7 @@ static int run_tucker_ref_batch(Request* q, hipStream_t st, const hipStream_t* a
         double fl = 0.0;
         tm.begin("sample", (double)n * 32, 0);
         rc = sample_points(q, st, n, xyz_d, out_d, nullptr, &fl);
-        if (fl > 0.0) tm.work(0, fl);   // a Tucker result: an FP64 contraction
+        if (fl > 0.0) tm.work(0, fl);   // a Tucker result: a contraction in the request's precision
         tm.end();
         if (rc) q->status.store(rc);
         else if (!q->points_on_device)
@@ -1571,7 +1576,7 @@ int run_batch(std::vector<Request*>& reqs, hipStream_t st, const hipStream_t* au
             double fl = 0.0;
             tm.begin("sample", (double)n * 32, 0);
             rc = sample_points(q, st, n, xyz_d, out_d, nullptr, &fl);
-            if (fl > 0.0) tm.work(0, fl);   // an FP64 contraction
+            if (fl > 0.0) tm.work(0, fl);   // a contraction in the request's precision
             tm.end();
             if (rc) {
                 q->status.store(rc);

@@ -281,7 +281,8 @@ struct CanonSample {
 };
 int sample_canonical(Context* c, hipStream_t st, const std::vector<CanonSample>& items, const KTime* kt);
 // kt (canonical requests only): kernel-bound timing of the sampling kernels; flops (Tucker
-// requests): the algorithmic flops of the contraction with the points' factor rows
+// requests, added to): the algorithmic flops of the contraction with the points' factor rows,
+// run in the request's precision with FP64 final sums
 int sample_points(Request* q, hipStream_t st, int n, const double* xyz_dev, double* out_dev,
                   const KTime* kt = nullptr, double* flops = nullptr);
 

@@ -203,6 +203,12 @@ def test_rhosvd_mixed_precision_error(ctx, prec):
     # (sum |mu||Z||Z||Z| / |V|, about 5 here).  Split-BF16x3 products are good to about 2^-16.
     tol = 6 * 2.0 ** -24 * 5 * 2 if prec == W.FP32 else 1e-4
     assert rel < tol, rel
+    # values at points: the mode-3 contraction in the request's precision (Z3 rows, the core and
+    # its product rounded to the element type, FP64 sums across chunks), the rest FP64
+    rng = np.random.default_rng(17)
+    cells = np.stack([rng.integers(0, n, 300) for n in p64.N], axis=1)
+    v64, vm = r64.sample(cells_xyz(p64, cells)), rm.sample(cells_xyz(pm, cells))
+    assert np.max(np.abs(vm - v64)) / np.max(np.abs(v64)) < tol
     r64.release()
     rm.release()
 
