@@ -7,8 +7,8 @@
 //                     on v_mfma_f64_16x16x4 (grid: chunks x pairs);
 //   2. k_pair_eig:    per pair, the chunk partials are summed in a fixed order (256 threads), the
 //                     coupling max |g_ij| / sqrt(g_ii g_jj) is measured and, unless the pair is
-//                     already orthogonal, two sweeps of cyclic two-sided Jacobi on the Gram run in
-//                     one wavefront (the outer sweeps converge as fast as with full inner solves);
+//                     already orthogonal, one or two sweeps of cyclic two-sided Jacobi on the Gram
+//                     run in one wavefront (one when a round holds many pairs);
 //   3. k_pair_rotate: X_pair <- Q^T X_pair over the same chunks, again on MFMA.
 // Columns are never squared against each other globally, so singular values keep an absolute
 // accuracy of a few eps * sigma_max -- the RHOSVD threshold at eps = 1e-6 sits near 1e-8 sigma_1,
@@ -387,10 +387,13 @@ int jacobi_svd(hipStream_t st, int D, int N, double* A, int lda, double tol, dou
     const double smax2 = sig2[perm[0]];
     const double irr2 = std::max(irrelevant * irrelevant, 1e-30 * smax2);
     const bool trace = std::getenv("LSUM_JACOBI_TRACE") != nullptr;
-    // two cyclic sweeps per visit of a pair: the outer sweep count stays the same as with inner
-    // solves run to convergence (measured on the defected 48^3 and step-lattice side matrices,
-    // D ~ 1500-2300), at a quarter of the inner work
-    constexpr int max_inner = 2;
+    // inner cyclic sweeps per visit of a pair.  Two keep the outer sweep count of inner solves
+    // run to convergence at a quarter of the inner work (measured on the defected 48^3 and
+    // step-lattice side matrices).  With many pairs per round the round time is the pair
+    // solve's latency, and one inner sweep is faster overall even though it costs about one
+    // more outer sweep (cfg3 side matrices: SVD 147 -> 134 ms); with few pairs and long rows
+    // the Gram and rotation passes dominate a round, and the second inner sweep pays for
+    // itself (few tens of columns of 5633-34305 cells: 30-50 % slower with one).
     int sweeps = 0;
     bool converged = false;
     // rank stop: the certified rank of the current rows, and the squared norm above which rows
@@ -403,6 +406,7 @@ int jacobi_svd(hipStream_t st, int D, int N, double* A, int lda, double tol, dou
         while (d_act < L.Dp && sig2[perm[d_act]] > irr2) ++d_act;
         const int nblk = std::max(2, (d_act + 15) / 16 * 2);
         const int npair = nblk / 2;
+        const int max_inner = npair >= 16 ? 1 : 2;
         LSUM_HIP(hipMemcpyAsync(perm_dev, perm.data(), L.Dp * sizeof(int32_t), hipMemcpyHostToDevice, st));
         hipLaunchKernelGGL(k_permute_rows, dim3(cdiv(L.ldx, 256), L.Dp), dim3(256), 0, st, L.ldx, perm_dev, X, X2,
                            L.ldx, L.ldx);
