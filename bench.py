@@ -387,7 +387,7 @@ def _timed(fn, reps=3):
 
 def run_extras(args):
     """Timings of the paths beyond the served lattice sum, each with an accuracy check: the choice
-    of M, a parallelogram lattice (Sec. 5 case (B)), ALS after the RHOSVD (Thm thm:C2Tucker (b)),
+    of M, a parallelogram lattice (Sec. 4.4 case (B)), ALS after the RHOSVD (Thm thm:C2Tucker (b)),
     the canonical form of a Tucker result (Can -> Tuck -> Can) and the Galerkin matrix (eq.
     nuc_pot)."""
     import oracle as O

@@ -82,7 +82,7 @@ typedef struct {
     double center[3];
     double charge;   /* charge of every site; -1 describes a tensor sub-lattice of vacancies */
     const double* x[3];   /* optional: the L[l] site coordinates of axis l (a non-equidistant
-                             tensor lattice, e.g. clusters on a coarse lattice, Sec. 5 case (D));
+                             tensor lattice, e.g. clusters on a coarse lattice, Sec. 4.4 case (D));
                              NULL: (k - (L-1)/2) b[l] + center[l].  Read while the request is
                              submitted (or by lsum_block_offsets); caller-owned              */
 } lsum_block;
@@ -157,7 +157,7 @@ typedef struct {
 int lsum_nodes(const lsum_kernel* k, const int N[3], double h, double* t, double* w, int cap,
                int* R);
 
-/* Parallelogram-type lattice (Sec. 5 case (B)): the sites of `base` with coordinate
+/* Parallelogram-type lattice (Sec. 4.4 case (B)): the sites of `base` with coordinate
  * `shear_axis` moved by (k - (L-1)/2) * shear, k the site index along `along_axis` (the two axes
  * differ).  Written as the base->L[along_axis] rectangular blocks of one site along that axis
  * (out[0..*n), cap at least that many), whose sum the canonical route assembles with its
@@ -165,7 +165,7 @@ int lsum_nodes(const lsum_kernel* k, const int N[3], double h, double* t, double
 int lsum_shear_blocks(const lsum_block* base, int shear_axis, int along_axis, double shear, int cap,
                       lsum_block* out, int* n);
 
-/* Lattice with the tensor structure in one axis only (Sec. 5 case (C)): the sites of `base`
+/* Lattice with the tensor structure in one axis only (Sec. 4.4 case (C)): the sites of `base`
  * along `axis` (its L, b, center or explicit coordinates), repeated at each of the n points of
  * the plane of the two other axes (pts: n pairs in increasing axis order).  Written as n blocks
  * of one site in those two axes (out[0..n), cap at least n), which the canonical route sums with
@@ -225,6 +225,10 @@ const char* lsum_last_error(void);
 #define LSUM_OPT_REF_CACHE_BYTES 2
 #define LSUM_OPT_RANGE_MIN 3
 #define LSUM_OPT_JACOBI_STOP 4
+/* LSUM_OPT_JACOBI_MAX_SWEEPS (default 40, 1..1000): sweeps a side-matrix SVD may take; a request
+ * whose SVD has not converged by then fails with LSUM_E_NOCONV (a bound on its latency).  Read
+ * when a request's SVD starts. */
+#define LSUM_OPT_JACOBI_MAX_SWEEPS 5
 int lsum_set_option(lsum_ctx ctx, int key, double value);
 /* Per stage (collocate, shift_sum, transpose, columns, norm, svd, projection, core, tile,
  * sample): summed event-timed GPU milliseconds, number of timed launches, and the algorithmic
@@ -311,10 +315,13 @@ typedef struct {
 } lsum_info;
 int lsum_get_info(lsum_req req, lsum_info* info);
 
-/* Canonical factors of block `block` (vector-major, R rows of N[l] each) into U[3][R*N[l]]
- * (host, or device if on_device) and the weight of the block (its charge).  Factors kept in
- * FP32 (canonical output at FP32/BF16X3 precision) are returned widened to double. */
-int lsum_get_canonical(lsum_req req, int block, double* U0, double* U1, double* U2, int on_device);
+/* Canonical factors of block `block` (eq. CP_form; Thm thm:sumCaseE (A)): the block's part of the
+ * sum is weight * sum_q U0[q, :] (x) U1[q, :] (x) U2[q, :].  U_l (vector-major, R rows of N[l]
+ * each; host, or device if on_device; NULL skips an axis) carry the node weights as w_q^(1/3)
+ * per axis; *weight (host; NULL skips it) receives the block's charge.  Factors kept in FP32
+ * (canonical output at FP32/BF16X3 precision) are returned widened to double. */
+int lsum_get_canonical(lsum_req req, int block, double* U0, double* U1, double* U2, double* weight,
+                       int on_device);
 /* Galerkin matrix of a finished Tucker result in a separable basis (eq. nuc_pot): basis function
  * k is g_k(x) = g_k^(1)(x_1) g_k^(2)(x_2) g_k^(3)(x_3), given by its values at the cell centres,
  * G_l (nb x N_l, row k = g_k^(l), row-major).  V[k * nb + m] = h^3 sum_i T_i g_k(x_i) g_m(x_i),
@@ -325,7 +332,7 @@ int lsum_galerkin(lsum_req req, int nb, const double* G0, const double* G1, cons
                   double* V, int on_device);
 
 /* Canonical form of a finished Tucker result (the canonical -> Tucker -> canonical rank
- * reduction of Sec. 4.3): each mode-3 slice of the core by its SVD, mu[:, :, k] = sum_i s_i
+ * reduction of Sec. 4.2): each mode-3 slice of the core by its SVD, mu[:, :, k] = sum_i s_i
  * u_i v_i^T, gives orthogonal rank-1 terms s_i (Z_1 u_i) (x) (Z_2 v_i) (x) z_3,k, so the rank is
  * at most r_3 min(r_1, r_2); the smallest s are dropped while their (sum s^2)^(1/2) stays
  * <= eps ||core||, which is then the Frobenius error (*err).  *R receives the rank; with xi ==

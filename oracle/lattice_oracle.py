@@ -177,7 +177,7 @@ def site_coords(L: int, b: float, center: float) -> np.ndarray:
 
 def block_axis_coords(block, a: int) -> np.ndarray:
     """The coordinates of the block's sites along axis a: its explicit list when it has one (a
-    non-equidistant tensor lattice, Sec. 5 case (D)), else the centred equidistant sites."""
+    non-equidistant tensor lattice, Sec. 4.4 case (D)), else the centred equidistant sites."""
     coords = getattr(block, "coords", None)
     if coords is not None and coords[a] is not None:
         return np.asarray(coords[a], dtype=np.float64)
@@ -190,7 +190,7 @@ def block_offsets(block, h: float, N: Sequence[int]) -> List[np.ndarray]:
 
 
 def shear_sites(base, shear_axis: int, along_axis: int, shear: float) -> np.ndarray:
-    """All sites (C,3) of a parallelogram-type lattice (Sec. 5 case (B)): the sites of ``base``
+    """All sites (C,3) of a parallelogram-type lattice (Sec. 4.4 case (B)): the sites of ``base``
     with coordinate ``shear_axis`` moved by (k - (L-1)/2) shear, k the index along ``along_axis``."""
     axes = [block_axis_coords(base, a) for a in range(3)]
     idx = np.stack(np.meshgrid(*[np.arange(len(x)) for x in axes], indexing="ij"), axis=-1).reshape(-1, 3)
@@ -488,7 +488,7 @@ def als_refine(xi: np.ndarray, A: Sequence[np.ndarray], Z: Sequence[np.ndarray],
 
 def tucker_to_canonical(core: np.ndarray, Z: Sequence[np.ndarray], eps: float):
     """Can -> Tuck -> Can (the rank reduction of a defected canonical sum through its Tucker form,
-    Sec. 4.3): each mode-3 slice of the core by its SVD, mu[:, :, k] = sum_i s_i u_i v_i^T, gives
+    Sec. 4.2): each mode-3 slice of the core by its SVD, mu[:, :, k] = sum_i s_i u_i v_i^T, gives
     the rank-1 terms s_i (Z_1 u_i) (x) (Z_2 v_i) (x) z_3,k, so the canonical rank is at most
     r_3 min(r_1, r_2).  With orthonormal Z_l these terms are mutually orthogonal: dropping the
     smallest s (over all slices, ties by slice then index) while the dropped (sum s^2)^(1/2)

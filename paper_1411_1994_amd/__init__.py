@@ -31,7 +31,7 @@ SYMBOLS = ["lsum_nodes", "lsum_block_offsets", "lsum_shear_blocks", "lsum_column
            "lsum_submit", "lsum_submit_many", "lsum_wait", "lsum_cancel", "lsum_get_info", "lsum_get_canonical",
            "lsum_get_tucker", "lsum_tucker_to_canonical", "lsum_galerkin", "lsum_get_sigma", "lsum_sample", "lsum_get_tile", "lsum_get_stats",
            "lsum_release", "lsum_finish_many", "lsum_set_option", "lsum_get_profile", "lsum_reset_profile"]
-OPT_MAX_BATCH, OPT_REF_CACHE_BYTES, OPT_RANGE_MIN, OPT_JACOBI_STOP = 1, 2, 3, 4
+OPT_MAX_BATCH, OPT_REF_CACHE_BYTES, OPT_RANGE_MIN, OPT_JACOBI_STOP, OPT_JACOBI_MAX_SWEEPS = 1, 2, 3, 4, 5
 
 
 class LsumError(RuntimeError):
@@ -107,7 +107,7 @@ def _load():
         "lsum_wait": (I, [VP, I]),
         "lsum_cancel": (I, [VP]),
         "lsum_get_info": (I, [VP, P(lsum_info)]),
-        "lsum_get_canonical": (I, [VP, I, VP, VP, VP, I]),
+        "lsum_get_canonical": (I, [VP, I, VP, VP, VP, P(D), I]),
         "lsum_get_tucker": (I, [VP, VP, VP, VP, VP, I]),
         "lsum_get_sigma": (I, [VP, P(D), P(D), P(D)]),
         "lsum_sample": (I, [VP, I, VP, VP, I]),
@@ -545,12 +545,15 @@ class Request:
         _check(_lib.lsum_get_info(self.handle, C.byref(inf)))
         return inf
 
-    def canonical(self, block: int = 0):
+    def canonical(self, block: int = 0, with_weight: bool = False):
+        """Factors [U0, U1, U2] (R x N_l) of a block's canonical sum, and with with_weight the
+        block's weight (its charge) as a second result."""
         p = self.problem
         inf = self.info()
         U = [np.zeros((inf.R, n)) for n in p.N]
-        _check(_lib.lsum_get_canonical(self.handle, block, *[u.ctypes.data for u in U], 0))
-        return U
+        w = C.c_double(0.0)
+        _check(_lib.lsum_get_canonical(self.handle, block, *[u.ctypes.data for u in U], C.byref(w), 0))
+        return (U, w.value) if with_weight else U
 
     def tucker(self):
         p = self.problem

@@ -276,12 +276,15 @@ static int copy_out(void* dst, const void* src, size_t bytes, int on_device, int
     return LSUM_OK;
 }
 
-int lsum_get_canonical(lsum_req r, int block, double* U0, double* U1, double* U2, int on_device) {
+int lsum_get_canonical(lsum_req r, int block, double* U0, double* U1, double* U2, double* weight,
+                       int on_device) {
     int rc = need_done(r);
     if (rc) return rc;
     Request& q = r->q;
     const Plan& P = q.plan();
     if (block < 0 || block >= (int)P.blocks.size()) return fail(LSUM_E_INVALID, "bad block index");
+    if (P.tucker_ref()) return fail(LSUM_E_STATE, "a Tucker-reference sum keeps no canonical factors");
+    if (weight) *weight = P.blocks[block].charge;
     double* dst[3] = {U0, U1, U2};
     const bool have_vm = q.U[block].p != nullptr;
     DevBuf tmp;
@@ -323,6 +326,7 @@ int lsum_tucker_to_canonical(lsum_req r, double eps, int cap, int* R, double* xi
     Context& c = *q.ctx;
     LSUM_HIP(hipSetDevice(c.device));
     hipStream_t st = c.own_stream;
+    FailStream fs(st);
     // the core on the host in FP64 (it is FP32 at FP32 / BF16X3 precision)
     const size_t plane = (size_t)r1 * r2 * r3;
     std::vector<double> mu(plane);
@@ -415,6 +419,7 @@ int lsum_galerkin(lsum_req r, int nb, const double* G0, const double* G1, const 
     Context& c = *q.ctx;
     LSUM_HIP(hipSetDevice(c.device));
     hipStream_t st = c.own_stream;
+    FailStream fs(st);
     const int r1 = q.r[0], r2 = q.r[1], r3 = q.r[2];
     const long Pn = (long)nb * nb;
     const double* G[3] = {G0, G1, G2};
@@ -515,6 +520,7 @@ int lsum_sample(lsum_req r, int n, const double* xyz, double* out, int on_device
     const Plan& P = q.plan();
     LSUM_HIP(hipSetDevice(c.device));
     hipStream_t st = c.own_stream;
+    FailStream fs(st);
     DevBuf xd, od;
     const double* xyz_d = xyz;
     double* out_d = out;
@@ -676,6 +682,10 @@ int lsum_set_option(lsum_ctx x, int key, double value) {
             if (!(value == 0 || value == 1)) return fail(LSUM_E_INVALID, "Jacobi stop rule must be 0 or 1");
             c.jacobi_rank_stop = value == 1;
             return LSUM_OK;
+        case LSUM_OPT_JACOBI_MAX_SWEEPS:
+            if (!(value >= 1 && value <= 1000)) return fail(LSUM_E_INVALID, "Jacobi sweep limit must be in [1, 1000]");
+            c.jacobi_max_sweeps.store((int)value);
+            return LSUM_OK;
         default:
             return fail(LSUM_E_INVALID, "unknown option");
     }
@@ -723,6 +733,7 @@ int lsum_collocate(lsum_ctx x, void* stream, int R, const double* t, const doubl
     if (R < 1 || N_ref < 1 || ldg < 2 * N_ref - 1 || !(h > 0)) return fail(LSUM_E_INVALID, "bad sizes");
     LSUM_HIP(hipSetDevice(x->c.device));
     hipStream_t st = pick(x, stream);
+    FailStream fs(st);
     std::vector<double> w13(R);
     for (int q = 0; q < R; ++q) {
         if (!(w[q] > 0.0) || !(t[q] >= 0.0)) return fail(LSUM_E_INVALID, "weights must be positive, nodes non-negative");
@@ -748,6 +759,7 @@ int lsum_shift_sum(lsum_ctx x, void* stream, int R, const double* G_dev, int ldg
         if (sites[k] < 0 || sites[k] >= N_axis) return fail(LSUM_E_OUT_OF_BOX, "site index outside the axis");
     LSUM_HIP(hipSetDevice(x->c.device));
     hipStream_t st = pick(x, stream);
+    FailStream fs(st);
     // terms: one per site, or one per comb on windowed strided sums of the rows
     std::vector<int2> terms;
     int stride = 0, n_hi = 0;
@@ -792,6 +804,7 @@ int lsum_sample_canonical(lsum_ctx x, void* stream, int n_fac, int R, const doub
     if (n_fac < 1 || R < 1 || ldu < std::max(N[0], std::max(N[1], N[2])) || n_pts < 0) return fail(LSUM_E_INVALID, "bad sizes");
     LSUM_HIP(hipSetDevice(x->c.device));
     hipStream_t st = pick(x, stream);
+    FailStream fs(st);
     DevBuf ld;
     int rc = ld.get(x->c.pool, n_fac * 8);
     if (rc) return rc;
@@ -809,6 +822,7 @@ int lsum_contract(lsum_ctx x, void* stream, int prec, int m, int n, int k, const
     if (m < 0 || n < 0 || k < 0 || prec < LSUM_FP64 || prec > LSUM_BF16X3) return fail(LSUM_E_INVALID, "bad sizes");
     LSUM_HIP(hipSetDevice(x->c.device));
     hipStream_t st = pick(x, stream);
+    FailStream fs(st);
     GemmArgs a{};
     a.m = m; a.n = n; a.k = k;
     a.A = A_dev; a.sam = sam; a.sak = sak;
@@ -828,6 +842,7 @@ int lsum_jacobi_svd(lsum_ctx x, void* stream, int D, int N, double* A_dev, int l
     if (D < 1 || N < 1 || lda < N || !(tol > 0) || max_sweeps < 1) return fail(LSUM_E_INVALID, "bad sizes");
     LSUM_HIP(hipSetDevice(x->c.device));
     hipStream_t st = pick(x, stream);
+    FailStream fs(st);
     DevBuf work;
     const size_t wb = jacobi_work_bytes(D, N);
     int rc = work.get(x->c.pool, wb);

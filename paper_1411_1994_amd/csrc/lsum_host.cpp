@@ -14,13 +14,24 @@
 namespace lsum {
 
 static thread_local std::string g_last_error;
+static thread_local hipStream_t g_fail_stream = nullptr;
 
 void set_error(const std::string& msg) { g_last_error = msg; }
 
+// An error is raised where it is detected, before the caller unwinds: waiting here for the
+// thread's stream means every kernel queued so far has finished before the unwinding returns
+// its device buffers to the shared pool, from which another slot may take them at once.
 int fail(int code, const std::string& msg) {
     g_last_error = msg;
+    if (g_fail_stream) {
+        (void)hipStreamSynchronize(g_fail_stream);
+        (void)hipGetLastError();
+    }
     return code;
 }
+
+FailStream::FailStream(hipStream_t st) : prev_(g_fail_stream) { g_fail_stream = st; }
+FailStream::~FailStream() { g_fail_stream = prev_; }
 
 const char* last_error() { return g_last_error.c_str(); }
 

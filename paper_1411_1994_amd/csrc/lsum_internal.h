@@ -16,7 +16,21 @@ namespace lsum {
 // error handling
 // ------------------------------------------------------------------------------------------
 void set_error(const std::string& msg);
+// Records the message and returns code.  When the calling thread has a FailStream, fail() first
+// waits for that stream (errors are raised where they are detected, so queued kernels finish
+// before the caller's device buffers unwind into the shared pool).
 int fail(int code, const std::string& msg);
+// Scope in which fail() on this thread waits for `st` (restores the previous stream on exit).
+class FailStream {
+  public:
+    explicit FailStream(hipStream_t st);
+    ~FailStream();
+    FailStream(const FailStream&) = delete;
+    FailStream& operator=(const FailStream&) = delete;
+
+  private:
+    hipStream_t prev_;
+};
 
 #define LSUM_HIP(call)                                                                      \
     do {                                                                                    \

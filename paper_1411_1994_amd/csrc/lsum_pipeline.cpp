@@ -125,7 +125,9 @@ static int range_svd(Context* c, hipStream_t st, int D, int N, const double* W, 
         }
         std::vector<double> sy;
         int sw = 0;
-        if ((rc = jacobi_svd(st, kb, N, Yt.as<double>(), N, 1e-12, 0.0, 40, sy, &sw, work.as<double>(), wb))) return rc;
+        if ((rc = jacobi_svd(st, kb, N, Yt.as<double>(), N, 1e-12, 0.0, c->jacobi_max_sweeps.load(), sy, &sw,
+                             work.as<double>(), wb)))
+            return rc;
         const double keep_rel = blocks == 0 ? 1e-12 : 1e-2;
         int keep = 0;
         while (keep < kb && sy[keep] > keep_rel * sy[0]) ++keep;
@@ -168,7 +170,8 @@ static int range_svd(Context* c, hipStream_t st, int D, int N, const double* W, 
     const size_t wb2 = jacobi_work_bytes(kq, (int)ld);
     if ((rc = work.get(c->pool, wb2))) return rc;
     // the rotated Q rows stay orthonormal in any sweep, so the rank stop needs no extra step here
-    rc = jacobi_svd(st, kq, (int)ld, AUG.as<double>(), (int)ld, 1e-12, irrelevant, 40, out.sigma, &out.sweeps,
+    rc = jacobi_svd(st, kq, (int)ld, AUG.as<double>(), (int)ld, 1e-12, irrelevant, c->jacobi_max_sweeps.load(),
+                    out.sigma, &out.sweeps,
                     work.as<double>(), wb2, D, c->jacobi_rank_stop ? thr * thr - res2 : 0.0);
     if (rc) return rc;
     out.res2 = res2;
@@ -198,7 +201,8 @@ static int mode_svd(Context* c, hipStream_t st, int D, int N, DevBuf& W, double 
     DevBuf work;
     const size_t wb = jacobi_work_bytes(D, N);
     if ((rc = work.get(c->pool, wb))) return rc;
-    rc = jacobi_svd(st, D, N, W.as<double>(), N, 1e-12, irrelevant, 40, out.sigma, &out.sweeps, work.as<double>(),
+    rc = jacobi_svd(st, D, N, W.as<double>(), N, 1e-12, irrelevant, c->jacobi_max_sweeps.load(), out.sigma,
+                    &out.sweeps, work.as<double>(),
                     wb, 0, c->jacobi_rank_stop ? thr * thr : 0.0);
     if (rc) return rc;
     out.res2 = 0.0;
@@ -505,6 +509,7 @@ static int run_tucker(Request* q, hipStream_t st, const hipStream_t* aux, StageT
         for (int l = 0; l < 3; ++l)
             th[l] = std::thread([&, l] {
                 (void)hipSetDevice(c->device);
+                FailStream fs(aux[l]);
                 mrc[l] = svd_one(l, aux[l]);
             });
         for (auto& t : th) t.join();

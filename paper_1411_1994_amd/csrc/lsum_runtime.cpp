@@ -386,6 +386,7 @@ static bool fits(const Context* c, const Request* q) {
 void worker(Context* c, int slot) {
     (void)hipSetDevice(c->device);
     hipStream_t st = c->streams[slot];
+    FailStream fs(st);   // an error inside a batch waits for the slot's queued kernels
     for (;;) {
         std::vector<Request*> batch;
         {

@@ -143,6 +143,7 @@ struct Context {
     int max_batch = 32;              // canonical requests fused into one batch
     int range_min = 512;             // min(D, N) from which side matrices use the range basis
     bool jacobi_rank_stop = true;    // Jacobi SVDs of side matrices end once the certified rank is settled
+    std::atomic<int> jacobi_max_sweeps{40};   // sweeps before a side-matrix SVD fails (LSUM_E_NOCONV)
     std::vector<hipStream_t> streams;
     std::vector<hipStream_t> aux;    // three per slot: the per-mode SVDs of a request run concurrently
     std::vector<std::thread> workers;

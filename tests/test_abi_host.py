@@ -194,7 +194,7 @@ def test_choose_M_errors():
 
 
 # ---------------------------------------------------------------------------------------
-# lattice classes beyond one rectangular block (Sec. 5 cases (B) and (D))
+# lattice classes beyond one rectangular block (Sec. 4.4 cases (B) and (D))
 # ---------------------------------------------------------------------------------------
 
 def test_shear_blocks_enumerate_the_parallelogram_sites():
