@@ -88,3 +88,38 @@ def test_degenerate_lattices_match_direct_sum(L):
         r.release()
     ref = O.brute_force_points(p, cells)
     assert np.max(np.abs(v - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("prec,tol", [(W.FP32, 1e-5), (W.BF16X3, 1e-4)])
+def test_yukawa_step_lattice_512_tile_matches_direct_sum(prec, tol):
+    # The Yukawa (kappa = 0.5) step lattice of three blocks (40x40x20, 40x20x20, 20x20x20; 56,000
+    # sites) with 500 vacancies on the 2049 grid, reduced at eps = 1e-5 and reconstructed on the
+    # centred 512^3 tile by three mode products (eq. Tucker_singePot), in FP32 and in split
+    # BF16x3, as the bench runs it.  At 160 seeded tile cells and 24 of the 4096 sample points the
+    # values are within tol of the oracle's direct sum over all 55,500 charges (relative to the
+    # largest of those values): tol = eps (the certified Frobenius-relative truncation) for FP32,
+    # whose rounding of Z, core and the two tile intermediates stays a few 1e-6; 1e-4 for BF16x3,
+    # whose products are good to about 2^-16 amplified by the cancellation in the Tucker sum.
+    require_gpu()
+    import paper_1411_1994_amd as L
+    p = W.Problem(**{**W.config(4).__dict__, "precision": prec})
+    x = W.sample_points(4, 4096, W.half_widths(p))
+    with L.Context(0) as c:
+        r = c.submit(p, points=x)
+        assert r.wait() == 0, r.stats()
+        inf = r.info()
+        v = r.values.copy()
+        tile = r.tile()
+        r.release()
+    assert tile.shape == (512, 512, 512) and tile.dtype == np.float32
+    assert inf.is_tucker == 1 and inf.rel_bound <= p.eps * (1 + 1e-9)
+    rng = np.random.default_rng(44)
+    loc = np.stack([rng.integers(0, 512, 160) for _ in range(3)], axis=1)
+    loc[0] = (256, 256, 256)                                  # the centre cell (a lattice site)
+    cells = loc + np.array(p.tile_lo)
+    ref = O.brute_force_points(p, cells)
+    got = tile[loc[:, 0], loc[:, 1], loc[:, 2]].astype(np.float64)
+    assert np.max(np.abs(got - ref)) <= tol * np.max(np.abs(ref)), np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    sel = np.random.default_rng(5).choice(len(x), 24, replace=False)
+    refp = O.brute_force_points(p, O.points_to_cells(x[sel], p.h, p.N))
+    assert np.max(np.abs(v[sel] - refp)) <= tol * np.max(np.abs(refp))

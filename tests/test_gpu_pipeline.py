@@ -84,7 +84,8 @@ def test_fp32_canonical_factors(ctx, kind, param):
     u = 2.0 ** -24
     Uo = O.assembled_canonical(p)
     for b in range(2):
-        U = r.canonical(b)
+        U, wb = r.canonical(b, with_weight=True)
+        assert wb == p.blocks[b].charge                 # the block's weight in eq. CP_form
         for a in range(3):
             # the FP64 sums agree with the oracle to 1e-12 (per-row floor for underflowing tails)
             floor = 1e-13 * np.max(np.abs(Uo[b][a]), axis=1, keepdims=True) + 2.0 ** -126
@@ -203,6 +204,12 @@ def test_rhosvd_mixed_precision_error(ctx, prec):
     # (sum |mu||Z||Z||Z| / |V|, about 5 here).  Split-BF16x3 products are good to about 2^-16.
     tol = 6 * 2.0 ** -24 * 5 * 2 if prec == W.FP32 else 1e-4
     assert rel < tol, rel
+    # against the oracle's full tensor (the canonical sum on the whole grid): within the certified
+    # truncation bound (Frobenius) plus the arithmetic error above (max norm, per cell)
+    xi, A = O.canonical_terms(pm)
+    full = O.cp_full(xi, A)
+    inf = rm.info()
+    assert np.max(np.abs(tm - full)) <= inf.bound * (1 + 1e-9) + tol * np.max(np.abs(full))
     # values at points: the mode-3 contraction in the request's precision (Z3 rows, the core and
     # its product rounded to the element type, FP64 sums across chunks), the rest FP64
     rng = np.random.default_rng(17)

@@ -223,3 +223,94 @@ def test_request_set_matches_single_submits():
         assert list(status) == [0] * 5 and all(infos[k].status == 0 for k in range(5))
         for o in outs:
             assert np.array_equal(host(o), alone)
+
+
+def _served_mix(n):
+    """The first n requests of the seeded served mixed workload: rectangular lattices L_l in
+    [8, 96], N up to 4097, Newton / Yukawa / Slater, 0..500 vacancies and impurities, eps in
+    {1e-4 (FP32 contractions), 1e-6 (FP64)}; every one is an RHOSVD request."""
+    return [p for _, p in W.served_stream(n, 1.0)]
+
+
+def test_served_mix_rhosvd_alone_equals_mix_and_oracle():
+    # Eight requests of the served mix (all three kernels, N from 243 to 4097, 59..345 defects,
+    # both eps), each run alone (one slot, no batching) and then all together on three slots,
+    # where their shift-sums, range bases, per-mode Jacobi SVDs and contractions overlap on the
+    # device.  Ranks, certified bounds and values at 64 points are bitwise those of the alone
+    # runs (every kernel sums in a fixed order whatever runs beside it), and at sampled points
+    # each result is within eps (relative to the largest value) of the oracle's direct sum.
+    require_gpu()
+    import paper_1411_1994_amd as L
+    probs = _served_mix(8)
+    assert {p.kind for p in probs} == {0, 1, 2} and {p.eps for p in probs} == {1e-4, 1e-6}
+    assert max(max(p.N) for p in probs) == 4097
+    rng = np.random.default_rng(55)
+    pts = [rng.uniform(-np.array(W.half_widths(p)), np.array(W.half_widths(p)), size=(64, 3)) for p in probs]
+    alone = []
+    with L.Context(0, n_slots=1) as c1:
+        c1.set_option(L.OPT_MAX_BATCH, 1)
+        for i, (p, x) in enumerate(zip(probs, pts)):
+            print(f"alone {i}: kernel {p.kind} N {p.N} defects {len(p.defects)} eps {p.eps}", flush=True)
+            r = c1.submit(p, points=x)
+            assert r.wait() == 0, r.stats()
+            inf = r.info()
+            alone.append((r.values.copy(), tuple(inf.r), inf.bound, inf.norm_A))
+            r.release()
+    with L.Context(0, n_slots=3) as c3:
+        reqs = [c3.submit(p, points=x) for p, x in zip(probs, pts)]
+        for i, (r, (v, ranks, bound, nA)) in enumerate(zip(reqs, alone)):
+            assert r.wait() == 0, r.stats()
+            inf = r.info()
+            assert tuple(inf.r) == ranks and inf.bound == bound and inf.norm_A == nA, i
+            assert np.array_equal(r.values, v), i
+            r.release()
+    for i, (p, x) in enumerate(zip(probs, pts)):
+        sel = [0, 1, 2]
+        ref = O.brute_force_points(p, O.points_to_cells(x[sel], p.h, p.N))
+        err = np.max(np.abs(alone[i][0][sel] - ref)) / np.max(np.abs(ref))
+        assert err <= p.eps, (i, err)
+
+
+def test_request_failing_mid_run_leaves_others_unchanged():
+    # A request made to fail from the host in the middle of its run: with the Jacobi sweep limit
+    # at 1 every side-matrix SVD stops unconverged, so the reduction requests fail with
+    # LSUM_E_NOCONV after their shift-sums, side matrices and norms have run (every kernel exits
+    # normally), while canonical requests on the other slots complete with the values they have
+    # alone.  With the limit restored the same context serves the reduction requests again, with
+    # the values they have on a fresh context.
+    require_gpu()
+    import paper_1411_1994_amd as L
+    canon = mixed_problems(6, seed=71)
+    red = [p for _, p in W.served_stream(3, 1.0, seed_offset=9, L_range=(6, 14), n_choices=(129, 257),
+                                         max_defects=40)]
+    rng = np.random.default_rng(72)
+    pts = [rng.uniform(-np.array(W.half_widths(p)), np.array(W.half_widths(p)), size=(50, 3))
+           for p in canon + red]
+    ref = []
+    with L.Context(0, n_slots=1) as c1:
+        for p, x in zip(canon + red, pts):
+            r = c1.submit(p, points=x)
+            assert r.wait() == 0
+            ref.append(r.values.copy())
+            r.release()
+    with L.Context(0, n_slots=3) as c:
+        c.set_option(L.OPT_JACOBI_MAX_SWEEPS, 1)
+        order = [canon[0], red[0], canon[1], canon[2], red[1], canon[3], red[2], canon[4], canon[5]]
+        reqs = [c.submit(p, points=pts[(canon + red).index(p)]) for p in order]
+        for p, r in zip(order, reqs):
+            rc = r.wait()
+            k = (canon + red).index(p)
+            if p.eps > 0:
+                assert rc == -10, rc                          # LSUM_E_NOCONV, mid-run
+            else:
+                assert rc == 0
+                assert np.array_equal(r.values, ref[k])
+            r.release()
+        c.set_option(L.OPT_JACOBI_MAX_SWEEPS, 40)
+        for k, p in enumerate(canon + red):
+            r = c.submit(p, points=pts[k])
+            assert r.wait() == 0
+            assert np.array_equal(r.values, ref[k])
+            r.release()
+        with pytest.raises(L.LsumError):
+            c.set_option(L.OPT_JACOBI_MAX_SWEEPS, 0)
