@@ -600,6 +600,15 @@ int lsum_get_stats(lsum_req r, char* buf, size_t len) {
             first = false;
         }
         o << "}";
+        if (!q.error.empty()) {
+            o << ",\"error\":\"";
+            for (char ch : q.error) {
+                if (ch == '"' || ch == '\\') o << '\\' << ch;
+                else if ((unsigned char)ch < 0x20) o << ' ';
+                else o << ch;
+            }
+            o << "\"";
+        }
         if (q.started) o << ",\"t_queue_ms\":" << ms_since(q.t_submit, q.t_start);
         if (q.done && q.started) o << ",\"t_run_ms\":" << ms_since(q.t_start, q.t_end);
         o << "}";
@@ -750,13 +759,19 @@ int lsum_collocate(lsum_ctx x, void* stream, int R, const double* t, const doubl
     return LSUM_OK;
 }
 
-int lsum_shift_sum(lsum_ctx x, void* stream, int R, const double* G_dev, int ldg, int N_ref, int N_axis,
-                   int n_sites, const int32_t* sites, double* U_dev, int ldu) {
+static int check_shift_sum_args(lsum_ctx x, int R, const double* G_dev, int ldg, int N_ref, int N_axis,
+                                int n_sites, const int32_t* sites, const double* U_dev, int ldu) {
     if (!x || !G_dev || !U_dev || (n_sites > 0 && !sites)) return fail(LSUM_E_INVALID, "null argument");
     if (R < 1 || N_axis < 1 || N_axis > N_ref || ldg < std::max(2, 2 * N_ref - 1) || ldu < N_axis || n_sites < 0)
         return fail(LSUM_E_INVALID, "bad sizes");
     for (int k = 0; k < n_sites; ++k)
         if (sites[k] < 0 || sites[k] >= N_axis) return fail(LSUM_E_OUT_OF_BOX, "site index outside the axis");
+    return LSUM_OK;
+}
+
+int lsum_shift_sum(lsum_ctx x, void* stream, int R, const double* G_dev, int ldg, int N_ref, int N_axis,
+                   int n_sites, const int32_t* sites, double* U_dev, int ldu) {
+    if (int rc0 = check_shift_sum_args(x, R, G_dev, ldg, N_ref, N_axis, n_sites, sites, U_dev, ldu)) return rc0;
     LSUM_HIP(hipSetDevice(x->c.device));
     hipStream_t st = pick(x, stream);
     FailStream fs(st);

@@ -20,6 +20,8 @@ void set_error(const std::string& msg);
 // waits for that stream (errors are raised where they are detected, so queued kernels finish
 // before the caller's device buffers unwind into the shared pool).
 int fail(int code, const std::string& msg);
+// The calling thread's last error message.
+const char* last_error();
 // Scope in which fail() on this thread waits for `st` (restores the previous stream on exit).
 class FailStream {
   public:

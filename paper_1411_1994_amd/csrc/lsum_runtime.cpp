@@ -102,17 +102,20 @@ StageTimer::~StageTimer() {
 }
 
 void StageTimer::begin(const std::string& name, double bytes, double flops) {
-    Ev e{name, nullptr, nullptr, bytes, flops};
+    Ev e{name, nullptr, nullptr, bytes, flops, false};
     (void)hipEventCreate(&e.a);
     (void)hipEventCreate(&e.b);
     (void)hipEventRecord(e.a, st_);
     ev_.push_back(e);
 }
 
-void StageTimer::end() { (void)hipEventRecord(ev_.back().b, st_); }
+void StageTimer::end() {
+    (void)hipEventRecord(ev_.back().b, st_);
+    ev_.back().closed = true;
+}
 
 KTime StageTimer::kernels(const std::string& name, double bytes, double flops) {
-    Ev e{name, nullptr, nullptr, bytes, flops};
+    Ev e{name, nullptr, nullptr, bytes, flops, true};
     (void)hipEventCreate(&e.a);
     (void)hipEventCreate(&e.b);
     ev_.push_back(e);
@@ -125,8 +128,15 @@ KTime StageTimer::kernels(const std::string& name, double bytes, double flops) {
 void StageTimer::collect(std::map<std::string, double>& out, Context* c) {
     std::lock_guard<std::mutex> lk(c->prof_mu);
     for (auto& e : ev_) {
+        // a stage left open by an error has no stop event; an event that a failed launch never
+        // recorded makes the query fail, and the error it leaves on this thread is cleared so
+        // that the worker's next batch does not report it as its own
+        if (!e.closed) continue;
         float ms = 0;
-        if (hipEventElapsedTime(&ms, e.a, e.b) != hipSuccess) continue;
+        if (hipEventElapsedTime(&ms, e.a, e.b) != hipSuccess) {
+            (void)hipGetLastError();
+            continue;
+        }
         out[e.name] += ms;
         StageStat& s = c->profile[e.name];
         s.ms += ms;
@@ -435,6 +445,10 @@ void worker(Context* c, int slot) {
             // a batch fails as a whole only on a device error; per-request errors are recorded
             int qrc = q->status.load() < 0 ? q->status.load() : rc;
             const size_t keep = qrc == LSUM_OK ? retained_bytes(q) : 0;
+            if (qrc != LSUM_OK) {
+                std::lock_guard<std::mutex> lk(q->mu);
+                if (q->error.empty()) q->error = last_error();
+            }
             {
                 std::lock_guard<std::mutex> lk(c->mu);
                 c->used -= q->reserved;

@@ -210,6 +210,7 @@ struct Request {
     int range_k[3]{};                  // size of the range basis per mode (0: direct)
     std::vector<double> als_core_norm;  // ||core|| after each ALS sweep
     int als_skipped = 0;               // 1: ALS asked for but the ranks do not allow it
+    std::string error;                 // message of a failed request (the worker's last error)
     DevBuf Z[3];                       // r_l x N_l FP64
     DevBuf core;                       // r1 r2 r3, FP64 or FP32 (precision)
     DevBuf tile;
@@ -244,6 +245,7 @@ class StageTimer {
         std::string name;
         hipEvent_t a, b;
         double bytes, flops;
+        bool closed;   // the stop event was recorded (or handed to the stage's last launch)
     };
     hipStream_t st_;
     std::vector<Ev> ev_;

@@ -301,9 +301,9 @@ def test_request_failing_mid_run_leaves_others_unchanged():
             rc = r.wait()
             k = (canon + red).index(p)
             if p.eps > 0:
-                assert rc == -10, rc                          # LSUM_E_NOCONV, mid-run
+                assert rc == -10, (rc, order.index(p), r.stats().get("error"))   # LSUM_E_NOCONV, mid-run
             else:
-                assert rc == 0
+                assert rc == 0, (rc, order.index(p), r.stats().get("error"))
                 assert np.array_equal(r.values, ref[k])
             r.release()
         c.set_option(L.OPT_JACOBI_MAX_SWEEPS, 40)
