@@ -253,6 +253,17 @@ int lsum_collocate(lsum_ctx ctx, void* stream, int R, const double* t, const dou
 int lsum_shift_sum(lsum_ctx ctx, void* stream, int R, const double* G_dev, int ldg, int N_ref,
                    int N_axis, int n_sites, const int32_t* sites, double* U_dev, int ldu);
 
+/* Allocation-free variant of lsum_shift_sum, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).  Same
+ * arguments, result (bitwise) and errors; the job descriptor, term list and window tables live
+ * in a static device array of 64 MiB per device (held until the process ends) instead of pool
+ * memory, so the call makes no allocation.  LSUM_E_NOMEM when the call needs more scratch than
+ * that: 256 B + 8 B per term + up to two R x ldg FP64 window tables.  Every call on a device
+ * shares that device's array: calls that overlap on one device race.  Synchronous. */
+int lsum_shift_sum_noalloc(lsum_ctx ctx, void* stream, int R, const double* G_dev, int ldg,
+                           int N_ref, int N_axis, int n_sites, const int32_t* sites,
+                           double* U_dev, int ldu);
+
 /* Potential of a canonical sum at points (eq. CP_form evaluated pointwise):
  * out_dev[p] = sum_f lam_f sum_q prod_l U_f,l[q, i_l(p)] over n_fac factor sets, where
  * i_l(p) snaps xyz_dev[3p+l]; U_dev holds n_fac sets of 3 axis blocks, each R x ldu

@@ -26,7 +26,7 @@ SUM_CANONICAL, SUM_TUCKER_REF = 0, 1
 
 # every symbol declared in include/lsum.h
 SYMBOLS = ["lsum_nodes", "lsum_block_offsets", "lsum_shear_blocks", "lsum_column_blocks", "lsum_sinc_error", "lsum_choose_M", "lsum_create", "lsum_destroy", "lsum_last_error",
-           "lsum_collocate", "lsum_shift_sum", "lsum_sample_canonical", "lsum_jacobi_svd",
+           "lsum_collocate", "lsum_shift_sum", "lsum_shift_sum_noalloc", "lsum_sample_canonical", "lsum_jacobi_svd",
            "lsum_contract",
            "lsum_submit", "lsum_submit_many", "lsum_wait", "lsum_cancel", "lsum_get_info", "lsum_get_canonical",
            "lsum_get_tucker", "lsum_tucker_to_canonical", "lsum_galerkin", "lsum_get_sigma", "lsum_sample", "lsum_get_tile", "lsum_get_stats",
@@ -96,6 +96,7 @@ def _load():
         "lsum_last_error": (C.c_char_p, []),
         "lsum_collocate": (I, [VP, VP, I, P(D), P(D), I, D, VP, I]),
         "lsum_shift_sum": (I, [VP, VP, I, VP, I, I, I, I, P(C.c_int32), VP, I]),
+        "lsum_shift_sum_noalloc": (I, [VP, VP, I, VP, I, I, I, I, P(C.c_int32), VP, I]),
         "lsum_sample_canonical": (I, [VP, VP, I, I, VP, I, P(D), P(I), D, I, VP, VP]),
         "lsum_jacobi_svd": (I, [VP, VP, I, I, VP, I, D, D, I, P(D), P(I)]),
         "lsum_galerkin": (I, [VP, I, VP, VP, VP, VP, I]),
@@ -303,6 +304,14 @@ class Context:
         _check(_lib.lsum_shift_sum(self.handle, _stream(stream), R, _ptr(G_dev), ldg, N_ref, N_axis,
                                    len(sites), sites.ctypes.data_as(C.POINTER(C.c_int32)),
                                    _ptr(U_dev), ldu))
+
+    def shift_sum_noalloc(self, R: int, G_dev, ldg: int, N_ref: int, N_axis: int, sites: np.ndarray, U_dev,
+                          ldu: int, stream=None):
+        """lsum_shift_sum without allocation (the device's static scratch array)."""
+        sites = np.ascontiguousarray(sites, dtype=np.int32)
+        _check(_lib.lsum_shift_sum_noalloc(self.handle, _stream(stream), R, _ptr(G_dev), ldg, N_ref, N_axis,
+                                           len(sites), sites.ctypes.data_as(C.POINTER(C.c_int32)),
+                                           _ptr(U_dev), ldu))
 
     def sample_canonical(self, n_fac: int, R: int, U_dev, ldu: int, lam: np.ndarray, N, h: float,
                          n_pts: int, xyz_dev, out_dev, stream=None):

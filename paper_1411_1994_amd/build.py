@@ -21,7 +21,7 @@ LIBDIR = os.path.join(HERE, "lib")
 LIB = os.path.join(LIBDIR, "liblsum.so")
 
 SOURCES = ["lsum_host.cpp", "lsum_sinc_error.cpp", "lsum_runtime.cpp", "lsum_pipeline.cpp", "lsum_capi.cpp",
-           "kernels_lattice.hip", "kernels_gemm.hip", "kernels_jacobi.hip"]
+           "kernels_lattice.hip", "kernels_gemm.hip", "kernels_jacobi.hip", "scratch_noalloc.hip"]
 
 # Packed FP32 instructions are disabled for all device code (only hand-checked FP32 paths).
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

@@ -812,6 +812,59 @@ int lsum_shift_sum(lsum_ctx x, void* stream, int R, const double* G_dev, int ldg
     return LSUM_OK;
 }
 
+// The same steps and kernels as lsum_shift_sum, with the job descriptor, the terms and the
+// window tables in the device's static scratch array instead of pool memory: no allocation.
+int lsum_shift_sum_noalloc(lsum_ctx x, void* stream, int R, const double* G_dev, int ldg, int N_ref, int N_axis,
+                           int n_sites, const int32_t* sites, double* U_dev, int ldu) {
+    if (int rc0 = check_shift_sum_args(x, R, G_dev, ldg, N_ref, N_axis, n_sites, sites, U_dev, ldu)) return rc0;
+    LSUM_HIP(hipSetDevice(x->c.device));
+    hipStream_t st = pick(x, stream);
+    FailStream fs(st);
+    std::vector<int2> terms;
+    int stride = 0, n_hi = 0;
+    bool two = false;
+    shift_terms(sites, n_sites, N_ref, terms, &stride, &n_hi, &two);
+    // scratch layout (256-byte aligned parts): job | terms | window table 0 | window table 1
+    auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t off_terms = up(sizeof(ShiftJob));
+    const size_t off_w0 = off_terms + up(std::max<size_t>(1, terms.size()) * sizeof(int2));
+    const size_t tab = up((size_t)R * ldg * 8);
+    const size_t need = off_w0 + (stride > 0 ? (two ? 2 : 1) * tab : 0);
+    if (need > kNoallocScratchBytes)
+        return fail(LSUM_E_NOMEM, "lsum_shift_sum_noalloc needs " + std::to_string(need) +
+                                      " bytes of scratch; the static array holds " +
+                                      std::to_string(kNoallocScratchBytes));
+    void* base = nullptr;
+    if (int rc = noalloc_scratch(x->c.device, &base)) return rc;
+    unsigned char* sp = static_cast<unsigned char*>(base);
+    ShiftJob j{};
+    j.T0 = G_dev;
+    if (stride > 0) {
+        double* w0 = reinterpret_cast<double*>(sp + off_w0);
+        launch_window_sums(st, R, G_dev, ldg, stride, n_hi, w0);
+        j.T0 = w0;
+        if (two) {
+            double* w1 = reinterpret_cast<double*>(sp + off_w0 + tab);
+            launch_window_sums(st, R, G_dev, ldg, stride, n_hi - 1, w1);
+            j.T1 = w1;
+        }
+    }
+    j.terms = reinterpret_cast<const int2*>(sp + off_terms);
+    j.n_terms = (int)terms.size();
+    j.U = U_dev;
+    j.ldu = ldu;
+    j.N_axis = N_axis;
+    j.ldg = ldg;
+    j.R = R;
+    if (!terms.empty())
+        LSUM_HIP(hipMemcpyAsync(sp + off_terms, terms.data(), terms.size() * sizeof(int2), hipMemcpyHostToDevice, st));
+    LSUM_HIP(hipMemcpyAsync(sp, &j, sizeof(j), hipMemcpyHostToDevice, st));
+    launch_shift_sum(st, reinterpret_cast<const ShiftJob*>(sp), 1, N_axis, R);
+    LSUM_HIP(hipGetLastError());
+    LSUM_HIP(hipStreamSynchronize(st));   // the host job and terms are read before return
+    return LSUM_OK;
+}
+
 int lsum_sample_canonical(lsum_ctx x, void* stream, int n_fac, int R, const double* U_dev, int ldu,
                           const double* lam, const int N[3], double h, int n_pts, const double* xyz_dev,
                           double* out_dev) {

@@ -172,6 +172,11 @@ void launch_shift_sum(hipStream_t st, const ShiftJob* jobs_dev, int n_jobs, int 
                       const KTime* kt = nullptr);
 // Q[q, x] = sum_{m=0}^{n-1} G[q, x - m S] over the terms with x - m S >= 0, for x < ldg.
 void launch_window_sums(hipStream_t st, int R, const double* G, int ldg, int stride, int n, double* Q);
+// The static scratch array of the allocation-free shift-sum (scratch_noalloc.hip): its size, and
+// its address on `device` (taken once per device with hipGetSymbolAddress; `device` current).
+constexpr size_t kNoallocScratchBytes = (size_t)64 << 20;
+constexpr int kMaxDevices = 64;
+int noalloc_scratch(int device, void** ptr);
 // Host: the smallest period p <= max_p with c[k+p] - c[k] constant (its stride), or 0.
 int comb_period(const int32_t* c, int n, int max_p, int* stride);
 // Host: the terms of one axis.  When the ascending sites c[0..n) are `period` interleaved
