@@ -311,6 +311,118 @@ __global__ void __launch_bounds__(256) k_random_signs(long n, unsigned long long
     out[i] = (z & 1ull) ? 1.0 : -1.0;
 }
 
+// Rank-revealing Cholesky of a Gram matrix and the inverse of its factor, in one workgroup (the
+// orthonormalisation of a block of sketch rows: Y_p = R^T Q_b with Q_b orthonormal, Q_b =
+// R^{-T} Y_p).  Phase 1 (right-looking, in A): at step j the largest remaining diagonal entry is
+// moved to position j (with `pivot`), row j of R is A's row divided by sqrt of the pivot, and the
+// trailing block loses the outer product of that row.  Positions are addressed through
+// perm (no rows are moved); the factorisation stops at the first pivot <= tau2 times the first.
+// Phase 2: T = R^{-1} column by column, T[i][j] = -(sum_{k=i}^{j-1} T[i][k] R[k][j]) / R[j][j],
+// one thread per row i, R's column j staged in LDS.  Phase 3: M[j][perm[i]] = T[i][j].
+constexpr int PC_THREADS = 1024;
+constexpr int PC_MAXN = 512;
+
+__global__ void __launch_bounds__(PC_THREADS) k_pchol_inverse(int n, double* __restrict__ A, double tau2, int pivot,
+                                                              double* __restrict__ M, double* __restrict__ T,
+                                                              int* __restrict__ keep_dev) {
+    __shared__ int perm[PC_MAXN];
+    __shared__ double col[PC_MAXN];
+    __shared__ double wv[PC_THREADS / 64];
+    __shared__ int wi[PC_THREADS / 64];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    constexpr int NW = PC_THREADS / 64;
+    for (int i = tid; i < n; i += PC_THREADS) perm[i] = i;
+    __syncthreads();
+    double d0 = 0.0;
+    int keep = n;
+    for (int j = 0; j < n; ++j) {
+        if (pivot) {
+            // the largest remaining diagonal entry (ties: the first position)
+            double bv = -__builtin_huge_val();
+            int bi = n;
+            for (int i = j + tid; i < n; i += PC_THREADS) {
+                const double v = A[(size_t)perm[i] * n + perm[i]];
+                if (v > bv) {
+                    bv = v;
+                    bi = i;
+                }
+            }
+            for (int off = 32; off > 0; off >>= 1) {
+                const double ov = __shfl_xor(bv, off);
+                const int oi = __shfl_xor(bi, off);
+                if (ov > bv || (ov == bv && oi < bi)) {
+                    bv = ov;
+                    bi = oi;
+                }
+            }
+            if (lane == 0) {
+                wv[wave] = bv;
+                wi[wave] = bi;
+            }
+            __syncthreads();
+            if (tid == 0) {
+                double b = wv[0];
+                int ib = wi[0];
+                for (int w = 1; w < NW; ++w)
+                    if (wv[w] > b || (wv[w] == b && wi[w] < ib)) {
+                        b = wv[w];
+                        ib = wi[w];
+                    }
+                if (ib < n) {   // no candidate (NaN diagonal): no swap, and the step below stops
+                    const int t = perm[j];
+                    perm[j] = perm[ib];
+                    perm[ib] = t;
+                }
+            }
+            __syncthreads();
+        }
+        const int pj = perm[j];
+        const double d = A[(size_t)pj * n + pj];
+        if (j == 0) d0 = d;
+        if (!(d > 0.0) || !(d > tau2 * d0)) {   // the same value on every thread: a uniform exit
+            keep = j;
+            break;
+        }
+        const double rjj = sqrt(d);
+        __syncthreads();   // every thread has read the pivot before row j is overwritten
+        double* __restrict__ aj = A + (size_t)pj * n;
+        for (int k = j + 1 + tid; k < n; k += PC_THREADS) aj[perm[k]] /= rjj;
+        if (tid == 0) aj[pj] = rjj;
+        __syncthreads();
+        // the whole trailing block (both triangles: later pivots reorder the positions, so an
+        // entry's place relative to the diagonal is not fixed): one wave per row, lanes along it
+        for (int i = j + 1 + wave; i < n; i += NW) {
+            double* __restrict__ ai = A + (size_t)perm[i] * n;
+            const double rji = aj[perm[i]];
+            for (int k = j + 1 + lane; k < n; k += 64) ai[perm[k]] -= rji * aj[perm[k]];
+        }
+        __syncthreads();
+    }
+    // T = R^{-1} (pivot order, row-major n x n workspace), R[a][b] = A[perm[a]][perm[b]], a <= b
+    for (int j = 0; j < keep; ++j) {
+        for (int k = tid; k <= j; k += PC_THREADS) col[k] = A[(size_t)perm[k] * n + perm[j]];
+        __syncthreads();
+        const double inv = 1.0 / col[j];
+        for (int i = tid; i <= j; i += PC_THREADS) {
+            if (i == j) {
+                T[(size_t)i * n + j] = inv;
+            } else {
+                const double* __restrict__ ti = T + (size_t)i * n;
+                double sacc = 0.0;
+                for (int k = i; k < j; ++k) sacc += ti[k] * col[k];
+                T[(size_t)i * n + j] = -sacc * inv;
+            }
+        }
+        __syncthreads();
+    }
+    // M rows 0..keep-1: M[j][perm[i]] = T[i][j] for i <= j, else 0
+    for (int e = tid; e < keep * n; e += PC_THREADS) {
+        const int j = e / n, i = e % n;
+        M[(size_t)j * n + perm[i]] = i <= j ? T[(size_t)i * n + j] : 0.0;
+    }
+    if (tid == 0) *keep_dev = keep;
+}
+
 inline unsigned cdiv(long a, long b) { return (unsigned)((a + b - 1) / b); }
 
 struct JacobiLayout {
@@ -343,6 +455,11 @@ JacobiLayout layout(int D, int N, int n_gram) {
 }  // namespace
 
 size_t jacobi_work_bytes(int D, int N) { return layout(D, N, N).total; }
+
+void launch_pchol_inverse(hipStream_t st, int n, double* A, double tau2, int pivot, double* M, double* T,
+                          int* keep_dev) {
+    hipLaunchKernelGGL(k_pchol_inverse, dim3(1), dim3(PC_THREADS), 0, st, n, A, tau2, pivot, M, T, keep_dev);
+}
 
 void launch_random_signs(hipStream_t st, long n, unsigned long long seed, double* out) {
     if (n <= 0) return;

@@ -302,6 +302,14 @@ int jacobi_svd(hipStream_t st, int D, int N, double* A, int lda, double tol, dou
 size_t jacobi_work_bytes(int D, int N);
 // out[i] = +-1, i < n, a deterministic function of (seed, i)
 void launch_random_signs(hipStream_t st, long n, unsigned long long seed, double* out);
+// Rank-revealing Cholesky of a symmetric positive semi-definite n x n matrix A (row-major,
+// n <= 512; destroyed): with `pivot`, the largest remaining diagonal is taken first, and the
+// factorisation stops at the first step whose pivot is <= tau2 times the first one (or not
+// positive).  With keep steps done (written to *keep_dev), the rows 0..keep-1 of M (n x n,
+// row-major) hold T^T P^T, T = R^{-1}: for the rows Y of a matrix with Gram A, M Y has
+// orthonormal rows spanning the kept pivot rows.  T: n x n workspace.  One workgroup.
+void launch_pchol_inverse(hipStream_t st, int n, double* A, double tau2, int pivot, double* M, double* T,
+                          int* keep_dev);
 
 // type conversions
 void launch_f64_to_f32(hipStream_t st, long n, const double* x, float* y);

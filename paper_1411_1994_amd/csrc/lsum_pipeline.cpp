@@ -86,27 +86,57 @@ static int frob2(Context* c, hipStream_t st, int rows, int n, const double* X, d
     return LSUM_OK;
 }
 
+// G (m x m) = X X^T for the m rows of X (length n, stride ldx); split over n when G has few tiles.
+static int gram_rows(Context* c, hipStream_t st, int m, int n, const double* X, long ldx, double* G) {
+    GemmArgs a{};
+    a.m = m; a.n = m; a.k = n;
+    a.A = X; a.sam = ldx; a.sak = 1;
+    a.B = X; a.sbk = 1; a.sbn = ldx;
+    a.C = G; a.scm = m; a.scn = 1;
+    a.alpha = 1.0; a.beta = 0.0; a.batch = 1;
+    return gemm_auto(c, st, GEMM_F64, a);
+}
+
+// Orthonormal rows spanning the significant rows of Y (m x n, stride n): the rank-revealing
+// Cholesky of Y Y^T keeps pivots above tau2 times the first (rows above sqrt(tau2) in norm), and
+// out (keep x n) = M Y with M = R^{-T} P^T.  Returns keep (0: nothing above the threshold).
+static int chol_rows(Context* c, hipStream_t st, int m, int n, const double* Y, double tau2, double* small,
+                     double* out, int* keep) {
+    double* G = small;
+    double* Mm = small + (size_t)m * m;
+    double* Tm = Mm + (size_t)m * m;
+    int* kd = (int*)(Tm + (size_t)m * m);
+    int rc;
+    if ((rc = gram_rows(c, st, m, n, Y, n, G))) return rc;
+    launch_pchol_inverse(st, m, G, tau2, 1, Mm, Tm, kd);
+    LSUM_HIP(hipGetLastError());
+    LSUM_HIP(hipMemcpyAsync(keep, kd, sizeof(int), hipMemcpyDeviceToHost, st));
+    LSUM_HIP(hipStreamSynchronize(st));
+    if (*keep > 0) gemm_rm(st, *keep, n, m, Mm, m, false, Y, n, false, out, n, 1.0, 0.0);
+    return LSUM_OK;
+}
+
 // Range basis grown in blocks (a blocked form of the adaptive randomized range finder): each
-// block sketches the current residual E (Y = Omega^T E, random signs), is orthogonalised twice
-// against the basis so far and orthonormalised by Jacobi; E loses the block's directions, and
-// the growth stops once ||E||_F <= thr / 10 or the basis would exceed k_max rows.  The first
-// block keeps every sketch row above 1e-12 of its largest; later blocks keep rows above 1e-2 of
-// theirs, so that the rounding left by the re-orthogonalisation stays at the Jacobi tolerance
-// relative to every kept row.  B = Q W^T and E = W - B^T Q are then recomputed from W, and
-// Jacobi on the rows [B | Q] (Gram over B) gives the singular vectors.
+// block sketches the current residual E (Y = Omega^T E, random signs) and is orthogonalised
+// twice against the basis so far.  Its significant rows (down to 1e-6 of the largest in norm)
+// are made orthonormal by the rank-revealing Cholesky of their Gram, once more orthogonalised
+// against the basis and orthonormalised by a second Cholesky pass (CholeskyQR2: orthonormal to
+// rounding); E then loses the block's directions.  The growth stops once ||E||_F <= thr / 10 or
+// the basis would exceed k_max rows.  B = Q W^T and E = W - B^T Q are then recomputed from W,
+// and Jacobi on the rows [B | Q] (Gram over B) gives the singular vectors.
 static int range_svd(Context* c, hipStream_t st, int D, int N, const double* W, int k_block, int k_max,
                      double thr, double irrelevant, ModeSVD& out, bool* enough) {
     int rc;
     *enough = false;
     if (k_block < 16 || k_max < k_block) return LSUM_OK;
-    DevBuf Qall, E, Om, Yt, P, work;
+    DevBuf Qall, E, Om, Yt, Y2, P, small;
     if ((rc = Qall.get(c->pool, (size_t)k_max * N * 8))) return rc;
     if ((rc = E.get(c->pool, (size_t)D * N * 8))) return rc;
     if ((rc = Om.get(c->pool, (size_t)D * k_block * 8))) return rc;
     if ((rc = Yt.get(c->pool, (size_t)k_block * N * 8))) return rc;
+    if ((rc = Y2.get(c->pool, (size_t)k_block * N * 8))) return rc;
     if ((rc = P.get(c->pool, (size_t)std::max(D, k_block) * k_max * 8))) return rc;
-    const size_t wb = jacobi_work_bytes(k_block, N);
-    if ((rc = work.get(c->pool, wb))) return rc;
+    if ((rc = small.get(c->pool, (size_t)3 * k_block * k_block * 8 + 256))) return rc;
     LSUM_HIP(hipMemcpyAsync(E.p, W, (size_t)D * N * 8, hipMemcpyDeviceToDevice, st));
     double* Q = Qall.as<double>();
     int kq = 0, blocks = 0;
@@ -123,28 +153,25 @@ static int range_svd(Context* c, hipStream_t st, int D, int N, const double* W, 
             gemm_rm(st, kb, kq, N, Yt.as<double>(), N, false, Q, N, true, P.as<double>(), kq, 1.0, 0.0);
             gemm_rm(st, kb, N, kq, P.as<double>(), kq, false, Q, N, false, Yt.as<double>(), N, -1.0, 1.0);
         }
-        std::vector<double> sy;
-        int sw = 0;
-        if ((rc = jacobi_svd(st, kb, N, Yt.as<double>(), N, 1e-12, 0.0, c->jacobi_max_sweeps.load(), sy, &sw,
-                             work.as<double>(), wb)))
-            return rc;
-        const double keep_rel = blocks == 0 ? 1e-12 : 1e-2;
         int keep = 0;
-        while (keep < kb && sy[keep] > keep_rel * sy[0]) ++keep;
+        if ((rc = chol_rows(c, st, kb, N, Yt.as<double>(), 1e-12, small.as<double>(), Y2.as<double>(), &keep)))
+            return rc;
         if (keep == 0) return LSUM_OK;
-        std::vector<double> inv(keep);
-        for (int i = 0; i < keep; ++i) inv[i] = 1.0 / sy[i];
-        DevBuf iv;
-        if ((rc = iv.get(c->pool, (size_t)keep * 8))) return rc;
-        LSUM_HIP(hipMemcpyAsync(iv.p, inv.data(), (size_t)keep * 8, hipMemcpyHostToDevice, st));
+        if (kq > 0) {
+            gemm_rm(st, keep, kq, N, Y2.as<double>(), N, false, Q, N, true, P.as<double>(), kq, 1.0, 0.0);
+            gemm_rm(st, keep, N, kq, P.as<double>(), kq, false, Q, N, false, Y2.as<double>(), N, -1.0, 1.0);
+        }
         double* Qb = Q + (size_t)kq * N;
-        launch_scale_rows(st, keep, N, Yt.as<double>(), N, iv.as<double>(), Qb, N);
+        int keep2 = 0;
+        if ((rc = chol_rows(c, st, keep, N, Y2.as<double>(), 1e-12, small.as<double>(), Qb, &keep2))) return rc;
+        if (keep2 == 0) return LSUM_OK;
+        keep = keep2;
         // E -= (E Qb^T) Qb
         gemm_rm(st, D, keep, N, E.as<double>(), N, false, Qb, N, true, P.as<double>(), keep, 1.0, 0.0);
         gemm_rm(st, D, N, keep, P.as<double>(), keep, false, Qb, N, false, E.as<double>(), N, -1.0, 1.0);
         kq += keep;
         ++blocks;
-        if ((rc = frob2(c, st, D, N, E.as<double>(), &res2))) return rc;   // synchronises (iv may go)
+        if ((rc = frob2(c, st, D, N, E.as<double>(), &res2))) return rc;   // synchronises
         if (std::getenv("LSUM_JACOBI_TRACE"))
             std::fprintf(stderr, "range D=%d N=%d block %d kept %d of %d basis %d of %d residual/thr %.3e\n", D, N,
                          blocks, keep, kb, kq, k_max, std::sqrt(res2) / thr);
@@ -152,8 +179,9 @@ static int range_svd(Context* c, hipStream_t st, int D, int N, const double* W, 
     }
     Om.reset();
     Yt.reset();
+    Y2.reset();
     P.reset();
-    work.reset();
+    small.reset();
     // AUG rows [B_a | Q_a]: B (kq x D) = Q W^T, and the exact residual E = W - B^T Q
     const long ld = (long)D + N;
     DevBuf AUG;
@@ -167,6 +195,7 @@ static int range_svd(Context* c, hipStream_t st, int D, int N, const double* W, 
     if (!(std::sqrt(res2) <= 0.1 * thr)) return LSUM_OK;   // basis too small
     E.reset();
     Qall.reset();
+    DevBuf work;
     const size_t wb2 = jacobi_work_bytes(kq, (int)ld);
     if ((rc = work.get(c->pool, wb2))) return rc;
     // the rotated Q rows stay orthonormal in any sweep, so the rank stop needs no extra step here
