@@ -229,6 +229,10 @@ const char* lsum_last_error(void);
  * whose SVD has not converged by then fails with LSUM_E_NOCONV (a bound on its latency).  Read
  * when a request's SVD starts. */
 #define LSUM_OPT_JACOBI_MAX_SWEEPS 5
+/* LSUM_OPT_GRAPHS (default 1): each sweep of a Jacobi SVD (the same kernel launches for the
+ * same number of column blocks) is captured once in a HIP graph and replayed; 0 launches the
+ * kernels one by one.  Results are the same bit for bit. */
+#define LSUM_OPT_GRAPHS 6
 int lsum_set_option(lsum_ctx ctx, int key, double value);
 /* Per stage (collocate, shift_sum, transpose, columns, norm, svd, projection, core, tile,
  * sample): summed event-timed GPU milliseconds, number of timed launches, and the algorithmic

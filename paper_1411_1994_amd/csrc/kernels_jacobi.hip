@@ -46,9 +46,10 @@ __device__ __forceinline__ void pair_of(int n, int round, int i, int* a, int* b)
 __device__ __forceinline__ int pair_row(int I, int J, int k) { return k < 8 ? I * 8 + k : J * 8 + (k - 8); }
 
 // 1. Gram partials: part[(pair * nchunk + chunk) * 256 + a*16 + b]
-__global__ void __launch_bounds__(256) k_pair_gram(const double* __restrict__ X, int ldx, int n_gram, int nblk,
+__global__ void __launch_bounds__(256) k_pair_gram(double* const* __restrict__ xp, int ldx, int n_gram, int nblk,
                                                    int round, int nchunk, double* __restrict__ part) {
     __shared__ double Gp[4][16][17];
+    const double* __restrict__ X = xp[0];
     const int chunk = blockIdx.x, pair = blockIdx.y;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int r = lane & 15, kg = lane >> 4;
@@ -119,12 +120,13 @@ constexpr int EIG_LOADS = 16;   // chunk partials in flight per thread
 // Besides the coupling of the pair (stat[0]) it records the largest coupling among columns whose
 // squared norms both exceed keep2 (stat[4]).
 __global__ void __launch_bounds__(256) k_pair_eig(int nchunk, const double* __restrict__ part, double tol,
-                                                  double irr2, double keep2, int max_inner,
+                                                  double irr2, const double* __restrict__ keep2p, int max_inner,
                                                   double* __restrict__ Qout,
                                                   int* __restrict__ active, unsigned long long* __restrict__ stat) {
     __shared__ double G[16][17];
     __shared__ double Q[16][17];
     const int pair = blockIdx.x, tid = threadIdx.x;
+    const double keep2 = *keep2p;
     {
         // entry tid over the chunks in chunk order; the loads of a group are issued together so
         // that the sum waits on one memory latency per EIG_LOADS chunks (indices past the last
@@ -227,11 +229,12 @@ __global__ void __launch_bounds__(256) k_pair_eig(int nchunk, const double* __re
 }
 
 // 3. rotation of the pair's 16 columns over one chunk: X_pair <- Q^T X_pair
-__global__ void __launch_bounds__(256) k_pair_rotate(double* __restrict__ X, int ldx, int nblk, int round,
+__global__ void __launch_bounds__(256) k_pair_rotate(double* const* __restrict__ xp, int ldx, int nblk, int round,
                                                      const double* __restrict__ Qin,
                                                      const int* __restrict__ active) {
     const int chunk = blockIdx.x, pair = blockIdx.y;
     if (!active[pair]) return;
+    double* __restrict__ X = xp[0];
     __shared__ double Q[16][17];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int r = lane & 15, kg = lane >> 4;
@@ -265,6 +268,44 @@ __global__ void __launch_bounds__(256) k_pair_rotate(double* __restrict__ X, int
                 X[(size_t)pair_row(I, J, kg + 4 * v) * ldx + col] = acc[t][v];   // FP64 MFMA result layout
         }
     }
+}
+
+// Sweep prologue and epilogue on the current / other buffer pair xp = {current, other}: rows of
+// the current buffer permuted into the other; then the pair swapped and the sweep statistics
+// cleared (one thread; a kernel, not a memset, so that a captured sweep holds no memset node);
+// after the rounds, the squared norms of the current rows.
+__global__ void __launch_bounds__(256) k_permute_xp(int ldx, const int32_t* __restrict__ perm,
+                                                    double* const* __restrict__ xp) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int row = blockIdx.y;
+    if (i >= ldx) return;
+    const double* __restrict__ X = xp[0];
+    double* __restrict__ Y = xp[1];
+    Y[(size_t)row * ldx + i] = X[(size_t)perm[row] * ldx + i];
+}
+
+__global__ void k_swap_clear(double** __restrict__ xp, unsigned long long* __restrict__ stat) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double* t = xp[0];
+        xp[0] = xp[1];
+        xp[1] = t;
+        for (int k = 0; k < 5; ++k) stat[k] = 0ull;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_norms_xp(int ldx, int n_gram, double* const* __restrict__ xp,
+                                                  double* __restrict__ nrm) {
+    __shared__ double red[256];
+    const double* x = xp[0] + (size_t)blockIdx.x * ldx;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n_gram; i += 256) acc += x[i] * x[i];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) nrm[blockIdx.x] = red[0];
 }
 
 __global__ void __launch_bounds__(256) k_copy_rows_in(int D, int N, const double* __restrict__ A, int lda,
@@ -428,7 +469,7 @@ inline unsigned cdiv(long a, long b) { return (unsigned)((a + b - 1) / b); }
 struct JacobiLayout {
     int Dp, ldx, nblk, npair, nchunk;   // nchunk: Gram chunks (over the first n_gram entries)
     int nchunk_all;                      // rotation chunks (whole rows)
-    size_t off_x2, off_nrm, off_perm, off_stat, off_part, off_q, off_act, total;
+    size_t off_x2, off_nrm, off_perm, off_stat, off_part, off_q, off_act, off_ptr, total;
 };
 
 JacobiLayout layout(int D, int N, int n_gram) {
@@ -448,7 +489,8 @@ JacobiLayout layout(int D, int N, int n_gram) {
     L.off_part = al(L.off_stat + 64);
     L.off_q = al(L.off_part + (size_t)L.npair * L.nchunk * 256 * sizeof(double));
     L.off_act = al(L.off_q + (size_t)L.npair * 256 * sizeof(double));
-    L.total = al(L.off_act + (size_t)L.npair * sizeof(int));
+    L.off_ptr = al(L.off_act + (size_t)L.npair * sizeof(int));   // {current, other} buffer, keep2
+    L.total = al(L.off_ptr + 3 * sizeof(double));
     return L;
 }
 
@@ -466,23 +508,34 @@ void launch_random_signs(hipStream_t st, long n, unsigned long long seed, double
     hipLaunchKernelGGL(k_random_signs, dim3(cdiv(n, 256)), dim3(256), 0, st, n, seed, out);
 }
 
-// Squared norms of the rows of X, and the permutation sorting them in descending order.
-static int sorted_norms(hipStream_t st, const JacobiLayout& L, int n_gram, double* X, char* base,
-                        std::vector<double>& sig2, std::vector<int32_t>& perm) {
-    double* nrm = (double*)(base + L.off_nrm);
-    hipLaunchKernelGGL(k_norms, dim3(L.Dp), dim3(256), 0, st, L.ldx, n_gram, X, nrm);
-    sig2.resize(L.Dp);
-    LSUM_HIP(hipMemcpyAsync(sig2.data(), nrm, L.Dp * sizeof(double), hipMemcpyDeviceToHost, st));
-    LSUM_HIP(hipStreamSynchronize(st));
-    perm.resize(L.Dp);
+// The permutation sorting squared row norms in descending order.
+static void sort_norms(const std::vector<double>& sig2, std::vector<int32_t>& perm) {
+    perm.resize(sig2.size());
     std::iota(perm.begin(), perm.end(), 0);
     std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) { return sig2[a] > sig2[b]; });
-    return LSUM_OK;
 }
+
+namespace {
+
+// Executable graphs of the sweep for one call, keyed by the number of column blocks (which only
+// changes when columns drop below the irrelevance floor); destroyed with the call.
+struct SweepGraphs {
+    std::vector<std::pair<int, hipGraphExec_t>> execs;
+    ~SweepGraphs() {
+        for (auto& e : execs) (void)hipGraphExecDestroy(e.second);
+    }
+    hipGraphExec_t find(int nblk) const {
+        for (auto& e : execs)
+            if (e.first == nblk) return e.second;
+        return nullptr;
+    }
+};
+
+}  // namespace
 
 int jacobi_svd(hipStream_t st, int D, int N, double* A, int lda, double tol, double irrelevant, int max_sweeps,
                std::vector<double>& sigma, int* sweeps_out, double* work_dev, size_t work_bytes, int n_gram,
-               double stop_tail2) {
+               double stop_tail2, int graphs) {
     if (n_gram <= 0 || n_gram > N) n_gram = N;
     if (D <= 0 || N <= 0) return fail(LSUM_E_INVALID, "empty side matrix");
     const JacobiLayout L = layout(D, N, n_gram);
@@ -490,57 +543,100 @@ int jacobi_svd(hipStream_t st, int D, int N, double* A, int lda, double tol, dou
     char* base = (char*)work_dev;
     double* X = (double*)base;
     double* X2 = (double*)(base + L.off_x2);
+    double* nrm = (double*)(base + L.off_nrm);
     int32_t* perm_dev = (int32_t*)(base + L.off_perm);
     unsigned long long* stat = (unsigned long long*)(base + L.off_stat);
     double* part = (double*)(base + L.off_part);
     double* Qd = (double*)(base + L.off_q);
     int* act = (int*)(base + L.off_act);
+    double** xp_dev = (double**)(base + L.off_ptr);
+    double* keep2_dev = (double*)(base + L.off_ptr + 2 * sizeof(double*));
+    // host values read by asynchronous copies: they live until the call returns, and every sweep
+    // synchronises before they change
+    double* xp_host[2] = {X, X2};
+    double keep2 = 0.0;
+    LSUM_HIP(hipMemcpyAsync(xp_dev, xp_host, sizeof(xp_host), hipMemcpyHostToDevice, st));
     hipLaunchKernelGGL(k_copy_rows_in, dim3(cdiv(L.ldx, 256), L.Dp), dim3(256), 0, st, D, N, A, lda, X, L.ldx);
-    std::vector<double> sig2;
+    hipLaunchKernelGGL(k_norms, dim3(L.Dp), dim3(256), 0, st, L.ldx, n_gram, X, nrm);
+    std::vector<double> sig2(L.Dp);
     std::vector<int32_t> perm;
-    int rc = sorted_norms(st, L, n_gram, X, base, sig2, perm);
-    if (rc) return rc;
+    LSUM_HIP(hipMemcpyAsync(sig2.data(), nrm, L.Dp * sizeof(double), hipMemcpyDeviceToHost, st));
+    LSUM_HIP(hipStreamSynchronize(st));
+    sort_norms(sig2, perm);
     // columns this small cannot move the certified tail; below 1e-15 sigma_max they are rounding
     const double smax2 = sig2[perm[0]];
     const double irr2 = std::max(irrelevant * irrelevant, 1e-30 * smax2);
     const bool trace = std::getenv("LSUM_JACOBI_TRACE") != nullptr;
-    // inner cyclic sweeps per visit of a pair.  Two keep the outer sweep count of inner solves
-    // run to convergence at a quarter of the inner work (measured on the defected 48^3 and
-    // step-lattice side matrices).  With many pairs per round the round time is the pair
-    // solve's latency, and one inner sweep is faster overall even though it costs about one
-    // more outer sweep (cfg3 side matrices: SVD 147 -> 134 ms); with few pairs and long rows
-    // the Gram and rotation passes dominate a round, and the second inner sweep pays for
-    // itself (few tens of columns of 5633-34305 cells: 30-50 % slower with one).
-    int sweeps = 0;
+    // One sweep: permute the rows (largest first) into the other buffer and make it current, then
+    // nblk - 1 rounds of (pair Grams, pair solves, rotations), then the new row norms.  Every
+    // sweep with the same nblk issues the same launches; the buffers and keep2 are read from
+    // device memory, so one captured graph replays any such sweep.
+    auto enqueue_sweep = [&](int nblk) {
+        const int npair = nblk / 2;
+        // inner cyclic sweeps per visit of a pair.  Two keep the outer sweep count of inner
+        // solves run to convergence at a quarter of the inner work (measured on the defected 48^3
+        // and step-lattice side matrices).  With many pairs per round the round time is the pair
+        // solve's latency, and one inner sweep is faster overall even though it costs about one
+        // more outer sweep (cfg3 side matrices: SVD 147 -> 134 ms); with few pairs and long rows
+        // the Gram and rotation passes dominate a round, and the second inner sweep pays for
+        // itself (few tens of columns of 5633-34305 cells: 30-50 % slower with one).
+        const int max_inner = npair >= 16 ? 1 : 2;
+        hipLaunchKernelGGL(k_permute_xp, dim3(cdiv(L.ldx, 256), L.Dp), dim3(256), 0, st, L.ldx, perm_dev, xp_dev);
+        hipLaunchKernelGGL(k_swap_clear, dim3(1), dim3(64), 0, st, xp_dev, stat);
+        for (int round = 0; round < nblk - 1; ++round) {
+            hipLaunchKernelGGL(k_pair_gram, dim3(L.nchunk, npair), dim3(256), 0, st, xp_dev, L.ldx, n_gram, nblk,
+                               round, L.nchunk, part);
+            hipLaunchKernelGGL(k_pair_eig, dim3(npair), dim3(256), 0, st, L.nchunk, part, tol, irr2, keep2_dev,
+                               max_inner, Qd, act, stat);
+            hipLaunchKernelGGL(k_pair_rotate, dim3(L.nchunk_all, npair), dim3(256), 0, st, xp_dev, L.ldx, nblk,
+                               round, Qd, act);
+        }
+        hipLaunchKernelGGL(k_norms_xp, dim3(L.Dp), dim3(256), 0, st, L.ldx, n_gram, xp_dev, nrm);
+    };
+    SweepGraphs cache;
+    int sweeps = 0, cur = 0;
     bool converged = false;
     // rank stop: the certified rank of the current rows, and the squared norm above which rows
     // count as kept (the rank plus a margin of max(16, r/8) rows; 0: every row)
     int r_prev = -1;
-    double keep2 = 0.0;
     for (; sweeps < max_sweeps && !converged; ++sweeps) {
         // only columns above the floor take part (sorted first); the rest are never rotated
         int d_act = 0;
         while (d_act < L.Dp && sig2[perm[d_act]] > irr2) ++d_act;
         const int nblk = std::max(2, (d_act + 15) / 16 * 2);
-        const int npair = nblk / 2;
-        const int max_inner = npair >= 16 ? 1 : 2;
         LSUM_HIP(hipMemcpyAsync(perm_dev, perm.data(), L.Dp * sizeof(int32_t), hipMemcpyHostToDevice, st));
-        hipLaunchKernelGGL(k_permute_rows, dim3(cdiv(L.ldx, 256), L.Dp), dim3(256), 0, st, L.ldx, perm_dev, X, X2,
-                           L.ldx, L.ldx);
-        std::swap(X, X2);
-        LSUM_HIP(hipMemsetAsync(stat, 0, 5 * sizeof(unsigned long long), st));
-        for (int round = 0; round < nblk - 1; ++round) {
-            hipLaunchKernelGGL(k_pair_gram, dim3(L.nchunk, npair), dim3(256), 0, st, X, L.ldx, n_gram, nblk,
-                               round, L.nchunk, part);
-            hipLaunchKernelGGL(k_pair_eig, dim3(npair), dim3(256), 0, st, L.nchunk, part, tol, irr2, keep2,
-                               max_inner, Qd, act, stat);
-            hipLaunchKernelGGL(k_pair_rotate, dim3(L.nchunk_all, npair), dim3(256), 0, st, X, L.ldx, nblk, round,
-                               Qd, act);
+        LSUM_HIP(hipMemcpyAsync(keep2_dev, &keep2, sizeof(double), hipMemcpyHostToDevice, st));
+        hipGraphExec_t ge = graphs ? cache.find(nblk) : nullptr;
+        if (graphs && !ge) {
+            // capture the sweep once per block count; if capture is refused, launch directly
+            hipGraph_t g = nullptr;
+            bool ok = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess;
+            if (ok) {
+                enqueue_sweep(nblk);
+                ok = hipStreamEndCapture(st, &g) == hipSuccess && g != nullptr;
+            }
+            if (ok) ok = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) == hipSuccess;
+            if (g) (void)hipGraphDestroy(g);
+            if (ok) {
+                cache.execs.push_back({nblk, ge});
+            } else {
+                (void)hipGetLastError();
+                ge = nullptr;
+                graphs = 0;
+            }
         }
+        if (ge) {
+            LSUM_HIP(hipGraphLaunch(ge, st));
+        } else {
+            enqueue_sweep(nblk);
+        }
+        cur ^= 1;
         unsigned long long st4[5] = {0, 0, 0, 0, 0};
         LSUM_HIP(hipMemcpyAsync(st4, stat, sizeof(st4), hipMemcpyDeviceToHost, st));
-        rc = sorted_norms(st, L, n_gram, X, base, sig2, perm);   // synchronises
-        if (rc) return rc;
+        LSUM_HIP(hipMemcpyAsync(sig2.data(), nrm, L.Dp * sizeof(double), hipMemcpyDeviceToHost, st));
+        LSUM_HIP(hipStreamSynchronize(st));
+        LSUM_HIP(hipGetLastError());
+        sort_norms(sig2, perm);
         double off, offk;
         std::memcpy(&off, &st4[0], sizeof(off));
         std::memcpy(&offk, &st4[4], sizeof(offk));
@@ -567,14 +663,15 @@ int jacobi_svd(hipStream_t st, int D, int N, double* A, int lda, double tol, dou
             keep2 = m < L.Dp ? sig2[perm[m]] : 0.0;
         }
         if (trace)
-            std::fprintf(stderr, "jacobi D=%d N=%d sweep %d active %d max coupling %.3e kept %.3e rank %d inner sweeps %.2f avg %llu max over %llu pairs\n",
+            std::fprintf(stderr, "jacobi D=%d N=%d sweep %d active %d max coupling %.3e kept %.3e rank %d inner sweeps %.2f avg %llu max over %llu pairs%s\n",
                          D, N, sweeps, d_act, off, offk, r_now, st4[3] ? (double)st4[1] / (double)st4[3] : 0.0, st4[2],
-                         st4[3]);
+                         st4[3], ge ? " (graph)" : "");
     }
-    LSUM_HIP(hipGetLastError());
     // write back the D largest columns in descending order
+    double* Xcur = cur ? X2 : X;
     LSUM_HIP(hipMemcpyAsync(perm_dev, perm.data(), L.Dp * sizeof(int32_t), hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(k_permute_rows, dim3(cdiv(N, 256), D), dim3(256), 0, st, L.ldx, perm_dev, X, A, lda, N);
+    hipLaunchKernelGGL(k_permute_rows, dim3(cdiv(N, 256), D), dim3(256), 0, st, L.ldx, perm_dev, Xcur, A, lda, N);
+    LSUM_HIP(hipGetLastError());
     LSUM_HIP(hipStreamSynchronize(st));
     sigma.resize(D);
     for (int a = 0; a < D; ++a) sigma[a] = std::sqrt(std::max(sig2[perm[a]], 0.0));

@@ -695,6 +695,10 @@ int lsum_set_option(lsum_ctx x, int key, double value) {
             if (!(value >= 1 && value <= 1000)) return fail(LSUM_E_INVALID, "Jacobi sweep limit must be in [1, 1000]");
             c.jacobi_max_sweeps.store((int)value);
             return LSUM_OK;
+        case LSUM_OPT_GRAPHS:
+            if (!(value == 0 || value == 1)) return fail(LSUM_E_INVALID, "graph option must be 0 or 1");
+            c.graphs.store((int)value);
+            return LSUM_OK;
         default:
             return fail(LSUM_E_INVALID, "unknown option");
     }
@@ -916,7 +920,8 @@ int lsum_jacobi_svd(lsum_ctx x, void* stream, int D, int N, double* A_dev, int l
     int rc = work.get(x->c.pool, wb);
     if (rc) return rc;
     std::vector<double> s;
-    rc = jacobi_svd(st, D, N, A_dev, lda, tol, irrelevant, max_sweeps, s, sweeps, work.as<double>(), wb);
+    rc = jacobi_svd(st, D, N, A_dev, lda, tol, irrelevant, max_sweeps, s, sweeps, work.as<double>(), wb, 0, 0.0,
+                    x->c.graphs.load());
     std::copy(s.begin(), s.end(), sigma);
     return rc;
 }

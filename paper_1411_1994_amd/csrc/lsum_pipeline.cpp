@@ -201,7 +201,7 @@ static int range_svd(Context* c, hipStream_t st, int D, int N, const double* W, 
     // the rotated Q rows stay orthonormal in any sweep, so the rank stop needs no extra step here
     rc = jacobi_svd(st, kq, (int)ld, AUG.as<double>(), (int)ld, 1e-12, irrelevant, c->jacobi_max_sweeps.load(),
                     out.sigma, &out.sweeps,
-                    work.as<double>(), wb2, D, c->jacobi_rank_stop ? thr * thr - res2 : 0.0);
+                    work.as<double>(), wb2, D, c->jacobi_rank_stop ? thr * thr - res2 : 0.0, c->graphs.load());
     if (rc) return rc;
     out.res2 = res2;
     out.rows = std::move(AUG);
@@ -232,7 +232,7 @@ static int mode_svd(Context* c, hipStream_t st, int D, int N, DevBuf& W, double 
     if ((rc = work.get(c->pool, wb))) return rc;
     rc = jacobi_svd(st, D, N, W.as<double>(), N, 1e-12, irrelevant, c->jacobi_max_sweeps.load(), out.sigma,
                     &out.sweeps, work.as<double>(),
-                    wb, 0, c->jacobi_rank_stop ? thr * thr : 0.0);
+                    wb, 0, c->jacobi_rank_stop ? thr * thr : 0.0, c->graphs.load());
     if (rc) return rc;
     out.res2 = 0.0;
     out.rows = std::move(W);
@@ -398,7 +398,7 @@ static int run_als(Request* q, hipStream_t st, DevBuf cols[3], StageTimer& tm) {
                 const size_t wb = jacobi_work_bytes(N, (int)ld);
                 if ((rc = work.get(c->pool, wb))) return rc;
                 rc = jacobi_svd(st, N, (int)ld, Mr.as<double>(), (int)ld, 1e-12, 0.0, 40, ms.sigma, &ms.sweeps,
-                                work.as<double>(), wb, D);
+                                work.as<double>(), wb, D, 0.0, c->graphs.load());
                 if (rc) return rc;
                 ms.rows = std::move(Mr);
                 ms.ld = ld;

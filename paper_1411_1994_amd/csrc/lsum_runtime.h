@@ -144,6 +144,7 @@ struct Context {
     int range_min = 512;             // min(D, N) from which side matrices use the range basis
     bool jacobi_rank_stop = true;    // Jacobi SVDs of side matrices end once the certified rank is settled
     std::atomic<int> jacobi_max_sweeps{40};   // sweeps before a side-matrix SVD fails (LSUM_E_NOCONV)
+    std::atomic<int> graphs{1};               // Jacobi sweeps captured in HIP graphs and replayed
     std::vector<hipStream_t> streams;
     std::vector<hipStream_t> aux;    // three per slot: the per-mode SVDs of a request run concurrently
     std::vector<std::thread> workers;
