@@ -535,7 +535,7 @@ struct SweepGraphs {
 
 int jacobi_svd(hipStream_t st, int D, int N, double* A, int lda, double tol, double irrelevant, int max_sweeps,
                std::vector<double>& sigma, int* sweeps_out, double* work_dev, size_t work_bytes, int n_gram,
-               double stop_tail2, int graphs) {
+               double stop_tail2, int graphs, double* flops_out) {
     if (n_gram <= 0 || n_gram > N) n_gram = N;
     if (D <= 0 || N <= 0) return fail(LSUM_E_INVALID, "empty side matrix");
     const JacobiLayout L = layout(D, N, n_gram);
@@ -631,6 +631,9 @@ int jacobi_svd(hipStream_t st, int D, int N, double* A, int lda, double tol, dou
             enqueue_sweep(nblk);
         }
         cur ^= 1;
+        // FP64 MFMA work of the sweep: every pair visit forms a 16 x 16 Gram over n_gram entries
+        // and (when active) rotates 16 rows of ldx entries; counted for every visit
+        if (flops_out) *flops_out += (double)(nblk / 2) * (nblk - 1) * 512.0 * ((double)n_gram + L.ldx);
         unsigned long long st4[5] = {0, 0, 0, 0, 0};
         LSUM_HIP(hipMemcpyAsync(st4, stat, sizeof(st4), hipMemcpyDeviceToHost, st));
         LSUM_HIP(hipMemcpyAsync(sig2.data(), nrm, L.Dp * sizeof(double), hipMemcpyDeviceToHost, st));

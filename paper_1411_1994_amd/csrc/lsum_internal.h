@@ -298,9 +298,11 @@ void launch_cp_norm2(hipStream_t st, int R, int n_groups, const int32_t* src1, c
 // rows are then bounds, not singular values (their squared sum bounds the true tail from above).
 // With `graphs` each sweep (the same launches for the same number of column blocks) is captured
 // once in a HIP graph and replayed; otherwise its kernels are launched one by one (same results).
+// flops_out (if given) accumulates the FP64 MFMA work of the pair Grams and rotations.
 int jacobi_svd(hipStream_t st, int D, int N, double* A, int lda, double tol, double irrelevant,
                int max_sweeps, std::vector<double>& sigma, int* sweeps_out, double* work_dev,
-               size_t work_bytes, int n_gram = 0, double stop_tail2 = 0.0, int graphs = 1);
+               size_t work_bytes, int n_gram = 0, double stop_tail2 = 0.0, int graphs = 1,
+               double* flops_out = nullptr);
 size_t jacobi_work_bytes(int D, int N);
 // out[i] = +-1, i < n, a deterministic function of (seed, i)
 void launch_random_signs(hipStream_t st, long n, unsigned long long seed, double* out);

@@ -57,6 +57,7 @@ struct ModeSVD {
     long ld = 0, off = 0;        // row stride, offset of the vector part
     bool unit = false;           // vector rows are unit (range path) or sigma-scaled (direct)
     int k = 0, sweeps = 0;
+    double flops = 0.0;          // FP64 MFMA work: range-basis GEMMs, Jacobi Grams and rotations
 };
 
 // C (m x n) = alpha * X Y + beta * C over row-major operands; tX / tY: use the transpose.
@@ -148,6 +149,7 @@ static int range_svd(Context* c, hipStream_t st, int D, int N, const double* W, 
                             Om.as<double>());
         // Yt (kb x N) = Omega^T E
         gemm_rm(st, kb, N, D, Om.as<double>(), kb, true, E.as<double>(), N, false, Yt.as<double>(), N, 1.0, 0.0);
+        out.flops += 2.0 * kb * (double)N * D + 8.0 * kb * (double)kq * N * (kq > 0) + 2.0 * kb * (double)kb * N;
         for (int pass = 0; kq > 0 && pass < 2; ++pass) {
             // Yt -= (Yt Q^T) Q
             gemm_rm(st, kb, kq, N, Yt.as<double>(), N, false, Q, N, true, P.as<double>(), kq, 1.0, 0.0);
@@ -166,6 +168,8 @@ static int range_svd(Context* c, hipStream_t st, int D, int N, const double* W, 
         if ((rc = chol_rows(c, st, keep, N, Y2.as<double>(), 1e-12, small.as<double>(), Qb, &keep2))) return rc;
         if (keep2 == 0) return LSUM_OK;
         keep = keep2;
+        out.flops += 2.0 * keep * (double)kb * N + 4.0 * keep * (double)kq * N + 4.0 * keep * (double)keep * N +
+                     4.0 * D * (double)keep * N;
         // E -= (E Qb^T) Qb
         gemm_rm(st, D, keep, N, E.as<double>(), N, false, Qb, N, true, P.as<double>(), keep, 1.0, 0.0);
         gemm_rm(st, D, N, keep, P.as<double>(), keep, false, Qb, N, false, E.as<double>(), N, -1.0, 1.0);
@@ -191,6 +195,7 @@ static int range_svd(Context* c, hipStream_t st, int D, int N, const double* W, 
     gemm_rm(st, kq, D, N, Q, N, false, W, N, true, AUG.as<double>(), ld, 1.0, 0.0);
     LSUM_HIP(hipMemcpyAsync(E.p, W, (size_t)D * N * 8, hipMemcpyDeviceToDevice, st));
     gemm_rm(st, D, N, kq, AUG.as<double>(), ld, true, AUG.as<double>() + D, ld, false, E.as<double>(), N, -1.0, 1.0);
+    out.flops += 4.0 * kq * (double)D * N;
     if ((rc = frob2(c, st, D, N, E.as<double>(), &res2))) return rc;
     if (!(std::sqrt(res2) <= 0.1 * thr)) return LSUM_OK;   // basis too small
     E.reset();
@@ -201,7 +206,8 @@ static int range_svd(Context* c, hipStream_t st, int D, int N, const double* W, 
     // the rotated Q rows stay orthonormal in any sweep, so the rank stop needs no extra step here
     rc = jacobi_svd(st, kq, (int)ld, AUG.as<double>(), (int)ld, 1e-12, irrelevant, c->jacobi_max_sweeps.load(),
                     out.sigma, &out.sweeps,
-                    work.as<double>(), wb2, D, c->jacobi_rank_stop ? thr * thr - res2 : 0.0, c->graphs.load());
+                    work.as<double>(), wb2, D, c->jacobi_rank_stop ? thr * thr - res2 : 0.0, c->graphs.load(),
+                    &out.flops);
     if (rc) return rc;
     out.res2 = res2;
     out.rows = std::move(AUG);
@@ -232,7 +238,7 @@ static int mode_svd(Context* c, hipStream_t st, int D, int N, DevBuf& W, double 
     if ((rc = work.get(c->pool, wb))) return rc;
     rc = jacobi_svd(st, D, N, W.as<double>(), N, 1e-12, irrelevant, c->jacobi_max_sweeps.load(), out.sigma,
                     &out.sweeps, work.as<double>(),
-                    wb, 0, c->jacobi_rank_stop ? thr * thr : 0.0, c->graphs.load());
+                    wb, 0, c->jacobi_rank_stop ? thr * thr : 0.0, c->graphs.load(), &out.flops);
     if (rc) return rc;
     out.res2 = 0.0;
     out.rows = std::move(W);
@@ -545,13 +551,16 @@ static int run_tucker(Request* q, hipStream_t st, const hipStream_t* aux, StageT
     } else {
         for (int l = 0; l < 3; ++l) mrc[l] = svd_one(l, st);
     }
+    double svd_flops = 0.0;
     for (int l = 0; l < 3; ++l) {
         if (mrc[l]) return fail(mrc[l], "SVD of mode " + std::to_string(l) + " failed");
         q->sigma[l] = ms[l].sigma;
         q->sweeps[l] = ms[l].sweeps;
         q->range_k[l] = ms[l].k;
         q->range_res[l] = std::sqrt(ms[l].res2);
+        svd_flops += ms[l].flops;
     }
+    tm.work(0, svd_flops);
     tm.end();
 
     // certified truncation: tail(r)^2 = res2 + sum_{a >= r} sigma_a^2 <= thr^2

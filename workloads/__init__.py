@@ -202,3 +202,15 @@ def served_stream(n: int, rate_per_s: float, seed_offset: int = 5, **kw):
     gaps = rng.exponential(1.0 / rate_per_s, size=n)
     t = np.cumsum(gaps)
     return [(float(t[i]), served_request(rng, i, **kw)) for i in range(n)]
+
+
+def served_mix_stream(count: int, n_total: int = 10_000):
+    """The first ``count`` requests of the served mixed workload of ``n_total`` requests with
+    Poisson arrivals: (gap at unit rate, Problem) pairs.  All ``n_total`` gaps are drawn first,
+    then the requests in order, so a prefix is the same for any ``count``; arrival times at rate
+    lam are the cumulative gaps divided by lam."""
+    if count > n_total:
+        raise ValueError("count exceeds the stream")
+    rng = np.random.default_rng(SEED_BASE + 5)
+    gaps = rng.exponential(1.0, size=n_total)
+    return [(float(gaps[i]), served_request(rng, i)) for i in range(count)]
