@@ -229,10 +229,20 @@ const char* lsum_last_error(void);
  * whose SVD has not converged by then fails with LSUM_E_NOCONV (a bound on its latency).  Read
  * when a request's SVD starts. */
 #define LSUM_OPT_JACOBI_MAX_SWEEPS 5
-/* LSUM_OPT_GRAPHS (default 1): each sweep of a Jacobi SVD (the same kernel launches for the
- * same number of column blocks) is captured once in a HIP graph and replayed; 0 launches the
- * kernels one by one.  Results are the same bit for bit. */
+/* How the sweeps of a Jacobi SVD are launched; every way gives the same results bit for bit.
+ * Default: round by round (three launches per round of disjoint column-block pairs).
+ * LSUM_OPT_JACOBI_PERSISTENT (default 0): a sweep is one launch with one workgroup per pair of
+ * column blocks, its rounds ordered by per-block completion counters in device memory; it runs
+ * persistently while the persistent workgroups in flight fit 3/4 of the device, else round by
+ * round.  Each wait is bounded by LSUM_OPT_JACOBI_WAIT_US (default 500000 microseconds, 0..1e8):
+ * when the workgroups are not all resident at once the sweep aborts (the rows stay an
+ * orthogonal transform of the input; lsum_get_stats counts such sweeps in "jacobi_aborted") and
+ * the rest of that SVD launches round by round.
+ * LSUM_OPT_GRAPHS (default 0; applies when not persistent): the round-by-round launches of a
+ * sweep are captured once per block count in a HIP graph and replayed. */
 #define LSUM_OPT_GRAPHS 6
+#define LSUM_OPT_JACOBI_PERSISTENT 7
+#define LSUM_OPT_JACOBI_WAIT_US 8
 int lsum_set_option(lsum_ctx ctx, int key, double value);
 /* Per stage (collocate, shift_sum, transpose, columns, norm, svd, projection, core, tile,
  * sample): summed event-timed GPU milliseconds, number of timed launches, and the algorithmic

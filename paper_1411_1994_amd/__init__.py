@@ -32,6 +32,7 @@ SYMBOLS = ["lsum_nodes", "lsum_block_offsets", "lsum_shear_blocks", "lsum_column
            "lsum_get_tucker", "lsum_tucker_to_canonical", "lsum_galerkin", "lsum_get_sigma", "lsum_sample", "lsum_get_tile", "lsum_get_stats",
            "lsum_release", "lsum_finish_many", "lsum_set_option", "lsum_get_profile", "lsum_reset_profile"]
 OPT_MAX_BATCH, OPT_REF_CACHE_BYTES, OPT_RANGE_MIN, OPT_JACOBI_STOP, OPT_JACOBI_MAX_SWEEPS, OPT_GRAPHS = 1, 2, 3, 4, 5, 6
+OPT_JACOBI_PERSISTENT, OPT_JACOBI_WAIT_US = 7, 8
 
 
 class LsumError(RuntimeError):

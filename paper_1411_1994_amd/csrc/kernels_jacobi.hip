@@ -21,6 +21,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 
 #include "lsum_internal.h"
@@ -116,36 +117,13 @@ __device__ __forceinline__ void rotation(double a, double d, double b, double ir
 
 constexpr int EIG_LOADS = 16;   // chunk partials in flight per thread
 
-// 256 threads sum the chunk partials (one Gram entry each); one wavefront then solves.
-// Besides the coupling of the pair (stat[0]) it records the largest coupling among columns whose
-// squared norms both exceed keep2 (stat[4]).
-__global__ void __launch_bounds__(256) k_pair_eig(int nchunk, const double* __restrict__ part, double tol,
-                                                  double irr2, const double* __restrict__ keep2p, int max_inner,
-                                                  double* __restrict__ Qout,
-                                                  int* __restrict__ active, unsigned long long* __restrict__ stat) {
-    __shared__ double G[16][17];
-    __shared__ double Q[16][17];
-    const int pair = blockIdx.x, tid = threadIdx.x;
-    const double keep2 = *keep2p;
-    {
-        // entry tid over the chunks in chunk order; the loads of a group are issued together so
-        // that the sum waits on one memory latency per EIG_LOADS chunks (indices past the last
-        // chunk repeat it and add 0)
-        const double* __restrict__ pp = part + (size_t)pair * nchunk * 256 + tid;
-        double s = 0.0;
-        for (int c = 0; c < nchunk; c += EIG_LOADS) {
-            double v[EIG_LOADS];
-#pragma unroll
-            for (int k = 0; k < EIG_LOADS; ++k) v[k] = pp[(size_t)min(c + k, nchunk - 1) * 256];
-#pragma unroll
-            for (int k = 0; k < EIG_LOADS; ++k) s += c + k < nchunk ? v[k] : 0.0;
-        }
-        G[tid >> 4][tid & 15] = s;
-        Q[tid >> 4][tid & 15] = ((tid >> 4) == (tid & 15)) ? 1.0 : 0.0;
-    }
-    __syncthreads();
-    if (tid >= 64) return;   // the solve below uses wavefront barriers only
-    const int lane = tid;
+// The 16 x 16 pair problem in LDS, solved by the 64 lanes of one wavefront (lane = its index):
+// the pair's coupling is recorded (stat[0]; stat[4]: the largest coupling among columns whose
+// squared norms both exceed keep2) and, unless the pair is already orthogonal to tol, G and Q
+// (entering as the identity) are updated by cyclic two-sided Jacobi.  Returns whether the pair
+// is to be rotated.
+__device__ __forceinline__ bool solve_pair(int lane, double (*G)[17], double (*Q)[17], double tol, double irr2, double keep2,
+                           int max_inner, unsigned long long* __restrict__ stat) {
     // coupling of relevant pairs (both squared norms above the irrelevance floor)
     double off = 0.0, offk = 0.0;
     for (int e = lane; e < 256; e += 64) {
@@ -169,9 +147,8 @@ __global__ void __launch_bounds__(256) k_pair_eig(int nchunk, const double* __re
         atomicMax(stat, bits);   // non-negative doubles order like their bit patterns
         std::memcpy(&bits, &offk, sizeof(bits));
         atomicMax(stat + 4, bits);
-        active[pair] = off > tol ? 1 : 0;
     }
-    if (!(off > tol)) return;
+    if (!(off > tol)) return false;
     // Each step applies 8 disjoint rotations at once: G <- J^T G J, Q <- Q J.  With the step's
     // pairing, index i of pair (p, q) maps to alpha_i row_i + beta_i row_partner, (alpha, beta) =
     // (c, -s) for p and (c, s) for q; lane (bi, bj) owns the 2x2 blocks {p_bi, q_bi} x {p_bj, q_bj}
@@ -225,7 +202,40 @@ __global__ void __launch_bounds__(256) k_pair_eig(int nchunk, const double* __re
         atomicMax(stat + 2, (unsigned long long)nsw);
         atomicAdd(stat + 3, 1ull);
     }
-    for (int e = lane; e < 256; e += 64) Qout[(size_t)pair * 256 + e] = Q[e >> 4][e & 15];
+    return true;
+}
+
+// 256 threads sum the chunk partials (one Gram entry each); one wavefront then solves.
+__global__ void __launch_bounds__(256) k_pair_eig(int nchunk, const double* __restrict__ part, double tol,
+                                                  double irr2, const double* __restrict__ keep2p, int max_inner,
+                                                  double* __restrict__ Qout,
+                                                  int* __restrict__ active, unsigned long long* __restrict__ stat) {
+    __shared__ double G[16][17];
+    __shared__ double Q[16][17];
+    const int pair = blockIdx.x, tid = threadIdx.x;
+    const double keep2 = *keep2p;
+    {
+        // entry tid over the chunks in chunk order; the loads of a group are issued together so
+        // that the sum waits on one memory latency per EIG_LOADS chunks (indices past the last
+        // chunk repeat it and add 0)
+        const double* __restrict__ pp = part + (size_t)pair * nchunk * 256 + tid;
+        double s = 0.0;
+        for (int c = 0; c < nchunk; c += EIG_LOADS) {
+            double v[EIG_LOADS];
+#pragma unroll
+            for (int k = 0; k < EIG_LOADS; ++k) v[k] = pp[(size_t)min(c + k, nchunk - 1) * 256];
+#pragma unroll
+            for (int k = 0; k < EIG_LOADS; ++k) s += c + k < nchunk ? v[k] : 0.0;
+        }
+        G[tid >> 4][tid & 15] = s;
+        Q[tid >> 4][tid & 15] = ((tid >> 4) == (tid & 15)) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    if (tid >= 64) return;   // the solve uses wavefront barriers only
+    const bool act = solve_pair(tid, G, Q, tol, irr2, keep2, max_inner, stat);
+    if (tid == 0) active[pair] = act ? 1 : 0;
+    if (!act) return;
+    for (int e = tid; e < 256; e += 64) Qout[(size_t)pair * 256 + e] = Q[e >> 4][e & 15];
 }
 
 // 3. rotation of the pair's 16 columns over one chunk: X_pair <- Q^T X_pair
@@ -270,6 +280,142 @@ __global__ void __launch_bounds__(256) k_pair_rotate(double* const* __restrict__
     }
 }
 
+// A whole sweep in one launch: workgroup p owns pair slot p of every round of the round robin.
+// A round on blocks (I, J) starts once both blocks have finished the previous round (their
+// version counters, set with release order after the rows are written; read with acquire
+// order), so no launch boundary separates the rounds.  Per pair the steps are those of the
+// three-kernel round, in the same arithmetic order: the 16 x 16 Gram over chunks of CW cells
+// (per chunk the four waves' MFMA partials ((w0 + w1) + w2) + w3, the chunks summed in order),
+// the pair solve, and the rotation of the pair's rows chunk by chunk.  Every wait is bounded by
+// tick_limit ticks of the constant-rate wall clock: a group that runs out raises the abort
+// flag, and every group leaves at its next wait once the flag is up.  A group rotates only
+// pairs it has started, so an aborted sweep leaves the rows an orthogonal transform of the
+// input.
+constexpr int PS_WAVES = 16;   // waves of a persistent pair group: four chunks of CW cells at a time
+
+__global__ void __launch_bounds__(PS_WAVES * 64) k_jacobi_sweep(double* const* __restrict__ xp, int ldx, int n_gram,
+                                                      int nblk, int nchunk, int nchunk_all, double tol, double irr2,
+                                                      const double* __restrict__ keep2p, int max_inner,
+                                                      unsigned long long* __restrict__ stat, int* __restrict__ ver,
+                                                      int* __restrict__ abort_flag, long long tick_limit) {
+    __shared__ double Gp[PS_WAVES][16][17];
+    __shared__ double G[16][17];
+    __shared__ double Q[16][17];
+    __shared__ int sh_go, sh_act;
+    const int p = blockIdx.x;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int r = lane & 15, kg = lane >> 4;
+    const int ga = (tid >> 4) & 15, gb = tid & 15;
+    const int sub = wave >> 2, quarter = wave & 3;   // chunk within a step of four, quarter of it
+    double* X = xp[0];   // not restrict: other groups write its rows between the rounds
+    const double keep2 = *keep2p;
+    const long long t0 = (long long)wall_clock64();
+    for (int round = 0; round < nblk - 1; ++round) {
+        int I, J;
+        pair_of(nblk, round, p, &I, &J);
+        if (tid == 0) {
+            int go = 1;
+            for (;;) {
+                // relaxed polling; one acquire fence once both counters are there
+                const int vi = __hip_atomic_load(ver + I, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const int vj = __hip_atomic_load(ver + J, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (vi >= round && vj >= round) {
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                    break;
+                }
+                if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                    go = 0;
+                    break;
+                }
+                if ((long long)wall_clock64() - t0 > tick_limit) {
+                    __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    go = 0;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+            sh_go = go;
+        }
+        __syncthreads();
+        if (!sh_go) return;   // the same value on every thread
+        // the rows other groups wrote: thread 0's acquire fence above invalidated this compute
+        // unit's caches; the barrier orders every wave's loads after it
+        // 1. the pair's Gram: wave (sub, quarter) takes quarter `quarter` of chunk step + sub
+        const double* xr = X + (size_t)pair_row(I, J, r) * ldx;
+        double gsum = 0.0;
+        for (int step = 0; step < nchunk; step += 4) {
+            const int c0 = (step + sub) * CW + quarter * (CW / 4);
+            double x[16];
+#pragma unroll
+            for (int s2 = 0; s2 < 16; ++s2) {
+                const int c = c0 + 4 * s2 + kg;
+                x[s2] = c < n_gram ? xr[c] : 0.0;
+            }
+            d4 acc = {0, 0, 0, 0};
+#pragma unroll
+            for (int s2 = 0; s2 < 16; ++s2) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x[s2], x[s2], acc, 0, 0, 0);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) Gp[wave][kg + 4 * v][r] = acc[v];
+            __syncthreads();
+            if (tid < 256)
+                for (int cc = 0; cc < 4 && step + cc < nchunk; ++cc)
+                    gsum += ((Gp[4 * cc][ga][gb] + Gp[4 * cc + 1][ga][gb]) + Gp[4 * cc + 2][ga][gb]) +
+                            Gp[4 * cc + 3][ga][gb];
+            __syncthreads();
+        }
+        if (tid < 256) {
+            G[ga][gb] = gsum;
+            Q[ga][gb] = ga == gb ? 1.0 : 0.0;
+        }
+        __syncthreads();
+        // 2. the pair solve (one wavefront)
+        if (tid < 64) {
+            const bool act = solve_pair(tid, G, Q, tol, irr2, keep2, max_inner, stat);
+            if (tid == 0) sh_act = act ? 1 : 0;
+        }
+        __syncthreads();
+        // 3. X_pair <- Q^T X_pair, four chunks at a time (each wave owns 64 cells of one)
+        if (sh_act) {
+            for (int step = 0; step < nchunk_all; step += 4) {
+                const int c0 = (step + sub) * CW + quarter * (CW / 4);
+                double b[4][4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+#pragma unroll
+                    for (int k0 = 0; k0 < 4; ++k0) {
+                        const int col = c0 + 16 * t + r;
+                        b[t][k0] = col < ldx ? X[(size_t)pair_row(I, J, 4 * k0 + kg) * ldx + col] : 0.0;
+                    }
+                d4 acc[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    acc[t] = d4{0, 0, 0, 0};
+#pragma unroll
+                    for (int k0 = 0; k0 < 4; ++k0)
+                        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(Q[4 * k0 + kg][r], b[t][k0], acc[t], 0, 0, 0);
+                }
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int col = c0 + 16 * t + r;
+                    if (col < ldx) {
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) X[(size_t)pair_row(I, J, kg + 4 * v) * ldx + col] = acc[t][v];
+                    }
+                }
+            }
+        }
+        // 4. publish: every wave's row stores complete (workgroup-scope release), then one
+        // agent-scope release by thread 0 makes them visible before the blocks' versions move on
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __syncthreads();
+        if (tid == 0) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __hip_atomic_store(ver + I, round + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(ver + J, round + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
 // Sweep prologue and epilogue on the current / other buffer pair xp = {current, other}: rows of
 // the current buffer permuted into the other; then the pair swapped and the sweep statistics
 // cleared (one thread; a kernel, not a memset, so that a captured sweep holds no memset node);
@@ -284,13 +430,16 @@ __global__ void __launch_bounds__(256) k_permute_xp(int ldx, const int32_t* __re
     Y[(size_t)row * ldx + i] = X[(size_t)perm[row] * ldx + i];
 }
 
-__global__ void k_swap_clear(double** __restrict__ xp, unsigned long long* __restrict__ stat) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
+__global__ void k_swap_clear(double** __restrict__ xp, unsigned long long* __restrict__ stat, int* __restrict__ ver,
+                             int n_ver) {
+    if (blockIdx.x != 0) return;
+    if (threadIdx.x == 0) {
         double* t = xp[0];
         xp[0] = xp[1];
         xp[1] = t;
         for (int k = 0; k < 5; ++k) stat[k] = 0ull;
     }
+    for (int k = threadIdx.x; k <= n_ver; k += blockDim.x) ver[k] = 0;   // versions, then the abort flag
 }
 
 __global__ void __launch_bounds__(256) k_norms_xp(int ldx, int n_gram, double* const* __restrict__ xp,
@@ -352,27 +501,27 @@ __global__ void __launch_bounds__(256) k_random_signs(long n, unsigned long long
     out[i] = (z & 1ull) ? 1.0 : -1.0;
 }
 
-// Rank-revealing Cholesky of a Gram matrix and the inverse of its factor, in one workgroup (the
-// orthonormalisation of a block of sketch rows: Y_p = R^T Q_b with Q_b orthonormal, Q_b =
-// R^{-T} Y_p).  Phase 1 (right-looking, in A): at step j the largest remaining diagonal entry is
-// moved to position j (with `pivot`), row j of R is A's row divided by sqrt of the pivot, and the
-// trailing block loses the outer product of that row.  Positions are addressed through
-// perm (no rows are moved); the factorisation stops at the first pivot <= tau2 times the first.
-// Phase 2: T = R^{-1} column by column, T[i][j] = -(sum_{k=i}^{j-1} T[i][k] R[k][j]) / R[j][j],
-// one thread per row i, R's column j staged in LDS.  Phase 3: M[j][perm[i]] = T[i][j].
+// Rank-revealing Cholesky of a Gram matrix, in one workgroup (the orthonormalisation of a block
+// of sketch rows: Y_p = R^T Q_b with Q_b orthonormal, Q_b = R^{-T} Y_p).  Right-looking, in A: at
+// step j the largest remaining diagonal entry is moved to position j (with `pivot`), row j of R
+// is A's row divided by sqrt of the pivot, and the trailing block loses the outer product of that
+// row.  The matrix is held in LDS (n <= PC_MAXN) and positions are addressed through perm (no
+// rows are moved); the factorisation stops at the first pivot <= tau2 times the first.  Out: R^T
+// (pivot order) and the pivot order.
 constexpr int PC_THREADS = 1024;
-constexpr int PC_MAXN = 512;
+constexpr int PC_MAXN = 128;   // the matrix lives in LDS: 128 x 129 doubles
 
-__global__ void __launch_bounds__(PC_THREADS) k_pchol_inverse(int n, double* __restrict__ A, double tau2, int pivot,
-                                                              double* __restrict__ M, double* __restrict__ T,
-                                                              int* __restrict__ keep_dev) {
+__global__ void __launch_bounds__(PC_THREADS) k_pchol(int n, const double* __restrict__ A, double tau2, int pivot,
+                                                      double* __restrict__ Rt, int* __restrict__ perm_out,
+                                                      int* __restrict__ keep_dev) {
+    __shared__ double As[PC_MAXN][PC_MAXN + 1];
     __shared__ int perm[PC_MAXN];
-    __shared__ double col[PC_MAXN];
     __shared__ double wv[PC_THREADS / 64];
     __shared__ int wi[PC_THREADS / 64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     constexpr int NW = PC_THREADS / 64;
     for (int i = tid; i < n; i += PC_THREADS) perm[i] = i;
+    for (int e = tid; e < n * n; e += PC_THREADS) As[e / n][e % n] = A[e];
     __syncthreads();
     double d0 = 0.0;
     int keep = n;
@@ -382,7 +531,7 @@ __global__ void __launch_bounds__(PC_THREADS) k_pchol_inverse(int n, double* __r
             double bv = -__builtin_huge_val();
             int bi = n;
             for (int i = j + tid; i < n; i += PC_THREADS) {
-                const double v = A[(size_t)perm[i] * n + perm[i]];
+                const double v = As[perm[i]][perm[i]];
                 if (v > bv) {
                     bv = v;
                     bi = i;
@@ -418,7 +567,7 @@ __global__ void __launch_bounds__(PC_THREADS) k_pchol_inverse(int n, double* __r
             __syncthreads();
         }
         const int pj = perm[j];
-        const double d = A[(size_t)pj * n + pj];
+        const double d = As[pj][pj];
         if (j == 0) d0 = d;
         if (!(d > 0.0) || !(d > tau2 * d0)) {   // the same value on every thread: a uniform exit
             keep = j;
@@ -426,42 +575,49 @@ __global__ void __launch_bounds__(PC_THREADS) k_pchol_inverse(int n, double* __r
         }
         const double rjj = sqrt(d);
         __syncthreads();   // every thread has read the pivot before row j is overwritten
-        double* __restrict__ aj = A + (size_t)pj * n;
+        double* aj = As[pj];
         for (int k = j + 1 + tid; k < n; k += PC_THREADS) aj[perm[k]] /= rjj;
         if (tid == 0) aj[pj] = rjj;
         __syncthreads();
         // the whole trailing block (both triangles: later pivots reorder the positions, so an
         // entry's place relative to the diagonal is not fixed): one wave per row, lanes along it
         for (int i = j + 1 + wave; i < n; i += NW) {
-            double* __restrict__ ai = A + (size_t)perm[i] * n;
+            double* ai = As[perm[i]];
             const double rji = aj[perm[i]];
             for (int k = j + 1 + lane; k < n; k += 64) ai[perm[k]] -= rji * aj[perm[k]];
         }
         __syncthreads();
     }
-    // T = R^{-1} (pivot order, row-major n x n workspace), R[a][b] = A[perm[a]][perm[b]], a <= b
-    for (int j = 0; j < keep; ++j) {
-        for (int k = tid; k <= j; k += PC_THREADS) col[k] = A[(size_t)perm[k] * n + perm[j]];
-        __syncthreads();
-        const double inv = 1.0 / col[j];
-        for (int i = tid; i <= j; i += PC_THREADS) {
-            if (i == j) {
-                T[(size_t)i * n + j] = inv;
-            } else {
-                const double* __restrict__ ti = T + (size_t)i * n;
-                double sacc = 0.0;
-                for (int k = i; k < j; ++k) sacc += ti[k] * col[k];
-                T[(size_t)i * n + j] = -sacc * inv;
-            }
-        }
-        __syncthreads();
+    // R^T in pivot order (Rt[j][k] = R[k][j], k <= j < keep) and the pivot order itself
+    for (int e = tid; e < keep * keep; e += PC_THREADS) {
+        const int jj = e / keep, k = e % keep;
+        if (k <= jj) Rt[(size_t)jj * n + k] = As[perm[k]][perm[jj]];
     }
-    // M rows 0..keep-1: M[j][perm[i]] = T[i][j] for i <= j, else 0
-    for (int e = tid; e < keep * n; e += PC_THREADS) {
-        const int j = e / n, i = e % n;
-        M[(size_t)j * n + perm[i]] = i <= j ? T[(size_t)i * n + j] : 0.0;
-    }
+    for (int e = tid; e < n; e += PC_THREADS) perm_out[e] = perm[e];
     if (tid == 0) *keep_dev = keep;
+}
+
+// Forward substitution R^T Q = Y_p for the kept rows (the rows of Y in pivot order): Q[i][c] =
+// (Y[perm[i]][c] - sum_{k<i} R[k][i] Q[k][c]) / R[i][i], each column c by its own lane, the
+// column's values so far in LDS (keep <= TS_MAXK), R^T's row i read by every lane alike.
+constexpr int TS_MAXK = 128;
+
+__global__ void __launch_bounds__(64) k_trsm_rows(int keep, int ncol, int n, const double* __restrict__ Rt,
+                                                  const int* __restrict__ perm, const double* __restrict__ Y,
+                                                  long ldy, double* __restrict__ out, long ldo) {
+    __shared__ double q[TS_MAXK][64];
+    const int lane = threadIdx.x;
+    const int col = blockIdx.x * 64 + lane;
+    const bool in = col < ncol;
+    for (int i = 0; i < keep; ++i) {
+        const double* __restrict__ ri = Rt + (size_t)i * n;
+        double sacc = 0.0;
+        for (int k = 0; k < i; ++k) sacc += ri[k] * q[k][lane];
+        const double y = in ? Y[(size_t)perm[i] * ldy + col] : 0.0;
+        const double v = (y - sacc) / ri[i];
+        q[i][lane] = v;
+        if (in) out[(size_t)i * ldo + col] = v;
+    }
 }
 
 inline unsigned cdiv(long a, long b) { return (unsigned)((a + b - 1) / b); }
@@ -469,7 +625,7 @@ inline unsigned cdiv(long a, long b) { return (unsigned)((a + b - 1) / b); }
 struct JacobiLayout {
     int Dp, ldx, nblk, npair, nchunk;   // nchunk: Gram chunks (over the first n_gram entries)
     int nchunk_all;                      // rotation chunks (whole rows)
-    size_t off_x2, off_nrm, off_perm, off_stat, off_part, off_q, off_act, off_ptr, total;
+    size_t off_x2, off_nrm, off_perm, off_stat, off_part, off_q, off_act, off_ptr, off_ver, total;
 };
 
 JacobiLayout layout(int D, int N, int n_gram) {
@@ -490,7 +646,8 @@ JacobiLayout layout(int D, int N, int n_gram) {
     L.off_q = al(L.off_part + (size_t)L.npair * L.nchunk * 256 * sizeof(double));
     L.off_act = al(L.off_q + (size_t)L.npair * 256 * sizeof(double));
     L.off_ptr = al(L.off_act + (size_t)L.npair * sizeof(int));   // {current, other} buffer, keep2
-    L.total = al(L.off_ptr + 3 * sizeof(double));
+    L.off_ver = al(L.off_ptr + 3 * sizeof(double));               // block versions, abort flag
+    L.total = al(L.off_ver + (size_t)(L.nblk + 1) * sizeof(int));
     return L;
 }
 
@@ -498,15 +655,59 @@ JacobiLayout layout(int D, int N, int n_gram) {
 
 size_t jacobi_work_bytes(int D, int N) { return layout(D, N, N).total; }
 
-void launch_pchol_inverse(hipStream_t st, int n, double* A, double tau2, int pivot, double* M, double* T,
-                          int* keep_dev) {
-    hipLaunchKernelGGL(k_pchol_inverse, dim3(1), dim3(PC_THREADS), 0, st, n, A, tau2, pivot, M, T, keep_dev);
+void launch_pchol(hipStream_t st, int n, const double* A, double tau2, int pivot, double* Rt, int* perm, int* keep_dev) {
+    hipLaunchKernelGGL(k_pchol, dim3(1), dim3(PC_THREADS), 0, st, n, A, tau2, pivot, Rt, perm, keep_dev);
+}
+
+void launch_trsm_rows(hipStream_t st, int keep, int ncol, int n, const double* Rt, const int* perm, const double* Y,
+                      long ldy, double* out, long ldo) {
+    if (keep <= 0 || ncol <= 0) return;
+    hipLaunchKernelGGL(k_trsm_rows, dim3(cdiv(ncol, 64)), dim3(64), 0, st, keep, ncol, n, Rt, perm, Y, ldy, out, ldo);
 }
 
 void launch_random_signs(hipStream_t st, long n, unsigned long long seed, double* out) {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_random_signs, dim3(cdiv(n, 256)), dim3(256), 0, st, n, seed, out);
 }
+
+// Persistent sweep groups the device holds at once (occupancy x compute units), per device.
+static int persistent_capacity() {
+    static std::mutex mu;
+    static std::vector<int> cap;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    std::lock_guard<std::mutex> lk(mu);
+    if ((int)cap.size() <= dev) cap.resize(dev + 1, -1);
+    if (cap[dev] < 0) {
+        int per_cu = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_jacobi_sweep, PS_WAVES * 64, 0) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+            (void)hipGetLastError();
+            per_cu = cus = 0;
+        }
+        cap[dev] = per_cu * cus;
+    }
+    return cap[dev];
+}
+
+// Reserves n persistent groups within 3/4 of the capacity; released on destruction.
+struct GroupTokens {
+    std::atomic<int>* use = nullptr;
+    int n = 0;
+    bool take(std::atomic<int>* u, int want, int budget) {
+        if (!u) return true;
+        int cur = u->load();
+        do {
+            if (cur + want > budget) return false;
+        } while (!u->compare_exchange_weak(cur, cur + want));
+        use = u;
+        n = want;
+        return true;
+    }
+    ~GroupTokens() {
+        if (use) use->fetch_sub(n);
+    }
+};
 
 // The permutation sorting squared row norms in descending order.
 static void sort_norms(const std::vector<double>& sig2, std::vector<int32_t>& perm) {
@@ -535,7 +736,11 @@ struct SweepGraphs {
 
 int jacobi_svd(hipStream_t st, int D, int N, double* A, int lda, double tol, double irrelevant, int max_sweeps,
                std::vector<double>& sigma, int* sweeps_out, double* work_dev, size_t work_bytes, int n_gram,
-               double stop_tail2, int graphs, double* flops_out) {
+               double stop_tail2, JacobiRun* run) {
+    JacobiRun defaults;
+    if (!run) run = &defaults;
+    int graphs = run->graphs;
+    int persistent = run->persistent;
     if (n_gram <= 0 || n_gram > N) n_gram = N;
     if (D <= 0 || N <= 0) return fail(LSUM_E_INVALID, "empty side matrix");
     const JacobiLayout L = layout(D, N, n_gram);
@@ -551,6 +756,18 @@ int jacobi_svd(hipStream_t st, int D, int N, double* A, int lda, double tol, dou
     int* act = (int*)(base + L.off_act);
     double** xp_dev = (double**)(base + L.off_ptr);
     double* keep2_dev = (double*)(base + L.off_ptr + 2 * sizeof(double*));
+    int* ver = (int*)(base + L.off_ver);
+    // the bound on a persistent sweep's waits, in ticks of the constant-rate wall clock (kHz)
+    long long tick_limit = 0;
+    if (persistent) {
+        int dev = 0, khz = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0) {
+            (void)hipGetLastError();
+            persistent = 0;
+        }
+        tick_limit = (long long)(run->wait_us * 1e-3 * khz);
+    }
     // host values read by asynchronous copies: they live until the call returns, and every sweep
     // synchronises before they change
     double* xp_host[2] = {X, X2};
@@ -582,7 +799,13 @@ int jacobi_svd(hipStream_t st, int D, int N, double* A, int lda, double tol, dou
         // itself (few tens of columns of 5633-34305 cells: 30-50 % slower with one).
         const int max_inner = npair >= 16 ? 1 : 2;
         hipLaunchKernelGGL(k_permute_xp, dim3(cdiv(L.ldx, 256), L.Dp), dim3(256), 0, st, L.ldx, perm_dev, xp_dev);
-        hipLaunchKernelGGL(k_swap_clear, dim3(1), dim3(64), 0, st, xp_dev, stat);
+        hipLaunchKernelGGL(k_swap_clear, dim3(1), dim3(64), 0, st, xp_dev, stat, ver, nblk);
+        if (persistent) {
+            hipLaunchKernelGGL(k_jacobi_sweep, dim3(npair), dim3(PS_WAVES * 64), 0, st, xp_dev, L.ldx, n_gram, nblk, L.nchunk,
+                               L.nchunk_all, tol, irr2, keep2_dev, max_inner, stat, ver, ver + nblk, tick_limit);
+            hipLaunchKernelGGL(k_norms_xp, dim3(L.Dp), dim3(256), 0, st, L.ldx, n_gram, xp_dev, nrm);
+            return;
+        }
         for (int round = 0; round < nblk - 1; ++round) {
             hipLaunchKernelGGL(k_pair_gram, dim3(L.nchunk, npair), dim3(256), 0, st, xp_dev, L.ldx, n_gram, nblk,
                                round, L.nchunk, part);
@@ -606,8 +829,13 @@ int jacobi_svd(hipStream_t st, int D, int N, double* A, int lda, double tol, dou
         const int nblk = std::max(2, (d_act + 15) / 16 * 2);
         LSUM_HIP(hipMemcpyAsync(perm_dev, perm.data(), L.Dp * sizeof(int32_t), hipMemcpyHostToDevice, st));
         LSUM_HIP(hipMemcpyAsync(keep2_dev, &keep2, sizeof(double), hipMemcpyHostToDevice, st));
-        hipGraphExec_t ge = graphs ? cache.find(nblk) : nullptr;
-        if (graphs && !ge) {
+        // a persistent sweep needs all its groups resident at once: it runs only while the groups
+        // of the persistent sweeps in flight stay within 3/4 of the device; else round by round
+        GroupTokens tokens;
+        const int persistent_mode = persistent;
+        if (persistent && !tokens.take(run->wg_in_use, nblk / 2, persistent_capacity() * 3 / 4)) persistent = 0;
+        hipGraphExec_t ge = graphs && !persistent ? cache.find(nblk) : nullptr;
+        if (graphs && !persistent && !ge) {
             // capture the sweep once per block count; if capture is refused, launch directly
             hipGraph_t g = nullptr;
             bool ok = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess;
@@ -633,9 +861,12 @@ int jacobi_svd(hipStream_t st, int D, int N, double* A, int lda, double tol, dou
         cur ^= 1;
         // FP64 MFMA work of the sweep: every pair visit forms a 16 x 16 Gram over n_gram entries
         // and (when active) rotates 16 rows of ldx entries; counted for every visit
-        if (flops_out) *flops_out += (double)(nblk / 2) * (nblk - 1) * 512.0 * ((double)n_gram + L.ldx);
+        run->flops += (double)(nblk / 2) * (nblk - 1) * 512.0 * ((double)n_gram + L.ldx);
+        const bool was_persistent = persistent != 0;
         unsigned long long st4[5] = {0, 0, 0, 0, 0};
+        int aborted = 0;
         LSUM_HIP(hipMemcpyAsync(st4, stat, sizeof(st4), hipMemcpyDeviceToHost, st));
+        if (was_persistent) LSUM_HIP(hipMemcpyAsync(&aborted, ver + nblk, sizeof(int), hipMemcpyDeviceToHost, st));
         LSUM_HIP(hipMemcpyAsync(sig2.data(), nrm, L.Dp * sizeof(double), hipMemcpyDeviceToHost, st));
         LSUM_HIP(hipStreamSynchronize(st));
         LSUM_HIP(hipGetLastError());
@@ -643,6 +874,20 @@ int jacobi_svd(hipStream_t st, int D, int N, double* A, int lda, double tol, dou
         double off, offk;
         std::memcpy(&off, &st4[0], sizeof(off));
         std::memcpy(&offk, &st4[4], sizeof(offk));
+        if (!was_persistent) persistent = persistent_mode;   // no tokens this sweep: try again next sweep
+        if (was_persistent) {
+            ++run->persistent_sweeps;
+            if (aborted) {
+                // some groups were not resident together (or the wait bound is tiny): the sweep
+                // visited only part of the pairs, so it decides nothing; the remaining sweeps
+                // launch round by round
+                ++run->aborted;
+                persistent = 0;
+                r_prev = -1;
+                if (trace) std::fprintf(stderr, "jacobi D=%d N=%d sweep %d: persistent sweep aborted\n", D, N, sweeps);
+                continue;
+            }
+        }
         if (off <= tol) converged = true;
         int r_now = -1;
         if (stop_tail2 > 0.0 && !converged) {
@@ -668,7 +913,7 @@ int jacobi_svd(hipStream_t st, int D, int N, double* A, int lda, double tol, dou
         if (trace)
             std::fprintf(stderr, "jacobi D=%d N=%d sweep %d active %d max coupling %.3e kept %.3e rank %d inner sweeps %.2f avg %llu max over %llu pairs%s\n",
                          D, N, sweeps, d_act, off, offk, r_now, st4[3] ? (double)st4[1] / (double)st4[3] : 0.0, st4[2],
-                         st4[3], ge ? " (graph)" : "");
+                         st4[3], was_persistent ? " (persistent)" : (ge ? " (graph)" : ""));
     }
     // write back the D largest columns in descending order
     double* Xcur = cur ? X2 : X;

@@ -570,7 +570,10 @@ int lsum_get_stats(lsum_req r, char* buf, size_t len) {
           << "],\"range_res\":[" << q.range_res[0] << "," << q.range_res[1] << "," << q.range_res[2]
           << "],\"norm_A\":" << q.norm_A
           << ",\"norm_xi\":" << q.norm_xi << ",\"bound\":" << q.bound << ",\"batch\":" << q.batch_size
-          << ",\"als_skipped\":" << q.als_skipped << ",\"als_core_norm\":[";
+          << ",\"als_skipped\":" << q.als_skipped << ",\"jacobi_persistent\":[" << q.jacobi_persistent[0] << ","
+          << q.jacobi_persistent[1] << "," << q.jacobi_persistent[2] << "],\"jacobi_aborted\":["
+          << q.jacobi_aborted[0] << "," << q.jacobi_aborted[1] << "," << q.jacobi_aborted[2]
+          << "],\"als_core_norm\":[";
         for (size_t k = 0; k < q.als_core_norm.size(); ++k) o << (k ? "," : "") << q.als_core_norm[k];
         o << "],\"offsets\":[";
         for (int b = 0; b < (int)P.blocks.size(); ++b) {
@@ -698,6 +701,14 @@ int lsum_set_option(lsum_ctx x, int key, double value) {
         case LSUM_OPT_GRAPHS:
             if (!(value == 0 || value == 1)) return fail(LSUM_E_INVALID, "graph option must be 0 or 1");
             c.graphs.store((int)value);
+            return LSUM_OK;
+        case LSUM_OPT_JACOBI_PERSISTENT:
+            if (!(value == 0 || value == 1)) return fail(LSUM_E_INVALID, "persistent option must be 0 or 1");
+            c.persistent.store((int)value);
+            return LSUM_OK;
+        case LSUM_OPT_JACOBI_WAIT_US:
+            if (!(value >= 0 && value <= 1e8)) return fail(LSUM_E_INVALID, "wait bound must be in [0, 1e8] us");
+            c.jacobi_wait_us.store((long long)value);
             return LSUM_OK;
         default:
             return fail(LSUM_E_INVALID, "unknown option");
@@ -920,8 +931,8 @@ int lsum_jacobi_svd(lsum_ctx x, void* stream, int D, int N, double* A_dev, int l
     int rc = work.get(x->c.pool, wb);
     if (rc) return rc;
     std::vector<double> s;
-    rc = jacobi_svd(st, D, N, A_dev, lda, tol, irrelevant, max_sweeps, s, sweeps, work.as<double>(), wb, 0, 0.0,
-                    x->c.graphs.load());
+    JacobiRun jr = jacobi_run(&x->c);
+    rc = jacobi_svd(st, D, N, A_dev, lda, tol, irrelevant, max_sweeps, s, sweeps, work.as<double>(), wb, 0, 0.0, &jr);
     std::copy(s.begin(), s.end(), sigma);
     return rc;
 }

@@ -6,6 +6,7 @@
 
 #include <cstdint>
 #include <string>
+#include <atomic>
 #include <vector>
 
 #include "lsum.h"
@@ -296,24 +297,41 @@ void launch_cp_norm2(hipStream_t st, int R, int n_groups, const int32_t* src1, c
 // (sum of the squared norms of rows r, r+1, ...) is at most stop_tail2 repeats between two
 // sweeps and the r largest rows (plus a margin) are orthogonal to tol; the norms of the tail
 // rows are then bounds, not singular values (their squared sum bounds the true tail from above).
-// With `graphs` each sweep (the same launches for the same number of column blocks) is captured
-// once in a HIP graph and replayed; otherwise its kernels are launched one by one (same results).
-// flops_out (if given) accumulates the FP64 MFMA work of the pair Grams and rotations.
+// How the sweeps are launched, and what a call reports back.  persistent: each sweep is one
+// launch of one workgroup per pair slot, rounds ordered by per-block version counters (waits
+// bounded by wait_us; a sweep whose groups were not all resident aborts and the remaining sweeps
+// launch round by round); otherwise, with graphs, the round-by-round launches of a sweep are
+// captured once per block count in a HIP graph and replayed; otherwise launched one by one.
+// Every way adds the same terms in the same order (the same results bit for bit).
+struct JacobiRun {
+    int graphs = 0;
+    int persistent = 0;
+    double wait_us = 5e5;
+    // workgroups of persistent sweeps running on the device (shared by every SVD of a context):
+    // a sweep runs persistently only while the total stays within 3/4 of what the device holds
+    // at once, else round by round (nullptr: no accounting)
+    std::atomic<int>* wg_in_use = nullptr;
+    double flops = 0.0;            // out: FP64 MFMA work of the pair Grams and rotations (added)
+    int persistent_sweeps = 0;     // out: sweeps launched persistently (added)
+    int aborted = 0;               // out: persistent sweeps that aborted (added)
+};
 int jacobi_svd(hipStream_t st, int D, int N, double* A, int lda, double tol, double irrelevant,
                int max_sweeps, std::vector<double>& sigma, int* sweeps_out, double* work_dev,
-               size_t work_bytes, int n_gram = 0, double stop_tail2 = 0.0, int graphs = 1,
-               double* flops_out = nullptr);
+               size_t work_bytes, int n_gram = 0, double stop_tail2 = 0.0, JacobiRun* run = nullptr);
 size_t jacobi_work_bytes(int D, int N);
 // out[i] = +-1, i < n, a deterministic function of (seed, i)
 void launch_random_signs(hipStream_t st, long n, unsigned long long seed, double* out);
 // Rank-revealing Cholesky of a symmetric positive semi-definite n x n matrix A (row-major,
-// n <= 512; destroyed): with `pivot`, the largest remaining diagonal is taken first, and the
+// n <= 128): with `pivot`, the largest remaining diagonal is taken first, and the
 // factorisation stops at the first step whose pivot is <= tau2 times the first one (or not
-// positive).  With keep steps done (written to *keep_dev), the rows 0..keep-1 of M (n x n,
-// row-major) hold T^T P^T, T = R^{-1}: for the rows Y of a matrix with Gram A, M Y has
-// orthonormal rows spanning the kept pivot rows.  T: n x n workspace.  One workgroup.
-void launch_pchol_inverse(hipStream_t st, int n, double* A, double tau2, int pivot, double* M, double* T,
-                          int* keep_dev);
+// positive).  Out: keep (the steps done, *keep_dev), the pivot order perm[n], and R^T in pivot
+// order, Rt[j*n + k] = R[k][j] for k <= j < keep, with (P A P^T)[0:keep, 0:keep] = R^T R.  One
+// workgroup.
+void launch_pchol(hipStream_t st, int n, const double* A, double tau2, int pivot, double* Rt, int* perm, int* keep_dev);
+// out (keep x ncol, stride ldo) = R^{-T} Y_p, Y_p the rows perm[0..keep) of Y (stride ldy):
+// orthonormal rows when A was their Gram.  keep <= 128.
+void launch_trsm_rows(hipStream_t st, int keep, int ncol, int n, const double* Rt, const int* perm, const double* Y,
+                      long ldy, double* out, long ldo);
 
 // type conversions
 void launch_f64_to_f32(hipStream_t st, long n, const double* x, float* y);

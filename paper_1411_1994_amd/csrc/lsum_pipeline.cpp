@@ -58,6 +58,7 @@ struct ModeSVD {
     bool unit = false;           // vector rows are unit (range path) or sigma-scaled (direct)
     int k = 0, sweeps = 0;
     double flops = 0.0;          // FP64 MFMA work: range-basis GEMMs, Jacobi Grams and rotations
+    int persistent = 0, aborted = 0;   // Jacobi sweeps launched persistently / aborted
 };
 
 // C (m x n) = alpha * X Y + beta * C over row-major operands; tX / tY: use the transpose.
@@ -98,22 +99,25 @@ static int gram_rows(Context* c, hipStream_t st, int m, int n, const double* X, 
     return gemm_auto(c, st, GEMM_F64, a);
 }
 
-// Orthonormal rows spanning the significant rows of Y (m x n, stride n): the rank-revealing
-// Cholesky of Y Y^T keeps pivots above tau2 times the first (rows above sqrt(tau2) in norm), and
-// out (keep x n) = M Y with M = R^{-T} P^T.  Returns keep (0: nothing above the threshold).
+// Orthonormal rows spanning the significant rows of Y (m x n, stride n; m <= 128): the
+// rank-revealing Cholesky of Y Y^T keeps pivots above tau2 times the first (rows above
+// sqrt(tau2) in norm), and out (keep x n) = R^{-T} Y_p by forward substitution.  Returns keep
+// (0: nothing above the threshold).
 static int chol_rows(Context* c, hipStream_t st, int m, int n, const double* Y, double tau2, double* small,
                      double* out, int* keep) {
+    if (m > 128) return fail(LSUM_E_INVALID, "chol_rows: more than 128 rows");
     double* G = small;
-    double* Mm = small + (size_t)m * m;
-    double* Tm = Mm + (size_t)m * m;
-    int* kd = (int*)(Tm + (size_t)m * m);
+    double* Rt = small + (size_t)m * m;
+    int* perm = (int*)(Rt + (size_t)m * m);
+    int* kd = perm + m;
     int rc;
     if ((rc = gram_rows(c, st, m, n, Y, n, G))) return rc;
-    launch_pchol_inverse(st, m, G, tau2, 1, Mm, Tm, kd);
+    launch_pchol(st, m, G, tau2, 1, Rt, perm, kd);
     LSUM_HIP(hipGetLastError());
     LSUM_HIP(hipMemcpyAsync(keep, kd, sizeof(int), hipMemcpyDeviceToHost, st));
     LSUM_HIP(hipStreamSynchronize(st));
-    if (*keep > 0) gemm_rm(st, *keep, n, m, Mm, m, false, Y, n, false, out, n, 1.0, 0.0);
+    launch_trsm_rows(st, *keep, n, m, Rt, perm, Y, n, out, n);
+    LSUM_HIP(hipGetLastError());
     return LSUM_OK;
 }
 
@@ -204,10 +208,13 @@ static int range_svd(Context* c, hipStream_t st, int D, int N, const double* W, 
     const size_t wb2 = jacobi_work_bytes(kq, (int)ld);
     if ((rc = work.get(c->pool, wb2))) return rc;
     // the rotated Q rows stay orthonormal in any sweep, so the rank stop needs no extra step here
+    JacobiRun jr = jacobi_run(c);
     rc = jacobi_svd(st, kq, (int)ld, AUG.as<double>(), (int)ld, 1e-12, irrelevant, c->jacobi_max_sweeps.load(),
                     out.sigma, &out.sweeps,
-                    work.as<double>(), wb2, D, c->jacobi_rank_stop ? thr * thr - res2 : 0.0, c->graphs.load(),
-                    &out.flops);
+                    work.as<double>(), wb2, D, c->jacobi_rank_stop ? thr * thr - res2 : 0.0, &jr);
+    out.flops += jr.flops;
+    out.persistent += jr.persistent_sweeps;
+    out.aborted += jr.aborted;
     if (rc) return rc;
     out.res2 = res2;
     out.rows = std::move(AUG);
@@ -225,10 +232,11 @@ static int mode_svd(Context* c, hipStream_t st, int D, int N, DevBuf& W, double 
     const int mn = std::min(D, N);
     const int range_min = allow_range ? c->range_min : 0;
     if (range_min > 0 && mn >= range_min) {
-        // a basis grown in blocks of 256 vectors up to min(D, N) / 2: it wins when the certified
-        // rank is below about half of min(D, N); past that the direct solve follows
+        // a basis grown in blocks of 128 vectors (the Gram of a block is factored in LDS) up to
+        // min(D, N) / 2: it wins when the certified rank is below about half of min(D, N); past
+        // that the direct solve follows
         const int k_max = mn / 2;
-        const int k_block = std::min(256, k_max);
+        const int k_block = std::min(128, k_max);
         bool enough = false;
         if ((rc = range_svd(c, st, D, N, W.as<double>(), k_block, k_max, thr, irrelevant, out, &enough))) return rc;
         if (enough) return LSUM_OK;
@@ -236,9 +244,13 @@ static int mode_svd(Context* c, hipStream_t st, int D, int N, DevBuf& W, double 
     DevBuf work;
     const size_t wb = jacobi_work_bytes(D, N);
     if ((rc = work.get(c->pool, wb))) return rc;
+    JacobiRun jr = jacobi_run(c);
     rc = jacobi_svd(st, D, N, W.as<double>(), N, 1e-12, irrelevant, c->jacobi_max_sweeps.load(), out.sigma,
                     &out.sweeps, work.as<double>(),
-                    wb, 0, c->jacobi_rank_stop ? thr * thr : 0.0, c->graphs.load(), &out.flops);
+                    wb, 0, c->jacobi_rank_stop ? thr * thr : 0.0, &jr);
+    out.flops += jr.flops;
+    out.persistent += jr.persistent_sweeps;
+    out.aborted += jr.aborted;
     if (rc) return rc;
     out.res2 = 0.0;
     out.rows = std::move(W);
@@ -403,8 +415,9 @@ static int run_als(Request* q, hipStream_t st, DevBuf cols[3], StageTimer& tm) {
                 DevBuf work;
                 const size_t wb = jacobi_work_bytes(N, (int)ld);
                 if ((rc = work.get(c->pool, wb))) return rc;
+                JacobiRun jr = jacobi_run(c);
                 rc = jacobi_svd(st, N, (int)ld, Mr.as<double>(), (int)ld, 1e-12, 0.0, 40, ms.sigma, &ms.sweeps,
-                                work.as<double>(), wb, D, 0.0, c->graphs.load());
+                                work.as<double>(), wb, D, 0.0, &jr);
                 if (rc) return rc;
                 ms.rows = std::move(Mr);
                 ms.ld = ld;
@@ -559,6 +572,8 @@ static int run_tucker(Request* q, hipStream_t st, const hipStream_t* aux, StageT
         q->range_k[l] = ms[l].k;
         q->range_res[l] = std::sqrt(ms[l].res2);
         svd_flops += ms[l].flops;
+        q->jacobi_persistent[l] = ms[l].persistent;
+        q->jacobi_aborted[l] = ms[l].aborted;
     }
     tm.work(0, svd_flops);
     tm.end();

@@ -144,7 +144,10 @@ struct Context {
     int range_min = 512;             // min(D, N) from which side matrices use the range basis
     bool jacobi_rank_stop = true;    // Jacobi SVDs of side matrices end once the certified rank is settled
     std::atomic<int> jacobi_max_sweeps{40};   // sweeps before a side-matrix SVD fails (LSUM_E_NOCONV)
-    std::atomic<int> graphs{1};               // Jacobi sweeps captured in HIP graphs and replayed
+    std::atomic<int> graphs{0};               // round-by-round Jacobi sweeps captured in HIP graphs
+    std::atomic<int> persistent{0};           // Jacobi sweeps as one persistent launch each
+    std::atomic<long long> jacobi_wait_us{500000};   // bound on a persistent sweep's waits
+    std::atomic<int> persistent_wgs{0};       // workgroups of persistent sweeps now on the device
     std::vector<hipStream_t> streams;
     std::vector<hipStream_t> aux;    // three per slot: the per-mode SVDs of a request run concurrently
     std::vector<std::thread> workers;
@@ -169,6 +172,16 @@ struct Context {
     std::map<std::string, StageStat> profile;
     ~Context();
 };
+
+// how the context runs Jacobi sweeps
+inline JacobiRun jacobi_run(Context* c) {
+    JacobiRun r;
+    r.graphs = c->graphs.load();
+    r.persistent = c->persistent.load();
+    r.wait_us = (double)c->jacobi_wait_us.load();
+    r.wg_in_use = &c->persistent_wgs;
+    return r;
+}
 
 // a request and its results
 struct Request {
@@ -211,6 +224,8 @@ struct Request {
     int range_k[3]{};                  // size of the range basis per mode (0: direct)
     std::vector<double> als_core_norm;  // ||core|| after each ALS sweep
     int als_skipped = 0;               // 1: ALS asked for but the ranks do not allow it
+    int jacobi_persistent[3]{};        // per mode: sweeps launched persistently
+    int jacobi_aborted[3]{};           // per mode: persistent sweeps that aborted
     std::string error;                 // message of a failed request (the worker's last error)
     DevBuf Z[3];                       // r_l x N_l FP64
     DevBuf core;                       // r1 r2 r3, FP64 or FP32 (precision)

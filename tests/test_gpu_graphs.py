@@ -29,6 +29,7 @@ def _run(graphs, problems):
     import paper_1411_1994_amd as L
     out = []
     with L.Context(0, n_slots=1) as c:
+        c.set_option(L.OPT_JACOBI_PERSISTENT, 0)   # graphs apply to the round-by-round launches
         c.set_option(L.OPT_GRAPHS, graphs)
         for p in problems + problems:          # every problem twice on the same context
             rng = np.random.default_rng(6)
@@ -60,3 +61,60 @@ def test_graph_replayed_sweeps_equal_direct_launches():
     for k, p in enumerate(probs):
         ref = O.brute_force_points(p, a[k]["cells"])
         assert np.max(np.abs(a[k]["v"] - ref)) <= a[k]["bound"] * (1 + 1e-9) + 1e-12 * np.max(np.abs(ref))
+
+
+def _run_opts(opts, problems):
+    import paper_1411_1994_amd as L
+    out = []
+    with L.Context(0, n_slots=1) as c:
+        for k, v in opts.items():
+            c.set_option(k, v)
+        for p in problems:
+            rng = np.random.default_rng(6)
+            cells = np.stack([rng.integers(0, n, 16) for n in p.N], axis=1)
+            xyz = np.stack([(cells[:, a] - (p.N[a] - 1) // 2) * p.h for a in range(3)], axis=1)
+            r = c.submit(p)
+            assert r.wait() == 0, r.stats()
+            st = r.stats()
+            out.append(dict(r=tuple(r.info().r), sweeps=tuple(st["sweeps"]), bound=r.info().bound, st=st,
+                            sig=[s.copy() for s in r.sigma()], v=r.sample(xyz), cells=cells))
+            r.release()
+    return out
+
+
+def test_persistent_sweeps_equal_round_by_round_launches():
+    # one launch per sweep (rounds ordered by per-block counters) against the round-by-round
+    # launches, directly and from graphs: bit for bit the same
+    require_gpu()
+    import paper_1411_1994_amd as L
+    probs = _problems()
+    per = _run_opts({L.OPT_JACOBI_PERSISTENT: 1}, probs)
+    direct = _run_opts({L.OPT_JACOBI_PERSISTENT: 0, L.OPT_GRAPHS: 0}, probs)
+    graph = _run_opts({L.OPT_JACOBI_PERSISTENT: 0, L.OPT_GRAPHS: 1}, probs)
+    for k in range(len(probs)):
+        assert sum(per[k]["st"]["jacobi_persistent"]) > 0 and sum(per[k]["st"]["jacobi_aborted"]) == 0, per[k]["st"]
+        assert sum(direct[k]["st"]["jacobi_persistent"]) == 0
+        for other in (direct, graph):
+            x, y = per[k], other[k]
+            assert x["r"] == y["r"] and x["sweeps"] == y["sweeps"] and x["bound"] == y["bound"], k
+            for l in range(3):
+                assert np.array_equal(x["sig"][l], y["sig"][l]), (k, l)
+            assert np.array_equal(x["v"], y["v"]), k
+
+
+def test_persistent_sweep_abort_falls_back_to_round_launches():
+    # a wait bound of 0 forces the persistent sweeps to abort at their first wait (set from the
+    # host; every kernel exits normally): the SVD finishes round by round and the result is
+    # still certified -- the same ranks as the uninterrupted run and values within the bound
+    require_gpu()
+    import paper_1411_1994_amd as L
+    p = _problems()[0]
+    ref = _run_opts({L.OPT_JACOBI_PERSISTENT: 0}, [p])[0]
+    got = _run_opts({L.OPT_JACOBI_PERSISTENT: 1, L.OPT_JACOBI_WAIT_US: 0}, [p])[0]
+    assert sum(got["st"]["jacobi_aborted"]) >= 1, got["st"]
+    nA = ref["st"]["norm_A"]
+    assert got["bound"] <= p.eps * nA * (1 + 1e-12)
+    for l in range(3):
+        assert abs(got["r"][l] - ref["r"][l]) <= max(2, ref["r"][l] // 50), (got["r"], ref["r"])
+    oracle_ref = O.brute_force_points(p, got["cells"])
+    assert np.max(np.abs(got["v"] - oracle_ref)) <= p.eps * nA
