@@ -284,6 +284,8 @@ def run_mix(args):
     outs = [torch.zeros(n_pts, dtype=torch.float64, device="cuda") for _ in probs]
     torch.cuda.synchronize()
 
+    probe = {}
+
     def closed(ctx, idx, inflight):
         """Submit the requests idx keeping at most `inflight` in flight; (seconds, latencies)."""
         from collections import deque
@@ -302,6 +304,7 @@ def run_mix(args):
                 raise RuntimeError(f"request {k} failed: {rc} {r.stats().get('error')}")
             inf = r.info()
             lat[k] = inf.t_queue_ms + inf.t_run_ms
+            probe[k] = (inf.probe_err, inf.rel_bound)
             r.release()
         torch.cuda.synchronize()
         return time.perf_counter() - t0, lat
@@ -418,6 +421,12 @@ def run_mix(args):
         "rel_err_vs_oracle_per_request": errs,
         "all_within_eps": bool(all(e <= ep for e, ep in zip(errs, eps_of))),
         "max_rel_dev_served_vs_plain": max(devs),
+        "stated_error": {"what": "each result's own statement (lsum_info.probe_err): max-norm relative deviation "
+                                 "from the untruncated FP64 canonical sum at 32 seeded cells, and its certified "
+                                 "Frobenius bound relative to ||A|| (rel_bound)",
+                         "probe_err_max": max(probe[k][0] for k in timed_idx),
+                         "probe_err_per_request": [probe[k][0] for k in timed_idx],
+                         "rel_bound_per_request": [probe[k][1] for k in timed_idx]},
         "roofline": roof,
         "mfma_stages": mfma,
         "stages": {k: {"ms_per_launch": v["ms"] / max(1, v["launches"]), "launches": v["launches"]}

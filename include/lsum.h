@@ -243,7 +243,21 @@ const char* lsum_last_error(void);
 #define LSUM_OPT_GRAPHS 6
 #define LSUM_OPT_JACOBI_PERSISTENT 7
 #define LSUM_OPT_JACOBI_WAIT_US 8
+/* LSUM_OPT_AUTOTUNE (default 1): launch variants that add the same terms in the same order (the
+ * three ways of launching a Jacobi sweep above; the shift-sum's 16- or 48-node workgroup tiles)
+ * are timed on the first launch of each shape bucket and the fastest is used from then on; the
+ * choice never changes a result.  With it, the sweep ways chosen override the two options
+ * above.  0: the options and fixed thresholds decide. */
+#define LSUM_OPT_AUTOTUNE 9
 int lsum_set_option(lsum_ctx ctx, int key, double value);
+/* The autotuner's decisions of earlier runs on a device of the same architecture and compute
+ * unit count are read from the text file at `path` (if it exists), and new ones are appended to
+ * it ("<device> <bucket> <choice> <ms per variant ...>" per line). */
+int lsum_tune_file(lsum_ctx ctx, const char* path);
+/* JSON of the autotuner's decisions: {"device", "file", "enabled", "decisions": {bucket:
+ * {"choice", "ms": [per variant, -1 if not measured]}}}; returns the full length (copy into
+ * buf of len bytes, truncated, NUL-terminated). */
+int lsum_get_tuning(lsum_ctx ctx, char* buf, size_t len);
 /* Per stage (collocate, shift_sum, transpose, columns, norm, svd, projection, core, tile,
  * sample): summed event-timed GPU milliseconds, number of timed launches, and the algorithmic
  * bytes and flops those launches had to move or compute, as JSON; returns the needed length. */
@@ -337,6 +351,14 @@ typedef struct {
     double bound;      /* ||xi|| sum_l tail_l: certified bound on ||A - A0||_F              */
     double rel_bound;  /* bound / norm_A                                                     */
     double t_queue_ms, t_run_ms;  /* enqueue->start, start->finish                            */
+    /* The result's own error (Tucker results; -1 for canonical ones, which are the canonical sum
+     * itself): at n_probe seeded cells, max |V(cell) - A(cell)| / max |A(cell)|, V the result
+     * evaluated as any sample (in the request's precision) and A the untruncated canonical sum
+     * in FP64 -- the discrete tensor the direct sum over the charges gives.  It holds the
+     * truncation error (certified in Frobenius norm by `bound`) and the rounding of the FP32 /
+     * split-BF16x3 contractions together. */
+    double probe_err;
+    int n_probe;
 } lsum_info;
 int lsum_get_info(lsum_req req, lsum_info* info);
 

@@ -30,9 +30,10 @@ SYMBOLS = ["lsum_nodes", "lsum_block_offsets", "lsum_shear_blocks", "lsum_column
            "lsum_contract",
            "lsum_submit", "lsum_submit_many", "lsum_wait", "lsum_cancel", "lsum_get_info", "lsum_get_canonical",
            "lsum_get_tucker", "lsum_tucker_to_canonical", "lsum_galerkin", "lsum_get_sigma", "lsum_sample", "lsum_get_tile", "lsum_get_stats",
-           "lsum_release", "lsum_finish_many", "lsum_set_option", "lsum_get_profile", "lsum_reset_profile"]
+           "lsum_release", "lsum_finish_many", "lsum_set_option", "lsum_get_profile", "lsum_reset_profile",
+           "lsum_tune_file", "lsum_get_tuning"]
 OPT_MAX_BATCH, OPT_REF_CACHE_BYTES, OPT_RANGE_MIN, OPT_JACOBI_STOP, OPT_JACOBI_MAX_SWEEPS, OPT_GRAPHS = 1, 2, 3, 4, 5, 6
-OPT_JACOBI_PERSISTENT, OPT_JACOBI_WAIT_US = 7, 8
+OPT_JACOBI_PERSISTENT, OPT_JACOBI_WAIT_US, OPT_AUTOTUNE = 7, 8, 9
 
 
 class LsumError(RuntimeError):
@@ -69,7 +70,8 @@ class lsum_info(C.Structure):
     _fields_ = [("status", C.c_int), ("R", C.c_int), ("n_terms", C.c_int), ("is_tucker", C.c_int),
                 ("r", C.c_int * 3), ("D", C.c_int * 3), ("norm_A", C.c_double),
                 ("norm_xi", C.c_double), ("bound", C.c_double), ("rel_bound", C.c_double),
-                ("t_queue_ms", C.c_double), ("t_run_ms", C.c_double)]
+                ("t_queue_ms", C.c_double), ("t_run_ms", C.c_double), ("probe_err", C.c_double),
+                ("n_probe", C.c_int)]
 
 
 def _load():
@@ -119,6 +121,8 @@ def _load():
         "lsum_finish_many": (I, [I, P(VP), P(I), P(lsum_info)]),
         "lsum_set_option": (I, [VP, I, D]),
         "lsum_get_profile": (I, [VP, C.c_char_p, C.c_size_t]),
+        "lsum_tune_file": (I, [VP, C.c_char_p]),
+        "lsum_get_tuning": (I, [VP, C.c_char_p, C.c_size_t]),
         "lsum_reset_profile": (I, [VP]),
     }
     for name, (res, args) in sig.items():
@@ -338,6 +342,16 @@ class Context:
     # -- options and profile --------------------------------------------------------------
     def set_option(self, key: int, value: float):
         _check(_lib.lsum_set_option(self.handle, key, float(value)))
+
+    def tune_file(self, path: str):
+        """Read and append the autotuner's decisions in a text file (lsum_tune_file)."""
+        _check(_lib.lsum_tune_file(self.handle, path.encode()))
+
+    def tuning(self) -> dict:
+        n = _lib.lsum_get_tuning(self.handle, None, 0)
+        buf = C.create_string_buffer(n + 16)
+        _lib.lsum_get_tuning(self.handle, buf, n + 16)
+        return json.loads(buf.value.decode())
 
     def profile(self) -> dict:
         n = _lib.lsum_get_profile(self.handle, None, 0)

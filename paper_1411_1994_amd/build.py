@@ -20,7 +20,7 @@ OBJ = os.path.join(ROOT, "_build", "obj")
 LIBDIR = os.path.join(HERE, "lib")
 LIB = os.path.join(LIBDIR, "liblsum.so")
 
-SOURCES = ["lsum_host.cpp", "lsum_sinc_error.cpp", "lsum_runtime.cpp", "lsum_pipeline.cpp", "lsum_capi.cpp",
+SOURCES = ["lsum_host.cpp", "lsum_sinc_error.cpp", "lsum_tune.cpp", "lsum_runtime.cpp", "lsum_pipeline.cpp", "lsum_capi.cpp",
            "kernels_lattice.hip", "kernels_gemm.hip", "kernels_jacobi.hip", "scratch_noalloc.hip"]
 
 # Packed FP32 instructions are disabled for all device code (only hand-checked FP32 paths).

@@ -754,6 +754,43 @@ void launch_core_groups(hipStream_t st, int elem, int r1, int r2, int j0, int nj
                            (const float*)Y1, ldy1, (const float*)Y2, ldy2, (float*)out);
 }
 
+// The canonical sum at probe cells, in FP64 (the discrete tensor before truncation):
+// out[p] = sum_g scale[g] sum_k prod_l C_l[(src_l[g] R + k) * N_l + cell_l(p)], one workgroup per
+// cell, the terms strided over its threads and summed by a fixed tree (deterministic).
+__global__ void __launch_bounds__(256) k_probe_canonical(int R, int n_groups, const int32_t* __restrict__ s1,
+                                                         const int32_t* __restrict__ s2,
+                                                         const int32_t* __restrict__ s3,
+                                                         const double* __restrict__ scale,
+                                                         const double* __restrict__ C1, const double* __restrict__ C2,
+                                                         const double* __restrict__ C3, int N1, int N2, int N3,
+                                                         const int32_t* __restrict__ cells, double* __restrict__ out) {
+    __shared__ double red[256];
+    const int p = blockIdx.x, tid = threadIdx.x;
+    const int i1 = cells[3 * p], i2 = cells[3 * p + 1], i3 = cells[3 * p + 2];
+    const long K = (long)n_groups * R;
+    double v = 0.0;
+    for (long nu = tid; nu < K; nu += 256) {
+        const int g = (int)(nu / R), k = (int)(nu % R);
+        v += scale[g] * C1[(size_t)(s1[g] * R + k) * N1 + i1] * C2[(size_t)(s2[g] * R + k) * N2 + i2] *
+             C3[(size_t)(s3[g] * R + k) * N3 + i3];
+    }
+    red[tid] = v;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (tid < w) red[tid] += red[tid + w];
+        __syncthreads();
+    }
+    if (tid == 0) out[p] = red[0];
+}
+
+void launch_probe_canonical(hipStream_t st, int n_cells, int R, int n_groups, const int32_t* s1, const int32_t* s2,
+                            const int32_t* s3, const double* scale, const double* C1, const double* C2,
+                            const double* C3, int N1, int N2, int N3, const int32_t* cells, double* out) {
+    if (n_cells <= 0) return;
+    hipLaunchKernelGGL(k_probe_canonical, dim3(n_cells), dim3(256), 0, st, R, n_groups, s1, s2, s3, scale, C1, C2,
+                       C3, N1, N2, N3, cells, out);
+}
+
 void launch_cp_norm2(hipStream_t st, int R, int n_groups, const int32_t* src1, const int32_t* src2,
                      const int32_t* src3, const double* scale, const double* C1, const double* C2,
                      const double* C3, int D1, int D2, int D3, double* partial, int n_partial) {

@@ -822,47 +822,113 @@ int jacobi_svd(hipStream_t st, int D, int N, double* A, int lda, double tol, dou
     // rank stop: the certified rank of the current rows, and the squared norm above which rows
     // count as kept (the rank plus a margin of max(16, r/8) rows; 0: every row)
     int r_prev = -1;
+    // the autotuner's shape bucket: rows, row length and Gram length, each rounded up to a power
+    // of two; its decision (once made) sets how the sweeps are launched
+    auto pow2 = [](long x) {
+        long b = 1;
+        while (b < x) b <<= 1;
+        return b;
+    };
+    const std::string tune_key = "jacobi/" + std::to_string(pow2(L.Dp)) + "/" + std::to_string(pow2(L.ldx)) + "/" +
+                                 std::to_string(pow2(n_gram));
+    int tune_key_choice = run->tuner ? run->tuner->get(tune_key) : -2;
+    if (tune_key_choice >= 0) {
+        persistent = tune_key_choice == 2;
+        graphs = tune_key_choice == 1;
+    }
     for (; sweeps < max_sweeps && !converged; ++sweeps) {
+        bool was_persistent = false, used_graph = false;
         // only columns above the floor take part (sorted first); the rest are never rotated
         int d_act = 0;
         while (d_act < L.Dp && sig2[perm[d_act]] > irr2) ++d_act;
         const int nblk = std::max(2, (d_act + 15) / 16 * 2);
         LSUM_HIP(hipMemcpyAsync(perm_dev, perm.data(), L.Dp * sizeof(int32_t), hipMemcpyHostToDevice, st));
         LSUM_HIP(hipMemcpyAsync(keep2_dev, &keep2, sizeof(double), hipMemcpyHostToDevice, st));
-        // a persistent sweep needs all its groups resident at once: it runs only while the groups
-        // of the persistent sweeps in flight stay within 3/4 of the device; else round by round
-        GroupTokens tokens;
-        const int persistent_mode = persistent;
-        if (persistent && !tokens.take(run->wg_in_use, nblk / 2, persistent_capacity() * 3 / 4)) persistent = 0;
-        hipGraphExec_t ge = graphs && !persistent ? cache.find(nblk) : nullptr;
-        if (graphs && !persistent && !ge) {
-            // capture the sweep once per block count; if capture is refused, launch directly
+        // the sweep's graph for this block count, captured on first use (nullptr if refused)
+        auto graph_for = [&](int nb) -> hipGraphExec_t {
+            hipGraphExec_t gx = cache.find(nb);
+            if (gx) return gx;
             hipGraph_t g = nullptr;
+            const int keep_persistent = persistent;
+            persistent = 0;
             bool ok = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess;
             if (ok) {
-                enqueue_sweep(nblk);
+                enqueue_sweep(nb);
                 ok = hipStreamEndCapture(st, &g) == hipSuccess && g != nullptr;
             }
-            if (ok) ok = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) == hipSuccess;
+            persistent = keep_persistent;
+            if (ok) ok = hipGraphInstantiate(&gx, g, nullptr, nullptr, 0) == hipSuccess;
             if (g) (void)hipGraphDestroy(g);
-            if (ok) {
-                cache.execs.push_back({nblk, ge});
-            } else {
+            if (!ok) {
                 (void)hipGetLastError();
-                ge = nullptr;
-                graphs = 0;
+                return nullptr;
             }
-        }
-        if (ge) {
-            LSUM_HIP(hipGraphLaunch(ge, st));
+            cache.execs.push_back({nb, gx});
+            return gx;
+        };
+        // autotuning (first sweep of a shape bucket not yet decided): the sweep runs once in each
+        // way -- persistent, from a graph, round by round -- from the same rows X (a sweep reads X
+        // and writes only the other buffer), each timed; all three give the same rows bit for bit,
+        // and the last one's stand as this sweep's result
+        if (sweeps == 0 && tune_key_choice == -1) {
+            std::vector<double> ms(3, -1.0);
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            LSUM_HIP(hipEventCreate(&e0));
+            LSUM_HIP(hipEventCreate(&e1));
+            for (int m : {2, 1, 0}) {
+                LSUM_HIP(hipMemcpyAsync(xp_dev, xp_host, sizeof(xp_host), hipMemcpyHostToDevice, st));
+                persistent = m == 2;
+                GroupTokens tk;
+                bool ok = true;
+                if (persistent && !tk.take(run->wg_in_use, nblk / 2, persistent_capacity() * 3 / 4)) {
+                    persistent = 0;
+                    ok = false;
+                }
+                hipGraphExec_t gx = m == 1 ? graph_for(nblk) : nullptr;
+                if (m == 1 && !gx) ok = false;
+                LSUM_HIP(hipEventRecord(e0, st));
+                if (gx) {
+                    LSUM_HIP(hipGraphLaunch(gx, st));
+                } else {
+                    enqueue_sweep(nblk);
+                }
+                LSUM_HIP(hipEventRecord(e1, st));
+                int ab = 0;
+                if (persistent) LSUM_HIP(hipMemcpyAsync(&ab, ver + nblk, sizeof(int), hipMemcpyDeviceToHost, st));
+                LSUM_HIP(hipStreamSynchronize(st));
+                float t = 0.f;
+                if (ok && !ab && hipEventElapsedTime(&t, e0, e1) == hipSuccess) ms[m] = t;
+                (void)hipGetLastError();
+            }
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            const int ch = run->tuner->put(tune_key, ms);
+            persistent = ch == 2;
+            graphs = ch == 1;
+            tune_key_choice = ch;
+            run->tuned = 1;
         } else {
-            enqueue_sweep(nblk);
+            // a persistent sweep needs all its groups resident at once: it runs only while the
+            // groups of the persistent sweeps in flight stay within 3/4 of the device; else round
+            // by round
+            GroupTokens tokens;
+            const int persistent_mode = persistent;
+            if (persistent && !tokens.take(run->wg_in_use, nblk / 2, persistent_capacity() * 3 / 4)) persistent = 0;
+            hipGraphExec_t ge = graphs && !persistent ? graph_for(nblk) : nullptr;
+            if (graphs && !persistent && !ge) graphs = 0;   // capture refused: launch directly
+            if (ge) {
+                LSUM_HIP(hipGraphLaunch(ge, st));
+                used_graph = true;
+            } else {
+                enqueue_sweep(nblk);
+            }
+            was_persistent = persistent != 0;
+            if (!was_persistent) persistent = persistent_mode;   // no tokens this sweep: try again next sweep
         }
         cur ^= 1;
         // FP64 MFMA work of the sweep: every pair visit forms a 16 x 16 Gram over n_gram entries
         // and (when active) rotates 16 rows of ldx entries; counted for every visit
         run->flops += (double)(nblk / 2) * (nblk - 1) * 512.0 * ((double)n_gram + L.ldx);
-        const bool was_persistent = persistent != 0;
         unsigned long long st4[5] = {0, 0, 0, 0, 0};
         int aborted = 0;
         LSUM_HIP(hipMemcpyAsync(st4, stat, sizeof(st4), hipMemcpyDeviceToHost, st));
@@ -874,7 +940,6 @@ int jacobi_svd(hipStream_t st, int D, int N, double* A, int lda, double tol, dou
         double off, offk;
         std::memcpy(&off, &st4[0], sizeof(off));
         std::memcpy(&offk, &st4[4], sizeof(offk));
-        if (!was_persistent) persistent = persistent_mode;   // no tokens this sweep: try again next sweep
         if (was_persistent) {
             ++run->persistent_sweeps;
             if (aborted) {
@@ -913,7 +978,7 @@ int jacobi_svd(hipStream_t st, int D, int N, double* A, int lda, double tol, dou
         if (trace)
             std::fprintf(stderr, "jacobi D=%d N=%d sweep %d active %d max coupling %.3e kept %.3e rank %d inner sweeps %.2f avg %llu max over %llu pairs%s\n",
                          D, N, sweeps, d_act, off, offk, r_now, st4[3] ? (double)st4[1] / (double)st4[3] : 0.0, st4[2],
-                         st4[3], was_persistent ? " (persistent)" : (ge ? " (graph)" : ""));
+                         st4[3], was_persistent ? " (persistent)" : (used_graph ? " (graph)" : ""));
     }
     // write back the D largest columns in descending order
     double* Xcur = cur ? X2 : X;

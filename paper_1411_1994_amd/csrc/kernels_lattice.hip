@@ -3,6 +3,9 @@
 // All arithmetic is FP64.  These stages stream memory (no dense contraction), so they use
 // plain coalesced loads/stores and leave MFMA to the contraction kernels.
 #include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
 #include <hip/hip_ext.h>
 
 #include "lsum_internal.h"
@@ -474,20 +477,58 @@ void launch_collocate(hipStream_t st, int R, const double* t_dev, const double* 
     hipLaunchKernelGGL(k_collocate, grid, dim3(256), 0, st, R, t_dev, w13_dev, N_ref, h, shift, G, ldg);
 }
 
-void launch_shift_sum(hipStream_t st, const ShiftJob* jobs_dev, int n_jobs, int max_N, int max_R,
-                      const KTime* kt) {
-    if (n_jobs <= 0 || max_N <= 0) return;
-    // a small batch splits the nodes over the grid's z dimension (blocks of 16) so that the chip
-    // has enough workgroups to cover the L2 latency; a large one takes 48 nodes per workgroup
-    const int tiles = cdiv(max_N, 64) * n_jobs;
-    hipEvent_t a = kt ? kt->start : nullptr, b = kt ? kt->stop : nullptr;
-    if (tiles < 1024 && max_R > 16) {
+// Workgroup tile of the shift-sum: 64 cells x 16 nodes (the nodes split over the grid's z
+// dimension, NU = 2) or 64 cells x 48 nodes (NU = 6).  Both add the same terms in the same order.
+static void launch_shift_variant(hipStream_t st, int variant, const ShiftJob* jobs_dev, int n_jobs, int max_N,
+                                 int max_R, hipEvent_t a, hipEvent_t b) {
+    if (variant == 0) {
         const dim3 grid(cdiv(max_N, 64), n_jobs, cdiv(max_R, 16));
         hipExtLaunchKernelGGL(k_shift_sum<2>, grid, dim3(256), 0, st, a, b, 0, jobs_dev);
     } else {
         const dim3 grid(cdiv(max_N, 64), n_jobs);
         hipExtLaunchKernelGGL(k_shift_sum<6>, grid, dim3(256), 0, st, a, b, 0, jobs_dev);
     }
+}
+
+void launch_shift_sum(hipStream_t st, const ShiftJob* jobs_dev, int n_jobs, int max_N, int max_R,
+                      const KTime* kt, Tuner* tuner) {
+    if (n_jobs <= 0 || max_N <= 0) return;
+    const int tiles = cdiv(max_N, 64) * n_jobs;
+    hipEvent_t a = kt ? kt->start : nullptr, b = kt ? kt->stop : nullptr;
+    // without a decision: a small batch splits the nodes over the grid's z dimension so that the
+    // chip has enough workgroups to cover the L2 latency; a large one takes 48 nodes per group
+    int variant = (tiles < 1024 && max_R > 16) ? 0 : 1;
+    if (tuner && max_R > 16) {
+        int b2 = 1;
+        while (b2 < tiles) b2 <<= 1;
+        const std::string key = "shift_sum/tiles" + std::to_string(b2) + "/R" + std::to_string(max_R <= 32 ? 32 : 64);
+        const int ch = tuner->get(key);
+        if (ch >= 0) {
+            variant = ch;
+        } else if (ch == -1) {
+            // time both tiles (each writes the same values) and keep the faster
+            std::vector<double> ms(2, -1.0);
+            hipEvent_t e[4] = {};
+            bool ok = true;
+            for (auto& ev : e) ok = ok && hipEventCreate(&ev) == hipSuccess;
+            if (ok) {
+                launch_shift_variant(st, 0, jobs_dev, n_jobs, max_N, max_R, e[0], e[1]);
+                launch_shift_variant(st, 1, jobs_dev, n_jobs, max_N, max_R, e[2], e[3]);
+                float t0 = 0.f, t1 = 0.f;
+                if (hipEventSynchronize(e[3]) == hipSuccess && hipEventElapsedTime(&t0, e[0], e[1]) == hipSuccess &&
+                    hipEventElapsedTime(&t1, e[2], e[3]) == hipSuccess) {
+                    ms[0] = t0;
+                    ms[1] = t1;
+                }
+            }
+            (void)hipGetLastError();
+            for (auto& ev : e)
+                if (ev) (void)hipEventDestroy(ev);
+            const int best = tuner->put(key, ms);
+            if (best >= 0) variant = best;
+        }
+    }
+    launch_shift_variant(st, variant, jobs_dev, n_jobs, max_N, max_R, a, b);
 }
 
 void launch_window_sums(hipStream_t st, int R, const double* G, int ldg, int stride, int n, double* Q) {

@@ -37,6 +37,19 @@ int lsum_create(lsum_ctx* out, int device, size_t budget, int n_slots) {
     c.budget = budget ? budget : (size_t)(0.8 * (double)fr);
     c.n_slots = n_slots > 0 ? n_slots : 4;
     c.pool = new DevPool();
+    {
+        // the autotuner's decisions hold for devices of the same architecture and size
+        hipDeviceProp_t prop{};
+        if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+            std::string arch(prop.gcnArchName);
+            const size_t colon = arch.find(':');
+            if (colon != std::string::npos) arch.resize(colon);
+            c.tuner.set_device_tag(arch + "-" + std::to_string(prop.multiProcessorCount) + "cu");
+        } else {
+            (void)hipGetLastError();
+            c.tuner.set_device_tag("unknown");
+        }
+    }
     if (hipStreamCreateWithFlags(&c.own_stream, hipStreamNonBlocking) != hipSuccess) {
         c.own_stream = nullptr;
         delete x;
@@ -265,6 +278,8 @@ int lsum_get_info(lsum_req r, lsum_info* info) {
     info->norm_xi = q.norm_xi;
     info->bound = q.bound;
     info->rel_bound = q.norm_A > 0 ? q.bound / q.norm_A : 0.0;
+    info->probe_err = q.probe_err;
+    info->n_probe = q.n_probe;
     if (q.started) info->t_queue_ms = ms_since(q.t_submit, q.t_start);
     if (q.done && q.started) info->t_run_ms = ms_since(q.t_start, q.t_end);
     return LSUM_OK;
@@ -569,12 +584,18 @@ int lsum_get_stats(lsum_req r, char* buf, size_t len) {
           << "],\"range_k\":[" << q.range_k[0] << "," << q.range_k[1] << "," << q.range_k[2]
           << "],\"range_res\":[" << q.range_res[0] << "," << q.range_res[1] << "," << q.range_res[2]
           << "],\"norm_A\":" << q.norm_A
-          << ",\"norm_xi\":" << q.norm_xi << ",\"bound\":" << q.bound << ",\"batch\":" << q.batch_size
+          << ",\"norm_xi\":" << q.norm_xi << ",\"bound\":" << q.bound << ",\"probe_err\":" << q.probe_err
+          << ",\"n_probe\":" << q.n_probe << ",\"batch\":" << q.batch_size
           << ",\"als_skipped\":" << q.als_skipped << ",\"jacobi_persistent\":[" << q.jacobi_persistent[0] << ","
           << q.jacobi_persistent[1] << "," << q.jacobi_persistent[2] << "],\"jacobi_aborted\":["
           << q.jacobi_aborted[0] << "," << q.jacobi_aborted[1] << "," << q.jacobi_aborted[2]
+          << "],\"jacobi_tuned\":[" << q.jacobi_tuned[0] << "," << q.jacobi_tuned[1] << "," << q.jacobi_tuned[2]
           << "],\"als_core_norm\":[";
         for (size_t k = 0; k < q.als_core_norm.size(); ++k) o << (k ? "," : "") << q.als_core_norm[k];
+        o << "],\"probe_cells\":[";
+        for (size_t k = 0; k + 2 < q.probe_cells.size(); k += 3)
+            o << (k ? "," : "") << "[" << q.probe_cells[k] << "," << q.probe_cells[k + 1] << "," << q.probe_cells[k + 2]
+              << "]";
         o << "],\"offsets\":[";
         for (int b = 0; b < (int)P.blocks.size(); ++b) {
             o << (b ? "," : "") << "[";
@@ -706,6 +727,10 @@ int lsum_set_option(lsum_ctx x, int key, double value) {
             if (!(value == 0 || value == 1)) return fail(LSUM_E_INVALID, "persistent option must be 0 or 1");
             c.persistent.store((int)value);
             return LSUM_OK;
+        case LSUM_OPT_AUTOTUNE:
+            if (!(value == 0 || value == 1)) return fail(LSUM_E_INVALID, "autotune option must be 0 or 1");
+            c.tuner.enable(value == 1);
+            return LSUM_OK;
         case LSUM_OPT_JACOBI_WAIT_US:
             if (!(value >= 0 && value <= 1e8)) return fail(LSUM_E_INVALID, "wait bound must be in [0, 1e8] us");
             c.jacobi_wait_us.store((long long)value);
@@ -713,6 +738,22 @@ int lsum_set_option(lsum_ctx x, int key, double value) {
         default:
             return fail(LSUM_E_INVALID, "unknown option");
     }
+}
+
+int lsum_tune_file(lsum_ctx x, const char* path) {
+    if (!x || !path) return fail(LSUM_E_INVALID, "null argument");
+    return x->c.tuner.use_file(path);
+}
+
+int lsum_get_tuning(lsum_ctx x, char* buf, size_t len) {
+    if (!x) return fail(LSUM_E_INVALID, "null ctx");
+    const std::string j = x->c.tuner.json();
+    if (buf && len > 0) {
+        const size_t n = std::min(len - 1, j.size());
+        std::memcpy(buf, j.data(), n);
+        buf[n] = 0;
+    }
+    return (int)j.size();
 }
 
 int lsum_get_profile(lsum_ctx x, char* buf, size_t len) {

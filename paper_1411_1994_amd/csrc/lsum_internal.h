@@ -7,6 +7,8 @@
 #include <cstdint>
 #include <string>
 #include <atomic>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "lsum.h"
@@ -144,6 +146,35 @@ void launch_collocate(hipStream_t st, int R, const double* t_dev, const double* 
                       double h, double* G, int ldg, double shift = 0.0);
 // Optional kernel-bound timing: both events are recorded by the dispatch of the kernel itself
 // (hipExtLaunchKernel), so their difference is the kernel's own execution time.
+// ------------------------------------------------------------------------------------------
+// autotuner: launch variants that add the same terms in the same order (so every variant gives
+// the same results bit for bit) are timed on the first launch of a shape bucket, and the
+// fastest is kept, per context and optionally in a file shared between processes
+// ------------------------------------------------------------------------------------------
+class Tuner {
+  public:
+    // the variant chosen for key, or -1 (none yet, or tuning off: -2)
+    int get(const std::string& key);
+    // records the timings (ms, < 0: variant not measured) and keeps the fastest; returns it
+    int put(const std::string& key, const std::vector<double>& ms);
+    void set_device_tag(const std::string& tag) { tag_ = tag; }
+    void enable(bool on) { on_.store(on ? 1 : 0); }
+    bool enabled() const { return on_.load() != 0; }
+    // decisions of earlier runs (same device tag) from `path`, which new ones are appended to
+    int use_file(const std::string& path);
+    std::string json();
+
+  private:
+    struct Entry {
+        int choice;
+        std::vector<double> ms;
+    };
+    std::mutex mu_;
+    std::string tag_, path_;
+    std::map<std::string, Entry> dec_;
+    std::atomic<int> on_{1};
+};
+
 struct KTime {
     hipEvent_t start = nullptr, stop = nullptr;
 };
@@ -170,7 +201,7 @@ struct ShiftJob {
 // max_N, max_R: largest N_axis and R of the jobs; kt: optional kernel-bound timing.  Every row read must
 // extend one entry past the last cell window (ldg >= 2 * N_ref - 1 and ldg >= 2).
 void launch_shift_sum(hipStream_t st, const ShiftJob* jobs_dev, int n_jobs, int max_N, int max_R,
-                      const KTime* kt = nullptr);
+                      const KTime* kt = nullptr, Tuner* tuner = nullptr);
 // Q[q, x] = sum_{m=0}^{n-1} G[q, x - m S] over the terms with x - m S >= 0, for x < ldg.
 void launch_window_sums(hipStream_t st, int R, const double* G, int ldg, int stride, int n, double* Q);
 // The static scratch array of the allocation-free shift-sum (scratch_noalloc.hip): its size, and
@@ -284,6 +315,11 @@ void launch_core_groups(hipStream_t st, int elem, int r1, int r2, int j0, int nj
                         const int32_t* i1, const int32_t* i2, const double* sc, const void* Y1, long ldy1,
                         const void* Y2, long ldy2, void* out);
 // ||A||^2 from the three unnormalised column Grams (D x D) and the group table.
+// The canonical sum (groups of R terms: sources src_l[g] in the unnormalised columns C_l, D_l x N_l,
+// weights scale[g]) at n_cells cells (cells[3p + l]), in FP64: out[p].
+void launch_probe_canonical(hipStream_t st, int n_cells, int R, int n_groups, const int32_t* s1, const int32_t* s2,
+                            const int32_t* s3, const double* scale, const double* C1, const double* C2,
+                            const double* C3, int N1, int N2, int N3, const int32_t* cells, double* out);
 void launch_cp_norm2(hipStream_t st, int R, int n_groups, const int32_t* src1, const int32_t* src2,
                      const int32_t* src3, const double* scale, const double* C1, const double* C2,
                      const double* C3, int D1, int D2, int D3, double* partial, int n_partial);
@@ -311,6 +347,8 @@ struct JacobiRun {
     // a sweep runs persistently only while the total stays within 3/4 of what the device holds
     // at once, else round by round (nullptr: no accounting)
     std::atomic<int>* wg_in_use = nullptr;
+    Tuner* tuner = nullptr;        // decides the launch way per shape bucket (nullptr: as above)
+    int tuned = 0;                 // out: 1 if this call timed the three ways
     double flops = 0.0;            // out: FP64 MFMA work of the pair Grams and rotations (added)
     int persistent_sweeps = 0;     // out: sweeps launched persistently (added)
     int aborted = 0;               // out: persistent sweeps that aborted (added)

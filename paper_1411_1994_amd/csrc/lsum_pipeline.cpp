@@ -16,6 +16,9 @@
 
 namespace lsum {
 
+// cells at which every Tucker result is compared with its untruncated canonical sum
+constexpr int kProbeCells = 32;
+
 static GemmPrec gemm_prec(int precision) {
     return precision == LSUM_FP64 ? GEMM_F64 : (precision == LSUM_FP32 ? GEMM_F32 : GEMM_BF16X3);
 }
@@ -59,6 +62,7 @@ struct ModeSVD {
     int k = 0, sweeps = 0;
     double flops = 0.0;          // FP64 MFMA work: range-basis GEMMs, Jacobi Grams and rotations
     int persistent = 0, aborted = 0;   // Jacobi sweeps launched persistently / aborted
+    int tuned = 0;                     // the autotuner timed the ways of launching a sweep
 };
 
 // C (m x n) = alpha * X Y + beta * C over row-major operands; tX / tY: use the transpose.
@@ -215,6 +219,7 @@ static int range_svd(Context* c, hipStream_t st, int D, int N, const double* W, 
     out.flops += jr.flops;
     out.persistent += jr.persistent_sweeps;
     out.aborted += jr.aborted;
+    out.tuned |= jr.tuned;
     if (rc) return rc;
     out.res2 = res2;
     out.rows = std::move(AUG);
@@ -251,6 +256,7 @@ static int mode_svd(Context* c, hipStream_t st, int D, int N, DevBuf& W, double 
     out.flops += jr.flops;
     out.persistent += jr.persistent_sweeps;
     out.aborted += jr.aborted;
+    out.tuned |= jr.tuned;
     if (rc) return rc;
     out.res2 = 0.0;
     out.rows = std::move(W);
@@ -574,6 +580,7 @@ static int run_tucker(Request* q, hipStream_t st, const hipStream_t* aux, StageT
         svd_flops += ms[l].flops;
         q->jacobi_persistent[l] = ms[l].persistent;
         q->jacobi_aborted[l] = ms[l].aborted;
+        q->jacobi_tuned[l] = ms[l].tuned;
     }
     tm.work(0, svd_flops);
     tm.end();
@@ -648,7 +655,7 @@ static int run_tucker(Request* q, hipStream_t st, const hipStream_t* aux, StageT
         LSUM_HIP(hipStreamSynchronize(st));
     }
     tm.end();
-    for (int l = 0; l < 3; ++l) cols[l].reset();
+    // the columns stay until the result's error has been probed against them (step 9)
 
     // (7) core mu = sum_nu xi_nu y1 (x) y2 (x) y3 (eq. C-core), unnormalised columns: xi = scale;
     // term tables nu = g R + q -> projection rows src_l(g) R + q and the group scale.  When the
@@ -749,6 +756,55 @@ static int run_tucker(Request* q, hipStream_t st, const hipStream_t* aux, StageT
     // (8) optional tile
     if (P.has_tile() && (rc = make_tile(q, st, tm))) return rc;
     LSUM_HIP(hipStreamSynchronize(st));
+
+    // (9) the result's own error: its values at kProbeCells seeded cells, evaluated like any
+    // sample (in the request's precision), against the untruncated canonical sum in FP64
+    {
+        const int np = kProbeCells;
+        std::vector<int32_t> cells(3 * (size_t)np);
+        std::vector<double> xyz(3 * (size_t)np);
+        uint64_t state = 0x1411199400000000ull ^ ((uint64_t)P.N[0] << 40) ^ ((uint64_t)P.N[1] << 20) ^ (uint64_t)P.N[2];
+        for (int p = 0; p < np; ++p)
+            for (int l = 0; l < 3; ++l) {
+                // SplitMix64 (Steele, Lea, Flood 2014) of a counter
+                uint64_t z = (state += 0x9E3779B97F4A7C15ull);
+                z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+                z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+                z ^= z >> 31;
+                const int i = (int)(z % (uint64_t)P.N[l]);
+                cells[3 * p + l] = i;
+                xyz[3 * p + l] = (i - (P.N[l] - 1) / 2) * P.h;
+            }
+        if (!cols[0].p || !cols[1].p || !cols[2].p || !src_d.p || !scale_d.p)
+            return fail(LSUM_E_STATE, "probe: the side-matrix columns or term tables were released");
+        DevBuf cd, xd, vt, vc;
+        if ((rc = cd.get(c->pool, cells.size() * 4)) || (rc = xd.get(c->pool, xyz.size() * 8)) ||
+            (rc = vt.get(c->pool, (size_t)np * 8)) || (rc = vc.get(c->pool, (size_t)np * 8)))
+            return rc;
+        LSUM_HIP(hipMemcpyAsync(cd.p, cells.data(), cells.size() * 4, hipMemcpyHostToDevice, st));
+        LSUM_HIP(hipMemcpyAsync(xd.p, xyz.data(), xyz.size() * 8, hipMemcpyHostToDevice, st));
+        tm.begin("probe");
+        launch_probe_canonical(st, np, P.R, ng, s1, s2, s3, scale_d.as<double>(), cols[0].as<double>(),
+                               cols[1].as<double>(), cols[2].as<double>(), P.N[0], P.N[1], P.N[2],
+                               cd.as<int32_t>(), vc.as<double>());
+        double fl = 0.0;
+        if ((rc = sample_points(q, st, np, xd.as<double>(), vt.as<double>(), nullptr, &fl))) return rc;
+        tm.work(0, fl);
+        tm.end();
+        std::vector<double> a(np), b(np);
+        LSUM_HIP(hipMemcpyAsync(a.data(), vt.p, (size_t)np * 8, hipMemcpyDeviceToHost, st));
+        LSUM_HIP(hipMemcpyAsync(b.data(), vc.p, (size_t)np * 8, hipMemcpyDeviceToHost, st));
+        LSUM_HIP(hipStreamSynchronize(st));
+        double dmax = 0.0, vmax = 0.0;
+        for (int p = 0; p < np; ++p) {
+            dmax = std::max(dmax, std::fabs(a[p] - b[p]));
+            vmax = std::max(vmax, std::fabs(b[p]));
+        }
+        q->probe_err = vmax > 0.0 ? dmax / vmax : dmax;
+        q->n_probe = np;
+        q->probe_cells = cells;
+    }
+    for (int l = 0; l < 3; ++l) cols[l].reset();
     return LSUM_OK;
 }
 
@@ -1567,7 +1623,7 @@ int run_batch(std::vector<Request*>& reqs, hipStream_t st, const hipStream_t* au
     LSUM_HIP(hipMemcpyAsync(jobs_d.p, jobs.data(), jobs.size() * sizeof(ShiftJob), hipMemcpyHostToDevice, st));
     // algorithmic traffic: every distinct reference read once, every factor written once
     const KTime kt = tm.kernels("shift_sum", ref_bytes + out_bytes, loads);
-    launch_shift_sum(st, jobs_d.as<ShiftJob>(), (int)jobs.size(), maxN, maxR, &kt);
+    launch_shift_sum(st, jobs_d.as<ShiftJob>(), (int)jobs.size(), maxN, maxR, &kt, &c->tuner);
     LSUM_HIP(hipGetLastError());
 
     // defect tables (canonical sampling evaluates defect windows from the reference rows)

@@ -148,6 +148,7 @@ struct Context {
     std::atomic<int> persistent{0};           // Jacobi sweeps as one persistent launch each
     std::atomic<long long> jacobi_wait_us{500000};   // bound on a persistent sweep's waits
     std::atomic<int> persistent_wgs{0};       // workgroups of persistent sweeps now on the device
+    Tuner tuner;                              // launch variants per shape bucket
     std::vector<hipStream_t> streams;
     std::vector<hipStream_t> aux;    // three per slot: the per-mode SVDs of a request run concurrently
     std::vector<std::thread> workers;
@@ -180,6 +181,7 @@ inline JacobiRun jacobi_run(Context* c) {
     r.persistent = c->persistent.load();
     r.wait_us = (double)c->jacobi_wait_us.load();
     r.wg_in_use = &c->persistent_wgs;
+    r.tuner = &c->tuner;
     return r;
 }
 
@@ -224,8 +226,12 @@ struct Request {
     int range_k[3]{};                  // size of the range basis per mode (0: direct)
     std::vector<double> als_core_norm;  // ||core|| after each ALS sweep
     int als_skipped = 0;               // 1: ALS asked for but the ranks do not allow it
+    double probe_err = -1.0;           // Tucker result vs the FP64 canonical sum at probe cells
+    int n_probe = 0;
+    std::vector<int32_t> probe_cells;  // 3 * n_probe cell indices
     int jacobi_persistent[3]{};        // per mode: sweeps launched persistently
     int jacobi_aborted[3]{};           // per mode: persistent sweeps that aborted
+    int jacobi_tuned[3]{};             // per mode: 1 if the SVD timed the ways of launching a sweep
     std::string error;                 // message of a failed request (the worker's last error)
     DevBuf Z[3];                       // r_l x N_l FP64
     DevBuf core;                       // r1 r2 r3, FP64 or FP32 (precision)

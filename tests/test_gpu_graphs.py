@@ -29,6 +29,7 @@ def _run(graphs, problems):
     import paper_1411_1994_amd as L
     out = []
     with L.Context(0, n_slots=1) as c:
+        c.set_option(L.OPT_AUTOTUNE, 0)            # the options below decide
         c.set_option(L.OPT_JACOBI_PERSISTENT, 0)   # graphs apply to the round-by-round launches
         c.set_option(L.OPT_GRAPHS, graphs)
         for p in problems + problems:          # every problem twice on the same context
@@ -67,6 +68,7 @@ def _run_opts(opts, problems):
     import paper_1411_1994_amd as L
     out = []
     with L.Context(0, n_slots=1) as c:
+        c.set_option(L.OPT_AUTOTUNE, 0)
         for k, v in opts.items():
             c.set_option(k, v)
         for p in problems:
@@ -118,3 +120,38 @@ def test_persistent_sweep_abort_falls_back_to_round_launches():
         assert abs(got["r"][l] - ref["r"][l]) <= max(2, ref["r"][l] // 50), (got["r"], ref["r"])
     oracle_ref = O.brute_force_points(p, got["cells"])
     assert np.max(np.abs(got["v"] - oracle_ref)) <= p.eps * nA
+
+
+def test_autotuned_sweeps_equal_fixed_ones_and_decisions_persist(tmp_path):
+    # the autotuner times the three ways of launching a sweep on the first sweep of each shape
+    # bucket and keeps the fastest; results are bit for bit those of a fixed way, and a second
+    # context reads the decisions back from the tuning file instead of timing again
+    require_gpu()
+    import paper_1411_1994_amd as L
+    probs = _problems()
+    fixed = _run_opts({L.OPT_JACOBI_PERSISTENT: 0}, probs)
+    path = str(tmp_path / "tune.txt")
+    tuned = []
+    for round_ in range(2):
+        with L.Context(0, n_slots=1) as c:
+            c.set_option(L.OPT_AUTOTUNE, 1)
+            c.tune_file(path)
+            for p in probs:
+                r = c.submit(p)
+                assert r.wait() == 0, r.stats()
+                st = r.stats()
+                tuned.append(sum(st["jacobi_tuned"]))
+                rng = np.random.default_rng(6)
+                cells = np.stack([rng.integers(0, n, 16) for n in p.N], axis=1)
+                xyz = np.stack([(cells[:, a] - (p.N[a] - 1) // 2) * p.h for a in range(3)], axis=1)
+                k = probs.index(p)
+                assert np.array_equal(r.sample(xyz), fixed[k]["v"]), k
+                assert tuple(st["sweeps"]) == fixed[k]["sweeps"]
+                r.release()
+            dec = c.tuning()
+        assert dec["enabled"] == 1 and any(key.startswith("jacobi/") for key in dec["decisions"]), dec
+        for v in dec["decisions"].values():
+            assert 0 <= v["choice"] < len(v["ms"]) and v["ms"][v["choice"]] >= 0
+    n = len(probs)
+    assert sum(tuned[:n]) >= 1          # the first context timed the ways
+    assert sum(tuned[n:]) == 0          # the second read the file

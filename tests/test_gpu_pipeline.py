@@ -221,6 +221,29 @@ def test_rhosvd_mixed_precision_error(ctx, prec):
 
 
 @pytest.mark.parametrize("prec", [W.FP64, W.FP32, W.BF16X3])
+def test_result_states_its_error_against_the_oracle(ctx, prec):
+    # Every Tucker result reports its max-norm relative deviation at seeded probe cells from the
+    # untruncated canonical sum (the discrete tensor the oracle's direct sum gives): the stated
+    # number is the deviation measured against the oracle at those cells, it respects the
+    # certified Frobenius bound, and it grows with the rounding of the precision
+    p = _small_defected(eps=1e-6, precision=prec)
+    r = run(ctx, p)
+    inf, st = r.info(), r.stats()
+    cells = np.array(st["probe_cells"])
+    assert inf.n_probe == st["n_probe"] == len(cells) == 32
+    ref = O.brute_force_points(p, cells)
+    v = r.sample(cells_xyz(p, cells))
+    scale = np.max(np.abs(ref))
+    err = np.max(np.abs(v - ref)) / scale
+    # the library's canonical sum and the oracle's direct sum agree to ~1e-14 of the values
+    assert abs(inf.probe_err - err) <= 1e-12, (inf.probe_err, err)
+    assert inf.probe_err * scale <= inf.bound * (1 + 1e-9) + (0 if prec == W.FP64 else 1e-4 * scale)
+    tol = {W.FP64: 1e-6, W.FP32: 1e-5, W.BF16X3: 1e-4}[prec]
+    assert inf.probe_err < tol, inf.probe_err
+    r.release()
+
+
+@pytest.mark.parametrize("prec", [W.FP64, W.FP32, W.BF16X3])
 def test_grouped_core_matches_oracle(ctx, prec):
     # 20 defects on the 5 x 4 x 4 lattice share at most 4 mode-3 planes: the terms of each mode-3
     # column are summed before the mode-3 contraction (D3 <= K / 2).  The core against the
