@@ -54,7 +54,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=None,
                     help="timed requests (default: 20 for the served mix, 2048 for the config-2 stream)")
     ap.add_argument("--warmup", type=int, default=None, help="untimed requests before them (5 / 128)")
-    ap.add_argument("--workload", default="mix", choices=["cfg2", "cfg3", "cfg4", "mix", "timesL", "extras"])
+    ap.add_argument("--workload", default="mix", choices=["cfg2", "cfg3", "cfg4", "mix", "timesL", "extras", "shiftrect"])
     ap.add_argument("--inflight", type=int, default=64)
     ap.add_argument("--slots", type=int, default=3)
     ap.add_argument("--batch", type=int, default=32)
@@ -264,6 +264,41 @@ def mix_cpu_baseline(probs, gpu_plain_s, seconds):
                                                 "unit": "lattice sums/s"}}
 
 
+def run_shift_rect(n_req=1024):
+    """The batched shift-sum on config-5-shaped lattices: n_req canonical requests (no defects,
+    FP64 point-major rows) with the served mix's rectangular L in [8, 96] per axis, grids of
+    257..4097 cells, the three kernels -- every axis a job of its own (no two axes alike) --
+    submitted together as one batch, so that all their shift-sums run as one launch."""
+    import paper_1411_1994_amd as L
+    import workloads as W
+    rng = np.random.default_rng(W.SEED_BASE + 77)
+    probs = [W.Problem(**{**W.served_request(rng, i).__dict__, "defects": [], "eps": 0.0, "precision": W.FP64})
+             for i in range(n_req)]
+    ctx = L.Context(0, n_slots=1)
+    ctx.set_option(L.OPT_MAX_BATCH, n_req)
+    ctx.set_option(L.OPT_AUTOTUNE, 0)      # the fixed tile rule (48 nodes per workgroup at this size)
+    prepared = [L.prepare(p) for p in probs]
+    for attempt in range(2):               # the first run fills the reference and window caches
+        ctx.reset_profile()
+        reqs = ctx.submit_many(prepared)
+        for r in reqs:
+            if r.wait() != 0:
+                raise RuntimeError(f"rectangular shift-sum request failed: {r.stats().get('error')}")
+        jobs = sum(sum(1 for l in range(3) if r.stats()["axis_src"][l] == l) for r in reqs)
+        for r in reqs:
+            r.release()
+    prof = ctx.profile()
+    ctx.close()
+    _, roof = dominant_roofline({"shift_sum": prof["shift_sum"]}, "f64")
+    if roof is not None:
+        roof["jobs_per_launch"] = jobs / max(1, prof["shift_sum"]["launches"])
+        roof["requests_per_launch"] = n_req / max(1, prof["shift_sum"]["launches"])
+        roof["traffic"] = traffic_from_profiles("shift_sum_rect", roof["jobs_per_launch"])
+        roof["workload"] = (f"{n_req} canonical requests of the served mix's shapes (L in [8, 96] per axis, "
+                            f"N 257..4097, Newton/Yukawa/Slater, FP64 rows), one batch")
+    return roof
+
+
 def run_mix(args):
     """The served mixed workload: requests of the seeded 10,000-request stream (uneven lattice,
     grid, kernel, defect count and eps); `warmup` requests untimed, then `steps` requests served
@@ -320,6 +355,7 @@ def run_mix(args):
     sctx.reset_profile()
     s_secs, s_lat = closed(sctx, timed_idx, 2 * args.slots)
     prof = sctx.profile()
+    tuning = sctx.tuning()
     served = steps / s_secs
     served_vals = {k: outs[k].cpu().numpy().copy() for k in timed_idx}
     infos = {}
@@ -429,6 +465,7 @@ def run_mix(args):
                          "rel_bound_per_request": [probe[k][1] for k in timed_idx]},
         "roofline": roof,
         "mfma_stages": mfma,
+        "autotuner": tuning,
         "stages": {k: {"ms_per_launch": v["ms"] / max(1, v["launches"]), "launches": v["launches"]}
                    for k, v in prof.items()},
     }
@@ -657,7 +694,11 @@ def main():
                                                     "served_over_plain", "served_fp64_rows", "served_exact_sites",
                                                     "max_rel_err_vs_oracle", "roofline", "roofline_shift_sum",
                                                     "roofline_shift_sum_batched", "dtype")}
+        out["roofline_shift_sum_rect"] = run_shift_rect()
         print(json.dumps(out))
+        return
+    if args.workload == "shiftrect":
+        print(json.dumps({"roofline_shift_sum_rect": run_shift_rect()}))
         return
     if args.steps is None:
         args.steps = 2048

@@ -758,13 +758,17 @@ int jacobi_svd(hipStream_t st, int D, int N, double* A, int lda, double tol, dou
     double* keep2_dev = (double*)(base + L.off_ptr + 2 * sizeof(double*));
     int* ver = (int*)(base + L.off_ver);
     // the bound on a persistent sweep's waits, in ticks of the constant-rate wall clock (kHz)
+    // (persistent sweeps may also be chosen later by the autotuner, so it is set up front; without
+    // a clock rate no sweep runs persistently)
     long long tick_limit = 0;
-    if (persistent) {
+    bool clock_ok = true;
+    {
         int dev = 0, khz = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0) {
             (void)hipGetLastError();
             persistent = 0;
+            clock_ok = false;
         }
         tick_limit = (long long)(run->wait_us * 1e-3 * khz);
     }
@@ -876,6 +880,7 @@ int jacobi_svd(hipStream_t st, int D, int N, double* A, int lda, double tol, dou
             LSUM_HIP(hipEventCreate(&e0));
             LSUM_HIP(hipEventCreate(&e1));
             for (int m : {2, 1, 0}) {
+                if (m == 2 && !clock_ok) continue;
                 LSUM_HIP(hipMemcpyAsync(xp_dev, xp_host, sizeof(xp_host), hipMemcpyHostToDevice, st));
                 persistent = m == 2;
                 GroupTokens tk;

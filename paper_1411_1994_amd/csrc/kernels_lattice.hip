@@ -69,13 +69,22 @@ typedef double dpair __attribute__((ext_vector_type(2), aligned(8)));
 // A register budget for 6 waves per SIMD (the limit the LDS tile sets anyway): more waves in
 // flight hide more of the gather latency (1024 jobs: 11 % faster than the compiler's own budget,
 // which leaves 5).
+// The grid is one-dimensional, tx x ny x nz work-groups (cell tile, job, node block) numbered so
+// that consecutive numbers stay on one XCD (the hardware deals work-groups round-robin over the
+// 8 XCDs): a job's tiles are then contiguous on one XCD and its table rows are fetched into that
+// XCD's L2 only, where the terms of all its tiles re-read them.
 template <int NU>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) k_shift_sum(const ShiftJob* __restrict__ jobs) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) k_shift_sum(const ShiftJob* __restrict__ jobs,
+                                                                                              int tx, int ny, int nz) {
     constexpr int QB = 8 * NU, TU = 2;
     __shared__ double tile[64][QB + 1];
-    const ShiftJob& jb = jobs[blockIdx.y];
+    const int per_xcd = (int)(gridDim.x / 8);
+    const int v = (int)(blockIdx.x % 8) * per_xcd + (int)(blockIdx.x / 8);
+    if (v >= tx * ny * nz) return;
+    const int bx = v % tx, by = (v / tx) % ny, bz = v / (tx * ny);
+    const ShiftJob& jb = jobs[by];
     const int N = jb.N_axis;
-    const int i0 = blockIdx.x * 64;
+    const int i0 = bx * 64;
     if (i0 >= N) return;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int pr = lane & 31;
@@ -94,7 +103,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))
     LSUM_GLOBAL double* __restrict__ UT = (LSUM_GLOBAL double*)jb.UT;
     LSUM_GLOBAL float* __restrict__ UT32 = (LSUM_GLOBAL float*)jb.UT32;
     const bool rows = UT || UT32;
-    for (int q0 = blockIdx.z * QB; q0 < jb.R; q0 += gridDim.z * QB) {
+    for (int q0 = bz * QB; q0 < jb.R; q0 += nz * QB) {
         const int qn = min(QB, jb.R - q0);
         size_t qo[NU];
 #pragma unroll
@@ -481,12 +490,14 @@ void launch_collocate(hipStream_t st, int R, const double* t_dev, const double* 
 // dimension, NU = 2) or 64 cells x 48 nodes (NU = 6).  Both add the same terms in the same order.
 static void launch_shift_variant(hipStream_t st, int variant, const ShiftJob* jobs_dev, int n_jobs, int max_N,
                                  int max_R, hipEvent_t a, hipEvent_t b) {
+    const int tx = cdiv(max_N, 64);
+    const int nz = variant == 0 ? cdiv(max_R, 16) : 1;
+    const long total = (long)tx * n_jobs * nz;
+    const dim3 grid((unsigned)((total + 7) / 8 * 8));   // a multiple of the 8 XCDs
     if (variant == 0) {
-        const dim3 grid(cdiv(max_N, 64), n_jobs, cdiv(max_R, 16));
-        hipExtLaunchKernelGGL(k_shift_sum<2>, grid, dim3(256), 0, st, a, b, 0, jobs_dev);
+        hipExtLaunchKernelGGL(k_shift_sum<2>, grid, dim3(256), 0, st, a, b, 0, jobs_dev, tx, n_jobs, nz);
     } else {
-        const dim3 grid(cdiv(max_N, 64), n_jobs);
-        hipExtLaunchKernelGGL(k_shift_sum<6>, grid, dim3(256), 0, st, a, b, 0, jobs_dev);
+        hipExtLaunchKernelGGL(k_shift_sum<6>, grid, dim3(256), 0, st, a, b, 0, jobs_dev, tx, n_jobs, nz);
     }
 }
 
