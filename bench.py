@@ -319,7 +319,7 @@ def run_mix(args):
     outs = [torch.zeros(n_pts, dtype=torch.float64, device="cuda") for _ in probs]
     torch.cuda.synchronize()
 
-    probe = {}
+    probe, sweeps = {}, {}
 
     def closed(ctx, idx, inflight):
         """Submit the requests idx keeping at most `inflight` in flight; (seconds, latencies)."""
@@ -340,6 +340,8 @@ def run_mix(args):
             inf = r.info()
             lat[k] = inf.t_queue_ms + inf.t_run_ms
             probe[k] = (inf.probe_err, inf.rel_bound)
+            st = r.stats()
+            sweeps[k] = (sum(st["sweeps"]), sum(st["jacobi_persistent"]), sum(st["jacobi_aborted"]))
             r.release()
         torch.cuda.synchronize()
         return time.perf_counter() - t0, lat
@@ -364,6 +366,7 @@ def run_mix(args):
     pctx = L.Context(0, n_slots=1)
     pctx.set_option(L.OPT_MAX_BATCH, 1)
     pctx.set_option(L.OPT_REF_CACHE_BYTES, 0)
+    pctx.set_option(L.OPT_AUTOTUNE, 0)       # fixed launches: round-by-round sweeps, no graphs
     plain_probs = [W.Problem(**{**p.__dict__, "precision": W.FP64}) for p in probs]
     plain_s, p_lat, plain_vals = {}, {}, {}
     for k in ([warm_idx[0]] if warm_idx else []) + timed_idx:
@@ -466,6 +469,9 @@ def run_mix(args):
         "roofline": roof,
         "mfma_stages": mfma,
         "autotuner": tuning,
+        "jacobi_sweeps": {"total": sum(sweeps[k][0] for k in timed_idx),
+                          "persistent": sum(sweeps[k][1] for k in timed_idx),
+                          "persistent_aborted": sum(sweeps[k][2] for k in timed_idx)},
         "stages": {k: {"ms_per_launch": v["ms"] / max(1, v["launches"]), "launches": v["launches"]}
                    for k, v in prof.items()},
     }

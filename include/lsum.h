@@ -231,20 +231,22 @@ const char* lsum_last_error(void);
 #define LSUM_OPT_JACOBI_MAX_SWEEPS 5
 /* How the sweeps of a Jacobi SVD are launched; every way gives the same results bit for bit.
  * Default: round by round (three launches per round of disjoint column-block pairs).
- * LSUM_OPT_JACOBI_PERSISTENT (default 0): a sweep is one launch with one workgroup per pair of
- * column blocks, its rounds ordered by per-block completion counters in device memory; it runs
- * persistently while the persistent workgroups in flight fit 3/4 of the device, else round by
- * round.  Each wait is bounded by LSUM_OPT_JACOBI_WAIT_US (default 500000 microseconds, 0..1e8):
- * when the workgroups are not all resident at once the sweep aborts (the rows stay an
- * orthogonal transform of the input; lsum_get_stats counts such sweeps in "jacobi_aborted") and
- * the rest of that SVD launches round by round.
+ * LSUM_OPT_JACOBI_PERSISTENT (default 0; 1: groups of 16 waves, 2: groups of 4 waves): a sweep
+ * is one launch with one workgroup per pair of column blocks, its rounds ordered by per-block
+ * completion counters in device memory; it runs persistently while the persistent workgroups
+ * in flight fit 3/4 of the device, else round by round.  Each wait is bounded by
+ * LSUM_OPT_JACOBI_WAIT_US (default 20000 microseconds, 0..1e8):
+ * when the workgroups are not all resident at once the sweep aborts; it read the rows before it
+ * and wrote only a second buffer, so it runs again round by round from those rows (the result
+ * is unchanged; lsum_get_stats counts such sweeps in "jacobi_aborted"), and the rest of that
+ * SVD launches round by round.
  * LSUM_OPT_GRAPHS (default 0; applies when not persistent): the round-by-round launches of a
  * sweep are captured once per block count in a HIP graph and replayed. */
 #define LSUM_OPT_GRAPHS 6
 #define LSUM_OPT_JACOBI_PERSISTENT 7
 #define LSUM_OPT_JACOBI_WAIT_US 8
 /* LSUM_OPT_AUTOTUNE (default 1): launch variants that add the same terms in the same order (the
- * three ways of launching a Jacobi sweep above; the shift-sum's 16- or 48-node workgroup tiles)
+ * four ways of launching a Jacobi sweep above; the shift-sum's 16- or 48-node workgroup tiles)
  * are timed on the first launch of each shape bucket and the fastest is used from then on; the
  * choice never changes a result.  With it, the sweep ways chosen override the two options
  * above.  0: the options and fixed thresholds decide. */

@@ -291,14 +291,17 @@ __global__ void __launch_bounds__(256) k_pair_rotate(double* const* __restrict__
 // flag, and every group leaves at its next wait once the flag is up.  A group rotates only
 // pairs it has started, so an aborted sweep leaves the rows an orthogonal transform of the
 // input.
-constexpr int PS_WAVES = 16;   // waves of a persistent pair group: four chunks of CW cells at a time
-
-__global__ void __launch_bounds__(PS_WAVES * 64) k_jacobi_sweep(double* const* __restrict__ xp, int ldx, int n_gram,
+// A pair group of WAVES waves takes WAVES / 4 chunks of CW cells at a time (16 waves: one group
+// fills a compute unit and has four chunks in flight; 4 waves: four groups share a compute unit,
+// which is easier to place next to other work).  Both add the chunk partials in chunk order.
+template <int WAVES>
+__global__ void __launch_bounds__(WAVES * 64) k_jacobi_sweep(double* const* __restrict__ xp, int ldx, int n_gram,
                                                       int nblk, int nchunk, int nchunk_all, double tol, double irr2,
                                                       const double* __restrict__ keep2p, int max_inner,
                                                       unsigned long long* __restrict__ stat, int* __restrict__ ver,
                                                       int* __restrict__ abort_flag, long long tick_limit) {
-    __shared__ double Gp[PS_WAVES][16][17];
+    constexpr int CPS = WAVES / 4;   // chunks per step
+    __shared__ double Gp[WAVES][16][17];
     __shared__ double G[16][17];
     __shared__ double Q[16][17];
     __shared__ int sh_go, sh_act;
@@ -306,7 +309,7 @@ __global__ void __launch_bounds__(PS_WAVES * 64) k_jacobi_sweep(double* const* _
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int r = lane & 15, kg = lane >> 4;
     const int ga = (tid >> 4) & 15, gb = tid & 15;
-    const int sub = wave >> 2, quarter = wave & 3;   // chunk within a step of four, quarter of it
+    const int sub = wave >> 2, quarter = wave & 3;   // chunk within a step, quarter of it
     double* X = xp[0];   // not restrict: other groups write its rows between the rounds
     const double keep2 = *keep2p;
     const long long t0 = (long long)wall_clock64();
@@ -343,7 +346,7 @@ __global__ void __launch_bounds__(PS_WAVES * 64) k_jacobi_sweep(double* const* _
         // 1. the pair's Gram: wave (sub, quarter) takes quarter `quarter` of chunk step + sub
         const double* xr = X + (size_t)pair_row(I, J, r) * ldx;
         double gsum = 0.0;
-        for (int step = 0; step < nchunk; step += 4) {
+        for (int step = 0; step < nchunk; step += CPS) {
             const int c0 = (step + sub) * CW + quarter * (CW / 4);
             double x[16];
 #pragma unroll
@@ -358,7 +361,7 @@ __global__ void __launch_bounds__(PS_WAVES * 64) k_jacobi_sweep(double* const* _
             for (int v = 0; v < 4; ++v) Gp[wave][kg + 4 * v][r] = acc[v];
             __syncthreads();
             if (tid < 256)
-                for (int cc = 0; cc < 4 && step + cc < nchunk; ++cc)
+                for (int cc = 0; cc < CPS && step + cc < nchunk; ++cc)
                     gsum += ((Gp[4 * cc][ga][gb] + Gp[4 * cc + 1][ga][gb]) + Gp[4 * cc + 2][ga][gb]) +
                             Gp[4 * cc + 3][ga][gb];
             __syncthreads();
@@ -376,7 +379,7 @@ __global__ void __launch_bounds__(PS_WAVES * 64) k_jacobi_sweep(double* const* _
         __syncthreads();
         // 3. X_pair <- Q^T X_pair, four chunks at a time (each wave owns 64 cells of one)
         if (sh_act) {
-            for (int step = 0; step < nchunk_all; step += 4) {
+            for (int step = 0; step < nchunk_all; step += CPS) {
                 const int c0 = (step + sub) * CW + quarter * (CW / 4);
                 double b[4][4];
 #pragma unroll
@@ -670,22 +673,40 @@ void launch_random_signs(hipStream_t st, long n, unsigned long long seed, double
     hipLaunchKernelGGL(k_random_signs, dim3(cdiv(n, 256)), dim3(256), 0, st, n, seed, out);
 }
 
-// Persistent sweep groups the device holds at once (occupancy x compute units), per device.
-static int persistent_capacity() {
+// Persistent sweep capacity of the device in units of a quarter compute unit (the CU count x 4),
+// and what one group of each persistent variant takes (4 / groups that fit in a compute unit:
+// 4 units for the 16-wave group, 1 for the 4-wave one), per device; 0 if unknown.
+struct PersistentCap {
+    int units = 0;
+    int per_group[3] = {0, 0, 0};   // indexed by the persistent variant (1: 16 waves, 2: 4 waves)
+};
+
+static PersistentCap persistent_capacity() {
     static std::mutex mu;
-    static std::vector<int> cap;
+    static std::vector<PersistentCap> cap;
+    static std::vector<int> known;
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipGetDevice(&dev) != hipSuccess) return PersistentCap{};
     std::lock_guard<std::mutex> lk(mu);
-    if ((int)cap.size() <= dev) cap.resize(dev + 1, -1);
-    if (cap[dev] < 0) {
-        int per_cu = 0, cus = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_jacobi_sweep, PS_WAVES * 64, 0) != hipSuccess ||
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+    if ((int)cap.size() <= dev) {
+        cap.resize(dev + 1);
+        known.resize(dev + 1, 0);
+    }
+    if (!known[dev]) {
+        PersistentCap c;
+        int b16 = 0, b4 = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b16, k_jacobi_sweep<16>, 16 * 64, 0) == hipSuccess &&
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&b4, k_jacobi_sweep<4>, 4 * 64, 0) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && b16 > 0 &&
+            b4 > 0) {
+            c.units = 4 * cus;
+            c.per_group[1] = (4 + b16 - 1) / b16;
+            c.per_group[2] = (4 + b4 - 1) / b4;
+        } else {
             (void)hipGetLastError();
-            per_cu = cus = 0;
         }
-        cap[dev] = per_cu * cus;
+        cap[dev] = c;
+        known[dev] = 1;
     }
     return cap[dev];
 }
@@ -805,8 +826,14 @@ int jacobi_svd(hipStream_t st, int D, int N, double* A, int lda, double tol, dou
         hipLaunchKernelGGL(k_permute_xp, dim3(cdiv(L.ldx, 256), L.Dp), dim3(256), 0, st, L.ldx, perm_dev, xp_dev);
         hipLaunchKernelGGL(k_swap_clear, dim3(1), dim3(64), 0, st, xp_dev, stat, ver, nblk);
         if (persistent) {
-            hipLaunchKernelGGL(k_jacobi_sweep, dim3(npair), dim3(PS_WAVES * 64), 0, st, xp_dev, L.ldx, n_gram, nblk, L.nchunk,
-                               L.nchunk_all, tol, irr2, keep2_dev, max_inner, stat, ver, ver + nblk, tick_limit);
+            if (persistent == 2)
+                hipLaunchKernelGGL(k_jacobi_sweep<4>, dim3(npair), dim3(4 * 64), 0, st, xp_dev, L.ldx, n_gram, nblk,
+                                   L.nchunk, L.nchunk_all, tol, irr2, keep2_dev, max_inner, stat, ver, ver + nblk,
+                                   tick_limit);
+            else
+                hipLaunchKernelGGL(k_jacobi_sweep<16>, dim3(npair), dim3(16 * 64), 0, st, xp_dev, L.ldx, n_gram, nblk,
+                                   L.nchunk, L.nchunk_all, tol, irr2, keep2_dev, max_inner, stat, ver, ver + nblk,
+                                   tick_limit);
             hipLaunchKernelGGL(k_norms_xp, dim3(L.Dp), dim3(256), 0, st, L.ldx, n_gram, xp_dev, nrm);
             return;
         }
@@ -837,9 +864,10 @@ int jacobi_svd(hipStream_t st, int D, int N, double* A, int lda, double tol, dou
                                  std::to_string(pow2(n_gram));
     int tune_key_choice = run->tuner ? run->tuner->get(tune_key) : -2;
     if (tune_key_choice >= 0) {
-        persistent = tune_key_choice == 2;
+        persistent = tune_key_choice == 2 ? 1 : (tune_key_choice == 3 ? 2 : 0);
         graphs = tune_key_choice == 1;
     }
+    const PersistentCap pcap = persistent_capacity();
     for (; sweeps < max_sweeps && !converged; ++sweeps) {
         bool was_persistent = false, used_graph = false;
         // only columns above the floor take part (sorted first); the rest are never rotated
@@ -848,6 +876,11 @@ int jacobi_svd(hipStream_t st, int D, int N, double* A, int lda, double tol, dou
         const int nblk = std::max(2, (d_act + 15) / 16 * 2);
         LSUM_HIP(hipMemcpyAsync(perm_dev, perm.data(), L.Dp * sizeof(int32_t), hipMemcpyHostToDevice, st));
         LSUM_HIP(hipMemcpyAsync(keep2_dev, &keep2, sizeof(double), hipMemcpyHostToDevice, st));
+        // persistent groups reserved against 3/4 of the device (per variant: its share of a CU)
+        auto take_tokens = [&](GroupTokens& t) -> bool {
+            if (pcap.units <= 0 || persistent < 1 || persistent > 2) return false;
+            return t.take(run->wg_in_use, (nblk / 2) * pcap.per_group[persistent], pcap.units * 3 / 4);
+        };
         // the sweep's graph for this block count, captured on first use (nullptr if refused)
         auto graph_for = [&](int nb) -> hipGraphExec_t {
             hipGraphExec_t gx = cache.find(nb);
@@ -875,17 +908,18 @@ int jacobi_svd(hipStream_t st, int D, int N, double* A, int lda, double tol, dou
         // and writes only the other buffer), each timed; all three give the same rows bit for bit,
         // and the last one's stand as this sweep's result
         if (sweeps == 0 && tune_key_choice == -1) {
-            std::vector<double> ms(3, -1.0);
+            // variants: 0 round by round, 1 graph, 2 persistent 16-wave groups, 3 persistent 4-wave
+            std::vector<double> ms(4, -1.0);
             hipEvent_t e0 = nullptr, e1 = nullptr;
             LSUM_HIP(hipEventCreate(&e0));
             LSUM_HIP(hipEventCreate(&e1));
-            for (int m : {2, 1, 0}) {
-                if (m == 2 && !clock_ok) continue;
+            for (int m : {3, 2, 1, 0}) {
+                if (m >= 2 && !clock_ok) continue;
                 LSUM_HIP(hipMemcpyAsync(xp_dev, xp_host, sizeof(xp_host), hipMemcpyHostToDevice, st));
-                persistent = m == 2;
+                persistent = m == 2 ? 1 : (m == 3 ? 2 : 0);
                 GroupTokens tk;
                 bool ok = true;
-                if (persistent && !tk.take(run->wg_in_use, nblk / 2, persistent_capacity() * 3 / 4)) {
+                if (persistent && !take_tokens(tk)) {
                     persistent = 0;
                     ok = false;
                 }
@@ -908,7 +942,7 @@ int jacobi_svd(hipStream_t st, int D, int N, double* A, int lda, double tol, dou
             (void)hipEventDestroy(e0);
             (void)hipEventDestroy(e1);
             const int ch = run->tuner->put(tune_key, ms);
-            persistent = ch == 2;
+            persistent = ch == 2 ? 1 : (ch == 3 ? 2 : 0);
             graphs = ch == 1;
             tune_key_choice = ch;
             run->tuned = 1;
@@ -918,7 +952,7 @@ int jacobi_svd(hipStream_t st, int D, int N, double* A, int lda, double tol, dou
             // by round
             GroupTokens tokens;
             const int persistent_mode = persistent;
-            if (persistent && !tokens.take(run->wg_in_use, nblk / 2, persistent_capacity() * 3 / 4)) persistent = 0;
+            if (persistent && !take_tokens(tokens)) persistent = 0;
             hipGraphExec_t ge = graphs && !persistent ? graph_for(nblk) : nullptr;
             if (graphs && !persistent && !ge) graphs = 0;   // capture refused: launch directly
             if (ge) {
@@ -930,6 +964,8 @@ int jacobi_svd(hipStream_t st, int D, int N, double* A, int lda, double tol, dou
             was_persistent = persistent != 0;
             if (!was_persistent) persistent = persistent_mode;   // no tokens this sweep: try again next sweep
         }
+        // the buffers before this sweep: it read the current one and wrote only the other
+        double* before[2] = {cur ? X2 : X, cur ? X : X2};
         cur ^= 1;
         // FP64 MFMA work of the sweep: every pair visit forms a 16 x 16 Gram over n_gram entries
         // and (when active) rotates 16 rows of ldx entries; counted for every visit
@@ -941,23 +977,29 @@ int jacobi_svd(hipStream_t st, int D, int N, double* A, int lda, double tol, dou
         LSUM_HIP(hipMemcpyAsync(sig2.data(), nrm, L.Dp * sizeof(double), hipMemcpyDeviceToHost, st));
         LSUM_HIP(hipStreamSynchronize(st));
         LSUM_HIP(hipGetLastError());
+        if (was_persistent) {
+            ++run->persistent_sweeps;
+            if (aborted) {
+                // some groups were not resident together (or the wait bound is tiny), so the
+                // sweep visited only part of the pairs.  It read the rows before it and wrote only
+                // the other buffer: it runs again, round by round, from those rows, which gives the
+                // rows an uninterrupted sweep gives; the remaining sweeps launch round by round
+                ++run->aborted;
+                persistent = 0;
+                was_persistent = false;
+                if (trace) std::fprintf(stderr, "jacobi D=%d N=%d sweep %d: persistent sweep aborted, run again\n", D, N, sweeps);
+                LSUM_HIP(hipMemcpyAsync(xp_dev, before, sizeof(before), hipMemcpyHostToDevice, st));
+                enqueue_sweep(nblk);
+                LSUM_HIP(hipMemcpyAsync(st4, stat, sizeof(st4), hipMemcpyDeviceToHost, st));
+                LSUM_HIP(hipMemcpyAsync(sig2.data(), nrm, L.Dp * sizeof(double), hipMemcpyDeviceToHost, st));
+                LSUM_HIP(hipStreamSynchronize(st));
+                LSUM_HIP(hipGetLastError());
+            }
+        }
         sort_norms(sig2, perm);
         double off, offk;
         std::memcpy(&off, &st4[0], sizeof(off));
         std::memcpy(&offk, &st4[4], sizeof(offk));
-        if (was_persistent) {
-            ++run->persistent_sweeps;
-            if (aborted) {
-                // some groups were not resident together (or the wait bound is tiny): the sweep
-                // visited only part of the pairs, so it decides nothing; the remaining sweeps
-                // launch round by round
-                ++run->aborted;
-                persistent = 0;
-                r_prev = -1;
-                if (trace) std::fprintf(stderr, "jacobi D=%d N=%d sweep %d: persistent sweep aborted\n", D, N, sweeps);
-                continue;
-            }
-        }
         if (off <= tol) converged = true;
         int r_now = -1;
         if (stop_tail2 > 0.0 && !converged) {

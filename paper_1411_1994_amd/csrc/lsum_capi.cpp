@@ -724,7 +724,8 @@ int lsum_set_option(lsum_ctx x, int key, double value) {
             c.graphs.store((int)value);
             return LSUM_OK;
         case LSUM_OPT_JACOBI_PERSISTENT:
-            if (!(value == 0 || value == 1)) return fail(LSUM_E_INVALID, "persistent option must be 0 or 1");
+            if (!(value == 0 || value == 1 || value == 2))
+                return fail(LSUM_E_INVALID, "persistent option must be 0, 1 or 2");
             c.persistent.store((int)value);
             return LSUM_OK;
         case LSUM_OPT_AUTOTUNE:

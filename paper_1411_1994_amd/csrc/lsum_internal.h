@@ -341,8 +341,8 @@ void launch_cp_norm2(hipStream_t st, int R, int n_groups, const int32_t* src1, c
 // Every way adds the same terms in the same order (the same results bit for bit).
 struct JacobiRun {
     int graphs = 0;
-    int persistent = 0;
-    double wait_us = 5e5;
+    int persistent = 0;            // 1: 16-wave pair groups, 2: 4-wave pair groups
+    double wait_us = 2e4;
     // workgroups of persistent sweeps running on the device (shared by every SVD of a context):
     // a sweep runs persistently only while the total stays within 3/4 of what the device holds
     // at once, else round by round (nullptr: no accounting)

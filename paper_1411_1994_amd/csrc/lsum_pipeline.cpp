@@ -16,8 +16,10 @@
 
 namespace lsum {
 
-// cells at which every Tucker result is compared with its untruncated canonical sum
+// cells at which every Tucker result is compared with its untruncated canonical sum, on this
+// many mode-3 planes
 constexpr int kProbeCells = 32;
+constexpr int kProbePlanes = 4;
 
 static GemmPrec gemm_prec(int precision) {
     return precision == LSUM_FP64 ? GEMM_F64 : (precision == LSUM_FP32 ? GEMM_F32 : GEMM_BF16X3);
@@ -758,20 +760,27 @@ static int run_tucker(Request* q, hipStream_t st, const hipStream_t* aux, StageT
     LSUM_HIP(hipStreamSynchronize(st));
 
     // (9) the result's own error: its values at kProbeCells seeded cells, evaluated like any
-    // sample (in the request's precision), against the untruncated canonical sum in FP64
+    // sample (in the request's precision), against the untruncated canonical sum in FP64.  The
+    // cells lie on kProbePlanes mode-3 planes (random along the other two axes), so that the
+    // evaluation forms only that many mode-3 products of the core.
     {
         const int np = kProbeCells;
         std::vector<int32_t> cells(3 * (size_t)np);
         std::vector<double> xyz(3 * (size_t)np);
         uint64_t state = 0x1411199400000000ull ^ ((uint64_t)P.N[0] << 40) ^ ((uint64_t)P.N[1] << 20) ^ (uint64_t)P.N[2];
+        auto next = [&state](int n) {
+            // SplitMix64 (Steele, Lea, Flood 2014) of a counter
+            uint64_t z = (state += 0x9E3779B97F4A7C15ull);
+            z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+            z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+            z ^= z >> 31;
+            return (int)(z % (uint64_t)n);
+        };
+        int planes[kProbePlanes];
+        for (int k = 0; k < kProbePlanes; ++k) planes[k] = next(P.N[2]);
         for (int p = 0; p < np; ++p)
             for (int l = 0; l < 3; ++l) {
-                // SplitMix64 (Steele, Lea, Flood 2014) of a counter
-                uint64_t z = (state += 0x9E3779B97F4A7C15ull);
-                z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-                z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-                z ^= z >> 31;
-                const int i = (int)(z % (uint64_t)P.N[l]);
+                const int i = l == 2 ? planes[p % kProbePlanes] : next(P.N[l]);
                 cells[3 * p + l] = i;
                 xyz[3 * p + l] = (i - (P.N[l] - 1) / 2) * P.h;
             }

@@ -146,7 +146,7 @@ struct Context {
     std::atomic<int> jacobi_max_sweeps{40};   // sweeps before a side-matrix SVD fails (LSUM_E_NOCONV)
     std::atomic<int> graphs{0};               // round-by-round Jacobi sweeps captured in HIP graphs
     std::atomic<int> persistent{0};           // Jacobi sweeps as one persistent launch each
-    std::atomic<long long> jacobi_wait_us{500000};   // bound on a persistent sweep's waits
+    std::atomic<long long> jacobi_wait_us{20000};    // bound on a persistent sweep's waits
     std::atomic<int> persistent_wgs{0};       // workgroups of persistent sweeps now on the device
     Tuner tuner;                              // launch variants per shape bucket
     std::vector<hipStream_t> streams;
