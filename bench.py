@@ -208,11 +208,12 @@ def _oracle_request(p):
     return time.perf_counter() - t0
 
 
-def mix_cpu_baseline(probs, gpu_plain_s, seconds):
+def mix_cpu_baseline(probs, seconds):
     """The oracle's same method on the host cores: one worker process per core (at most 16, one
-    BLAS thread each) takes the timed requests smallest first (by literal side-matrix size, those
-    under about 1.5 GB of side matrices and Grams) until `seconds` have passed; unfinished ones
-    are abandoned.  Beside it, the plain FP64 GPU path's rate on the same finished requests."""
+    BLAS thread each) takes requests smallest first (by literal side-matrix size, those under
+    about 1.5 GB of side matrices and Grams) until `seconds` have passed; unfinished ones are
+    abandoned.  `probs` are the timed requests followed by later ones of the same stream (so that
+    every worker has work); the indices of the finished ones are returned in "finished"."""
     import multiprocessing as mp
     try:
         import psutil
@@ -252,16 +253,14 @@ def mix_cpu_baseline(probs, gpu_plain_s, seconds):
         used = sum(getattr(c1, f) - getattr(c0, f) for f in ("user", "system", "children_user", "children_system"))
         cores = round(used / wall, 2)
     ks = sorted(done)
-    gpu_s = sum(gpu_plain_s[k] for k in ks)
     return {"value": len(ks) / wall, "unit": "lattice sums/s", "cores": cores, "kind": "oracle",
             "workers": workers, "host_cpus": ncpu,
-            "sample": f"{len(ks)} of the {len(probs)} timed served-mix requests finished in {wall:.1f} s by "
-                      f"{workers} worker processes (one BLAS thread each), smallest first (timed-set indices "
-                      f"{ks}); each: canonical terms, LAPACK SVD of the literal side matrices with the certified "
-                      f"truncation, core by canonical projection, values at 3 cells",
+            "sample": f"{len(ks)} of {len(probs)} served-mix requests (the timed ones and the next ones of the same "
+                      f"stream) finished in {wall:.1f} s by {workers} worker processes (one BLAS thread each), "
+                      f"smallest first; each: canonical terms, LAPACK SVD of the literal side matrices with the "
+                      f"certified truncation, core by canonical projection, values at 3 cells",
             "seconds_per_request": {str(k): round(done[k], 2) for k in ks},
-            "plain_fp64_gpu_on_same_requests": {"value": len(ks) / gpu_s if gpu_s > 0 else None,
-                                                "unit": "lattice sums/s"}}
+            "finished": ks}
 
 
 def run_shift_rect(n_req=1024):
@@ -476,8 +475,29 @@ def run_mix(args):
                    for k, v in prof.items()},
     }
     if not args.no_cpu:
-        out["cpu_baseline"] = mix_cpu_baseline([probs[k] for k in timed_idx], [plain_s[k] for k in timed_idx],
-                                               args.cpu_seconds)
+        extra = [p for _, p in W.served_mix_stream(warmup + steps + 200)[warmup + steps:]]
+        cprobs = [probs[k] for k in timed_idx] + extra
+        cb = mix_cpu_baseline(cprobs, args.cpu_seconds)
+        # the plain FP64 GPU path on exactly the requests the oracle finished
+        done = cb.pop("finished")
+        if done:
+            gctx = L.Context(0, n_slots=1)
+            gctx.set_option(L.OPT_MAX_BATCH, 1)
+            gctx.set_option(L.OPT_REF_CACHE_BYTES, 0)
+            gctx.set_option(L.OPT_AUTOTUNE, 0)
+            gs = 0.0
+            for k in done:
+                p = W.Problem(**{**cprobs[k].__dict__, "precision": W.FP64})
+                t0 = time.perf_counter()
+                r = gctx.submit(L.prepare(p))
+                if r.wait() != 0:
+                    raise RuntimeError("plain request for the CPU comparison failed")
+                gs += time.perf_counter() - t0
+                r.release()
+            gctx.close()
+            cb["plain_fp64_gpu_on_same_requests"] = {"value": len(done) / gs, "unit": "lattice sums/s",
+                                                     "requests": len(done)}
+        out["cpu_baseline"] = cb
     return out
 
 
