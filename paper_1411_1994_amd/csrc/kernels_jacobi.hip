@@ -91,14 +91,12 @@ __device__ __forceinline__ int inner_q(int t, int i) { return i == 0 ? t : (t - 
 // and the squared relative coupling b^2 / (a d) it removes (0 for a pair that is left alone).
 __device__ __forceinline__ void rotation(double a, double d, double b, double irr2, double* c, double* s,
                                          double* rel2) {
-    *c = 1.0;
-    *s = 0.0;
-    *rel2 = 0.0;
-    if (!coupled(a, d, b, irr2)) return;
+    // computed without branches (every lane of the wavefront takes the same path) and selected
+    // at the end: a pair left alone gets (1, 0)
+    const bool cpl = coupled(a, d, b, irr2);
     // the coupling only steers decisions: an approximate reciprocal suffices
     const double r2 = (b * b) * __builtin_amdgcn_rcp(a * d);
-    *rel2 = r2;
-    if (!(r2 > 1e-32)) return;
+    const bool go = cpl && r2 > 1e-32;
     // tan of the angle that annihilates b: t = 2b / (z + sign(z) sqrt(z^2 + 4 b^2)), z = d - a (the
     // smaller root, |t| <= 1).  t may be approximate (the rotation is then slightly short of
     // optimal but still orthogonal); c = (1 + t^2)^(-1/2) is refined to full precision so that
@@ -111,8 +109,9 @@ __device__ __forceinline__ void rotation(double a, double d, double b, double ir
     double y = __builtin_amdgcn_rsq(u);
     y = y * (1.5 - 0.5 * u * y * y);
     y = y * (1.5 - 0.5 * u * y * y);
-    *c = y;
-    *s = t * y;
+    *c = go ? y : 1.0;
+    *s = go ? t * y : 0.0;
+    *rel2 = cpl ? r2 : 0.0;
 }
 
 constexpr int EIG_LOADS = 16;   // chunk partials in flight per thread
@@ -164,12 +163,16 @@ __device__ __forceinline__ bool solve_pair(int lane, double (*G)[17], double (*Q
         for (int step = 0; step < 15; ++step) {
             const int pi = inner_p(step, bi), qi = inner_q(step, bi);
             const int pj = inner_p(step, bj), qj = inner_q(step, bj);
-            double ci, si, cj, sj, ri, rj;
-            rotation(G[pi][pi], G[qi][qi], G[pi][qi], irr2, &ci, &si, &ri);
-            rotation(G[pj][pj], G[qj][qj], G[pj][qj], irr2, &cj, &sj, &rj);
-            mx = fmax(mx, ri);
+            // every read of the step first (one LDS round trip), then the rotations
+            const double gpp_i = G[pi][pi], gqq_i = G[qi][qi], gpq_i = G[pi][qi];
+            const double gpp_j = G[pj][pj], gqq_j = G[qj][qj], gpq_j = G[pj][qj];
             // G block [pi qi] x [pj qj]
             const double g00 = G[pi][pj], g01 = G[pi][qj], g10 = G[qi][pj], g11 = G[qi][qj];
+            const double q00 = Q[pi][pj], q01 = Q[pi][qj], q10 = Q[qi][pj], q11 = Q[qi][qj];
+            double ci, si, cj, sj, ri, rj;
+            rotation(gpp_i, gqq_i, gpq_i, irr2, &ci, &si, &ri);
+            rotation(gpp_j, gqq_j, gpq_j, irr2, &cj, &sj, &rj);
+            mx = fmax(mx, ri);
             // rows: J^T
             const double h00 = ci * g00 - si * g10, h01 = ci * g01 - si * g11;
             const double h10 = si * g00 + ci * g10, h11 = si * g01 + ci * g11;
@@ -179,7 +182,6 @@ __device__ __forceinline__ bool solve_pair(int lane, double (*G)[17], double (*Q
             G[qi][pj] = cj * h10 - sj * h11;
             G[qi][qj] = sj * h10 + cj * h11;
             // Q rows {pi, qi} (any row partition), columns {pj, qj}
-            const double q00 = Q[pi][pj], q01 = Q[pi][qj], q10 = Q[qi][pj], q11 = Q[qi][qj];
             Q[pi][pj] = cj * q00 - sj * q01;
             Q[pi][qj] = sj * q00 + cj * q01;
             Q[qi][pj] = cj * q10 - sj * q11;
@@ -505,36 +507,50 @@ __global__ void __launch_bounds__(256) k_random_signs(long n, unsigned long long
 }
 
 // Rank-revealing Cholesky of a Gram matrix, in one workgroup (the orthonormalisation of a block
-// of sketch rows: Y_p = R^T Q_b with Q_b orthonormal, Q_b = R^{-T} Y_p).  Right-looking, in A: at
-// step j the largest remaining diagonal entry is moved to position j (with `pivot`), row j of R
-// is A's row divided by sqrt of the pivot, and the trailing block loses the outer product of that
-// row.  The matrix is held in LDS (n <= PC_MAXN) and positions are addressed through perm (no
-// rows are moved); the factorisation stops at the first pivot <= tau2 times the first.  Out: R^T
-// (pivot order) and the pivot order.
+// of sketch rows: Y_p = R^T Q_b with Q_b orthonormal, Q_b = R^{-T} Y_p).  Right-looking: at step
+// j the largest diagonal entry not yet pivoted (ties: the lowest index; without `pivot`, index j)
+// is the j-th pivot p, R's row j is A's row p divided by sqrt(A_pp) (0 at earlier pivots), and
+// A loses the outer product of that row.  A (n <= PC_MAXN) is held in registers, a 4 x 4 tile
+// per thread, and updated whole (rows and columns of earlier pivots then only change by rounding
+// and are never read again), so a step is two barriers and sixteen fused multiply-adds per
+// thread.  The factorisation stops at the first pivot <= tau2 times the first.  Out: R^T in
+// pivot order (Rt[jj][k] = R[k][pivot jj], k <= jj < keep), the pivot order (the unpivoted
+// indices follow in increasing order) and keep.
 constexpr int PC_THREADS = 1024;
-constexpr int PC_MAXN = 128;   // the matrix lives in LDS: 128 x 129 doubles
+constexpr int PC_MAXN = 128;   // 32 x 32 tiles of 4 x 4
 
 __global__ void __launch_bounds__(PC_THREADS) k_pchol(int n, const double* __restrict__ A, double tau2, int pivot,
                                                       double* __restrict__ Rt, int* __restrict__ perm_out,
                                                       int* __restrict__ keep_dev) {
-    __shared__ double As[PC_MAXN][PC_MAXN + 1];
-    __shared__ int perm[PC_MAXN];
-    __shared__ double wv[PC_THREADS / 64];
-    __shared__ int wi[PC_THREADS / 64];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    constexpr int NW = PC_THREADS / 64;
-    for (int i = tid; i < n; i += PC_THREADS) perm[i] = i;
-    for (int e = tid; e < n * n; e += PC_THREADS) As[e / n][e % n] = A[e];
+    __shared__ double Rr[PC_MAXN][PC_MAXN + 1];   // R's row j by original index
+    __shared__ double diag[PC_MAXN];
+    __shared__ double row[PC_MAXN];
+    __shared__ int piv[PC_MAXN];
+    __shared__ int done[PC_MAXN];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int i0 = (tid >> 5) * 4, k0 = (tid & 31) * 4;   // this thread's tile
+    const double ninf = -__builtin_huge_val();
+    double a[4][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+            a[u][v] = (i0 + u < n && k0 + v < n) ? A[(size_t)(i0 + u) * n + k0 + v] : 0.0;
+    if (tid < PC_MAXN) done[tid] = tid < n ? 0 : 1;
+    if (i0 == k0)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) diag[i0 + u] = a[u][u];
     __syncthreads();
     double d0 = 0.0;
     int keep = n;
     for (int j = 0; j < n; ++j) {
+        // the pivot, found by every wave alike from the same diagonal
+        int p = j;
         if (pivot) {
-            // the largest remaining diagonal entry (ties: the first position)
-            double bv = -__builtin_huge_val();
-            int bi = n;
-            for (int i = j + tid; i < n; i += PC_THREADS) {
-                const double v = As[perm[i]][perm[i]];
+            double bv = ninf;
+            int bi = PC_MAXN;
+            for (int i = lane; i < PC_MAXN; i += 64) {
+                const double v = done[i] ? ninf : diag[i];
                 if (v > bv) {
                     bv = v;
                     bi = i;
@@ -548,79 +564,106 @@ __global__ void __launch_bounds__(PC_THREADS) k_pchol(int n, const double* __res
                     bi = oi;
                 }
             }
-            if (lane == 0) {
-                wv[wave] = bv;
-                wi[wave] = bi;
-            }
-            __syncthreads();
-            if (tid == 0) {
-                double b = wv[0];
-                int ib = wi[0];
-                for (int w = 1; w < NW; ++w)
-                    if (wv[w] > b || (wv[w] == b && wi[w] < ib)) {
-                        b = wv[w];
-                        ib = wi[w];
-                    }
-                if (ib < n) {   // no candidate (NaN diagonal): no swap, and the step below stops
-                    const int t = perm[j];
-                    perm[j] = perm[ib];
-                    perm[ib] = t;
-                }
-            }
-            __syncthreads();
+            p = bi;
         }
-        const int pj = perm[j];
-        const double d = As[pj][pj];
+        const double d = p < n ? diag[p] : 0.0;   // no candidate left (NaN diagonal): stop
         if (j == 0) d0 = d;
         if (!(d > 0.0) || !(d > tau2 * d0)) {   // the same value on every thread: a uniform exit
             keep = j;
             break;
         }
         const double rjj = sqrt(d);
-        __syncthreads();   // every thread has read the pivot before row j is overwritten
-        double* aj = As[pj];
-        for (int k = j + 1 + tid; k < n; k += PC_THREADS) aj[perm[k]] /= rjj;
-        if (tid == 0) aj[pj] = rjj;
-        __syncthreads();
-        // the whole trailing block (both triangles: later pivots reorder the positions, so an
-        // entry's place relative to the diagonal is not fixed): one wave per row, lanes along it
-        for (int i = j + 1 + wave; i < n; i += NW) {
-            double* ai = As[perm[i]];
-            const double rji = aj[perm[i]];
-            for (int k = j + 1 + lane; k < n; k += 64) ai[perm[k]] -= rji * aj[perm[k]];
+        if (i0 == (p & ~3)) {   // the 32 threads holding row p
+            const int u = p & 3;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int k = k0 + v;
+                row[k] = k == p ? rjj : (done[k] ? 0.0 : a[u][v] / rjj);
+            }
         }
-        __syncthreads();
+        __syncthreads();   // row j of R is complete; every wave has read diag and done
+        if (tid == 0) {
+            done[p] = 1;
+            piv[j] = p;
+        }
+        if (tid < PC_MAXN) Rr[j][tid] = row[tid];
+        double ri[4], rk[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) ri[u] = row[i0 + u];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) rk[v] = row[k0 + v];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) a[u][v] -= ri[u] * rk[v];
+        if (i0 == k0)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) diag[i0 + u] = a[u][u];
+        __syncthreads();   // diag and done for the next step; row free again
     }
-    // R^T in pivot order (Rt[j][k] = R[k][j], k <= j < keep) and the pivot order itself
+    __syncthreads();
     for (int e = tid; e < keep * keep; e += PC_THREADS) {
         const int jj = e / keep, k = e % keep;
-        if (k <= jj) Rt[(size_t)jj * n + k] = As[perm[k]][perm[jj]];
+        if (k <= jj) Rt[(size_t)jj * n + k] = Rr[k][piv[jj]];
     }
-    for (int e = tid; e < n; e += PC_THREADS) perm_out[e] = perm[e];
-    if (tid == 0) *keep_dev = keep;
+    if (tid == 0) {
+        for (int j = 0; j < keep; ++j) perm_out[j] = piv[j];
+        int pos = keep;
+        for (int i = 0; i < n; ++i)
+            if (!done[i]) perm_out[pos++] = i;
+        *keep_dev = keep;
+    }
 }
 
 // Forward substitution R^T Q = Y_p for the kept rows (the rows of Y in pivot order): Q[i][c] =
-// (Y[perm[i]][c] - sum_{k<i} R[k][i] Q[k][c]) / R[i][i], each column c by its own lane, the
-// column's values so far in LDS (keep <= TS_MAXK), R^T's row i read by every lane alike.
+// (Y[perm[i]][c] - sum_{k<i} R[k][i] Q[k][c]) / R[i][i], each column c by its own lane of the
+// first wave.  The workgroup first loads R^T's lower triangle (packed by rows) and its 64
+// columns of Y_p into LDS.  Rows are then solved 16 at a time: all earlier rows are subtracted
+// from the 16 right-hand sides at once (16 independent sums, so the LDS reads overlap), then the
+// 16 x 16 triangle is solved in registers.
 constexpr int TS_MAXK = 128;
+constexpr int TS_COLS = 64;
+constexpr int TS_BLK = 16;
 
-__global__ void __launch_bounds__(64) k_trsm_rows(int keep, int ncol, int n, const double* __restrict__ Rt,
-                                                  const int* __restrict__ perm, const double* __restrict__ Y,
-                                                  long ldy, double* __restrict__ out, long ldo) {
-    __shared__ double q[TS_MAXK][64];
-    const int lane = threadIdx.x;
-    const int col = blockIdx.x * 64 + lane;
-    const bool in = col < ncol;
-    for (int i = 0; i < keep; ++i) {
-        const double* __restrict__ ri = Rt + (size_t)i * n;
-        double sacc = 0.0;
-        for (int k = 0; k < i; ++k) sacc += ri[k] * q[k][lane];
-        const double y = in ? Y[(size_t)perm[i] * ldy + col] : 0.0;
-        const double v = (y - sacc) / ri[i];
-        q[i][lane] = v;
-        if (in) out[(size_t)i * ldo + col] = v;
+__device__ __forceinline__ int tri(int i) { return i * (i + 1) / 2; }
+
+__global__ void __launch_bounds__(256) k_trsm_rows(int keep, int ncol, int n, const double* __restrict__ Rt,
+                                                   const int* __restrict__ perm, const double* __restrict__ Y,
+                                                   long ldy, double* __restrict__ out, long ldo) {
+    __shared__ double rl[TS_MAXK * (TS_MAXK + 1) / 2];
+    __shared__ double q[TS_MAXK][TS_COLS];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int col = blockIdx.x * TS_COLS + lane;
+    for (int i = 0; i < keep; ++i)
+        for (int k = tid; k <= i; k += 256) rl[tri(i) + k] = Rt[(size_t)i * n + k];
+    for (int i = wave; i < keep; i += 4) q[i][lane] = col < ncol ? Y[(size_t)perm[i] * ldy + col] : 0.0;
+    __syncthreads();
+    if (wave == 0) {
+        for (int b0 = 0; b0 < keep; b0 += TS_BLK) {
+            double x[TS_BLK];
+#pragma unroll
+            for (int r = 0; r < TS_BLK; ++r) x[r] = b0 + r < keep ? q[b0 + r][lane] : 0.0;
+            for (int k = 0; k < b0; ++k) {
+                const double qk = q[k][lane];
+#pragma unroll
+                for (int r = 0; r < TS_BLK; ++r)
+                    if (b0 + r < keep) x[r] -= rl[tri(b0 + r) + k] * qk;
+            }
+#pragma unroll
+            for (int r = 0; r < TS_BLK; ++r) {
+                if (b0 + r < keep) {
+                    const double* ri = rl + tri(b0 + r) + b0;
+#pragma unroll
+                    for (int rr = 0; rr < r; ++rr) x[r] -= ri[rr] * x[rr];
+                    x[r] /= ri[r];
+                    q[b0 + r][lane] = x[r];
+                }
+            }
+        }
     }
+    __syncthreads();
+    for (int i = wave; i < keep; i += 4)
+        if (col < ncol) out[(size_t)i * ldo + col] = q[i][lane];
 }
 
 inline unsigned cdiv(long a, long b) { return (unsigned)((a + b - 1) / b); }
@@ -665,7 +708,8 @@ void launch_pchol(hipStream_t st, int n, const double* A, double tau2, int pivot
 void launch_trsm_rows(hipStream_t st, int keep, int ncol, int n, const double* Rt, const int* perm, const double* Y,
                       long ldy, double* out, long ldo) {
     if (keep <= 0 || ncol <= 0) return;
-    hipLaunchKernelGGL(k_trsm_rows, dim3(cdiv(ncol, 64)), dim3(64), 0, st, keep, ncol, n, Rt, perm, Y, ldy, out, ldo);
+    hipLaunchKernelGGL(k_trsm_rows, dim3(cdiv(ncol, TS_COLS)), dim3(256), 0, st, keep, ncol, n, Rt, perm, Y, ldy, out,
+                       ldo);
 }
 
 void launch_random_signs(hipStream_t st, long n, unsigned long long seed, double* out) {

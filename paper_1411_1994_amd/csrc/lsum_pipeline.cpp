@@ -108,9 +108,10 @@ static int gram_rows(Context* c, hipStream_t st, int m, int n, const double* X, 
 // Orthonormal rows spanning the significant rows of Y (m x n, stride n; m <= 128): the
 // rank-revealing Cholesky of Y Y^T keeps pivots above tau2 times the first (rows above
 // sqrt(tau2) in norm), and out (keep x n) = R^{-T} Y_p by forward substitution.  Returns keep
-// (0: nothing above the threshold).
+// (0: nothing above the threshold).  Without `pivot` the rows are taken in their order (for
+// rows that are already orthonormal to a few digits, whose Gram is near the identity).
 static int chol_rows(Context* c, hipStream_t st, int m, int n, const double* Y, double tau2, double* small,
-                     double* out, int* keep) {
+                     double* out, int* keep, int pivot = 1) {
     if (m > 128) return fail(LSUM_E_INVALID, "chol_rows: more than 128 rows");
     double* G = small;
     double* Rt = small + (size_t)m * m;
@@ -118,7 +119,7 @@ static int chol_rows(Context* c, hipStream_t st, int m, int n, const double* Y, 
     int* kd = perm + m;
     int rc;
     if ((rc = gram_rows(c, st, m, n, Y, n, G))) return rc;
-    launch_pchol(st, m, G, tau2, 1, Rt, perm, kd);
+    launch_pchol(st, m, G, tau2, pivot, Rt, perm, kd);
     LSUM_HIP(hipGetLastError());
     LSUM_HIP(hipMemcpyAsync(keep, kd, sizeof(int), hipMemcpyDeviceToHost, st));
     LSUM_HIP(hipStreamSynchronize(st));
@@ -133,8 +134,11 @@ static int chol_rows(Context* c, hipStream_t st, int m, int n, const double* Y, 
 // are made orthonormal by the rank-revealing Cholesky of their Gram, once more orthogonalised
 // against the basis and orthonormalised by a second Cholesky pass (CholeskyQR2: orthonormal to
 // rounding); E then loses the block's directions.  The growth stops once ||E||_F <= thr / 10 or
-// the basis would exceed k_max rows.  B = Q W^T and E = W - B^T Q are then recomputed from W,
-// and Jacobi on the rows [B | Q] (Gram over B) gives the singular vectors.
+// the basis would exceed k_max rows.  B = Q W^T and E = W - B^T Q are then recomputed from W.
+// Jacobi on the rows [B | I] (Gram over B) finds the orthogonal V whose rows V B are orthogonal
+// (their norms the singular values), the identity block accumulating V; the singular vectors
+// are then the rows of V Q, one product at the end instead of rotating Q's N entries per row in
+// every round (rows of D + k entries instead of D + N).
 static int range_svd(Context* c, hipStream_t st, int D, int N, const double* W, int k_block, int k_max,
                      double thr, double irrelevant, ModeSVD& out, bool* enough) {
     int rc;
@@ -175,7 +179,8 @@ static int range_svd(Context* c, hipStream_t st, int D, int N, const double* W, 
         }
         double* Qb = Q + (size_t)kq * N;
         int keep2 = 0;
-        if ((rc = chol_rows(c, st, keep, N, Y2.as<double>(), 1e-12, small.as<double>(), Qb, &keep2))) return rc;
+        // the second pass factors a Gram within rounding of the identity: no pivots needed
+        if ((rc = chol_rows(c, st, keep, N, Y2.as<double>(), 1e-12, small.as<double>(), Qb, &keep2, 0))) return rc;
         if (keep2 == 0) return LSUM_OK;
         keep = keep2;
         out.flops += 2.0 * keep * (double)kb * N + 4.0 * keep * (double)kq * N + 4.0 * keep * (double)keep * N +
@@ -196,24 +201,24 @@ static int range_svd(Context* c, hipStream_t st, int D, int N, const double* W, 
     Y2.reset();
     P.reset();
     small.reset();
-    // AUG rows [B_a | Q_a]: B (kq x D) = Q W^T, and the exact residual E = W - B^T Q
-    const long ld = (long)D + N;
+    // AUG rows [B_a | I_a]: B (kq x D) = Q W^T; the exact residual E = W - B^T Q
+    const long ld = (long)D + kq;
     DevBuf AUG;
     if ((rc = AUG.get(c->pool, (size_t)kq * ld * 8))) return rc;
-    LSUM_HIP(hipMemcpy2DAsync(AUG.as<double>() + D, ld * 8, Q, (size_t)N * 8, (size_t)N * 8, kq,
-                              hipMemcpyDeviceToDevice, st));
+    LSUM_HIP(hipMemsetAsync(AUG.p, 0, (size_t)kq * ld * 8, st));
     gemm_rm(st, kq, D, N, Q, N, false, W, N, true, AUG.as<double>(), ld, 1.0, 0.0);
+    launch_unit_diag(st, kq, ld, D, AUG.as<double>());
     LSUM_HIP(hipMemcpyAsync(E.p, W, (size_t)D * N * 8, hipMemcpyDeviceToDevice, st));
-    gemm_rm(st, D, N, kq, AUG.as<double>(), ld, true, AUG.as<double>() + D, ld, false, E.as<double>(), N, -1.0, 1.0);
+    gemm_rm(st, D, N, kq, AUG.as<double>(), ld, true, Q, N, false, E.as<double>(), N, -1.0, 1.0);
     out.flops += 4.0 * kq * (double)D * N;
     if ((rc = frob2(c, st, D, N, E.as<double>(), &res2))) return rc;
     if (!(std::sqrt(res2) <= 0.1 * thr)) return LSUM_OK;   // basis too small
     E.reset();
-    Qall.reset();
     DevBuf work;
     const size_t wb2 = jacobi_work_bytes(kq, (int)ld);
     if ((rc = work.get(c->pool, wb2))) return rc;
-    // the rotated Q rows stay orthonormal in any sweep, so the rank stop needs no extra step here
+    // the accumulated rows of V stay orthonormal in any sweep, so the rank stop needs no extra
+    // step here
     JacobiRun jr = jacobi_run(c);
     rc = jacobi_svd(st, kq, (int)ld, AUG.as<double>(), (int)ld, 1e-12, irrelevant, c->jacobi_max_sweeps.load(),
                     out.sigma, &out.sweeps,
@@ -223,10 +228,17 @@ static int range_svd(Context* c, hipStream_t st, int D, int N, const double* W, 
     out.aborted += jr.aborted;
     out.tuned |= jr.tuned;
     if (rc) return rc;
+    work.reset();
+    // the singular vectors: rows of V Q (kq x N), in the sorted order of the rows
+    DevBuf Z;
+    if ((rc = Z.get(c->pool, (size_t)kq * N * 8))) return rc;
+    gemm_rm(st, kq, N, kq, AUG.as<double>() + D, ld, false, Q, N, false, Z.as<double>(), N, 1.0, 0.0);
+    out.flops += 2.0 * kq * (double)kq * N;
+    LSUM_HIP(hipGetLastError());
     out.res2 = res2;
-    out.rows = std::move(AUG);
-    out.ld = ld;
-    out.off = D;
+    out.rows = std::move(Z);
+    out.ld = N;
+    out.off = 0;
     out.unit = true;
     out.k = kq;
     *enough = true;
