@@ -130,7 +130,8 @@ __device__ __forceinline__ bool solve_pair(int lane, double (*G)[17], double (*Q
         if (a < b) {
             const double gaa = G[a][a], gbb = G[b][b];
             if (coupled(gaa, gbb, G[a][b], irr2)) {
-                const double cab = fabs(G[a][b]) / sqrt(gaa * gbb);
+                // decisions only: the approximate reciprocal square root suffices
+                const double cab = fabs(G[a][b]) * __builtin_amdgcn_rsq(gaa * gbb);
                 off = fmax(off, cab);
                 if (gaa > keep2 && gbb > keep2) offk = fmax(offk, cab);
             }
@@ -509,7 +510,7 @@ __global__ void __launch_bounds__(256) k_random_signs(long n, unsigned long long
 // Rank-revealing Cholesky of a Gram matrix, in one workgroup (the orthonormalisation of a block
 // of sketch rows: Y_p = R^T Q_b with Q_b orthonormal, Q_b = R^{-T} Y_p).  Right-looking: at step
 // j the largest diagonal entry not yet pivoted (ties: the lowest index; without `pivot`, index j)
-// is the j-th pivot p, R's row j is A's row p divided by sqrt(A_pp) (0 at earlier pivots), and
+// is the j-th pivot p, R's row j is A's row p times 1 / sqrt(A_pp) (0 at earlier pivots), and
 // A loses the outer product of that row.  A (n <= PC_MAXN) is held in registers, a 4 x 4 tile
 // per thread, and updated whole (rows and columns of earlier pivots then only change by rounding
 // and are never read again), so a step is two barriers and sixteen fused multiply-adds per
@@ -529,7 +530,6 @@ __global__ void __launch_bounds__(PC_THREADS) k_pchol(int n, const double* __res
     __shared__ int done[PC_MAXN];
     const int tid = threadIdx.x, lane = tid & 63;
     const int i0 = (tid >> 5) * 4, k0 = (tid & 31) * 4;   // this thread's tile
-    const double ninf = -__builtin_huge_val();
     double a[4][4];
 #pragma unroll
     for (int u = 0; u < 4; ++u)
@@ -544,29 +544,28 @@ __global__ void __launch_bounds__(PC_THREADS) k_pchol(int n, const double* __res
     double d0 = 0.0;
     int keep = n;
     for (int j = 0; j < n; ++j) {
-        // the pivot, found by every wave alike from the same diagonal
+        // the pivot, found by every wave alike from the same diagonal: the largest of the keys
+        // (positive entry's bits with the low 7 bits replaced by 127 - index; 0 for entries
+        // already pivoted or not positive), so values equal to within 2^-45 relative tie and
+        // the lowest index wins
         int p = j;
         if (pivot) {
-            double bv = ninf;
-            int bi = PC_MAXN;
+            unsigned long long key = 0;
             for (int i = lane; i < PC_MAXN; i += 64) {
-                const double v = done[i] ? ninf : diag[i];
-                if (v > bv) {
-                    bv = v;
-                    bi = i;
-                }
+                const double v = diag[i];
+                unsigned long long bits;
+                __builtin_memcpy(&bits, &v, sizeof(bits));
+                const unsigned long long ki =
+                    (!done[i] && v > 0.0) ? ((bits & ~0x7Full) | (unsigned long long)(PC_MAXN - 1 - i)) : 0ull;
+                key = ki > key ? ki : key;
             }
             for (int off = 32; off > 0; off >>= 1) {
-                const double ov = __shfl_xor(bv, off);
-                const int oi = __shfl_xor(bi, off);
-                if (ov > bv || (ov == bv && oi < bi)) {
-                    bv = ov;
-                    bi = oi;
-                }
+                const unsigned long long o = __shfl_xor(key, off);
+                key = o > key ? o : key;
             }
-            p = bi;
+            p = key ? PC_MAXN - 1 - (int)(key & 0x7F) : PC_MAXN;
         }
-        const double d = p < n ? diag[p] : 0.0;   // no candidate left (NaN diagonal): stop
+        const double d = p < n ? diag[p] : 0.0;   // no candidate left: stop
         if (j == 0) d0 = d;
         if (!(d > 0.0) || !(d > tau2 * d0)) {   // the same value on every thread: a uniform exit
             keep = j;
@@ -575,10 +574,11 @@ __global__ void __launch_bounds__(PC_THREADS) k_pchol(int n, const double* __res
         const double rjj = sqrt(d);
         if (i0 == (p & ~3)) {   // the 32 threads holding row p
             const int u = p & 3;
+            const double inv = 1.0 / rjj;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int k = k0 + v;
-                row[k] = k == p ? rjj : (done[k] ? 0.0 : a[u][v] / rjj);
+                row[k] = k == p ? rjj : (done[k] ? 0.0 : a[u][v] * inv);
             }
         }
         __syncthreads();   // row j of R is complete; every wave has read diag and done
@@ -634,31 +634,50 @@ __global__ void __launch_bounds__(256) k_trsm_rows(int keep, int ncol, int n, co
     __shared__ double q[TS_MAXK][TS_COLS];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int col = blockIdx.x * TS_COLS + lane;
-    for (int i = 0; i < keep; ++i)
-        for (int k = tid; k <= i; k += 256) rl[tri(i) + k] = Rt[(size_t)i * n + k];
+    // R^T's lower triangle: eight loads in flight per thread (indices past the end repeat the
+    // last entry and are not stored)
+    const int kk = keep * keep;
+    for (int e0 = tid; e0 < kk; e0 += 256 * 8) {
+        double v[8];
+        int dst[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = min(e0 + 256 * u, kk - 1);
+            const int i = e / keep, k = e - i * keep;
+            v[u] = Rt[(size_t)i * n + k];
+            dst[u] = (e0 + 256 * u < kk && k <= i) ? tri(i) + k : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (dst[u] >= 0) rl[dst[u]] = v[u];
+    }
     for (int i = wave; i < keep; i += 4) q[i][lane] = col < ncol ? Y[(size_t)perm[i] * ldy + col] : 0.0;
     __syncthreads();
     if (wave == 0) {
         for (int b0 = 0; b0 < keep; b0 += TS_BLK) {
+            // a block's rows past keep (indices below TS_MAXK, inside both LDS arrays) are
+            // computed from unset entries and discarded: no branch separates the 16 sums
             double x[TS_BLK];
+            const double* rrow[TS_BLK];
 #pragma unroll
-            for (int r = 0; r < TS_BLK; ++r) x[r] = b0 + r < keep ? q[b0 + r][lane] : 0.0;
+            for (int r = 0; r < TS_BLK; ++r) {
+                x[r] = q[b0 + r][lane];
+                rrow[r] = rl + tri(b0 + r);
+            }
             for (int k = 0; k < b0; ++k) {
                 const double qk = q[k][lane];
 #pragma unroll
-                for (int r = 0; r < TS_BLK; ++r)
-                    if (b0 + r < keep) x[r] -= rl[tri(b0 + r) + k] * qk;
+                for (int r = 0; r < TS_BLK; ++r) x[r] -= rrow[r][k] * qk;
             }
 #pragma unroll
             for (int r = 0; r < TS_BLK; ++r) {
-                if (b0 + r < keep) {
-                    const double* ri = rl + tri(b0 + r) + b0;
 #pragma unroll
-                    for (int rr = 0; rr < r; ++rr) x[r] -= ri[rr] * x[rr];
-                    x[r] /= ri[r];
-                    q[b0 + r][lane] = x[r];
-                }
+                for (int rr = 0; rr < r; ++rr) x[r] -= rrow[r][b0 + rr] * x[rr];
+                x[r] /= rrow[r][b0 + r];
             }
+#pragma unroll
+            for (int r = 0; r < TS_BLK; ++r)
+                if (b0 + r < keep) q[b0 + r][lane] = x[r];
         }
     }
     __syncthreads();
@@ -707,7 +726,7 @@ void launch_pchol(hipStream_t st, int n, const double* A, double tau2, int pivot
 
 void launch_trsm_rows(hipStream_t st, int keep, int ncol, int n, const double* Rt, const int* perm, const double* Y,
                       long ldy, double* out, long ldo) {
-    if (keep <= 0 || ncol <= 0) return;
+    if (keep <= 0 || ncol <= 0 || keep > TS_MAXK) return;   // callers pass at most TS_MAXK rows
     hipLaunchKernelGGL(k_trsm_rows, dim3(cdiv(ncol, TS_COLS)), dim3(256), 0, st, keep, ncol, n, Rt, perm, Y, ldy, out,
                        ldo);
 }

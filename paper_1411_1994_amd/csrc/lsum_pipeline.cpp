@@ -32,9 +32,9 @@ static GemmPrec gemm_prec(int precision) {
 //  * range basis, for min(D, N) >= range_min: an orthonormal basis Q of k <= min(D, N) / 2 rows
 //    grown in blocks of random-sign sketches of the residual, B = Q W^T, and the residual
 //    E = W - B^T Q computed explicitly (res2 = ||E||_F^2, which must stay below (thr/10)^2, else
-//    the direct solve runs); then Jacobi on the k rows [B | Q] with the Gram taken over B only, so
-//    the rotated Q part holds orthonormal vectors and ||A - Z_r Z_r^T A||^2 = res2 +
-//    sum_{a >= r} sigma_a^2 exactly.
+//    the direct solve runs); then Jacobi on the k rows [B | I] with the Gram taken over B only
+//    (the identity part accumulates the rotation V), and the vectors V Q are orthonormal, so
+//    ||A - Z_r Z_r^T A||^2 = res2 + sum_{a >= r} sigma_a^2 exactly.
 // A GEMM launch that splits a long FP64 reduction over many workgroups when the output has few
 // tiles (Grams of a few tens of columns over N_l cells, projections onto a few tens of vectors):
 // one tile would otherwise walk all N_l terms alone.  Synchronous when split (the workspace goes
@@ -235,6 +235,8 @@ static int range_svd(Context* c, hipStream_t st, int D, int N, const double* W, 
     gemm_rm(st, kq, N, kq, AUG.as<double>() + D, ld, false, Q, N, false, Z.as<double>(), N, 1.0, 0.0);
     out.flops += 2.0 * kq * (double)kq * N;
     LSUM_HIP(hipGetLastError());
+    // AUG and Q return to the pool (which hands memory on at once) when this returns
+    LSUM_HIP(hipStreamSynchronize(st));
     out.res2 = res2;
     out.rows = std::move(Z);
     out.ld = N;
