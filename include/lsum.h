@@ -393,7 +393,10 @@ int lsum_tucker_to_canonical(lsum_req req, double eps, int cap, int* R, double* 
                              double* U1, double* U2, double* err, int on_device);
 /* Tucker factors Z_l (r_l rows of N[l]) and core (r1*r2*r3, last index fastest), FP64. */
 int lsum_get_tucker(lsum_req req, double* Z0, double* Z1, double* Z2, double* core, int on_device);
-/* Singular values of the three side matrices (D[l] each, descending). */
+/* Singular values of the three side matrices, descending: min(D[l], N[l]) values (or the size of
+ * the range basis, when one is used) are written into buffers of D[l] entries; the entries
+ * after them are left as they are (the side matrix has no further nonzero values above the
+ * basis residual, which the certified bound carries). */
 int lsum_get_sigma(lsum_req req, double* s0, double* s1, double* s2);
 /* Potential at n points xyz[3n]: the canonical sum with all defects, or the Tucker tensor.
  * Synchronous. */

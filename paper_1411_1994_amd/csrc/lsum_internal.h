@@ -226,6 +226,8 @@ void launch_sample_cp(hipStream_t st, int n_fac, int R, const double* U, int ldu
 // R x N (stride ldu) -> N x R
 void launch_transpose(hipStream_t st, int R, int N, const double* U, int ldu, double* UT);
 void launch_transpose(hipStream_t st, int R, int N, const float* U, int ldu, double* UT);
+// UT[i * ldt + q] = U[q * ldu + i] for q < R, i < N
+void launch_transpose_ld(hipStream_t st, int R, int N, const double* U, int ldu, double* UT, long ldt);
 // One block of a canonical request in a batched sampling launch: its factor base (axis 0 rows;
 // axes 1 and 2 at the job's offsets) and its charge.
 struct SampleBlock {

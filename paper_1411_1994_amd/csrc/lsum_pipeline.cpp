@@ -28,7 +28,9 @@ static GemmPrec gemm_prec(int precision) {
 // Truncated SVD of one weighted side matrix W (D rows of length N; Def. def:RHOSVD).  The
 // result is a list of singular values and rows holding the matching left singular vectors,
 // such that for every r, ||A - Z_r Z_r^T A||_F^2 <= res2 + sum_{a >= r} sigma_a^2.
-//  * direct: one-sided Jacobi on W itself (res2 = 0; rows = rotated W, sigma-scaled);
+//  * direct: one-sided Jacobi on W itself (res2 = 0; rows = rotated W, sigma-scaled) when
+//    D <= N, else on the N rows of [W^T | I] (the identity block accumulates the rotation and
+//    holds the unit vectors);
 //  * range basis, for min(D, N) >= range_min: an orthonormal basis Q of k <= min(D, N) / 2 rows
 //    grown in blocks of random-sign sketches of the residual, B = Q W^T, and the residual
 //    E = W - B^T Q computed explicitly (res2 = ||E||_F^2, which must stay below (thr/10)^2, else
@@ -261,6 +263,40 @@ static int mode_svd(Context* c, hipStream_t st, int D, int N, DevBuf& W, double 
         bool enough = false;
         if ((rc = range_svd(c, st, D, N, W.as<double>(), k_block, k_max, thr, irrelevant, out, &enough))) return rc;
         if (enough) return LSUM_OK;
+    }
+    if (N < D) {
+        // more columns than cells: Jacobi on the N rows of [W^T | I] with the Gram over W^T's D
+        // entries.  The identity block accumulates the orthogonal V; for any V the rows W v_a of
+        // the W^T part satisfy ||W - W Z_r^T Z_r||^2 = sum_{a >= r} ||W v_a||^2 with Z_r the first
+        // r rows of V^T, so the certificate is that of the direct solve, and the unit rows of the
+        // identity block are the vectors.  N rows instead of D: no D - N null-space rows to drain.
+        const long ld = (long)D + N;
+        DevBuf AUG;
+        if ((rc = AUG.get(c->pool, (size_t)N * ld * 8))) return rc;
+        LSUM_HIP(hipMemsetAsync(AUG.p, 0, (size_t)N * ld * 8, st));
+        launch_transpose_ld(st, D, N, W.as<double>(), N, AUG.as<double>(), ld);
+        launch_unit_diag(st, N, ld, D, AUG.as<double>());
+        LSUM_HIP(hipGetLastError());
+        DevBuf work;
+        const size_t wb = jacobi_work_bytes(N, (int)ld);
+        if ((rc = work.get(c->pool, wb))) return rc;
+        // no irrelevance floor here: a row is a cell, and a cell of small norm still carries small
+        // components of the leading vectors, which a row left unrotated would drop
+        JacobiRun jr = jacobi_run(c);
+        rc = jacobi_svd(st, N, (int)ld, AUG.as<double>(), (int)ld, 1e-12, 0.0, c->jacobi_max_sweeps.load(),
+                        out.sigma, &out.sweeps, work.as<double>(), wb, D, c->jacobi_rank_stop ? thr * thr : 0.0, &jr);
+        out.flops += jr.flops;
+        out.persistent += jr.persistent_sweeps;
+        out.aborted += jr.aborted;
+        out.tuned |= jr.tuned;
+        if (rc) return rc;
+        out.res2 = 0.0;
+        out.rows = std::move(AUG);
+        out.ld = ld;
+        out.off = D;
+        out.unit = true;
+        out.k = 0;
+        return LSUM_OK;
     }
     DevBuf work;
     const size_t wb = jacobi_work_bytes(D, N);
