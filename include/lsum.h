@@ -212,10 +212,11 @@ const char* lsum_last_error(void);
  * fuses into one batch whose shift-sums run as one launch (1: no batching).
  * LSUM_OPT_REF_CACHE_BYTES (default 4 GiB): HBM kept for reference vectors shared by requests
  * with the same kernel, quadrature and grid (0: every request recomputes its own).
- * LSUM_OPT_RANGE_MIN (default 512): side matrices with min(D, N) at least this large are
- * compressed to a randomized range basis, grown in blocks of 128 vectors up to min(D, N) / 2,
- * before the Jacobi SVD (the residual outside the basis
- * is computed exactly and enters the certified tail); 0 disables the compression.
+ * LSUM_OPT_RANGE_MIN (default 64): side matrices with min(D, N) at least this large are
+ * compressed to a randomized range basis, grown in blocks of 128 vectors up to min(D, N),
+ * before the Jacobi SVD (the residual outside the basis is computed exactly and enters the
+ * certified tail; the directions below a tenth of the threshold then never reach the Jacobi
+ * sweeps); 0 disables the compression.
  * LSUM_OPT_JACOBI_STOP (default 1): the Jacobi SVD of a side matrix (Def. def:RHOSVD) ends as
  * soon as the certified truncation rank is the same after two sweeps and the rows kept for it
  * are orthogonal; the reported sigma beyond that rank are then row norms whose squared sum

@@ -31,7 +31,7 @@ static GemmPrec gemm_prec(int precision) {
 //  * direct: one-sided Jacobi on W itself (res2 = 0; rows = rotated W, sigma-scaled) when
 //    D <= N, else on the N rows of [W^T | I] (the identity block accumulates the rotation and
 //    holds the unit vectors);
-//  * range basis, for min(D, N) >= range_min: an orthonormal basis Q of k <= min(D, N) / 2 rows
+//  * range basis, for min(D, N) >= range_min: an orthonormal basis Q of k <= min(D, N) rows
 //    grown in blocks of random-sign sketches of the residual, B = Q W^T, and the residual
 //    E = W - B^T Q computed explicitly (res2 = ||E||_F^2, which must stay below (thr/10)^2, else
 //    the direct solve runs); then Jacobi on the k rows [B | I] with the Gram taken over B only
@@ -256,9 +256,9 @@ static int mode_svd(Context* c, hipStream_t st, int D, int N, DevBuf& W, double 
     const int range_min = allow_range ? c->range_min : 0;
     if (range_min > 0 && mn >= range_min) {
         // a basis grown in blocks of 128 vectors (the Gram of a block is factored in LDS) up to
-        // min(D, N) / 2: it wins when the certified rank is below about half of min(D, N); past
-        // that the direct solve follows
-        const int k_max = mn / 2;
+        // min(D, N): the residual E takes the directions below thr / 10, which the direct solve
+        // would otherwise drain row by row over many sweeps
+        const int k_max = mn;
         const int k_block = std::min(128, k_max);
         bool enough = false;
         if ((rc = range_svd(c, st, D, N, W.as<double>(), k_block, k_max, thr, irrelevant, out, &enough))) return rc;

@@ -141,7 +141,7 @@ struct Context {
     size_t used = 0;                 // bytes reserved by admitted requests and retained results
     int n_slots = 0;
     int max_batch = 32;              // canonical requests fused into one batch
-    int range_min = 512;             // min(D, N) from which side matrices use the range basis
+    int range_min = 64;              // min(D, N) from which side matrices use the range basis
     bool jacobi_rank_stop = true;    // Jacobi SVDs of side matrices end once the certified rank is settled
     std::atomic<int> jacobi_max_sweeps{40};   // sweeps before a side-matrix SVD fails (LSUM_E_NOCONV)
     std::atomic<int> graphs{0};               // round-by-round Jacobi sweeps captured in HIP graphs
