@@ -464,14 +464,16 @@ __global__ void __launch_bounds__(256) k_gather_terms(int K, int r, const T* __r
 // a time (the scale folded into the mode-1 row) and summed in FP64 in term order.
 constexpr int CG_T = 32;
 template <typename T>
-__global__ void __launch_bounds__(256) k_core_groups(int r1, int r2, int j0, const int32_t* __restrict__ off,
+__global__ void __launch_bounds__(256) k_core_groups(int r1, int r2, int a_begin, int a_count, int j0,
+                                                     const int32_t* __restrict__ off,
                                                      const int32_t* __restrict__ i1, const int32_t* __restrict__ i2,
                                                      const double* __restrict__ sc, const T* __restrict__ Y1,
                                                      long ldy1, const T* __restrict__ Y2, long ldy2,
                                                      T* __restrict__ out) {
     __shared__ double s1[CG_T][64];
     __shared__ double s2[CG_T][64];
-    const int a0 = blockIdx.y * 64, b0 = blockIdx.x * 64, jl = blockIdx.z, j = j0 + jl;
+    const int a_end = min(r1, a_begin + a_count);
+    const int a0 = a_begin + blockIdx.y * 64, b0 = blockIdx.x * 64, jl = blockIdx.z, j = j0 + jl;
     const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
     const int t0 = off[j], t1 = off[j + 1];
     double acc[4][4];
@@ -486,7 +488,7 @@ __global__ void __launch_bounds__(256) k_core_groups(int r1, int r2, int j0, con
             double v1 = 0.0, v2 = 0.0;
             if (t < nt) {
                 const int a = a0 + c, b = b0 + c;
-                if (a < r1) v1 = sc[tb + t] * (double)Y1[(long)i1[tb + t] * ldy1 + a];
+                if (a < a_end) v1 = sc[tb + t] * (double)Y1[(long)i1[tb + t] * ldy1 + a];
                 if (b < r2) v2 = (double)Y2[(long)i2[tb + t] * ldy2 + b];
             }
             s1[t][c] = v1;
@@ -507,15 +509,15 @@ __global__ void __launch_bounds__(256) k_core_groups(int r1, int r2, int j0, con
         }
         __syncthreads();
     }
-    T* o = out + (long)jl * r1 * r2;
+    T* o = out + (long)jl * a_count * r2;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int a = a0 + ty * 4 + i;
-        if (a >= r1) continue;
+        if (a >= a_end) continue;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const int b = b0 + tx * 4 + k;
-            if (b < r2) o[(long)a * r2 + b] = (T)acc[i][k];
+            if (b < r2) o[(long)(a - a_begin) * r2 + b] = (T)acc[i][k];
         }
     }
 }
@@ -741,17 +743,17 @@ void launch_gather_terms(hipStream_t st, int elem, int K, int r, const void* Yt,
                            ldy, idx, sc, (float*)X, ldx);
 }
 
-void launch_core_groups(hipStream_t st, int elem, int r1, int r2, int j0, int nj, const int32_t* off,
-                        const int32_t* i1, const int32_t* i2, const double* sc, const void* Y1, long ldy1,
-                        const void* Y2, long ldy2, void* out) {
-    if (nj <= 0 || r1 <= 0 || r2 <= 0) return;
-    const dim3 grid(cdiv(r2, 64), cdiv(r1, 64), nj);
+void launch_core_groups(hipStream_t st, int elem, int r1, int r2, int a_begin, int a_count, int j0, int nj,
+                        const int32_t* off, const int32_t* i1, const int32_t* i2, const double* sc, const void* Y1,
+                        long ldy1, const void* Y2, long ldy2, void* out) {
+    if (nj <= 0 || r1 <= 0 || r2 <= 0 || a_count <= 0 || a_begin < 0 || a_begin >= r1) return;
+    const dim3 grid(cdiv(r2, 64), cdiv(std::min(a_count, r1 - a_begin), 64), nj);
     if (elem == 8)
-        hipLaunchKernelGGL(k_core_groups<double>, grid, dim3(256), 0, st, r1, r2, j0, off, i1, i2, sc,
-                           (const double*)Y1, ldy1, (const double*)Y2, ldy2, (double*)out);
+        hipLaunchKernelGGL(k_core_groups<double>, grid, dim3(256), 0, st, r1, r2, a_begin, a_count, j0, off, i1, i2,
+                           sc, (const double*)Y1, ldy1, (const double*)Y2, ldy2, (double*)out);
     else
-        hipLaunchKernelGGL(k_core_groups<float>, grid, dim3(256), 0, st, r1, r2, j0, off, i1, i2, sc,
-                           (const float*)Y1, ldy1, (const float*)Y2, ldy2, (float*)out);
+        hipLaunchKernelGGL(k_core_groups<float>, grid, dim3(256), 0, st, r1, r2, a_begin, a_count, j0, off, i1, i2,
+                           sc, (const float*)Y1, ldy1, (const float*)Y2, ldy2, (float*)out);
 }
 
 // The canonical sum at probe cells, in FP64 (the discrete tensor before truncation):

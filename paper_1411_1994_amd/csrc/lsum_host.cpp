@@ -226,8 +226,8 @@ size_t Plan::planned_bytes() const {
             b += (size_t)D[l] * D[l] * 8;                      // column Gram
         }
         b += rmax[0] * rmax[1] * rmax[2] * 8;                  // core
-        if (2 * (size_t)D[2] <= (size_t)n_groups * R)          // grouped core terms (<= 2 GiB chunks)
-            b += std::min<size_t>(rmax[0] * rmax[1] * D[2] * 8, std::max<size_t>(2ull << 30, rmax[0] * rmax[1] * 8));
+        if (2 * (size_t)D[2] <= (size_t)n_groups * R)          // grouped core terms (<= 2 GiB chunks of rows)
+            b += std::min<size_t>(rmax[0] * rmax[1] * D[2] * 8, std::max<size_t>(2ull << 30, rmax[1] * (size_t)D[2] * 8));
         if (has_tile()) {
             size_t T0 = tile_T[0], T1 = tile_T[1], T2 = tile_T[2];
             size_t e = precision == LSUM_FP64 ? 8 : 4;

@@ -311,11 +311,12 @@ struct CoreArgs {
 void launch_gather_terms(hipStream_t st, int elem, int K, int r, const void* Yt, long ldy,
                          const int32_t* idx, const double* sc, void* X, long ldx);
 void launch_core(hipStream_t st, GemmPrec prec, const CoreArgs& a, int k_split, void* work);
-// T[jl][a][b] = sum_{t in [off[j], off[j+1])} sc[t] Y1[i1[t], a] Y2[i2[t], b] for j = j0 + jl,
-// jl < nj (a < r1, b < r2; FP64 sums, stored as elem 4 or 8 bytes like Y1, Y2).
-void launch_core_groups(hipStream_t st, int elem, int r1, int r2, int j0, int nj, const int32_t* off,
-                        const int32_t* i1, const int32_t* i2, const double* sc, const void* Y1, long ldy1,
-                        const void* Y2, long ldy2, void* out);
+// T[jl][a - a_begin][b] = sum_{t in [off[j], off[j+1])} sc[t] Y1[i1[t], a] Y2[i2[t], b] for
+// j = j0 + jl, jl < nj, a_begin <= a < min(r1, a_begin + a_count), b < r2 (FP64 sums, stored as
+// elem 4 or 8 bytes like Y1, Y2; column jl of the chunk is a_count * r2 entries).
+void launch_core_groups(hipStream_t st, int elem, int r1, int r2, int a_begin, int a_count, int j0, int nj,
+                        const int32_t* off, const int32_t* i1, const int32_t* i2, const double* sc, const void* Y1,
+                        long ldy1, const void* Y2, long ldy2, void* out);
 // ||A||^2 from the three unnormalised column Grams (D x D) and the group table.
 // The canonical sum (groups of R terms: sources src_l[g] in the unnormalised columns C_l, D_l x N_l,
 // weights scale[g]) at n_cells cells (cells[3p + l]), in FP64: out[p].

@@ -744,22 +744,28 @@ static int run_tucker(Request* q, hipStream_t st, const hipStream_t* aux, StageT
         const int r1 = q->r[0], r2 = q->r[1], r3 = q->r[2];
         const long plane = (long)r1 * r2 * r3;
         if ((rc = q->core.get(c->pool, (size_t)plane * es))) return rc;
-        // T in chunks of columns of at most 2 GiB; the chunks' GEMMs accumulate into the core
-        const long per_col = (long)r1 * r2 * (long)es;
-        const int chunk = (int)std::max<long>(1, std::min<long>({(long)D3, (2L << 30) / per_col, 65535L}));
+        // T in chunks of rows a (at most 2 GiB each, every column j up to the launch limit): each
+        // chunk's GEMM runs over all D3 columns and writes its rows of the core once (chunks of
+        // columns instead re-read and re-wrote the whole core for every chunk)
+        const long per_a = (long)r2 * D3 * (long)es;
+        const int a_chunk = (int)std::max<long>(1, std::min<long>((long)r1, (2L << 30) / per_a));
+        const int j_chunk = std::min(D3, 65535);
         DevBuf Tb;
-        if ((rc = Tb.get(c->pool, (size_t)per_col * chunk))) return rc;
-        for (int j0 = 0; j0 < D3; j0 += chunk) {
-            const int nj = std::min(chunk, D3 - j0);
-            launch_core_groups(st, (int)es, r1, r2, j0, nj, off_d.as<int32_t>(), i1_d.as<int32_t>(),
-                               i2_d.as<int32_t>(), sc_d.as<double>(), Y[0].p, ldy[0], Y[1].p, ldy[1], Tb.p);
-            GemmArgs a{};
-            a.m = r1 * r2; a.n = r3; a.k = nj;
-            a.A = Tb.p; a.sam = 1; a.sak = (long)r1 * r2;
-            a.B = (const char*)Y[2].p + (size_t)j0 * ldy[2] * es; a.sbk = ldy[2]; a.sbn = 1;
-            a.C = q->core.p; a.scm = r3; a.scn = 1;
-            a.alpha = 1.0; a.beta = j0 == 0 ? 0.0 : 1.0; a.batch = 1;
-            launch_gemm(st, prec, a);
+        if ((rc = Tb.get(c->pool, (size_t)a_chunk * r2 * (size_t)j_chunk * es))) return rc;
+        for (int a0 = 0; a0 < r1; a0 += a_chunk) {
+            const int na = std::min(a_chunk, r1 - a0);
+            for (int j0 = 0; j0 < D3; j0 += j_chunk) {
+                const int nj = std::min(j_chunk, D3 - j0);
+                launch_core_groups(st, (int)es, r1, r2, a0, na, j0, nj, off_d.as<int32_t>(), i1_d.as<int32_t>(),
+                                   i2_d.as<int32_t>(), sc_d.as<double>(), Y[0].p, ldy[0], Y[1].p, ldy[1], Tb.p);
+                GemmArgs a{};
+                a.m = na * r2; a.n = r3; a.k = nj;
+                a.A = Tb.p; a.sam = 1; a.sak = (long)na * r2;
+                a.B = (const char*)Y[2].p + (size_t)j0 * ldy[2] * es; a.sbk = ldy[2]; a.sbn = 1;
+                a.C = (char*)q->core.p + (size_t)a0 * r2 * r3 * es; a.scm = r3; a.scn = 1;
+                a.alpha = 1.0; a.beta = j0 == 0 ? 0.0 : 1.0; a.batch = 1;
+                launch_gemm(st, prec, a);
+            }
         }
         LSUM_HIP(hipGetLastError());
         LSUM_HIP(hipStreamSynchronize(st));
