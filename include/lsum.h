@@ -252,6 +252,12 @@ const char* lsum_last_error(void);
  * choice never changes a result.  With it, the sweep ways chosen override the two options
  * above.  0: the options and fixed thresholds decide. */
 #define LSUM_OPT_AUTOTUNE 9
+/* LSUM_OPT_GEMM_LIBRARY (default 1; applies to the whole process, not only this context): plain
+ * FP64 products with unit-stride operands and at least 2^24 multiply-adds (the range basis,
+ * the singular vectors, FP64 projections and core GEMMs, lsum_contract) run on the ROCm BLAS
+ * library's DGEMM with atomics disabled (results independent of concurrent work); 0: every
+ * product on this library's own MFMA kernels. */
+#define LSUM_OPT_GEMM_LIBRARY 11
 int lsum_set_option(lsum_ctx ctx, int key, double value);
 /* The autotuner's decisions of earlier runs on a device of the same architecture and compute
  * unit count are read from the text file at `path` (if it exists), and new ones are appended to

@@ -21,6 +21,7 @@ LIBDIR = os.path.join(HERE, "lib")
 LIB = os.path.join(LIBDIR, "liblsum.so")
 
 SOURCES = ["lsum_host.cpp", "lsum_sinc_error.cpp", "lsum_tune.cpp", "lsum_runtime.cpp", "lsum_pipeline.cpp", "lsum_capi.cpp",
+           "lsum_blas.cpp",
            "kernels_lattice.hip", "kernels_gemm.hip", "kernels_jacobi.hip", "scratch_noalloc.hip"]
 
 # Packed FP32 instructions are disabled for all device code (only hand-checked FP32 paths).
@@ -56,7 +57,7 @@ def build(verbose: bool = True) -> str:
         objs = list(ex.map(compile_one, SOURCES))
     os.makedirs(LIBDIR, exist_ok=True)
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + ["-lpthread"]
+    cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + ["-lrocblas", "-lpthread"]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"link failed\n{' '.join(cmd)}\n{res.stdout}\n{res.stderr}")

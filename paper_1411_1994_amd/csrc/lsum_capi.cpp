@@ -732,6 +732,10 @@ int lsum_set_option(lsum_ctx x, int key, double value) {
             if (!(value == 0 || value == 1)) return fail(LSUM_E_INVALID, "autotune option must be 0 or 1");
             c.tuner.enable(value == 1);
             return LSUM_OK;
+        case LSUM_OPT_GEMM_LIBRARY:
+            if (!(value == 0 || value == 1)) return fail(LSUM_E_INVALID, "GEMM library option must be 0 or 1");
+            set_gemm_library(value == 1);
+            return LSUM_OK;
         case LSUM_OPT_JACOBI_WAIT_US:
             if (!(value >= 0 && value <= 1e8)) return fail(LSUM_E_INVALID, "wait bound must be in [0, 1e8] us");
             c.jacobi_wait_us.store((long long)value);

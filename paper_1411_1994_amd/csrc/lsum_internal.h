@@ -282,6 +282,12 @@ struct GemmArgs {
 };
 enum GemmPrec { GEMM_F64 = 0, GEMM_F32 = 1, GEMM_BF16X3 = 2 };
 void launch_gemm(hipStream_t st, GemmPrec prec, const GemmArgs& a);
+// Plain FP64 products (batch 1, unit-stride operands, at least 2^24 multiply-adds) through the
+// ROCm BLAS library's DGEMM, on st; false (nothing launched) for anything else.  Process-wide
+// switch: set_gemm_library.
+bool blas_dgemm(hipStream_t st, const GemmArgs& a);
+void set_gemm_library(bool on);
+bool gemm_library();
 // FP64 GEMM (batch 1) with the reduction split into about `split` slices of a multiple of the
 // staging depth: the slices' products go to work (gemm_split_slices(a, split) x m x n doubles),
 // then C = alpha * (their sum in slice order) + beta * C.

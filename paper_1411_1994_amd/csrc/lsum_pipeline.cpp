@@ -43,6 +43,7 @@ static GemmPrec gemm_prec(int precision) {
 // back to the pool).
 int gemm_auto(Context* c, hipStream_t st, GemmPrec prec, const GemmArgs& a) {
     const long tiles = (long)((a.n + 63) / 64) * ((a.m + 127) / 128) * a.batch;
+    if (prec == GEMM_F64 && blas_dgemm(st, a)) return LSUM_OK;
     if (prec != GEMM_F64 || a.batch != 1 || tiles >= 64 || a.k < 2048) {
         launch_gemm(st, prec, a);
         return LSUM_OK;

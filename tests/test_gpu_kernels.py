@@ -25,9 +25,22 @@ def ctx():
 # MFMA contraction (projections and mode products)
 # ------------------------------------------------------------------------------------------
 
-@pytest.mark.parametrize("m,n,k", [(1, 1, 1), (16, 16, 4), (64, 64, 16), (70, 33, 129), (200, 150, 517)])
+@pytest.fixture(params=[0, 1], ids=["own-kernel", "blas-library"])
+def gemm_lib(request):
+    # FP64 products on the library's own MFMA kernel, or (large unit-stride ones) on the ROCm
+    # BLAS DGEMM; the switch is process-wide, so it is restored afterwards
+    import paper_1411_1994_amd as L
+    with L.Context(0) as c:
+        c.set_option(L.OPT_GEMM_LIBRARY, request.param)
+    yield request.param
+    with L.Context(0) as c:
+        c.set_option(L.OPT_GEMM_LIBRARY, 1)
+
+
+@pytest.mark.parametrize("m,n,k", [(1, 1, 1), (16, 16, 4), (64, 64, 16), (70, 33, 129), (200, 150, 517),
+                                   (300, 400, 301)])
 @pytest.mark.parametrize("layout", ["nn", "tn", "nt", "tt"])
-def test_contract_fp64(ctx, m, n, k, layout):
+def test_contract_fp64(ctx, gemm_lib, m, n, k, layout):
     import torch
     import paper_1411_1994_amd as L
     rng = np.random.default_rng(m * 1000 + n + k)
@@ -50,7 +63,7 @@ def test_contract_fp64(ctx, m, n, k, layout):
 @pytest.mark.parametrize("m,n,k", [(33, 33, 34305), (50, 50, 4099), (7, 200, 5000), (128, 64, 2048),
                                    (1, 1, 100003)])
 @pytest.mark.parametrize("layout", ["nn", "tn", "nt", "tt"])
-def test_contract_fp64_split_reduction(ctx, m, n, k, layout):
+def test_contract_fp64_split_reduction(ctx, gemm_lib, m, n, k, layout):
     # few output tiles and a long reduction: the reduction is split over workgroups and the slices'
     # products summed in order; C has a row stride wider than n (only its m x n part is written)
     import paper_1411_1994_amd as L
