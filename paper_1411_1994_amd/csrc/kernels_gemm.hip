@@ -576,6 +576,23 @@ __global__ void __launch_bounds__(256) k_galerkin_finish(int P, int r1, int r2, 
 }
 
 // A[i * ld + off + i] = 1 for i < n: the identity block of an augmented matrix.
+// UT[i * ldt + q] = U[q * ldu + i] (q < R, i < N), through a 32 x 32 LDS tile.
+__global__ void __launch_bounds__(256) k_transpose_ld(int R, int N, const double* __restrict__ U, int ldu,
+                                                      double* __restrict__ UT, long ldt) {
+    __shared__ double tile[32][33];
+    const int i0 = blockIdx.x * 32, q0 = blockIdx.y * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+    for (int k = ty; k < 32; k += 8) {
+        const int q = q0 + k, i = i0 + tx;
+        tile[k][tx] = (q < R && i < N) ? U[(size_t)q * ldu + i] : 0.0;
+    }
+    __syncthreads();
+    for (int k = ty; k < 32; k += 8) {
+        const int i = i0 + k, q = q0 + tx;
+        if (i < N && q < R) UT[(size_t)i * ldt + q] = tile[tx][k];
+    }
+}
+
 __global__ void __launch_bounds__(256) k_unit_diag(int n, long ld, long off, double* __restrict__ A) {
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i < n) A[(long)i * ld + off + i] = 1.0;
@@ -663,6 +680,11 @@ void launch_galerkin_finish(hipStream_t st, int P, int r1, int r2, const double*
                             const double* Y2, double scale, double* v) {
     if (P <= 0) return;
     hipLaunchKernelGGL(k_galerkin_finish, dim3(cdiv(P, 4)), dim3(256), 0, st, P, r1, r2, X, Y1, Y2, scale, v);
+}
+
+void launch_transpose_ld(hipStream_t st, int R, int N, const double* U, int ldu, double* UT, long ldt) {
+    if (R <= 0 || N <= 0) return;
+    hipLaunchKernelGGL(k_transpose_ld, dim3(cdiv(N, 32), cdiv(R, 32)), dim3(256), 0, st, R, N, U, ldu, UT, ldt);
 }
 
 void launch_unit_diag(hipStream_t st, int n, long ld, long off, double* A) {

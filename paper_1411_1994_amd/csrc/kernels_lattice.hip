@@ -209,10 +209,10 @@ __global__ void __launch_bounds__(256) k_sample_cp(int n_fac, int R, const doubl
     out[p] = total;
 }
 
-// Vector-major R x N rows -> point-major N x R rows (row stride ldt), through a 32 x 32 LDS tile.
+// Vector-major R x N rows -> point-major N x R rows, through a 32 x 32 LDS tile.
 template <typename T>
 __global__ void __launch_bounds__(256) k_transpose(int R, int N, const T* __restrict__ U, int ldu,
-                                                   double* __restrict__ UT, long ldt) {
+                                                   double* __restrict__ UT) {
     __shared__ double tile[32][33];
     const int i0 = blockIdx.x * 32, q0 = blockIdx.y * 32;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
@@ -223,7 +223,7 @@ __global__ void __launch_bounds__(256) k_transpose(int R, int N, const T* __rest
     __syncthreads();
     for (int k = ty; k < 32; k += 8) {
         const int i = i0 + k, q = q0 + tx;
-        if (i < N && q < R) UT[(size_t)i * ldt + q] = tile[tx][k];
+        if (i < N && q < R) UT[(size_t)i * R + q] = tile[tx][k];
     }
 }
 
@@ -557,19 +557,12 @@ void launch_sample_cp(hipStream_t st, int n_fac, int R, const double* U, int ldu
 
 void launch_transpose(hipStream_t st, int R, int N, const double* U, int ldu, double* UT) {
     if (R <= 0 || N <= 0) return;
-    hipLaunchKernelGGL(k_transpose<double>, dim3(cdiv(N, 32), cdiv(R, 32)), dim3(256), 0, st, R, N, U, ldu, UT,
-                       (long)R);
+    hipLaunchKernelGGL(k_transpose<double>, dim3(cdiv(N, 32), cdiv(R, 32)), dim3(256), 0, st, R, N, U, ldu, UT);
 }
 
 void launch_transpose(hipStream_t st, int R, int N, const float* U, int ldu, double* UT) {
     if (R <= 0 || N <= 0) return;
-    hipLaunchKernelGGL(k_transpose<float>, dim3(cdiv(N, 32), cdiv(R, 32)), dim3(256), 0, st, R, N, U, ldu, UT,
-                       (long)R);
-}
-
-void launch_transpose_ld(hipStream_t st, int R, int N, const double* U, int ldu, double* UT, long ldt) {
-    if (R <= 0 || N <= 0) return;
-    hipLaunchKernelGGL(k_transpose<double>, dim3(cdiv(N, 32), cdiv(R, 32)), dim3(256), 0, st, R, N, U, ldu, UT, ldt);
+    hipLaunchKernelGGL(k_transpose<float>, dim3(cdiv(N, 32), cdiv(R, 32)), dim3(256), 0, st, R, N, U, ldu, UT);
 }
 
 int sample_points_per_wg(bool f32) { return f32 ? 64 : 32; }
