@@ -230,7 +230,8 @@ const char* lsum_last_error(void);
  * whose SVD has not converged by then fails with LSUM_E_NOCONV (a bound on its latency).  Read
  * when a request's SVD starts. */
 #define LSUM_OPT_JACOBI_MAX_SWEEPS 5
-/* How the sweeps of a Jacobi SVD are launched; every way gives the same results bit for bit.
+/* How the sweeps of a Jacobi SVD are launched; for a given block width (LSUM_OPT_JACOBI_BLOCK
+ * below) every way gives the same results bit for bit.
  * Default: round by round (three launches per round of disjoint column-block pairs).
  * LSUM_OPT_JACOBI_PERSISTENT (default 0; 1: groups of 16 waves, 2: groups of 4 waves): a sweep
  * is one launch with one workgroup per pair of column blocks, its rounds ordered by per-block
@@ -258,6 +259,12 @@ const char* lsum_last_error(void);
  * library's DGEMM with atomics disabled (results independent of concurrent work); 0: every
  * product on this library's own MFMA kernels. */
 #define LSUM_OPT_GEMM_LIBRARY 11
+/* LSUM_OPT_JACOBI_BLOCK (default 16; or 8): columns per Jacobi block.  Blocks of 16 (pair
+ * problems of 32 columns, solved by four waves) halve the rounds of a sweep; such sweeps run
+ * round by round (directly or from graphs).  The persistent ways
+ * (LSUM_OPT_JACOBI_PERSISTENT) need blocks of 8.  Both widths give an SVD to the same
+ * tolerance and the same certificate, not the same bits. */
+#define LSUM_OPT_JACOBI_BLOCK 12
 int lsum_set_option(lsum_ctx ctx, int key, double value);
 /* The autotuner's decisions of earlier runs on a device of the same architecture and compute
  * unit count are read from the text file at `path` (if it exists), and new ones are appended to

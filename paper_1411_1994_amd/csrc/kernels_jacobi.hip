@@ -283,6 +283,230 @@ __global__ void __launch_bounds__(256) k_pair_rotate(double* const* __restrict__
     }
 }
 
+// ---- 16-column blocks: pairs of 32 rows, half the rounds per sweep --------------------------
+// The same three launches per round on blocks of 16 columns: the 32 x 32 pair Gram (three
+// 16 x 16 MFMA tiles per chunk, the fourth its transpose), the 32 x 32 pair solve by four
+// waves, and the rotation of the pair's 32 rows.  A sweep has nblk - 1 rounds for nblk
+// blocks, so doubling the block halves the rounds (and the launches) per sweep.
+
+__device__ __forceinline__ int pair_row32(int I, int J, int k) { return k < 16 ? I * 16 + k : J * 16 + (k - 16); }
+
+// 1. Gram partials: part[(pair * nchunk + chunk) * 1024 + a*32 + b]
+__global__ void __launch_bounds__(256) k_pair_gram32(double* const* __restrict__ xp, int ldx, int n_gram, int nblk,
+                                                     int round, int nchunk, double* __restrict__ part) {
+    __shared__ double Gp[4][32][33];
+    const double* __restrict__ X = xp[0];
+    const int chunk = blockIdx.x, pair = blockIdx.y;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int r = lane & 15, kg = lane >> 4;
+    int I, J;
+    pair_of(nblk, round, pair, &I, &J);
+    const double* __restrict__ x0r = X + (size_t)pair_row32(I, J, r) * ldx;
+    const double* __restrict__ x1r = X + (size_t)pair_row32(I, J, 16 + r) * ldx;
+    const int c0 = chunk * CW + wave * (CW / 4);
+    double x0[16], x1[16];
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+        const int c = c0 + 4 * s + kg;
+        x0[s] = c < n_gram ? x0r[c] : 0.0;
+        x1[s] = c < n_gram ? x1r[c] : 0.0;
+    }
+    d4 a00 = {0, 0, 0, 0}, a01 = {0, 0, 0, 0}, a11 = {0, 0, 0, 0};
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+        a00 = __builtin_amdgcn_mfma_f64_16x16x4f64(x0[s], x0[s], a00, 0, 0, 0);
+        a01 = __builtin_amdgcn_mfma_f64_16x16x4f64(x0[s], x1[s], a01, 0, 0, 0);
+        a11 = __builtin_amdgcn_mfma_f64_16x16x4f64(x1[s], x1[s], a11, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {   // FP64 MFMA result layout: row kg + 4v, column r
+        Gp[wave][kg + 4 * v][r] = a00[v];
+        Gp[wave][kg + 4 * v][16 + r] = a01[v];
+        Gp[wave][16 + r][kg + 4 * v] = a01[v];
+        Gp[wave][16 + kg + 4 * v][16 + r] = a11[v];
+    }
+    __syncthreads();
+    for (int e = tid; e < 1024; e += 256) {
+        const int a = e >> 5, b = e & 31;
+        part[((size_t)pair * nchunk + chunk) * 1024 + e] = ((Gp[0][a][b] + Gp[1][a][b]) + Gp[2][a][b]) + Gp[3][a][b];
+    }
+}
+
+// Round-robin pairing of 32 columns for the 31 steps of an inner sweep: step t pairs (31, t)
+// and ((t + i) % 31, (t - i + 31) % 31) for i = 1..15.
+__device__ __forceinline__ int inner_p32(int t, int i) { return i == 0 ? 31 : (t + i >= 31 ? t + i - 31 : t + i); }
+__device__ __forceinline__ int inner_q32(int t, int i) { return i == 0 ? t : (t - i < 0 ? t - i + 31 : t - i); }
+
+// The 32 x 32 pair problem solved by the 256 threads of a workgroup: as solve_pair, with thread
+// (bi, bj) = (tid / 16, tid % 16) owning the 2 x 2 blocks {p_bi, q_bi} x {p_bj, q_bj} of G and
+// of Q in each step.  G alternates between two LDS copies (a step reads one and writes the
+// other), so one barrier per step orders its reads before the next step's writes; Q is updated
+// in place (a thread reads and writes only its own entries of it).  Returns whether the pair is
+// to be rotated (the same value on every thread) and leaves the final G in G[cur].
+__device__ bool solve_pair32(int tid, double (*G)[32][33], double (*Q)[33], int* cur_out, double tol, double irr2,
+                             double keep2, int max_inner, unsigned long long* __restrict__ stat, double* red) {
+    const int lane = tid & 63, wave = tid >> 6;
+    double off = 0.0, offk = 0.0;
+    for (int e = tid; e < 1024; e += 256) {
+        const int a = e >> 5, b = e & 31;
+        if (a < b) {
+            const double gaa = G[0][a][a], gbb = G[0][b][b], gab = G[0][a][b];
+            if (coupled(gaa, gbb, gab, irr2)) {
+                const double cab = fabs(gab) * __builtin_amdgcn_rsq(gaa * gbb);
+                off = fmax(off, cab);
+                if (gaa > keep2 && gbb > keep2) offk = fmax(offk, cab);
+            }
+        }
+    }
+    for (int m = 32; m > 0; m >>= 1) {
+        off = fmax(off, __shfl_xor(off, m));
+        offk = fmax(offk, __shfl_xor(offk, m));
+    }
+    if (lane == 0) {
+        red[wave] = off;
+        red[4 + wave] = offk;
+    }
+    __syncthreads();
+    off = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    offk = fmax(fmax(red[4], red[5]), fmax(red[6], red[7]));
+    if (tid == 0) {
+        unsigned long long bits;
+        std::memcpy(&bits, &off, sizeof(bits));
+        atomicMax(stat, bits);   // non-negative doubles order like their bit patterns
+        std::memcpy(&bits, &offk, sizeof(bits));
+        atomicMax(stat + 4, bits);
+    }
+    *cur_out = 0;
+    if (!(off > tol)) return false;
+    const int bi = tid >> 4, bj = tid & 15;
+    int cur = 0;
+    double prev = 2.0;
+    int nsw = 0;
+    for (int sw = 0; sw < max_inner; ++sw) {
+        nsw = sw + 1;
+        double mx = 0.0;
+        for (int step = 0; step < 31; ++step) {
+            const int pi = inner_p32(step, bi), qi = inner_q32(step, bi);
+            const int pj = inner_p32(step, bj), qj = inner_q32(step, bj);
+            const double (*Gc)[33] = G[cur];
+            double (*Gn)[33] = G[cur ^ 1];
+            const double gpp_i = Gc[pi][pi], gqq_i = Gc[qi][qi], gpq_i = Gc[pi][qi];
+            const double gpp_j = Gc[pj][pj], gqq_j = Gc[qj][qj], gpq_j = Gc[pj][qj];
+            const double g00 = Gc[pi][pj], g01 = Gc[pi][qj], g10 = Gc[qi][pj], g11 = Gc[qi][qj];
+            const double q00 = Q[pi][pj], q01 = Q[pi][qj], q10 = Q[qi][pj], q11 = Q[qi][qj];
+            double ci, si, cj, sj, ri, rj;
+            rotation(gpp_i, gqq_i, gpq_i, irr2, &ci, &si, &ri);
+            rotation(gpp_j, gqq_j, gpq_j, irr2, &cj, &sj, &rj);
+            mx = fmax(mx, ri);
+            const double h00 = ci * g00 - si * g10, h01 = ci * g01 - si * g11;
+            const double h10 = si * g00 + ci * g10, h11 = si * g01 + ci * g11;
+            Gn[pi][pj] = cj * h00 - sj * h01;
+            Gn[pi][qj] = sj * h00 + cj * h01;
+            Gn[qi][pj] = cj * h10 - sj * h11;
+            Gn[qi][qj] = sj * h10 + cj * h11;
+            Q[pi][pj] = cj * q00 - sj * q01;
+            Q[pi][qj] = sj * q00 + cj * q01;
+            Q[qi][pj] = cj * q10 - sj * q11;
+            Q[qi][qj] = sj * q10 + cj * q11;
+            __syncthreads();
+            cur ^= 1;
+        }
+        for (int m = 32; m > 0; m >>= 1) mx = fmax(mx, __shfl_xor(mx, m));
+        if (lane == 0) red[wave] = mx;
+        __syncthreads();
+        mx = sqrt(fmax(fmax(red[0], red[1]), fmax(red[2], red[3])));
+        __syncthreads();   // red is reused
+        if (mx <= 1e-16) break;
+        if (sw >= 2 && mx > 0.9 * prev) break;
+        prev = mx;
+    }
+    if (tid == 0) {   // inner sweep statistics: total, maximum, solved pairs
+        atomicAdd(stat + 1, (unsigned long long)nsw);
+        atomicMax(stat + 2, (unsigned long long)nsw);
+        atomicAdd(stat + 3, 1ull);
+    }
+    *cur_out = cur;
+    return true;
+}
+
+// 2. per pair: the chunk partials summed in chunk order (four entries per thread), then solved
+__global__ void __launch_bounds__(256) k_pair_eig32(int nchunk, const double* __restrict__ part, double tol,
+                                                    double irr2, const double* __restrict__ keep2p, int max_inner,
+                                                    double* __restrict__ Qout, int* __restrict__ active,
+                                                    unsigned long long* __restrict__ stat) {
+    __shared__ double G[2][32][33];
+    __shared__ double Q[32][33];
+    __shared__ double red[8];
+    const int pair = blockIdx.x, tid = threadIdx.x;
+    for (int u = 0; u < 4; ++u) {
+        const int e = tid + 256 * u;
+        const double* pp = part + (size_t)pair * nchunk * 1024 + e;
+        double s = 0.0;
+        for (int c = 0; c < nchunk; c += EIG_LOADS) {
+            double v[EIG_LOADS];
+#pragma unroll
+            for (int k = 0; k < EIG_LOADS; ++k) v[k] = pp[(size_t)min(c + k, nchunk - 1) * 1024];
+#pragma unroll
+            for (int k = 0; k < EIG_LOADS; ++k) s += c + k < nchunk ? v[k] : 0.0;
+        }
+        G[0][e >> 5][e & 31] = s;
+        Q[e >> 5][e & 31] = ((e >> 5) == (e & 31)) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    int cur = 0;
+    const bool act = solve_pair32(tid, G, Q, &cur, tol, irr2, *keep2p, max_inner, stat, red);
+    if (tid == 0) active[pair] = act ? 1 : 0;
+    if (!act) return;
+    for (int e = tid; e < 1024; e += 256) Qout[(size_t)pair * 1024 + e] = Q[e >> 5][e & 31];
+}
+
+// 3. X_pair <- Q^T X_pair over one chunk: each wave 64 cells (4 tiles of 16) x 32 rows
+__global__ void __launch_bounds__(256) k_pair_rotate32(double* const* __restrict__ xp, int ldx, int nblk, int round,
+                                                       const double* __restrict__ Qin,
+                                                       const int* __restrict__ active) {
+    const int chunk = blockIdx.x, pair = blockIdx.y;
+    if (!active[pair]) return;
+    double* __restrict__ X = xp[0];
+    __shared__ double Q[32][33];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int r = lane & 15, kg = lane >> 4;
+    for (int e = tid; e < 1024; e += 256) Q[e >> 5][e & 31] = Qin[(size_t)pair * 1024 + e];
+    __syncthreads();
+    int I, J;
+    pair_of(nblk, round, pair, &I, &J);
+    const int c0 = chunk * CW + wave * (CW / 4);
+    double b[4][8];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int k0 = 0; k0 < 8; ++k0) {
+            const int col = c0 + 16 * t + r;
+            b[t][k0] = col < ldx ? X[(size_t)pair_row32(I, J, 4 * k0 + kg) * ldx + col] : 0.0;
+        }
+    d4 acc[4][2];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt) {
+            acc[t][rt] = d4{0, 0, 0, 0};
+#pragma unroll
+            for (int k0 = 0; k0 < 8; ++k0)
+                acc[t][rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(Q[4 * k0 + kg][16 * rt + r], b[t][k0], acc[t][rt],
+                                                                   0, 0, 0);
+        }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int col = c0 + 16 * t + r;
+        if (col < ldx) {
+#pragma unroll
+            for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    X[(size_t)pair_row32(I, J, 16 * rt + kg + 4 * v) * ldx + col] = acc[t][rt][v];
+        }
+    }
+}
+
 // A whole sweep in one launch: workgroup p owns pair slot p of every round of the round robin.
 // A round on blocks (I, J) starts once both blocks have finished the previous round (their
 // version counters, set with release order after the rows are written; read with acquire
@@ -693,11 +917,12 @@ struct JacobiLayout {
     size_t off_x2, off_nrm, off_perm, off_stat, off_part, off_q, off_act, off_ptr, off_ver, total;
 };
 
-JacobiLayout layout(int D, int N, int n_gram) {
+// bw: columns per block (8, or 16 for pairs of 32 rows); rows are padded to whole block pairs
+JacobiLayout layout(int D, int N, int n_gram, int bw = 8) {
     JacobiLayout L{};
-    L.Dp = std::max(16, (D + 15) / 16 * 16);
+    L.Dp = std::max(2 * bw, (D + 2 * bw - 1) / (2 * bw) * (2 * bw));
     L.ldx = (N + 15) / 16 * 16;
-    L.nblk = L.Dp / 8;
+    L.nblk = L.Dp / bw;
     L.npair = L.nblk / 2;
     L.nchunk = (n_gram + CW - 1) / CW;
     L.nchunk_all = (L.ldx + CW - 1) / CW;
@@ -708,8 +933,9 @@ JacobiLayout layout(int D, int N, int n_gram) {
     L.off_perm = al(L.off_nrm + (size_t)L.Dp * sizeof(double));
     L.off_stat = al(L.off_perm + (size_t)L.Dp * sizeof(int32_t));
     L.off_part = al(L.off_stat + 64);
-    L.off_q = al(L.off_part + (size_t)L.npair * L.nchunk * 256 * sizeof(double));
-    L.off_act = al(L.off_q + (size_t)L.npair * 256 * sizeof(double));
+    const size_t pe = (size_t)4 * bw * bw;   // entries of a pair's Gram
+    L.off_q = al(L.off_part + (size_t)L.npair * L.nchunk * pe * sizeof(double));
+    L.off_act = al(L.off_q + (size_t)L.npair * pe * sizeof(double));
     L.off_ptr = al(L.off_act + (size_t)L.npair * sizeof(int));   // {current, other} buffer, keep2
     L.off_ver = al(L.off_ptr + 3 * sizeof(double));               // block versions, abort flag
     L.total = al(L.off_ver + (size_t)(L.nblk + 1) * sizeof(int));
@@ -718,7 +944,7 @@ JacobiLayout layout(int D, int N, int n_gram) {
 
 }  // namespace
 
-size_t jacobi_work_bytes(int D, int N) { return layout(D, N, N).total; }
+size_t jacobi_work_bytes(int D, int N) { return std::max(layout(D, N, N, 8).total, layout(D, N, N, 16).total); }
 
 void launch_pchol(hipStream_t st, int n, const double* A, double tau2, int pivot, double* Rt, int* perm, int* keep_dev) {
     hipLaunchKernelGGL(k_pchol, dim3(1), dim3(PC_THREADS), 0, st, n, A, tau2, pivot, Rt, perm, keep_dev);
@@ -827,7 +1053,11 @@ int jacobi_svd(hipStream_t st, int D, int N, double* A, int lda, double tol, dou
     int persistent = run->persistent;
     if (n_gram <= 0 || n_gram > N) n_gram = N;
     if (D <= 0 || N <= 0) return fail(LSUM_E_INVALID, "empty side matrix");
-    const JacobiLayout L = layout(D, N, n_gram);
+    // 16-column blocks (pairs of 32 rows) halve the rounds per sweep; they run round by round
+    // (the persistent ways are written for 8-column blocks)
+    const int bw = run->block == 16 ? 16 : 8;
+    if (bw == 16) persistent = 0;
+    const JacobiLayout L = layout(D, N, n_gram, bw);
     if (work_bytes < L.total) return fail(LSUM_E_INVALID, "Jacobi workspace too small");
     char* base = (char*)work_dev;
     double* X = (double*)base;
@@ -901,6 +1131,15 @@ int jacobi_svd(hipStream_t st, int D, int N, double* A, int lda, double tol, dou
             return;
         }
         for (int round = 0; round < nblk - 1; ++round) {
+            if (bw == 16) {
+                hipLaunchKernelGGL(k_pair_gram32, dim3(L.nchunk, npair), dim3(256), 0, st, xp_dev, L.ldx, n_gram,
+                                   nblk, round, L.nchunk, part);
+                hipLaunchKernelGGL(k_pair_eig32, dim3(npair), dim3(256), 0, st, L.nchunk, part, tol, irr2, keep2_dev,
+                                   max_inner, Qd, act, stat);
+                hipLaunchKernelGGL(k_pair_rotate32, dim3(L.nchunk_all, npair), dim3(256), 0, st, xp_dev, L.ldx, nblk,
+                                   round, Qd, act);
+                continue;
+            }
             hipLaunchKernelGGL(k_pair_gram, dim3(L.nchunk, npair), dim3(256), 0, st, xp_dev, L.ldx, n_gram, nblk,
                                round, L.nchunk, part);
             hipLaunchKernelGGL(k_pair_eig, dim3(npair), dim3(256), 0, st, L.nchunk, part, tol, irr2, keep2_dev,
@@ -924,10 +1163,10 @@ int jacobi_svd(hipStream_t st, int D, int N, double* A, int lda, double tol, dou
         return b;
     };
     const std::string tune_key = "jacobi/" + std::to_string(pow2(L.Dp)) + "/" + std::to_string(pow2(L.ldx)) + "/" +
-                                 std::to_string(pow2(n_gram));
+                                 std::to_string(pow2(n_gram)) + (bw == 16 ? "/b16" : "");
     int tune_key_choice = run->tuner ? run->tuner->get(tune_key) : -2;
     if (tune_key_choice >= 0) {
-        persistent = tune_key_choice == 2 ? 1 : (tune_key_choice == 3 ? 2 : 0);
+        persistent = bw == 16 ? 0 : (tune_key_choice == 2 ? 1 : (tune_key_choice == 3 ? 2 : 0));
         graphs = tune_key_choice == 1;
     }
     const PersistentCap pcap = persistent_capacity();
@@ -936,7 +1175,7 @@ int jacobi_svd(hipStream_t st, int D, int N, double* A, int lda, double tol, dou
         // only columns above the floor take part (sorted first); the rest are never rotated
         int d_act = 0;
         while (d_act < L.Dp && sig2[perm[d_act]] > irr2) ++d_act;
-        const int nblk = std::max(2, (d_act + 15) / 16 * 2);
+        const int nblk = std::max(2, (d_act + 2 * bw - 1) / (2 * bw) * 2);
         LSUM_HIP(hipMemcpyAsync(perm_dev, perm.data(), L.Dp * sizeof(int32_t), hipMemcpyHostToDevice, st));
         LSUM_HIP(hipMemcpyAsync(keep2_dev, &keep2, sizeof(double), hipMemcpyHostToDevice, st));
         // persistent groups reserved against 3/4 of the device (per variant: its share of a CU)
@@ -977,7 +1216,7 @@ int jacobi_svd(hipStream_t st, int D, int N, double* A, int lda, double tol, dou
             LSUM_HIP(hipEventCreate(&e0));
             LSUM_HIP(hipEventCreate(&e1));
             for (int m : {3, 2, 1, 0}) {
-                if (m >= 2 && !clock_ok) continue;
+                if (m >= 2 && (!clock_ok || bw == 16)) continue;
                 LSUM_HIP(hipMemcpyAsync(xp_dev, xp_host, sizeof(xp_host), hipMemcpyHostToDevice, st));
                 persistent = m == 2 ? 1 : (m == 3 ? 2 : 0);
                 GroupTokens tk;
@@ -1005,7 +1244,7 @@ int jacobi_svd(hipStream_t st, int D, int N, double* A, int lda, double tol, dou
             (void)hipEventDestroy(e0);
             (void)hipEventDestroy(e1);
             const int ch = run->tuner->put(tune_key, ms);
-            persistent = ch == 2 ? 1 : (ch == 3 ? 2 : 0);
+            persistent = bw == 16 ? 0 : (ch == 2 ? 1 : (ch == 3 ? 2 : 0));
             graphs = ch == 1;
             tune_key_choice = ch;
             run->tuned = 1;
@@ -1032,7 +1271,7 @@ int jacobi_svd(hipStream_t st, int D, int N, double* A, int lda, double tol, dou
         cur ^= 1;
         // FP64 MFMA work of the sweep: every pair visit forms a 16 x 16 Gram over n_gram entries
         // and (when active) rotates 16 rows of ldx entries; counted for every visit
-        run->flops += (double)(nblk / 2) * (nblk - 1) * 512.0 * ((double)n_gram + L.ldx);
+        run->flops += (double)(nblk / 2) * (nblk - 1) * 8.0 * bw * bw * ((double)n_gram + L.ldx);
         unsigned long long st4[5] = {0, 0, 0, 0, 0};
         int aborted = 0;
         LSUM_HIP(hipMemcpyAsync(st4, stat, sizeof(st4), hipMemcpyDeviceToHost, st));

@@ -350,6 +350,8 @@ void launch_cp_norm2(hipStream_t st, int R, int n_groups, const int32_t* src1, c
 // Every way adds the same terms in the same order (the same results bit for bit).
 struct JacobiRun {
     int graphs = 0;
+    int block = 8;                 // columns per block: 8, or 16 (pairs of 32 rows, round by round)
+                                   // (contexts default to 16; this struct's default serves direct callers)
     int persistent = 0;            // 1: 16-wave pair groups, 2: 4-wave pair groups
     double wait_us = 2e4;
     // workgroups of persistent sweeps running on the device (shared by every SVD of a context):

@@ -25,12 +25,13 @@ def _problems():
     return [med, small]
 
 
-def _run(graphs, problems):
+def _run(graphs, problems, block=8):
     import paper_1411_1994_amd as L
     out = []
     with L.Context(0, n_slots=1) as c:
         c.set_option(L.OPT_AUTOTUNE, 0)            # the options below decide
         c.set_option(L.OPT_JACOBI_PERSISTENT, 0)   # graphs apply to the round-by-round launches
+        c.set_option(L.OPT_JACOBI_BLOCK, block)
         c.set_option(L.OPT_GRAPHS, graphs)
         for p in problems + problems:          # every problem twice on the same context
             rng = np.random.default_rng(6)
@@ -49,6 +50,10 @@ def test_graph_replayed_sweeps_equal_direct_launches():
     require_gpu()
     probs = _problems()
     a, b = _run(1, probs), _run(0, probs)
+    a16, b16 = _run(1, probs, 16), _run(0, probs, 16)
+    for k, (x, y) in enumerate(zip(a16, b16)):
+        assert x["r"] == y["r"] and x["sweeps"] == y["sweeps"] and x["bound"] == y["bound"], k
+        assert np.array_equal(x["v"], y["v"]), k
     for k, (x, y) in enumerate(zip(a, b)):
         assert x["r"] == y["r"] and x["sweeps"] == y["sweeps"] and x["bound"] == y["bound"], k
         for l in range(3):
@@ -65,10 +70,12 @@ def test_graph_replayed_sweeps_equal_direct_launches():
 
 
 def _run_opts(opts, problems):
+    # blocks of 8 columns unless the options say otherwise: the persistent ways need them
     import paper_1411_1994_amd as L
     out = []
     with L.Context(0, n_slots=1) as c:
         c.set_option(L.OPT_AUTOTUNE, 0)
+        c.set_option(L.OPT_JACOBI_BLOCK, 8)
         for k, v in opts.items():
             c.set_option(k, v)
         for p in problems:
@@ -141,6 +148,7 @@ def test_autotuned_sweeps_equal_fixed_ones_and_decisions_persist(tmp_path):
     for round_ in range(2):
         with L.Context(0, n_slots=1) as c:
             c.set_option(L.OPT_AUTOTUNE, 1)
+            c.set_option(L.OPT_JACOBI_BLOCK, 8)   # all four ways (the persistent ones need 8)
             c.tune_file(path)
             for p in probs:
                 r = c.submit(p)
@@ -161,3 +169,30 @@ def test_autotuned_sweeps_equal_fixed_ones_and_decisions_persist(tmp_path):
     n = len(probs)
     assert sum(tuned[:n]) >= 1          # the first context timed the ways
     assert sum(tuned[n:]) == 0          # the second read the file
+
+
+def test_16_column_blocks_graphs_equal_direct_and_match_8_column_blocks():
+    # Jacobi on blocks of 16 columns: graph replay equals direct launches bit for bit; against
+    # blocks of 8 the ranks agree (or sit at a threshold within rounding), both bounds are
+    # certified, and both results are within their bound of the oracle's direct sum
+    require_gpu()
+    import paper_1411_1994_amd as L
+    probs = _problems()
+    b16d = _run_opts({L.OPT_JACOBI_BLOCK: 16, L.OPT_GRAPHS: 0}, probs)
+    b16g = _run_opts({L.OPT_JACOBI_BLOCK: 16, L.OPT_GRAPHS: 1}, probs)
+    b8 = _run_opts({L.OPT_JACOBI_BLOCK: 8}, probs)
+    for k, p in enumerate(probs):
+        x, y, z = b16d[k], b16g[k], b8[k]
+        assert x["r"] == y["r"] and x["sweeps"] == y["sweeps"] and x["bound"] == y["bound"], k
+        for l in range(3):
+            assert np.array_equal(x["sig"][l], y["sig"][l]), (k, l)
+        assert np.array_equal(x["v"], y["v"]), k
+        assert all(abs(a - b) <= 1 for a, b in zip(x["r"], z["r"])), (x["r"], z["r"])
+        nA = x["st"]["norm_A"]
+        ref = O.brute_force_points(p, x["cells"])
+        for o in (x, z):
+            assert o["bound"] <= p.eps * nA * (1 + 1e-12)
+            assert np.max(np.abs(o["v"] - ref)) <= o["bound"] * (1 + 1e-9) + 1e-12 * np.max(np.abs(ref))
+        for l in range(3):
+            n = min(len(x["sig"][l]), len(z["sig"][l]), min(x["r"][l], z["r"][l]))
+            assert np.allclose(x["sig"][l][:n], z["sig"][l][:n], rtol=1e-10, atol=1e-12 * z["sig"][l][0])

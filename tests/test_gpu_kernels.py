@@ -14,9 +14,11 @@ pytestmark = pytest.mark.gpu
 
 @pytest.fixture(scope="module")
 def ctx():
+    # Jacobi on blocks of 8 columns here; the 16-column blocks have a test of their own
     require_gpu()
     import paper_1411_1994_amd as L
     c = L.Context(0)
+    c.set_option(L.OPT_JACOBI_BLOCK, 8)
     yield c
     c.close()
 
@@ -217,6 +219,21 @@ def test_sample_canonical_snaps_like_oracle(ctx):
 
 @pytest.mark.parametrize("D,N,decay", [(16, 40, 1.0), (40, 100, 1e-12), (100, 64, 1e-6), (257, 300, 1e-14)])
 def test_jacobi_svd_known_spectrum(ctx, D, N, decay):
+    _check_known_spectrum(ctx, D, N, decay)
+
+
+@pytest.mark.parametrize("D,N,decay", [(16, 40, 1.0), (33, 100, 1e-12), (100, 64, 1e-6), (257, 300, 1e-14),
+                                       (700, 1500, 1e-9)])
+def test_jacobi_svd_16_column_blocks_known_spectrum(D, N, decay):
+    # pairs of 32 rows (four-wave pair solves, half the rounds per sweep): the same checks
+    import paper_1411_1994_amd as L
+    require_gpu()
+    with L.Context(0, n_slots=1) as c:
+        c.set_option(L.OPT_JACOBI_BLOCK, 16)
+        _check_known_spectrum(c, D, N, decay)
+
+
+def _check_known_spectrum(ctx, D, N, decay):
     rng = np.random.default_rng(D + N)
     r = min(D, N)
     U, _ = np.linalg.qr(rng.standard_normal((N, r)))
