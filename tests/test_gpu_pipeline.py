@@ -642,3 +642,34 @@ def test_galerkin_and_canonical_form_with_device_buffers(ctx):
     r.release()
     assert rc == 0 and Rc.value == R and ec.value == err
     assert np.array_equal(host(xd), xi) and all(np.array_equal(host(Ud[l]), U[l]) for l in range(3))
+
+
+def test_own_fp64_gemm_kernels_match_the_library_path():
+    # the medium defected request (range bases, FP64 projections and core) with every FP64
+    # product on the library's own MFMA kernels and with the large ones on the ROCm BLAS DGEMM:
+    # the same certified ranks, bounds within rounding, and values within 1e-10 of each other
+    # and within the bound of the oracle's direct sum
+    require_gpu()
+    import paper_1411_1994_amd as L
+    p = _medium_defected(eps=1e-4)
+    rng = np.random.default_rng(8)
+    cells = np.stack([rng.integers(0, n, 24) for n in p.N], axis=1)
+    out = {}
+    try:
+        for lib in (0, 1):
+            with L.Context(0, n_slots=1) as c:
+                c.set_option(L.OPT_GEMM_LIBRARY, lib)
+                r = c.submit(p)
+                assert r.wait() == 0, r.stats()
+                out[lib] = (r.info(), r.sample(cells_xyz(p, cells)))
+                r.release()
+    finally:
+        with L.Context(0, n_slots=1) as c:
+            c.set_option(L.OPT_GEMM_LIBRARY, 1)
+    (ia, va), (ib, vb) = out[0], out[1]
+    assert tuple(ia.r) == tuple(ib.r)
+    assert abs(ia.bound - ib.bound) <= 1e-9 * ib.bound
+    scale = np.max(np.abs(vb))
+    assert np.max(np.abs(va - vb)) <= 1e-10 * scale
+    ref = O.brute_force_points(p, cells)
+    assert np.max(np.abs(vb - ref)) <= ib.bound * (1 + 1e-9) + 1e-12 * np.max(np.abs(ref))
