@@ -704,7 +704,7 @@ def main():
         copy_calibration()
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU; multi-GPU runs are not part of this build",
+        print(json.dumps({"error": "this benchmark runs on one GPU only (--gpus 1); it has no multi-GPU path",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     if args.workload == "mix":
