@@ -265,6 +265,12 @@ const char* lsum_last_error(void);
  * (LSUM_OPT_JACOBI_PERSISTENT) need blocks of 8.  Both widths give an SVD to the same
  * tolerance and the same certificate, not the same bits. */
 #define LSUM_OPT_JACOBI_BLOCK 12
+/* LSUM_OPT_JACOBI_SKIP (default 1; or 0): with 16-column blocks, the pair solve leaves out
+ * rotations whose relative coupling |g_ab| / sqrt(g_aa g_bb) is at most a tenth of the sweep
+ * tolerance, and a step of the pair's cyclic sweep with no rotation left is skipped; 0: every
+ * rotation above the rounding floor (1e-16) is applied.  The sweeps end on the same
+ * convergence test either way. */
+#define LSUM_OPT_JACOBI_SKIP 13
 int lsum_set_option(lsum_ctx ctx, int key, double value);
 /* The autotuner's decisions of earlier runs on a device of the same architecture and compute
  * unit count are read from the text file at `path` (if it exists), and new ones are appended to

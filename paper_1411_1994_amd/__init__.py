@@ -35,6 +35,7 @@ SYMBOLS = ["lsum_nodes", "lsum_block_offsets", "lsum_shear_blocks", "lsum_column
 OPT_MAX_BATCH, OPT_REF_CACHE_BYTES, OPT_RANGE_MIN, OPT_JACOBI_STOP, OPT_JACOBI_MAX_SWEEPS, OPT_GRAPHS = 1, 2, 3, 4, 5, 6
 OPT_JACOBI_PERSISTENT, OPT_JACOBI_WAIT_US, OPT_AUTOTUNE, OPT_GEMM_LIBRARY = 7, 8, 9, 11
 OPT_JACOBI_BLOCK = 12
+OPT_JACOBI_SKIP = 13
 
 
 class LsumError(RuntimeError):

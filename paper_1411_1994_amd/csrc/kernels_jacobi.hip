@@ -90,13 +90,13 @@ __device__ __forceinline__ int inner_q(int t, int i) { return i == 0 ? t : (t - 
 // The rotation (c, s) that annihilates the coupling b of two columns with squared norms a and d,
 // and the squared relative coupling b^2 / (a d) it removes (0 for a pair that is left alone).
 __device__ __forceinline__ void rotation(double a, double d, double b, double irr2, double* c, double* s,
-                                         double* rel2) {
+                                         double* rel2, double skip2 = 1e-32) {
     // computed without branches (every lane of the wavefront takes the same path) and selected
     // at the end: a pair left alone gets (1, 0)
     const bool cpl = coupled(a, d, b, irr2);
     // the coupling only steers decisions: an approximate reciprocal suffices
     const double r2 = (b * b) * __builtin_amdgcn_rcp(a * d);
-    const bool go = cpl && r2 > 1e-32;
+    const bool go = cpl && r2 > skip2;
     // tan of the angle that annihilates b: t = 2b / (z + sign(z) sqrt(z^2 + 4 b^2)), z = d - a (the
     // smaller root, |t| <= 1).  t may be approximate (the rotation is then slightly short of
     // optimal but still orthogonal); c = (1 + t^2)^(-1/2) is refined to full precision so that
@@ -343,8 +343,15 @@ __device__ __forceinline__ int inner_q32(int t, int i) { return i == 0 ? t : (t 
 // other), so one barrier per step orders its reads before the next step's writes; Q is updated
 // in place (a thread reads and writes only its own entries of it).  Returns whether the pair is
 // to be rotated (the same value on every thread) and leaves the final G in G[cur].
+// Each lane computes one rotation, that of pair bj (lanes 0..15 of every wavefront hold the 16
+// rotations of the step); the rotation of pair bi is read from lane bi of the same wavefront
+// (bi = 4 wave + lane / 16 < 16, and lane bi has bj = bi).  Rotations whose squared relative
+// coupling is at most skip2 are not applied, and a step with none to apply is skipped whole:
+// every wavefront computes the same 16 rotations from the same entries, so all of them take the
+// same decision and the barrier stays uniform.
 __device__ bool solve_pair32(int tid, double (*G)[32][33], double (*Q)[33], int* cur_out, double tol, double irr2,
-                             double keep2, int max_inner, unsigned long long* __restrict__ stat, double* red) {
+                             double keep2, double skip2, int max_inner, unsigned long long* __restrict__ stat,
+                             double* red) {
     const int lane = tid & 63, wave = tid >> 6;
     double off = 0.0, offk = 0.0;
     for (int e = tid; e < 1024; e += 256) {
@@ -381,23 +388,23 @@ __device__ bool solve_pair32(int tid, double (*G)[32][33], double (*Q)[33], int*
     const int bi = tid >> 4, bj = tid & 15;
     int cur = 0;
     double prev = 2.0;
-    int nsw = 0;
+    int nsw = 0, nrun = 0;
     for (int sw = 0; sw < max_inner; ++sw) {
         nsw = sw + 1;
         double mx = 0.0;
         for (int step = 0; step < 31; ++step) {
-            const int pi = inner_p32(step, bi), qi = inner_q32(step, bi);
             const int pj = inner_p32(step, bj), qj = inner_q32(step, bj);
             const double (*Gc)[33] = G[cur];
+            double cj, sj, rj;
+            rotation(Gc[pj][pj], Gc[qj][qj], Gc[pj][qj], irr2, &cj, &sj, &rj, skip2);
+            mx = fmax(mx, rj);
+            if (__ballot(sj != 0.0) == 0ull) continue;   // no rotation of this step is applied
+            ++nrun;
+            const int pi = inner_p32(step, bi), qi = inner_q32(step, bi);
             double (*Gn)[33] = G[cur ^ 1];
-            const double gpp_i = Gc[pi][pi], gqq_i = Gc[qi][qi], gpq_i = Gc[pi][qi];
-            const double gpp_j = Gc[pj][pj], gqq_j = Gc[qj][qj], gpq_j = Gc[pj][qj];
             const double g00 = Gc[pi][pj], g01 = Gc[pi][qj], g10 = Gc[qi][pj], g11 = Gc[qi][qj];
             const double q00 = Q[pi][pj], q01 = Q[pi][qj], q10 = Q[qi][pj], q11 = Q[qi][qj];
-            double ci, si, cj, sj, ri, rj;
-            rotation(gpp_i, gqq_i, gpq_i, irr2, &ci, &si, &ri);
-            rotation(gpp_j, gqq_j, gpq_j, irr2, &cj, &sj, &rj);
-            mx = fmax(mx, ri);
+            const double ci = __shfl(cj, bi), si = __shfl(sj, bi);
             const double h00 = ci * g00 - si * g10, h01 = ci * g01 - si * g11;
             const double h10 = si * g00 + ci * g10, h11 = si * g01 + ci * g11;
             Gn[pi][pj] = cj * h00 - sj * h01;
@@ -420,10 +427,12 @@ __device__ bool solve_pair32(int tid, double (*G)[32][33], double (*Q)[33], int*
         if (sw >= 2 && mx > 0.9 * prev) break;
         prev = mx;
     }
-    if (tid == 0) {   // inner sweep statistics: total, maximum, solved pairs
+    if (tid == 0) {   // inner sweep statistics: total, maximum, solved pairs; steps applied, steps visited
         atomicAdd(stat + 1, (unsigned long long)nsw);
         atomicMax(stat + 2, (unsigned long long)nsw);
         atomicAdd(stat + 3, 1ull);
+        atomicAdd(stat + 5, (unsigned long long)nrun);
+        atomicAdd(stat + 6, (unsigned long long)(31 * nsw));
     }
     *cur_out = cur;
     return true;
@@ -431,7 +440,8 @@ __device__ bool solve_pair32(int tid, double (*G)[32][33], double (*Q)[33], int*
 
 // 2. per pair: the chunk partials summed in chunk order (four entries per thread), then solved
 __global__ void __launch_bounds__(256) k_pair_eig32(int nchunk, const double* __restrict__ part, double tol,
-                                                    double irr2, const double* __restrict__ keep2p, int max_inner,
+                                                    double irr2, double skip2, const double* __restrict__ keep2p,
+                                                    int max_inner,
                                                     double* __restrict__ Qout, int* __restrict__ active,
                                                     unsigned long long* __restrict__ stat) {
     __shared__ double G[2][32][33];
@@ -454,7 +464,7 @@ __global__ void __launch_bounds__(256) k_pair_eig32(int nchunk, const double* __
     }
     __syncthreads();
     int cur = 0;
-    const bool act = solve_pair32(tid, G, Q, &cur, tol, irr2, *keep2p, max_inner, stat, red);
+    const bool act = solve_pair32(tid, G, Q, &cur, tol, irr2, *keep2p, skip2, max_inner, stat, red);
     if (tid == 0) active[pair] = act ? 1 : 0;
     if (!act) return;
     for (int e = tid; e < 1024; e += 256) Qout[(size_t)pair * 1024 + e] = Q[e >> 5][e & 31];
@@ -667,7 +677,7 @@ __global__ void k_swap_clear(double** __restrict__ xp, unsigned long long* __res
         double* t = xp[0];
         xp[0] = xp[1];
         xp[1] = t;
-        for (int k = 0; k < 5; ++k) stat[k] = 0ull;
+        for (int k = 0; k < 7; ++k) stat[k] = 0ull;
     }
     for (int k = threadIdx.x; k <= n_ver; k += blockDim.x) ver[k] = 0;   // versions, then the abort flag
 }
@@ -1102,6 +1112,8 @@ int jacobi_svd(hipStream_t st, int D, int N, double* A, int lda, double tol, dou
     const double smax2 = sig2[perm[0]];
     const double irr2 = std::max(irrelevant * irrelevant, 1e-30 * smax2);
     const bool trace = std::getenv("LSUM_JACOBI_TRACE") != nullptr;
+    // squared relative coupling at or below which the 32-column pair solve applies no rotation
+    const double skip2 = std::max(1e-32, run->skip_rel * run->skip_rel * tol * tol);
     // One sweep: permute the rows (largest first) into the other buffer and make it current, then
     // nblk - 1 rounds of (pair Grams, pair solves, rotations), then the new row norms.  Every
     // sweep with the same nblk issues the same launches; the buffers and keep2 are read from
@@ -1134,8 +1146,8 @@ int jacobi_svd(hipStream_t st, int D, int N, double* A, int lda, double tol, dou
             if (bw == 16) {
                 hipLaunchKernelGGL(k_pair_gram32, dim3(L.nchunk, npair), dim3(256), 0, st, xp_dev, L.ldx, n_gram,
                                    nblk, round, L.nchunk, part);
-                hipLaunchKernelGGL(k_pair_eig32, dim3(npair), dim3(256), 0, st, L.nchunk, part, tol, irr2, keep2_dev,
-                                   max_inner, Qd, act, stat);
+                hipLaunchKernelGGL(k_pair_eig32, dim3(npair), dim3(256), 0, st, L.nchunk, part, tol, irr2, skip2,
+                                   keep2_dev, max_inner, Qd, act, stat);
                 hipLaunchKernelGGL(k_pair_rotate32, dim3(L.nchunk_all, npair), dim3(256), 0, st, xp_dev, L.ldx, nblk,
                                    round, Qd, act);
                 continue;
@@ -1272,7 +1284,7 @@ int jacobi_svd(hipStream_t st, int D, int N, double* A, int lda, double tol, dou
         // FP64 MFMA work of the sweep: every pair visit forms a 16 x 16 Gram over n_gram entries
         // and (when active) rotates 16 rows of ldx entries; counted for every visit
         run->flops += (double)(nblk / 2) * (nblk - 1) * 8.0 * bw * bw * ((double)n_gram + L.ldx);
-        unsigned long long st4[5] = {0, 0, 0, 0, 0};
+        unsigned long long st4[7] = {0, 0, 0, 0, 0, 0, 0};
         int aborted = 0;
         LSUM_HIP(hipMemcpyAsync(st4, stat, sizeof(st4), hipMemcpyDeviceToHost, st));
         if (was_persistent) LSUM_HIP(hipMemcpyAsync(&aborted, ver + nblk, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -1325,9 +1337,9 @@ int jacobi_svd(hipStream_t st, int D, int N, double* A, int lda, double tol, dou
             keep2 = m < L.Dp ? sig2[perm[m]] : 0.0;
         }
         if (trace)
-            std::fprintf(stderr, "jacobi D=%d N=%d sweep %d active %d max coupling %.3e kept %.3e rank %d inner sweeps %.2f avg %llu max over %llu pairs%s\n",
+            std::fprintf(stderr, "jacobi D=%d N=%d sweep %d active %d max coupling %.3e kept %.3e rank %d inner sweeps %.2f avg %llu max over %llu pairs, steps applied %llu of %llu%s\n",
                          D, N, sweeps, d_act, off, offk, r_now, st4[3] ? (double)st4[1] / (double)st4[3] : 0.0, st4[2],
-                         st4[3], was_persistent ? " (persistent)" : (used_graph ? " (graph)" : ""));
+                         st4[3], st4[5], st4[6], was_persistent ? " (persistent)" : (used_graph ? " (graph)" : ""));
     }
     // write back the D largest columns in descending order
     double* Xcur = cur ? X2 : X;

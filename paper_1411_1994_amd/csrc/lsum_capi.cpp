@@ -732,6 +732,10 @@ int lsum_set_option(lsum_ctx x, int key, double value) {
             if (!(value == 0 || value == 1)) return fail(LSUM_E_INVALID, "autotune option must be 0 or 1");
             c.tuner.enable(value == 1);
             return LSUM_OK;
+        case LSUM_OPT_JACOBI_SKIP:
+            if (!(value == 0 || value == 1)) return fail(LSUM_E_INVALID, "Jacobi skip option must be 0 or 1");
+            c.jacobi_skip.store((int)value);
+            return LSUM_OK;
         case LSUM_OPT_JACOBI_BLOCK:
             if (!(value == 8 || value == 16)) return fail(LSUM_E_INVALID, "Jacobi block must be 8 or 16 columns");
             c.jacobi_block.store((int)value);

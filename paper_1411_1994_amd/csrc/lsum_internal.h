@@ -353,6 +353,9 @@ struct JacobiRun {
     int block = 8;                 // columns per block: 8, or 16 (pairs of 32 rows, round by round)
                                    // (contexts default to 16; this struct's default serves direct callers)
     int persistent = 0;            // 1: 16-wave pair groups, 2: 4-wave pair groups
+    // 16-column blocks: rotations whose relative coupling is at most skip_rel * tol are not
+    // applied in the pair solve (0: every rotation above the rounding floor)
+    double skip_rel = 0.0;
     double wait_us = 2e4;
     // workgroups of persistent sweeps running on the device (shared by every SVD of a context):
     // a sweep runs persistently only while the total stays within 3/4 of what the device holds

@@ -146,6 +146,7 @@ struct Context {
     std::atomic<int> jacobi_max_sweeps{40};   // sweeps before a side-matrix SVD fails (LSUM_E_NOCONV)
     std::atomic<int> graphs{0};               // round-by-round Jacobi sweeps captured in HIP graphs
     std::atomic<int> jacobi_block{16};        // Jacobi columns per block (16, or 8 for the persistent ways)
+    std::atomic<int> jacobi_skip{1};          // 16-column pair solves skip rotations below tol / 10
     std::atomic<int> persistent{0};           // Jacobi sweeps as one persistent launch each
     std::atomic<long long> jacobi_wait_us{20000};    // bound on a persistent sweep's waits
     std::atomic<int> persistent_wgs{0};       // workgroups of persistent sweeps now on the device
@@ -180,6 +181,7 @@ inline JacobiRun jacobi_run(Context* c) {
     JacobiRun r;
     r.graphs = c->graphs.load();
     r.block = c->jacobi_block.load();
+    r.skip_rel = c->jacobi_skip.load() ? 0.1 : 0.0;
     r.persistent = c->persistent.load();
     r.wait_us = (double)c->jacobi_wait_us.load();
     r.wg_in_use = &c->persistent_wgs;
