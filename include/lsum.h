@@ -257,7 +257,8 @@ const char* lsum_last_error(void);
  * FP64 products with unit-stride operands and at least 2^24 multiply-adds (the range basis,
  * the singular vectors, FP64 projections and core GEMMs, lsum_contract) run on the ROCm BLAS
  * library's DGEMM with atomics disabled (results independent of concurrent work); 0: every
- * product on this library's own MFMA kernels. */
+ * product on this library's own MFMA kernels.  FP32 products always run on the library's own
+ * kernel (FP32 partial sums of 32 terms added in FP64). */
 #define LSUM_OPT_GEMM_LIBRARY 11
 /* LSUM_OPT_JACOBI_BLOCK (default 16; or 8): columns per Jacobi block.  Blocks of 16 (pair
  * problems of 32 columns, solved by four waves) halve the rounds of a sweep; such sweeps run
@@ -339,7 +340,8 @@ int lsum_jacobi_svd(lsum_ctx ctx, void* stream, int D, int N, double* A_dev, int
  * B(k,n) + beta * C(m,n) with A(m,k) = A_dev[m*sam + k*sak], B(k,n) = B_dev[k*sbk + n*sbn],
  * C(m,n) = C_dev[m*scm + n*scn] (element strides).  prec: LSUM_FP64 (double operands, FP64
  * MFMA), LSUM_FP32 (float operands, FP32 MFMA) or LSUM_BF16X3 (float operands split into two
- * bfloat16 parts, three BF16 MFMA products, FP32 accumulation).  Synchronous. */
+ * bfloat16 parts, three BF16 MFMA products, FP32 accumulation).  Large unit-stride FP64
+ * products go to the ROCm BLAS library (LSUM_OPT_GEMM_LIBRARY).  Synchronous. */
 int lsum_contract(lsum_ctx ctx, void* stream, int prec, int m, int n, int k, const void* A_dev,
                   long sam, long sak, const void* B_dev, long sbk, long sbn, void* C_dev, long scm,
                   long scn, double alpha, double beta);

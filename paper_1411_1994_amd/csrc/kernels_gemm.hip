@@ -650,7 +650,7 @@ inline unsigned cdiv(long a, long b) { return (unsigned)((a + b - 1) / b); }
 
 void launch_gemm(hipStream_t st, GemmPrec prec, const GemmArgs& a) {
     if (a.m <= 0 || a.n <= 0 || a.batch <= 0) return;
-    if (prec == GEMM_F64 && blas_dgemm(st, a)) return;
+    if (blas_gemm(st, prec, a)) return;
     dim3 grid(cdiv(a.n, GBN), cdiv(a.m, GBM), a.batch);
     switch (prec) {
         case GEMM_F64: hipLaunchKernelGGL(k_gemm<GEMM_F64>, grid, dim3(256), 0, st, a); break;

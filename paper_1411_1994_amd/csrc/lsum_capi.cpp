@@ -583,7 +583,7 @@ int lsum_get_stats(lsum_req r, char* buf, size_t len) {
           << "],\"axis_src\":[" << q.axis_src[0] << "," << q.axis_src[1] << "," << q.axis_src[2]
           << "],\"range_k\":[" << q.range_k[0] << "," << q.range_k[1] << "," << q.range_k[2]
           << "],\"range_res\":[" << q.range_res[0] << "," << q.range_res[1] << "," << q.range_res[2]
-          << "],\"norm_A\":" << q.norm_A
+          << "],\"core_mode\":" << q.core_mode << ",\"norm_A\":" << q.norm_A
           << ",\"norm_xi\":" << q.norm_xi << ",\"bound\":" << q.bound << ",\"probe_err\":" << q.probe_err
           << ",\"n_probe\":" << q.n_probe << ",\"batch\":" << q.batch_size
           << ",\"als_skipped\":" << q.als_skipped << ",\"jacobi_persistent\":[" << q.jacobi_persistent[0] << ","

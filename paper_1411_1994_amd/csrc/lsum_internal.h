@@ -282,10 +282,11 @@ struct GemmArgs {
 };
 enum GemmPrec { GEMM_F64 = 0, GEMM_F32 = 1, GEMM_BF16X3 = 2 };
 void launch_gemm(hipStream_t st, GemmPrec prec, const GemmArgs& a);
-// Plain FP64 products (batch 1, unit-stride operands, at least 2^24 multiply-adds) through the
-// ROCm BLAS library's DGEMM, on st; false (nothing launched) for anything else.  Process-wide
+// Plain FP64 products (unit-stride operands, at least 2^24 multiply-adds in all; a batch at
+// fixed strides) through the ROCm BLAS library's DGEMM (strided batched for a batch), on st;
+// false (nothing launched) for anything else (FP32 and split-BF16x3 included).  Process-wide
 // switch: set_gemm_library.
-bool blas_dgemm(hipStream_t st, const GemmArgs& a);
+bool blas_gemm(hipStream_t st, GemmPrec prec, const GemmArgs& a);
 void set_gemm_library(bool on);
 bool gemm_library();
 // FP64 GEMM (batch 1) with the reduction split into about `split` slices of a multiple of the

@@ -43,7 +43,7 @@ static GemmPrec gemm_prec(int precision) {
 // back to the pool).
 int gemm_auto(Context* c, hipStream_t st, GemmPrec prec, const GemmArgs& a) {
     const long tiles = (long)((a.n + 63) / 64) * ((a.m + 127) / 128) * a.batch;
-    if (prec == GEMM_F64 && blas_dgemm(st, a)) return LSUM_OK;
+    if (blas_gemm(st, prec, a)) return LSUM_OK;
     if (prec != GEMM_F64 || a.batch != 1 || tiles >= 64 || a.k < 2048) {
         launch_gemm(st, prec, a);
         return LSUM_OK;
@@ -712,59 +712,94 @@ static int run_tucker(Request* q, hipStream_t st, const hipStream_t* aux, StageT
 
     // (7) core mu = sum_nu xi_nu y1 (x) y2 (x) y3 (eq. C-core), unnormalised columns: xi = scale;
     // term tables nu = g R + q -> projection rows src_l(g) R + q and the group scale.  When the
-    // terms share mode-3 columns (defects on common lattice planes: D3 <= K / 2), the terms of
-    // each column are summed first, T[j] = sum_{nu: src_3 = j} xi y1 (x) y2, and the core is the
-    // GEMM T x_3 Y3 over the D3 columns: 2 r1 r2 (K + D3 r3) flops instead of 2 r1 r2 r3 K.
+    // terms share the columns of a mode m (defects on common lattice planes: D_m <= K / 2), the
+    // terms of each such column j are summed first over the other two modes (u, v),
+    // T[j] = sum_{nu: src_m = j} xi y_u (x) y_v, and the core is the product of T with Y_m over
+    // the D_m columns: 2 r_u r_v (K + D_m r_m) flops instead of 2 r1 r2 r3 K.  The mode with the
+    // fewest flops is taken (mode 2 only when it saves at least 5 %: its product is a batch of
+    // r1 GEMMs rather than one).
     const long K = (long)ng * P.R;
-    const int D3 = P.D[2];
-    const bool grouped = 2L * D3 <= K;
-    const double r12 = (double)q->r[0] * q->r[1];
-    tm.begin("core", 0, grouped ? 2.0 * r12 * ((double)K + (double)D3 * q->r[2]) : 2.0 * r12 * q->r[2] * (double)K);
-    if (grouped) {
-        std::vector<int32_t> off(D3 + 1, 0), i1(K), i2(K);
+    const int r1 = q->r[0], r2 = q->r[1], r3 = q->r[2];
+    int gm = -1;
+    double gflops = 2.0 * r1 * (double)r2 * r3 * (double)K;
+    {
+        double best[3];
+        for (int m = 0; m < 3; ++m) {
+            const double ru = q->r[m == 0 ? 1 : 0], rv = q->r[m == 2 ? 1 : 2];
+            best[m] = 2L * P.D[m] <= K ? 2.0 * ru * rv * ((double)K + (double)P.D[m] * q->r[m]) : -1.0;
+        }
+        for (int m : {2, 0})
+            if (best[m] >= 0 && (gm < 0 || best[m] < gflops)) { gm = m; gflops = best[m]; }
+        if (best[1] >= 0 && (gm < 0 ? best[1] < gflops : best[1] < 0.95 * gflops)) { gm = 1; gflops = best[1]; }
+    }
+    q->core_mode = gm;
+    tm.begin("core", 0, gflops);
+    if (gm >= 0) {
+        // the grouping mode m and the two others u < v
+        const int m = gm, u = m == 0 ? 1 : 0, v = m == 2 ? 1 : 2;
+        const int Dm = P.D[m], ru = q->r[u], rv = q->r[v];
+        std::vector<int32_t> off(Dm + 1, 0), iu(K), iv(K);
         std::vector<double> scv(K);
         for (int g = 0; g < ng; ++g)
-            for (int k = 0; k < P.R; ++k) ++off[P.g_src[2][g] * P.R + k + 1];
-        for (int j = 0; j < D3; ++j) off[j + 1] += off[j];
+            for (int k = 0; k < P.R; ++k) ++off[P.g_src[m][g] * P.R + k + 1];
+        for (int j = 0; j < Dm; ++j) off[j + 1] += off[j];
         std::vector<int32_t> pos(off.begin(), off.end() - 1);
         for (int g = 0; g < ng; ++g)
             for (int k = 0; k < P.R; ++k) {
-                const int t = pos[P.g_src[2][g] * P.R + k]++;
-                i1[t] = P.g_src[0][g] * P.R + k;
-                i2[t] = P.g_src[1][g] * P.R + k;
+                const int t = pos[P.g_src[m][g] * P.R + k]++;
+                iu[t] = P.g_src[u][g] * P.R + k;
+                iv[t] = P.g_src[v][g] * P.R + k;
                 scv[t] = P.g_scale[g];
             }
-        DevBuf off_d, i1_d, i2_d, sc_d;
-        if ((rc = off_d.get(c->pool, off.size() * 4)) || (rc = i1_d.get(c->pool, (size_t)K * 4)) ||
-            (rc = i2_d.get(c->pool, (size_t)K * 4)) || (rc = sc_d.get(c->pool, (size_t)K * 8)))
+        DevBuf off_d, iu_d, iv_d, sc_d;
+        if ((rc = off_d.get(c->pool, off.size() * 4)) || (rc = iu_d.get(c->pool, (size_t)K * 4)) ||
+            (rc = iv_d.get(c->pool, (size_t)K * 4)) || (rc = sc_d.get(c->pool, (size_t)K * 8)))
             return rc;
         LSUM_HIP(hipMemcpyAsync(off_d.p, off.data(), off.size() * 4, hipMemcpyHostToDevice, st));
-        LSUM_HIP(hipMemcpyAsync(i1_d.p, i1.data(), (size_t)K * 4, hipMemcpyHostToDevice, st));
-        LSUM_HIP(hipMemcpyAsync(i2_d.p, i2.data(), (size_t)K * 4, hipMemcpyHostToDevice, st));
+        LSUM_HIP(hipMemcpyAsync(iu_d.p, iu.data(), (size_t)K * 4, hipMemcpyHostToDevice, st));
+        LSUM_HIP(hipMemcpyAsync(iv_d.p, iv.data(), (size_t)K * 4, hipMemcpyHostToDevice, st));
         LSUM_HIP(hipMemcpyAsync(sc_d.p, scv.data(), (size_t)K * 8, hipMemcpyHostToDevice, st));
-        const int r1 = q->r[0], r2 = q->r[1], r3 = q->r[2];
         const long plane = (long)r1 * r2 * r3;
         if ((rc = q->core.get(c->pool, (size_t)plane * es))) return rc;
-        // T in chunks of rows a (at most 2 GiB each, every column j up to the launch limit): each
-        // chunk's GEMM runs over all D3 columns and writes its rows of the core once (chunks of
-        // columns instead re-read and re-wrote the whole core for every chunk)
-        const long per_a = (long)r2 * D3 * (long)es;
-        const int a_chunk = (int)std::max<long>(1, std::min<long>((long)r1, (2L << 30) / per_a));
-        const int j_chunk = std::min(D3, 65535);
+        // T in chunks of mode-u rows x (at most 2 GiB each, every column j up to the launch
+        // limit), laid out T[j][x - x0][y]: each chunk's product runs over all D_m columns and
+        // writes its part of the core once (chunks of columns instead re-read and re-wrote the
+        // whole core for every chunk)
+        const long per_x = (long)rv * Dm * (long)es;
+        const int x_chunk = (int)std::max<long>(1, std::min<long>((long)ru, (2L << 30) / per_x));
+        const int j_chunk = std::min(Dm, 65535);
         DevBuf Tb;
-        if ((rc = Tb.get(c->pool, (size_t)a_chunk * r2 * (size_t)j_chunk * es))) return rc;
-        for (int a0 = 0; a0 < r1; a0 += a_chunk) {
-            const int na = std::min(a_chunk, r1 - a0);
-            for (int j0 = 0; j0 < D3; j0 += j_chunk) {
-                const int nj = std::min(j_chunk, D3 - j0);
-                launch_core_groups(st, (int)es, r1, r2, a0, na, j0, nj, off_d.as<int32_t>(), i1_d.as<int32_t>(),
-                                   i2_d.as<int32_t>(), sc_d.as<double>(), Y[0].p, ldy[0], Y[1].p, ldy[1], Tb.p);
+        if ((rc = Tb.get(c->pool, (size_t)x_chunk * rv * (size_t)j_chunk * es))) return rc;
+        for (int x0 = 0; x0 < ru; x0 += x_chunk) {
+            const int nx = std::min(x_chunk, ru - x0);
+            for (int j0 = 0; j0 < Dm; j0 += j_chunk) {
+                const int nj = std::min(j_chunk, Dm - j0);
+                launch_core_groups(st, (int)es, ru, rv, x0, nx, j0, nj, off_d.as<int32_t>(), iu_d.as<int32_t>(),
+                                   iv_d.as<int32_t>(), sc_d.as<double>(), Y[u].p, ldy[u], Y[v].p, ldy[v], Tb.p);
+                const char* Ym = (const char*)Y[m].p + (size_t)j0 * ldy[m] * es;   // Y_m[j][idx_m]
                 GemmArgs a{};
-                a.m = na * r2; a.n = r3; a.k = nj;
-                a.A = Tb.p; a.sam = 1; a.sak = (long)na * r2;
-                a.B = (const char*)Y[2].p + (size_t)j0 * ldy[2] * es; a.sbk = ldy[2]; a.sbn = 1;
-                a.C = (char*)q->core.p + (size_t)a0 * r2 * r3 * es; a.scm = r3; a.scn = 1;
                 a.alpha = 1.0; a.beta = j0 == 0 ? 0.0 : 1.0; a.batch = 1;
+                if (m == 2) {
+                    // core[(x, y)][c] = sum_j T[j][(x, y)] Y3[j][c]: rows x0.. of the core
+                    a.m = nx * r2; a.n = r3; a.k = nj;
+                    a.A = Tb.p; a.sam = 1; a.sak = (long)nx * r2;
+                    a.B = Ym; a.sbk = ldy[2]; a.sbn = 1;
+                    a.C = (char*)q->core.p + (size_t)x0 * r2 * r3 * es; a.scm = r3; a.scn = 1;
+                } else if (m == 0) {
+                    // core[a][(x, y)] = sum_j Y1[j][a] T[j][(x, y)]: columns x0 r3.. of every row a
+                    a.m = r1; a.n = nx * r3; a.k = nj;
+                    a.A = Ym; a.sam = 1; a.sak = ldy[0];
+                    a.B = Tb.p; a.sbk = (long)nx * r3; a.sbn = 1;
+                    a.C = (char*)q->core.p + (size_t)x0 * r3 * es; a.scm = (long)r2 * r3; a.scn = 1;
+                } else {
+                    // core[x][b][y] = sum_j Y2[j][b] T[j][x][y]: one product per x (Y2 shared)
+                    a.m = r2; a.n = r3; a.k = nj;
+                    a.A = Ym; a.sam = 1; a.sak = ldy[1]; a.bA = 0;
+                    a.B = Tb.p; a.sbk = (long)nx * r3; a.sbn = 1; a.bB = r3;
+                    a.C = (char*)q->core.p + (size_t)x0 * r2 * r3 * es; a.scm = r3; a.scn = 1;
+                    a.bC = (long)r2 * r3;
+                    a.batch = nx;
+                }
                 launch_gemm(st, prec, a);
             }
         }

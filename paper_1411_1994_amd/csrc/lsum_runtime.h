@@ -228,6 +228,7 @@ struct Request {
     double norm_A = 0, norm_xi = 0, bound = 0;
     double range_res[3]{};             // residual outside the range basis per mode (0: direct)
     int range_k[3]{};                  // size of the range basis per mode (0: direct)
+    int core_mode = -1;                // mode whose shared columns grouped the core's terms (-1: none)
     std::vector<double> als_core_norm;  // ||core|| after each ALS sweep
     int als_skipped = 0;               // 1: ALS asked for but the ranks do not allow it
     double probe_err = -1.0;           // Tucker result vs the FP64 canonical sum at probe cells

@@ -89,15 +89,20 @@ def test_contract_fp64_split_reduction(ctx, gemm_lib, m, n, k, layout):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
-@pytest.mark.parametrize("m,n,k", [(16, 16, 32), (70, 33, 129), (130, 257, 700)])
-def test_contract_fp32_and_split_bf16(ctx, prec, m, n, k):
+@pytest.mark.parametrize("m,n,k", [(16, 16, 32), (70, 33, 129), (130, 257, 700), (300, 400, 301)])
+@pytest.mark.parametrize("layout", ["nn", "tn", "nt", "tt"])
+def test_contract_fp32_and_split_bf16(ctx, prec, m, n, k, layout):
     import paper_1411_1994_amd as L
     rng = np.random.default_rng(7 + m + n + k)
     A = rng.standard_normal((m, k)).astype(np.float32)
     B = rng.standard_normal((k, n)).astype(np.float32)
-    dA, dB, dC = dev(A), dev(B), dev(np.zeros((m, n), np.float32))
+    As = A if layout[0] == "n" else np.ascontiguousarray(A.T)
+    Bs = B if layout[1] == "n" else np.ascontiguousarray(B.T)
+    sam, sak = (k, 1) if layout[0] == "n" else (1, m)
+    sbk, sbn = (n, 1) if layout[1] == "n" else (1, k)
+    dA, dB, dC = dev(As), dev(Bs), dev(np.zeros((m, n), np.float32))
     P = L.FP32 if prec == "fp32" else L.BF16X3
-    ctx.contract(P, m, n, k, dA, k, 1, dB, n, 1, dC, n, 1)
+    ctx.contract(P, m, n, k, dA, sam, sak, dB, sbk, sbn, dC, n, 1)
     got = host(dC).astype(np.float64)
     ref = A.astype(np.float64) @ B.astype(np.float64)
     scale = np.abs(A).astype(np.float64) @ np.abs(B).astype(np.float64)

@@ -644,14 +644,45 @@ def test_galerkin_and_canonical_form_with_device_buffers(ctx):
     assert np.array_equal(host(xd), xi) and all(np.array_equal(host(Ud[l]), U[l]) for l in range(3))
 
 
-def test_own_fp64_gemm_kernels_match_the_library_path():
-    # the medium defected request (range bases, FP64 projections and core) with every FP64
-    # product on the library's own MFMA kernels and with the large ones on the ROCm BLAS DGEMM:
-    # the same certified ranks, bounds within rounding, and values within 1e-10 of each other
-    # and within the bound of the oracle's direct sum
+@pytest.mark.parametrize("prec", [W.FP64, W.FP32], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_grouped_core_in_each_mode_matches_direct_sum(ctx, axis, prec):
+    # vacancies and impurities on one lattice plane across `axis`: that axis has the fewest
+    # distinct defect columns (D = 2 R), so the core sums the terms sharing its columns first and
+    # contracts over them (mode 3: one product over rows of the core; mode 1: over columns; mode
+    # 2: one product per core slice); each placement against the oracle's direct sum
+    rng = np.random.default_rng(40 + axis)
+    blk = W.Block((4, 4, 4), (1.0, 1.0, 1.0), (0.1, -0.15, 0.05))
+    sites = rng.choice(16, 10, replace=False)
+    defects = []
+    for k, f in enumerate(sites):
+        s = [int(f // 4), int(f % 4)]
+        s.insert(axis, 1)
+        defects.append(W.Defect(0, tuple(s), -1.0 if k < 6 else 0.5))
+    p = W.Problem("plane", W.NEWTON, 0.0, 20, (33, 35, 31), 0.37, [blk], defects, eps=1e-6, precision=prec)
+    r = run(ctx, p)
+    st = r.stats()
+    assert st["core_mode"] == axis, st["core_mode"]
+    inf = r.info()
+    pts = np.stack([rng.integers(0, n, 200) for n in p.N], axis=1)
+    got = r.sample(cells_xyz(p, pts))
+    ref = O.brute_force_points(p, pts)
+    slack = 1e-12 if prec == W.FP64 else 1e-5
+    assert np.max(np.abs(got - ref)) <= inf.bound * (1 + 1e-9) + slack * np.max(np.abs(ref))
+    r.release()
+
+
+@pytest.mark.parametrize("prec", [W.FP64, W.FP32], ids=["fp64", "fp32"])
+def test_own_gemm_kernels_match_the_library_path(prec):
+    # the medium defected request (range bases, projections and core) with every product on the
+    # library's own MFMA kernels and with the large FP64 ones on the ROCm BLAS DGEMM (the range
+    # basis is FP64 at either precision): the same certified ranks, bounds within rounding, and
+    # values within 1e-10 (FP64) or 2e-6 (FP32) of each other and within the bound of the
+    # oracle's direct sum (FP32: plus 1e-5 of the largest value)
     require_gpu()
     import paper_1411_1994_amd as L
     p = _medium_defected(eps=1e-4)
+    p.precision = prec
     rng = np.random.default_rng(8)
     cells = np.stack([rng.integers(0, n, 24) for n in p.N], axis=1)
     out = {}
@@ -670,6 +701,8 @@ def test_own_fp64_gemm_kernels_match_the_library_path():
     assert tuple(ia.r) == tuple(ib.r)
     assert abs(ia.bound - ib.bound) <= 1e-9 * ib.bound
     scale = np.max(np.abs(vb))
-    assert np.max(np.abs(va - vb)) <= 1e-10 * scale
+    assert np.max(np.abs(va - vb)) <= (1e-10 if prec == W.FP64 else 2e-6) * scale
     ref = O.brute_force_points(p, cells)
-    assert np.max(np.abs(vb - ref)) <= ib.bound * (1 + 1e-9) + 1e-12 * np.max(np.abs(ref))
+    slack = 1e-12 if prec == W.FP64 else 1e-5
+    for v in (va, vb):
+        assert np.max(np.abs(v - ref)) <= ib.bound * (1 + 1e-9) + slack * np.max(np.abs(ref))
