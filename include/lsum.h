@@ -260,11 +260,11 @@ const char* lsum_last_error(void);
  * product on this library's own MFMA kernels.  FP32 products always run on the library's own
  * kernel (FP32 partial sums of 32 terms added in FP64). */
 #define LSUM_OPT_GEMM_LIBRARY 11
-/* LSUM_OPT_JACOBI_BLOCK (default 16; or 8): columns per Jacobi block.  Blocks of 16 (pair
- * problems of 32 columns, solved by four waves) halve the rounds of a sweep; such sweeps run
- * round by round (directly or from graphs).  The persistent ways
- * (LSUM_OPT_JACOBI_PERSISTENT) need blocks of 8.  Both widths give an SVD to the same
- * tolerance and the same certificate, not the same bits. */
+/* LSUM_OPT_JACOBI_BLOCK (default 16; or 8, 32): columns per Jacobi block.  Blocks of 16 (pair
+ * problems of 32 columns, solved by four waves) halve the rounds of a sweep, blocks of 32 (pair
+ * problems of 64 columns) halve them again; such sweeps run round by round (directly or from
+ * graphs).  The persistent ways (LSUM_OPT_JACOBI_PERSISTENT) need blocks of 8.  Every width
+ * gives an SVD to the same tolerance and the same certificate, not the same bits. */
 #define LSUM_OPT_JACOBI_BLOCK 12
 /* LSUM_OPT_JACOBI_SKIP (default 1; or 0): with 16-column blocks, the pair solve leaves out
  * rotations whose relative coupling |g_ab| / sqrt(g_aa g_bb) is at most a tenth of the sweep

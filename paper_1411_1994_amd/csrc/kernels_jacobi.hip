@@ -517,6 +517,274 @@ __global__ void __launch_bounds__(256) k_pair_rotate32(double* const* __restrict
     }
 }
 
+// ---- 32-column blocks: pairs of 64 rows, a quarter of the rounds of 8-column blocks ----------
+// The three launches of a round on blocks of 32 columns: the 64 x 64 pair Gram (ten 16 x 16
+// MFMA tiles per chunk, the other six their transposes), the 64 x 64 pair solve by four waves,
+// and the rotation of the pair's 64 rows.  Every round still reads and writes each row once, so
+// halving the rounds of a sweep halves the bytes a sweep moves.
+
+__device__ __forceinline__ int pair_row64(int I, int J, int k) { return k < 32 ? I * 32 + k : J * 32 + (k - 32); }
+
+// 1. Gram partials: part[(pair * nchunk + chunk) * 4096 + a*64 + b].  Each wave multiplies its
+// quarter of the chunk for all ten tiles (row tiles ti <= tj); the quarters are then added in
+// wave order ((w0 + w1) + w2) + w3 one tile at a time through LDS.
+__global__ void __launch_bounds__(256) k_pair_gram64(double* const* __restrict__ xp, int ldx, int n_gram, int nblk,
+                                                     int round, int nchunk, double* __restrict__ part) {
+    __shared__ double Gp[4][16][17];
+    const double* __restrict__ X = xp[0];
+    const int chunk = blockIdx.x, pair = blockIdx.y;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int r = lane & 15, kg = lane >> 4;
+    int I, J;
+    pair_of(nblk, round, pair, &I, &J);
+    const int c0 = chunk * CW + wave * (CW / 4);
+    double x[4][16];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const double* __restrict__ xr = X + (size_t)pair_row64(I, J, 16 * t + r) * ldx;
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+            const int c = c0 + 4 * s + kg;
+            x[t][s] = c < n_gram ? xr[c] : 0.0;
+        }
+    }
+    d4 acc[10];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) acc[k] = d4{0, 0, 0, 0};
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+        int k = 0;
+#pragma unroll
+        for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+            for (int tj = ti; tj < 4; ++tj, ++k)
+                acc[k] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[ti][s], x[tj][s], acc[k], 0, 0, 0);
+    }
+    double* __restrict__ out = part + ((size_t)pair * nchunk + chunk) * 4096;
+    int k = 0;
+#pragma unroll
+    for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+        for (int tj = ti; tj < 4; ++tj, ++k) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) Gp[wave][kg + 4 * v][r] = acc[k][v];   // FP64 MFMA result layout
+            __syncthreads();
+            {
+                const int a = tid >> 4, b = tid & 15;
+                const double g = ((Gp[0][a][b] + Gp[1][a][b]) + Gp[2][a][b]) + Gp[3][a][b];
+                out[(16 * ti + a) * 64 + 16 * tj + b] = g;
+                if (ti != tj) out[(16 * tj + b) * 64 + 16 * ti + a] = g;
+            }
+            __syncthreads();
+        }
+}
+
+// Round-robin pairing of 64 columns for the 63 steps of an inner sweep: step t pairs (63, t)
+// and ((t + i) % 63, (t - i + 63) % 63) for i = 1..31.
+__device__ __forceinline__ int inner_p64(int t, int i) { return i == 0 ? 63 : (t + i >= 63 ? t + i - 63 : t + i); }
+__device__ __forceinline__ int inner_q64(int t, int i) { return i == 0 ? t : (t - i < 0 ? t - i + 63 : t - i); }
+
+// The 64 x 64 pair problem solved by the 256 threads of a workgroup, as solve_pair32 with four
+// 2 x 2 blocks per thread: thread (i0, j0) = (tid / 16, tid % 16) owns the blocks
+// {p_bi, q_bi} x {p_bj, q_bj} for bi in {i0, i0 + 16}, bj in {j0, j0 + 16} of G and of Q.  Each
+// lane computes the rotations of pairs j0 and j0 + 16; those of i0 and i0 + 16 are read from
+// lane i0 of the same wavefront (i0 = 4 wave + lane / 16 < 16).  Rotations whose squared
+// relative coupling is at most skip2 are not applied, and a step with none left is skipped whole
+// (every wavefront computes the same 32 rotations from the same entries).
+__device__ bool solve_pair64(int tid, double (*G)[64][65], double (*Q)[65], int* cur_out, double tol, double irr2,
+                             double keep2, double skip2, int max_inner, unsigned long long* __restrict__ stat,
+                             double* red) {
+    const int lane = tid & 63, wave = tid >> 6;
+    double off = 0.0, offk = 0.0;
+    for (int e = tid; e < 4096; e += 256) {
+        const int a = e >> 6, b = e & 63;
+        if (a < b) {
+            const double gaa = G[0][a][a], gbb = G[0][b][b], gab = G[0][a][b];
+            if (coupled(gaa, gbb, gab, irr2)) {
+                const double cab = fabs(gab) * __builtin_amdgcn_rsq(gaa * gbb);
+                off = fmax(off, cab);
+                if (gaa > keep2 && gbb > keep2) offk = fmax(offk, cab);
+            }
+        }
+    }
+    for (int m = 32; m > 0; m >>= 1) {
+        off = fmax(off, __shfl_xor(off, m));
+        offk = fmax(offk, __shfl_xor(offk, m));
+    }
+    if (lane == 0) {
+        red[wave] = off;
+        red[4 + wave] = offk;
+    }
+    __syncthreads();
+    off = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    offk = fmax(fmax(red[4], red[5]), fmax(red[6], red[7]));
+    if (tid == 0) {
+        unsigned long long bits;
+        std::memcpy(&bits, &off, sizeof(bits));
+        atomicMax(stat, bits);   // non-negative doubles order like their bit patterns
+        std::memcpy(&bits, &offk, sizeof(bits));
+        atomicMax(stat + 4, bits);
+    }
+    *cur_out = 0;
+    __syncthreads();   // red is reused below
+    if (!(off > tol)) return false;
+    const int i0 = tid >> 4, j0 = tid & 15;
+    int cur = 0;
+    double prev = 2.0;
+    int nsw = 0, nrun = 0;
+    for (int sw = 0; sw < max_inner; ++sw) {
+        nsw = sw + 1;
+        double mx = 0.0;
+        for (int step = 0; step < 63; ++step) {
+            const double (*Gc)[65] = G[cur];
+            int pj[2], qj[2];
+            double cj[2], sj[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                pj[h] = inner_p64(step, j0 + 16 * h);
+                qj[h] = inner_q64(step, j0 + 16 * h);
+                double rj;
+                rotation(Gc[pj[h]][pj[h]], Gc[qj[h]][qj[h]], Gc[pj[h]][qj[h]], irr2, &cj[h], &sj[h], &rj, skip2);
+                mx = fmax(mx, rj);
+            }
+            if (__ballot(sj[0] != 0.0 || sj[1] != 0.0) == 0ull) continue;   // no rotation of this step is applied
+            ++nrun;
+            double (*Gn)[65] = G[cur ^ 1];
+#pragma unroll
+            for (int hi = 0; hi < 2; ++hi) {
+                const int bi = i0 + 16 * hi;
+                const int pi = inner_p64(step, bi), qi = inner_q64(step, bi);
+                // pair bi's rotation: lane i0 computed pairs i0 (h = 0) and i0 + 16 (h = 1)
+                const double ci = __shfl(cj[hi], i0), si = __shfl(sj[hi], i0);
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const double g00 = Gc[pi][pj[h]], g01 = Gc[pi][qj[h]], g10 = Gc[qi][pj[h]], g11 = Gc[qi][qj[h]];
+                    const double q00 = Q[pi][pj[h]], q01 = Q[pi][qj[h]], q10 = Q[qi][pj[h]], q11 = Q[qi][qj[h]];
+                    const double c = cj[h], s = sj[h];
+                    const double h00 = ci * g00 - si * g10, h01 = ci * g01 - si * g11;
+                    const double h10 = si * g00 + ci * g10, h11 = si * g01 + ci * g11;
+                    Gn[pi][pj[h]] = c * h00 - s * h01;
+                    Gn[pi][qj[h]] = s * h00 + c * h01;
+                    Gn[qi][pj[h]] = c * h10 - s * h11;
+                    Gn[qi][qj[h]] = s * h10 + c * h11;
+                    Q[pi][pj[h]] = c * q00 - s * q01;
+                    Q[pi][qj[h]] = s * q00 + c * q01;
+                    Q[qi][pj[h]] = c * q10 - s * q11;
+                    Q[qi][qj[h]] = s * q10 + c * q11;
+                }
+            }
+            __syncthreads();
+            cur ^= 1;
+        }
+        for (int m = 32; m > 0; m >>= 1) mx = fmax(mx, __shfl_xor(mx, m));
+        if (lane == 0) red[wave] = mx;
+        __syncthreads();
+        mx = sqrt(fmax(fmax(red[0], red[1]), fmax(red[2], red[3])));
+        __syncthreads();   // red is reused
+        if (mx <= 1e-16) break;
+        if (sw >= 2 && mx > 0.9 * prev) break;
+        prev = mx;
+    }
+    if (tid == 0) {   // inner sweep statistics: total, maximum, solved pairs; steps applied, steps visited
+        atomicAdd(stat + 1, (unsigned long long)nsw);
+        atomicMax(stat + 2, (unsigned long long)nsw);
+        atomicAdd(stat + 3, 1ull);
+        atomicAdd(stat + 5, (unsigned long long)nrun);
+        atomicAdd(stat + 6, (unsigned long long)(63 * nsw));
+    }
+    *cur_out = cur;
+    return true;
+}
+
+// 2. per pair: the chunk partials summed in chunk order (sixteen entries per thread, four chunks
+// of them in flight at a time), then solved
+__global__ void __launch_bounds__(256) k_pair_eig64(int nchunk, const double* __restrict__ part, double tol,
+                                                    double irr2, double skip2, const double* __restrict__ keep2p,
+                                                    int max_inner, double* __restrict__ Qout, int* __restrict__ active,
+                                                    unsigned long long* __restrict__ stat) {
+    __shared__ double G[2][64][65];
+    __shared__ double Q[64][65];
+    __shared__ double red[8];
+    const int pair = blockIdx.x, tid = threadIdx.x;
+    const double* pp = part + (size_t)pair * nchunk * 4096 + tid;
+    double s[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) s[u] = 0.0;
+    for (int c = 0; c < nchunk; c += 4) {
+        double v[4][16];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int u = 0; u < 16; ++u) v[k][u] = pp[(size_t)min(c + k, nchunk - 1) * 4096 + 256 * u];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int u = 0; u < 16; ++u) s[u] += c + k < nchunk ? v[k][u] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        const int e = tid + 256 * u;
+        G[0][e >> 6][e & 63] = s[u];
+        Q[e >> 6][e & 63] = ((e >> 6) == (e & 63)) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    int cur = 0;
+    const bool act = solve_pair64(tid, G, Q, &cur, tol, irr2, *keep2p, skip2, max_inner, stat, red);
+    if (tid == 0) active[pair] = act ? 1 : 0;
+    if (!act) return;
+    for (int e = tid; e < 4096; e += 256) Qout[(size_t)pair * 4096 + e] = Q[e >> 6][e & 63];
+}
+
+// 3. X_pair <- Q^T X_pair over one chunk: each wave 64 cells (two passes of 2 tiles of 16) x 64 rows
+__global__ void __launch_bounds__(256) k_pair_rotate64(double* const* __restrict__ xp, int ldx, int nblk, int round,
+                                                       const double* __restrict__ Qin,
+                                                       const int* __restrict__ active) {
+    const int chunk = blockIdx.x, pair = blockIdx.y;
+    if (!active[pair]) return;
+    double* __restrict__ X = xp[0];
+    __shared__ double Q[64][65];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int r = lane & 15, kg = lane >> 4;
+    for (int e = tid; e < 4096; e += 256) Q[e >> 6][e & 63] = Qin[(size_t)pair * 4096 + e];
+    __syncthreads();
+    int I, J;
+    pair_of(nblk, round, pair, &I, &J);
+#pragma unroll 1
+    for (int half = 0; half < 2; ++half) {
+        const int c0 = chunk * CW + wave * (CW / 4) + 32 * half;
+        double b[2][16];
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int k0 = 0; k0 < 16; ++k0) {
+                const int col = c0 + 16 * t + r;
+                b[t][k0] = col < ldx ? X[(size_t)pair_row64(I, J, 4 * k0 + kg) * ldx + col] : 0.0;
+            }
+        d4 acc[2][4];
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int rt = 0; rt < 4; ++rt) {
+                acc[t][rt] = d4{0, 0, 0, 0};
+#pragma unroll
+                for (int k0 = 0; k0 < 16; ++k0)
+                    acc[t][rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(Q[4 * k0 + kg][16 * rt + r], b[t][k0],
+                                                                       acc[t][rt], 0, 0, 0);
+            }
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            const int col = c0 + 16 * t + r;
+            if (col < ldx) {
+#pragma unroll
+                for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        X[(size_t)pair_row64(I, J, 16 * rt + kg + 4 * v) * ldx + col] = acc[t][rt][v];
+            }
+        }
+    }
+}
+
 // A whole sweep in one launch: workgroup p owns pair slot p of every round of the round robin.
 // A round on blocks (I, J) starts once both blocks have finished the previous round (their
 // version counters, set with release order after the rows are written; read with acquire
@@ -927,7 +1195,8 @@ struct JacobiLayout {
     size_t off_x2, off_nrm, off_perm, off_stat, off_part, off_q, off_act, off_ptr, off_ver, total;
 };
 
-// bw: columns per block (8, or 16 for pairs of 32 rows); rows are padded to whole block pairs
+// bw: columns per block (8, 16 for pairs of 32 rows, 32 for pairs of 64); rows are padded to whole
+// block pairs
 JacobiLayout layout(int D, int N, int n_gram, int bw = 8) {
     JacobiLayout L{};
     L.Dp = std::max(2 * bw, (D + 2 * bw - 1) / (2 * bw) * (2 * bw));
@@ -954,7 +1223,9 @@ JacobiLayout layout(int D, int N, int n_gram, int bw = 8) {
 
 }  // namespace
 
-size_t jacobi_work_bytes(int D, int N) { return std::max(layout(D, N, N, 8).total, layout(D, N, N, 16).total); }
+size_t jacobi_work_bytes(int D, int N) {
+    return std::max(std::max(layout(D, N, N, 8).total, layout(D, N, N, 16).total), layout(D, N, N, 32).total);
+}
 
 void launch_pchol(hipStream_t st, int n, const double* A, double tau2, int pivot, double* Rt, int* perm, int* keep_dev) {
     hipLaunchKernelGGL(k_pchol, dim3(1), dim3(PC_THREADS), 0, st, n, A, tau2, pivot, Rt, perm, keep_dev);
@@ -1063,10 +1334,10 @@ int jacobi_svd(hipStream_t st, int D, int N, double* A, int lda, double tol, dou
     int persistent = run->persistent;
     if (n_gram <= 0 || n_gram > N) n_gram = N;
     if (D <= 0 || N <= 0) return fail(LSUM_E_INVALID, "empty side matrix");
-    // 16-column blocks (pairs of 32 rows) halve the rounds per sweep; they run round by round
-    // (the persistent ways are written for 8-column blocks)
-    const int bw = run->block == 16 ? 16 : 8;
-    if (bw == 16) persistent = 0;
+    // 16- and 32-column blocks (pairs of 32 or 64 rows) halve or quarter the rounds per sweep;
+    // they run round by round (the persistent ways are written for 8-column blocks)
+    const int bw = run->block == 32 ? 32 : (run->block == 16 ? 16 : 8);
+    if (bw != 8) persistent = 0;
     const JacobiLayout L = layout(D, N, n_gram, bw);
     if (work_bytes < L.total) return fail(LSUM_E_INVALID, "Jacobi workspace too small");
     char* base = (char*)work_dev;
@@ -1127,7 +1398,7 @@ int jacobi_svd(hipStream_t st, int D, int N, double* A, int lda, double tol, dou
         // more outer sweep (cfg3 side matrices: SVD 147 -> 134 ms); with few pairs and long rows
         // the Gram and rotation passes dominate a round, and the second inner sweep pays for
         // itself (few tens of columns of 5633-34305 cells: 30-50 % slower with one).
-        const int max_inner = npair >= 16 ? 1 : 2;
+        const int max_inner = npair >= (bw == 32 ? 8 : 16) ? 1 : 2;
         hipLaunchKernelGGL(k_permute_xp, dim3(cdiv(L.ldx, 256), L.Dp), dim3(256), 0, st, L.ldx, perm_dev, xp_dev);
         hipLaunchKernelGGL(k_swap_clear, dim3(1), dim3(64), 0, st, xp_dev, stat, ver, nblk);
         if (persistent) {
@@ -1143,6 +1414,15 @@ int jacobi_svd(hipStream_t st, int D, int N, double* A, int lda, double tol, dou
             return;
         }
         for (int round = 0; round < nblk - 1; ++round) {
+            if (bw == 32) {
+                hipLaunchKernelGGL(k_pair_gram64, dim3(L.nchunk, npair), dim3(256), 0, st, xp_dev, L.ldx, n_gram,
+                                   nblk, round, L.nchunk, part);
+                hipLaunchKernelGGL(k_pair_eig64, dim3(npair), dim3(256), 0, st, L.nchunk, part, tol, irr2, skip2,
+                                   keep2_dev, max_inner, Qd, act, stat);
+                hipLaunchKernelGGL(k_pair_rotate64, dim3(L.nchunk_all, npair), dim3(256), 0, st, xp_dev, L.ldx, nblk,
+                                   round, Qd, act);
+                continue;
+            }
             if (bw == 16) {
                 hipLaunchKernelGGL(k_pair_gram32, dim3(L.nchunk, npair), dim3(256), 0, st, xp_dev, L.ldx, n_gram,
                                    nblk, round, L.nchunk, part);
@@ -1175,10 +1455,10 @@ int jacobi_svd(hipStream_t st, int D, int N, double* A, int lda, double tol, dou
         return b;
     };
     const std::string tune_key = "jacobi/" + std::to_string(pow2(L.Dp)) + "/" + std::to_string(pow2(L.ldx)) + "/" +
-                                 std::to_string(pow2(n_gram)) + (bw == 16 ? "/b16" : "");
+                                 std::to_string(pow2(n_gram)) + (bw == 16 ? "/b16" : (bw == 32 ? "/b32" : ""));
     int tune_key_choice = run->tuner ? run->tuner->get(tune_key) : -2;
     if (tune_key_choice >= 0) {
-        persistent = bw == 16 ? 0 : (tune_key_choice == 2 ? 1 : (tune_key_choice == 3 ? 2 : 0));
+        persistent = bw != 8 ? 0 : (tune_key_choice == 2 ? 1 : (tune_key_choice == 3 ? 2 : 0));
         graphs = tune_key_choice == 1;
     }
     const PersistentCap pcap = persistent_capacity();
@@ -1228,7 +1508,7 @@ int jacobi_svd(hipStream_t st, int D, int N, double* A, int lda, double tol, dou
             LSUM_HIP(hipEventCreate(&e0));
             LSUM_HIP(hipEventCreate(&e1));
             for (int m : {3, 2, 1, 0}) {
-                if (m >= 2 && (!clock_ok || bw == 16)) continue;
+                if (m >= 2 && (!clock_ok || bw != 8)) continue;
                 LSUM_HIP(hipMemcpyAsync(xp_dev, xp_host, sizeof(xp_host), hipMemcpyHostToDevice, st));
                 persistent = m == 2 ? 1 : (m == 3 ? 2 : 0);
                 GroupTokens tk;
@@ -1256,7 +1536,7 @@ int jacobi_svd(hipStream_t st, int D, int N, double* A, int lda, double tol, dou
             (void)hipEventDestroy(e0);
             (void)hipEventDestroy(e1);
             const int ch = run->tuner->put(tune_key, ms);
-            persistent = bw == 16 ? 0 : (ch == 2 ? 1 : (ch == 3 ? 2 : 0));
+            persistent = bw != 8 ? 0 : (ch == 2 ? 1 : (ch == 3 ? 2 : 0));
             graphs = ch == 1;
             tune_key_choice = ch;
             run->tuned = 1;
@@ -1281,8 +1561,8 @@ int jacobi_svd(hipStream_t st, int D, int N, double* A, int lda, double tol, dou
         // the buffers before this sweep: it read the current one and wrote only the other
         double* before[2] = {cur ? X2 : X, cur ? X : X2};
         cur ^= 1;
-        // FP64 MFMA work of the sweep: every pair visit forms a 16 x 16 Gram over n_gram entries
-        // and (when active) rotates 16 rows of ldx entries; counted for every visit
+        // FP64 MFMA work of the sweep: every pair visit forms a 2bw x 2bw Gram over n_gram entries
+        // and (when active) rotates 2bw rows of ldx entries; counted for every visit
         run->flops += (double)(nblk / 2) * (nblk - 1) * 8.0 * bw * bw * ((double)n_gram + L.ldx);
         unsigned long long st4[7] = {0, 0, 0, 0, 0, 0, 0};
         int aborted = 0;

@@ -171,15 +171,16 @@ def test_autotuned_sweeps_equal_fixed_ones_and_decisions_persist(tmp_path):
     assert sum(tuned[n:]) == 0          # the second read the file
 
 
-def test_16_column_blocks_graphs_equal_direct_and_match_8_column_blocks():
-    # Jacobi on blocks of 16 columns: graph replay equals direct launches bit for bit; against
-    # blocks of 8 the ranks agree (or sit at a threshold within rounding), both bounds are
-    # certified, and both results are within their bound of the oracle's direct sum
+@pytest.mark.parametrize("block", [16, 32])
+def test_wide_blocks_graphs_equal_direct_and_match_8_column_blocks(block):
+    # Jacobi on blocks of 16 or 32 columns: graph replay equals direct launches bit for bit;
+    # against blocks of 8 the ranks agree (or sit at a threshold within rounding), both bounds
+    # are certified, and both results are within their bound of the oracle's direct sum
     require_gpu()
     import paper_1411_1994_amd as L
     probs = _problems()
-    b16d = _run_opts({L.OPT_JACOBI_BLOCK: 16, L.OPT_GRAPHS: 0}, probs)
-    b16g = _run_opts({L.OPT_JACOBI_BLOCK: 16, L.OPT_GRAPHS: 1}, probs)
+    b16d = _run_opts({L.OPT_JACOBI_BLOCK: block, L.OPT_GRAPHS: 0}, probs)
+    b16g = _run_opts({L.OPT_JACOBI_BLOCK: block, L.OPT_GRAPHS: 1}, probs)
     b8 = _run_opts({L.OPT_JACOBI_BLOCK: 8}, probs)
     for k, p in enumerate(probs):
         x, y, z = b16d[k], b16g[k], b8[k]

@@ -227,14 +227,16 @@ def test_jacobi_svd_known_spectrum(ctx, D, N, decay):
     _check_known_spectrum(ctx, D, N, decay)
 
 
+@pytest.mark.parametrize("block", [16, 32])
 @pytest.mark.parametrize("D,N,decay", [(16, 40, 1.0), (33, 100, 1e-12), (100, 64, 1e-6), (257, 300, 1e-14),
                                        (700, 1500, 1e-9)])
-def test_jacobi_svd_16_column_blocks_known_spectrum(D, N, decay):
-    # pairs of 32 rows (four-wave pair solves, half the rounds per sweep): the same checks
+def test_jacobi_svd_wide_blocks_known_spectrum(block, D, N, decay):
+    # pairs of 32 or 64 rows (four-wave pair solves, a half or a quarter of the rounds per sweep):
+    # the same checks
     import paper_1411_1994_amd as L
     require_gpu()
     with L.Context(0, n_slots=1) as c:
-        c.set_option(L.OPT_JACOBI_BLOCK, 16)
+        c.set_option(L.OPT_JACOBI_BLOCK, block)
         _check_known_spectrum(c, D, N, decay)
 
 
