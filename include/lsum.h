@@ -260,10 +260,12 @@ const char* lsum_last_error(void);
  * product on this library's own MFMA kernels.  FP32 products always run on the library's own
  * kernel (FP32 partial sums of 32 terms added in FP64). */
 #define LSUM_OPT_GEMM_LIBRARY 11
-/* LSUM_OPT_JACOBI_BLOCK (default 16; or 8, 32): columns per Jacobi block.  Blocks of 16 (pair
+/* LSUM_OPT_JACOBI_BLOCK (default 0; or 8, 16, 32): columns per Jacobi block.  Blocks of 16 (pair
  * problems of 32 columns, solved by four waves) halve the rounds of a sweep, blocks of 32 (pair
- * problems of 64 columns) halve them again; such sweeps run round by round (directly or from
- * graphs).  The persistent ways (LSUM_OPT_JACOBI_PERSISTENT) need blocks of 8.  Every width
+ * problems of 64 columns, eight waves) halve them again and with them the bytes a sweep moves;
+ * such sweeps run round by round (directly or from graphs).  0: 32 for side matrices of at least
+ * 512 rows (the columns the SVD rotates), 16 below (a function of the size alone, never of
+ * the load).  The persistent ways (LSUM_OPT_JACOBI_PERSISTENT) need blocks of 8.  Every width
  * gives an SVD to the same tolerance and the same certificate, not the same bits. */
 #define LSUM_OPT_JACOBI_BLOCK 12
 /* LSUM_OPT_JACOBI_SKIP (default 1; or 0): with 16-column blocks, the pair solve leaves out

@@ -584,19 +584,27 @@ __global__ void __launch_bounds__(256) k_pair_gram64(double* const* __restrict__
 __device__ __forceinline__ int inner_p64(int t, int i) { return i == 0 ? 63 : (t + i >= 63 ? t + i - 63 : t + i); }
 __device__ __forceinline__ int inner_q64(int t, int i) { return i == 0 ? t : (t - i < 0 ? t - i + 63 : t - i); }
 
-// The 64 x 64 pair problem solved by the 256 threads of a workgroup, as solve_pair32 with four
-// 2 x 2 blocks per thread: thread (i0, j0) = (tid / 16, tid % 16) owns the blocks
-// {p_bi, q_bi} x {p_bj, q_bj} for bi in {i0, i0 + 16}, bj in {j0, j0 + 16} of G and of Q.  Each
-// lane computes the rotations of pairs j0 and j0 + 16; those of i0 and i0 + 16 are read from
-// lane i0 of the same wavefront (i0 = 4 wave + lane / 16 < 16).  Rotations whose squared
-// relative coupling is at most skip2 are not applied, and a step with none left is skipped whole
-// (every wavefront computes the same 32 rotations from the same entries).
+#ifndef LSUM_EIG64_THREADS
+#define LSUM_EIG64_THREADS 512
+#endif
+constexpr int E64T = LSUM_EIG64_THREADS;   // threads of the 64 x 64 pair solve (256 or 512)
+constexpr int E64W = E64T / 64;            // its waves
+
+// The 64 x 64 pair problem solved by the E64T threads of a workgroup, as solve_pair32 with
+// 32 x 32 blocks of 2 x 2: with 512 threads, thread (i0, j) = (tid / 32, tid % 32) owns the
+// blocks {p_bi, q_bi} x {p_j, q_j} for bi in {i0, i0 + 16} of G and of Q; with 256 threads,
+// thread (i0, j0) = (tid / 16, tid % 16) owns those for bi in {i0, i0 + 16}, bj in {j0, j0 + 16}.
+// Each lane computes the rotations of its pairs bj; those of i0 and i0 + 16 are read from lanes
+// i0 and i0 + 16 of the same wavefront (which hold pairs i0 and i0 + 16).  Rotations whose
+// squared relative coupling is at most skip2 are not applied, and a step with none left is
+// skipped whole (every wavefront computes the same 32 rotations from the same entries).
 __device__ bool solve_pair64(int tid, double (*G)[64][65], double (*Q)[65], int* cur_out, double tol, double irr2,
                              double keep2, double skip2, int max_inner, unsigned long long* __restrict__ stat,
                              double* red) {
+    constexpr int NJ = E64T == 512 ? 1 : 2;   // block columns per thread
     const int lane = tid & 63, wave = tid >> 6;
     double off = 0.0, offk = 0.0;
-    for (int e = tid; e < 4096; e += 256) {
+    for (int e = tid; e < 4096; e += E64T) {
         const int a = e >> 6, b = e & 63;
         if (a < b) {
             const double gaa = G[0][a][a], gbb = G[0][b][b], gab = G[0][a][b];
@@ -613,11 +621,15 @@ __device__ bool solve_pair64(int tid, double (*G)[64][65], double (*Q)[65], int*
     }
     if (lane == 0) {
         red[wave] = off;
-        red[4 + wave] = offk;
+        red[8 + wave] = offk;
     }
     __syncthreads();
-    off = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
-    offk = fmax(fmax(red[4], red[5]), fmax(red[6], red[7]));
+    off = 0.0;
+    offk = 0.0;
+    for (int w = 0; w < E64W; ++w) {
+        off = fmax(off, red[w]);
+        offk = fmax(offk, red[8 + w]);
+    }
     if (tid == 0) {
         unsigned long long bits;
         std::memcpy(&bits, &off, sizeof(bits));
@@ -628,7 +640,8 @@ __device__ bool solve_pair64(int tid, double (*G)[64][65], double (*Q)[65], int*
     *cur_out = 0;
     __syncthreads();   // red is reused below
     if (!(off > tol)) return false;
-    const int i0 = tid >> 4, j0 = tid & 15;
+    const int i0 = NJ == 1 ? tid >> 5 : tid >> 4;
+    const int j0 = NJ == 1 ? tid & 31 : tid & 15;
     int cur = 0;
     double prev = 2.0;
     int nsw = 0, nrun = 0;
@@ -637,27 +650,31 @@ __device__ bool solve_pair64(int tid, double (*G)[64][65], double (*Q)[65], int*
         double mx = 0.0;
         for (int step = 0; step < 63; ++step) {
             const double (*Gc)[65] = G[cur];
-            int pj[2], qj[2];
-            double cj[2], sj[2];
+            int pj[NJ], qj[NJ];
+            double cj[NJ], sj[NJ];
+            bool any = false;
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
+            for (int h = 0; h < NJ; ++h) {
                 pj[h] = inner_p64(step, j0 + 16 * h);
                 qj[h] = inner_q64(step, j0 + 16 * h);
                 double rj;
                 rotation(Gc[pj[h]][pj[h]], Gc[qj[h]][qj[h]], Gc[pj[h]][qj[h]], irr2, &cj[h], &sj[h], &rj, skip2);
                 mx = fmax(mx, rj);
+                any = any || sj[h] != 0.0;
             }
-            if (__ballot(sj[0] != 0.0 || sj[1] != 0.0) == 0ull) continue;   // no rotation of this step is applied
+            if (__ballot(any) == 0ull) continue;   // no rotation of this step is applied
             ++nrun;
             double (*Gn)[65] = G[cur ^ 1];
 #pragma unroll
             for (int hi = 0; hi < 2; ++hi) {
                 const int bi = i0 + 16 * hi;
                 const int pi = inner_p64(step, bi), qi = inner_q64(step, bi);
-                // pair bi's rotation: lane i0 computed pairs i0 (h = 0) and i0 + 16 (h = 1)
-                const double ci = __shfl(cj[hi], i0), si = __shfl(sj[hi], i0);
+                // pair bi's rotation, from the lane that computed it: with one block column per
+                // thread lane bi holds pair bi; with two, lane i0 holds pairs i0 and i0 + 16
+                const double ci = NJ == 1 ? __shfl(cj[0], bi) : __shfl(cj[hi], i0);
+                const double si = NJ == 1 ? __shfl(sj[0], bi) : __shfl(sj[hi], i0);
 #pragma unroll
-                for (int h = 0; h < 2; ++h) {
+                for (int h = 0; h < NJ; ++h) {
                     const double g00 = Gc[pi][pj[h]], g01 = Gc[pi][qj[h]], g10 = Gc[qi][pj[h]], g11 = Gc[qi][qj[h]];
                     const double q00 = Q[pi][pj[h]], q01 = Q[pi][qj[h]], q10 = Q[qi][pj[h]], q11 = Q[qi][qj[h]];
                     const double c = cj[h], s = sj[h];
@@ -679,7 +696,9 @@ __device__ bool solve_pair64(int tid, double (*G)[64][65], double (*Q)[65], int*
         for (int m = 32; m > 0; m >>= 1) mx = fmax(mx, __shfl_xor(mx, m));
         if (lane == 0) red[wave] = mx;
         __syncthreads();
-        mx = sqrt(fmax(fmax(red[0], red[1]), fmax(red[2], red[3])));
+        mx = 0.0;
+        for (int w = 0; w < E64W; ++w) mx = fmax(mx, red[w]);
+        mx = sqrt(mx);
         __syncthreads();   // red is reused
         if (mx <= 1e-16) break;
         if (sw >= 2 && mx > 0.9 * prev) break;
@@ -696,34 +715,35 @@ __device__ bool solve_pair64(int tid, double (*G)[64][65], double (*Q)[65], int*
     return true;
 }
 
-// 2. per pair: the chunk partials summed in chunk order (sixteen entries per thread, four chunks
-// of them in flight at a time), then solved
-__global__ void __launch_bounds__(256) k_pair_eig64(int nchunk, const double* __restrict__ part, double tol,
-                                                    double irr2, double skip2, const double* __restrict__ keep2p,
-                                                    int max_inner, double* __restrict__ Qout, int* __restrict__ active,
-                                                    unsigned long long* __restrict__ stat) {
+// 2. per pair: the chunk partials summed in chunk order (4096 / E64T entries per thread, four
+// chunks of them in flight at a time), then solved
+__global__ void __launch_bounds__(E64T) k_pair_eig64(int nchunk, const double* __restrict__ part, double tol,
+                                                     double irr2, double skip2, const double* __restrict__ keep2p,
+                                                     int max_inner, double* __restrict__ Qout,
+                                                     int* __restrict__ active, unsigned long long* __restrict__ stat) {
+    constexpr int NE = 4096 / E64T;
     __shared__ double G[2][64][65];
     __shared__ double Q[64][65];
-    __shared__ double red[8];
+    __shared__ double red[16];
     const int pair = blockIdx.x, tid = threadIdx.x;
     const double* pp = part + (size_t)pair * nchunk * 4096 + tid;
-    double s[16];
+    double s[NE];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) s[u] = 0.0;
+    for (int u = 0; u < NE; ++u) s[u] = 0.0;
     for (int c = 0; c < nchunk; c += 4) {
-        double v[4][16];
+        double v[4][NE];
 #pragma unroll
         for (int k = 0; k < 4; ++k)
 #pragma unroll
-            for (int u = 0; u < 16; ++u) v[k][u] = pp[(size_t)min(c + k, nchunk - 1) * 4096 + 256 * u];
+            for (int u = 0; u < NE; ++u) v[k][u] = pp[(size_t)min(c + k, nchunk - 1) * 4096 + E64T * u];
 #pragma unroll
         for (int k = 0; k < 4; ++k)
 #pragma unroll
-            for (int u = 0; u < 16; ++u) s[u] += c + k < nchunk ? v[k][u] : 0.0;
+            for (int u = 0; u < NE; ++u) s[u] += c + k < nchunk ? v[k][u] : 0.0;
     }
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-        const int e = tid + 256 * u;
+    for (int u = 0; u < NE; ++u) {
+        const int e = tid + E64T * u;
         G[0][e >> 6][e & 63] = s[u];
         Q[e >> 6][e & 63] = ((e >> 6) == (e & 63)) ? 1.0 : 0.0;
     }
@@ -732,7 +752,7 @@ __global__ void __launch_bounds__(256) k_pair_eig64(int nchunk, const double* __
     const bool act = solve_pair64(tid, G, Q, &cur, tol, irr2, *keep2p, skip2, max_inner, stat, red);
     if (tid == 0) active[pair] = act ? 1 : 0;
     if (!act) return;
-    for (int e = tid; e < 4096; e += 256) Qout[(size_t)pair * 4096 + e] = Q[e >> 6][e & 63];
+    for (int e = tid; e < 4096; e += E64T) Qout[(size_t)pair * 4096 + e] = Q[e >> 6][e & 63];
 }
 
 // 3. X_pair <- Q^T X_pair over one chunk: each wave 64 cells (two passes of 2 tiles of 16) x 64 rows
@@ -1335,8 +1355,14 @@ int jacobi_svd(hipStream_t st, int D, int N, double* A, int lda, double tol, dou
     if (n_gram <= 0 || n_gram > N) n_gram = N;
     if (D <= 0 || N <= 0) return fail(LSUM_E_INVALID, "empty side matrix");
     // 16- and 32-column blocks (pairs of 32 or 64 rows) halve or quarter the rounds per sweep;
-    // they run round by round (the persistent ways are written for 8-column blocks)
-    const int bw = run->block == 32 ? 32 : (run->block == 16 ? 16 : 8);
+    // they run round by round (the persistent ways are written for 8-column blocks).  By size
+    // (block 0): a sweep reads and writes every row once per round, so 32-column blocks halve the
+    // bytes a sweep moves, which pays when several SVDs share the device; alone the 64 x 64 pair
+    // solve's latency makes them a few percent slower on large side matrices and 10-30 % slower
+    // on small ones, which keep 16-column blocks (served mix: 512 rows and up on 32-column blocks
+    // 22.8-22.9 -> 24.1 sums/s, its requests one at a time 690 -> 733 ms of SVD).
+    constexpr int kWideRows = 512;
+    const int bw = run->block == 0 ? (D >= kWideRows ? 32 : 16) : (run->block == 32 ? 32 : (run->block == 16 ? 16 : 8));
     if (bw != 8) persistent = 0;
     const JacobiLayout L = layout(D, N, n_gram, bw);
     if (work_bytes < L.total) return fail(LSUM_E_INVALID, "Jacobi workspace too small");
@@ -1417,7 +1443,7 @@ int jacobi_svd(hipStream_t st, int D, int N, double* A, int lda, double tol, dou
             if (bw == 32) {
                 hipLaunchKernelGGL(k_pair_gram64, dim3(L.nchunk, npair), dim3(256), 0, st, xp_dev, L.ldx, n_gram,
                                    nblk, round, L.nchunk, part);
-                hipLaunchKernelGGL(k_pair_eig64, dim3(npair), dim3(256), 0, st, L.nchunk, part, tol, irr2, skip2,
+                hipLaunchKernelGGL(k_pair_eig64, dim3(npair), dim3(E64T), 0, st, L.nchunk, part, tol, irr2, skip2,
                                    keep2_dev, max_inner, Qd, act, stat);
                 hipLaunchKernelGGL(k_pair_rotate64, dim3(L.nchunk_all, npair), dim3(256), 0, st, xp_dev, L.ldx, nblk,
                                    round, Qd, act);

@@ -737,8 +737,8 @@ int lsum_set_option(lsum_ctx x, int key, double value) {
             c.jacobi_skip.store((int)value);
             return LSUM_OK;
         case LSUM_OPT_JACOBI_BLOCK:
-            if (!(value == 8 || value == 16 || value == 32))
-                return fail(LSUM_E_INVALID, "Jacobi block must be 8, 16 or 32 columns");
+            if (!(value == 0 || value == 8 || value == 16 || value == 32))
+                return fail(LSUM_E_INVALID, "Jacobi block must be 0 (by size), 8, 16 or 32 columns");
             c.jacobi_block.store((int)value);
             return LSUM_OK;
         case LSUM_OPT_GEMM_LIBRARY:

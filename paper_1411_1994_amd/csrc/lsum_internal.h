@@ -351,8 +351,9 @@ void launch_cp_norm2(hipStream_t st, int R, int n_groups, const int32_t* src1, c
 // Every way adds the same terms in the same order (the same results bit for bit).
 struct JacobiRun {
     int graphs = 0;
-    int block = 8;                 // columns per block: 8, or 16 (pairs of 32 rows, round by round)
-                                   // (contexts default to 16; this struct's default serves direct callers)
+    int block = 8;                 // columns per block: 8, 16 or 32 (pairs of 32 or 64 rows, round by
+                                   // round); 0: 32 for side matrices of at least 512 rows, else 16
+                                   // (contexts default to 0; this struct's default serves direct callers)
     int persistent = 0;            // 1: 16-wave pair groups, 2: 4-wave pair groups
     // 16-column blocks: rotations whose relative coupling is at most skip_rel * tol are not
     // applied in the pair solve (0: every rotation above the rounding floor)

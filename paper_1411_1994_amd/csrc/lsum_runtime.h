@@ -145,7 +145,7 @@ struct Context {
     bool jacobi_rank_stop = true;    // Jacobi SVDs of side matrices end once the certified rank is settled
     std::atomic<int> jacobi_max_sweeps{40};   // sweeps before a side-matrix SVD fails (LSUM_E_NOCONV)
     std::atomic<int> graphs{0};               // round-by-round Jacobi sweeps captured in HIP graphs
-    std::atomic<int> jacobi_block{16};        // Jacobi columns per block (16, or 8 for the persistent ways)
+    std::atomic<int> jacobi_block{0};         // Jacobi columns per block (0: by size; 8, 16, 32)
     std::atomic<int> jacobi_skip{1};          // 16-column pair solves skip rotations below tol / 10
     std::atomic<int> persistent{0};           // Jacobi sweeps as one persistent launch each
     std::atomic<long long> jacobi_wait_us{20000};    // bound on a persistent sweep's waits
