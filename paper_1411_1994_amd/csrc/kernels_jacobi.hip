@@ -970,6 +970,48 @@ __global__ void k_swap_clear(double** __restrict__ xp, unsigned long long* __res
     for (int k = threadIdx.x; k <= n_ver; k += blockDim.x) ver[k] = 0;   // versions, then the abort flag
 }
 
+// The largest relative coupling |g_ab| / sqrt(g_aa g_bb) over the pairs a < b of the n x n Gram G
+// (row stride ldg) whose squared norms both exceed irr2 (out[0]), and over those whose squared
+// norms both exceed keep2 (out[1]), as the bit patterns of non-negative doubles (out zeroed
+// before).  The same test as the pair solves' coupling pass, on all pairs at once.
+__global__ void __launch_bounds__(256) k_gram_coupling(int n, const double* __restrict__ G, long ldg, double irr2,
+                                                       double keep2, unsigned long long* __restrict__ out) {
+    __shared__ double red[2][4];
+    const int b = blockIdx.x * 256 + threadIdx.x, a = blockIdx.y;
+    double off = 0.0, offk = 0.0;
+    if (a < b && b < n) {
+        const double gaa = G[(size_t)a * ldg + a], gbb = G[(size_t)b * ldg + b], gab = G[(size_t)a * ldg + b];
+        if (coupled(gaa, gbb, gab, irr2)) {
+            const double cab = fabs(gab) / sqrt(gaa * gbb);
+            off = cab;
+            if (gaa > keep2 && gbb > keep2) offk = cab;
+        }
+    }
+    for (int m = 32; m > 0; m >>= 1) {
+        off = fmax(off, __shfl_xor(off, m));
+        offk = fmax(offk, __shfl_xor(offk, m));
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) {
+        red[0][wave] = off;
+        red[1][wave] = offk;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        off = fmax(fmax(red[0][0], red[0][1]), fmax(red[0][2], red[0][3]));
+        offk = fmax(fmax(red[1][0], red[1][1]), fmax(red[1][2], red[1][3]));
+        unsigned long long bits;
+        std::memcpy(&bits, &off, sizeof(bits));
+        atomicMax(out, bits);
+        std::memcpy(&bits, &offk, sizeof(bits));
+        atomicMax(out + 1, bits);
+    }
+}
+
+__global__ void k_zero_u64(unsigned long long* __restrict__ p, int n) {
+    for (int k = threadIdx.x; k < n; k += blockDim.x) p[k] = 0ull;
+}
+
 __global__ void __launch_bounds__(256) k_norms_xp(int ldx, int n_gram, double* const* __restrict__ xp,
                                                   double* __restrict__ nrm) {
     __shared__ double red[256];
@@ -1642,9 +1684,36 @@ int jacobi_svd(hipStream_t st, int D, int N, double* A, int lda, double tol, dou
             const int m = r_now + std::max(16, r_now / 8);
             keep2 = m < L.Dp ? sig2[perm[m]] : 0.0;
         }
+        // A sweep whose pairs were already close to orthogonal when visited (quadratic
+        // convergence: couplings of 1e-4 .. 1e-8 measured to leave 1e-11 .. 1e-13) usually
+        // leaves every coupling below tol; the sweep that would find that out rotates nothing but
+        // still forms every pair's Gram.  The rows' full Gram (one FP64 GEMM into the buffer the
+        // next sweep writes) checks all couplings at once instead.
+        double off_after = -1.0;
+        if (!converged && off <= 1e-4 && L.Dp <= L.ldx) {
+            double* Xc = cur ? X2 : X;
+            double* Gs = cur ? X : X2;   // free until the next sweep permutes into it
+            GemmArgs g{};
+            g.m = L.Dp; g.n = L.Dp; g.k = n_gram;
+            g.A = Xc; g.sam = L.ldx; g.sak = 1;
+            g.B = Xc; g.sbk = 1; g.sbn = L.ldx;
+            g.C = Gs; g.scm = L.Dp; g.scn = 1;
+            g.alpha = 1.0; g.beta = 0.0; g.batch = 1;
+            unsigned long long* cbits = (unsigned long long*)part;
+            hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, cbits, 2);
+            launch_gemm(st, GEMM_F64, g);
+            hipLaunchKernelGGL(k_gram_coupling, dim3(cdiv(L.Dp, 256), L.Dp), dim3(256), 0, st, L.Dp, Gs, (long)L.Dp,
+                               irr2, keep2, cbits);
+            unsigned long long cb[2] = {0, 0};
+            LSUM_HIP(hipMemcpyAsync(cb, cbits, sizeof(cb), hipMemcpyDeviceToHost, st));
+            LSUM_HIP(hipStreamSynchronize(st));
+            LSUM_HIP(hipGetLastError());
+            std::memcpy(&off_after, &cb[0], sizeof(off_after));
+            if (off_after <= tol) converged = true;
+        }
         if (trace)
-            std::fprintf(stderr, "jacobi D=%d N=%d sweep %d active %d max coupling %.3e kept %.3e rank %d inner sweeps %.2f avg %llu max over %llu pairs, steps applied %llu of %llu%s\n",
-                         D, N, sweeps, d_act, off, offk, r_now, st4[3] ? (double)st4[1] / (double)st4[3] : 0.0, st4[2],
+            std::fprintf(stderr, "jacobi D=%d N=%d sweep %d active %d max coupling %.3e (after the sweep %.3e) kept %.3e rank %d inner sweeps %.2f avg %llu max over %llu pairs, steps applied %llu of %llu%s\n",
+                         D, N, sweeps, d_act, off, off_after, offk, r_now, st4[3] ? (double)st4[1] / (double)st4[3] : 0.0, st4[2],
                          st4[3], st4[5], st4[6], was_persistent ? " (persistent)" : (used_graph ? " (graph)" : ""));
     }
     // write back the D largest columns in descending order
