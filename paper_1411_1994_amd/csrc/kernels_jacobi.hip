@@ -587,7 +587,7 @@ __device__ __forceinline__ int inner_q64(int t, int i) { return i == 0 ? t : (t 
 #ifndef LSUM_EIG64_THREADS
 #define LSUM_EIG64_THREADS 512
 #endif
-constexpr int E64T = LSUM_EIG64_THREADS;   // threads of the 64 x 64 pair solve (256 or 512)
+constexpr int E64T = LSUM_EIG64_THREADS;   // threads of the 64 x 64 pair solve (256, 512 or 1024)
 constexpr int E64W = E64T / 64;            // its waves
 
 // The 64 x 64 pair problem solved by the E64T threads of a workgroup, as solve_pair32 with
@@ -601,7 +601,8 @@ constexpr int E64W = E64T / 64;            // its waves
 __device__ bool solve_pair64(int tid, double (*G)[64][65], double (*Q)[65], int* cur_out, double tol, double irr2,
                              double keep2, double skip2, int max_inner, unsigned long long* __restrict__ stat,
                              double* red) {
-    constexpr int NJ = E64T == 512 ? 1 : 2;   // block columns per thread
+    constexpr int NJ = E64T >= 512 ? 1 : 2;     // block columns per thread
+    constexpr int NI = E64T == 1024 ? 1 : 2;    // block rows per thread
     const int lane = tid & 63, wave = tid >> 6;
     double off = 0.0, offk = 0.0;
     for (int e = tid; e < 4096; e += E64T) {
@@ -621,14 +622,14 @@ __device__ bool solve_pair64(int tid, double (*G)[64][65], double (*Q)[65], int*
     }
     if (lane == 0) {
         red[wave] = off;
-        red[8 + wave] = offk;
+        red[16 + wave] = offk;
     }
     __syncthreads();
     off = 0.0;
     offk = 0.0;
     for (int w = 0; w < E64W; ++w) {
         off = fmax(off, red[w]);
-        offk = fmax(offk, red[8 + w]);
+        offk = fmax(offk, red[16 + w]);
     }
     if (tid == 0) {
         unsigned long long bits;
@@ -666,7 +667,7 @@ __device__ bool solve_pair64(int tid, double (*G)[64][65], double (*Q)[65], int*
             ++nrun;
             double (*Gn)[65] = G[cur ^ 1];
 #pragma unroll
-            for (int hi = 0; hi < 2; ++hi) {
+            for (int hi = 0; hi < NI; ++hi) {
                 const int bi = i0 + 16 * hi;
                 const int pi = inner_p64(step, bi), qi = inner_q64(step, bi);
                 // pair bi's rotation, from the lane that computed it: with one block column per
@@ -724,7 +725,7 @@ __global__ void __launch_bounds__(E64T) k_pair_eig64(int nchunk, const double* _
     constexpr int NE = 4096 / E64T;
     __shared__ double G[2][64][65];
     __shared__ double Q[64][65];
-    __shared__ double red[16];
+    __shared__ double red[32];
     const int pair = blockIdx.x, tid = threadIdx.x;
     const double* pp = part + (size_t)pair * nchunk * 4096 + tid;
     double s[NE];
