@@ -1082,8 +1082,13 @@ __global__ void __launch_bounds__(256) k_random_signs(long n, unsigned long long
 // thread.  The factorisation stops at the first pivot <= tau2 times the first.  Out: R^T in
 // pivot order (Rt[jj][k] = R[k][pivot jj], k <= jj < keep), the pivot order (the unpivoted
 // indices follow in increasing order) and keep.
-constexpr int PC_THREADS = 1024;
-constexpr int PC_MAXN = 128;   // 32 x 32 tiles of 4 x 4
+#ifndef LSUM_PCHOL_THREADS
+#define LSUM_PCHOL_THREADS 1024
+#endif
+constexpr int PC_THREADS = LSUM_PCHOL_THREADS;          // 1024 (tiles of 4 x 4) or 256 (8 x 8)
+constexpr int PC_MAXN = 128;
+constexpr int PC_SIDE = PC_THREADS == 1024 ? 32 : 16;    // threads per side of the tile grid
+constexpr int PC_TT = PC_MAXN / PC_SIDE;                 // tile edge
 
 __global__ void __launch_bounds__(PC_THREADS) k_pchol(int n, const double* __restrict__ A, double tau2, int pivot,
                                                       double* __restrict__ Rt, int* __restrict__ perm_out,
@@ -1094,17 +1099,17 @@ __global__ void __launch_bounds__(PC_THREADS) k_pchol(int n, const double* __res
     __shared__ int piv[PC_MAXN];
     __shared__ int done[PC_MAXN];
     const int tid = threadIdx.x, lane = tid & 63;
-    const int i0 = (tid >> 5) * 4, k0 = (tid & 31) * 4;   // this thread's tile
-    double a[4][4];
+    const int i0 = (tid / PC_SIDE) * PC_TT, k0 = (tid % PC_SIDE) * PC_TT;   // this thread's tile
+    double a[PC_TT][PC_TT];
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < PC_TT; ++u)
 #pragma unroll
-        for (int v = 0; v < 4; ++v)
+        for (int v = 0; v < PC_TT; ++v)
             a[u][v] = (i0 + u < n && k0 + v < n) ? A[(size_t)(i0 + u) * n + k0 + v] : 0.0;
     if (tid < PC_MAXN) done[tid] = tid < n ? 0 : 1;
     if (i0 == k0)
 #pragma unroll
-        for (int u = 0; u < 4; ++u) diag[i0 + u] = a[u][u];
+        for (int u = 0; u < PC_TT; ++u) diag[i0 + u] = a[u][u];
     __syncthreads();
     double d0 = 0.0;
     int keep = n;
@@ -1137,13 +1142,16 @@ __global__ void __launch_bounds__(PC_THREADS) k_pchol(int n, const double* __res
             break;
         }
         const double rjj = sqrt(d);
-        if (i0 == (p & ~3)) {   // the 32 threads holding row p
-            const int u = p & 3;
+        if (i0 == p - p % PC_TT) {   // the threads holding row p
+            const int u = p % PC_TT;
             const double inv = 1.0 / rjj;
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
+            for (int v = 0; v < PC_TT; ++v) {
                 const int k = k0 + v;
-                row[k] = k == p ? rjj : (done[k] ? 0.0 : a[u][v] * inv);
+                double av = a[0][v];   // a[u][v] by selects (a dynamic index would send a to scratch)
+#pragma unroll
+                for (int uu = 1; uu < PC_TT; ++uu) av = uu == u ? a[uu][v] : av;
+                row[k] = k == p ? rjj : (done[k] ? 0.0 : av * inv);
             }
         }
         __syncthreads();   // row j of R is complete; every wave has read diag and done
@@ -1152,18 +1160,18 @@ __global__ void __launch_bounds__(PC_THREADS) k_pchol(int n, const double* __res
             piv[j] = p;
         }
         if (tid < PC_MAXN) Rr[j][tid] = row[tid];
-        double ri[4], rk[4];
+        double ri[PC_TT], rk[PC_TT];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) ri[u] = row[i0 + u];
+        for (int u = 0; u < PC_TT; ++u) ri[u] = row[i0 + u];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) rk[v] = row[k0 + v];
+        for (int v = 0; v < PC_TT; ++v) rk[v] = row[k0 + v];
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < PC_TT; ++u)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) a[u][v] -= ri[u] * rk[v];
+            for (int v = 0; v < PC_TT; ++v) a[u][v] -= ri[u] * rk[v];
         if (i0 == k0)
 #pragma unroll
-            for (int u = 0; u < 4; ++u) diag[i0 + u] = a[u][u];
+            for (int u = 0; u < PC_TT; ++u) diag[i0 + u] = a[u][u];
         __syncthreads();   // diag and done for the next step; row free again
     }
     __syncthreads();
