@@ -1224,7 +1224,19 @@ __global__ void __launch_bounds__(256) k_trsm_rows(int keep, int ncol, int n, co
         for (int u = 0; u < 8; ++u)
             if (dst[u] >= 0) rl[dst[u]] = v[u];
     }
-    for (int i = wave; i < keep; i += 4) q[i][lane] = col < ncol ? Y[(size_t)perm[i] * ldy + col] : 0.0;
+    // the right-hand sides: eight rows per wave in flight (indices past keep repeat the last row
+    // and are not stored)
+    for (int i0 = wave; i0 < keep; i0 += 32) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = min(i0 + 4 * u, keep - 1);
+            v[u] = col < ncol ? Y[(size_t)perm[i] * ldy + col] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (i0 + 4 * u < keep) q[i0 + 4 * u][lane] = v[u];
+    }
     __syncthreads();
     if (wave == 0) {
         for (int b0 = 0; b0 < keep; b0 += TS_BLK) {
