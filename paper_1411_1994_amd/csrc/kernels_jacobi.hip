@@ -1,8 +1,9 @@
 // One-sided block-Jacobi SVD (FP64) of a side matrix, for the truncated SVD of Def. def:RHOSVD.
 //
 // The D columns of the side matrix are the rows of X (length N).  A sweep visits every pair of
-// 8-column blocks once (circle-method round robin: nblk-1 rounds of nblk/2 disjoint pairs).
-// One round is three wide launches:
+// column blocks once (circle-method round robin: nblk-1 rounds of nblk/2 disjoint pairs); blocks
+// hold 8, 16 or 32 columns (the wider ones below: pair problems of 32 or 64 columns, half or a
+// quarter of the rounds).  One round of 8-column blocks is three wide launches:
 //   1. k_pair_gram:   16x16 Gram partials of every pair's 16 columns over chunks of 256 cells,
 //                     on v_mfma_f64_16x16x4 (grid: chunks x pairs);
 //   2. k_pair_eig:    per pair, the chunk partials are summed in a fixed order (256 threads), the
@@ -14,7 +15,9 @@
 // accuracy of a few eps * sigma_max -- the RHOSVD threshold at eps = 1e-6 sits near 1e-8 sigma_1,
 // far below what a Gram-matrix eigensolver can resolve.  Pairs in which one column is below the
 // caller's irrelevance floor are left alone: such a column cannot change the certified tail.
-// Between sweeps the columns are re-sorted by norm so that blocks hold similar magnitudes.
+// Between sweeps the columns are re-sorted by norm so that blocks hold similar magnitudes, and
+// once a sweep's couplings are small the rows' full Gram checks whether the next sweep would
+// only confirm convergence.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -519,7 +522,7 @@ __global__ void __launch_bounds__(256) k_pair_rotate32(double* const* __restrict
 
 // ---- 32-column blocks: pairs of 64 rows, a quarter of the rounds of 8-column blocks ----------
 // The three launches of a round on blocks of 32 columns: the 64 x 64 pair Gram (ten 16 x 16
-// MFMA tiles per chunk, the other six their transposes), the 64 x 64 pair solve by four waves,
+// MFMA tiles per chunk, the other six their transposes), the 64 x 64 pair solve by eight waves,
 // and the rotation of the pair's 64 rows.  Every round still reads and writes each row once, so
 // halving the rounds of a sweep halves the bytes a sweep moves.
 
