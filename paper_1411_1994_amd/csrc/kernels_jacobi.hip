@@ -759,7 +759,12 @@ __global__ void __launch_bounds__(E64T) k_pair_eig64(int nchunk, const double* _
     for (int e = tid; e < 4096; e += E64T) Qout[(size_t)pair * 4096 + e] = Q[e >> 6][e & 63];
 }
 
-// 3. X_pair <- Q^T X_pair over one chunk: each wave 64 cells (two passes of 2 tiles of 16) x 64 rows
+// 3. X_pair <- Q^T X_pair over one chunk of CWR64 cells: each wave 32 cells (2 tiles of 16) x 64
+// rows (chunks of 128 cells: twice the work-groups of 256-cell chunks, one pass per wave)
+#ifndef LSUM_ROT64_CHUNK
+#define LSUM_ROT64_CHUNK 128
+#endif
+constexpr int CWR64 = LSUM_ROT64_CHUNK;
 __global__ void __launch_bounds__(256) k_pair_rotate64(double* const* __restrict__ xp, int ldx, int nblk, int round,
                                                        const double* __restrict__ Qin,
                                                        const int* __restrict__ active) {
@@ -774,8 +779,8 @@ __global__ void __launch_bounds__(256) k_pair_rotate64(double* const* __restrict
     int I, J;
     pair_of(nblk, round, pair, &I, &J);
 #pragma unroll 1
-    for (int half = 0; half < 2; ++half) {
-        const int c0 = chunk * CW + wave * (CW / 4) + 32 * half;
+    for (int half = 0; half < CWR64 / 128; ++half) {
+        const int c0 = chunk * CWR64 + wave * (CWR64 / 4) + 32 * half;
         double b[2][16];
 #pragma unroll
         for (int t = 0; t < 2; ++t)
@@ -1511,8 +1516,8 @@ int jacobi_svd(hipStream_t st, int D, int N, double* A, int lda, double tol, dou
                                    nblk, round, L.nchunk, part);
                 hipLaunchKernelGGL(k_pair_eig64, dim3(npair), dim3(E64T), 0, st, L.nchunk, part, tol, irr2, skip2,
                                    keep2_dev, max_inner, Qd, act, stat);
-                hipLaunchKernelGGL(k_pair_rotate64, dim3(L.nchunk_all, npair), dim3(256), 0, st, xp_dev, L.ldx, nblk,
-                                   round, Qd, act);
+                hipLaunchKernelGGL(k_pair_rotate64, dim3(cdiv(L.ldx, CWR64), npair), dim3(256), 0, st, xp_dev, L.ldx,
+                                   nblk, round, Qd, act);
                 continue;
             }
             if (bw == 16) {
