@@ -473,7 +473,11 @@ __global__ void __launch_bounds__(256) k_pair_eig32(int nchunk, const double* __
     for (int e = tid; e < 1024; e += 256) Qout[(size_t)pair * 1024 + e] = Q[e >> 5][e & 31];
 }
 
-// 3. X_pair <- Q^T X_pair over one chunk: each wave 64 cells (4 tiles of 16) x 32 rows
+// 3. X_pair <- Q^T X_pair over one chunk of CWR32 cells: each wave a quarter of it x 32 rows
+#ifndef LSUM_ROT32_CHUNK
+#define LSUM_ROT32_CHUNK 128
+#endif
+constexpr int CWR32 = LSUM_ROT32_CHUNK;
 __global__ void __launch_bounds__(256) k_pair_rotate32(double* const* __restrict__ xp, int ldx, int nblk, int round,
                                                        const double* __restrict__ Qin,
                                                        const int* __restrict__ active) {
@@ -487,18 +491,19 @@ __global__ void __launch_bounds__(256) k_pair_rotate32(double* const* __restrict
     __syncthreads();
     int I, J;
     pair_of(nblk, round, pair, &I, &J);
-    const int c0 = chunk * CW + wave * (CW / 4);
-    double b[4][8];
+    constexpr int NT = CWR32 / 64;   // tiles of 16 cells per wave
+    const int c0 = chunk * CWR32 + wave * (CWR32 / 4);
+    double b[NT][8];
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+    for (int t = 0; t < NT; ++t)
 #pragma unroll
         for (int k0 = 0; k0 < 8; ++k0) {
             const int col = c0 + 16 * t + r;
             b[t][k0] = col < ldx ? X[(size_t)pair_row32(I, J, 4 * k0 + kg) * ldx + col] : 0.0;
         }
-    d4 acc[4][2];
+    d4 acc[NT][2];
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+    for (int t = 0; t < NT; ++t)
 #pragma unroll
         for (int rt = 0; rt < 2; ++rt) {
             acc[t][rt] = d4{0, 0, 0, 0};
@@ -508,7 +513,7 @@ __global__ void __launch_bounds__(256) k_pair_rotate32(double* const* __restrict
                                                                    0, 0, 0);
         }
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
+    for (int t = 0; t < NT; ++t) {
         const int col = c0 + 16 * t + r;
         if (col < ldx) {
 #pragma unroll
@@ -1525,8 +1530,8 @@ int jacobi_svd(hipStream_t st, int D, int N, double* A, int lda, double tol, dou
                                    nblk, round, L.nchunk, part);
                 hipLaunchKernelGGL(k_pair_eig32, dim3(npair), dim3(256), 0, st, L.nchunk, part, tol, irr2, skip2,
                                    keep2_dev, max_inner, Qd, act, stat);
-                hipLaunchKernelGGL(k_pair_rotate32, dim3(L.nchunk_all, npair), dim3(256), 0, st, xp_dev, L.ldx, nblk,
-                                   round, Qd, act);
+                hipLaunchKernelGGL(k_pair_rotate32, dim3(cdiv(L.ldx, CWR32), npair), dim3(256), 0, st, xp_dev, L.ldx,
+                                   nblk, round, Qd, act);
                 continue;
             }
             hipLaunchKernelGGL(k_pair_gram, dim3(L.nchunk, npair), dim3(256), 0, st, xp_dev, L.ldx, n_gram, nblk,
