@@ -450,6 +450,8 @@ __global__ void __launch_bounds__(256) k_pair_eig32(int nchunk, const double* __
     __shared__ double G[2][32][33];
     __shared__ double Q[32][33];
     __shared__ double red[8];
+    // the pair solve is the latency chain of a round: its waves issue first on a shared SIMD
+    __builtin_amdgcn_s_setprio(3);
     const int pair = blockIdx.x, tid = threadIdx.x;
     for (int u = 0; u < 4; ++u) {
         const int e = tid + 256 * u;
@@ -734,6 +736,8 @@ __global__ void __launch_bounds__(E64T) k_pair_eig64(int nchunk, const double* _
     __shared__ double G[2][64][65];
     __shared__ double Q[64][65];
     __shared__ double red[32];
+    // the pair solve is the latency chain of a round: its waves issue first on a shared SIMD
+    __builtin_amdgcn_s_setprio(3);
     const int pair = blockIdx.x, tid = threadIdx.x;
     const double* pp = part + (size_t)pair * nchunk * 4096 + tid;
     double s[NE];
