@@ -197,3 +197,27 @@ def test_wide_blocks_graphs_equal_direct_and_match_8_column_blocks(block):
         for l in range(3):
             n = min(len(x["sig"][l]), len(z["sig"][l]), min(x["r"][l], z["r"][l]))
             assert np.allclose(x["sig"][l][:n], z["sig"][l][:n], rtol=1e-10, atol=1e-12 * z["sig"][l][0])
+
+
+@pytest.mark.parametrize("block", [16, 32])
+def test_skipped_rotations_match_every_rotation_applied(block):
+    # wide-block pair solves leave out rotations below a tenth of the sweep tolerance (and skip
+    # steps with none left); with every rotation above the rounding floor applied instead, the
+    # certified ranks agree (or sit at a threshold within rounding), both bounds are certified
+    # and both results are within their bound of the oracle's direct sum
+    require_gpu()
+    import paper_1411_1994_amd as L
+    probs = _problems()
+    on = _run_opts({L.OPT_JACOBI_BLOCK: block, L.OPT_JACOBI_SKIP: 1}, probs)
+    off = _run_opts({L.OPT_JACOBI_BLOCK: block, L.OPT_JACOBI_SKIP: 0}, probs)
+    for k, p in enumerate(probs):
+        x, z = on[k], off[k]
+        assert all(abs(a - b) <= 1 for a, b in zip(x["r"], z["r"])), (x["r"], z["r"])
+        nA = x["st"]["norm_A"]
+        ref = O.brute_force_points(p, x["cells"])
+        for o in (x, z):
+            assert o["bound"] <= p.eps * nA * (1 + 1e-12)
+            assert np.max(np.abs(o["v"] - ref)) <= o["bound"] * (1 + 1e-9) + 1e-12 * np.max(np.abs(ref))
+        for l in range(3):
+            n = min(len(x["sig"][l]), len(z["sig"][l]), min(x["r"][l], z["r"][l]))
+            assert np.allclose(x["sig"][l][:n], z["sig"][l][:n], rtol=1e-10, atol=1e-12 * z["sig"][l][0])
