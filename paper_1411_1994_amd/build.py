@@ -67,5 +67,32 @@ def build(verbose: bool = True) -> str:
     return LIB
 
 
+# The host-side steps (quadrature, snapping, lattice classes, request plans, the autotuner's
+# file) with a self-test driver, compiled by the host compiler with AddressSanitizer and
+# UndefinedBehaviorSanitizer: host code only, nothing for the GPU.
+HOST_SELFTEST_SOURCES = ["host_selftest.cpp", "lsum_host.cpp", "lsum_sinc_error.cpp", "lsum_tune.cpp"]
+HOST_SELFTEST = os.path.join(ROOT, "_build", "host_selftest")
+
+
+def build_host_selftest(verbose: bool = True) -> str:
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    os.makedirs(os.path.dirname(HOST_SELFTEST), exist_ok=True)
+    cmd = ["g++", "-std=c++17", "-O1", "-g", "-fno-omit-frame-pointer",
+           "-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-D__HIP_PLATFORM_AMD__",
+           "-I", os.path.join(rocm, "include"), "-I", INCLUDE, "-I", CSRC]
+    cmd += [os.path.join(CSRC, s) for s in HOST_SELFTEST_SOURCES]
+    cmd += ["-L", os.path.join(rocm, "lib"), "-lamdhip64", "-Wl,-rpath," + os.path.join(rocm, "lib"),
+            "-o", HOST_SELFTEST]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"host self-test build failed\n{' '.join(cmd)}\n{res.stdout}\n{res.stderr}")
+    if verbose:
+        print(f"built {HOST_SELFTEST}")
+    return HOST_SELFTEST
+
+
 if __name__ == "__main__":
-    build()
+    if "--host-selftest" in sys.argv:
+        build_host_selftest()
+    else:
+        build()
