@@ -131,7 +131,8 @@ def dominant_roofline(prof: dict, dtype_peak: str):
     ms = st["ms"] / n
     if st["flops"] > 0 and st["bytes"] == 0 or name in ("core", "tile", "projection", "norm"):
         achieved = st["flops"] / n / (ms * 1e-3) / 1e12
-        peak = PEAK_TFLOPS[dtype_peak]
+        # the SVD and the norm are FP64 at every precision; the contractions take the request's
+        peak = PEAK_TFLOPS["f64" if name in ("svd", "norm") else dtype_peak]
         return name, {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                       "frac": achieved / peak, "traffic": None, "kernel_stage": name,
                       "avg_launch_ms": ms, "launches": st["launches"],
