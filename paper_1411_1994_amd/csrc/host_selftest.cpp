@@ -276,6 +276,100 @@ void test_tuner() {
 
 }  // namespace
 
+// The terms of an axis (Thm thm:sumCaseE (A)) reproduce the direct sum over its sites exactly:
+// rows of integers (exact in FP64), the tables built here from their stated definitions (window
+// sums, strided prefix and suffix sums), every term read checked inside the row, and the terms
+// never more than the sites.  Site lists: snapped lattices with b/h of small and of large
+// denominator (the served mix's b/h = (N - 1) / (L + 16)), periodic combs, and random sites
+// with repeats.
+void test_shift_terms(std::mt19937_64& rng) {
+    auto table = [](const std::vector<double>& g, int R, int ldg, int S, int n) {
+        std::vector<double> Q((size_t)R * ldg, 0.0);
+        for (int q = 0; q < R; ++q)
+            for (int x = 0; x < ldg; ++x) {
+                double a = 0.0;
+                if (n > 0) {
+                    for (int m = 0; m < n && x - m * S >= 0; ++m) a += g[(size_t)q * ldg + x - m * S];
+                } else if (n == lsum::kPrefixSums) {
+                    for (int y = x; y >= 0; y -= S) a += g[(size_t)q * ldg + y];
+                } else {
+                    for (int y = x; y < ldg; y += S) a += g[(size_t)q * ldg + y];
+                }
+                Q[(size_t)q * ldg + x] = a;
+            }
+        return Q;
+    };
+    int fewer = 0, strided = 0;
+    for (int it = 0; it < 160; ++it) {
+        const int N_ref = 2 * (int)(rng() % 700) + 1 + (it % 7 == 0 ? 0 : 4);
+        const int N_axis = std::max(1, N_ref - 2 * (int)(rng() % 40));
+        const int ldg = std::max(2, 2 * N_ref - 1) + (int)(rng() % 8);
+        std::vector<int32_t> c;
+        const int kind = it % 4;
+        if (kind == 0 || kind == 1) {
+            // a snapped lattice: L sites at spacing beta cells (kind 1: b/h = (N - 1) / (L + 16))
+            const int L = 3 + (int)(rng() % 100);
+            const double beta = kind == 1 ? (double)(N_axis - 1) / (L + 16)
+                                          : 1.0 + std::uniform_real_distribution<double>(0.0, 40.0)(rng);
+            const double c0 = 0.5 * (N_axis - 1);
+            for (int k = 0; k < L; ++k) {
+                const double x = (k - 0.5 * (L - 1)) * beta;
+                const long v = std::lround(c0 + x);
+                if (v >= 0 && v < N_axis) c.push_back((int32_t)v);
+            }
+        } else if (kind == 2) {   // periodic combs: b/h = P / Q
+            const int P = 1 + (int)(rng() % 60), Qd = 1 + (int)(rng() % 6), L = 4 + (int)(rng() % 60);
+            for (int k = 0; k < L; ++k) {
+                const long v = (long)k * P / Qd;
+                if (v < N_axis) c.push_back((int32_t)v);
+            }
+        } else {                  // random sites, repeats allowed, unsorted
+            const int n = (int)(rng() % 90);
+            for (int k = 0; k < n; ++k) c.push_back((int32_t)(rng() % N_axis));
+        }
+        const int n = (int)c.size();
+        std::vector<int2> terms;
+        int stride = 0, n_tab[2] = {0, 0};
+        bool two = false;
+        lsum::shift_terms(c.data(), n, N_ref, N_axis, ldg, terms, &stride, n_tab, &two);
+        check((int)terms.size() <= std::max(n, 0), "no more terms than sites");
+        if ((int)terms.size() < n) ++fewer;
+        if (n_tab[0] == lsum::kPrefixSums) ++strided;
+        const int R = 2;
+        std::vector<double> g((size_t)R * ldg, 0.0);
+        for (int q = 0; q < R; ++q)
+            for (int x = 0; x < 2 * N_ref - 1; ++x) g[(size_t)q * ldg + x] = (double)((long)(rng() % 2001) - 1000);
+        std::vector<double> T0 = g, T1 = g;
+        if (stride > 0) {
+            T0 = table(g, R, ldg, stride, n_tab[0]);
+            T1 = table(g, R, ldg, stride, n_tab[1]);
+        }
+        bool inside = true, exact = true, tab_ok = true;
+        const int Nr = std::max(N_axis, 2);
+        for (const int2& t : terms) {
+            inside = inside && t.x >= 0 && t.x + Nr - 1 < ldg;
+            tab_ok = tab_ok && t.y >= 0 && t.y <= 3 && (two || !(t.y & 1)) && (stride > 0 || t.y == 0);
+        }
+        check(inside, "every term reads inside the row");
+        check(tab_ok, "term tables and signs as announced");
+        if (!inside || !tab_ok) continue;
+        for (int q = 0; q < R; ++q)
+            for (int i = 0; i < N_axis; ++i) {
+                double direct = 0.0, sum = 0.0;
+                for (int k = 0; k < n; ++k) direct += g[(size_t)q * ldg + i + N_ref - 1 - c[k]];
+                for (const int2& t : terms) {
+                    const double v = ((t.y & 1) ? T1 : T0)[(size_t)q * ldg + i + t.x];
+                    sum += (t.y & 2) ? -v : v;
+                }
+                exact = exact && sum == direct;
+            }
+        check(exact, "terms reproduce the direct sum over the sites");
+    }
+    std::printf("shift terms: %d of 160 axes with fewer terms than sites, %d on strided runs\n", fewer, strided);
+    check(fewer > 40, "most lattices need fewer terms than sites");
+    check(strided > 10, "strided runs are taken for lattices without a short period");
+}
+
 int main() {
     std::mt19937_64 rng(1411);
     test_nodes();
@@ -283,6 +377,7 @@ int main() {
     test_classes();
     test_sinc_error();
     test_plans(rng);
+    test_shift_terms(rng);
     test_tuner();
     std::printf("host self-test: %d checks, %d failed\n", g_checks, g_failed);
     return g_failed ? 1 : 0;

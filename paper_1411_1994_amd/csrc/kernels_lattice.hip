@@ -54,7 +54,8 @@ __global__ void __launch_bounds__(256) k_collocate(int R, const double* __restri
 
 // --------------------------------------------------------------------------------------------
 // Assembled 1D sums (Thm thm:sumCaseE (A)) for a batch of jobs: out[q, i] = sum_t
-// T_tab(t)[q * ldg + i + off_t], summed in term order.  One workgroup per (64-cell tile, job).
+// +-T_tab(t)[q * ldg + i + off_t], summed in term order (bit 0 of tab picks the table, bit 1 the
+// sign).  One workgroup per (64-cell tile, job).
 // Each lane owns a pair of adjacent cells and loads both with one 16-byte access (the unit that
 // bounds this kernel is the vector-memory path, not HBM: five 8-byte loads per output for the
 // period-5 combs of a 64-site axis); the two halves of a wavefront serve two node slots, so the
@@ -113,18 +114,22 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))
         for (int u = 0; u < NU; ++u) acc[u] = dpair{0.0, 0.0};
         for (int t = 0; t < nt; t += TU) {
             dpair v[TU][NU];
+            double sg[TU];
 #pragma unroll
             for (int e = 0; e < TU; ++e) {
                 const int te = min(t + e, nt - 1);
-                const LSUM_GLOBAL double* r = (terms[2 * te + 1] ? T1 : T0) + terms[2 * te];
+                const int tab = terms[2 * te + 1];
+                const LSUM_GLOBAL double* r = ((tab & 1) ? T1 : T0) + terms[2 * te];
+                sg[e] = (tab & 2) ? -1.0 : 1.0;
 #pragma unroll
                 for (int u = 0; u < NU; ++u) v[e][u] = *(const LSUM_GLOBAL dpair*)(r + qo[u]);
             }
+            // a sign of +-1 scales exactly: acc + sg v rounds as acc +- v
 #pragma unroll
             for (int e = 0; e < TU; ++e)
                 if (t + e < nt)
 #pragma unroll
-                    for (int u = 0; u < NU; ++u) acc[u] += v[e][u];
+                    for (int u = 0; u < NU; ++u) acc[u] += sg[e] * v[e][u];
         }
 #pragma unroll
         for (int u = 0; u < NU; ++u) {
@@ -161,14 +166,28 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))
 
 // Windowed strided sums of the reference rows: Q[q, x] = sum_{m=0}^{n-1} G[q, x - m S] (terms
 // with x - m S < 0 are absent).  A comb of n sites c, c + S, ..., c + (n-1) S adds
-// Q[q, i + N_ref - 1 - c] to cell i.
+// Q[q, i + N_ref - 1 - c] to cell i.  n = kPrefixSums sums the whole chain below x and
+// n = kSuffixSums the chain above it (x + m S < ldg); those two are compensated sums
+// (Neumaier's variant of Kahan summation), since a run of sites is read as the difference of
+// two of them.
 __global__ void __launch_bounds__(256) k_window_sums(int ldg, const double* __restrict__ G, int S, int n,
                                                      double* __restrict__ Q) {
     const int x = blockIdx.x * 256 + threadIdx.x;
     if (x >= ldg) return;
     const double* g = G + (size_t)blockIdx.y * ldg;
     double acc = 0.0;
-    for (int m = 0, y = x; m < n && y >= 0; ++m, y -= S) acc += g[y];
+    if (n > 0) {
+        for (int m = 0, y = x; m < n && y >= 0; ++m, y -= S) acc += g[y];
+    } else {
+        const int step = n == kSuffixSums ? S : -S;
+        double comp = 0.0;
+        for (int y = x; y >= 0 && y < ldg; y += step) {
+            const double v = g[y], s = acc + v;
+            comp += fabs(acc) >= fabs(v) ? (acc - s) + v : (v - s) + acc;
+            acc = s;
+        }
+        acc += comp;
+    }
     Q[(size_t)blockIdx.y * ldg + x] = acc;
 }
 

@@ -845,11 +845,12 @@ int lsum_shift_sum(lsum_ctx x, void* stream, int R, const double* G_dev, int ldg
     LSUM_HIP(hipSetDevice(x->c.device));
     hipStream_t st = pick(x, stream);
     FailStream fs(st);
-    // terms: one per site, or one per comb on windowed strided sums of the rows
+    // terms: one per site, one per comb on windowed strided sums of the rows, or two per run of
+    // one stride on strided prefix / suffix sums of the rows
     std::vector<int2> terms;
-    int stride = 0, n_hi = 0;
+    int stride = 0, n_tab[2] = {0, 0};
     bool two = false;
-    shift_terms(sites, n_sites, N_ref, terms, &stride, &n_hi, &two);
+    shift_terms(sites, n_sites, N_ref, N_axis, ldg, terms, &stride, n_tab, &two);
     DevBuf td, jd, w0, w1;
     int rc = td.get(x->c.pool, std::max<size_t>(1, terms.size()) * sizeof(int2));
     if (rc) return rc;
@@ -858,11 +859,11 @@ int lsum_shift_sum(lsum_ctx x, void* stream, int R, const double* G_dev, int ldg
     j.T0 = G_dev;
     if (stride > 0) {
         if ((rc = w0.get(x->c.pool, (size_t)R * ldg * 8))) return rc;
-        launch_window_sums(st, R, G_dev, ldg, stride, n_hi, w0.as<double>());
+        launch_window_sums(st, R, G_dev, ldg, stride, n_tab[0], w0.as<double>());
         j.T0 = w0.as<double>();
         if (two) {
             if ((rc = w1.get(x->c.pool, (size_t)R * ldg * 8))) return rc;
-            launch_window_sums(st, R, G_dev, ldg, stride, n_hi - 1, w1.as<double>());
+            launch_window_sums(st, R, G_dev, ldg, stride, n_tab[1], w1.as<double>());
             j.T1 = w1.as<double>();
         }
     }
@@ -891,9 +892,9 @@ int lsum_shift_sum_noalloc(lsum_ctx x, void* stream, int R, const double* G_dev,
     hipStream_t st = pick(x, stream);
     FailStream fs(st);
     std::vector<int2> terms;
-    int stride = 0, n_hi = 0;
+    int stride = 0, n_tab[2] = {0, 0};
     bool two = false;
-    shift_terms(sites, n_sites, N_ref, terms, &stride, &n_hi, &two);
+    shift_terms(sites, n_sites, N_ref, N_axis, ldg, terms, &stride, n_tab, &two);
     // scratch layout (256-byte aligned parts): job | terms | window table 0 | window table 1
     auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
     const size_t off_terms = up(sizeof(ShiftJob));
@@ -911,11 +912,11 @@ int lsum_shift_sum_noalloc(lsum_ctx x, void* stream, int R, const double* G_dev,
     j.T0 = G_dev;
     if (stride > 0) {
         double* w0 = reinterpret_cast<double*>(sp + off_w0);
-        launch_window_sums(st, R, G_dev, ldg, stride, n_hi, w0);
+        launch_window_sums(st, R, G_dev, ldg, stride, n_tab[0], w0);
         j.T0 = w0;
         if (two) {
             double* w1 = reinterpret_cast<double*>(sp + off_w0 + tab);
-            launch_window_sums(st, R, G_dev, ldg, stride, n_hi - 1, w1);
+            launch_window_sums(st, R, G_dev, ldg, stride, n_tab[1], w1);
             j.T1 = w1;
         }
     }

@@ -8,6 +8,7 @@
 #include <map>
 #include <set>
 #include <tuple>
+#include <vector>
 
 #include "lsum_internal.h"
 
@@ -255,14 +256,108 @@ int comb_period(const int32_t* c, int n, int max_p, int* stride) {
 // a lattice of spacing b on a grid of step h repeat with period p whenever b/h = S/p is
 // rational: the axis is then p interleaved combs of stride S, and each comb is one window of
 // the strided sums of the reference row (one term instead of n_j).
-void shift_terms(const int32_t* c, int n, int N_ref, std::vector<int2>& terms, int* stride, int* n_hi,
-                 bool* two_tables) {
+//
+// When b/h has a large denominator (no period below n/2) the snapped sites still split into a
+// few runs of one stride S (a convergent of b/h: the rounding drifts by one cell only every so
+// many sites).  A run a, a + S, ..., a + (n - 1) S is the difference of two strided prefix sums
+// Pb[x] = sum_{m >= 0, x - mS >= 0} g[x - mS] (two terms, whatever n), or of two strided suffix
+// sums Pu[x] = sum_{m >= 0, x + mS < ldg} g[x + mS] when the prefix difference would read below
+// the row; a run that fits neither is split between them.  This form is taken when it needs
+// fewer terms than the sites (or the periodic combs).
+namespace {
+
+// the runs of stride S over the ascending sites u[0..n) (each in [0, expect.size() - S)):
+// (first site, count), in order of their first site (greedy: a site extends the open run that
+// expects it, else opens a run).  `expect` (site -> open run expecting it, or -1) enters and
+// leaves all -1.
+void stride_runs(const std::vector<int32_t>& u, int S, std::vector<int2>& runs, std::vector<int>& expect) {
+    runs.clear();
+    for (int32_t v : u) {
+        int r = expect[v];
+        if (r >= 0) {
+            expect[v] = -1;
+            ++runs[r].y;
+        } else {
+            r = (int)runs.size();
+            runs.push_back(make_int2(v, 1));
+        }
+        if (expect[v + S] < 0) expect[v + S] = r;   // a run already expecting v + S keeps it (equal sites)
+    }
+    for (const int2& r : runs) expect[r.x + r.y * S] = -1;
+}
+
+// terms of one run of stride S on the prefix (tab 0) and suffix (tab 1) tables; bit 1 of tab
+// marks a term that is subtracted.  Every term read i + off stays in [0, ldg) for i < max(N, 2)
+// (stride_ok below).
+void run_terms(int a, int n, int S, int N_ref, int lo_suffix, std::vector<int2>& terms) {
+    const int last = a + (n - 1) * S;
+    if (last + S <= N_ref - 1) {   // prefix: Pb[y] - Pb[y - nS], y - nS >= 0
+        terms.push_back(make_int2(N_ref - 1 - a, 0));
+        terms.push_back(make_int2(N_ref - 1 - last - S, 2));
+    } else if (a >= lo_suffix) {   // suffix: Pu[y - (n - 1) S] - Pu[y + S], y + S inside the row
+        terms.push_back(make_int2(N_ref - 1 - last, 1));
+        terms.push_back(make_int2(N_ref - 1 - a + S, 3));
+    } else {                       // the sites up to N_ref - 1 - S on the prefix, the rest on the suffix
+        const int j = (N_ref - 1 - S - a) / S;   // >= 0: a <= N_ref - 1 - S here
+        run_terms(a, j + 1, S, N_ref, lo_suffix, terms);
+        run_terms(a + (j + 1) * S, n - j - 1, S, N_ref, lo_suffix, terms);
+    }
+}
+
+}  // namespace
+
+void shift_terms(const int32_t* c, int n, int N_ref, int N_axis, int ldg, std::vector<int2>& terms, int* stride,
+                 int n_tab[2], bool* two_tables) {
     terms.clear();
     *stride = 0;
-    *n_hi = 0;
+    n_tab[0] = n_tab[1] = 0;
     *two_tables = false;
     int S = 0;
     const int period = n >= 4 ? comb_period(c, n, n / 2, &S) : 0;
+    int best = period > 0 ? period : n;   // terms of the periodic combs, or of the sites
+    int bestS = 0;
+    std::vector<int2> runs;
+    // strided runs: a stride S <= (ldg + 1 - max(N, 2)) / 2 lets every run take the prefix or the
+    // suffix form (split at most once)
+    const int Nr = std::max(N_axis, 2);
+    const int S_max = (ldg + 1 - Nr) / 2;
+    const int lo_suffix = N_ref + Nr - 1 - ldg;   // + S: the first site a suffix run may start at
+    if (n >= 3 && S_max >= 1) {
+        std::vector<int32_t> u(c, c + n);
+        std::sort(u.begin(), u.end());
+        // candidate strides: the distances from three anchor sites to the next 32 (an outlying
+        // first site does not hide the lattice's stride)
+        std::vector<int> cand;
+        for (int a : {0, n / 3, (2 * n) / 3})
+            for (int p = 1; p <= 32 && a + p < n; ++p) {
+                const int d = u[a + p] - u[a];
+                if (d >= 1 && d <= S_max && std::find(cand.begin(), cand.end(), d) == cand.end()) cand.push_back(d);
+            }
+        int S_top = 0;
+        for (int d : cand) S_top = std::max(S_top, d);
+        std::vector<int> expect((size_t)u.back() + S_top + 2, -1);
+        for (int d : cand) {
+            stride_runs(u, d, runs, expect);
+            int cost = 0;
+            for (const int2& r : runs) {
+                const int last = r.x + (r.y - 1) * d;
+                cost += (last + d <= N_ref - 1 || r.x >= lo_suffix + d) ? 2 : 4;
+            }
+            if (cost < best) {
+                best = cost;
+                bestS = d;
+            }
+        }
+        if (bestS > 0) {
+            stride_runs(u, bestS, runs, expect);
+            for (const int2& r : runs) run_terms(r.x, r.y, bestS, N_ref, lo_suffix + bestS, terms);
+            *stride = bestS;
+            n_tab[0] = kPrefixSums;
+            n_tab[1] = kSuffixSums;
+            for (const int2& t : terms) *two_tables = *two_tables || (t.y & 1);
+            return;
+        }
+    }
     if (period > 0) {
         const int hi = (n + period - 1) / period;
         for (int j = 0; j < period; ++j) {
@@ -271,7 +366,8 @@ void shift_terms(const int32_t* c, int n, int N_ref, std::vector<int2>& terms, i
             if (nj != hi) *two_tables = true;
         }
         *stride = S;
-        *n_hi = hi;
+        n_tab[0] = hi;
+        n_tab[1] = hi - 1;
         return;
     }
     for (int k = 0; k < n; ++k) terms.push_back(make_int2(N_ref - 1 - c[k], 0));

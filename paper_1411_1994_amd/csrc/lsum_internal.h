@@ -180,13 +180,15 @@ struct KTime {
 };
 
 // Shift-sum for a batch of (axis, block) jobs; see kernels_lattice.hip.  Each job is a list of
-// terms (off, tab): out[q, i] = sum_t T_tab[q * ldg + i + off] for i < N_axis, q < R.  With the
-// reference rows as T0 and off = N_ref - 1 - c_k per site this is the direct sum over the
-// sites; an axis whose sites form interleaved uniform combs uses windowed strided sums of the
-// reference rows (launch_window_sums) and one term per comb.
+// terms (off, tab): out[q, i] = sum_t s_t T_(tab & 1)[q * ldg + i + off] for i < N_axis, q < R,
+// with s_t = -1 when bit 1 of tab is set and +1 otherwise.  With the reference rows as T0 and
+// off = N_ref - 1 - c_k per site this is the direct sum over the sites; an axis whose sites form
+// interleaved uniform combs uses windowed strided sums of the reference rows
+// (launch_window_sums) and one term per comb, and one whose sites form runs of one stride uses
+// differences of strided prefix or suffix sums, two terms per run.
 struct ShiftJob {
     const double* T0;      // rows of length >= ldg, R of them
-    const double* T1;      // second table (combs one site shorter) or nullptr
+    const double* T1;      // second table (combs one site shorter, or the suffix sums) or nullptr
     const int2* terms;     // n_terms pairs (off, tab)
     double* U;             // vector-major output (R x ldu) or nullptr
     double* UT;            // point-major output (N_axis x ldt, zero padded beyond R) or nullptr
@@ -202,7 +204,12 @@ struct ShiftJob {
 // extend one entry past the last cell window (ldg >= 2 * N_ref - 1 and ldg >= 2).
 void launch_shift_sum(hipStream_t st, const ShiftJob* jobs_dev, int n_jobs, int max_N, int max_R,
                       const KTime* kt = nullptr, Tuner* tuner = nullptr);
-// Q[q, x] = sum_{m=0}^{n-1} G[q, x - m S] over the terms with x - m S >= 0, for x < ldg.
+// Q[q, x] = sum_{m=0}^{n-1} G[q, x - m S] over the terms with x - m S >= 0, for x < ldg; with
+// n = kPrefixSums every m >= 0 (the strided prefix sum), with n = kSuffixSums the strided
+// suffix sum Q[q, x] = sum_{m >= 0, x + m S < ldg} G[q, x + m S].  The prefix and suffix sums are
+// compensated (each within a few units of roundoff of the exact sum of |G| along the chain).
+constexpr int kPrefixSums = -1;
+constexpr int kSuffixSums = -2;
 void launch_window_sums(hipStream_t st, int R, const double* G, int ldg, int stride, int n, double* Q);
 // The static scratch array of the allocation-free shift-sum (scratch_noalloc.hip): its size, and
 // its address on `device` (taken once per device with hipGetSymbolAddress; `device` current).
@@ -211,13 +218,19 @@ constexpr int kMaxDevices = 64;
 int noalloc_scratch(int device, void** ptr);
 // Host: the smallest period p <= max_p with c[k+p] - c[k] constant (its stride), or 0.
 int comb_period(const int32_t* c, int n, int max_p, int* stride);
-// Host: the terms of one axis.  When the ascending sites c[0..n) are `period` interleaved
-// combs of uniform stride, comb j (sites c[j], c[j] + S, ...) has n_j = ceil((n - j) / period)
-// sites and one term (N_ref - 1 - c[j], tab) with tab 0 for n_j == n_hi and 1 for n_hi - 1;
-// *stride, *n_hi are set and *two_tables tells whether table 1 is used.  Otherwise one term
-// (N_ref - 1 - c[k], 0) per site on the reference rows and *stride = 0.
-void shift_terms(const int32_t* c, int n, int N_ref, std::vector<int2>& terms, int* stride, int* n_hi,
-                 bool* two_tables);
+// Host: the terms of one axis of N_axis cells (sites c[0..n) in [0, N_axis), rows of ldg >=
+// max(2, 2 N_ref - 1) entries), the form with the fewest terms of:
+// * runs of one stride S (sites a, a + S, ..., a + (n_r - 1) S): each two terms on the strided
+//   prefix sums (table 0, n_tab[0] = kPrefixSums) or suffix sums (table 1, kSuffixSums) of the
+//   rows, bit 1 of tab marking the subtracted one (a run that fits neither is split in two);
+// * when the ascending sites are `period` interleaved combs of uniform stride, comb j (sites
+//   c[j], c[j] + S, ...) with n_j = ceil((n - j) / period) sites: one term (N_ref - 1 - c[j], tab),
+//   tab 0 for n_j == n_tab[0] and 1 for n_tab[1] = n_tab[0] - 1 (window sums of that length);
+// * otherwise one term (N_ref - 1 - c[k], 0) per site on the reference rows, *stride = 0.
+// *stride is the tables' stride and *two_tables tells whether table 1 is used.  Every term's
+// reads i + off lie in [0, ldg) for i < max(N_axis, 2).
+void shift_terms(const int32_t* c, int n, int N_ref, int N_axis, int ldg, std::vector<int2>& terms, int* stride,
+                 int n_tab[2], bool* two_tables);
 // Canonical sum at points from n_fac factor sets given vector-major (the sample stage of the
 // C ABI): out[p] = sum_f lam[f] sum_q prod_l U_f,l[q, i_l(p)], NaN outside the grid.
 void launch_sample_cp(hipStream_t st, int n_fac, int R, const double* U, int ldu,

@@ -1135,14 +1135,14 @@ static int run_tucker_ref(Request* q, hipStream_t st, const hipStream_t* aux, St
     for (int b = 0; b < nb; ++b)
         for (int l = 0; l < 3; ++l) {
             const auto& sites = P.offs[l][b];
-            int stride = 0, n_hi = 0;
+            int stride = 0, n_tab[2] = {0, 0};
             bool two = false;
-            shift_terms(sites.data(), (int)sites.size(), P.N_ref, tv, &stride, &n_hi, &two);
+            shift_terms(sites.data(), (int)sites.size(), P.N_ref, P.N[l], P.ldg, tv, &stride, n_tab, &two);
             ShiftJob j{};
             j.T0 = Zr[l];
             if (stride > 0) {
-                if ((rc = windows(l, stride, n_hi, &j.T0))) return rc;
-                if (two && (rc = windows(l, stride, n_hi - 1, &j.T1))) return rc;
+                if ((rc = windows(l, stride, n_tab[0], &j.T0))) return rc;
+                if (two && (rc = windows(l, stride, n_tab[1], &j.T1))) return rc;
             }
             term_off.push_back(terms_h.size());
             terms_h.insert(terms_h.end(), tv.begin(), tv.end());
@@ -1551,12 +1551,12 @@ static int offgrid_terms(Context* c, Request* q, hipStream_t st, std::map<int, s
                 for (size_t k = 0; k < sites.size(); ++k)
                     if (cls[k] == cl) cs.push_back(sites[k]);
                 if (cs.empty()) continue;
-                int stride = 0, n_hi = 0;
+                int stride = 0, n_tab[2] = {0, 0};
                 bool two = false;
-                shift_terms(cs.data(), (int)cs.size(), P.N_ref, tv, &stride, &n_hi, &two);
+                shift_terms(cs.data(), (int)cs.size(), P.N_ref, P.N[l], P.ldg, tv, &stride, n_tab, &two);
                 for (const int2& t : tv) {
-                    const int table = stride == 0 ? cl : table_of(cl, stride, t.y == 0 ? n_hi : n_hi - 1);
-                    terms.push_back(make_int2((int)(t.x + table * tab), 0));
+                    const int table = stride == 0 ? cl : table_of(cl, stride, n_tab[t.y & 1]);
+                    terms.push_back(make_int2((int)(t.x + table * tab), t.y & 2));   // keeps the sign
                 }
             }
         }
@@ -1672,22 +1672,22 @@ int run_batch(std::vector<Request*>& reqs, hipStream_t st, const hipStream_t* au
             for (int l = 0; l < 3; ++l) {
                 if (q->axis_src[l] != l) continue;
                 const auto& sites = P.offs[l][b];
-                int stride = 0, n_hi = 0;
+                int stride = 0, n_tab[2] = {0, 0};
                 bool two = false;
                 ShiftJob j{};
                 if (P.off_grid()) {
                     tv = og[b * 3 + l];
                     j.T0 = q->tabs->G.as<double>();
                 } else {
-                    shift_terms(sites.data(), (int)sites.size(), P.N_ref, tv, &stride, &n_hi, &two);
+                    shift_terms(sites.data(), (int)sites.size(), P.N_ref, P.N[l], P.ldg, tv, &stride, n_tab, &two);
                     j.T0 = q->ref->G.as<double>();
                 }
                 if (stride > 0) {
                     const double* w = nullptr;
-                    if ((rc = get_windows(c, *q->ref, stride, n_hi, st, &w))) return rc;
+                    if ((rc = get_windows(c, *q->ref, stride, n_tab[0], st, &w))) return rc;
                     j.T0 = w;
                     if (two) {
-                        if ((rc = get_windows(c, *q->ref, stride, n_hi - 1, st, &w))) return rc;
+                        if ((rc = get_windows(c, *q->ref, stride, n_tab[1], st, &w))) return rc;
                         j.T1 = w;
                     }
                 }

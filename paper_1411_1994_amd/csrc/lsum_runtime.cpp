@@ -346,7 +346,8 @@ int get_windows(Context* c, RefEntry& e, int stride, int n, hipStream_t st, cons
     }
     if (build) {
         StageTimer tm(st);
-        tm.begin("windows", 2.0 * e.R * e.ldg * 8, (double)e.R * e.ldg * n);
+        // additions: n per entry, or half a chain of ldg / stride for the prefix and suffix sums
+        tm.begin("windows", 2.0 * e.R * e.ldg * 8, (double)e.R * e.ldg * (n > 0 ? n : 0.5 * e.ldg / stride));
         launch_window_sums(st, e.R, e.G.as<double>(), e.ldg, stride, n, wr->Q.as<double>());
         tm.end();
         hipError_t err = hipGetLastError();

@@ -184,6 +184,53 @@ def test_shift_sum_matches_oracle(ctx, N_axis, N_ref, sites, M):
     assert np.all(np.abs(got - ref2) <= 1e-12 * np.abs(ref2) + floor)
 
 
+def _snapped(L, beta, N):
+    # L sites at spacing beta cells, centred on an N-cell axis and snapped to the nearest cell
+    x = (np.arange(L) - (L - 1) / 2) * beta
+    return [int(np.sign(v) * np.floor(abs(v) + 0.5)) + (N - 1) // 2 for v in x]
+
+
+# sites whose spacing in cells has no short period (the served mix's b/h = (N - 1) / (L + 16)
+# with L + 16 odd): they split into a few runs of one stride, each read as the difference of two
+# strided prefix or suffix sums of the rows
+STRIDED = [(4097, 4097, _snapped(87, 4096 / 103, 4097)),     # 9 runs of stride 159 (period 43)
+           (4097, 4097, _snapped(82, 4096 / 98, 4097)),      # 6 runs of stride 209
+           (809, 809, _snapped(36, 1024 / 66, 809)),         # 17 runs of stride 16 (34 terms)
+           (2969, 4097, _snapped(55, 4096 / 98, 2969)),      # N_axis < N_ref: 13 runs
+           (4097, 4097, _snapped(87, 4096 / 103, 4097) + [2048, 30, 4000]),   # runs and lone sites
+           (3915, 4097, _snapped(91, 4096 / 112, 3915))]     # period 7: the comb form stays
+
+
+@pytest.mark.parametrize("N_axis,N_ref,sites", STRIDED)
+def test_shift_sum_on_strided_runs_matches_oracle(ctx, N_axis, N_ref, sites):
+    import torch
+    import paper_1411_1994_amd as L
+    h = 0.03
+    t, w = L.lsum_nodes(W.NEWTON, 0.0, 40, (N_ref, N_ref, N_ref), h)
+    R = len(t)
+    ldg = 2 * N_ref - 1 + 1
+    G = empty(R * ldg, torch.float64)
+    ctx.collocate(t, w, N_ref, h, G, ldg)
+    U = empty(R * N_axis, torch.float64)
+    ctx.shift_sum(R, G, ldg, N_ref, N_axis, np.array(sites, np.int32), U, N_axis)
+    Gh = host(G).reshape(R, ldg)[:, :2 * N_ref - 1]
+    got = host(U).reshape(R, N_axis)
+    ref = O.shift_sum(Gh, np.array(sites), N_axis, N_ref)
+    # a run read as a difference of two strided sums: each table entry is a compensated sum
+    # (within two unit roundoffs of its chain's sum, and a chain is a subset of the row), and the
+    # at most n terms are added in order, so the error is below 3.5 n u times the row's sum
+    # besides the (n - 1) u relative of the positive site terms themselves
+    n = len(sites)
+    u = 2.0 ** -53
+    rowsum = np.sum(np.abs(Gh), axis=1, keepdims=True)
+    assert np.all(np.abs(got - ref) <= 1.2e-16 * n * np.abs(ref) + 3.5 * n * u * rowsum)
+    # where the lattice sits (every cell between its first and last site) the sum is of the
+    # row's order, and the comparison is relative to it
+    lo, hi = min(sites), max(sites)
+    inner = slice(lo, hi + 1)
+    assert np.all(np.abs(got[:, inner] - ref[:, inner]) <= 1e-13 * np.abs(ref[:, inner]) + 1e-15 * rowsum)
+
+
 def test_shift_sum_rejects_bad_sites(ctx):
     import torch
     import paper_1411_1994_amd as L
