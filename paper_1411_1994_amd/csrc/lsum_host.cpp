@@ -318,18 +318,22 @@ void shift_terms(const int32_t* c, int n, int N_ref, int N_axis, int ldg, std::v
     int bestS = 0;
     std::vector<int2> runs;
     // strided runs: a stride S <= (ldg + 1 - max(N, 2)) / 2 lets every run take the prefix or the
-    // suffix form (split at most once)
+    // suffix form (split at most once).  The search (tens of microseconds for ~100 sites) is
+    // skipped where it cannot pay: few sites, or a short period whose comb form already reads at
+    // most 8 entries (a stream of small canonical requests spends a few microseconds of host time
+    // per request in all).
     const int Nr = std::max(N_axis, 2);
     const int S_max = (ldg + 1 - Nr) / 2;
     const int lo_suffix = N_ref + Nr - 1 - ldg;   // + S: the first site a suffix run may start at
-    if (n >= 3 && S_max >= 1) {
+    if (n >= 6 && !(period > 0 && period <= 8) && S_max >= 1) {
         std::vector<int32_t> u(c, c + n);
         std::sort(u.begin(), u.end());
-        // candidate strides: the distances from three anchor sites to the next 32 (an outlying
-        // first site does not hide the lattice's stride)
+        // candidate strides: the distances from three anchor sites to the next 16 (an outlying
+        // first site does not hide the lattice's stride; a stride of a few lattice spacings, a
+        // convergent of b/h, is among them)
         std::vector<int> cand;
         for (int a : {0, n / 3, (2 * n) / 3})
-            for (int p = 1; p <= 32 && a + p < n; ++p) {
+            for (int p = 1; p <= 16 && a + p < n; ++p) {
                 const int d = u[a + p] - u[a];
                 if (d >= 1 && d <= S_max && std::find(cand.begin(), cand.end(), d) == cand.end()) cand.push_back(d);
             }
