@@ -195,9 +195,9 @@ def _snapped(L, beta, N):
 # strided prefix or suffix sums of the rows
 STRIDED = [(4097, 4097, _snapped(87, 4096 / 103, 4097)),     # 9 runs of stride 159 (period 43)
            (4097, 4097, _snapped(82, 4096 / 98, 4097)),      # 6 runs of stride 209
-           (809, 809, _snapped(36, 1024 / 66, 809)),         # 17 runs of stride 16 (34 terms)
-           (2969, 4097, _snapped(55, 4096 / 98, 2969)),      # N_axis < N_ref: 13 runs
-           (4097, 4097, _snapped(87, 4096 / 103, 4097) + [2048, 30, 4000]),   # runs and lone sites
+           (809, 809, _snapped(36, 1024 / 66, 809)),         # 4 runs of stride 31
+           (2969, 4097, _snapped(55, 4096 / 98, 2969)),      # N_axis < N_ref: 7 runs
+           (4097, 4097, _snapped(87, 4096 / 103, 4097) + [2048, 30, 4000]),   # 12 runs, lone sites among them
            (3915, 4097, _snapped(91, 4096 / 112, 3915))]     # period 7: the comb form stays
 
 

@@ -52,6 +52,52 @@ def test_cfg1_all_points_match_brute_force(ctx):
     r.release()
 
 
+def _shortest_period(c):
+    c = np.sort(np.asarray(c))
+    for p in range(1, len(c) // 2 + 1):
+        d = c[p:] - c[:-p]
+        if d[0] > 0 and np.all(d == d[0]):
+            return p
+    return 0
+
+
+@pytest.mark.parametrize("kind,param", [(W.NEWTON, 0.0), (W.SLATER, 1.0)])
+def test_served_mix_shape_canonical_matches_oracle(ctx, kind, param):
+    # a served-mix-shaped lattice (b/h = (N - 1) / (L_max + 16) = 512 / 55): no axis has a comb
+    # period of 8 or less (13, none, none), and runs of one stride need 10 terms per axis against
+    # 13, 25 and 17, so the request's shift-sums read those runs as differences of strided
+    # prefix / suffix sums.  Values at points within 1e-12 of the largest direct-sum
+    # value; factors within 1e-12 relative of the oracle's site-by-site sums near the lattice,
+    # and everywhere within 5 n u of the reference row's sum (each of at most n terms is within
+    # two roundoffs of its chain's sum, a chain being part of the row, plus the additions)
+    L = (39, 25, 17)
+    h = 2.0 * (max(L) / 2 + 8) / 512
+    N = tuple(513 if l == max(L) else int(2 * np.ceil((l / 2 + 8) / h) + 1) for l in L)
+    p = W.Problem("mixshape", kind, param, 30, N, h, [W.Block(L, (1.0, 1.0, 1.0), (0.0, 0.0, 0.0))], [])
+    r = run(ctx, p)
+    offs = r.stats()["offsets"][0]   # block 0: the sites of each axis
+    assert all(_shortest_period(offs[a]) in (0, 13) for a in range(3))
+    rng = np.random.default_rng(41 + kind)
+    pts = np.stack([rng.integers(0, n, 400) for n in p.N], axis=1)
+    got = r.sample(cells_xyz(p, pts))
+    ref = O.brute_force_points(p, pts)
+    assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
+    t, w = O.quadrature_of(p)
+    Nr = max(p.N)
+    rowsum = np.sum(np.abs(O.reference_vectors(t, w, Nr, p.h)), axis=1, keepdims=True)
+    U = r.canonical(0)
+    Uo = O.assembled_canonical(p)[0]
+    u = 2.0 ** -53
+    for a in range(3):
+        n = L[a]
+        assert np.all(np.abs(U[a] - Uo[a]) <= 1.2e-16 * n * np.abs(Uo[a]) + 5 * n * u * rowsum)
+        lo, hi = min(offs[a]), max(offs[a])
+        near = slice(lo, hi + 1)
+        floor = 1e-13 * np.max(np.abs(Uo[a]), axis=1, keepdims=True)
+        assert np.all(np.abs(U[a][:, near] - Uo[a][:, near]) <= 1e-12 * np.abs(Uo[a][:, near]) + floor)
+    r.release()
+
+
 @pytest.mark.parametrize("kind,param", [(W.NEWTON, 0.0), (W.YUKAWA, 0.5), (W.SLATER, 1.0)])
 def test_defects_and_blocks_canonical(ctx, kind, param):
     rng = np.random.default_rng(21 + kind)
