@@ -14,7 +14,7 @@ pytestmark = pytest.mark.gpu
 COMB_51_2 = [int(np.sign(x) * np.floor(abs(x) + 0.5)) + 1024 for x in (np.arange(40) - 19.5) * 51.2 / 2]
 
 
-def _one(ctx, M, N_ref, N_axis, sites, h=0.05):
+def _one(ctx, M, N_ref, N_axis, sites, h=0.05, runs=False):
     import torch
     import paper_1411_1994_amd as L
     t, w = L.lsum_nodes(W.NEWTON, 0.0, M, (N_ref, N_ref, N_ref), h)
@@ -32,10 +32,13 @@ def _one(ctx, M, N_ref, N_axis, sites, h=0.05):
     b = host(U_free).reshape(R, ldu)[:, :N_axis]
     assert np.array_equal(a, b)
     # and the oracle's sum of the same reference rows (positive terms: any order agrees to
-    # (n - 1) unit roundoffs relative)
+    # (n - 1) unit roundoffs relative; runs of one stride read as differences of two compensated
+    # strided sums add at most 5 n u of the row's sum)
     Gh = host(G).reshape(R, ldg)[:, :2 * N_ref - 1]
     ref = O.shift_sum(Gh, sites, N_axis, N_ref)
-    assert np.all(np.abs(b - ref) <= 1.2e-16 * max(1, len(sites)) * np.abs(ref))
+    n = max(1, len(sites))
+    floor = 5 * n * 2.0 ** -53 * np.sum(np.abs(Gh), axis=1, keepdims=True) if runs else 0.0
+    assert np.all(np.abs(b - ref) <= 1.2e-16 * n * np.abs(ref) + floor)
 
 
 def test_noalloc_shift_sum_equals_allocating_call_twice():
@@ -52,6 +55,11 @@ def test_noalloc_shift_sum_equals_allocating_call_twice():
         # and sites that form no comb (one term per site on the reference rows)
         print("noalloc call 3: N = 129, 4 sites", flush=True)
         _one(ctx, 16, 129, 129, [48, 59, 69, 80])
+        # and snapped sites without a short period (b/h = 1024 / 66): 4 runs of stride 31 on the
+        # strided prefix and suffix sums, both tables in the scratch array
+        print("noalloc call 4: N = 809, 36 sites in runs of one stride", flush=True)
+        x = (np.arange(36) - 17.5) * (1024 / 66)
+        _one(ctx, 30, 809, 809, [int(np.sign(v) * np.floor(abs(v) + 0.5)) + 404 for v in x], runs=True)
 
 
 def test_noalloc_shift_sum_rejects_sizes_beyond_its_scratch():
