@@ -298,11 +298,14 @@ int lsum_collocate(lsum_ctx ctx, void* stream, int R, const double* t, const dou
 
 /* Assembled 1D sums (Thm thm:sumCaseE (A)): U_dev[q*ldu + i] = sum_k G[q*ldg + i - c_k +
  * N_ref - 1] for i < N_axis, over the n_sites host cell indices c_k (0 <= c_k < N_axis <=
- * N_ref), in any order; ldg >= max(2, 2*N_ref-1).  FP64.  When the sites form p interleaved uniform combs
- * (c_{k+p} - c_k constant), each comb is summed first (as a windowed strided sum of the row)
- * and the p comb sums are added in order; otherwise the sites are added in order k = 0..n-1.
- * Errors: LSUM_E_INVALID for bad sizes or null pointers, LSUM_E_OUT_OF_BOX for a site outside
- * [0, N_axis).  Synchronous. */
+ * N_ref), in any order; ldg >= max(2, 2*N_ref-1).  FP64.  The form with the fewest terms is
+ * taken: when the sites form p interleaved uniform combs (c_{k+p} - c_k constant), each comb is
+ * summed first (as a windowed strided sum of the row) and the p comb sums are added in order;
+ * when they split into fewer runs of one stride S than that (at least 6 sites, no period of 8
+ * or less), each run is the difference of two compensated strided prefix (or suffix) sums of the
+ * row, whose error is a few units of roundoff of the row's sum |G| rather than of the value;
+ * otherwise the sites are added in order k = 0..n-1.  Errors: LSUM_E_INVALID for bad sizes or
+ * null pointers, LSUM_E_OUT_OF_BOX for a site outside [0, N_axis).  Synchronous. */
 int lsum_shift_sum(lsum_ctx ctx, void* stream, int R, const double* G_dev, int ldg, int N_ref,
                    int N_axis, int n_sites, const int32_t* sites, double* U_dev, int ldu);
 
@@ -311,7 +314,7 @@ int lsum_shift_sum(lsum_ctx ctx, void* stream, int R, const double* G_dev, int l
  * arguments, result (bitwise) and errors; the job descriptor, term list and window tables live
  * in a static device array of 64 MiB per device (held until the process ends) instead of pool
  * memory, so the call makes no allocation.  LSUM_E_NOMEM when the call needs more scratch than
- * that: 256 B + 8 B per term + up to two R x ldg FP64 window tables.  Every call on a device
+ * that: 256 B + 8 B per term + up to two R x ldg FP64 tables (window, prefix or suffix sums).  Every call on a device
  * shares that device's array: calls that overlap on one device race.  Synchronous. */
 int lsum_shift_sum_noalloc(lsum_ctx ctx, void* stream, int R, const double* G_dev, int ldg,
                            int N_ref, int N_axis, int n_sites, const int32_t* sites,
