@@ -287,8 +287,9 @@ void stride_runs(const std::vector<int32_t>& u, int S, std::vector<int2>& runs, 
 }
 
 // terms of one run of stride S on the prefix (tab 0) and suffix (tab 1) tables; bit 1 of tab
-// marks a term that is subtracted.  Every term read i + off stays in [0, ldg) for i < max(N, 2)
-// (stride_ok below).
+// marks a term that is subtracted.  lo_suffix is the first site a suffix run may start at.
+// With S within the bound shift_terms sets, every term read i + off stays in [0, ldg) for
+// i < max(N_axis, 2), and a run that fits neither form splits into one of each.
 void run_terms(int a, int n, int S, int N_ref, int lo_suffix, std::vector<int2>& terms) {
     const int last = a + (n - 1) * S;
     if (last + S <= N_ref - 1) {   // prefix: Pb[y] - Pb[y - nS], y - nS >= 0
