@@ -365,6 +365,22 @@ void test_shift_terms(std::mt19937_64& rng) {
             }
         check(exact, "terms reproduce the direct sum over the sites");
     }
+    // a lattice whose snapped sites repeat with a short period keeps its comb form, one term per
+    // comb (the 64^3 lattice on the 4097 grid: b/h = 51.2, five combs of 64 sites)
+    {
+        std::vector<int32_t> c;
+        for (int k = 0; k < 64; ++k) {
+            const double x = (k - 31.5) * 51.2;
+            const double j = std::floor(std::fabs(x) + 0.5);
+            c.push_back((int32_t)((x < 0 ? -j : j) + 2048));
+        }
+        std::vector<int2> terms;
+        int stride = 0, n_tab[2] = {0, 0};
+        bool two = false;
+        lsum::shift_terms(c.data(), 64, 4097, 4097, 8200, terms, &stride, n_tab, &two);
+        check(terms.size() == 5 && stride == 256 && n_tab[0] == 13 && n_tab[1] == 12,
+              "a period-5 lattice keeps its five combs");
+    }
     std::printf("shift terms: %d of 160 axes with fewer terms than sites, %d on strided runs\n", fewer, strided);
     check(fewer > 40, "most lattices need fewer terms than sites");
     check(strided > 10, "strided runs are taken for lattices without a short period");
